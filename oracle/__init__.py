@@ -1,0 +1,160 @@
+"""ORACLE -- test infrastructure, not part of the product.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It shares no code with the HIP path
+(``paper_2402_11868_amd``) and never imports it.
+
+Contents
+--------
+* ``heev`` -- 256-bit MPFR cyclic-Jacobi eigen-solver (``jacobi.c``) on the
+  exact limb sum of the input: the plain definition H = V diag(lam) V^H that
+  the paper's FP64-eig + Rayleigh-quotient-iteration method converges to
+  (Sec. 2, ZKCM_CUS paragraph).
+* ``residuals`` / ``gram`` -- MPFR evaluations of ||H v - lam v|| / ||v|| and
+  V^H V on returned limbs exactly as returned.
+* ``exact`` -- closed forms and exact rational pins used to check the Jacobi
+  solver itself (characteristic polynomial roots at n <= 4, invariants).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_MPFR_INC = "/opt/conda/include"
+_MPFR_LIB = "/opt/conda/lib"
+_lib = None
+
+DEFAULT_PREC = 256
+
+
+def build(force: bool = True) -> str:
+    """Compile jacobi.c (gcc + MPFR/GMP from /opt/conda, OpenMP)."""
+    if force or not os.path.exists(_LIB_PATH):
+        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", os.path.join(_HERE, "jacobi.c"),
+               "-I" + _MPFR_INC, "-L" + _MPFR_LIB, "-Wl,-rpath," + _MPFR_LIB,
+               "-lmpfr", "-lgmp", "-lm", "-o", _LIB_PATH + ".tmp"]
+        subprocess.check_call(cmd)
+        os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        I = ctypes.c_int
+        lib.or_heev.restype = I
+        lib.or_heev.argtypes = [I, I, P, I, I, I, I, P, P, P]
+        lib.or_residuals.restype = I
+        lib.or_residuals.argtypes = [I, I, P, I, I, I, P, I, I, P, I, I, P, P]
+        lib.or_gram.restype = I
+        lib.or_gram.argtypes = [I, I, I, P, I, I, I, P, P, P]
+        lib.or_set_mutation.restype = None
+        lib.or_set_mutation.argtypes = [I]
+        _lib = lib
+    return _lib
+
+
+def set_mutation(m: int) -> None:
+    """Plant deliberate mistake number m in the oracle (0 = none). Pin tests only."""
+    _load().or_set_mutation(int(m))
+
+
+def _planes_colmajor(planes) -> tuple[np.ndarray, int]:
+    """Stack limb planes (list of (n,n) complex arrays) into one column-major buffer."""
+    if isinstance(planes, np.ndarray) and planes.ndim == 2:
+        planes = [planes]
+    n = planes[0].shape[0]
+    buf = np.empty((len(planes), n, n), dtype=np.complex128)
+    for l, P in enumerate(planes):
+        buf[l] = np.asarray(P, dtype=np.complex128).T  # row j of buf[l] = column j of P
+    return np.ascontiguousarray(buf), n
+
+
+def _threads(nthreads):
+    if nthreads is None:
+        nthreads = int(os.environ.get("ORACLE_THREADS", "0")) or (os.cpu_count() or 1)
+    return int(nthreads)
+
+
+class HeevResult:
+    def __init__(self, w_limbs, v_limbs, info):
+        self.w_limbs = w_limbs          # (4, n) limbs of the ascending eigenvalues
+        self.v_limbs = v_limbs          # (4, n, n) limbs, column k = eigenvector k, or None
+        self.sweeps = int(info[0])
+        self.rotations = int(info[1])
+        self.off_rel = float(info[2])
+
+    @property
+    def w(self) -> np.ndarray:
+        return self.w_limbs[0]
+
+    @property
+    def V(self) -> np.ndarray | None:
+        return None if self.v_limbs is None else self.v_limbs[0]
+
+
+def heev(planes, want_vectors: bool = True, prec: int = DEFAULT_PREC, nthreads=None) -> HeevResult:
+    """Eigen-decomposition of sum(planes) (lower triangles read) at `prec` bits."""
+    buf, n = _planes_colmajor(planes)
+    L = buf.shape[0]
+    w = np.zeros((4, n), dtype=np.float64)
+    v = np.zeros((4, n, n), dtype=np.complex128) if want_vectors else None
+    info = np.zeros(3, dtype=np.float64)
+    rc = _load().or_heev(n, L, buf.ctypes.data, n, int(prec), int(bool(want_vectors)), _threads(nthreads),
+                         w.ctypes.data, v.ctypes.data if v is not None else None, info.ctypes.data)
+    if rc != 0:
+        raise RuntimeError(f"oracle or_heev failed: {rc}")
+    if v is not None:
+        # v[l] is column-major: row k of the buffer holds eigenvector k
+        v = np.ascontiguousarray(np.transpose(v, (0, 2, 1)))
+    return HeevResult(w, v, info)
+
+
+def residuals(planes, w_limbs, v_limbs, prec: int = DEFAULT_PREC, nthreads=None):
+    """||H v_j - lam_j v_j|| / ||v_j|| and ||v_j|| for every returned pair (MPFR).
+
+    w_limbs: (Lw, k) limbs; v_limbs: (Lv, n, k) complex limbs (column j = pair j).
+    """
+    buf, n = _planes_colmajor(planes)
+    w_limbs = np.ascontiguousarray(np.atleast_2d(np.asarray(w_limbs, dtype=np.float64)))
+    v_limbs = np.asarray(v_limbs, dtype=np.complex128)
+    if v_limbs.ndim == 2:
+        v_limbs = v_limbs[None]
+    Lv, nv, k = v_limbs.shape
+    assert nv == n and w_limbs.shape[1] == k
+    vbuf = np.ascontiguousarray(np.transpose(v_limbs, (0, 2, 1)))  # column-major per plane
+    res = np.zeros(k)
+    vn = np.zeros(k)
+    rc = _load().or_residuals(n, buf.shape[0], buf.ctypes.data, n, k, Lv, vbuf.ctypes.data, n,
+                              w_limbs.shape[0], w_limbs.ctypes.data, int(prec), _threads(nthreads),
+                              res.ctypes.data, vn.ctypes.data)
+    if rc != 0:
+        raise RuntimeError(f"oracle or_residuals failed: {rc}")
+    return res, vn
+
+
+def gram(v_limbs, prec: int = DEFAULT_PREC, nthreads=None, full: bool = False):
+    """(max_{i!=j} |v_i^H v_j|, max_i |v_i^H v_i - 1| [, |G|]) in MPFR."""
+    v_limbs = np.asarray(v_limbs, dtype=np.complex128)
+    if v_limbs.ndim == 2:
+        v_limbs = v_limbs[None]
+    Lv, n, k = v_limbs.shape
+    vbuf = np.ascontiguousarray(np.transpose(v_limbs, (0, 2, 1)))
+    mo = ctypes.c_double()
+    md = ctypes.c_double()
+    g = np.zeros((k, k)) if full else None
+    rc = _load().or_gram(n, k, Lv, vbuf.ctypes.data, n, int(prec), _threads(nthreads),
+                         ctypes.addressof(mo), ctypes.addressof(md),
+                         g.ctypes.data if g is not None else None)
+    if rc != 0:
+        raise RuntimeError(f"oracle or_gram failed: {rc}")
+    return (mo.value, md.value, g) if full else (mo.value, md.value)

@@ -1,0 +1,295 @@
+"""Seeded synthetic inputs for the Hermitian eigen-solver.
+
+This module only *builds inputs*: it contains none of the solver's arithmetic,
+and both the HIP path's tests/bench and the oracle's self-checks draw their
+matrices from here.
+
+Matrix families
+---------------
+* ``householder_hermitian`` -- H = U diag(lam) U^H, U a product of seeded
+  random Householder reflectors, built in binary64 by ``gen.c``.  This is the
+  "matrix with a designed spectrum" family used for every workload; the stored
+  binary64 matrix (not the design) is the ground truth.
+* ``hadamard_exact`` -- H = (1/N) Phi P W diag(lam) W P^T Phi^H with W the
+  Sylvester Hadamard matrix, P a seeded permutation and Phi seeded phases in
+  {1, i, -1, -i}.  Every entry is an exact dyadic rational that is stored
+  exactly in L binary64 limbs, so the eigenvalues are *exactly* lam and the
+  eigenvectors exactly Phi P W e_k / sqrt(N).
+* ``schmidt_pair`` -- the 2x2 density matrix with eigenvalues exactly 1-eps and
+  eps, the squared Schmidt coefficients of the controlled-rotation example in
+  the paper's introduction (footnote 1, eps = 2^(-n+1)).
+* ``random_elements`` -- Hermitian matrix with i.i.d. U(-1,1) real/imag parts,
+  the "random elements" matrices of the paper's diagonalisation timing (Sec. 2.1).
+
+Layout convention everywhere: a matrix is a numpy complex128 array ``A`` of
+shape (n, n); limb inputs are a list of such arrays whose *exact* sum is the
+matrix.  ``colmajor(A)`` gives the column-major buffer handed to C code.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from fractions import Fraction
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libzkgen.so")
+_lib = None
+
+SEED_BASE = 240211868
+
+
+def build(force: bool = True) -> str:
+    """Compile gen.c into libzkgen.so (plain gcc, no FP contraction)."""
+    if force or not os.path.exists(_LIB_PATH):
+        cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+               "-shared", os.path.join(_HERE, "gen.c"), "-o", _LIB_PATH + ".tmp", "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB_PATH)
+        lib.gen_householder_hermitian.restype = ctypes.c_int
+        lib.gen_householder_hermitian.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                                  ctypes.c_void_p, ctypes.c_void_p]
+        _lib = lib
+    return _lib
+
+
+def colmajor(A: np.ndarray) -> np.ndarray:
+    """Column-major complex128 buffer (entry (i, j) at offset j*n + i)."""
+    return np.ascontiguousarray(np.asarray(A, dtype=np.complex128).T)
+
+
+def seed_for(config: int, index: int = 0) -> int:
+    return SEED_BASE + 1000 * config + index
+
+
+# ---------------------------------------------------------------- families --
+
+def householder_hermitian(lam, seed: int, m: int | None = None) -> np.ndarray:
+    """Hermitian matrix with designed spectrum ``lam`` (binary64, exactly Hermitian)."""
+    lam = np.ascontiguousarray(np.asarray(lam, dtype=np.float64))
+    n = lam.size
+    m = n if m is None else int(m)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    u = np.ascontiguousarray(rng.standard_normal((m, n, 2)))
+    # seeded eigenvalue placement: the design order is shuffled so that the
+    # Householder product does not align the spectrum with the coordinate axes
+    perm = rng.permutation(n)
+    lam = np.ascontiguousarray(lam[perm])
+    out = np.zeros(2 * n * n, dtype=np.float64)
+    rc = _load().gen_householder_hermitian(n, m, lam.ctypes.data, u.ctypes.data, out.ctypes.data)
+    if rc != 0:
+        raise RuntimeError(f"gen_householder_hermitian failed: {rc}")
+    # out is column-major: entry (i, j) at j*n + i
+    return out.view(np.complex128).reshape(n, n).T.copy()
+
+
+def random_elements(n: int, seed: int) -> np.ndarray:
+    """Hermitian matrix with i.i.d. U(-1,1) real and imaginary parts (lower triangle drawn)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    re = rng.uniform(-1.0, 1.0, (n, n))
+    im = rng.uniform(-1.0, 1.0, (n, n))
+    A = np.tril(re + 1j * im, -1)
+    A = A + A.conj().T + np.diag(rng.uniform(-1.0, 1.0, n))
+    return A
+
+
+def _split_limbs(x: Fraction, L: int):
+    """Greedy round-to-nearest split of an exact rational into L binary64 limbs.
+
+    Returns (limbs, remainder).  limb_i = RN(x - sum of previous limbs).
+    """
+    limbs = []
+    r = Fraction(x)
+    for _ in range(L):
+        f = float(r)  # int/int true division: correctly rounded
+        limbs.append(f)
+        r -= Fraction(f)
+    return limbs, r
+
+
+def _popcount_parity(a: np.ndarray) -> np.ndarray:
+    a = a.astype(np.uint64)
+    p = np.zeros_like(a)
+    while np.any(a):
+        p ^= a & np.uint64(1)
+        a >>= np.uint64(1)
+    return p
+
+
+class HadamardExact:
+    """Exact-spectrum Hermitian matrix on n = 2^m (see module docstring).
+
+    Attributes: n, lam (sorted ascending, Fractions), planes (list of L
+    complex128 arrays whose exact sum is H), vectors(k) exact eigenvectors.
+    """
+
+    def __init__(self, lam, seed: int, limbs: int = 1, allow_inexact: bool = False):
+        lam = [Fraction(x) for x in lam]
+        n = len(lam)
+        if n < 1 or n & (n - 1):
+            raise ValueError("Hadamard family needs n = 2^m")
+        self.n = n
+        rng = np.random.Generator(np.random.PCG64(seed))
+        self.perm = rng.permutation(n)
+        self.q = rng.integers(0, 4, n)          # phase of row i is 1j**q[i]
+        self.lam_by_column = lam                # lam[k] belongs to Hadamard column k
+        # g(c) = sum_k lam_k (-1)^{popcount(c & k)}, by a fast Walsh-Hadamard
+        # transform on exact integers (all lam scaled to a common denominator)
+        den = 1
+        for x in lam:
+            den = max(den, x.denominator)
+        for x in lam:
+            assert den % x.denominator == 0, "lam must be dyadic"
+        g = [int(x * den) for x in lam]
+        h = 1
+        while h < n:
+            for i in range(0, n, 2 * h):
+                for j in range(i, i + h):
+                    a, b = g[j], g[j + h]
+                    g[j], g[j + h] = a + b, a - b
+            h *= 2
+        vals = [Fraction(gc, den * n) for gc in g]      # entry magnitudes x_c = g(c)/N
+        limb_tab = np.zeros((limbs, n), dtype=np.float64)
+        self.exact = True
+        for c, x in enumerate(vals):
+            ls, r = _split_limbs(x, limbs)
+            if r != 0:
+                self.exact = False
+            limb_tab[:, c] = ls
+        if not self.exact and not allow_inexact:
+            raise ValueError("entries are not exactly representable in %d limbs" % limbs)
+        idx = self.perm[:, None] ^ self.perm[None, :]
+        rot = (self.q[:, None] - self.q[None, :]) % 4
+        unit = np.array([1, 1j, -1, -1j], dtype=np.complex128)[rot]
+        self.planes = [limb_tab[l][idx] * unit for l in range(limbs)]
+        self.lam = sorted(lam)
+        self._order = sorted(range(n), key=lambda k: lam[k])
+
+    def vectors_unnormalised(self) -> np.ndarray:
+        """Columns (in ascending eigenvalue order) Phi P W e_k, entries in {±1, ±i}; norm sqrt(n)."""
+        n = self.n
+        W = 1 - 2 * _popcount_parity(self.perm[:, None].astype(np.uint64) &
+                                     np.arange(n, dtype=np.uint64)[None, :]).astype(np.int64)
+        phase = np.array([1, 1j, -1, -1j], dtype=np.complex128)[self.q]
+        V = phase[:, None] * W
+        return V[:, self._order]
+
+
+def hadamard_exact(lam, seed: int, limbs: int = 1) -> HadamardExact:
+    return HadamardExact(lam, seed, limbs)
+
+
+def schmidt_pair(k: int, omega: complex = 1.0, limbs: int = 2):
+    """2x2 matrix [[1/2, (1/2-eps) w], [(1/2-eps) conj(w), 1/2]] with eps = 2^-k.
+
+    Its eigenvalues are exactly 1-eps and eps (the squares of the Schmidt
+    coefficients sqrt(1-eps), sqrt(eps)).  omega must be in {±1, ±i}.
+    Returns (planes, (eps, 1-eps) as Fractions).
+    """
+    assert omega in (1, -1, 1j, -1j)
+    eps = Fraction(1, 2 ** k)
+    off = Fraction(1, 2) - eps
+    offl, r = _split_limbs(off, limbs)
+    if r != 0:
+        raise ValueError("1/2 - 2^-%d needs more than %d limbs" % (k, limbs))
+    planes = []
+    for l in range(limbs):
+        d = 0.5 if l == 0 else 0.0
+        A = np.array([[d, offl[l] * omega], [offl[l] * np.conj(omega), d]], dtype=np.complex128)
+        planes.append(A)
+    return planes, (eps, 1 - eps)
+
+
+# ----------------------------------------------------------------- spectra --
+# The readings below fix details the workload descriptions leave open; each is
+# listed with its reason in the design notes.
+
+def spectrum_c1() -> np.ndarray:
+    """n=64: one eigenvalue exactly 2^-20; 63 values prop. to 2^(-k/2), k=0..62, summing to 1-2^-20."""
+    k = np.arange(63)
+    base = 2.0 ** (-k / 2.0)
+    lam = base * ((1.0 - 2.0 ** -20) / base.sum())
+    return np.concatenate([lam, [2.0 ** -20]])
+
+
+def spectrum_c2(seed: int) -> tuple[np.ndarray, np.ndarray]:
+    """n=128: 10^(-k/8), k=0..123, four seeded distinct k doubled (exact 2-fold degeneracies), trace 1."""
+    rng = np.random.Generator(np.random.PCG64(seed + 7))
+    dup = np.sort(rng.choice(124, size=4, replace=False))
+    k = np.concatenate([np.arange(124), dup])
+    lam = 10.0 ** (-k / 8.0)
+    return lam / lam.sum(), dup
+
+
+def spectrum_c3() -> np.ndarray:
+    """n=1024: clusters of 8, lam_{j,m} = 2^(-50 j/127) (1 + m 1e-12), j=0..127, m=0..7 (span 1 .. 2^-50)."""
+    j = np.arange(128)[:, None]
+    m = np.arange(8)[None, :]
+    return (2.0 ** (-50.0 * j / 127.0) * (1.0 + m * 1e-12)).ravel()
+
+
+def spectrum_c4(s: int) -> np.ndarray:
+    """Serving sizes: lam_k prop. to 2^(-39 k/(s-1)), k=0..s-1, trace 1 (tail 2^-39, the 40-qubit pair)."""
+    k = np.arange(s)
+    lam = 2.0 ** (-39.0 * k / (s - 1))
+    return lam / lam.sum()
+
+
+def spectrum_c5(n: int = 2048, exact: bool = False):
+    """{1-2^-59, 2^-59} U {2^(-120 k/(n-2)) : k=1..n-2}.  exact=True returns Fractions (1-2^-59 kept)."""
+    k = np.arange(1, n - 1)
+    geo = 2.0 ** (-120.0 * k / (n - 2))
+    if exact:
+        return [Fraction(1) - Fraction(1, 2 ** 59), Fraction(1, 2 ** 59)] + [Fraction(float(x)) for x in geo]
+    return np.concatenate([[1.0 - 2.0 ** -59, 2.0 ** -59], geo])
+
+
+def serving_sizes() -> list[int]:
+    return list(range(16, 513, 16))
+
+
+def poisson_stream(rate_hz: float, count: int, seed: int, sizes=None):
+    """Open-loop Poisson arrivals: (arrival_times_s, sizes) with exponential gaps of mean 1/rate."""
+    sizes = serving_sizes() if sizes is None else list(sizes)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    gaps = rng.exponential(1.0 / rate_hz, count)
+    t = np.cumsum(gaps)
+    sz = np.asarray(sizes)[rng.integers(0, len(sizes), count)]
+    return t, sz
+
+
+# ------------------------------------------------------------- workloads --
+
+def workload(config: int, index: int = 0, n: int | None = None) -> dict:
+    """The matrices of the named workloads (Householder family, binary64 = 1 limb).
+
+    config 1: 64x64 one matrix; config 2: 256 x 128x128 batch (index selects the
+    member); config 3: 1024x1024 clustered; config 4: serving size n (index
+    selects the pool member); config 5: 2048x2048 or the 256 companions (n=256).
+    """
+    seed = seed_for(config, index)
+    if config == 1:
+        lam = spectrum_c1()
+    elif config == 2:
+        lam, _ = spectrum_c2(seed)
+    elif config == 3:
+        lam = spectrum_c3()
+    elif config == 4:
+        lam = spectrum_c4(n or 512)
+    elif config == 5:
+        lam = spectrum_c5(n or 2048)
+    else:
+        raise ValueError(config)
+    A = householder_hermitian(lam, seed)
+    return {"A": A, "design": np.sort(lam), "seed": seed}
