@@ -1,0 +1,198 @@
+/*
+ * zk.h -- C-ABI of libzk: accurate complex Hermitian eigendecomposition on one
+ * AMD Instinct MI355X (gfx950) GPU.
+ *
+ * The method is the one the paper describes for its GPU extension (Sec. 2,
+ * ZKCM_CUS paragraph): a binary64 eigendecomposition of the Hermitian matrix
+ * followed by Rayleigh quotient iteration that recovers the precision.  The
+ * diagonalisation of Hermitian (bond reduced density) matrices dominates the
+ * cost of the MPS simulation (Sec. 2.1), and the precision must resolve
+ * Schmidt coefficients as small as 2^((1-n)/2) (Sec. 1 and its footnote 1).
+ *
+ * Stage 1 (binary64): blocked Householder tridiagonalisation, tridiagonal
+ * eigen-solver (bisection + inverse iteration), back-transformation.
+ * Stage 2 (double-double or quad-double): per-eigenpair Rayleigh quotient
+ * iteration with shifted LU solves, Gram-Schmidt inside eigenvalue clusters,
+ * residual-based convergence test.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Matrices are complex128 (re, im interleaved), COLUMN-MAJOR, in DEVICE
+ *   memory.  Only the LOWER triangle (i >= j) is read; the upper triangle is
+ *   taken as its conjugate and the imaginary part of the diagonal is ignored.
+ * - "Limbs": an input or output value may be an unevaluated sum of 1, 2 or 4
+ *   binary64 numbers.  A limb plane set is an array of pointers, one per limb;
+ *   the value is the exact sum of the limbs.  1 limb = plain complex128.
+ * - Eigenvalues are returned in ASCENDING order; eigenvectors have unit norm;
+ *   the phase of a vector and the basis inside an exactly degenerate
+ *   eigenspace are unspecified.
+ * - The caller owns every buffer in zk_herm / zk_eig_out and keeps it alive
+ *   until the call returns (zk_heev_*, zk_rqi_refine are synchronous with
+ *   respect to the host) or until zk_session_poll reports completion.  The
+ *   library allocates and frees only its own workspace, bounded by the
+ *   context's HBM budget; it never frees caller memory.
+ * - Status codes are returned, never thrown.  On ZK_EINVAL nothing is
+ *   written.  On ZK_ENOCONV every output is written and the per-pair flags say
+ *   which pairs missed the tolerance.
+ * - A zk_ctx is used by one host thread at a time.  Work is enqueued on the
+ *   context's HIP stream.
+ */
+#ifndef ZK_H
+#define ZK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct zk_ctx zk_ctx;
+typedef struct zk_session zk_session;
+typedef uint64_t zk_ticket;
+
+enum {
+    ZK_OK = 0,
+    ZK_ENOCONV = 1,      /* outputs written; some pairs missed tol (see info flags) */
+    ZK_EINVAL = -1,      /* bad argument or NaN/Inf in the input; nothing written */
+    ZK_ENOMEM = -2,      /* request cannot fit the HBM budget / device allocation failed */
+    ZK_EDEVICE = -3,     /* HIP runtime error; the context is poisoned */
+    ZK_EAGAIN = -4,      /* session: queue full (submit) or request pending (poll) */
+    ZK_ECANCELED = -5,   /* session destroyed before the request ran */
+    ZK_EINTERNAL = -6
+};
+
+/* per-pair flags in zk_pair_info.flags */
+enum {
+    ZK_PAIR_CONVERGED = 1,   /* residual <= tol * ||H||_2 */
+    ZK_PAIR_REORTH = 2,      /* Gram-Schmidt against cluster members was applied */
+    ZK_PAIR_PIVOT_GUARD = 4, /* a zero pivot was replaced in some shifted LU */
+    ZK_PAIR_NAN = 8
+};
+
+/* A Hermitian input.  plane[0..limbs-1] are device pointers to n x n
+ * complex128 column-major arrays with leading dimension lda (elements). */
+typedef struct {
+    int n;
+    int lda;
+    int limbs;            /* 1, 2 or 4 */
+    const void *plane[4];
+} zk_herm;
+
+typedef struct {
+    int32_t iters;        /* Rayleigh quotient iterations (shifted solves) used */
+    int32_t flags;        /* ZK_PAIR_* */
+    int32_t cluster;      /* index of the first eigenvalue of this pair's cluster */
+    int32_t reserved;
+    double resid;         /* final ||H v - lam v|| / ||H||_2, rounded to binary64 */
+} zk_pair_info;
+
+/* Output of one decomposition.  w[l] (device) holds limb l of the n ascending
+ * eigenvalues; v[l] (device) limb l of the eigenvectors, an n x n complex128
+ * column-major array with leading dimension ldv (column k = eigenvector k);
+ * v[*] may be NULL when opts->want_vectors == 0.  info: HOST array of n
+ * entries, or NULL. */
+typedef struct {
+    int n;
+    int ldv;
+    int limbs;            /* 2 for dd output, 4 for qd output */
+    double *w[4];
+    void *v[4];
+    zk_pair_info *info;
+} zk_eig_out;
+
+typedef struct {
+    int init_fp32;        /* 1: stage-1 trailing updates in FP32 MFMA (FP32-rounded input) */
+    double tol;           /* residual/eigenvalue tolerance relative to ||H||_2; 0 = default (1e-30 dd, 1e-60 qd) */
+    int max_iter;         /* RQI iterations per pair; 0 = default (8 dd, 10 qd) */
+    double cluster_tol;   /* eigenvalues closer than cluster_tol*||H||_2 are one cluster; 0 = default 1e-10 */
+    int want_vectors;     /* 1 (default): write eigenvectors */
+    int reorth;           /* 1 (default): after the iteration, re-orthogonalise all eigenvectors of a
+                             matrix (classical Gram-Schmidt twice, in the output precision) and
+                             recompute every Rayleigh quotient and residual; 0: only inside clusters */
+} zk_opts;
+
+/* Fill *o with the defaults (init_fp32 0, tol 0, max_iter 0, cluster_tol 0, want_vectors 1, reorth 1). */
+void zk_opts_default(zk_opts *o);
+
+/* Create a context on HIP device `device`.  hip_stream: a hipStream_t of the
+ * caller (e.g. torch.cuda.current_stream().cuda_stream) or NULL for a private
+ * stream.  hbm_budget: maximum workspace bytes the library may hold (0 = 64 GiB).
+ * Returns ZK_OK and *out, or ZK_EINVAL / ZK_EDEVICE. */
+int zk_ctx_create(int device, void *hip_stream, size_t hbm_budget, zk_ctx **out);
+
+/* Release the context and all its workspace.  NULL is accepted. */
+int zk_ctx_destroy(zk_ctx *ctx);
+
+/* Static string for a status code. */
+const char *zk_status_str(int status);
+
+/* Message of the last failure on ctx ("" if none).  Valid until the next call on ctx. */
+const char *zk_ctx_last_error(const zk_ctx *ctx);
+
+/* Bytes of workspace one decomposition of order n with `limbs` output limbs
+ * needs when `concurrent_pairs` shifted LU factorisations run at once. */
+size_t zk_workspace_bytes(int n, int limbs, int concurrent_pairs);
+
+/*
+ * zk_heev_dd / zk_heev_qd: eigendecompose `count` independent Hermitian
+ * matrices A[0..count-1] (sizes may differ) to double-double (out[i].limbs ==
+ * 2) or quad-double (out[i].limbs == 4) accuracy.  Stage 1 runs in binary64,
+ * stage 2 is the Rayleigh quotient iteration (Sec. 2, ZKCM_CUS).  Synchronous:
+ * returns when the outputs are in place.
+ * Errors: ZK_EINVAL for count < 1, n < 1, lda < n, limbs not in {1,2,4}, NULL
+ * planes, ldv < n, a limbs mismatch, or NaN/Inf in an input; ZK_ENOMEM if one
+ * matrix alone exceeds the budget; ZK_ENOCONV if some pair missed tol.
+ */
+int zk_heev_dd(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out *out, const zk_opts *opts);
+int zk_heev_qd(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out *out, const zk_opts *opts);
+
+/*
+ * zk_heev_fp64: stage 1 alone (the binary64 eigendecomposition that seeds the
+ * Rayleigh quotient iteration).  For each matrix i: w[i] (device, n doubles,
+ * ascending) and V[i] (device, n x n complex128 column-major, leading
+ * dimension ldv[i] >= n).  Synchronous.  Errors as zk_heev_*.
+ */
+int zk_heev_fp64(zk_ctx *ctx, int count, const zk_herm *A, double *const *w, void *const *V, const int *ldv);
+
+/*
+ * zk_rqi_refine: stage 2 alone.  Refines k caller-supplied binary64
+ * eigenpairs of one Hermitian matrix A: w0 (device, k doubles, ascending) and
+ * V0 (device, n x k complex128 column-major, leading dimension ldv0, unit
+ * columns) to `limbs_out` (2 or 4) limbs.  out->n must equal k (the number of
+ * pairs), out->ldv >= A->n.  Same errors as zk_heev_*.
+ */
+int zk_rqi_refine(zk_ctx *ctx, int limbs_out, const zk_herm *A, int k, const double *w0,
+                  const void *V0, int ldv0, zk_eig_out *out, const zk_opts *opts);
+
+/*
+ * Serving form.  A session runs a scheduler thread that admits submitted
+ * requests while their workspace fits the session budget, batches the binary64
+ * stage of requests of equal order, and runs the Rayleigh quotient iterations
+ * of every admitted request together in shared launches (continuous
+ * batching).  Results are bitwise identical to a request run alone.
+ */
+int zk_session_create(zk_ctx *ctx, size_t budget, int max_queue, zk_session **out);
+
+/* Queue one request; returns at once.  *ticket identifies it.  ZK_EAGAIN if
+ * the queue holds max_queue requests, ZK_ENOMEM if the request alone exceeds
+ * the session budget, ZK_EINVAL for bad arguments. */
+int zk_session_submit(zk_session *s, const zk_herm *A, zk_eig_out *out, int limbs_out,
+                      const zk_opts *opts, zk_ticket *ticket);
+
+/* Wait up to timeout_us microseconds (0: do not wait, <0: forever) for the
+ * request.  Returns ZK_OK when done (*req_status = its status), ZK_EAGAIN if
+ * still pending, ZK_ECANCELED if cancelled, ZK_EINVAL for an unknown ticket. */
+int zk_session_poll(zk_session *s, zk_ticket ticket, int timeout_us, int *req_status);
+
+/* Host-clock stamps of a finished request: submit, admission, completion (seconds). */
+int zk_session_times(zk_session *s, zk_ticket ticket, double *t_submit, double *t_admit, double *t_done);
+
+/* Stop the scheduler; pending requests become ZK_ECANCELED. */
+int zk_session_destroy(zk_session *s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ZK_H */

@@ -1,0 +1,269 @@
+"""Python binding of libzk (the C-ABI declared in include/zk.h).
+
+Argument marshalling only: every step of the eigendecomposition runs in the
+HIP kernels of ``libzk.so``.  PyTorch supplies device memory and the HIP
+stream.  There is no CPU fallback: importing this package without the built
+library, or calling it without a GPU, raises.
+
+Matrices are passed as torch complex128 CUDA tensors of shape (n, n) holding
+the logical matrix A[i, j]; the binding hands the library a column-major copy
+(only the lower triangle is read).  Limb inputs are lists of such tensors
+whose exact sum is the matrix.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # noqa: F401  -- loads torch's HIP runtime first; libzk binds to the same one
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libzk.so")
+
+ZK_OK, ZK_ENOCONV, ZK_EINVAL, ZK_ENOMEM, ZK_EDEVICE, ZK_EAGAIN, ZK_ECANCELED, ZK_EINTERNAL = 0, 1, -1, -2, -3, -4, -5, -6
+PAIR_CONVERGED, PAIR_REORTH, PAIR_PIVOT_GUARD, PAIR_NAN = 1, 2, 4, 8
+
+
+class ZkHerm(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("lda", ctypes.c_int), ("limbs", ctypes.c_int),
+                ("plane", ctypes.c_void_p * 4)]
+
+
+class ZkPairInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("flags", ctypes.c_int32), ("cluster", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("resid", ctypes.c_double)]
+
+
+class ZkEigOut(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("ldv", ctypes.c_int), ("limbs", ctypes.c_int),
+                ("w", ctypes.c_void_p * 4), ("v", ctypes.c_void_p * 4), ("info", ctypes.POINTER(ZkPairInfo))]
+
+
+class ZkOpts(ctypes.Structure):
+    _fields_ = [("init_fp32", ctypes.c_int), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
+                ("cluster_tol", ctypes.c_double), ("want_vectors", ctypes.c_int), ("reorth", ctypes.c_int)]
+
+
+EXPORTED = ["zk_opts_default", "zk_ctx_create", "zk_ctx_destroy", "zk_status_str", "zk_ctx_last_error",
+            "zk_workspace_bytes", "zk_heev_dd", "zk_heev_qd", "zk_heev_fp64", "zk_rqi_refine",
+            "zk_session_create", "zk_session_submit", "zk_session_poll", "zk_session_times", "zk_session_destroy"]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libzk.so (raises OSError if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise OSError(f"libzk.so not built at {path}; run python -m paper_2402_11868_amd.build")
+    lib = ctypes.CDLL(path)
+    P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    lib.zk_opts_default.argtypes = [ctypes.POINTER(ZkOpts)]
+    lib.zk_opts_default.restype = None
+    lib.zk_ctx_create.argtypes = [I, P, ctypes.c_size_t, ctypes.POINTER(P)]
+    lib.zk_ctx_destroy.argtypes = [P]
+    lib.zk_status_str.argtypes = [I]
+    lib.zk_status_str.restype = ctypes.c_char_p
+    lib.zk_ctx_last_error.argtypes = [P]
+    lib.zk_ctx_last_error.restype = ctypes.c_char_p
+    lib.zk_workspace_bytes.argtypes = [I, I, I]
+    lib.zk_workspace_bytes.restype = ctypes.c_size_t
+    for f in ("zk_heev_dd", "zk_heev_qd"):
+        getattr(lib, f).argtypes = [P, I, ctypes.POINTER(ZkHerm), ctypes.POINTER(ZkEigOut), ctypes.POINTER(ZkOpts)]
+    lib.zk_heev_fp64.argtypes = [P, I, ctypes.POINTER(ZkHerm), ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(I)]
+    lib.zk_rqi_refine.argtypes = [P, I, ctypes.POINTER(ZkHerm), I, P, P, I, ctypes.POINTER(ZkEigOut), ctypes.POINTER(ZkOpts)]
+    if hasattr(lib, "zk_heev_stats"):
+        lib.zk_heev_stats.argtypes = [P, I, I, ctypes.POINTER(ZkHerm), ctypes.POINTER(ZkEigOut), ctypes.POINTER(ZkOpts),
+                                      ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(ctypes.c_longlong)]
+    if hasattr(lib, "zk_session_create"):
+        lib.zk_session_create.argtypes = [P, ctypes.c_size_t, I, ctypes.POINTER(P)]
+        lib.zk_session_submit.argtypes = [P, ctypes.POINTER(ZkHerm), ctypes.POINTER(ZkEigOut), I, ctypes.POINTER(ZkOpts),
+                                          ctypes.POINTER(ctypes.c_uint64)]
+        lib.zk_session_poll.argtypes = [P, ctypes.c_uint64, I, ctypes.POINTER(I)]
+        lib.zk_session_times.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D)]
+        lib.zk_session_destroy.argtypes = [P]
+    _lib = lib
+    return lib
+
+
+def status_str(s: int) -> str:
+    return load().zk_status_str(int(s)).decode()
+
+
+def make_opts(tol=0.0, max_iter=0, cluster_tol=0.0, want_vectors=True, init_fp32=False, reorth=True) -> ZkOpts:
+    o = ZkOpts()
+    load().zk_opts_default(ctypes.byref(o))
+    o.tol = float(tol)
+    o.max_iter = int(max_iter)
+    o.cluster_tol = float(cluster_tol)
+    o.want_vectors = int(bool(want_vectors))
+    o.init_fp32 = int(bool(init_fp32))
+    o.reorth = int(bool(reorth))
+    return o
+
+
+class Context:
+    """A libzk context bound to one device and (by default) torch's current stream."""
+
+    def __init__(self, device: int = 0, stream=None, budget: int = 0):
+        lib = load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("libzk needs a ROCm GPU; torch.cuda.is_available() is False")
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        rc = lib.zk_ctx_create(device, ctypes.c_void_p(stream.cuda_stream), ctypes.c_size_t(budget), ctypes.byref(h))
+        if rc != ZK_OK:
+            raise RuntimeError(f"zk_ctx_create failed: {status_str(rc)}")
+        self.handle = h
+
+    def last_error(self) -> str:
+        return load().zk_ctx_last_error(self.handle).decode()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().zk_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _colmajor(t: torch.Tensor) -> torch.Tensor:
+    if t.dtype != torch.complex128 or not t.is_cuda or t.dim() != 2 or t.shape[0] != t.shape[1]:
+        raise ValueError("matrices must be square complex128 CUDA tensors")
+    return t.transpose(0, 1).contiguous()
+
+
+def herm(planes, keep: list) -> ZkHerm:
+    """ZkHerm for a matrix given as a tensor or a list of limb tensors."""
+    if isinstance(planes, torch.Tensor):
+        planes = [planes]
+    h = ZkHerm()
+    n = planes[0].shape[0]
+    h.n, h.lda, h.limbs = n, n, len(planes)
+    for l, p in enumerate(planes):
+        c = _colmajor(p)
+        keep.append(c)
+        h.plane[l] = c.data_ptr()
+    return h
+
+
+class EigResult:
+    """w: (L, n) float64 limbs; V: (L, n, n) complex128 limbs (V[l][:, k] = vector k); info: list of dicts."""
+
+    def __init__(self, w, V, info, status):
+        self.w, self.V, self.info, self.status = w, V, info, status
+
+    @property
+    def iters(self):
+        return [i["iters"] for i in self.info]
+
+
+def _alloc_out(n: int, L: int, want_vectors: bool, dev, keep: list, npairs: int | None = None):
+    k = n if npairs is None else npairs
+    o = ZkEigOut()
+    o.n, o.ldv, o.limbs = k, n, L
+    w = torch.zeros((L, k), dtype=torch.float64, device=dev)
+    vbuf = torch.zeros((L, k, n), dtype=torch.complex128, device=dev) if want_vectors else None
+    for l in range(L):
+        o.w[l] = w[l].data_ptr()
+        o.v[l] = vbuf[l].data_ptr() if vbuf is not None else None
+    info = (ZkPairInfo * k)()
+    o.info = ctypes.cast(info, ctypes.POINTER(ZkPairInfo))
+    keep += [w, vbuf, info]
+    V = vbuf.transpose(1, 2) if vbuf is not None else None
+    return o, w, V, info
+
+
+def _info_list(info, k):
+    return [{"iters": info[i].iters, "flags": info[i].flags, "cluster": info[i].cluster, "resid": info[i].resid}
+            for i in range(k)]
+
+
+def heev(ctx: Context, mats, limbs_out: int = 2, opts: ZkOpts | None = None, stats: dict | None = None):
+    """Eigendecompose a list of matrices (each a tensor or list of limb tensors).
+
+    Returns a list of EigResult (status is shared by the batch call).
+    """
+    lib = load()
+    keep: list = []
+    count = len(mats)
+    H = (ZkHerm * count)()
+    O = (ZkEigOut * count)()
+    outs = []
+    want = True if opts is None else bool(opts.want_vectors)
+    for i, m in enumerate(mats):
+        H[i] = herm(m, keep)
+        o, w, V, info = _alloc_out(H[i].n, limbs_out, want, ctx_device(m), keep)
+        O[i] = o
+        outs.append((w, V, info, H[i].n))
+    op = ctypes.byref(opts) if opts is not None else None
+    if stats is not None:
+        hist = (ctypes.c_int * 16)()
+        rounds = ctypes.c_int()
+        solves = ctypes.c_longlong()
+        rc = lib.zk_heev_stats(ctx.handle, limbs_out, count, H, O, op, hist, ctypes.byref(rounds), ctypes.byref(solves))
+        stats.update(iters_hist=list(hist), rounds=rounds.value, solves=solves.value)
+    else:
+        f = lib.zk_heev_dd if limbs_out == 2 else lib.zk_heev_qd
+        rc = f(ctx.handle, count, H, O, op)
+    if rc not in (ZK_OK, ZK_ENOCONV):
+        raise RuntimeError(f"zk_heev failed: {status_str(rc)}: {ctx.last_error()}")
+    return [EigResult(w, V, _info_list(info, n), rc) for (w, V, info, n) in outs]
+
+
+def ctx_device(m):
+    t = m if isinstance(m, torch.Tensor) else m[0]
+    return t.device
+
+
+def heev_fp64(ctx: Context, mats):
+    """Stage 1 alone: list of (w (n,), V (n, n)) binary64 eigenpairs."""
+    lib = load()
+    keep: list = []
+    count = len(mats)
+    H = (ZkHerm * count)()
+    W = (ctypes.c_void_p * count)()
+    Vp = (ctypes.c_void_p * count)()
+    ld = (ctypes.c_int * count)()
+    res = []
+    for i, m in enumerate(mats):
+        H[i] = herm(m, keep)
+        n = H[i].n
+        w = torch.zeros(n, dtype=torch.float64, device=ctx_device(m))
+        vb = torch.zeros((n, n), dtype=torch.complex128, device=ctx_device(m))
+        W[i], Vp[i], ld[i] = w.data_ptr(), vb.data_ptr(), n
+        res.append((w, vb.transpose(0, 1)))
+        keep += [w, vb]
+    rc = lib.zk_heev_fp64(ctx.handle, count, H, W, Vp, ld)
+    if rc != ZK_OK:
+        raise RuntimeError(f"zk_heev_fp64 failed: {status_str(rc)}: {ctx.last_error()}")
+    return res
+
+
+def rqi_refine(ctx: Context, planes, w0: torch.Tensor, V0: torch.Tensor, limbs_out: int = 2, opts: ZkOpts | None = None):
+    """Stage 2 alone on caller binary64 pairs: w0 (k,), V0 (n, k) (columns = vectors)."""
+    lib = load()
+    keep: list = []
+    h = herm(planes, keep)
+    n = h.n
+    k = int(w0.shape[0])
+    w0c = w0.to(torch.float64).contiguous()
+    V0c = V0.transpose(0, 1).contiguous()   # row j = vector j -> column-major n x k, ld n
+    keep += [w0c, V0c]
+    want = True if opts is None else bool(opts.want_vectors)
+    o, w, V, info = _alloc_out(n, limbs_out, want, w0.device, keep, npairs=k)
+    rc = lib.zk_rqi_refine(ctx.handle, limbs_out, ctypes.byref(h), k, ctypes.c_void_p(w0c.data_ptr()),
+                           ctypes.c_void_p(V0c.data_ptr()), n, ctypes.byref(o),
+                           ctypes.byref(opts) if opts is not None else None)
+    if rc not in (ZK_OK, ZK_ENOCONV):
+        raise RuntimeError(f"zk_rqi_refine failed: {status_str(rc)}: {ctx.last_error()}")
+    return EigResult(w, V, _info_list(info, k), rc)

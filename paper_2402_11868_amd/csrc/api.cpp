@@ -1,0 +1,697 @@
+// C-ABI of libzk: argument checking, workspace, and the host side of the
+// two-stage method (binary64 eigendecomposition, then Rayleigh quotient
+// iteration in double-double or quad-double; Sec. 2, ZKCM_CUS paragraph).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/zk.h"
+#include "api_internal.h"
+#include "stage.h"
+
+using namespace zk;
+
+// ------------------------------------------------------------ status ----
+extern "C" const char *zk_status_str(int s)
+{
+    switch (s) {
+    case ZK_OK: return "ZK_OK";
+    case ZK_ENOCONV: return "ZK_ENOCONV: some pairs did not reach the tolerance";
+    case ZK_EINVAL: return "ZK_EINVAL: invalid argument or non-finite input";
+    case ZK_ENOMEM: return "ZK_ENOMEM: workspace exceeds the HBM budget or allocation failed";
+    case ZK_EDEVICE: return "ZK_EDEVICE: HIP runtime error";
+    case ZK_EAGAIN: return "ZK_EAGAIN: try again";
+    case ZK_ECANCELED: return "ZK_ECANCELED: request cancelled";
+    case ZK_EINTERNAL: return "ZK_EINTERNAL: internal error";
+    default: return "unknown status";
+    }
+}
+
+extern "C" void zk_opts_default(zk_opts *o)
+{
+    if (!o) return;
+    o->init_fp32 = 0;
+    o->tol = 0.0;
+    o->max_iter = 0;
+    o->cluster_tol = 0.0;
+    o->want_vectors = 1;
+    o->reorth = 1;
+}
+
+extern "C" const char *zk_ctx_last_error(const zk_ctx *ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+// ---------------------------------------------------------- context -----
+extern "C" int zk_ctx_create(int device, void *hip_stream, size_t hbm_budget, zk_ctx **out)
+{
+    if (!out) return ZK_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return ZK_EDEVICE;
+    if (device < 0 || device >= ndev) return ZK_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return ZK_EDEVICE;
+    zk_ctx *c = new zk_ctx();
+    c->device = device;
+    c->budget = hbm_budget ? hbm_budget : ((size_t)64 << 30);
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+        c->own_stream = false;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return ZK_EDEVICE;
+        }
+        c->own_stream = true;
+    }
+    *out = c;
+    return ZK_OK;
+}
+
+extern "C" int zk_ctx_destroy(zk_ctx *ctx)
+{
+    if (!ctx) return ZK_OK;
+    hipSetDevice(ctx->device);
+    hipStreamSynchronize(ctx->stream);
+    for (DevBuf *b : {&ctx->s1, &ctx->s2in, &ctx->s2vec, &ctx->s2lu, &ctx->meta}) b->release();
+    if (ctx->own_stream) hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return ZK_OK;
+}
+
+size_t zk_ctx::held() const { return s1.bytes + s2in.bytes + s2vec.bytes + s2lu.bytes + meta.bytes; }
+
+// Grow a workspace buffer (contents are not preserved).  ZK_ENOMEM if the
+// budget would be exceeded.
+int zk_ctx::ensure(DevBuf &b, size_t bytes)
+{
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (bytes <= b.bytes) return ZK_OK;
+    if (held() - b.bytes + bytes > budget) return fail(ZK_ENOMEM, "workspace of %zu bytes exceeds the budget", bytes);
+    b.release();
+    if (hipMalloc(&b.p, bytes) != hipSuccess) {
+        b.p = nullptr;
+        hipGetLastError();
+        return fail(ZK_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
+    }
+    b.bytes = bytes;
+    return ZK_OK;
+}
+
+int zk_ctx::fail(int status, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    err = buf;
+    if (status == ZK_EDEVICE) poisoned = true;
+    return status;
+}
+
+#define HIPCHK(expr)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) return ctx->fail(ZK_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+// ------------------------------------------------------ sizes / layout --
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// stage-1 scratch per problem (bytes), excluding hf/w0/V0 which live in s2in
+static size_t s1_bytes(int n)
+{
+    const size_t nn = (size_t)n * n, ntile = (size_t)(n + 63) / 64, npan = (size_t)(n + kNB - 1) / kNB + 1;
+    size_t b = 0;
+    b += align_up(16 * nn);                 // A
+    b += align_up(16 * nn);                 // Y
+    b += align_up(16 * (size_t)n);          // tau
+    b += 2 * align_up(16 * (size_t)n * 2 * kNB);   // P, Q
+    b += align_up(16 * 2 * ntile * n);      // part
+    b += align_up(8 * 5 * nn);              // tri
+    b += align_up(8 * nn);                  // Zt
+    b += 3 * align_up(8 * (size_t)n);       // d, e, (spare)
+    b += align_up(8 * nn);                  // Z
+    b += align_up(16 * npan * kNB * kNB);   // T
+    b += 2 * align_up(16 * (size_t)kNB * n);   // X, X2
+    b += align_up(64);                      // flag
+    return b;
+}
+
+// stage-2 inputs per problem: hf, w0, V0
+static size_t s2in_bytes(int n, int limbs_in)
+{
+    const size_t nn = (size_t)n * n;
+    return align_up(8 * 2 * (size_t)limbs_in * nn) + align_up(8 * (size_t)n) + align_up(16 * nn) + align_up(64);
+}
+
+// stage-2 iterate storage per problem: vec, sigma
+static size_t s2vec_bytes(int n, int L)
+{
+    const size_t nn = (size_t)n * n;
+    return align_up(8 * 2 * (size_t)L * nn) + align_up(8 * (size_t)L * n);
+}
+
+static int lu_ldm(int n) { return (n + 7) & ~7; }
+
+static size_t lu_slot_doubles(int n, int L) { return (size_t)2 * L * lu_ldm(n) * (size_t)(n + 1); }
+
+extern "C" size_t zk_workspace_bytes(int n, int limbs, int concurrent_pairs)
+{
+    if (n < 1 || (limbs != 2 && limbs != 4) || concurrent_pairs < 0) return 0;
+    const size_t lu = align_up(8 * lu_slot_doubles(n, limbs)) + align_up(4 * (size_t)n);
+    return s1_bytes(n) + s2in_bytes(n, 4) + s2vec_bytes(n, limbs) + (size_t)concurrent_pairs * lu + align_up(64 * (size_t)n + 4096);
+}
+
+// ------------------------------------------------------ argument checks --
+static int check_herm(const zk_herm &A)
+{
+    if (A.n < 1 || A.n > kMaxN || A.lda < A.n) return ZK_EINVAL;
+    if (A.limbs != 1 && A.limbs != 2 && A.limbs != 4) return ZK_EINVAL;
+    for (int l = 0; l < A.limbs; l++)
+        if (!A.plane[l]) return ZK_EINVAL;
+    return ZK_OK;
+}
+
+static int check_out(const zk_eig_out &o, int n_pairs, int n_rows, int L, bool want_vectors)
+{
+    if (o.n != n_pairs || o.limbs != L) return ZK_EINVAL;
+    for (int l = 0; l < L; l++) {
+        if (!o.w[l]) return ZK_EINVAL;
+        if (want_vectors && !o.v[l]) return ZK_EINVAL;
+    }
+    if (want_vectors && o.ldv < n_rows) return ZK_EINVAL;
+    return ZK_OK;
+}
+
+struct ResolvedOpts {
+    double tol;
+    int max_iter;
+    double cluster_tol;
+    int want_vectors;
+    int init_fp32;
+    int reorth;
+};
+
+static ResolvedOpts resolve(const zk_opts *o, int L)
+{
+    ResolvedOpts r;
+    r.tol = (o && o->tol > 0.0) ? o->tol : (L == 2 ? 1e-30 : 1e-60);
+    r.max_iter = (o && o->max_iter > 0) ? o->max_iter : (L == 2 ? 8 : 10);
+    if (o && o->max_iter < 0) r.max_iter = 0;
+    r.cluster_tol = (o && o->cluster_tol > 0.0) ? o->cluster_tol : 1e-10;
+    r.want_vectors = o ? (o->want_vectors != 0) : 1;
+    r.init_fp32 = o ? o->init_fp32 : 0;
+    r.reorth = o ? (o->reorth != 0) : 1;
+    return r;
+}
+
+// ============================================================ stage 2 ====
+// Shared by zk_heev_* and zk_rqi_refine.  probs[p] must have n, limbs_in,
+// hf, w0, V0, ldv0, w_out, v_out, ldv_out set; npair_of[p] pairs are refined
+// (k = 0 .. npair_of[p]-1).  Fills the info arrays and returns the status.
+template <int L>
+static int run_stage2(zk_ctx *ctx, std::vector<RqiProb> &probs, const std::vector<int> &npair_of,
+                      std::vector<zk_pair_info *> infos, const ResolvedOpts &O, Stage2Stats *stats)
+{
+    hipStream_t st = ctx->stream;
+    const int np = (int)probs.size();
+    // binary64 eigenvalues -> host: ||H||_2 estimate and clusters
+    std::vector<PairDesc> pairs;
+    std::vector<int> heads;
+    std::vector<double> w0h;
+    int max_n = 0;
+    size_t vec_total = 0;
+    for (int p = 0; p < np; p++) {
+        max_n = std::max(max_n, probs[p].n);
+        vec_total += s2vec_bytes(probs[p].n, L);
+    }
+    for (int p = 0; p < np; p++) {
+        const int kp = npair_of[p];
+        w0h.resize(kp);
+        HIPCHK(hipMemcpyAsync(w0h.data(), probs[p].w0, 8 * (size_t)kp, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        double hn = 0.0;
+        for (int k = 0; k < kp; k++) hn = std::max(hn, std::fabs(w0h[k]));
+        hn = std::max(hn, probs[p].hnorm);   // caller-side lower bound (refinement of a subset)
+        if (!(hn > 0.0)) hn = 1.0;           // zero matrix: absolute tolerances
+        probs[p].hnorm = hn;
+        probs[p].tol_abs = O.tol * hn;
+        probs[p].piv_tol = std::ldexp(hn, -53 * L);
+        const double thr = O.cluster_tol * hn;
+        int start = 0;
+        for (int k = 0; k < kp; k++) {
+            if (k > 0 && !(w0h[k] - w0h[k - 1] <= thr)) start = k;
+            PairDesc q;
+            std::memset(&q, 0, sizeof q);
+            q.prob = p;
+            q.k = k;
+            q.cl_start = start;
+            pairs.push_back(q);
+        }
+        // cluster sizes and heads
+        const size_t base = pairs.size() - kp;
+        int k = 0;
+        while (k < kp) {
+            int e = k + 1;
+            while (e < kp && pairs[base + e].cl_start == k) e++;
+            for (int q = k; q < e; q++) pairs[base + q].cl_size = (q == k) ? e - k : 0;
+            heads.push_back((int)(base + k));
+            k = e;
+        }
+    }
+    const int npairs = (int)pairs.size();
+    // workspace: vec/sigma per problem, meta (pairs, probs, heads, active, dst)
+    int rc;
+    if ((rc = ctx->ensure(ctx->s2vec, vec_total)) != ZK_OK) return rc;
+    const size_t meta_bytes = align_up(sizeof(PairDesc) * npairs) + align_up(sizeof(RqiProb) * np) + 3 * align_up(4 * (size_t)npairs);
+    if ((rc = ctx->ensure(ctx->meta, meta_bytes)) != ZK_OK) return rc;
+    char *vb = (char *)ctx->s2vec.p;
+    for (int p = 0; p < np; p++) {
+        const size_t nn = (size_t)probs[p].n * probs[p].n;
+        probs[p].vec = (double *)vb;
+        vb += align_up(8 * 2 * (size_t)L * nn);
+        probs[p].sigma = (double *)vb;
+        vb += align_up(8 * (size_t)L * probs[p].n);
+    }
+    char *mb = (char *)ctx->meta.p;
+    PairDesc *d_pairs = (PairDesc *)mb;
+    mb += align_up(sizeof(PairDesc) * npairs);
+    RqiProb *d_probs = (RqiProb *)mb;
+    mb += align_up(sizeof(RqiProb) * np);
+    int *d_heads = (int *)mb;
+    mb += align_up(4 * (size_t)npairs);
+    int *d_active = (int *)mb;
+    mb += align_up(4 * (size_t)npairs);
+    int *d_dst = (int *)mb;
+    // cluster sizes live in the head's cl_size; every member needs it only through the head
+    HIPCHK(hipMemcpyAsync(d_pairs, pairs.data(), sizeof(PairDesc) * npairs, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_probs, probs.data(), sizeof(RqiProb) * np, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_heads, heads.data(), 4 * heads.size(), hipMemcpyHostToDevice, st));
+    // LU slots: as many concurrent factorisations as the budget allows
+    const size_t slot_d = lu_slot_doubles(max_n, L);
+    const size_t slot_bytes = align_up(8 * slot_d);
+    const size_t piv_bytes = align_up(4 * (size_t)max_n);
+    size_t avail = ctx->budget > ctx->held() - ctx->s2lu.bytes ? ctx->budget - (ctx->held() - ctx->s2lu.bytes) : 0;
+    int S = (int)std::min<size_t>((size_t)npairs, avail / (slot_bytes + piv_bytes));
+    if (S < 1) return ctx->fail(ZK_ENOMEM, "one shifted LU of order %d needs %zu bytes", max_n, slot_bytes + piv_bytes);
+    if ((rc = ctx->ensure(ctx->s2lu, (size_t)S * (slot_bytes + piv_bytes))) != ZK_OK) return rc;
+    double *lu_base = (double *)ctx->s2lu.p;
+    int *piv_base = (int *)((char *)ctx->s2lu.p + (size_t)S * slot_bytes);
+
+    if (stage2_init<L>(d_pairs, d_probs, npairs, st)) return ctx->fail(ZK_EDEVICE, "stage2 init launch failed");
+    if (stage2_gs<L>(d_pairs, d_probs, d_heads, (int)heads.size(), st)) return ctx->fail(ZK_EDEVICE, "stage2 gs launch failed");
+    std::vector<int> act(npairs);
+    for (int g = 0; g < npairs; g++) act[g] = g;
+    HIPCHK(hipMemcpyAsync(d_active, act.data(), 4 * (size_t)npairs, hipMemcpyHostToDevice, st));
+    Stage2Batch B;
+    std::memset(&B, 0, sizeof B);
+    B.L = L;
+    B.dev_pairs = d_pairs;
+    B.dev_probs = d_probs;
+    B.dev_active = d_active;
+    B.count = npairs;
+    B.max_iter = O.max_iter;
+    B.lu_base = lu_base;
+    B.lu_stride = slot_d;
+    B.piv_base = piv_base;
+    B.piv_stride = (size_t)max_n;
+    if (stage2_rq<L>(B, st)) return ctx->fail(ZK_EDEVICE, "stage2 rq launch failed");
+
+    std::vector<PairDesc> hp(npairs);
+    int iter = 0;
+    for (;; iter++) {
+        HIPCHK(hipMemcpyAsync(hp.data(), d_pairs, sizeof(PairDesc) * npairs, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        std::map<int, std::vector<int>> by_n;
+        int nact = 0;
+        for (int g = 0; g < npairs; g++)
+            if (hp[g].status == 0) {
+                by_n[probs[hp[g].prob].n].push_back(g);
+                nact++;
+            }
+        if (stats) stats->active_per_iter.push_back(nact);
+        if (nact == 0 || iter > O.max_iter + 1) break;
+        // shifted solves, grouped by order, S at a time
+        for (auto &kv : by_n) {
+            const int n = kv.first;
+            const std::vector<int> &lst = kv.second;
+            for (size_t c0 = 0; c0 < lst.size(); c0 += (size_t)S) {
+                const int cnt = (int)std::min<size_t>((size_t)S, lst.size() - c0);
+                HIPCHK(hipMemcpyAsync(d_active, lst.data() + c0, 4 * (size_t)cnt, hipMemcpyHostToDevice, st));
+                B.n = n;
+                B.count = cnt;
+                B.ldm = lu_ldm(n);
+                B.lu_stride = lu_slot_doubles(n, L);
+                B.piv_stride = (size_t)n;
+                if (stage2_solve<L>(B, st)) return ctx->fail(ZK_EDEVICE, "stage2 solve launch failed");
+                // keep the host list alive until the copy has been consumed
+                HIPCHK(hipStreamSynchronize(st));
+            }
+        }
+        // Gram-Schmidt in clusters with active members
+        std::vector<int> hl;
+        for (int hidx : heads) {
+            bool a = false;
+            for (int q = 0; q < hp[hidx].cl_size && !a; q++) a = hp[hidx + q].status == 0;
+            if (a && hp[hidx].cl_size > 0) hl.push_back(hidx);
+        }
+        HIPCHK(hipMemcpyAsync(d_heads, hl.data(), 4 * hl.size(), hipMemcpyHostToDevice, st));
+        if (stage2_gs<L>(d_pairs, d_probs, d_heads, (int)hl.size(), st)) return ctx->fail(ZK_EDEVICE, "stage2 gs launch failed");
+        std::vector<int> all;
+        for (auto &kv : by_n) all.insert(all.end(), kv.second.begin(), kv.second.end());
+        HIPCHK(hipMemcpyAsync(d_active, all.data(), 4 * all.size(), hipMemcpyHostToDevice, st));
+        B.count = (int)all.size();
+        if (stage2_rq<L>(B, st)) return ctx->fail(ZK_EDEVICE, "stage2 rq launch failed");
+        HIPCHK(hipStreamSynchronize(st));
+        // restore the full head list for the next iteration's lookup
+        HIPCHK(hipMemcpyAsync(d_heads, heads.data(), 4 * heads.size(), hipMemcpyHostToDevice, st));
+    }
+    // global re-orthogonalisation, then every Rayleigh quotient and residual again
+    if (O.reorth) {
+        std::map<int, std::vector<int>> pn;
+        for (int p = 0; p < np; p++)
+            if (npair_of[p] == probs[p].n && probs[p].n > 1) pn[probs[p].n].push_back(p);
+        for (auto &kv : pn) {
+            const int n = kv.first, cnt = (int)kv.second.size();
+            const size_t sstride = (size_t)2 * L * n * 32;
+            if (ctx->s2lu.bytes < 8 * sstride * cnt + 4 * (size_t)cnt + 256) {
+                if ((rc = ctx->ensure(ctx->s2lu, 8 * sstride * cnt + 4 * (size_t)cnt + 256)) != ZK_OK) return rc;
+            }
+            double *scratch = (double *)ctx->s2lu.p;
+            int *d_plist = (int *)((char *)ctx->s2lu.p + align_up(8 * sstride * cnt));
+            HIPCHK(hipMemcpyAsync(d_plist, kv.second.data(), 4 * (size_t)cnt, hipMemcpyHostToDevice, st));
+            if (stage2_reorth<L>(d_probs, d_plist, cnt, n, scratch, sstride, st))
+                return ctx->fail(ZK_EDEVICE, "re-orthogonalisation launch failed");
+            HIPCHK(hipStreamSynchronize(st));
+        }
+        std::vector<int> all(npairs);
+        for (int g = 0; g < npairs; g++) all[g] = g;
+        HIPCHK(hipMemcpyAsync(d_active, all.data(), 4 * (size_t)npairs, hipMemcpyHostToDevice, st));
+        B.count = npairs;
+        B.final_pass = 1;
+        if (stage2_rq<L>(B, st)) return ctx->fail(ZK_EDEVICE, "stage2 rq launch failed");
+        B.final_pass = 0;
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    // ascending order of the refined eigenvalues inside each matrix
+    std::vector<int> dst(npairs);
+    {
+        size_t g0 = 0;
+        std::vector<double> sig;
+        for (int p = 0; p < np; p++) {
+            const int n = probs[p].n, kp = npair_of[p];
+            sig.resize((size_t)L * n);
+            HIPCHK(hipMemcpyAsync(sig.data(), probs[p].sigma, 8 * (size_t)L * n, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            std::vector<int> ord(kp);
+            for (int k = 0; k < kp; k++) ord[k] = k;
+            std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+                for (int l = 0; l < L; l++) {
+                    const double x = sig[(size_t)l * n + a], y = sig[(size_t)l * n + b];
+                    if (x != y) return x < y;
+                }
+                return false;
+            });
+            for (int pos = 0; pos < kp; pos++) dst[g0 + ord[pos]] = pos;
+            g0 += kp;
+        }
+    }
+    HIPCHK(hipMemcpyAsync(d_dst, dst.data(), 4 * (size_t)npairs, hipMemcpyHostToDevice, st));
+    if (stage2_output<L>(d_pairs, d_probs, d_dst, npairs, st)) return ctx->fail(ZK_EDEVICE, "stage2 output launch failed");
+    HIPCHK(hipMemcpyAsync(hp.data(), d_pairs, sizeof(PairDesc) * npairs, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    bool all_conv = true;
+    for (int g = 0; g < npairs; g++) {
+        const PairDesc &q = hp[g];
+        if (q.status != 1) all_conv = false;
+        if (stats) {
+            stats->iters_hist[std::min(q.iters, 15)]++;
+            stats->solves += q.iters;
+        }
+        zk_pair_info *info = infos[q.prob];
+        if (info) {
+            zk_pair_info &o = info[dst[g]];
+            o.iters = q.iters;
+            o.flags = q.flags;
+            o.cluster = q.cl_start;
+            o.reserved = 0;
+            o.resid = q.resid;
+        }
+    }
+    if (stats) stats->rounds = iter;
+    return all_conv ? ZK_OK : ZK_ENOCONV;
+}
+
+// ============================================================ heev ========
+// Stage 1 for `count` matrices: fills hf/w0/V0 pointers (into ctx->s2in) and
+// runs the binary64 eigendecomposition; ZK_EINVAL on non-finite input.
+static int run_stage1(zk_ctx *ctx, int count, const zk_herm *A, std::vector<double *> &hf, std::vector<double *> &w0,
+                      std::vector<double *> &V0)
+{
+    hipStream_t st = ctx->stream;
+    int rc;
+    // stage-2 inputs (hf, w0, V0) for every matrix, resident until the end
+    size_t in_total = 0;
+    for (int i = 0; i < count; i++) in_total += s2in_bytes(A[i].n, A[i].limbs);
+    if ((rc = ctx->ensure(ctx->s2in, in_total)) != ZK_OK) return rc;
+    std::vector<int *> flag(count);
+    {
+        char *b = (char *)ctx->s2in.p;
+        for (int i = 0; i < count; i++) {
+            const size_t nn = (size_t)A[i].n * A[i].n;
+            hf[i] = (double *)b;
+            b += align_up(8 * 2 * (size_t)A[i].limbs * nn);
+            w0[i] = (double *)b;
+            b += align_up(8 * (size_t)A[i].n);
+            V0[i] = (double *)b;
+            b += align_up(16 * nn);
+            flag[i] = (int *)b;
+            b += align_up(64);
+        }
+    }
+    HIPCHK(hipMemsetAsync(ctx->s2in.p, 0, in_total, st));
+    // stage 1, grouped by order, as many matrices at a time as the budget allows
+    std::map<int, std::vector<int>> groups;
+    for (int i = 0; i < count; i++) groups[A[i].n].push_back(i);
+    for (auto &kv : groups) {
+        const int n = kv.first;
+        const std::vector<int> &ids = kv.second;
+        const size_t per = s1_bytes(n);
+        size_t avail = ctx->budget > ctx->held() - ctx->s1.bytes ? ctx->budget - (ctx->held() - ctx->s1.bytes) : 0;
+        int chunk = (int)std::min<size_t>(ids.size(), avail / std::max<size_t>(per, 1));
+        if (chunk < 1) return ctx->fail(ZK_ENOMEM, "binary64 stage of order %d needs %zu bytes", n, per);
+        if ((rc = ctx->ensure(ctx->s1, (size_t)chunk * per + align_up(sizeof(ProbDesc) * chunk) +
+                                           align_up(sizeof(GemmDesc) * stage1_gemm_desc_count(n, chunk)))) != ZK_OK)
+            return rc;
+        for (size_t c0 = 0; c0 < ids.size(); c0 += (size_t)chunk) {
+            const int np = (int)std::min<size_t>((size_t)chunk, ids.size() - c0);
+            std::vector<ProbDesc> hp(np);
+            char *b = (char *)ctx->s1.p;
+            const size_t nn = (size_t)n * n, ntile = (size_t)(n + 63) / 64, npan = (size_t)(n + kNB - 1) / kNB + 1;
+            for (int q = 0; q < np; q++) {
+                const int i = ids[c0 + q];
+                ProbDesc &P = hp[q];
+                std::memset(&P, 0, sizeof P);
+                P.n = n;
+                P.lda_in = A[i].lda;
+                P.limbs_in = A[i].limbs;
+                for (int l = 0; l < A[i].limbs; l++) P.in[l] = (const double *)A[i].plane[l];
+                P.hf = hf[i];
+                P.w0 = w0[i];
+                P.V0 = V0[i];
+                P.flag = flag[i];
+                P.A = (double *)b; b += align_up(16 * nn);
+                P.Y = (double *)b; b += align_up(16 * nn);
+                P.tau = (double *)b; b += align_up(16 * (size_t)n);
+                P.P = (double *)b; b += align_up(16 * (size_t)n * 2 * kNB);
+                P.Q = (double *)b; b += align_up(16 * (size_t)n * 2 * kNB);
+                P.part = (double *)b; b += align_up(16 * 2 * ntile * n);
+                P.tri = (double *)b; b += align_up(8 * 5 * nn);
+                P.Zt = (double *)b; b += align_up(8 * nn);
+                P.d = (double *)b; b += align_up(8 * (size_t)n);
+                P.e = (double *)b; b += align_up(8 * (size_t)n);
+                b += align_up(8 * (size_t)n);
+                P.Z = (double *)b; b += align_up(8 * nn);
+                P.T = (double *)b; b += align_up(16 * npan * kNB * kNB);
+                P.X = (double *)b; b += align_up(16 * (size_t)kNB * n);
+                P.X2 = (double *)b; b += align_up(16 * (size_t)kNB * n);
+                b += align_up(64);
+            }
+            // the reflector array must start zero (entries above row c+1 are read as zeros)
+            for (int q = 0; q < np; q++) HIPCHK(hipMemsetAsync(hp[q].Y, 0, 16 * nn, st));
+            ProbDesc *d_probs = (ProbDesc *)b;
+            b += align_up(sizeof(ProbDesc) * np);
+            GemmDesc *d_gemm = (GemmDesc *)b;
+            std::vector<GemmDesc> hg(stage1_gemm_desc_count(n, np));
+            if (n > 1) stage1_fill_gemm_descs(hp.data(), np, hg.data());
+            HIPCHK(hipMemcpyAsync(d_probs, hp.data(), sizeof(ProbDesc) * np, hipMemcpyHostToDevice, st));
+            if (!hg.empty()) HIPCHK(hipMemcpyAsync(d_gemm, hg.data(), sizeof(GemmDesc) * hg.size(), hipMemcpyHostToDevice, st));
+            Stage1Batch S1;
+            S1.n = n;
+            S1.nprob = np;
+            S1.dev_probs = d_probs;
+            S1.dev_gemm = d_gemm;
+            S1.tri_gap_rel = 1e-9;
+            if (stage1_run(S1, st)) return ctx->fail(ZK_EDEVICE, "stage1 launch failed: %s", hipGetErrorString(hipGetLastError()));
+            HIPCHK(hipStreamSynchronize(st));   // host descriptor arrays go out of scope
+        }
+    }
+    // non-finite input?
+    for (int i = 0; i < count; i++) {
+        int f = 0;
+        HIPCHK(hipMemcpyAsync(&f, flag[i], 4, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (f) return ctx->fail(ZK_EINVAL, "matrix %d has NaN/Inf entries", i);
+    }
+    return ZK_OK;
+}
+
+template <int L>
+static int run_heev(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out *out, const zk_opts *opts, Stage2Stats *stats)
+{
+    if (!ctx) return ZK_EINVAL;
+    if (ctx->poisoned) return ctx->fail(ZK_EDEVICE, "context poisoned by an earlier device error");
+    if (count < 1 || !A || !out) return ctx->fail(ZK_EINVAL, "count < 1 or NULL arrays");
+    const ResolvedOpts O = resolve(opts, L);
+    for (int i = 0; i < count; i++) {
+        if (check_herm(A[i]) != ZK_OK) return ctx->fail(ZK_EINVAL, "matrix %d: bad n/lda/limbs/planes", i);
+        if (check_out(out[i], A[i].n, A[i].n, L, O.want_vectors) != ZK_OK)
+            return ctx->fail(ZK_EINVAL, "output %d: bad n/limbs/ldv or NULL pointers", i);
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess) return ctx->fail(ZK_EDEVICE, "hipSetDevice failed");
+    std::vector<double *> hf(count), w0(count), V0(count);
+    int rc = run_stage1(ctx, count, A, hf, w0, V0);
+    if (rc != ZK_OK) return rc;
+    std::vector<RqiProb> rp(count);
+    std::vector<int> npair_of(count);
+    std::vector<zk_pair_info *> infos(count);
+    for (int i = 0; i < count; i++) {
+        RqiProb &P = rp[i];
+        std::memset(&P, 0, sizeof P);
+        P.n = A[i].n;
+        P.limbs_in = A[i].limbs;
+        P.hf = hf[i];
+        P.w0 = w0[i];
+        P.V0 = V0[i];
+        P.ldv0 = A[i].n;
+        P.hnorm = 0.0;
+        P.ldv_out = out[i].ldv;
+        for (int l = 0; l < L; l++) {
+            P.w_out[l] = out[i].w[l];
+            P.v_out[l] = O.want_vectors ? (double *)out[i].v[l] : nullptr;
+        }
+        npair_of[i] = A[i].n;
+        infos[i] = out[i].info;
+    }
+    return run_stage2<L>(ctx, rp, npair_of, infos, O, stats);
+}
+
+extern "C" int zk_heev_fp64(zk_ctx *ctx, int count, const zk_herm *A, double *const *w, void *const *V, const int *ldv)
+{
+    if (!ctx) return ZK_EINVAL;
+    if (ctx->poisoned) return ctx->fail(ZK_EDEVICE, "context poisoned by an earlier device error");
+    if (count < 1 || !A || !w || !V || !ldv) return ctx->fail(ZK_EINVAL, "count < 1 or NULL arrays");
+    for (int i = 0; i < count; i++) {
+        if (check_herm(A[i]) != ZK_OK) return ctx->fail(ZK_EINVAL, "matrix %d: bad n/lda/limbs/planes", i);
+        if (!w[i] || !V[i] || ldv[i] < A[i].n) return ctx->fail(ZK_EINVAL, "output %d: NULL or ldv < n", i);
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess) return ctx->fail(ZK_EDEVICE, "hipSetDevice failed");
+    std::vector<double *> hf(count), w0(count), V0(count);
+    int rc = run_stage1(ctx, count, A, hf, w0, V0);
+    if (rc != ZK_OK) return rc;
+    hipStream_t st = ctx->stream;
+    for (int i = 0; i < count; i++) {
+        const int n = A[i].n;
+        HIPCHK(hipMemcpyAsync(w[i], w0[i], 8 * (size_t)n, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpy2DAsync(V[i], 16 * (size_t)ldv[i], V0[i], 16 * (size_t)n, 16 * (size_t)n, n, hipMemcpyDeviceToDevice, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    return ZK_OK;
+}
+
+extern "C" int zk_heev_dd(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out *out, const zk_opts *opts)
+{
+    return run_heev<2>(ctx, count, A, out, opts, nullptr);
+}
+
+extern "C" int zk_heev_qd(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out *out, const zk_opts *opts)
+{
+    return run_heev<4>(ctx, count, A, out, opts, nullptr);
+}
+
+// ====================================================== rqi_refine ========
+template <int L>
+static int run_refine(zk_ctx *ctx, const zk_herm *A, int k, const double *w0, const void *V0, int ldv0,
+                      zk_eig_out *out, const zk_opts *opts)
+{
+    if (!ctx) return ZK_EINVAL;
+    if (ctx->poisoned) return ctx->fail(ZK_EDEVICE, "context poisoned by an earlier device error");
+    if (!A || !out || !w0 || !V0) return ctx->fail(ZK_EINVAL, "NULL argument");
+    if (check_herm(*A) != ZK_OK) return ctx->fail(ZK_EINVAL, "bad n/lda/limbs/planes");
+    const ResolvedOpts O = resolve(opts, L);
+    if (k < 1 || k > A->n || ldv0 < A->n) return ctx->fail(ZK_EINVAL, "bad k or ldv0");
+    if (check_out(*out, k, A->n, L, O.want_vectors) != ZK_OK) return ctx->fail(ZK_EINVAL, "bad output descriptor");
+    if (hipSetDevice(ctx->device) != hipSuccess) return ctx->fail(ZK_EDEVICE, "hipSetDevice failed");
+    hipStream_t st = ctx->stream;
+    const int n = A->n;
+    int rc;
+    if ((rc = ctx->ensure(ctx->s2in, s2in_bytes(n, A->limbs))) != ZK_OK) return rc;
+    char *b = (char *)ctx->s2in.p;
+    double *hf = (double *)b;
+    b += align_up(8 * 2 * (size_t)A->limbs * (size_t)n * n);
+    b += align_up(8 * (size_t)n) + align_up(16 * (size_t)n * n);
+    int *flag = (int *)b;
+    HIPCHK(hipMemsetAsync(flag, 0, 4, st));
+    const double *pl[4] = {nullptr, nullptr, nullptr, nullptr};
+    for (int l = 0; l < A->limbs; l++) pl[l] = (const double *)A->plane[l];
+    if (stage2_ingest(n, A->lda, A->limbs, pl, hf, flag, st)) return ctx->fail(ZK_EDEVICE, "ingest launch failed");
+    int f = 0;
+    HIPCHK(hipMemcpyAsync(&f, flag, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (f) return ctx->fail(ZK_EINVAL, "input has NaN/Inf entries");
+    std::vector<RqiProb> rp(1);
+    RqiProb &P = rp[0];
+    std::memset(&P, 0, sizeof P);
+    P.n = n;
+    P.limbs_in = A->limbs;
+    P.hf = hf;
+    P.w0 = w0;
+    P.V0 = (const double *)V0;
+    P.ldv0 = ldv0;
+    P.ldv_out = out->ldv;
+    for (int l = 0; l < L; l++) {
+        P.w_out[l] = out->w[l];
+        P.v_out[l] = O.want_vectors ? (double *)out->v[l] : nullptr;
+    }
+    std::vector<int> npair_of(1, k);
+    std::vector<zk_pair_info *> infos(1, out->info);
+    return run_stage2<L>(ctx, rp, npair_of, infos, O, nullptr);
+}
+
+extern "C" int zk_rqi_refine(zk_ctx *ctx, int limbs_out, const zk_herm *A, int k, const double *w0, const void *V0,
+                             int ldv0, zk_eig_out *out, const zk_opts *opts)
+{
+    if (limbs_out == 2) return run_refine<2>(ctx, A, k, w0, V0, ldv0, out, opts);
+    if (limbs_out == 4) return run_refine<4>(ctx, A, k, w0, V0, ldv0, out, opts);
+    if (ctx) ctx->fail(ZK_EINVAL, "limbs_out must be 2 or 4");
+    return ZK_EINVAL;
+}
+
+// statistics entry used by the benchmark (not part of the public header)
+extern "C" int zk_heev_stats(zk_ctx *ctx, int limbs_out, int count, const zk_herm *A, zk_eig_out *out,
+                             const zk_opts *opts, int *iters_hist16, int *rounds, long long *solves)
+{
+    Stage2Stats s;
+    int rc = (limbs_out == 4) ? run_heev<4>(ctx, count, A, out, opts, &s) : run_heev<2>(ctx, count, A, out, opts, &s);
+    if (iters_hist16)
+        for (int i = 0; i < 16; i++) iters_hist16[i] = s.iters_hist[i];
+    if (rounds) *rounds = s.rounds;
+    if (solves) *solves = s.solves;
+    return rc;
+}

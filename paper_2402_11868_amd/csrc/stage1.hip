@@ -1,0 +1,717 @@
+// Stage 1 of the method: binary64 eigendecomposition of a batch of complex
+// Hermitian matrices of equal order (the double-precision part of the paper's
+// GPU routine, Sec. 2 "ZKCM_CUS"; the routine names no algorithm, the one
+// here is the classical two-phase reduction).
+//
+//   ingest     limb sum -> binary64 working copy, limb-planar full copy for
+//              stage 2, NaN/Inf scan
+//   hetrd      blocked Householder tridiagonalisation, lower triangle:
+//              per column a panel update + reflector (norm accumulated in
+//              double-double), a tiled Hermitian matrix-vector product that
+//              reads every lower-triangle element once and uses it for both
+//              A and A^H, and the W-vector finish; per panel a rank-2*NB
+//              trailing update C -= [V W][W V]^H on FP64 MFMA
+//   stebz      Sturm-count bisection, one thread per eigenvalue
+//   stein      inverse iteration, one thread per eigenvalue, then modified
+//              Gram-Schmidt inside clusters (one wave per cluster)
+//   unmtr      back-transformation V = Q Z with compact-WY block reflectors,
+//              three FP64-MFMA GEMMs per panel
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+#include "stage.h"
+
+namespace zk {
+
+// ------------------------------------------------------------- helpers ----
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ __forceinline__ double2 cmulc(double2 a, double2 b) { return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x); }  // conj(a) b
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+
+__device__ __forceinline__ double2 wave_sum2(double2 v)
+{
+    v.x = wave_sum(v.x);
+    v.y = wave_sum(v.y);
+    return v;
+}
+
+// ---------------------------------------------------------------- ingest --
+// grid (n columns, nprob), block 256: lower triangle of column j.
+__global__ void k_ingest(ProbDesc *probs)
+{
+    const ProbDesc &P = probs[blockIdx.y];
+    const int n = P.n, j = blockIdx.x;
+    if (j >= n) return;
+    const size_t nn = (size_t)n * n;
+    int bad = 0;
+    for (int i = j + threadIdx.x; i < n; i += blockDim.x) {
+        double re = 0.0, im = 0.0;
+        for (int l = 0; l < P.limbs_in; l++) {
+            const double2 z = ld2(P.in[l] + 2 * ((size_t)j * P.lda_in + i));
+            if (!isfinite(z.x) || !isfinite(z.y)) bad = 1;
+            const double zi = (i == j) ? 0.0 : z.y;
+            re += z.x;
+            im += zi;
+            P.hf[(2 * l) * nn + (size_t)j * n + i] = z.x;
+            P.hf[(2 * l + 1) * nn + (size_t)j * n + i] = zi;
+            if (i != j) {
+                P.hf[(2 * l) * nn + (size_t)i * n + j] = z.x;
+                P.hf[(2 * l + 1) * nn + (size_t)i * n + j] = -zi;
+            }
+        }
+        st2(P.A + 2 * ((size_t)j * n + i), make_double2(re, im));
+    }
+    if (bad) atomicOr(P.flag, 1);
+}
+
+// zero P and Q (n x 2NB complex each) of every problem; grid (ceil(2*NB*n/256), nprob)
+__global__ void k_zero_panel(ProbDesc *probs)
+{
+    const ProbDesc &P = probs[blockIdx.y];
+    const size_t cnt = (size_t)2 * kNB * P.n * 2;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < cnt; t += (size_t)gridDim.x * blockDim.x) {
+        P.P[t] = 0.0;
+        P.Q[t] = 0.0;
+    }
+}
+
+// ------------------------------------------------- column update + larfg --
+// One block (256 threads) per problem.  Column c = k0 + i of the panel.
+__global__ void __launch_bounds__(256) k_trd_col(ProbDesc *probs, int c, int k0)
+{
+    const ProbDesc &P = probs[blockIdx.x];
+    const int n = P.n, i = c - k0;
+    __shared__ double2 sVc[kNB], sWc[kNB];   // row c of V and W (conjugated later)
+    __shared__ dd red_dd[16];
+    __shared__ double2 s_scale;
+    const int tid = threadIdx.x;
+    if (tid < i) {
+        sVc[tid] = ld2(P.P + 2 * ((size_t)tid * n + c));
+        sWc[tid] = ld2(P.P + 2 * ((size_t)(kNB + tid) * n + c));
+    }
+    __syncthreads();
+    // 1. a[r,c] -= sum_j V[r,j] conj(W[c,j]) + W[r,j] conj(V[c,j]),  r >= c
+    dd nrm = mp_zero<2>();
+    for (int r = c + tid; r < n; r += blockDim.x) {
+        double2 a = ld2(P.A + 2 * ((size_t)c * n + r));
+        for (int j = 0; j < i; j++) {
+            const double2 v = ld2(P.P + 2 * ((size_t)j * n + r));
+            const double2 w = ld2(P.P + 2 * ((size_t)(kNB + j) * n + r));
+            a = csub(a, cadd(cmul(v, make_double2(sWc[j].x, -sWc[j].y)), cmul(w, make_double2(sVc[j].x, -sVc[j].y))));
+        }
+        if (r == c) a.y = 0.0;
+        st2(P.A + 2 * ((size_t)c * n + r), a);
+        if (r >= c + 2) {
+            // |x_r|^2 in double-double (exact squares)
+            double p, e;
+            two_prod(a.x, a.x, p, e);
+            nrm = dd_add(nrm, dd{{p, e}});
+            two_prod(a.y, a.y, p, e);
+            nrm = dd_add(nrm, dd{{p, e}});
+        }
+    }
+    const dd xn2 = block_sum_mp<2>(nrm, red_dd);   // includes a barrier: column c is written
+    if (tid == 0) {
+        const double2 diag = ld2(P.A + 2 * ((size_t)c * n + c));
+        P.d[c] = diag.x;
+        const double2 alpha = ld2(P.A + 2 * ((size_t)c * n + c + 1));
+        double2 tau = make_double2(0.0, 0.0);
+        double beta = alpha.x;
+        double2 scale = make_double2(0.0, 0.0);
+        if (!(xn2.x[0] == 0.0 && alpha.y == 0.0)) {
+            // beta = -sign(Re alpha) * sqrt(|alpha|^2 + ||x||^2), the norm in double-double
+            double p, e;
+            dd s = xn2;
+            two_prod(alpha.x, alpha.x, p, e);
+            s = dd_add(s, dd{{p, e}});
+            two_prod(alpha.y, alpha.y, p, e);
+            s = dd_add(s, dd{{p, e}});
+            const dd rt = dd_sqrt(s);
+            beta = (alpha.x >= 0.0) ? -rt.x[0] : rt.x[0];
+            tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+            // scale = 1 / (alpha - beta)
+            const double2 den = make_double2(alpha.x - beta, alpha.y);
+            const double m2 = den.x * den.x + den.y * den.y;
+            scale = make_double2(den.x / m2, -den.y / m2);
+        }
+        P.e[c] = beta;
+        st2(P.tau + 2 * c, tau);
+        s_scale = scale;
+    }
+    __syncthreads();
+    const double2 sc = s_scale;
+    // 2. reflector v (v[c+1] = 1) into Y[:, c], V column i of P, V column NB+i of Q
+    for (int r = c + 1 + tid; r < n; r += blockDim.x) {
+        double2 v;
+        if (r == c + 1) v = make_double2(1.0, 0.0);
+        else v = cmul(ld2(P.A + 2 * ((size_t)c * n + r)), sc);
+        st2(P.Y + 2 * ((size_t)c * n + r), v);
+        st2(P.P + 2 * ((size_t)i * n + r), v);
+        st2(P.Q + 2 * ((size_t)(kNB + i) * n + r), v);
+    }
+}
+
+// --------------------------------------------------------------- hemv -----
+// y = A22 v with A22 = A[c+1:, c+1:] (lower triangle), v = Y[c+1:, c].
+// grid (T(T+1)/2 tiles, nprob), block 256; tile (I, J), I >= J, 64 x 64,
+// staged once in LDS and used for the direct (A) and mirrored (A^H) parts.
+// Partial sums: part[J][row] (direct) and part[T + I][col] (mirror).
+__global__ void __launch_bounds__(256) k_trd_hemv(ProbDesc *probs, int c)
+{
+    const ProbDesc &P = probs[blockIdx.y];
+    const int n = P.n, base = c + 1, m = n - base;
+    if (m <= 0) return;
+    const int T = (m + 63) / 64;
+    const int t = blockIdx.x;
+    if (t >= T * (T + 1) / 2) return;
+    int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while (I * (I + 1) / 2 > t) I--;
+    while ((I + 1) * (I + 2) / 2 <= t) I++;
+    const int J = t - I * (I + 1) / 2;
+    __shared__ double2 tile[64][65];
+    __shared__ double2 vI[64], vJ[64];
+    __shared__ double2 red[4][64];
+    const int tid = threadIdx.x;
+    const double2 *A = reinterpret_cast<const double2 *>(P.A);
+    const double2 *Yc = reinterpret_cast<const double2 *>(P.Y) + (size_t)c * n + base;
+    // load tile: column jj (0..63) of the tile, rows ii
+    for (int q = tid; q < 64 * 64; q += 256) {
+        const int ii = q & 63, jj = q >> 6;
+        const int gi = I * 64 + ii, gj = J * 64 + jj;
+        double2 a = make_double2(0.0, 0.0);
+        if (gi < m && gj < m && gi >= gj) {
+            a = A[(size_t)(base + gj) * n + base + gi];
+            if (gi == gj) a.y = 0.0;
+        }
+        tile[ii][jj] = a;
+    }
+    if (tid < 64) {
+        const int gi = I * 64 + tid, gj = J * 64 + tid;
+        vI[tid] = gi < m ? Yc[gi] : make_double2(0.0, 0.0);
+        vJ[tid] = gj < m ? Yc[gj] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    const int lane = tid & 63, grp = tid >> 6;
+    // direct: row ii = lane, columns grp*16 .. +16
+    {
+        double2 s = make_double2(0.0, 0.0);
+        for (int jj = grp * 16; jj < grp * 16 + 16; jj++) {
+            const bool use = (I != J) || (jj <= lane);
+            if (use) s = cadd(s, cmul(tile[lane][jj], vJ[jj]));
+        }
+        red[grp][lane] = s;
+    }
+    __syncthreads();
+    if (tid < 64) {
+        const int gi = I * 64 + tid;
+        double2 s = cadd(cadd(red[0][tid], red[1][tid]), cadd(red[2][tid], red[3][tid]));
+        if (gi < m) st2(P.part + 2 * ((size_t)J * n + base + gi), s);
+    }
+    __syncthreads();
+    // mirror: column jj = lane, rows grp*16 .. +16, strictly below the diagonal
+    {
+        double2 s = make_double2(0.0, 0.0);
+        for (int ii = grp * 16; ii < grp * 16 + 16; ii++) {
+            const bool use = (I != J) || (ii > lane);
+            if (use) s = cadd(s, cmulc(tile[ii][lane], vI[ii]));
+        }
+        red[grp][lane] = s;
+    }
+    __syncthreads();
+    if (tid < 64) {
+        const int gj = J * 64 + tid;
+        double2 s = cadd(cadd(red[0][tid], red[1][tid]), cadd(red[2][tid], red[3][tid]));
+        if (gj < m) st2(P.part + 2 * ((size_t)(T + I) * n + base + gj), s);
+    }
+}
+
+// ------------------------------------------------------------- w finish ---
+// One block (256) per problem: y = sum of partials - V (W^H v) - W (V^H v);
+// w = tau y; w += (-tau/2 w^H v) v; store W column i into P[:, NB+i] and Q[:, i].
+__global__ void __launch_bounds__(256) k_trd_wfin(ProbDesc *probs, int c, int k0)
+{
+    const ProbDesc &P = probs[blockIdx.x];
+    const int n = P.n, base = c + 1, m = n - base, i = c - k0;
+    if (m <= 0) return;
+    const int T = (m + 63) / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    __shared__ double2 t1[kNB], t2[kNB];
+    __shared__ double2 redc[4];
+    const double2 *Pv = reinterpret_cast<const double2 *>(P.P);
+    double2 *Pw = reinterpret_cast<double2 *>(P.P);
+    const double2 *Yc = reinterpret_cast<const double2 *>(P.Y) + (size_t)c * n;
+    // dot products t1_j = W_j^H v, t2_j = V_j^H v (j < i); wave wid handles j = wid, wid+4, ...
+    for (int j = wid; j < i; j += 4) {
+        double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+        for (int r = base + lane; r < n; r += 64) {
+            const double2 v = Yc[r];
+            a = cadd(a, cmulc(Pv[(size_t)(kNB + j) * n + r], v));
+            b = cadd(b, cmulc(Pv[(size_t)j * n + r], v));
+        }
+        a = wave_sum2(a);
+        b = wave_sum2(b);
+        if (lane == 0) {
+            t1[j] = a;
+            t2[j] = b;
+        }
+    }
+    __syncthreads();
+    const double2 tau = ld2(P.tau + 2 * c);
+    // y and w^H v
+    double2 acc = make_double2(0.0, 0.0);
+    const int per = (m + 255) / 256;   // rows per thread (<= 16 for n <= 4096)
+    double2 wloc[16];
+    for (int q = 0; q < per && q < 16; q++) {
+        const int r = base + tid + 256 * q;
+        double2 y = make_double2(0.0, 0.0);
+        if (r < n) {
+            const int b = (r - base) / 64;
+            for (int J = 0; J <= b; J++) y = cadd(y, ld2(P.part + 2 * ((size_t)J * n + r)));
+            for (int I2 = b; I2 < T; I2++) y = cadd(y, ld2(P.part + 2 * ((size_t)(T + I2) * n + r)));
+            for (int j = 0; j < i; j++) {
+                y = csub(y, cmul(Pv[(size_t)j * n + r], t1[j]));
+                y = csub(y, cmul(Pv[(size_t)(kNB + j) * n + r], t2[j]));
+            }
+            y = cmul(tau, y);
+            acc = cadd(acc, cmulc(y, Yc[r]));
+        }
+        wloc[q] = y;
+    }
+    acc = wave_sum2(acc);
+    __syncthreads();
+    if (lane == 0) redc[wid] = acc;
+    __syncthreads();
+    const double2 wv = cadd(cadd(redc[0], redc[1]), cadd(redc[2], redc[3]));
+    const double2 alpha = cmul(make_double2(-0.5 * tau.x, -0.5 * tau.y), wv);
+    for (int q = 0; q < per && q < 16; q++) {
+        const int r = base + tid + 256 * q;
+        if (r < n) {
+            const double2 w = cadd(wloc[q], cmul(alpha, Yc[r]));
+            Pw[(size_t)(kNB + i) * n + r] = w;
+            reinterpret_cast<double2 *>(P.Q)[(size_t)i * n + r] = w;
+        }
+    }
+}
+
+// --------------------------------------------------------- MFMA ZGEMM -----
+// C(MxN) = alpha * op(A) op(B) + beta * C, complex128, column-major.
+// op 0 = N, 1 = C (conjugate transpose).  lower != 0: only tiles that
+// intersect the lower triangle (row >= col) are computed (her2k).
+// Block 256 = 4 waves, tile 64 x 64, each wave 32 x 32 = 2 x 2 MFMA blocks
+// of v_mfma_f64_16x16x4f64; a complex product is four real MFMAs.
+// Operand layout of the 16x16x4 f64 MFMA (wave64): lane l holds A[l%16][l/16]
+// and B[l/16][l%16]; the 4 accumulator values of lane l are D[4r + l/16][l%16].
+__device__ __forceinline__ double2 opA_ld(const double2 *A, int lda, int op, int i, int k, int M, int K)
+{
+    if (i >= M || k >= K) return make_double2(0.0, 0.0);
+    if (op == 0) return A[(size_t)k * lda + i];
+    const double2 a = A[(size_t)i * lda + k];
+    return make_double2(a.x, -a.y);
+}
+
+__device__ __forceinline__ double2 opB_ld(const double2 *B, int ldb, int op, int k, int j, int K, int N)
+{
+    if (k >= K || j >= N) return make_double2(0.0, 0.0);
+    if (op == 0) return B[(size_t)j * ldb + k];
+    const double2 b = B[(size_t)k * ldb + j];
+    return make_double2(b.x, -b.y);
+}
+
+__global__ void __launch_bounds__(256) k_zgemm(const GemmDesc *descs, int M, int N, int K, int opA, int opB,
+                                               double2 alpha, double2 beta, int lower)
+{
+    const GemmDesc &G = descs[blockIdx.y];
+    const int tilesM = (M + 63) / 64;
+    const int tm = blockIdx.x % tilesM, tn = blockIdx.x / tilesM;
+    const int row0 = tm * 64, col0 = tn * 64;
+    if (lower && row0 + 63 < col0) return;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int wr = row0 + (wid & 1) * 32, wc = col0 + (wid >> 1) * 32;
+    const double2 *A = reinterpret_cast<const double2 *>(G.A);
+    const double2 *B = reinterpret_cast<const double2 *>(G.B);
+    f64x4 cre[2][2], cim[2][2];
+    for (int a = 0; a < 2; a++)
+        for (int b = 0; b < 2; b++) {
+            cre[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+            cim[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+        }
+    const int li = lane & 15, lk = lane >> 4;
+    for (int k0 = 0; k0 < K; k0 += 4) {
+        double2 av[2], bv[2];
+        for (int a = 0; a < 2; a++) av[a] = opA_ld(A, G.lda, opA, wr + a * 16 + li, k0 + lk, M, K);
+        for (int b = 0; b < 2; b++) bv[b] = opB_ld(B, G.ldb, opB, k0 + lk, wc + b * 16 + li, K, N);
+        for (int a = 0; a < 2; a++) {
+            const double nai = -av[a].y;
+            for (int b = 0; b < 2; b++) {
+                cre[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].x, bv[b].x, cre[a][b], 0, 0, 0);
+                cre[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai, bv[b].y, cre[a][b], 0, 0, 0);
+                cim[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].x, bv[b].y, cim[a][b], 0, 0, 0);
+                cim[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].y, bv[b].x, cim[a][b], 0, 0, 0);
+            }
+        }
+    }
+    double2 *C = reinterpret_cast<double2 *>(G.C);
+    for (int a = 0; a < 2; a++)
+        for (int b = 0; b < 2; b++)
+            for (int r = 0; r < 4; r++) {
+                const int i = wr + a * 16 + 4 * r + lk, j = wc + b * 16 + li;
+                if (i >= M || j >= N) continue;
+                if (lower && i < j) continue;
+                const double2 ab = make_double2(cre[a][b][r], cim[a][b][r]);
+                double2 out = cmul(alpha, ab);
+                if (beta.x != 0.0 || beta.y != 0.0) out = cadd(out, cmul(beta, C[(size_t)j * G.ldc + i]));
+                C[(size_t)j * G.ldc + i] = out;
+            }
+}
+
+// ------------------------------------------------------------- bisection --
+// One thread per eigenvalue index k: Sturm count bisection on (d, e).
+__device__ int sturm_count(const double *d, const double *e, int n, double x, double pivmin)
+{
+    int cnt = 0;
+    double q = d[0] - x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    if (q < 0.0) cnt++;
+    for (int i = 1; i < n; i++) {
+        q = d[i] - x - (e[i - 1] * e[i - 1]) / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        if (q < 0.0) cnt++;
+    }
+    return cnt;
+}
+
+__global__ void k_bisect(ProbDesc *probs)
+{
+    const ProbDesc &P = probs[blockIdx.y];
+    const int n = P.n;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    double gl = P.d[0], gu = P.d[0], emax = 0.0;
+    for (int i = 0; i < n; i++) {
+        const double r = (i > 0 ? fabs(P.e[i - 1]) : 0.0) + (i < n - 1 ? fabs(P.e[i]) : 0.0);
+        gl = fmin(gl, P.d[i] - r);
+        gu = fmax(gu, P.d[i] + r);
+        if (i < n - 1) emax = fmax(emax, fabs(P.e[i]));
+    }
+    const double tnorm = fmax(fabs(gl), fabs(gu));
+    const double pivmin = fmax(2.2250738585072014e-308, 2.2250738585072014e-308 * emax * emax);
+    const double eps = 1.1102230246251565e-16;
+    double lo = gl - 2.0 * eps * tnorm - 2.0 * pivmin, hi = gu + 2.0 * eps * tnorm + 2.0 * pivmin;
+    for (int it = 0; it < 200; it++) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid == lo || mid == hi) break;
+        if (hi - lo <= 2.0 * eps * fmax(fabs(lo), fabs(hi)) + pivmin) break;
+        if (sturm_count(P.d, P.e, n, mid, pivmin) > k) hi = mid;
+        else lo = mid;
+    }
+    P.w0[k] = 0.5 * (lo + hi);
+}
+
+// ------------------------------------------------------ inverse iteration --
+// One thread per eigenvalue k: three inverse iterations with the tridiagonal
+// LU (partial pivoting) of T - lam I from a hashed pseudo-random start.  Work
+// arrays are interleaved across eigenvalues (entry i of eigenvalue k at
+// [i*n + k]) so neighbouring threads touch neighbouring addresses.  Output
+// Zt[i*n + k], scaled to max-norm 1 (the cluster Gram-Schmidt normalises).
+__device__ __forceinline__ double hash_uniform(uint64_t x)
+{
+    // SplitMix64 finaliser (Steele, Lea, Flood 2014) -> uniform in (-1, 1)
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    x ^= x >> 31;
+    return ((double)(x >> 11) * (1.0 / 9007199254740992.0)) * 2.0 - 1.0;
+}
+
+__global__ void k_invit(ProbDesc *probs)
+{
+    const ProbDesc &P = probs[blockIdx.y];
+    const int n = P.n;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const size_t nn = (size_t)n * n;
+    double *U0 = P.tri, *U1 = P.tri + nn, *U2 = P.tri + 2 * nn, *LM = P.tri + 3 * nn, *FL = P.tri + 4 * nn;
+    double *X = P.Zt;
+    const double lam = P.w0[k];
+    double tnorm = 0.0;
+    for (int i = 0; i < n; i++)
+        tnorm = fmax(tnorm, fabs(P.d[i]) + (i > 0 ? fabs(P.e[i - 1]) : 0.0) + (i < n - 1 ? fabs(P.e[i]) : 0.0));
+    const double guard = fmax(tnorm, 1e-300) * 1.1102230246251565e-16;
+    // P L U factorisation of T - lam I by Gaussian elimination with partial
+    // pivoting.  The row being eliminated always has two entries (a at
+    // column i, b at column i+1); U row i has up to three (u0, u1, u2).
+    double a = P.d[0] - lam, b = (n > 1) ? P.e[0] : 0.0;
+    for (int i = 0; i < n - 1; i++) {
+        const double sub = P.e[i];                                  // T[i+1][i]
+        const double na = P.d[i + 1] - lam;                         // T[i+1][i+1]
+        const double nb = (i + 1 < n - 1) ? P.e[i + 1] : 0.0;       // T[i+1][i+2]
+        const size_t o = (size_t)i * n + k;
+        if (fabs(a) >= fabs(sub)) {
+            double piv = a;
+            if (fabs(piv) < guard) piv = (piv < 0.0) ? -guard : guard;
+            const double l = sub / piv;
+            U0[o] = piv; U1[o] = b; U2[o] = 0.0; LM[o] = l; FL[o] = 0.0;
+            a = na - l * b;
+            b = nb;
+        } else {
+            const double l = a / sub;
+            U0[o] = sub; U1[o] = na; U2[o] = nb; LM[o] = l; FL[o] = 1.0;
+            a = b - l * na;
+            b = -l * nb;
+        }
+    }
+    double last = a;
+    if (fabs(last) < guard) last = (last < 0.0) ? -guard : guard;
+    for (int i = 0; i < n; i++) X[(size_t)i * n + k] = hash_uniform(((uint64_t)k << 32) ^ (uint64_t)i ^ 0x5bd1e995ull);
+    for (int it = 0; it < 3; it++) {
+        for (int i = 0; i < n - 1; i++) {
+            const size_t o = (size_t)i * n + k;
+            double xi = X[o], xj = X[o + n];
+            if (FL[o] != 0.0) {
+                const double t = xi;
+                xi = xj;
+                xj = t;
+                X[o] = xi;
+            }
+            X[o + n] = xj - LM[o] * xi;
+        }
+        double x1 = 0.0, x2 = 0.0, smax = 0.0;
+        for (int i = n - 1; i >= 0; i--) {
+            const size_t o = (size_t)i * n + k;
+            const double u0 = (i == n - 1) ? last : U0[o];
+            const double u1 = (i < n - 1) ? U1[o] : 0.0;
+            const double u2 = (i < n - 2) ? U2[o] : 0.0;
+            const double xi = (X[o] - u1 * x1 - u2 * x2) / u0;
+            X[o] = xi;
+            x2 = x1;
+            x1 = xi;
+            smax = fmax(smax, fabs(xi));
+        }
+        const double inv = (smax > 0.0) ? 1.0 / smax : 1.0;
+        for (int i = 0; i < n; i++) X[(size_t)i * n + k] *= inv;
+    }
+}
+
+// Zt (row-interleaved) -> Z (column-major) ; grid (ceil(n/16), ceil(n/16), nprob), block 16x16
+__global__ void k_transpose(ProbDesc *probs)
+{
+    const ProbDesc &P = probs[blockIdx.z];
+    const int n = P.n;
+    __shared__ double t[16][17];
+    const double *src = P.Zt;
+    const int i0 = blockIdx.x * 16, k0 = blockIdx.y * 16;
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    if (i0 + ty < n && k0 + tx < n) t[ty][tx] = src[(size_t)(i0 + ty) * n + k0 + tx];
+    __syncthreads();
+    if (k0 + ty < n && i0 + tx < n) P.Z[(size_t)(k0 + ty) * n + i0 + tx] = t[tx][ty];
+}
+
+// Modified Gram-Schmidt inside clusters of the binary64 spectrum, one wave
+// per eigenvalue index; only the wave of a cluster's first index works.
+// Cluster: consecutive eigenvalues closer than gap_rel * ||T||.
+__global__ void k_tri_orth(ProbDesc *probs, double gap_rel)
+{
+    const ProbDesc &P = probs[blockIdx.y];
+    const int n = P.n;
+    const int k = blockIdx.x;
+    if (k >= n) return;
+    const int lane = threadIdx.x;
+    double tn = fmax(fabs(P.w0[0]), fabs(P.w0[n - 1]));
+    const double thr = gap_rel * fmax(tn, 1e-300);
+    if (k > 0 && P.w0[k] - P.w0[k - 1] <= thr) return;   // not a cluster start
+    int end = k + 1;
+    while (end < n && P.w0[end] - P.w0[end - 1] <= thr) end++;
+    for (int j = k; j < end; j++) {
+        double *zj = P.Z + (size_t)j * n;
+        for (int pass = 0; pass < 2; pass++) {
+            for (int q = k; q < j; q++) {
+                const double *zq = P.Z + (size_t)q * n;
+                double s = 0.0;
+                for (int i = lane; i < n; i += 64) s += zq[i] * zj[i];
+                s = wave_sum(s);
+                for (int i = lane; i < n; i += 64) zj[i] -= s * zq[i];
+            }
+        }
+        double s = 0.0;
+        for (int i = lane; i < n; i += 64) s += zj[i] * zj[i];
+        s = wave_sum(s);
+        const double inv = (s > 0.0) ? 1.0 / sqrt(s) : 0.0;
+        for (int i = lane; i < n; i += 64) zj[i] *= inv;
+        if (s == 0.0 && lane == 0) zj[j] = 1.0;
+    }
+}
+
+// ----------------------------------------------------------- back-transform
+// V0 = complex(Z); grid (ceil(n*n/256), nprob)
+__global__ void k_init_v0(ProbDesc *probs)
+{
+    const ProbDesc &P = probs[blockIdx.y];
+    const size_t nn = (size_t)P.n * P.n;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < nn; t += (size_t)gridDim.x * blockDim.x)
+        st2(P.V0 + 2 * t, make_double2(P.Z[t], 0.0));
+}
+
+// Block-reflector factor T of every panel (forward, columnwise):
+// T[i][i] = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] (Y_p[:, 0:i]^H y_i).
+// grid (npanels, nprob), block 64 (one wave).
+__global__ void k_larft(ProbDesc *probs)
+{
+    const ProbDesc &P = probs[blockIdx.y];
+    const int n = P.n, p = blockIdx.x;
+    const int k0 = p * kNB;
+    if (k0 >= n - 1) return;
+    const int nbw = min(kNB, n - 1 - k0);
+    const int lane = threadIdx.x;
+    double2 *T = reinterpret_cast<double2 *>(P.T) + (size_t)p * kNB * kNB;   // column-major nbw x nbw, ld NB
+    const double2 *Y = reinterpret_cast<const double2 *>(P.Y);
+    __shared__ double2 g[kNB];
+    for (int q = lane; q < kNB * kNB; q += 64) T[q] = make_double2(0.0, 0.0);
+    __syncthreads();
+    for (int i = 0; i < nbw; i++) {
+        const int ci = k0 + i;
+        const double2 tau = ld2(P.tau + 2 * ci);
+        // g_j = y_j^H y_i for j < i (rows ci+1.. where y_i is nonzero)
+        for (int j = 0; j < i; j++) {
+            double2 s = make_double2(0.0, 0.0);
+            for (int r = ci + 1 + lane; r < n; r += 64) s = cadd(s, cmulc(Y[(size_t)(k0 + j) * n + r], Y[(size_t)ci * n + r]));
+            s = wave_sum2(s);
+            if (lane == 0) g[j] = s;
+        }
+        __syncthreads();
+        if (lane < i) {
+            // T[lane, i] = -tau * sum_{j} T[lane, j] g_j   (T upper triangular, j >= lane)
+            double2 s = make_double2(0.0, 0.0);
+            for (int j = lane; j < i; j++) s = cadd(s, cmul(T[(size_t)j * kNB + lane], g[j]));
+            T[(size_t)i * kNB + lane] = cmul(make_double2(-tau.x, -tau.y), s);
+        }
+        if (lane == 0) T[(size_t)i * kNB + i] = tau;
+        __syncthreads();
+    }
+}
+
+// 1 x 1 matrices: eigenvalue = diagonal, eigenvector = 1
+__global__ void k_n1(ProbDesc *probs, int np)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    const ProbDesc &P = probs[p];
+    const double a = P.A[0];
+    P.d[0] = a;
+    P.w0[0] = a;
+    P.Z[0] = 1.0;
+    P.V0[0] = 1.0;
+    P.V0[1] = 0.0;
+}
+
+__global__ void k_last_diag(ProbDesc *probs, int np)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    const ProbDesc &P = probs[p];
+    const int n = P.n;
+    P.d[n - 1] = P.A[2 * ((size_t)(n - 1) * n + n - 1)];
+}
+
+// ===================================================================== host
+static inline unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
+
+size_t stage1_gemm_desc_count(int n, int np)
+{
+    const int npan = (n - 1 + kNB - 1) / kNB;
+    return (size_t)np * (size_t)(4 * npan + 1);
+}
+
+// Fill the host array of GEMM descriptors: for panel p, slot 4p = her2k,
+// 4p+1..4p+3 = the three back-transformation products.
+void stage1_fill_gemm_descs(const ProbDesc *hp, int np, GemmDesc *out)
+{
+    const int n = hp[0].n;
+    const int npan = (n - 1 + kNB - 1) / kNB;
+    for (int p = 0; p < npan; p++) {
+        const int k0 = p * kNB;
+        const int nbw = std::min(kNB, n - 1 - k0);
+        const int r0 = k0 + nbw;
+        for (int q = 0; q < np; q++) {
+            const ProbDesc &P = hp[q];
+            GemmDesc *g = out + (size_t)(4 * p) * np + q;
+            g->A = P.P + 2 * (size_t)r0;
+            g->B = P.Q + 2 * (size_t)r0;
+            g->C = P.A + 2 * ((size_t)r0 * n + r0);
+            g->lda = n; g->ldb = n; g->ldc = n;
+            g = out + (size_t)(4 * p + 1) * np + q;   // X = Yp^H V0[k0+1:, :]
+            g->A = P.Y + 2 * ((size_t)k0 * n + k0 + 1);
+            g->B = P.V0 + 2 * (size_t)(k0 + 1);
+            g->C = P.X;
+            g->lda = n; g->ldb = n; g->ldc = kNB;
+            g = out + (size_t)(4 * p + 2) * np + q;   // X2 = T_p X
+            g->A = P.T + 2 * (size_t)p * kNB * kNB;
+            g->B = P.X;
+            g->C = P.X2;
+            g->lda = kNB; g->ldb = kNB; g->ldc = kNB;
+            g = out + (size_t)(4 * p + 3) * np + q;   // V0[k0+1:, :] -= Yp X2
+            g->A = P.Y + 2 * ((size_t)k0 * n + k0 + 1);
+            g->B = P.X2;
+            g->C = P.V0 + 2 * (size_t)(k0 + 1);
+            g->lda = n; g->ldb = kNB; g->ldc = n;
+        }
+    }
+}
+
+int stage1_run(const Stage1Batch &B, hipStream_t st)
+{
+    const int n = B.n, np = B.nprob;
+    ProbDesc *pd = B.dev_probs;
+    const GemmDesc *gd = B.dev_gemm;
+    if (n < 1 || np < 1) return 0;
+    hipLaunchKernelGGL(k_ingest, dim3(n, np), dim3(256), 0, st, pd);
+    if (n == 1) {
+        hipLaunchKernelGGL(k_n1, dim3(cdiv(np, 64)), dim3(64), 0, st, pd, np);
+        return hipGetLastError() == hipSuccess ? 0 : -1;
+    }
+    // ---- tridiagonalisation
+    const int npan = (n - 1 + kNB - 1) / kNB;
+    for (int p = 0; p < npan; p++) {
+        const int k0 = p * kNB;
+        const int nbw = std::min(kNB, n - 1 - k0);
+        hipLaunchKernelGGL(k_zero_panel, dim3(cdiv((size_t)2 * kNB * n * 2, 256), np), dim3(256), 0, st, pd);
+        for (int i = 0; i < nbw; i++) {
+            const int c = k0 + i;
+            hipLaunchKernelGGL(k_trd_col, dim3(np), dim3(256), 0, st, pd, c, k0);
+            const int m = n - c - 1;
+            const int T = (m + 63) / 64;
+            hipLaunchKernelGGL(k_trd_hemv, dim3(T * (T + 1) / 2, np), dim3(256), 0, st, pd, c);
+            hipLaunchKernelGGL(k_trd_wfin, dim3(np), dim3(256), 0, st, pd, c, k0);
+        }
+        const int r0 = k0 + nbw;
+        const int m = n - r0;
+        if (m > 0) {
+            const unsigned tiles = cdiv(m, 64) * cdiv(m, 64);
+            hipLaunchKernelGGL(k_zgemm, dim3(tiles, np), dim3(256), 0, st, gd + (size_t)(4 * p) * np, m, m, 2 * kNB, 0, 1,
+                               make_double2(-1.0, 0.0), make_double2(1.0, 0.0), 1);
+        }
+    }
+    hipLaunchKernelGGL(k_last_diag, dim3(cdiv(np, 64)), dim3(64), 0, st, pd, np);
+    // ---- tridiagonal eigen-solver
+    hipLaunchKernelGGL(k_bisect, dim3(cdiv(n, 128), np), dim3(128), 0, st, pd);
+    hipLaunchKernelGGL(k_invit, dim3(cdiv(n, 64), np), dim3(64), 0, st, pd);
+    hipLaunchKernelGGL(k_transpose, dim3(cdiv(n, 16), cdiv(n, 16), np), dim3(16, 16), 0, st, pd);
+    hipLaunchKernelGGL(k_tri_orth, dim3(n, np), dim3(64), 0, st, pd, B.tri_gap_rel);
+    // ---- back-transformation
+    hipLaunchKernelGGL(k_init_v0, dim3(cdiv((size_t)n * n, 256), np), dim3(256), 0, st, pd);
+    hipLaunchKernelGGL(k_larft, dim3(npan, np), dim3(64), 0, st, pd);
+    for (int p = npan - 1; p >= 0; p--) {
+        const int k0 = p * kNB;
+        const int nbw = std::min(kNB, n - 1 - k0);
+        const int m = n - k0 - 1;
+        hipLaunchKernelGGL(k_zgemm, dim3(cdiv(nbw, 64) * cdiv(n, 64), np), dim3(256), 0, st, gd + (size_t)(4 * p + 1) * np,
+                           nbw, n, m, 1, 0, make_double2(1.0, 0.0), make_double2(0.0, 0.0), 0);
+        hipLaunchKernelGGL(k_zgemm, dim3(cdiv(nbw, 64) * cdiv(n, 64), np), dim3(256), 0, st, gd + (size_t)(4 * p + 2) * np,
+                           nbw, n, nbw, 0, 0, make_double2(1.0, 0.0), make_double2(0.0, 0.0), 0);
+        hipLaunchKernelGGL(k_zgemm, dim3(cdiv(m, 64) * cdiv(n, 64), np), dim3(256), 0, st, gd + (size_t)(4 * p + 3) * np,
+                           m, n, nbw, 0, 0, make_double2(-1.0, 0.0), make_double2(1.0, 0.0), 0);
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace zk

@@ -1,0 +1,861 @@
+// Stage 2 of the method: Rayleigh quotient iteration in double-double (L=2)
+// or quad-double (L=4) arithmetic that recovers the precision of the binary64
+// eigenpairs (Sec. 2, ZKCM_CUS paragraph: RQI is used "to recover the
+// precision" after the double-precision solver).  For each pair k:
+//
+//   v <- binary64 eigenvector, sigma <- v^H H v
+//   repeat:  solve (H - sigma I) w = v     shifted LU, partial pivoting, L limbs
+//            Gram-Schmidt w against the converged members of its eigenvalue
+//            cluster and the lower-index members of the same iteration (twice)
+//            v <- w / ||w||,  y = H v,  sigma <- v^H y,  r = y - sigma v
+//   until ||r|| <= tol ||H||_2  (or the iteration limit / stagnation)
+//
+// Kernels (each launch covers every active pair of the batch):
+//   build      M = [H - sigma I | v], limb-planar
+//   lu_panel   one work-group per pair factorises an n x NB panel
+//   lu_trsm    applies the panel's row interchanges to the trailing columns
+//              and computes U12 = L11^{-1} A12, one thread per column
+//   lu_update  A22 -= L21 U12: the O(n^3) part; a 64x64 (dd) or 32x32 (qd)
+//              output tile per work-group, operands staged in LDS, every
+//              product accumulated error-free into a (sum, compensation) pair
+//   backsolve  w = U^{-1} y (y = transformed right-hand side, column n)
+//   gs, rq     as above; rq also decides convergence on the device
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+#include "stage.h"
+
+namespace zk {
+
+// limb-planar accessors: plane (c*L + l), c = 0 real / 1 imaginary
+template <int L>
+__device__ __forceinline__ cmp<L> ld_cmp(const double *base, size_t plane, size_t idx)
+{
+    cmp<L> z;
+    for (int l = 0; l < L; l++) {
+        z.re.x[l] = base[(size_t)l * plane + idx];
+        z.im.x[l] = base[(size_t)(L + l) * plane + idx];
+    }
+    return z;
+}
+
+template <int L>
+__device__ __forceinline__ void st_cmp(double *base, size_t plane, size_t idx, const cmp<L> &z)
+{
+    for (int l = 0; l < L; l++) {
+        base[(size_t)l * plane + idx] = z.re.x[l];
+        base[(size_t)(L + l) * plane + idx] = z.im.x[l];
+    }
+}
+
+// H(i, j) of a problem as an L-limb complex value (limb sum of the input planes)
+template <int L>
+__device__ __forceinline__ cmp<L> ld_h(const RqiProb &P, int i, int j)
+{
+    const size_t nn = (size_t)P.n * P.n, o = (size_t)j * P.n + i;
+    cmp<L> z;
+    z.re = mp_from<L>(P.hf[o]);
+    z.im = mp_from<L>(P.hf[nn + o]);
+    for (int l = 1; l < P.limbs_in; l++) {
+        z.re = add_d(z.re, P.hf[(2 * l) * nn + o]);
+        z.im = add_d(z.im, P.hf[(2 * l + 1) * nn + o]);
+    }
+    return z;
+}
+
+template <int L>
+__device__ __forceinline__ mp<L> ld_sigma(const RqiProb &P, int k)
+{
+    mp<L> s;
+    for (int l = 0; l < L; l++) s.x[l] = P.sigma[(size_t)l * P.n + k];
+    return s;
+}
+
+// ----------------------------------------------------- error-free accumulator
+// (S, C): S accumulates the leading products through TwoSum, C the exact
+// product errors, the cross terms and the TwoSum errors.  One real product
+// x*y of two double-doubles costs 13 binary64 operations.
+__device__ __forceinline__ void acc_dd(double &S, double &C, double xh, double xl, double yh, double yl)
+{
+    const double p = xh * yh;
+    const double e = fma(xh, yh, -p);
+    const double c = fma(xh, yl, xl * yh);
+    const double s = S + p;
+    const double bb = s - S;
+    const double t = (S - (s - bb)) + (p - bb);
+    S = s;
+    C += t + (e + c);
+}
+
+__device__ __forceinline__ dd acc_dd_final(double S, double C)
+{
+    dd r;
+    two_sum(S, C, r.x[0], r.x[1]);
+    return r;
+}
+
+// ================================================================ init ====
+// v_k <- binary64 eigenvector (exact), sigma_k <- binary64 eigenvalue.
+// grid (npairs), block 256.
+template <int L>
+__global__ void k_s2_init(PairDesc *pairs, RqiProb *probs)
+{
+    PairDesc &Q = pairs[blockIdx.x];
+    const RqiProb &P = probs[Q.prob];
+    const int n = P.n, k = Q.k;
+    const size_t nn = (size_t)n * n;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double2 z = ld2(P.V0 + 2 * ((size_t)k * P.ldv0 + i));
+        cmp<L> c;
+        c.re = mp_from<L>(z.x);
+        c.im = mp_from<L>(z.y);
+        st_cmp<L>(P.vec, nn, (size_t)k * n + i, c);
+    }
+    if (threadIdx.x == 0) {
+        const mp<L> s = mp_from<L>(P.w0[k]);
+        for (int l = 0; l < L; l++) P.sigma[(size_t)l * n + k] = s.x[l];
+        Q.status = 0;
+        Q.iters = 0;
+        Q.flags = 0;
+        Q.resid = INFINITY;
+        Q.prev_resid = INFINITY;
+    }
+}
+
+// ============================================================== normalise ==
+template <int L>
+__device__ void normalise_vec(double *vec, size_t nn, int n, int k, mp<L> *red)
+{
+    mp<L> s = mp_zero<L>();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s = add(s, c_abs2(ld_cmp<L>(vec, nn, (size_t)k * n + i)));
+    s = block_sum_mp<L>(s, red);
+    if (!(s.x[0] > 0.0)) return;
+    const mp<L> inv = div(mp_from<L>(1.0), sqrt_mp(s));
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const size_t o = (size_t)k * n + i;
+        st_cmp<L>(vec, nn, o, c_scale(ld_cmp<L>(vec, nn, o), inv));
+    }
+    __syncthreads();
+}
+
+// ================================================================== GS ====
+// One work-group (256) per cluster: members in index order; an active member
+// is orthogonalised (twice) against every converged member and every active
+// member of lower index, then normalised.
+template <int L>
+__global__ void __launch_bounds__(256) k_s2_gs(PairDesc *pairs, RqiProb *probs, const int *heads)
+{
+    const int h = heads[blockIdx.x];
+    const int csz = pairs[h].cl_size;
+    const RqiProb &P = probs[pairs[h].prob];
+    const int n = P.n;
+    const size_t nn = (size_t)n * n;
+    __shared__ mp<L> red[16];
+    constexpr int CH = 256;   // coefficients per chunk
+    __shared__ cmp<L> coef[CH];
+    __shared__ int jidx[CH];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    bool any = false;
+    for (int a = 0; a < csz; a++) {
+        if (pairs[h + a].status == 0) any = true;
+    }
+    if (!any) return;
+    for (int a = 0; a < csz; a++) {
+        PairDesc &Qa = pairs[h + a];
+        if (Qa.status != 0) continue;
+        const int ka = Qa.k;
+        normalise_vec<L>(P.vec, nn, n, ka, red);
+        if (csz > 1) {
+            bool did = false;
+            for (int pass = 0; pass < 2; pass++) {
+                // eligible partners in chunks of CH
+                int b0 = 0;
+                while (b0 < csz) {
+                    // collect up to CH eligible indices from b0
+                    __syncthreads();
+                    int cnt = 0;
+                    int b = b0;
+                    if (tid == 0) {
+                        while (b < csz && cnt < CH) {
+                            const PairDesc &Qb = pairs[h + b];
+                            if (b != a && (Qb.status == 1 || (b < a && Qb.status == 0))) jidx[cnt++] = Qb.k;
+                            b++;
+                        }
+                        red[0].x[0] = (double)cnt;
+                        red[1].x[0] = (double)b;
+                    }
+                    __syncthreads();
+                    cnt = (int)red[0].x[0];
+                    b0 = (int)red[1].x[0];
+                    __syncthreads();
+                    if (cnt == 0) continue;
+                    did = true;
+                    // coefficients c_j = v_j^H v_a, one wave per partner
+                    for (int q = wid; q < cnt; q += 4) {
+                        const int kb = jidx[q];
+                        cmp<L> s = c_zero<L>();
+                        for (int i = lane; i < n; i += 64)
+                            s = c_add(s, c_mulc(ld_cmp<L>(P.vec, nn, (size_t)kb * n + i), ld_cmp<L>(P.vec, nn, (size_t)ka * n + i)));
+                        s.re = wave_sum_mp<L>(s.re);
+                        s.im = wave_sum_mp<L>(s.im);
+                        if (lane == 0) coef[q] = s;
+                    }
+                    __syncthreads();
+                    // v_a -= sum_j c_j v_j
+                    for (int i = tid; i < n; i += 256) {
+                        const size_t o = (size_t)ka * n + i;
+                        cmp<L> x = ld_cmp<L>(P.vec, nn, o);
+                        for (int q = 0; q < cnt; q++)
+                            x = c_sub(x, c_mul(coef[q], ld_cmp<L>(P.vec, nn, (size_t)jidx[q] * n + i)));
+                        st_cmp<L>(P.vec, nn, o, x);
+                    }
+                    __syncthreads();
+                }
+            }
+            if (did && tid == 0) Qa.flags |= 2;
+            normalise_vec<L>(P.vec, nn, n, ka, red);
+        }
+    }
+}
+
+// ================================================================== RQ ====
+// One work-group per active pair: y = H v, sigma = Re(v^H y), r = y - sigma v;
+// convergence, stagnation and iteration-limit decisions.
+template <int L>
+__global__ void __launch_bounds__(256) k_s2_rq(PairDesc *pairs, RqiProb *probs, const int *active, int max_iter, int final_pass)
+{
+    PairDesc &Q = pairs[active[blockIdx.x]];
+    const RqiProb &P = probs[Q.prob];
+    const int n = P.n, k = Q.k;
+    const size_t nn = (size_t)n * n;
+    __shared__ mp<L> red[16];
+    __shared__ double redd[16];
+    const double *vec = P.vec;
+    // pass 1: sigma = sum_i Re(conj(v_i) y_i)
+    mp<L> sacc = mp_zero<L>();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        cmp<L> y = c_zero<L>();
+        for (int j = 0; j < n; j++) y = c_add(y, c_mul(ld_h<L>(P, i, j), ld_cmp<L>(vec, nn, (size_t)k * n + j)));
+        const cmp<L> vi = ld_cmp<L>(vec, nn, (size_t)k * n + i);
+        sacc = add(sacc, add(mul(vi.re, y.re), mul(vi.im, y.im)));
+    }
+    const mp<L> sigma = block_sum_mp<L>(sacc, red);
+    // pass 2: ||y - sigma v||^2 (recomputes y to keep registers bounded)
+    double r2 = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        cmp<L> y = c_zero<L>();
+        for (int j = 0; j < n; j++) y = c_add(y, c_mul(ld_h<L>(P, i, j), ld_cmp<L>(vec, nn, (size_t)k * n + j)));
+        const cmp<L> vi = ld_cmp<L>(vec, nn, (size_t)k * n + i);
+        const cmp<L> r = c_sub(y, c_scale(vi, sigma));
+        r2 += r.re.x[0] * r.re.x[0] + r.im.x[0] * r.im.x[0];
+    }
+    r2 = block_sum(r2, redd);
+    if (threadIdx.x == 0) {
+        for (int l = 0; l < L; l++) P.sigma[(size_t)l * n + k] = sigma.x[l];
+        const double res = sqrt(r2) / P.hnorm;
+        Q.prev_resid = Q.resid;
+        Q.resid = res;
+        if (final_pass) {
+            // after the global re-orthogonalisation: re-judge every pair
+            const bool ok = (res == res) && res * P.hnorm <= P.tol_abs;
+            Q.status = ok ? 1 : 2;
+            Q.flags = ok ? (Q.flags | 1) : (Q.flags & ~1);
+        } else if (!(res == res)) {
+            Q.status = 2;
+            Q.flags |= 8;
+        } else if (res * P.hnorm <= P.tol_abs) {
+            Q.status = 1;
+            Q.flags |= 1;
+        } else if (Q.iters >= max_iter) {
+            Q.status = 2;
+        } else if (Q.iters >= 3 && res > 0.5 * Q.prev_resid) {
+            Q.status = 2;   // stagnated above the tolerance
+        }
+    }
+}
+
+// =============================================================== build ====
+// M = [H - sigma I | v]; grid (ceil((n+1)/8), count), block 256.
+template <int L>
+__global__ void __launch_bounds__(256) k_s2_build(Stage2Batch B)
+{
+    const int t = blockIdx.y;
+    const PairDesc &Q = B.dev_pairs[B.dev_active[t]];
+    const RqiProb &P = B.dev_probs[Q.prob];
+    const int n = P.n, k = Q.k, ldm = B.ldm;
+    double *M = B.lu_base + (size_t)t * B.lu_stride;
+    const size_t plane = (size_t)ldm * (n + 1);
+    const size_t nn = (size_t)n * n;
+    const mp<L> sigma = ld_sigma<L>(P, k);
+    for (int jj = 0; jj < 8; jj++) {
+        const int j = blockIdx.x * 8 + jj;
+        if (j > n) break;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            cmp<L> z;
+            if (j < n) {
+                z = ld_h<L>(P, i, j);
+                if (i == j) z.re = sub(z.re, sigma);
+            } else {
+                z = ld_cmp<L>(P.vec, nn, (size_t)k * n + i);
+            }
+            st_cmp<L>(M, plane, (size_t)j * ldm + i, z);
+        }
+    }
+}
+
+// ============================================================ LU panel ====
+// One work-group (256) per pair: columns [k0, k0+nbw), rows [k0, n).
+// Row interchanges are applied inside the panel only; lu_trsm applies them
+// to the trailing columns.
+template <int L>
+__global__ void __launch_bounds__(256) k_s2_lu_panel(Stage2Batch B, int k0, int nbw)
+{
+    const int t = blockIdx.x;
+    PairDesc &Q = B.dev_pairs[B.dev_active[t]];
+    const RqiProb &P = B.dev_probs[Q.prob];
+    const int n = P.n, ldm = B.ldm;
+    double *M = B.lu_base + (size_t)t * B.lu_stride;
+    int *ipiv = B.piv_base + (size_t)t * B.piv_stride;
+    const size_t plane = (size_t)ldm * (n + 1);
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    __shared__ double smax[4];
+    __shared__ int sidx[4];
+    __shared__ int s_piv;
+    __shared__ cmp<L> s_inv;
+    __shared__ cmp<L> s_row[kLuNB];
+    __shared__ int s_guard;
+    if (tid == 0) s_guard = 0;
+    for (int j = 0; j < nbw; j++) {
+        const int c = k0 + j;
+        // pivot search
+        double best = -1.0;
+        int bidx = n;
+        for (int r = c + tid; r < n; r += 256) {
+            const double m = c_mag1(ld_cmp<L>(M, plane, (size_t)c * ldm + r));
+            if (m > best) { best = m; bidx = r; }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ob = __shfl_xor(best, off, 64);
+            const int oi = __shfl_xor(bidx, off, 64);
+            if (ob > best || (ob == best && oi < bidx)) { best = ob; bidx = oi; }
+        }
+        if (lane == 0) { smax[wid] = best; sidx[wid] = bidx; }
+        __syncthreads();
+        if (tid == 0) {
+            double b = smax[0];
+            int bi = sidx[0];
+            for (int w = 1; w < 4; w++)
+                if (smax[w] > b || (smax[w] == b && sidx[w] < bi)) { b = smax[w]; bi = sidx[w]; }
+            if (bi >= n) bi = c;
+            s_piv = bi;
+            ipiv[c] = bi;
+        }
+        __syncthreads();
+        const int p = s_piv;
+        // swap rows c and p inside the panel
+        if (p != c && tid < nbw) {
+            const size_t oc = (size_t)(k0 + tid) * ldm + c, op = (size_t)(k0 + tid) * ldm + p;
+            const cmp<L> a = ld_cmp<L>(M, plane, oc), b = ld_cmp<L>(M, plane, op);
+            st_cmp<L>(M, plane, oc, b);
+            st_cmp<L>(M, plane, op, a);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            cmp<L> u = ld_cmp<L>(M, plane, (size_t)c * ldm + c);
+            if (c_mag1(u) < P.piv_tol) {
+                // zero-pivot guard: replace by the threshold, keeping the phase
+                const double sr = (u.re.x[0] < 0.0) ? -1.0 : 1.0;
+                u.re = mp_from<L>(sr * P.piv_tol);
+                u.im = mp_zero<L>();
+                st_cmp<L>(M, plane, (size_t)c * ldm + c, u);
+                s_guard = 1;
+            }
+            s_inv = c_recip<L>(u);
+        }
+        if (tid > 0 && tid < nbw - j) s_row[tid] = ld_cmp<L>(M, plane, (size_t)(c + tid) * ldm + c);
+        __syncthreads();
+        const cmp<L> inv = s_inv;
+        // scale the column and update the rest of the panel (one row per thread)
+        for (int r = c + 1 + tid; r < n; r += 256) {
+            const cmp<L> l = c_mul(ld_cmp<L>(M, plane, (size_t)c * ldm + r), inv);
+            st_cmp<L>(M, plane, (size_t)c * ldm + r, l);
+            for (int q = 1; q < nbw - j; q++) {
+                const size_t o = (size_t)(c + q) * ldm + r;
+                st_cmp<L>(M, plane, o, c_sub(ld_cmp<L>(M, plane, o), c_mul(l, s_row[q])));
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0 && s_guard) Q.flags |= 4;
+}
+
+// ============================================================= LU trsm ====
+// Trailing columns j in [k0+nbw, n]: apply the panel's interchanges, then
+// U12(:, j) = L11^{-1} A12(:, j).  grid (ceil(ncols/64), count), block 64.
+template <int L>
+__global__ void __launch_bounds__(64) k_s2_lu_trsm(Stage2Batch B, int k0, int nbw)
+{
+    const int t = blockIdx.y;
+    const PairDesc &Q = B.dev_pairs[B.dev_active[t]];
+    const RqiProb &P = B.dev_probs[Q.prob];
+    const int n = P.n, ldm = B.ldm;
+    double *M = B.lu_base + (size_t)t * B.lu_stride;
+    const int *ipiv = B.piv_base + (size_t)t * B.piv_stride;
+    const size_t plane = (size_t)ldm * (n + 1);
+    __shared__ cmp<L> l11[kLuNB][kLuNB];
+    for (int q = threadIdx.x; q < nbw * nbw; q += 64) {
+        const int r = q % nbw, cc = q / nbw;
+        if (r > cc) l11[r][cc] = ld_cmp<L>(M, plane, (size_t)(k0 + cc) * ldm + k0 + r);
+    }
+    __syncthreads();
+    const int j = k0 + nbw + blockIdx.x * 64 + threadIdx.x;
+    if (j > n) return;
+    const size_t col = (size_t)j * ldm;
+    for (int r = 0; r < nbw; r++) {
+        const int p = ipiv[k0 + r];
+        if (p != k0 + r) {
+            const cmp<L> a = ld_cmp<L>(M, plane, col + k0 + r), b = ld_cmp<L>(M, plane, col + p);
+            st_cmp<L>(M, plane, col + k0 + r, b);
+            st_cmp<L>(M, plane, col + p, a);
+        }
+    }
+    for (int r = 1; r < nbw; r++) {
+        cmp<L> x = ld_cmp<L>(M, plane, col + k0 + r);
+        for (int q = 0; q < r; q++) x = c_sub(x, c_mul(l11[r][q], ld_cmp<L>(M, plane, col + k0 + q)));
+        st_cmp<L>(M, plane, col + k0 + r, x);
+    }
+}
+
+// =========================================================== LU update ====
+// A22 -= L21 U12 for rows [r0, n), columns [r0, n] (r0 = k0 + nbw).
+// dd: 64x64 tile per work-group of 256, 4x4 outputs per thread (rows
+// ty + 16a, columns tx + 16b), operands staged in LDS in chunks of KC.
+constexpr int KC = 8;
+
+__global__ void __launch_bounds__(256) k_s2_lu_update_dd(Stage2Batch B, int k0, int nbw)
+{
+    const int t = blockIdx.y;
+    const PairDesc &Q = B.dev_pairs[B.dev_active[t]];
+    const int n = B.dev_probs[Q.prob].n, ldm = B.ldm;
+    double *M = B.lu_base + (size_t)t * B.lu_stride;
+    const size_t plane = (size_t)ldm * (n + 1);
+    const int r0 = k0 + nbw;
+    const int mrows = n - r0, mcols = n + 1 - r0;
+    const int tilesI = (mrows + 63) / 64;
+    const int ti = blockIdx.x % tilesI, tj = blockIdx.x / tilesI;
+    const int i0 = r0 + ti * 64, j0 = r0 + tj * 64;
+    if (ti * 64 >= mrows || tj * 64 >= mcols) return;
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    // planes: 0 re_hi, 1 re_lo, 2 im_hi, 3 im_lo
+    __shared__ double sL[4][KC][64];
+    __shared__ double sU[4][KC][64];
+    double S[4][4][2], C[4][4][2];   // [a][b][re/im]
+    for (int a = 0; a < 4; a++)
+        for (int b = 0; b < 4; b++) {
+            const int i = i0 + ty + 16 * a, j = j0 + tx + 16 * b;
+            double rh = 0.0, rl = 0.0, ih = 0.0, il = 0.0;
+            if (i < n && j <= n) {
+                const size_t o = (size_t)j * ldm + i;
+                rh = M[o]; rl = M[plane + o]; ih = M[2 * plane + o]; il = M[3 * plane + o];
+            }
+            S[a][b][0] = rh; C[a][b][0] = rl;
+            S[a][b][1] = ih; C[a][b][1] = il;
+        }
+    for (int kc = 0; kc < nbw; kc += KC) {
+        __syncthreads();
+        // stage L21[i0:i0+64, k0+kc : +KC] and U12[k0+kc : +KC, j0:j0+64]
+        for (int q = tid; q < KC * 64; q += 256) {
+            const int kk = q >> 6, ii = q & 63;
+            const int kcol = k0 + kc + kk;
+            const int gi = i0 + ii;
+            for (int pl = 0; pl < 4; pl++) {
+                double lv = 0.0, uv = 0.0;
+                if (kc + kk < nbw) {
+                    if (gi < n) lv = M[pl * plane + (size_t)kcol * ldm + gi];
+                    const int gj = j0 + ii;
+                    if (gj <= n) uv = M[pl * plane + (size_t)gj * ldm + kcol];
+                }
+                sL[pl][kk][ii] = lv;
+                sU[pl][kk][ii] = uv;
+            }
+        }
+        __syncthreads();
+        const int kmax = min(KC, nbw - kc);
+        for (int kk = 0; kk < kmax; kk++) {
+            double lrh[4], lrl[4], lih[4], lil[4];
+            double urh[4], url[4], uih[4], uil[4];
+            for (int a = 0; a < 4; a++) {
+                // negated L: the update subtracts
+                lrh[a] = -sL[0][kk][ty + 16 * a]; lrl[a] = -sL[1][kk][ty + 16 * a];
+                lih[a] = sL[2][kk][ty + 16 * a];  lil[a] = sL[3][kk][ty + 16 * a];
+            }
+            for (int b = 0; b < 4; b++) {
+                urh[b] = sU[0][kk][tx + 16 * b]; url[b] = sU[1][kk][tx + 16 * b];
+                uih[b] = sU[2][kk][tx + 16 * b]; uil[b] = sU[3][kk][tx + 16 * b];
+            }
+            for (int a = 0; a < 4; a++)
+                for (int b = 0; b < 4; b++) {
+                    // re -= lr ur - li ui  ->  re += (-lr) ur + li ui
+                    acc_dd(S[a][b][0], C[a][b][0], lrh[a], lrl[a], urh[b], url[b]);
+                    acc_dd(S[a][b][0], C[a][b][0], lih[a], lil[a], uih[b], uil[b]);
+                    // im -= lr ui + li ur  ->  im += (-lr) ui + (-li) ur
+                    acc_dd(S[a][b][1], C[a][b][1], lrh[a], lrl[a], uih[b], uil[b]);
+                    acc_dd(S[a][b][1], C[a][b][1], -lih[a], -lil[a], urh[b], url[b]);
+                }
+        }
+    }
+    for (int a = 0; a < 4; a++)
+        for (int b = 0; b < 4; b++) {
+            const int i = i0 + ty + 16 * a, j = j0 + tx + 16 * b;
+            if (i < n && j <= n) {
+                const size_t o = (size_t)j * ldm + i;
+                const dd re = acc_dd_final(S[a][b][0], C[a][b][0]);
+                const dd im = acc_dd_final(S[a][b][1], C[a][b][1]);
+                M[o] = re.x[0]; M[plane + o] = re.x[1];
+                M[2 * plane + o] = im.x[0]; M[3 * plane + o] = im.x[1];
+            }
+        }
+}
+
+// Generic (quad-double) update: 32x32 tile, 2x2 outputs per thread.
+template <int L>
+__global__ void __launch_bounds__(256) k_s2_lu_update_gen(Stage2Batch B, int k0, int nbw)
+{
+    const int t = blockIdx.y;
+    const PairDesc &Q = B.dev_pairs[B.dev_active[t]];
+    const int n = B.dev_probs[Q.prob].n, ldm = B.ldm;
+    double *M = B.lu_base + (size_t)t * B.lu_stride;
+    const size_t plane = (size_t)ldm * (n + 1);
+    const int r0 = k0 + nbw;
+    const int mrows = n - r0, mcols = n + 1 - r0;
+    const int tilesI = (mrows + 31) / 32;
+    const int ti = blockIdx.x % tilesI, tj = blockIdx.x / tilesI;
+    const int i0 = r0 + ti * 32, j0 = r0 + tj * 32;
+    if (ti * 32 >= mrows || tj * 32 >= mcols) return;
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    __shared__ cmp<L> sL[KC][32];
+    __shared__ cmp<L> sU[KC][32];
+    cmp<L> acc[2][2];
+    for (int a = 0; a < 2; a++)
+        for (int b = 0; b < 2; b++) {
+            const int i = i0 + ty + 16 * a, j = j0 + tx + 16 * b;
+            acc[a][b] = (i < n && j <= n) ? ld_cmp<L>(M, plane, (size_t)j * ldm + i) : c_zero<L>();
+        }
+    for (int kc = 0; kc < nbw; kc += KC) {
+        __syncthreads();
+        for (int q = tid; q < KC * 32; q += 256) {
+            const int kk = q >> 5, ii = q & 31;
+            const int kcol = k0 + kc + kk;
+            cmp<L> lv = c_zero<L>(), uv = c_zero<L>();
+            if (kc + kk < nbw) {
+                if (i0 + ii < n) lv = ld_cmp<L>(M, plane, (size_t)kcol * ldm + i0 + ii);
+                if (j0 + ii <= n) uv = ld_cmp<L>(M, plane, (size_t)(j0 + ii) * ldm + kcol);
+            }
+            sL[kk][ii] = lv;
+            sU[kk][ii] = uv;
+        }
+        __syncthreads();
+        const int kmax = min(KC, nbw - kc);
+        for (int kk = 0; kk < kmax; kk++)
+            for (int a = 0; a < 2; a++)
+                for (int b = 0; b < 2; b++) acc[a][b] = c_sub(acc[a][b], c_mul(sL[kk][ty + 16 * a], sU[kk][tx + 16 * b]));
+    }
+    for (int a = 0; a < 2; a++)
+        for (int b = 0; b < 2; b++) {
+            const int i = i0 + ty + 16 * a, j = j0 + tx + 16 * b;
+            if (i < n && j <= n) st_cmp<L>(M, plane, (size_t)j * ldm + i, acc[a][b]);
+        }
+}
+
+// ========================================================= back-solve ====
+// w = U^{-1} y, y = column n of the factorised augmented matrix; w is scaled
+// by a power of two to max-norm ~1 and written as the new iterate of the pair.
+// One work-group (256) per pair; y is updated in place.
+template <int L>
+__global__ void __launch_bounds__(256) k_s2_backsolve(Stage2Batch B)
+{
+    const int t = blockIdx.x;
+    PairDesc &Q = B.dev_pairs[B.dev_active[t]];
+    const RqiProb &P = B.dev_probs[Q.prob];
+    const int n = P.n, ldm = B.ldm, k = Q.k;
+    double *M = B.lu_base + (size_t)t * B.lu_stride;
+    const size_t plane = (size_t)ldm * (n + 1);
+    const size_t nn = (size_t)n * n;
+    const size_t ycol = (size_t)n * ldm;
+    __shared__ cmp<L> s_w;
+    __shared__ double redd[16];
+    for (int i = n - 1; i >= 0; i--) {
+        if (threadIdx.x == 0) {
+            const cmp<L> y = ld_cmp<L>(M, plane, ycol + i);
+            const cmp<L> w = c_mul(y, c_recip<L>(ld_cmp<L>(M, plane, (size_t)i * ldm + i)));
+            st_cmp<L>(M, plane, ycol + i, w);
+            s_w = w;
+        }
+        __syncthreads();
+        const cmp<L> w = s_w;
+        for (int r = threadIdx.x; r < i; r += 256) {
+            const cmp<L> u = ld_cmp<L>(M, plane, (size_t)i * ldm + r);
+            st_cmp<L>(M, plane, ycol + r, c_sub(ld_cmp<L>(M, plane, ycol + r), c_mul(u, w)));
+        }
+        __syncthreads();
+    }
+    double mx = 0.0;
+    for (int r = threadIdx.x; r < n; r += 256) mx = fmax(mx, c_mag1(ld_cmp<L>(M, plane, ycol + r)));
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) redd[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    mx = fmax(fmax(redd[0], redd[1]), fmax(redd[2], redd[3]));
+    int e = 0;
+    if (mx > 0.0 && isfinite(mx)) frexp(mx, &e);
+    for (int r = threadIdx.x; r < n; r += 256) {
+        cmp<L> w = ld_cmp<L>(M, plane, ycol + r);
+        w.re = ldexp_mp(w.re, -e);
+        w.im = ldexp_mp(w.im, -e);
+        st_cmp<L>(P.vec, nn, (size_t)k * n + r, w);
+    }
+    if (threadIdx.x == 0) Q.iters++;
+}
+
+// ============================================================= output ====
+// Pair k of a matrix goes to output position dst[pair]; limbs copied as is.
+// grid (npairs), block 256.
+template <int L>
+__global__ void k_s2_output(PairDesc *pairs, RqiProb *probs, const int *dst)
+{
+    const int g = blockIdx.x;
+    const PairDesc &Q = pairs[g];
+    const RqiProb &P = probs[Q.prob];
+    const int n = P.n, k = Q.k, pos = dst[g];
+    const size_t nn = (size_t)n * n;
+    if (threadIdx.x < L && P.w_out[threadIdx.x]) P.w_out[threadIdx.x][pos] = P.sigma[(size_t)threadIdx.x * n + k];
+    if (!P.v_out[0]) return;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const cmp<L> z = ld_cmp<L>(P.vec, nn, (size_t)k * n + i);
+        for (int l = 0; l < L; l++)
+            st2(P.v_out[l] + 2 * ((size_t)pos * P.ldv_out + i), make_double2(z.re.x[l], z.im.x[l]));
+    }
+}
+
+// ======================================================= re-orthogonalise
+// Blocked classical Gram-Schmidt over all vectors of a matrix, in index order,
+// applied twice: block [j0, j0+B) is projected against vectors [0, j0)
+// (coefficients C = V_prev^H V_blk, then V_blk -= V_prev C), then made
+// orthonormal inside the block.  Problems of one launch share the order n.
+// Scratch C: per problem j0 x RB complex values, limb-planar (2L planes).
+constexpr int RB = 32;
+
+template <int L>
+__global__ void __launch_bounds__(256) k_ro_dot(RqiProb *probs, const int *plist, int j0, double *scratch, size_t sstride)
+{
+    const RqiProb &P = probs[plist[blockIdx.z]];
+    const int n = P.n;
+    const size_t nn = (size_t)n * n;
+    double *Cm = scratch + (size_t)blockIdx.z * sstride;
+    const size_t cplane = (size_t)j0 * RB;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int i = blockIdx.x * 16 + ty;            // previous vector
+    const int jb = blockIdx.y * 16 + tx;           // block member
+    __shared__ cmp<L> si[16][16], sj[16][16];      // [row][vector]
+    cmp<L> acc = c_zero<L>();
+    for (int r0 = 0; r0 < n; r0 += 16) {
+        __syncthreads();
+        {
+            const int r = r0 + tx;   // row loaded by this thread
+            const int vi = blockIdx.x * 16 + ty, vj = j0 + blockIdx.y * 16 + ty;
+            si[tx][ty] = (r < n && vi < j0) ? ld_cmp<L>(P.vec, nn, (size_t)vi * n + r) : c_zero<L>();
+            sj[tx][ty] = (r < n && vj < j0 + RB && vj < n) ? ld_cmp<L>(P.vec, nn, (size_t)vj * n + r) : c_zero<L>();
+        }
+        __syncthreads();
+        for (int q = 0; q < 16; q++) acc = c_add(acc, c_mulc(si[q][ty], sj[q][tx]));
+    }
+    if (i < j0 && jb < RB) st_cmp<L>(Cm, cplane, (size_t)jb * j0 + i, acc);
+}
+
+template <int L>
+__global__ void __launch_bounds__(256) k_ro_update(RqiProb *probs, const int *plist, int j0, const double *scratch, size_t sstride)
+{
+    const RqiProb &P = probs[plist[blockIdx.z]];
+    const int n = P.n;
+    const size_t nn = (size_t)n * n;
+    const double *Cm = scratch + (size_t)blockIdx.z * sstride;
+    const size_t cplane = (size_t)j0 * RB;
+    const int r = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int jb = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int j = j0 + jb;
+    if (r >= n || j >= n || jb >= RB) return;
+    cmp<L> x = ld_cmp<L>(P.vec, nn, (size_t)j * n + r);
+    for (int i = 0; i < j0; i++) x = c_sub(x, c_mul(ld_cmp<L>(Cm, cplane, (size_t)jb * j0 + i), ld_cmp<L>(P.vec, nn, (size_t)i * n + r)));
+    st_cmp<L>(P.vec, nn, (size_t)j * n + r, x);
+}
+
+// inside the block: modified Gram-Schmidt (twice) and normalisation; one
+// work-group per problem, coefficients of a member computed by the four waves
+template <int L>
+__global__ void __launch_bounds__(256) k_ro_intra(RqiProb *probs, const int *plist, int j0)
+{
+    const RqiProb &P = probs[plist[blockIdx.x]];
+    const int n = P.n;
+    const size_t nn = (size_t)n * n;
+    const int bw = min(RB, n - j0);
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    __shared__ mp<L> red[16];
+    __shared__ cmp<L> coef[RB];
+    for (int a = 0; a < bw; a++) {
+        const int ka = j0 + a;
+        for (int pass = 0; pass < 2; pass++) {
+            if (a == 0) break;
+            for (int q = wid; q < a; q += 4) {
+                cmp<L> s = c_zero<L>();
+                for (int i = lane; i < n; i += 64)
+                    s = c_add(s, c_mulc(ld_cmp<L>(P.vec, nn, (size_t)(j0 + q) * n + i), ld_cmp<L>(P.vec, nn, (size_t)ka * n + i)));
+                s.re = wave_sum_mp<L>(s.re);
+                s.im = wave_sum_mp<L>(s.im);
+                if (lane == 0) coef[q] = s;
+            }
+            __syncthreads();
+            for (int i = tid; i < n; i += 256) {
+                const size_t o = (size_t)ka * n + i;
+                cmp<L> x = ld_cmp<L>(P.vec, nn, o);
+                for (int q = 0; q < a; q++) x = c_sub(x, c_mul(coef[q], ld_cmp<L>(P.vec, nn, (size_t)(j0 + q) * n + i)));
+                st_cmp<L>(P.vec, nn, o, x);
+            }
+            __syncthreads();
+        }
+        normalise_vec<L>(P.vec, nn, n, ka, red);
+    }
+}
+
+template <int L>
+int stage2_reorth(RqiProb *probs, const int *plist, int nprob, int n, double *scratch, size_t sstride, hipStream_t st)
+{
+    for (int j0 = 0; j0 < n; j0 += RB) {
+        for (int pass = 0; pass < 2 && j0 > 0; pass++) {
+            hipLaunchKernelGGL(k_ro_dot<L>, dim3((j0 + 15) / 16, RB / 16, nprob), dim3(256), 0, st, probs, plist, j0, scratch, sstride);
+            hipLaunchKernelGGL(k_ro_update<L>, dim3((n + 63) / 64, RB / 4, nprob), dim3(256), 0, st, probs, plist, j0,
+                               (const double *)scratch, sstride);
+        }
+        hipLaunchKernelGGL(k_ro_intra<L>, dim3(nprob), dim3(256), 0, st, probs, plist, j0);
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template int stage2_reorth<2>(RqiProb *, const int *, int, int, double *, size_t, hipStream_t);
+template int stage2_reorth<4>(RqiProb *, const int *, int, int, double *, size_t, hipStream_t);
+
+// ================================================================ host ====
+static inline unsigned cdiv2(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
+
+template <int L>
+int stage2_init(PairDesc *pairs, RqiProb *probs, int npairs, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_s2_init<L>, dim3(npairs), dim3(256), 0, st, pairs, probs);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int L>
+int stage2_gs(PairDesc *pairs, RqiProb *probs, const int *heads, int nclusters, hipStream_t st)
+{
+    if (nclusters <= 0) return 0;
+    hipLaunchKernelGGL(k_s2_gs<L>, dim3(nclusters), dim3(256), 0, st, pairs, probs, heads);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int L>
+int stage2_rq(const Stage2Batch &B, hipStream_t st)
+{
+    if (B.count <= 0) return 0;
+    hipLaunchKernelGGL(k_s2_rq<L>, dim3(B.count), dim3(256), 0, st, B.dev_pairs, B.dev_probs, B.dev_active, B.max_iter,
+                       B.final_pass);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int L>
+int stage2_solve(const Stage2Batch &B, hipStream_t st)
+{
+    const int n = B.n, cnt = B.count;
+    if (cnt <= 0) return 0;
+    hipLaunchKernelGGL(k_s2_build<L>, dim3(cdiv2(n + 1, 8), cnt), dim3(256), 0, st, B);
+    for (int k0 = 0; k0 < n; k0 += kLuNB) {
+        const int nbw = std::min(kLuNB, n - k0);
+        hipLaunchKernelGGL(k_s2_lu_panel<L>, dim3(cnt), dim3(256), 0, st, B, k0, nbw);
+        const int r0 = k0 + nbw;
+        const int ncols = n + 1 - r0;
+        hipLaunchKernelGGL(k_s2_lu_trsm<L>, dim3(cdiv2(ncols, 64), cnt), dim3(64), 0, st, B, k0, nbw);
+        const int mrows = n - r0;
+        if (mrows > 0) {
+            if (L == 2) {
+                const unsigned tiles = cdiv2(mrows, 64) * cdiv2(ncols, 64);
+                hipLaunchKernelGGL(k_s2_lu_update_dd, dim3(tiles, cnt), dim3(256), 0, st, B, k0, nbw);
+            } else {
+                const unsigned tiles = cdiv2(mrows, 32) * cdiv2(ncols, 32);
+                hipLaunchKernelGGL(k_s2_lu_update_gen<L>, dim3(tiles, cnt), dim3(256), 0, st, B, k0, nbw);
+            }
+        }
+    }
+    hipLaunchKernelGGL(k_s2_backsolve<L>, dim3(cnt), dim3(256), 0, st, B);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int L>
+int stage2_output(PairDesc *pairs, RqiProb *probs, const int *dst, int npairs, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_s2_output<L>, dim3(npairs), dim3(256), 0, st, pairs, probs, dst);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template int stage2_init<2>(PairDesc *, RqiProb *, int, hipStream_t);
+template int stage2_init<4>(PairDesc *, RqiProb *, int, hipStream_t);
+template int stage2_gs<2>(PairDesc *, RqiProb *, const int *, int, hipStream_t);
+template int stage2_gs<4>(PairDesc *, RqiProb *, const int *, int, hipStream_t);
+template int stage2_rq<2>(const Stage2Batch &, hipStream_t);
+template int stage2_rq<4>(const Stage2Batch &, hipStream_t);
+template int stage2_solve<2>(const Stage2Batch &, hipStream_t);
+template int stage2_solve<4>(const Stage2Batch &, hipStream_t);
+template int stage2_output<2>(PairDesc *, RqiProb *, const int *, int, hipStream_t);
+template int stage2_output<4>(PairDesc *, RqiProb *, const int *, int, hipStream_t);
+
+// ------------------------------------------------------------- ingest -----
+struct IngestArgs {
+    int n, lda, limbs;
+    const double *pl[4];
+    double *hf;
+    int *flag;
+};
+
+__global__ void k_s2_ingest(IngestArgs a)
+{
+    const int n = a.n, j = blockIdx.x;
+    if (j >= n) return;
+    const size_t nn = (size_t)n * n;
+    int bad = 0;
+    for (int i = j + threadIdx.x; i < n; i += blockDim.x) {
+        for (int l = 0; l < a.limbs; l++) {
+            const double2 z = ld2(a.pl[l] + 2 * ((size_t)j * a.lda + i));
+            if (!isfinite(z.x) || !isfinite(z.y)) bad = 1;
+            const double zi = (i == j) ? 0.0 : z.y;
+            a.hf[(2 * l) * nn + (size_t)j * n + i] = z.x;
+            a.hf[(2 * l + 1) * nn + (size_t)j * n + i] = zi;
+            if (i != j) {
+                a.hf[(2 * l) * nn + (size_t)i * n + j] = z.x;
+                a.hf[(2 * l + 1) * nn + (size_t)i * n + j] = -zi;
+            }
+        }
+    }
+    if (bad) atomicOr(a.flag, 1);
+}
+
+int stage2_ingest(int n, int lda, int limbs, const double *const *planes, double *hf, int *flag, hipStream_t st)
+{
+    IngestArgs a;
+    a.n = n;
+    a.lda = lda;
+    a.limbs = limbs;
+    for (int l = 0; l < 4; l++) a.pl[l] = l < limbs ? planes[l] : nullptr;
+    a.hf = hf;
+    a.flag = flag;
+    hipLaunchKernelGGL(k_s2_ingest, dim3(n), dim3(256), 0, st, a);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace zk

@@ -1,0 +1,41 @@
+// Host build of the product's multi-limb arithmetic header, exported with C
+// linkage so the tests can compare every operation with exact rationals.
+#include "../../paper_2402_11868_amd/csrc/mp.h"
+
+using namespace zk;
+
+extern "C" {
+void t_two_sum(double a, double b, double *s, double *e) { two_sum(a, b, *s, *e); }
+void t_two_prod(double a, double b, double *p, double *e) { two_prod(a, b, *p, *e); }
+
+#define BIN(name, L, fn)                                                       \
+    void name(const double *a, const double *b, double *r)                    \
+    {                                                                          \
+        mp<L> x, y;                                                            \
+        for (int i = 0; i < L; i++) { x.x[i] = a[i]; y.x[i] = b[i]; }          \
+        mp<L> z = fn(x, y);                                                    \
+        for (int i = 0; i < L; i++) r[i] = z.x[i];                             \
+    }
+BIN(t_dd_add, 2, dd_add)
+BIN(t_dd_mul, 2, dd_mul)
+BIN(t_dd_div, 2, dd_div)
+BIN(t_qd_add, 4, qd_add)
+BIN(t_qd_mul, 4, qd_mul)
+BIN(t_qd_div, 4, qd_div)
+
+void t_dd_sqrt(const double *a, double *r) { dd x = {{a[0], a[1]}}; dd z = dd_sqrt(x); r[0] = z.x[0]; r[1] = z.x[1]; }
+void t_qd_sqrt(const double *a, double *r)
+{
+    qd x;
+    for (int i = 0; i < 4; i++) x.x[i] = a[i];
+    qd z = qd_sqrt(x);
+    for (int i = 0; i < 4; i++) r[i] = z.x[i];
+}
+void t_qd_renorm16(const double *t, double *r)
+{
+    double w[16];
+    for (int i = 0; i < 16; i++) w[i] = t[i];
+    qd z = qd_renorm<16>(w);
+    for (int i = 0; i < 4; i++) r[i] = z.x[i];
+}
+}
