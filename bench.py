@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Benchmark of the accurate Hermitian eigendecomposition on one MI355X.
+
+Workload (default): one 1024 x 1024 complex128 Hermitian matrix with
+eigenvalues in clusters of 8 (relative separation 1e-12 inside a cluster,
+cluster centres geometric from 1 down to 2^-50), eigenbasis a product of 1024
+seeded Householder reflectors; binary64 eigendecomposition followed by
+double-double Rayleigh quotient iteration to 1e-30.
+
+One step = one full call of zk_heev_dd on the device-resident matrix (both
+stages, every eigenpair, eigenvectors written).  value = eigenpairs per second
+that pass every gate: eigenvalue error vs the stored 256-bit oracle values and
+the device-computed residual, both <= 1e-30 ||H||_2.
+
+Prints one JSON line.  usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+sys.path.insert(0, os.path.join(ROOT, "tests"))
+
+# MI355X published peaks and unit counts
+FP64_VALU_LANE_OPS = 256 * 64 * 2.4e9     # FP64 vector instructions per second (one per lane per cycle)
+FP64_MFMA_TFLOPS = 78.6
+HBM_GBS = 8000.0
+# binary64 instructions of one complex double-double multiply-add in the LU
+# trailing update (4 real products x 13: two-product, cross terms, two-sum,
+# compensation); counted from the kernel source, see the design notes
+CPLX_DD_FMA_INSTR = 52
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def workload_matrix(name):
+    import workloads as W
+    if name == "c3":
+        wl = W.workload(3)
+        return wl["A"], "c3", {"workload": "herm1024_clustered_dd", "n": 1024, "limbs_in": 1,
+                               "spectrum": "clusters of 8, rel. sep. 1e-12, centres 2^(-50 j/127)",
+                               "eigenbasis": "1024 seeded Householder reflectors", "tol": 1e-30, "output": "dd"}
+    if name == "c1":
+        wl = W.workload(1)
+        return wl["A"], "c1", {"workload": "herm64_dd", "n": 64, "limbs_in": 1, "tol": 1e-30, "output": "dd"}
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(seconds_hint=20.0):
+    """The oracle (MPFR-256 Jacobi, eigenvalues and vectors) on a bounded sample of the same family."""
+    import numpy as np
+    import oracle
+    import workloads as W
+    n = 160
+    j = np.arange(n // 8)[:, None]
+    m = np.arange(8)[None, :]
+    lam = (2.0 ** (-50.0 * j / (n // 8 - 1)) * (1.0 + m * 1e-12)).ravel()
+    A = W.householder_hermitian(lam, seed=W.seed_for(3, 1))
+    threads = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    r = oracle.heev([A], want_vectors=True, nthreads=threads)
+    dt = time.perf_counter() - t0
+    rate_n = n / dt
+    # Jacobi cost per eigenpair grows like n^2 (O(n^3) per sweep, n pairs)
+    rate_1024 = rate_n * (n / 1024.0) ** 2
+    return {"value": rate_1024, "unit": "eigenpairs/s", "cores": threads, "kind": "oracle",
+            "sample": f"MPFR-256 cyclic Jacobi (values+vectors) on a {n}x{n} matrix of the same clustered family: "
+                      f"{dt:.1f} s, {rate_n:.2f} eigenpairs/s at n={n}, {r.sweeps} sweeps; value scaled by (n/1024)^2"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path runs on a single "
+              f"MI355X; multi-GPU sharding is described in the design notes but not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2402_11868_amd as Z
+    import golden_io as G
+
+    A, tag, config = workload_matrix(args.workload)
+    n = A.shape[0]
+    gold = None
+    if G.exists(tag):
+        hdr, gold = G.load(tag)
+        if hdr.get("sha256") != G.sha(A):
+            log("golden checksum mismatch: eigenvalue gate disabled")
+            gold = None
+    tol = 1e-30
+    Z.load()
+    ctx = Z.Context(0)
+    Ad = torch.from_numpy(A).to("cuda")
+    log(f"workload {tag} n={n}; warmup {args.warmup}")
+    for _ in range(args.warmup):
+        Z.heev(ctx, [Ad], limbs_out=2)
+    torch.cuda.synchronize()
+    ctx.prof(True)
+    ctx.prof_reset()
+    stats = {}
+    times = []
+    res = None
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    for s in range(args.steps):
+        t0 = time.perf_counter()
+        res, = Z.heev(ctx, [Ad], limbs_out=2, stats=stats)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        log(f"step {s}: {times[-1] * 1e3:.1f} ms, iterations {stats.get('iters_hist')[:8]}")
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_all
+    prof = ctx.prof_read()
+    ctx.prof(False)
+    ms_per_step = 1e3 * total / args.steps
+
+    # gates on the last step's output
+    w = res.w.cpu().numpy()
+    resid = np.array([i["resid"] for i in res.info])
+    ok = resid <= tol
+    eig_err = None
+    if gold is not None:
+        hn = float(np.max(np.abs(gold[0])))
+        d = (w[0] - gold[0]) + (w[1] - gold[1]) - gold[2] - gold[3]
+        # exact enough: limb differences are each exact or tiny, evaluated in binary64 on O(1e-30) quantities
+        err = np.abs(d) / hn
+        ok &= err <= tol
+        eig_err = float(err.max())
+    passing = int(ok.sum())
+    value = passing / (ms_per_step / 1e3)
+
+    # roofline of the dominant kernel: the shifted-LU trailing update (FP64 VALU bound)
+    ms_u, la_u, work_u = prof["lu_update"]
+    achieved = work_u / (ms_u / 1e3) if ms_u > 0 else 0.0             # complex dd multiply-adds per second
+    peak = FP64_VALU_LANE_OPS / CPLX_DD_FMA_INSTR
+    roof = {"bound": "alu", "kernel": "k_s2_lu_update_dd", "achieved": achieved / 1e9, "peak": peak / 1e9,
+            "unit": "G cplx-dd-FMA/s", "frac": achieved / peak if peak else 0.0, "traffic": None,
+            "avg_launch_ms": ms_u / max(la_u, 1), "launches": la_u,
+            "peak_basis": f"256 CU x 64 lanes x 2.4 GHz FP64 VALU / {CPLX_DD_FMA_INSTR} instructions per complex dd FMA"}
+    ms_h, la_h, fl_h = prof["her2k"]
+    ms_v, la_v, by_v = prof["hemv"]
+    phases = {k: round(v[0] / args.steps, 3) for k, v in prof.items()}
+    out = {
+        "metric": "eigenpairs/sec at <=1e-30 rel err (dd), 1024^2 Hermitian",
+        "value": value,
+        "unit": "eigenpairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "dd (f64 pairs)",
+        "data": "synthetic",
+        "config": config,
+        "passing_pairs": passing,
+        "total_pairs": int(n),
+        "max_eig_err_rel": eig_err,
+        "max_resid_rel": float(resid.max()),
+        "iters_hist": stats.get("iters_hist"),
+        "phase_ms_per_step": phases,
+        "roofline": roof,
+        "stage1_mfma": {"her2k_tflops": (fl_h / (ms_h / 1e3) / 1e12) if ms_h > 0 else None,
+                        "frac_of_fp64_mfma": (fl_h / (ms_h / 1e3) / 1e12 / FP64_MFMA_TFLOPS) if ms_h > 0 else None,
+                        "hemv_gbs": (by_v / (ms_v / 1e3) / 1e9) if ms_v > 0 else None},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle sample)")
+        out["cpu_baseline"] = cpu_baseline()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

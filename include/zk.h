@@ -166,6 +166,25 @@ int zk_rqi_refine(zk_ctx *ctx, int limbs_out, const zk_herm *A, int k, const dou
                   const void *V0, int ldv0, zk_eig_out *out, const zk_opts *opts);
 
 /*
+ * Instrumentation.  When enabled, the context records a pair of HIP events on
+ * its stream around every launch of a kernel class and accumulates elapsed
+ * milliseconds, launch counts and the algorithmic work of each launch.
+ * Classes: 0 shifted-LU trailing update (work: complex multi-limb
+ * multiply-adds), 1 LU panel, 2 LU triangular solve + interchanges,
+ * 3 back-substitution, 4 Rayleigh quotient/residual, 5 cluster Gram-Schmidt,
+ * 6 global re-orthogonalisation, 7 whole binary64 stage, 8 FP64-MFMA trailing
+ * update of the tridiagonalisation (work: flops), 9 Hermitian mat-vec of the
+ * tridiagonalisation (work: bytes), 10 shifted-matrix build, 11 column update,
+ * reflector and W-vector of the tridiagonalisation, 12 tridiagonal
+ * eigen-solver (bisection, inverse iteration, Gram-Schmidt), 13
+ * back-transformation (work: flops).
+ * zk_prof_read waits for the recorded events.
+ */
+int zk_prof_enable(zk_ctx *ctx, int on);
+int zk_prof_reset(zk_ctx *ctx);
+int zk_prof_read(zk_ctx *ctx, int kernel_class, double *ms, long long *launches, double *work);
+
+/*
  * Serving form.  A session runs a scheduler thread that admits submitted
  * requests while their workspace fits the session budget, batches the binary64
  * stage of requests of equal order, and runs the Rayleigh quotient iterations

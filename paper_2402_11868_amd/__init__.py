@@ -44,7 +44,10 @@ class ZkOpts(ctypes.Structure):
                 ("cluster_tol", ctypes.c_double), ("want_vectors", ctypes.c_int), ("reorth", ctypes.c_int)]
 
 
-EXPORTED = ["zk_opts_default", "zk_ctx_create", "zk_ctx_destroy", "zk_status_str", "zk_ctx_last_error",
+KERNEL_CLASSES = ["lu_update", "lu_panel", "lu_trsm", "backsolve", "rq", "gs", "reorth", "stage1", "her2k", "hemv",
+                  "build", "trd_vec", "tridiag", "backt"]
+
+EXPORTED = ["zk_prof_enable", "zk_prof_reset", "zk_prof_read", "zk_opts_default", "zk_ctx_create", "zk_ctx_destroy", "zk_status_str", "zk_ctx_last_error",
             "zk_workspace_bytes", "zk_heev_dd", "zk_heev_qd", "zk_heev_fp64", "zk_rqi_refine",
             "zk_session_create", "zk_session_submit", "zk_session_poll", "zk_session_times", "zk_session_destroy"]
 
@@ -77,6 +80,9 @@ def load(path: str = LIB_PATH):
     if hasattr(lib, "zk_heev_stats"):
         lib.zk_heev_stats.argtypes = [P, I, I, ctypes.POINTER(ZkHerm), ctypes.POINTER(ZkEigOut), ctypes.POINTER(ZkOpts),
                                       ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(ctypes.c_longlong)]
+    lib.zk_prof_enable.argtypes = [P, I]
+    lib.zk_prof_reset.argtypes = [P]
+    lib.zk_prof_read.argtypes = [P, I, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(D)]
     if hasattr(lib, "zk_session_create"):
         lib.zk_session_create.argtypes = [P, ctypes.c_size_t, I, ctypes.POINTER(P)]
         lib.zk_session_submit.argtypes = [P, ctypes.POINTER(ZkHerm), ctypes.POINTER(ZkEigOut), I, ctypes.POINTER(ZkOpts),
@@ -120,6 +126,21 @@ class Context:
         if rc != ZK_OK:
             raise RuntimeError(f"zk_ctx_create failed: {status_str(rc)}")
         self.handle = h
+
+    def prof(self, on: bool = True):
+        load().zk_prof_enable(self.handle, int(bool(on)))
+
+    def prof_reset(self):
+        load().zk_prof_reset(self.handle)
+
+    def prof_read(self) -> dict:
+        """{class name: (total ms, launches, algorithmic work)} of the recorded launches."""
+        out = {}
+        for c, name in enumerate(KERNEL_CLASSES):
+            ms, la, wk = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_double()
+            load().zk_prof_read(self.handle, c, ctypes.byref(ms), ctypes.byref(la), ctypes.byref(wk))
+            out[name] = (ms.value, la.value, wk.value)
+        return out
 
     def last_error(self) -> str:
         return load().zk_ctx_last_error(self.handle).decode()
@@ -267,3 +288,63 @@ def rqi_refine(ctx: Context, planes, w0: torch.Tensor, V0: torch.Tensor, limbs_o
     if rc not in (ZK_OK, ZK_ENOCONV):
         raise RuntimeError(f"zk_rqi_refine failed: {status_str(rc)}: {ctx.last_error()}")
     return EigResult(w, V, _info_list(info, k), rc)
+
+
+class Session:
+    """Serving session (continuous batching) on a context; see zk_session_* in zk.h."""
+
+    def __init__(self, ctx: Context, budget: int = 0, max_queue: int = 0):
+        lib = load()
+        h = ctypes.c_void_p()
+        rc = lib.zk_session_create(ctx.handle, ctypes.c_size_t(budget), int(max_queue), ctypes.byref(h))
+        if rc != ZK_OK:
+            raise RuntimeError(f"zk_session_create failed: {status_str(rc)}")
+        self.ctx = ctx
+        self.handle = h
+        self._req = {}
+
+    def submit(self, planes, limbs_out: int = 2, opts: ZkOpts | None = None) -> int:
+        """Queue a request; returns its ticket.  Raises on ZK_EINVAL / ZK_ENOMEM / ZK_EAGAIN."""
+        lib = load()
+        keep: list = []
+        h = herm(planes, keep)
+        want = True if opts is None else bool(opts.want_vectors)
+        o, w, V, info = _alloc_out(h.n, limbs_out, want, ctx_device(planes), keep)
+        t = ctypes.c_uint64()
+        # the column-major copies and outputs must be complete before the scheduler reads them
+        torch.cuda.current_stream().synchronize()
+        rc = lib.zk_session_submit(self.handle, ctypes.byref(h), ctypes.byref(o), limbs_out,
+                                   ctypes.byref(opts) if opts is not None else None, ctypes.byref(t))
+        if rc != ZK_OK:
+            raise RuntimeError(f"zk_session_submit: {status_str(rc)}")
+        self._req[t.value] = (keep, w, V, info, h.n, o, h)
+        return t.value
+
+    def poll(self, ticket: int, timeout_us: int = -1):
+        """(rc, request status): rc ZK_OK when done, ZK_EAGAIN while pending."""
+        st = ctypes.c_int()
+        rc = load().zk_session_poll(self.handle, ctypes.c_uint64(ticket), int(timeout_us), ctypes.byref(st))
+        return rc, st.value
+
+    def times(self, ticket: int):
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        load().zk_session_times(self.handle, ctypes.c_uint64(ticket), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+        return a.value, b.value, c.value
+
+    def result(self, ticket: int) -> EigResult:
+        rc, status = self.poll(ticket, -1)
+        if rc != ZK_OK:
+            raise RuntimeError(f"request {ticket}: {status_str(rc)}")
+        keep, w, V, info, n, o, h = self._req[ticket]
+        return EigResult(w, V, _info_list(info, n), status)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().zk_session_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -13,6 +14,7 @@
 
 #include "../../include/zk.h"
 #include "api_internal.h"
+#include "engine.h"
 #include "stage.h"
 
 using namespace zk;
@@ -83,7 +85,7 @@ extern "C" int zk_ctx_destroy(zk_ctx *ctx)
     return ZK_OK;
 }
 
-size_t zk_ctx::held() const { return s1.bytes + s2in.bytes + s2vec.bytes + s2lu.bytes + meta.bytes; }
+size_t zk_ctx::held() const { return s1.bytes + s2in.bytes + s2vec.bytes + s2lu.bytes + meta.bytes + extra; }
 
 // Grow a workspace buffer (contents are not preserved).  ZK_ENOMEM if the
 // budget would be exceeded.
@@ -189,16 +191,9 @@ static int check_out(const zk_eig_out &o, int n_pairs, int n_rows, int L, bool w
     return ZK_OK;
 }
 
-struct ResolvedOpts {
-    double tol;
-    int max_iter;
-    double cluster_tol;
-    int want_vectors;
-    int init_fp32;
-    int reorth;
-};
 
-static ResolvedOpts resolve(const zk_opts *o, int L)
+
+ResolvedOpts zk_resolve_opts(const zk_opts *o, int L)
 {
     ResolvedOpts r;
     r.tol = (o && o->tol > 0.0) ? o->tol : (L == 2 ? 1e-30 : 1e-60);
@@ -211,271 +206,71 @@ static ResolvedOpts resolve(const zk_opts *o, int L)
     return r;
 }
 
+int zk_check_request(const zk_herm &A, const zk_eig_out &o, int L, bool want_vectors)
+{
+    if (check_herm(A) != ZK_OK) return ZK_EINVAL;
+    return check_out(o, A.n, A.n, L, want_vectors);
+}
+
 // ============================================================ stage 2 ====
-// Shared by zk_heev_* and zk_rqi_refine.  probs[p] must have n, limbs_in,
-// hf, w0, V0, ldv0, w_out, v_out, ldv_out set; npair_of[p] pairs are refined
-// (k = 0 .. npair_of[p]-1).  Fills the info arrays and returns the status.
+// One-shot use of the stage-2 engine: every matrix joins at once, rounds run
+// until all pairs have stopped.
 template <int L>
 static int run_stage2(zk_ctx *ctx, std::vector<RqiProb> &probs, const std::vector<int> &npair_of,
                       std::vector<zk_pair_info *> infos, const ResolvedOpts &O, Stage2Stats *stats)
 {
-    hipStream_t st = ctx->stream;
-    const int np = (int)probs.size();
-    // binary64 eigenvalues -> host: ||H||_2 estimate and clusters
-    std::vector<PairDesc> pairs;
-    std::vector<int> heads;
-    std::vector<double> w0h;
-    int max_n = 0;
-    size_t vec_total = 0;
-    for (int p = 0; p < np; p++) {
-        max_n = std::max(max_n, probs[p].n);
-        vec_total += s2vec_bytes(probs[p].n, L);
+    std::vector<S2Prob> store(probs.size());
+    std::vector<S2Prob *> batch;
+    for (size_t i = 0; i < probs.size(); i++) {
+        store[i].rp = probs[i];
+        store[i].opts = O;
+        store[i].npairs = npair_of[i];
+        store[i].info = infos[i];
+        batch.push_back(&store[i]);
     }
-    for (int p = 0; p < np; p++) {
-        const int kp = npair_of[p];
-        w0h.resize(kp);
-        HIPCHK(hipMemcpyAsync(w0h.data(), probs[p].w0, 8 * (size_t)kp, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        double hn = 0.0;
-        for (int k = 0; k < kp; k++) hn = std::max(hn, std::fabs(w0h[k]));
-        hn = std::max(hn, probs[p].hnorm);   // caller-side lower bound (refinement of a subset)
-        if (!(hn > 0.0)) hn = 1.0;           // zero matrix: absolute tolerances
-        probs[p].hnorm = hn;
-        probs[p].tol_abs = O.tol * hn;
-        probs[p].piv_tol = std::ldexp(hn, -53 * L);
-        const double thr = O.cluster_tol * hn;
-        int start = 0;
-        for (int k = 0; k < kp; k++) {
-            if (k > 0 && !(w0h[k] - w0h[k - 1] <= thr)) start = k;
-            PairDesc q;
-            std::memset(&q, 0, sizeof q);
-            q.prob = p;
-            q.k = k;
-            q.cl_start = start;
-            pairs.push_back(q);
-        }
-        // cluster sizes and heads
-        const size_t base = pairs.size() - kp;
-        int k = 0;
-        while (k < kp) {
-            int e = k + 1;
-            while (e < kp && pairs[base + e].cl_start == k) e++;
-            for (int q = k; q < e; q++) pairs[base + q].cl_size = (q == k) ? e - k : 0;
-            heads.push_back((int)(base + k));
-            k = e;
-        }
-    }
-    const int npairs = (int)pairs.size();
-    // workspace: vec/sigma per problem, meta (pairs, probs, heads, active, dst)
-    int rc;
-    if ((rc = ctx->ensure(ctx->s2vec, vec_total)) != ZK_OK) return rc;
-    const size_t meta_bytes = align_up(sizeof(PairDesc) * npairs) + align_up(sizeof(RqiProb) * np) + 3 * align_up(4 * (size_t)npairs);
-    if ((rc = ctx->ensure(ctx->meta, meta_bytes)) != ZK_OK) return rc;
-    char *vb = (char *)ctx->s2vec.p;
-    for (int p = 0; p < np; p++) {
-        const size_t nn = (size_t)probs[p].n * probs[p].n;
-        probs[p].vec = (double *)vb;
-        vb += align_up(8 * 2 * (size_t)L * nn);
-        probs[p].sigma = (double *)vb;
-        vb += align_up(8 * (size_t)L * probs[p].n);
-    }
-    char *mb = (char *)ctx->meta.p;
-    PairDesc *d_pairs = (PairDesc *)mb;
-    mb += align_up(sizeof(PairDesc) * npairs);
-    RqiProb *d_probs = (RqiProb *)mb;
-    mb += align_up(sizeof(RqiProb) * np);
-    int *d_heads = (int *)mb;
-    mb += align_up(4 * (size_t)npairs);
-    int *d_active = (int *)mb;
-    mb += align_up(4 * (size_t)npairs);
-    int *d_dst = (int *)mb;
-    // cluster sizes live in the head's cl_size; every member needs it only through the head
-    HIPCHK(hipMemcpyAsync(d_pairs, pairs.data(), sizeof(PairDesc) * npairs, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(d_probs, probs.data(), sizeof(RqiProb) * np, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(d_heads, heads.data(), 4 * heads.size(), hipMemcpyHostToDevice, st));
-    // LU slots: as many concurrent factorisations as the budget allows
-    const size_t slot_d = lu_slot_doubles(max_n, L);
-    const size_t slot_bytes = align_up(8 * slot_d);
-    const size_t piv_bytes = align_up(4 * (size_t)max_n);
-    size_t avail = ctx->budget > ctx->held() - ctx->s2lu.bytes ? ctx->budget - (ctx->held() - ctx->s2lu.bytes) : 0;
-    int S = (int)std::min<size_t>((size_t)npairs, avail / (slot_bytes + piv_bytes));
-    if (S < 1) return ctx->fail(ZK_ENOMEM, "one shifted LU of order %d needs %zu bytes", max_n, slot_bytes + piv_bytes);
-    if ((rc = ctx->ensure(ctx->s2lu, (size_t)S * (slot_bytes + piv_bytes))) != ZK_OK) return rc;
-    double *lu_base = (double *)ctx->s2lu.p;
-    int *piv_base = (int *)((char *)ctx->s2lu.p + (size_t)S * slot_bytes);
-
-    if (stage2_init<L>(d_pairs, d_probs, npairs, st)) return ctx->fail(ZK_EDEVICE, "stage2 init launch failed");
-    if (stage2_gs<L>(d_pairs, d_probs, d_heads, (int)heads.size(), st)) return ctx->fail(ZK_EDEVICE, "stage2 gs launch failed");
-    std::vector<int> act(npairs);
-    for (int g = 0; g < npairs; g++) act[g] = g;
-    HIPCHK(hipMemcpyAsync(d_active, act.data(), 4 * (size_t)npairs, hipMemcpyHostToDevice, st));
-    Stage2Batch B;
-    std::memset(&B, 0, sizeof B);
-    B.L = L;
-    B.dev_pairs = d_pairs;
-    B.dev_probs = d_probs;
-    B.dev_active = d_active;
-    B.count = npairs;
-    B.max_iter = O.max_iter;
-    B.lu_base = lu_base;
-    B.lu_stride = slot_d;
-    B.piv_base = piv_base;
-    B.piv_stride = (size_t)max_n;
-    if (stage2_rq<L>(B, st)) return ctx->fail(ZK_EDEVICE, "stage2 rq launch failed");
-
-    std::vector<PairDesc> hp(npairs);
-    int iter = 0;
-    for (;; iter++) {
-        HIPCHK(hipMemcpyAsync(hp.data(), d_pairs, sizeof(PairDesc) * npairs, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        std::map<int, std::vector<int>> by_n;
-        int nact = 0;
-        for (int g = 0; g < npairs; g++)
-            if (hp[g].status == 0) {
-                by_n[probs[hp[g].prob].n].push_back(g);
-                nact++;
-            }
-        if (stats) stats->active_per_iter.push_back(nact);
-        if (nact == 0 || iter > O.max_iter + 1) break;
-        // shifted solves, grouped by order, S at a time
-        for (auto &kv : by_n) {
-            const int n = kv.first;
-            const std::vector<int> &lst = kv.second;
-            for (size_t c0 = 0; c0 < lst.size(); c0 += (size_t)S) {
-                const int cnt = (int)std::min<size_t>((size_t)S, lst.size() - c0);
-                HIPCHK(hipMemcpyAsync(d_active, lst.data() + c0, 4 * (size_t)cnt, hipMemcpyHostToDevice, st));
-                B.n = n;
-                B.count = cnt;
-                B.ldm = lu_ldm(n);
-                B.lu_stride = lu_slot_doubles(n, L);
-                B.piv_stride = (size_t)n;
-                if (stage2_solve<L>(B, st)) return ctx->fail(ZK_EDEVICE, "stage2 solve launch failed");
-                // keep the host list alive until the copy has been consumed
-                HIPCHK(hipStreamSynchronize(st));
-            }
-        }
-        // Gram-Schmidt in clusters with active members
-        std::vector<int> hl;
-        for (int hidx : heads) {
-            bool a = false;
-            for (int q = 0; q < hp[hidx].cl_size && !a; q++) a = hp[hidx + q].status == 0;
-            if (a && hp[hidx].cl_size > 0) hl.push_back(hidx);
-        }
-        HIPCHK(hipMemcpyAsync(d_heads, hl.data(), 4 * hl.size(), hipMemcpyHostToDevice, st));
-        if (stage2_gs<L>(d_pairs, d_probs, d_heads, (int)hl.size(), st)) return ctx->fail(ZK_EDEVICE, "stage2 gs launch failed");
-        std::vector<int> all;
-        for (auto &kv : by_n) all.insert(all.end(), kv.second.begin(), kv.second.end());
-        HIPCHK(hipMemcpyAsync(d_active, all.data(), 4 * all.size(), hipMemcpyHostToDevice, st));
-        B.count = (int)all.size();
-        if (stage2_rq<L>(B, st)) return ctx->fail(ZK_EDEVICE, "stage2 rq launch failed");
-        HIPCHK(hipStreamSynchronize(st));
-        // restore the full head list for the next iteration's lookup
-        HIPCHK(hipMemcpyAsync(d_heads, heads.data(), 4 * heads.size(), hipMemcpyHostToDevice, st));
-    }
-    // global re-orthogonalisation, then every Rayleigh quotient and residual again
-    if (O.reorth) {
-        std::map<int, std::vector<int>> pn;
-        for (int p = 0; p < np; p++)
-            if (npair_of[p] == probs[p].n && probs[p].n > 1) pn[probs[p].n].push_back(p);
-        for (auto &kv : pn) {
-            const int n = kv.first, cnt = (int)kv.second.size();
-            const size_t sstride = (size_t)2 * L * n * 32;
-            if (ctx->s2lu.bytes < 8 * sstride * cnt + 4 * (size_t)cnt + 256) {
-                if ((rc = ctx->ensure(ctx->s2lu, 8 * sstride * cnt + 4 * (size_t)cnt + 256)) != ZK_OK) return rc;
-            }
-            double *scratch = (double *)ctx->s2lu.p;
-            int *d_plist = (int *)((char *)ctx->s2lu.p + align_up(8 * sstride * cnt));
-            HIPCHK(hipMemcpyAsync(d_plist, kv.second.data(), 4 * (size_t)cnt, hipMemcpyHostToDevice, st));
-            if (stage2_reorth<L>(d_probs, d_plist, cnt, n, scratch, sstride, st))
-                return ctx->fail(ZK_EDEVICE, "re-orthogonalisation launch failed");
-            HIPCHK(hipStreamSynchronize(st));
-        }
-        std::vector<int> all(npairs);
-        for (int g = 0; g < npairs; g++) all[g] = g;
-        HIPCHK(hipMemcpyAsync(d_active, all.data(), 4 * (size_t)npairs, hipMemcpyHostToDevice, st));
-        B.count = npairs;
-        B.final_pass = 1;
-        if (stage2_rq<L>(B, st)) return ctx->fail(ZK_EDEVICE, "stage2 rq launch failed");
-        B.final_pass = 0;
-        HIPCHK(hipStreamSynchronize(st));
-    }
-    // ascending order of the refined eigenvalues inside each matrix
-    std::vector<int> dst(npairs);
-    {
-        size_t g0 = 0;
-        std::vector<double> sig;
-        for (int p = 0; p < np; p++) {
-            const int n = probs[p].n, kp = npair_of[p];
-            sig.resize((size_t)L * n);
-            HIPCHK(hipMemcpyAsync(sig.data(), probs[p].sigma, 8 * (size_t)L * n, hipMemcpyDeviceToHost, st));
-            HIPCHK(hipStreamSynchronize(st));
-            std::vector<int> ord(kp);
-            for (int k = 0; k < kp; k++) ord[k] = k;
-            std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
-                for (int l = 0; l < L; l++) {
-                    const double x = sig[(size_t)l * n + a], y = sig[(size_t)l * n + b];
-                    if (x != y) return x < y;
-                }
-                return false;
-            });
-            for (int pos = 0; pos < kp; pos++) dst[g0 + ord[pos]] = pos;
-            g0 += kp;
-        }
-    }
-    HIPCHK(hipMemcpyAsync(d_dst, dst.data(), 4 * (size_t)npairs, hipMemcpyHostToDevice, st));
-    if (stage2_output<L>(d_pairs, d_probs, d_dst, npairs, st)) return ctx->fail(ZK_EDEVICE, "stage2 output launch failed");
-    HIPCHK(hipMemcpyAsync(hp.data(), d_pairs, sizeof(PairDesc) * npairs, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    bool all_conv = true;
-    for (int g = 0; g < npairs; g++) {
-        const PairDesc &q = hp[g];
-        if (q.status != 1) all_conv = false;
-        if (stats) {
-            stats->iters_hist[std::min(q.iters, 15)]++;
-            stats->solves += q.iters;
-        }
-        zk_pair_info *info = infos[q.prob];
-        if (info) {
-            zk_pair_info &o = info[dst[g]];
-            o.iters = q.iters;
-            o.flags = q.flags;
-            o.cluster = q.cl_start;
-            o.reserved = 0;
-            o.resid = q.resid;
-        }
-    }
-    if (stats) stats->rounds = iter;
-    return all_conv ? ZK_OK : ZK_ENOCONV;
+    Stage2Engine<L> eng(ctx, O, stats);
+    int rc = eng.add(batch);
+    while (rc == ZK_OK && eng.any_live()) rc = eng.round();
+    if (stats) stats->rounds = eng.rounds;
+    if (rc != ZK_OK) return rc;
+    for (auto &p : store)
+        if (p.status != ZK_OK) return p.status;
+    return ZK_OK;
 }
 
 // ============================================================ heev ========
-// Stage 1 for `count` matrices: fills hf/w0/V0 pointers (into ctx->s2in) and
-// runs the binary64 eigendecomposition; ZK_EINVAL on non-finite input.
-static int run_stage1(zk_ctx *ctx, int count, const zk_herm *A, std::vector<double *> &hf, std::vector<double *> &w0,
-                      std::vector<double *> &V0)
+// stage-2 inputs (hf, w0, V0, flag) of every matrix, carved from ctx->s2in
+static int carve_s2in(zk_ctx *ctx, int count, const zk_herm *A, std::vector<double *> &hf, std::vector<double *> &w0,
+                      std::vector<double *> &V0, std::vector<int *> &flag)
+{
+    size_t in_total = 0;
+    for (int i = 0; i < count; i++) in_total += s2in_bytes(A[i].n, A[i].limbs);
+    int rc = ctx->ensure(ctx->s2in, in_total);
+    if (rc != ZK_OK) return rc;
+    char *b = (char *)ctx->s2in.p;
+    for (int i = 0; i < count; i++) {
+        const size_t nn = (size_t)A[i].n * A[i].n;
+        hf[i] = (double *)b;
+        b += align_up(8 * 2 * (size_t)A[i].limbs * nn);
+        w0[i] = (double *)b;
+        b += align_up(8 * (size_t)A[i].n);
+        V0[i] = (double *)b;
+        b += align_up(16 * nn);
+        flag[i] = (int *)b;
+        b += align_up(64);
+    }
+    return ZK_OK;
+}
+
+// Stage 1 for `count` matrices into caller-chosen buffers: hf (limb-planar
+// copy, 2*limbs*n*n doubles), w0 (n), V0 (n*n complex), flag (int, zeroed
+// here); ZK_EINVAL on non-finite input.
+int run_stage1(zk_ctx *ctx, int count, const zk_herm *A, const std::vector<double *> &hf, const std::vector<double *> &w0,
+               const std::vector<double *> &V0, const std::vector<int *> &flag)
 {
     hipStream_t st = ctx->stream;
     int rc;
-    // stage-2 inputs (hf, w0, V0) for every matrix, resident until the end
-    size_t in_total = 0;
-    for (int i = 0; i < count; i++) in_total += s2in_bytes(A[i].n, A[i].limbs);
-    if ((rc = ctx->ensure(ctx->s2in, in_total)) != ZK_OK) return rc;
-    std::vector<int *> flag(count);
-    {
-        char *b = (char *)ctx->s2in.p;
-        for (int i = 0; i < count; i++) {
-            const size_t nn = (size_t)A[i].n * A[i].n;
-            hf[i] = (double *)b;
-            b += align_up(8 * 2 * (size_t)A[i].limbs * nn);
-            w0[i] = (double *)b;
-            b += align_up(8 * (size_t)A[i].n);
-            V0[i] = (double *)b;
-            b += align_up(16 * nn);
-            flag[i] = (int *)b;
-            b += align_up(64);
-        }
-    }
-    HIPCHK(hipMemsetAsync(ctx->s2in.p, 0, in_total, st));
+    for (int i = 0; i < count; i++) HIPCHK(hipMemsetAsync(flag[i], 0, 4, st));
     // stage 1, grouped by order, as many matrices at a time as the budget allows
     std::map<int, std::vector<int>> groups;
     for (int i = 0; i < count; i++) groups[A[i].n].push_back(i);
@@ -537,8 +332,11 @@ static int run_stage1(zk_ctx *ctx, int count, const zk_herm *A, std::vector<doub
             S1.nprob = np;
             S1.dev_probs = d_probs;
             S1.dev_gemm = d_gemm;
-            S1.tri_gap_rel = 1e-9;
+            S1.tri_gap_rel = 1e-12;
+            S1.timer = ctx->tp();
+            const int t1 = S1.timer ? S1.timer->begin(KC_STAGE1, (double)np, st) : -1;
             if (stage1_run(S1, st)) return ctx->fail(ZK_EDEVICE, "stage1 launch failed: %s", hipGetErrorString(hipGetLastError()));
+            if (S1.timer) S1.timer->end(t1, st);
             HIPCHK(hipStreamSynchronize(st));   // host descriptor arrays go out of scope
         }
     }
@@ -558,7 +356,7 @@ static int run_heev(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out *out, c
     if (!ctx) return ZK_EINVAL;
     if (ctx->poisoned) return ctx->fail(ZK_EDEVICE, "context poisoned by an earlier device error");
     if (count < 1 || !A || !out) return ctx->fail(ZK_EINVAL, "count < 1 or NULL arrays");
-    const ResolvedOpts O = resolve(opts, L);
+    const ResolvedOpts O = zk_resolve_opts(opts, L);
     for (int i = 0; i < count; i++) {
         if (check_herm(A[i]) != ZK_OK) return ctx->fail(ZK_EINVAL, "matrix %d: bad n/lda/limbs/planes", i);
         if (check_out(out[i], A[i].n, A[i].n, L, O.want_vectors) != ZK_OK)
@@ -566,8 +364,10 @@ static int run_heev(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out *out, c
     }
     if (hipSetDevice(ctx->device) != hipSuccess) return ctx->fail(ZK_EDEVICE, "hipSetDevice failed");
     std::vector<double *> hf(count), w0(count), V0(count);
-    int rc = run_stage1(ctx, count, A, hf, w0, V0);
+    std::vector<int *> flag(count);
+    int rc = carve_s2in(ctx, count, A, hf, w0, V0, flag);
     if (rc != ZK_OK) return rc;
+    if ((rc = run_stage1(ctx, count, A, hf, w0, V0, flag)) != ZK_OK) return rc;
     std::vector<RqiProb> rp(count);
     std::vector<int> npair_of(count);
     std::vector<zk_pair_info *> infos(count);
@@ -603,8 +403,10 @@ extern "C" int zk_heev_fp64(zk_ctx *ctx, int count, const zk_herm *A, double *co
     }
     if (hipSetDevice(ctx->device) != hipSuccess) return ctx->fail(ZK_EDEVICE, "hipSetDevice failed");
     std::vector<double *> hf(count), w0(count), V0(count);
-    int rc = run_stage1(ctx, count, A, hf, w0, V0);
+    std::vector<int *> flag(count);
+    int rc = carve_s2in(ctx, count, A, hf, w0, V0, flag);
     if (rc != ZK_OK) return rc;
+    if ((rc = run_stage1(ctx, count, A, hf, w0, V0, flag)) != ZK_OK) return rc;
     hipStream_t st = ctx->stream;
     for (int i = 0; i < count; i++) {
         const int n = A[i].n;
@@ -634,7 +436,7 @@ static int run_refine(zk_ctx *ctx, const zk_herm *A, int k, const double *w0, co
     if (ctx->poisoned) return ctx->fail(ZK_EDEVICE, "context poisoned by an earlier device error");
     if (!A || !out || !w0 || !V0) return ctx->fail(ZK_EINVAL, "NULL argument");
     if (check_herm(*A) != ZK_OK) return ctx->fail(ZK_EINVAL, "bad n/lda/limbs/planes");
-    const ResolvedOpts O = resolve(opts, L);
+    const ResolvedOpts O = zk_resolve_opts(opts, L);
     if (k < 1 || k > A->n || ldv0 < A->n) return ctx->fail(ZK_EINVAL, "bad k or ldv0");
     if (check_out(*out, k, A->n, L, O.want_vectors) != ZK_OK) return ctx->fail(ZK_EINVAL, "bad output descriptor");
     if (hipSetDevice(ctx->device) != hipSuccess) return ctx->fail(ZK_EDEVICE, "hipSetDevice failed");
@@ -681,6 +483,32 @@ extern "C" int zk_rqi_refine(zk_ctx *ctx, int limbs_out, const zk_herm *A, int k
     if (limbs_out == 4) return run_refine<4>(ctx, A, k, w0, V0, ldv0, out, opts);
     if (ctx) ctx->fail(ZK_EINVAL, "limbs_out must be 2 or 4");
     return ZK_EINVAL;
+}
+
+// ------------------------------------------------------ instrumentation --
+extern "C" int zk_prof_enable(zk_ctx *ctx, int on)
+{
+    if (!ctx) return ZK_EINVAL;
+    ctx->timer.collect();
+    ctx->timer.on = on != 0;
+    return ZK_OK;
+}
+
+extern "C" int zk_prof_reset(zk_ctx *ctx)
+{
+    if (!ctx) return ZK_EINVAL;
+    ctx->timer.reset();
+    return ZK_OK;
+}
+
+extern "C" int zk_prof_read(zk_ctx *ctx, int cls, double *ms, long long *launches, double *work)
+{
+    if (!ctx || cls < 0 || cls >= KC_COUNT) return ZK_EINVAL;
+    ctx->timer.collect();
+    if (ms) *ms = ctx->timer.ms[cls];
+    if (launches) *launches = ctx->timer.launches[cls];
+    if (work) *work = ctx->timer.work[cls];
+    return ZK_OK;
 }
 
 // statistics entry used by the benchmark (not part of the public header)

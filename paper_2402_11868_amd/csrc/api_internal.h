@@ -7,6 +7,8 @@
 #include <string>
 #include <vector>
 
+#include "stage.h"
+
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
@@ -31,6 +33,9 @@ struct zk_ctx {
     DevBuf s2vec;   // stage-2 iterates and Rayleigh quotients
     DevBuf s2lu;    // shifted-LU slots
     DevBuf meta;    // descriptor tables
+    size_t extra = 0;        // per-matrix iterate buffers held by stage-2 engines
+    zk::KernelTimer timer;   // per-kernel-class HIP-event timing (instrumentation)
+    zk::KernelTimer *tp() { return timer.on ? &timer : nullptr; }
     size_t held() const;
     int ensure(DevBuf &b, size_t bytes);
     int fail(int status, const char *fmt, ...);

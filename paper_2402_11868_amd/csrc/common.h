@@ -61,6 +61,8 @@ struct RqiProb {
     int limbs_in;
     int ldv_out;
     int ldv0;
+    int max_iter;          // iteration limit of this matrix's pairs
+    int pad1;
     const double *hf;      // limb-planar full Hermitian copy (ld n)
     const double *w0;      // binary64 starting eigenvalues (n)
     const double *V0;      // binary64 starting eigenvectors, complex128 n x n (ld ldv0)

@@ -1,0 +1,550 @@
+// Stage-2 engine: the Rayleigh quotient iteration of any number of matrices,
+// driven round by round.  Matrices can join (add) and leave (when all their
+// pairs have finished) between rounds, which is what the serving session
+// uses for continuous batching; the one-shot zk_heev_* calls add everything
+// at once and run rounds until nothing is active.  Every kernel works per
+// pair, per cluster or per matrix, so a matrix's result does not depend on
+// what else is in the batch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <vector>
+
+#include "../../include/zk.h"
+#include "api_internal.h"
+#include "stage.h"
+
+#define HIPCHK_(expr)                                          \
+    do {                                                       \
+        hipError_t e_ = (expr);                                \
+        if (e_ != hipSuccess) return HIPFAIL(e_, #expr);       \
+    } while (0)
+
+namespace zk {
+
+struct ResolvedOpts {
+    double tol;
+    int max_iter;
+    double cluster_tol;
+    int want_vectors;
+    int init_fp32;
+    int reorth;
+};
+
+inline size_t s2_align(size_t x) { return (x + 255) & ~(size_t)255; }
+inline int s2_lu_ldm(int n) { return (n + 7) & ~7; }
+inline size_t s2_lu_slot_doubles(int n, int L) { return (size_t)2 * L * s2_lu_ldm(n) * (size_t)(n + 1); }
+
+// One matrix in the engine.  The caller sets rp (n, limbs_in, hf, w0, V0,
+// ldv0, ldv_out, w_out, v_out, hnorm lower bound), npairs and info.
+struct S2Prob {
+    RqiProb rp;
+    ResolvedOpts opts;
+    int npairs = 0;
+    zk_pair_info *info = nullptr;
+    std::vector<PairDesc> pairs;   // authoritative host copy of the pair states
+    std::vector<int> heads;        // local index of every cluster's first pair
+    void *vecbuf = nullptr;
+    size_t vecbytes = 0;
+    int status = ZK_OK;
+    bool done = false;
+    void *cookie = nullptr;        // owner's handle (session request)
+};
+
+template <int L>
+class Stage2Engine {
+  public:
+    Stage2Engine(zk_ctx *c, const ResolvedOpts &o, Stage2Stats *s) : ctx(c), O(o), stats(s) { st = c->stream; }
+    ~Stage2Engine()
+    {
+        for (S2Prob *p : live) release(p);
+    }
+
+    std::vector<S2Prob *> live;      // matrices still iterating
+    std::vector<S2Prob *> finished;  // filled by round(); the owner takes them
+
+    bool any_live() const { return !live.empty(); }
+
+    // Prepare new matrices (clusters, start vectors, Gram-Schmidt, Rayleigh-Ritz,
+    // first Rayleigh quotients) and let them join the iteration.
+    int add(const std::vector<S2Prob *> &batch)
+    {
+        int rc;
+        std::vector<double> w0h;
+        for (S2Prob *p : batch) {
+            RqiProb &P = p->rp;
+            const int n = P.n, kp = p->npairs;
+            p->vecbytes = s2_align(8 * 2 * (size_t)L * n * n) + s2_align(8 * (size_t)L * n);
+            if (ctx->held() + p->vecbytes > ctx->budget) return ctx->fail(ZK_ENOMEM, "iterate storage exceeds the budget");
+            if (hipMalloc(&p->vecbuf, p->vecbytes) != hipSuccess) {
+                p->vecbuf = nullptr;
+                hipGetLastError();
+                return ctx->fail(ZK_ENOMEM, "hipMalloc of %zu bytes failed", p->vecbytes);
+            }
+            ctx->extra += p->vecbytes;
+            P.vec = (double *)p->vecbuf;
+            P.sigma = (double *)((char *)p->vecbuf + s2_align(8 * 2 * (size_t)L * n * n));
+            w0h.resize(kp);
+            HIPCHK_(hipMemcpyAsync(w0h.data(), P.w0, 8 * (size_t)kp, hipMemcpyDeviceToHost, st));
+            HIPCHK_(hipStreamSynchronize(st));
+            double hn = 0.0;
+            for (int k = 0; k < kp; k++) hn = std::max(hn, std::fabs(w0h[k]));
+            hn = std::max(hn, P.hnorm);
+            if (!(hn > 0.0)) hn = 1.0;   // zero matrix: absolute tolerances
+            P.hnorm = hn;
+            P.tol_abs = p->opts.tol * hn;
+            P.piv_tol = std::ldexp(hn, -53 * L);
+            P.max_iter = p->opts.max_iter;
+            const double thr = p->opts.cluster_tol * hn;
+            p->pairs.assign(kp, PairDesc());
+            int start = 0;
+            for (int k = 0; k < kp; k++) {
+                if (k > 0 && !(w0h[k] - w0h[k - 1] <= thr)) start = k;
+                PairDesc &q = p->pairs[k];
+                std::memset(&q, 0, sizeof q);
+                q.k = k;
+                q.cl_start = start;
+            }
+            p->heads.clear();
+            int k = 0;
+            while (k < kp) {
+                int e = k + 1;
+                while (e < kp && p->pairs[e].cl_start == k) e++;
+                for (int q = k; q < e; q++) p->pairs[q].cl_size = (q == k) ? e - k : 0;
+                p->heads.push_back(k);
+                k = e;
+            }
+        }
+        if ((rc = upload(batch)) != ZK_OK) return rc;
+        if (stage2_init<L>(d_pairs, d_probs, total_pairs, st)) return ctx->fail(ZK_EDEVICE, "init launch failed");
+        for (S2Prob *p : batch)
+            for (auto &q : p->pairs) q.status = 0;
+        if ((rc = run_gs(batch, false)) != ZK_OK) return rc;
+        if ((rc = run_rr(batch)) != ZK_OK) return rc;
+        std::vector<int> all(total_pairs);
+        for (int g = 0; g < total_pairs; g++) all[g] = g;
+        if ((rc = run_rq(all, 0)) != ZK_OK) return rc;
+        if ((rc = download(batch)) != ZK_OK) return rc;
+        for (S2Prob *p : batch) live.push_back(p);
+        return settle();
+    }
+
+    // One round over every live matrix: shifted solves of all active pairs,
+    // Gram-Schmidt in their clusters, Rayleigh quotients and convergence.
+    // Matrices whose pairs have all stopped are finalised and moved to `finished`.
+    int round()
+    {
+        int rc;
+        if (live.empty()) return ZK_OK;
+        if ((rc = upload(live)) != ZK_OK) return rc;
+        std::map<int, std::vector<int>> by_n;
+        int nact = 0;
+        for (size_t pi = 0; pi < live.size(); pi++)
+            for (int k = 0; k < live[pi]->npairs; k++)
+                if (live[pi]->pairs[k].status == 0) {
+                    by_n[live[pi]->rp.n].push_back(base[pi] + k);
+                    nact++;
+                }
+        if (stats) stats->active_per_iter.push_back(nact);
+        if (nact > 0) {
+            int max_n = 0;
+            for (auto &kv : by_n) max_n = std::max(max_n, kv.first);
+            if ((rc = ensure_slots(max_n, nact)) != ZK_OK) return rc;
+            Stage2Batch B = batch_base();
+            for (auto &kv : by_n) {
+                const int n = kv.first;
+                const std::vector<int> &lst = kv.second;
+                for (size_t c0 = 0; c0 < lst.size(); c0 += (size_t)S) {
+                    const int cnt = (int)std::min<size_t>((size_t)S, lst.size() - c0);
+                    HIPCHK_(hipMemcpyAsync(d_active, lst.data() + c0, 4 * (size_t)cnt, hipMemcpyHostToDevice, st));
+                    B.n = n;
+                    B.count = cnt;
+                    B.ldm = s2_lu_ldm(n);
+                    B.lu_stride = s2_lu_slot_doubles(n, L);
+                    B.piv_stride = (size_t)n;
+                    if (stage2_solve<L>(B, st)) return ctx->fail(ZK_EDEVICE, "solve launch failed");
+                    HIPCHK_(hipStreamSynchronize(st));
+                }
+            }
+            if ((rc = run_gs(live, false)) != ZK_OK) return rc;
+            std::vector<int> all;
+            for (auto &kv : by_n) all.insert(all.end(), kv.second.begin(), kv.second.end());
+            if ((rc = run_rq(all, 0)) != ZK_OK) return rc;
+            if ((rc = download(live)) != ZK_OK) return rc;
+            rounds++;
+            if (std::getenv("ZK_TRACE")) trace();
+        }
+        return settle();
+    }
+
+    int rounds = 0;
+
+  private:
+    zk_ctx *ctx;
+    ResolvedOpts O;
+    Stage2Stats *stats;
+    hipStream_t st;
+    // device tables of the current upload
+    std::vector<int> base;   // pair-table offset of every uploaded matrix
+    int total_pairs = 0;
+    PairDesc *d_pairs = nullptr;
+    RqiProb *d_probs = nullptr;
+    int *d_active = nullptr, *d_dst = nullptr, *d_glist = nullptr;
+    GsCluster *d_gcls = nullptr;
+    double *d_gscratch = nullptr;
+    size_t gs_scratch_bytes = 0;
+    int S = 0, slot_n = 0;
+
+    int HIPFAIL(hipError_t e, const char *what) { return ctx->fail(ZK_EDEVICE, "%s: %s", what, hipGetErrorString(e)); }
+
+    void release(S2Prob *p)
+    {
+        if (p->vecbuf) {
+            hipFree(p->vecbuf);
+            ctx->extra -= p->vecbytes;
+            p->vecbuf = nullptr;
+        }
+    }
+
+    Stage2Batch batch_base()
+    {
+        Stage2Batch B;
+        std::memset(&B, 0, sizeof B);
+        B.L = L;
+        B.dev_pairs = d_pairs;
+        B.dev_probs = d_probs;
+        B.dev_active = d_active;
+        B.max_iter = O.max_iter;
+        B.lu_base = (double *)ctx->s2lu.p;
+        B.piv_base = (int *)((char *)ctx->s2lu.p + (size_t)S * s2_align(8 * s2_lu_slot_doubles(std::max(slot_n, 1), L)));
+        B.timer = ctx->tp();
+        return B;
+    }
+
+    // LU slots for orders up to n: as many as the budget allows (<= wanted)
+    int ensure_slots(int n, int wanted)
+    {
+        if (n <= slot_n && S >= std::min(wanted, 64) && ctx->s2lu.p) return ZK_OK;
+        const int nn = std::max(n, slot_n);
+        const size_t per = s2_align(8 * s2_lu_slot_doubles(nn, L)) + s2_align(4 * (size_t)nn);
+        const size_t others = ctx->held() - ctx->s2lu.bytes;
+        const size_t avail = ctx->budget > others ? ctx->budget - others : 0;
+        int want = std::max(wanted, S);
+        int s = (int)std::min<size_t>((size_t)want, avail / per);
+        if (s < 1) return ctx->fail(ZK_ENOMEM, "one shifted LU of order %d needs %zu bytes", nn, per);
+        int rc = ctx->ensure(ctx->s2lu, (size_t)s * per);
+        if (rc != ZK_OK) return rc;
+        S = s;
+        slot_n = nn;
+        return ZK_OK;
+    }
+
+    // upload the tables of `set` (matrix i gets table index i)
+    int upload(const std::vector<S2Prob *> &set)
+    {
+        base.assign(set.size(), 0);
+        total_pairs = 0;
+        for (size_t i = 0; i < set.size(); i++) {
+            base[i] = total_pairs;
+            total_pairs += set[i]->npairs;
+        }
+        const size_t np = set.size();
+        gs_scratch_bytes = s2_align((size_t)total_pairs * 32 * 2 * L * 8);
+        const size_t need = s2_align(sizeof(PairDesc) * total_pairs) + s2_align(sizeof(RqiProb) * np) +
+                            3 * s2_align(4 * (size_t)total_pairs) + s2_align(sizeof(GsCluster) * total_pairs) + gs_scratch_bytes;
+        int rc = ctx->ensure(ctx->meta, need);
+        if (rc != ZK_OK) return rc;
+        char *mb = (char *)ctx->meta.p;
+        d_pairs = (PairDesc *)mb;
+        mb += s2_align(sizeof(PairDesc) * total_pairs);
+        d_probs = (RqiProb *)mb;
+        mb += s2_align(sizeof(RqiProb) * np);
+        d_active = (int *)mb;
+        mb += s2_align(4 * (size_t)total_pairs);
+        d_dst = (int *)mb;
+        mb += s2_align(4 * (size_t)total_pairs);
+        d_glist = (int *)mb;
+        mb += s2_align(4 * (size_t)total_pairs);
+        d_gcls = (GsCluster *)mb;
+        mb += s2_align(sizeof(GsCluster) * total_pairs);
+        d_gscratch = (double *)mb;
+        hp.resize(total_pairs);
+        hprobs.resize(np);
+        for (size_t i = 0; i < np; i++) {
+            hprobs[i] = set[i]->rp;
+            for (int k = 0; k < set[i]->npairs; k++) {
+                hp[base[i] + k] = set[i]->pairs[k];
+                hp[base[i] + k].prob = (int)i;
+            }
+        }
+        HIPCHK_(hipMemcpyAsync(d_pairs, hp.data(), sizeof(PairDesc) * total_pairs, hipMemcpyHostToDevice, st));
+        HIPCHK_(hipMemcpyAsync(d_probs, hprobs.data(), sizeof(RqiProb) * np, hipMemcpyHostToDevice, st));
+        HIPCHK_(hipStreamSynchronize(st));
+        up = set;
+        return ZK_OK;
+    }
+
+    int download(const std::vector<S2Prob *> &set)
+    {
+        HIPCHK_(hipMemcpyAsync(hp.data(), d_pairs, sizeof(PairDesc) * total_pairs, hipMemcpyDeviceToHost, st));
+        HIPCHK_(hipStreamSynchronize(st));
+        for (size_t i = 0; i < set.size(); i++)
+            for (int k = 0; k < set[i]->npairs; k++) set[i]->pairs[k] = hp[base[i] + k];
+        return ZK_OK;
+    }
+
+    int run_rq(const std::vector<int> &idx, int final_pass)
+    {
+        if (idx.empty()) return ZK_OK;
+        HIPCHK_(hipMemcpyAsync(d_active, idx.data(), 4 * idx.size(), hipMemcpyHostToDevice, st));
+        Stage2Batch B = batch_base();
+        B.count = (int)idx.size();
+        B.final_pass = final_pass;
+        KernelTimer *tm = ctx->tp();
+        const int id = tm ? tm->begin(KC_RQ, (double)idx.size(), st) : -1;
+        if (stage2_rq<L>(B, st)) return ctx->fail(ZK_EDEVICE, "rq launch failed");
+        if (tm) tm->end(id, st);
+        HIPCHK_(hipStreamSynchronize(st));
+        return ZK_OK;
+    }
+
+    // Gram-Schmidt over the uploaded set: clusters with active members
+    // (global = every vector of the matrices in `only`, nobody frozen)
+    int run_gs(const std::vector<S2Prob *> &set, bool global, const std::vector<int> *only = nullptr)
+    {
+        std::vector<GsCluster> cls;
+        std::vector<int> list;
+        GsPlan G;
+        std::memset(&G, 0, sizeof G);
+        long long sofs = 0;
+        auto add = [&](int pi, const std::vector<int> &fro, const std::vector<int> &act) {
+            GsCluster c;
+            c.prob = pi;
+            c.pair_base = base[pi];
+            c.off = (int)list.size();
+            c.nconv = (int)fro.size();
+            c.nact = (int)act.size();
+            c.size = c.nconv + c.nact;
+            c.sofs = sofs;
+            sofs += (long long)c.size * 32 * 2 * L;
+            list.insert(list.end(), fro.begin(), fro.end());
+            list.insert(list.end(), act.begin(), act.end());
+            cls.push_back(c);
+            G.max_blocks = std::max(G.max_blocks, (c.nact + 31) / 32);
+            G.max_nconv = std::max(G.max_nconv, c.nconv);
+            G.max_n = std::max(G.max_n, set[pi]->rp.n);
+        };
+        if (global) {
+            for (int pi : *only) {
+                S2Prob *p = set[pi];
+                if (p->npairs != p->rp.n || p->rp.n < 2) continue;
+                std::vector<int> act(p->rp.n), none;
+                for (int k = 0; k < p->rp.n; k++) act[k] = k;
+                add(pi, none, act);
+            }
+        } else {
+            for (size_t pi = 0; pi < set.size(); pi++) {
+                S2Prob *p = set[pi];
+                for (int h : p->heads) {
+                    const int sz = p->pairs[h].cl_size;
+                    std::vector<int> fro, act;
+                    for (int q = 0; q < sz; q++) (p->pairs[h + q].status == 0 ? act : fro).push_back(p->pairs[h + q].k);
+                    if (!act.empty()) add((int)pi, fro, act);
+                }
+            }
+        }
+        if (cls.empty()) return ZK_OK;
+        if ((size_t)sofs * 8 > gs_scratch_bytes) return ctx->fail(ZK_EINTERNAL, "Gram-Schmidt scratch too small");
+        HIPCHK_(hipMemcpyAsync(d_gcls, cls.data(), sizeof(GsCluster) * cls.size(), hipMemcpyHostToDevice, st));
+        HIPCHK_(hipMemcpyAsync(d_glist, list.data(), 4 * list.size(), hipMemcpyHostToDevice, st));
+        G.ncl = (int)cls.size();
+        G.dev_cls = d_gcls;
+        G.dev_list = d_glist;
+        G.scratch = d_gscratch;
+        KernelTimer *tm = ctx->tp();
+        const int id = tm ? tm->begin(global ? KC_REORTH : KC_GS, (double)list.size(), st) : -1;
+        if (stage2_gs<L>(G, d_probs, global ? nullptr : d_pairs, st)) return ctx->fail(ZK_EDEVICE, "Gram-Schmidt launch failed");
+        if (tm) tm->end(id, st);
+        HIPCHK_(hipStreamSynchronize(st));
+        return ZK_OK;
+    }
+
+    // Rayleigh-Ritz inside the clusters of 2..32 members of a new batch
+    int run_rr(const std::vector<S2Prob *> &set)
+    {
+        int max_n = 1;
+        for (S2Prob *p : set) max_n = std::max(max_n, p->rp.n);
+        int rc = ensure_slots(max_n, 1);   // the slot memory is free here: use it as scratch
+        if (rc != ZK_OK) return rc;
+        const size_t cap = ctx->s2lu.bytes / 8;
+        std::vector<GsCluster> cls;
+        std::vector<int> list;
+        long long sofs = 0;
+        auto flush = [&]() -> int {
+            if (cls.empty()) return ZK_OK;
+            HIPCHK_(hipMemcpyAsync(d_gcls, cls.data(), sizeof(GsCluster) * cls.size(), hipMemcpyHostToDevice, st));
+            HIPCHK_(hipMemcpyAsync(d_glist, list.data(), 4 * list.size(), hipMemcpyHostToDevice, st));
+            GsPlan G;
+            std::memset(&G, 0, sizeof G);
+            G.ncl = (int)cls.size();
+            G.dev_cls = d_gcls;
+            G.dev_list = d_glist;
+            G.scratch = (double *)ctx->s2lu.p;
+            KernelTimer *tm = ctx->tp();
+            const int id = tm ? tm->begin(KC_GS, (double)list.size(), st) : -1;
+            if (stage2_rr<L>(G, d_probs, L == 2 ? 10 : 14, st)) return ctx->fail(ZK_EDEVICE, "Rayleigh-Ritz launch failed");
+            if (tm) tm->end(id, st);
+            HIPCHK_(hipStreamSynchronize(st));
+            cls.clear();
+            list.clear();
+            sofs = 0;
+            return ZK_OK;
+        };
+        for (size_t pi = 0; pi < set.size(); pi++) {
+            S2Prob *p = set[pi];
+            const size_t need = (size_t)2 * L * p->rp.n * 32;
+            if (need > cap) continue;   // no room: skip the Ritz step
+            for (int h : p->heads) {
+                const int sz = p->pairs[h].cl_size;
+                if (sz < 2 || sz > 32) continue;
+                if ((size_t)sofs + need > cap || cls.size() >= (size_t)total_pairs) {
+                    if ((rc = flush()) != ZK_OK) return rc;
+                }
+                GsCluster c;
+                c.prob = (int)pi;
+                c.pair_base = base[pi];
+                c.off = (int)list.size();
+                c.nconv = 0;
+                c.nact = sz;
+                c.size = sz;
+                c.sofs = sofs;
+                sofs += (long long)need;
+                for (int q = 0; q < sz; q++) list.push_back(p->pairs[h + q].k);
+                cls.push_back(c);
+            }
+        }
+        return flush();
+    }
+
+    // finalise the live matrices that have no active pair
+    int settle()
+    {
+        std::vector<int> fin;
+        for (size_t pi = 0; pi < live.size(); pi++) {
+            bool act = false;
+            for (auto &q : live[pi]->pairs) act = act || q.status == 0;
+            if (!act) fin.push_back((int)pi);
+        }
+        if (fin.empty()) return ZK_OK;
+        int rc;
+        if ((rc = upload(live)) != ZK_OK) return rc;
+        std::vector<int> ro;
+        for (int pi : fin)
+            if (live[pi]->opts.reorth) ro.push_back(pi);
+        if (!ro.empty()) {
+            if ((rc = run_gs(live, true, &ro)) != ZK_OK) return rc;
+            std::vector<int> idx;
+            for (int pi : ro)
+                if (live[pi]->npairs == live[pi]->rp.n && live[pi]->rp.n > 1)
+                    for (int k = 0; k < live[pi]->npairs; k++) idx.push_back(base[pi] + k);
+            if ((rc = run_rq(idx, 1)) != ZK_OK) return rc;
+            if ((rc = download(live)) != ZK_OK) return rc;
+        }
+        // ascending order of the refined eigenvalues inside each matrix
+        std::vector<int> dst(total_pairs, 0);
+        std::vector<int> outidx;
+        std::vector<double> sig;
+        for (int pi : fin) {
+            S2Prob *p = live[pi];
+            const int n = p->rp.n, kp = p->npairs;
+            sig.resize((size_t)L * n);
+            HIPCHK_(hipMemcpyAsync(sig.data(), p->rp.sigma, 8 * (size_t)L * n, hipMemcpyDeviceToHost, st));
+            HIPCHK_(hipStreamSynchronize(st));
+            std::vector<int> ord(kp);
+            for (int k = 0; k < kp; k++) ord[k] = k;
+            std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+                for (int l = 0; l < L; l++) {
+                    const double x = sig[(size_t)l * n + a], y = sig[(size_t)l * n + b];
+                    if (x != y) return x < y;
+                }
+                return false;
+            });
+            for (int pos = 0; pos < kp; pos++) dst[base[pi] + ord[pos]] = pos;
+            for (int k = 0; k < kp; k++) outidx.push_back(base[pi] + k);
+        }
+        // output kernel over the finished pairs only: pass their indices as the pair list
+        std::vector<PairDesc> sub(outidx.size());
+        std::vector<int> subdst(outidx.size());
+        for (size_t i = 0; i < outidx.size(); i++) {
+            sub[i] = hp[outidx[i]];
+            subdst[i] = dst[outidx[i]];
+        }
+        HIPCHK_(hipMemcpyAsync(d_pairs, sub.data(), sizeof(PairDesc) * sub.size(), hipMemcpyHostToDevice, st));
+        HIPCHK_(hipMemcpyAsync(d_dst, subdst.data(), 4 * subdst.size(), hipMemcpyHostToDevice, st));
+        if (stage2_output<L>(d_pairs, d_probs, d_dst, (int)sub.size(), st)) return ctx->fail(ZK_EDEVICE, "output launch failed");
+        HIPCHK_(hipStreamSynchronize(st));
+        std::vector<S2Prob *> keep;
+        std::vector<char> isfin(live.size(), 0);
+        for (int pi : fin) isfin[pi] = 1;
+        for (size_t pi = 0; pi < live.size(); pi++) {
+            S2Prob *p = live[pi];
+            if (!isfin[pi]) {
+                keep.push_back(p);
+                continue;
+            }
+            bool all_conv = true;
+            for (int k = 0; k < p->npairs; k++) {
+                const PairDesc &q = p->pairs[k];
+                if (q.status != 1) all_conv = false;
+                if (stats) {
+                    stats->iters_hist[std::min(q.iters, 15)]++;
+                    stats->solves += q.iters;
+                }
+                if (p->info) {
+                    zk_pair_info &o = p->info[dst[base[pi] + k]];
+                    o.iters = q.iters;
+                    o.flags = q.flags;
+                    o.cluster = q.cl_start;
+                    o.reserved = 0;
+                    o.resid = q.resid;
+                }
+            }
+            p->status = all_conv ? ZK_OK : ZK_ENOCONV;
+            p->done = true;
+            release(p);
+            finished.push_back(p);
+        }
+        live = keep;
+        return ZK_OK;
+    }
+
+    void trace()
+    {
+        std::vector<double> rs;
+        int nact = 0;
+        for (S2Prob *p : live)
+            for (auto &q : p->pairs) {
+                if (q.iters == rounds) rs.push_back(q.resid);
+                nact += q.status == 0;
+            }
+        std::sort(rs.begin(), rs.end());
+        auto qt = [&](double f) { return rs.empty() ? 0.0 : rs[std::min(rs.size() - 1, (size_t)(f * rs.size()))]; };
+        std::fprintf(stderr, "[zk] round %d: still active %d, judged %zu, resid q10 %.2e q50 %.2e q90 %.2e max %.2e\n", rounds, nact,
+                     rs.size(), qt(0.1), qt(0.5), qt(0.9), rs.empty() ? 0.0 : rs.back());
+    }
+
+    std::vector<PairDesc> hp;
+    std::vector<RqiProb> hprobs;
+    std::vector<S2Prob *> up;
+};
+
+}  // namespace zk
+
+#undef HIPCHK_

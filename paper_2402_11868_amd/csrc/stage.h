@@ -8,9 +8,79 @@
 
 #include "common.h"
 
+#include <vector>
+
 namespace zk {
 
 constexpr int kMaxN = 4096;   // largest matrix order accepted
+
+// Per-kernel-class timing with HIP events recorded on the launch stream
+// around each launch (instrumentation; off unless enabled on the context).
+enum KernelClass { KC_LU_UPDATE = 0, KC_LU_PANEL, KC_LU_TRSM, KC_BACKSOLVE, KC_RQ, KC_GS, KC_REORTH, KC_STAGE1,
+                   KC_HER2K, KC_HEMV, KC_BUILD, KC_TRD_VEC, KC_TRIDIAG, KC_BACKT, KC_COUNT };
+
+struct KernelTimer {
+    bool on = false;
+    struct Rec {
+        int cls;
+        hipEvent_t a, b;
+        double work;
+    };
+    std::vector<Rec> open;
+    std::vector<hipEvent_t> pool;
+    double ms[KC_COUNT] = {0};
+    double work[KC_COUNT] = {0};
+    long long launches[KC_COUNT] = {0};
+    hipEvent_t get()
+    {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e;
+        hipEventCreate(&e);
+        return e;
+    }
+    // returns the index of the record to close with end()
+    int begin(int cls, double w, hipStream_t st)
+    {
+        if (!on) return -1;
+        Rec r{cls, get(), get(), w};
+        hipEventRecord(r.a, st);
+        open.push_back(r);
+        return (int)open.size() - 1;
+    }
+    void end(int id, hipStream_t st)
+    {
+        if (id >= 0) hipEventRecord(open[id].b, st);
+    }
+    // fold finished records into the totals (synchronises on the events)
+    void collect()
+    {
+        for (Rec &r : open) {
+            hipEventSynchronize(r.b);
+            float t = 0.0f;
+            hipEventElapsedTime(&t, r.a, r.b);
+            ms[r.cls] += t;
+            work[r.cls] += r.work;
+            launches[r.cls]++;
+            pool.push_back(r.a);
+            pool.push_back(r.b);
+        }
+        open.clear();
+    }
+    void reset()
+    {
+        collect();
+        for (int c = 0; c < KC_COUNT; c++) ms[c] = work[c] = 0, launches[c] = 0;
+    }
+    ~KernelTimer()
+    {
+        for (Rec &r : open) { hipEventDestroy(r.a); hipEventDestroy(r.b); }
+        for (hipEvent_t e : pool) hipEventDestroy(e);
+    }
+};
 
 struct GemmDesc {
     const double *A;
@@ -21,6 +91,7 @@ struct GemmDesc {
 
 // A batch of stage-1 problems of equal order n.
 struct Stage1Batch {
+    KernelTimer *timer;        // may be null
     int n;
     int nprob;
     ProbDesc *dev_probs;       // nprob descriptors (device)
@@ -55,6 +126,7 @@ struct Stage2Batch {
     int ldm;                // leading dimension of the LU planes
     int max_iter;
     int final_pass;         // rq: re-judge converged pairs after re-orthogonalisation
+    KernelTimer *timer;     // host object, may be null
 };
 
 // ingest of a matrix for stage 2 alone (refinement of caller pairs):
@@ -62,12 +134,31 @@ struct Stage2Batch {
 int stage2_ingest(int n, int lda, int limbs, const double *const *planes, double *hf, int *flag, hipStream_t st);
 
 template <int L> int stage2_init(PairDesc *pairs, RqiProb *probs, int npairs, hipStream_t st);
-template <int L> int stage2_gs(PairDesc *pairs, RqiProb *probs, const int *cluster_heads, int nclusters, hipStream_t st);
+// Gram-Schmidt plan: clusters with their column lists (see stage2.hip)
+struct GsCluster {
+    int prob;        // problem index
+    int pair_base;   // pair-table index of the problem's pair 0
+    int off;         // offset of the column list
+    int nconv;       // leading entries left untouched
+    int nact;        // entries orthogonalised, in order
+    int size;        // nconv + nact
+    long long sofs;  // scratch offset (doubles), 2L planes of size * 32 values
+};
+struct GsPlan {
+    int ncl;
+    int max_blocks;   // max over clusters of ceil(nact / 32)
+    int max_nconv;
+    int max_n;
+    const GsCluster *dev_cls;
+    const int *dev_list;
+    double *scratch;
+};
+template <int L> int stage2_gs(const GsPlan &G, RqiProb *probs, PairDesc *pairs, hipStream_t st);
+// Rayleigh-Ritz inside clusters of 2..32 members (plan entries: nconv = 0,
+// scratch per cluster 2L * n * 32 doubles)
+template <int L> int stage2_rr(const GsPlan &G, RqiProb *probs, int sweeps, hipStream_t st);
 template <int L> int stage2_rq(const Stage2Batch &B, hipStream_t st);
 template <int L> int stage2_solve(const Stage2Batch &B, hipStream_t st);
-// scratch: nprob * sstride doubles, sstride >= 2L * n * 32
-template <int L> int stage2_reorth(RqiProb *probs, const int *plist, int nprob, int n, double *scratch, size_t sstride,
-                                   hipStream_t st);
 template <int L> int stage2_output(PairDesc *pairs, RqiProb *probs, const int *dst, int npairs, hipStream_t st);
 
 }  // namespace zk

@@ -677,27 +677,40 @@ int stage1_run(const Stage1Batch &B, hipStream_t st)
         hipLaunchKernelGGL(k_zero_panel, dim3(cdiv((size_t)2 * kNB * n * 2, 256), np), dim3(256), 0, st, pd);
         for (int i = 0; i < nbw; i++) {
             const int c = k0 + i;
+            int idv = B.timer ? B.timer->begin(KC_TRD_VEC, 0.0, st) : -1;
             hipLaunchKernelGGL(k_trd_col, dim3(np), dim3(256), 0, st, pd, c, k0);
+            if (B.timer) B.timer->end(idv, st);
             const int m = n - c - 1;
             const int T = (m + 63) / 64;
+            // algorithmic bytes: the lower triangle of A22 once (16 bytes per complex entry)
+            const int id = B.timer ? B.timer->begin(KC_HEMV, 8.0 * (double)m * (m + 1) * np, st) : -1;
             hipLaunchKernelGGL(k_trd_hemv, dim3(T * (T + 1) / 2, np), dim3(256), 0, st, pd, c);
+            if (B.timer) B.timer->end(id, st);
+            idv = B.timer ? B.timer->begin(KC_TRD_VEC, 0.0, st) : -1;
             hipLaunchKernelGGL(k_trd_wfin, dim3(np), dim3(256), 0, st, pd, c, k0);
+            if (B.timer) B.timer->end(idv, st);
         }
         const int r0 = k0 + nbw;
         const int m = n - r0;
         if (m > 0) {
             const unsigned tiles = cdiv(m, 64) * cdiv(m, 64);
+            // algorithmic flops of the lower-triangle rank-2*nbw update: 8 nbw m (m+1)
+            const int id = B.timer ? B.timer->begin(KC_HER2K, 8.0 * nbw * (double)m * (m + 1) * np, st) : -1;
             hipLaunchKernelGGL(k_zgemm, dim3(tiles, np), dim3(256), 0, st, gd + (size_t)(4 * p) * np, m, m, 2 * kNB, 0, 1,
                                make_double2(-1.0, 0.0), make_double2(1.0, 0.0), 1);
+            if (B.timer) B.timer->end(id, st);
         }
     }
     hipLaunchKernelGGL(k_last_diag, dim3(cdiv(np, 64)), dim3(64), 0, st, pd, np);
     // ---- tridiagonal eigen-solver
+    const int idt = B.timer ? B.timer->begin(KC_TRIDIAG, 0.0, st) : -1;
     hipLaunchKernelGGL(k_bisect, dim3(cdiv(n, 128), np), dim3(128), 0, st, pd);
     hipLaunchKernelGGL(k_invit, dim3(cdiv(n, 64), np), dim3(64), 0, st, pd);
     hipLaunchKernelGGL(k_transpose, dim3(cdiv(n, 16), cdiv(n, 16), np), dim3(16, 16), 0, st, pd);
     hipLaunchKernelGGL(k_tri_orth, dim3(n, np), dim3(64), 0, st, pd, B.tri_gap_rel);
+    if (B.timer) B.timer->end(idt, st);
     // ---- back-transformation
+    const int idb = B.timer ? B.timer->begin(KC_BACKT, 8.0 * (double)n * n * n * np, st) : -1;
     hipLaunchKernelGGL(k_init_v0, dim3(cdiv((size_t)n * n, 256), np), dim3(256), 0, st, pd);
     hipLaunchKernelGGL(k_larft, dim3(npan, np), dim3(64), 0, st, pd);
     for (int p = npan - 1; p >= 0; p--) {
@@ -711,6 +724,7 @@ int stage1_run(const Stage1Batch &B, hipStream_t st)
         hipLaunchKernelGGL(k_zgemm, dim3(cdiv(m, 64) * cdiv(n, 64), np), dim3(256), 0, st, gd + (size_t)(4 * p + 3) * np,
                            m, n, nbw, 0, 0, make_double2(-1.0, 0.0), make_double2(1.0, 0.0), 0);
     }
+    if (B.timer) B.timer->end(idb, st);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

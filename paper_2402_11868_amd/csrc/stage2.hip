@@ -94,6 +94,40 @@ __device__ __forceinline__ dd acc_dd_final(double S, double C)
     return r;
 }
 
+// complex multi-limb accumulator; the double-double form keeps (sum,
+// compensation) pairs and costs 13 binary64 operations per real product
+template <int L>
+struct CAcc {
+    cmp<L> v;
+    __device__ void init(const cmp<L> &x) { v = x; }
+    __device__ void add_mulc(const cmp<L> &a, const cmp<L> &b) { v = c_add(v, c_mulc(a, b)); }   // += conj(a) b
+    __device__ void sub_mul(const cmp<L> &a, const cmp<L> &b) { v = c_sub(v, c_mul(a, b)); }     // -= a b
+    __device__ cmp<L> get() const { return v; }
+};
+
+template <>
+struct CAcc<2> {
+    double Sr, Cr, Si, Ci;
+    __device__ void init(const cmp<2> &x) { Sr = x.re.x[0]; Cr = x.re.x[1]; Si = x.im.x[0]; Ci = x.im.x[1]; }
+    __device__ void add_mulc(const cmp<2> &a, const cmp<2> &b)
+    {
+        // re += ar br + ai bi ; im += ar bi - ai br
+        acc_dd(Sr, Cr, a.re.x[0], a.re.x[1], b.re.x[0], b.re.x[1]);
+        acc_dd(Sr, Cr, a.im.x[0], a.im.x[1], b.im.x[0], b.im.x[1]);
+        acc_dd(Si, Ci, a.re.x[0], a.re.x[1], b.im.x[0], b.im.x[1]);
+        acc_dd(Si, Ci, -a.im.x[0], -a.im.x[1], b.re.x[0], b.re.x[1]);
+    }
+    __device__ void sub_mul(const cmp<2> &a, const cmp<2> &b)
+    {
+        // re -= ar br - ai bi ; im -= ar bi + ai br
+        acc_dd(Sr, Cr, -a.re.x[0], -a.re.x[1], b.re.x[0], b.re.x[1]);
+        acc_dd(Sr, Cr, a.im.x[0], a.im.x[1], b.im.x[0], b.im.x[1]);
+        acc_dd(Si, Ci, -a.re.x[0], -a.re.x[1], b.im.x[0], b.im.x[1]);
+        acc_dd(Si, Ci, -a.im.x[0], -a.im.x[1], b.re.x[0], b.re.x[1]);
+    }
+    __device__ cmp<2> get() const { return {acc_dd_final(Sr, Cr), acc_dd_final(Si, Ci)}; }
+};
+
 // ================================================================ init ====
 // v_k <- binary64 eigenvector (exact), sigma_k <- binary64 eigenvalue.
 // grid (npairs), block 256.
@@ -138,91 +172,11 @@ __device__ void normalise_vec(double *vec, size_t nn, int n, int k, mp<L> *red)
     __syncthreads();
 }
 
-// ================================================================== GS ====
-// One work-group (256) per cluster: members in index order; an active member
-// is orthogonalised (twice) against every converged member and every active
-// member of lower index, then normalised.
-template <int L>
-__global__ void __launch_bounds__(256) k_s2_gs(PairDesc *pairs, RqiProb *probs, const int *heads)
-{
-    const int h = heads[blockIdx.x];
-    const int csz = pairs[h].cl_size;
-    const RqiProb &P = probs[pairs[h].prob];
-    const int n = P.n;
-    const size_t nn = (size_t)n * n;
-    __shared__ mp<L> red[16];
-    constexpr int CH = 256;   // coefficients per chunk
-    __shared__ cmp<L> coef[CH];
-    __shared__ int jidx[CH];
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    bool any = false;
-    for (int a = 0; a < csz; a++) {
-        if (pairs[h + a].status == 0) any = true;
-    }
-    if (!any) return;
-    for (int a = 0; a < csz; a++) {
-        PairDesc &Qa = pairs[h + a];
-        if (Qa.status != 0) continue;
-        const int ka = Qa.k;
-        normalise_vec<L>(P.vec, nn, n, ka, red);
-        if (csz > 1) {
-            bool did = false;
-            for (int pass = 0; pass < 2; pass++) {
-                // eligible partners in chunks of CH
-                int b0 = 0;
-                while (b0 < csz) {
-                    // collect up to CH eligible indices from b0
-                    __syncthreads();
-                    int cnt = 0;
-                    int b = b0;
-                    if (tid == 0) {
-                        while (b < csz && cnt < CH) {
-                            const PairDesc &Qb = pairs[h + b];
-                            if (b != a && (Qb.status == 1 || (b < a && Qb.status == 0))) jidx[cnt++] = Qb.k;
-                            b++;
-                        }
-                        red[0].x[0] = (double)cnt;
-                        red[1].x[0] = (double)b;
-                    }
-                    __syncthreads();
-                    cnt = (int)red[0].x[0];
-                    b0 = (int)red[1].x[0];
-                    __syncthreads();
-                    if (cnt == 0) continue;
-                    did = true;
-                    // coefficients c_j = v_j^H v_a, one wave per partner
-                    for (int q = wid; q < cnt; q += 4) {
-                        const int kb = jidx[q];
-                        cmp<L> s = c_zero<L>();
-                        for (int i = lane; i < n; i += 64)
-                            s = c_add(s, c_mulc(ld_cmp<L>(P.vec, nn, (size_t)kb * n + i), ld_cmp<L>(P.vec, nn, (size_t)ka * n + i)));
-                        s.re = wave_sum_mp<L>(s.re);
-                        s.im = wave_sum_mp<L>(s.im);
-                        if (lane == 0) coef[q] = s;
-                    }
-                    __syncthreads();
-                    // v_a -= sum_j c_j v_j
-                    for (int i = tid; i < n; i += 256) {
-                        const size_t o = (size_t)ka * n + i;
-                        cmp<L> x = ld_cmp<L>(P.vec, nn, o);
-                        for (int q = 0; q < cnt; q++)
-                            x = c_sub(x, c_mul(coef[q], ld_cmp<L>(P.vec, nn, (size_t)jidx[q] * n + i)));
-                        st_cmp<L>(P.vec, nn, o, x);
-                    }
-                    __syncthreads();
-                }
-            }
-            if (did && tid == 0) Qa.flags |= 2;
-            normalise_vec<L>(P.vec, nn, n, ka, red);
-        }
-    }
-}
-
 // ================================================================== RQ ====
 // One work-group per active pair: y = H v, sigma = Re(v^H y), r = y - sigma v;
 // convergence, stagnation and iteration-limit decisions.
 template <int L>
-__global__ void __launch_bounds__(256) k_s2_rq(PairDesc *pairs, RqiProb *probs, const int *active, int max_iter, int final_pass)
+__global__ void __launch_bounds__(256) k_s2_rq(PairDesc *pairs, RqiProb *probs, const int *active, int final_pass)
 {
     PairDesc &Q = pairs[active[blockIdx.x]];
     const RqiProb &P = probs[Q.prob];
@@ -266,7 +220,7 @@ __global__ void __launch_bounds__(256) k_s2_rq(PairDesc *pairs, RqiProb *probs, 
         } else if (res * P.hnorm <= P.tol_abs) {
             Q.status = 1;
             Q.flags |= 1;
-        } else if (Q.iters >= max_iter) {
+        } else if (Q.iters >= P.max_iter) {
             Q.status = 2;
         } else if (Q.iters >= 3 && res > 0.5 * Q.prev_resid) {
             Q.status = 2;   // stagnated above the tolerance
@@ -391,9 +345,23 @@ __global__ void __launch_bounds__(256) k_s2_lu_panel(Stage2Batch B, int k0, int 
 
 // ============================================================= LU trsm ====
 // Trailing columns j in [k0+nbw, n]: apply the panel's interchanges, then
-// U12(:, j) = L11^{-1} A12(:, j).  grid (ceil(ncols/64), count), block 64.
+// U12(:, j) = L11^{-1} A12(:, j).  Eight columns per work-group of 256, 32
+// threads per column (one per row of the block): x_q is final at step q and
+// broadcast by a wave shuffle, every other row subtracts l_rq x_q into its
+// compensated accumulator.  grid (ceil(ncols/8), count).
 template <int L>
-__global__ void __launch_bounds__(64) k_s2_lu_trsm(Stage2Batch B, int k0, int nbw)
+__device__ __forceinline__ cmp<L> shfl_cmp(const cmp<L> &v, int src)
+{
+    cmp<L> r;
+    for (int l = 0; l < L; l++) {
+        r.re.x[l] = __shfl(v.re.x[l], src, 64);
+        r.im.x[l] = __shfl(v.im.x[l], src, 64);
+    }
+    return r;
+}
+
+template <int L>
+__global__ void __launch_bounds__(256) k_s2_lu_trsm(Stage2Batch B, int k0, int nbw)
 {
     const int t = blockIdx.y;
     const PairDesc &Q = B.dev_pairs[B.dev_active[t]];
@@ -402,28 +370,37 @@ __global__ void __launch_bounds__(64) k_s2_lu_trsm(Stage2Batch B, int k0, int nb
     double *M = B.lu_base + (size_t)t * B.lu_stride;
     const int *ipiv = B.piv_base + (size_t)t * B.piv_stride;
     const size_t plane = (size_t)ldm * (n + 1);
-    __shared__ cmp<L> l11[kLuNB][kLuNB];
-    for (int q = threadIdx.x; q < nbw * nbw; q += 64) {
-        const int r = q % nbw, cc = q / nbw;
-        if (r > cc) l11[r][cc] = ld_cmp<L>(M, plane, (size_t)(k0 + cc) * ldm + k0 + r);
+    __shared__ cmp<L> l11t[kLuNB][kLuNB];   // l11t[q][r] = L11(r, q)
+    for (int e = threadIdx.x; e < nbw * nbw; e += 256) {
+        const int r = e % nbw, q = e / nbw;
+        if (r > q) l11t[q][r] = ld_cmp<L>(M, plane, (size_t)(k0 + q) * ldm + k0 + r);
     }
-    __syncthreads();
-    const int j = k0 + nbw + blockIdx.x * 64 + threadIdx.x;
-    if (j > n) return;
+    const int cl = threadIdx.x >> 5, rr = threadIdx.x & 31, lane = threadIdx.x & 63;
+    const int j = k0 + nbw + blockIdx.x * 8 + cl;
+    const bool valid = j <= n;
     const size_t col = (size_t)j * ldm;
-    for (int r = 0; r < nbw; r++) {
-        const int p = ipiv[k0 + r];
-        if (p != k0 + r) {
-            const cmp<L> a = ld_cmp<L>(M, plane, col + k0 + r), b = ld_cmp<L>(M, plane, col + p);
-            st_cmp<L>(M, plane, col + k0 + r, b);
-            st_cmp<L>(M, plane, col + p, a);
+    if (valid && rr == 0) {
+        for (int r = 0; r < nbw; r++) {
+            const int p = ipiv[k0 + r];
+            if (p != k0 + r) {
+                const cmp<L> a = ld_cmp<L>(M, plane, col + k0 + r), b = ld_cmp<L>(M, plane, col + p);
+                st_cmp<L>(M, plane, col + k0 + r, b);
+                st_cmp<L>(M, plane, col + p, a);
+            }
         }
     }
-    for (int r = 1; r < nbw; r++) {
-        cmp<L> x = ld_cmp<L>(M, plane, col + k0 + r);
-        for (int q = 0; q < r; q++) x = c_sub(x, c_mul(l11[r][q], ld_cmp<L>(M, plane, col + k0 + q)));
-        st_cmp<L>(M, plane, col + k0 + r, x);
+    __syncthreads();
+    CAcc<L> acc;
+    acc.init((valid && rr < nbw) ? ld_cmp<L>(M, plane, col + k0 + rr) : c_zero<L>());
+    cmp<L> x = c_zero<L>();
+    const int src0 = lane & 32;
+    for (int q = 0; q < nbw; q++) {
+        const cmp<L> mine = acc.get();
+        const cmp<L> xq = shfl_cmp<L>(mine, src0 + q);
+        if (rr == q) x = mine;
+        if (rr > q) acc.sub_mul(l11t[q][rr], xq);
     }
+    if (valid && rr < nbw) st_cmp<L>(M, plane, col + k0 + rr, x);
 }
 
 // =========================================================== LU update ====
@@ -637,111 +614,356 @@ __global__ void k_s2_output(PairDesc *pairs, RqiProb *probs, const int *dst)
     }
 }
 
-// ======================================================= re-orthogonalise
-// Blocked classical Gram-Schmidt over all vectors of a matrix, in index order,
-// applied twice: block [j0, j0+B) is projected against vectors [0, j0)
-// (coefficients C = V_prev^H V_blk, then V_blk -= V_prev C), then made
-// orthonormal inside the block.  Problems of one launch share the order n.
-// Scratch C: per problem j0 x RB complex values, limb-planar (2L planes).
+// ====================================================== Gram-Schmidt ====
+// Block classical Gram-Schmidt in index order over a list of vector columns.
+// For a cluster the list is [converged members..., active members in index
+// order]; the converged prefix is left untouched and every active member is
+// made orthogonal (twice) to everything before it in the list: the converged
+// members and the active members of lower index.  The same kernels, with a
+// list of all columns of a matrix and an empty prefix, re-orthogonalise a
+// whole eigenbasis.  Blocks of RB active members: the block is projected
+// against all earlier entries (coefficients by 16x16 tiles, then the update),
+// then orthonormalised inside the block by modified Gram-Schmidt (twice).
 constexpr int RB = 32;
 
 template <int L>
-__global__ void __launch_bounds__(256) k_ro_dot(RqiProb *probs, const int *plist, int j0, double *scratch, size_t sstride)
+__global__ void __launch_bounds__(256) k_gs_dot(const GsCluster *cls, const int *list, const RqiProb *probs, int b,
+                                                double *scratch)
 {
-    const RqiProb &P = probs[plist[blockIdx.z]];
+    const GsCluster C = cls[blockIdx.z];
+    const int j0 = C.nconv + b * RB, bw = min(RB, C.nact - b * RB);
+    if (bw <= 0 || j0 == 0) return;
+    if (blockIdx.x * 16 >= j0 || blockIdx.y * 16 >= bw) return;
+    const RqiProb &P = probs[C.prob];
     const int n = P.n;
     const size_t nn = (size_t)n * n;
-    double *Cm = scratch + (size_t)blockIdx.z * sstride;
-    const size_t cplane = (size_t)j0 * RB;
+    const int *lst = list + C.off;
+    double *Cm = scratch + C.sofs;
+    const size_t cplane = (size_t)C.size * RB;
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    const int i = blockIdx.x * 16 + ty;            // previous vector
-    const int jb = blockIdx.y * 16 + tx;           // block member
-    __shared__ cmp<L> si[16][16], sj[16][16];      // [row][vector]
-    cmp<L> acc = c_zero<L>();
+    const int i = blockIdx.x * 16 + ty, jb = blockIdx.y * 16 + tx;
+    __shared__ cmp<L> si[16][16], sj[16][16];   // [row][vector]
+    const int vi = blockIdx.x * 16 + ty, vj = blockIdx.y * 16 + ty;
+    const int ci = vi < j0 ? lst[vi] : -1, cj = vj < bw ? lst[j0 + vj] : -1;
+    CAcc<L> acc;
+    acc.init(c_zero<L>());
     for (int r0 = 0; r0 < n; r0 += 16) {
         __syncthreads();
-        {
-            const int r = r0 + tx;   // row loaded by this thread
-            const int vi = blockIdx.x * 16 + ty, vj = j0 + blockIdx.y * 16 + ty;
-            si[tx][ty] = (r < n && vi < j0) ? ld_cmp<L>(P.vec, nn, (size_t)vi * n + r) : c_zero<L>();
-            sj[tx][ty] = (r < n && vj < j0 + RB && vj < n) ? ld_cmp<L>(P.vec, nn, (size_t)vj * n + r) : c_zero<L>();
-        }
+        const int r = r0 + tx;
+        si[tx][ty] = (r < n && ci >= 0) ? ld_cmp<L>(P.vec, nn, (size_t)ci * n + r) : c_zero<L>();
+        sj[tx][ty] = (r < n && cj >= 0) ? ld_cmp<L>(P.vec, nn, (size_t)cj * n + r) : c_zero<L>();
         __syncthreads();
-        for (int q = 0; q < 16; q++) acc = c_add(acc, c_mulc(si[q][ty], sj[q][tx]));
+        for (int q = 0; q < 16; q++) acc.add_mulc(si[q][ty], sj[q][tx]);
     }
-    if (i < j0 && jb < RB) st_cmp<L>(Cm, cplane, (size_t)jb * j0 + i, acc);
+    if (i < j0 && jb < bw) st_cmp<L>(Cm, cplane, (size_t)jb * C.size + i, acc.get());
 }
 
 template <int L>
-__global__ void __launch_bounds__(256) k_ro_update(RqiProb *probs, const int *plist, int j0, const double *scratch, size_t sstride)
+__global__ void __launch_bounds__(256) k_gs_update(const GsCluster *cls, const int *list, RqiProb *probs, int b,
+                                                   const double *scratch)
 {
-    const RqiProb &P = probs[plist[blockIdx.z]];
+    const GsCluster C = cls[blockIdx.z];
+    const int j0 = C.nconv + b * RB, bw = min(RB, C.nact - b * RB);
+    if (bw <= 0 || j0 == 0) return;
+    const RqiProb &P = probs[C.prob];
     const int n = P.n;
     const size_t nn = (size_t)n * n;
-    const double *Cm = scratch + (size_t)blockIdx.z * sstride;
-    const size_t cplane = (size_t)j0 * RB;
     const int r = blockIdx.x * 64 + (threadIdx.x & 63);
     const int jb = blockIdx.y * 4 + (threadIdx.x >> 6);
-    const int j = j0 + jb;
-    if (r >= n || j >= n || jb >= RB) return;
-    cmp<L> x = ld_cmp<L>(P.vec, nn, (size_t)j * n + r);
-    for (int i = 0; i < j0; i++) x = c_sub(x, c_mul(ld_cmp<L>(Cm, cplane, (size_t)jb * j0 + i), ld_cmp<L>(P.vec, nn, (size_t)i * n + r)));
-    st_cmp<L>(P.vec, nn, (size_t)j * n + r, x);
+    if (r >= n || jb >= bw) return;
+    const int *lst = list + C.off;
+    const double *Cm = scratch + C.sofs;
+    const size_t cplane = (size_t)C.size * RB;
+    const int cj = lst[j0 + jb];
+    CAcc<L> acc;
+    acc.init(ld_cmp<L>(P.vec, nn, (size_t)cj * n + r));
+    for (int i = 0; i < j0; i++)
+        acc.sub_mul(ld_cmp<L>(Cm, cplane, (size_t)jb * C.size + i), ld_cmp<L>(P.vec, nn, (size_t)lst[i] * n + r));
+    st_cmp<L>(P.vec, nn, (size_t)cj * n + r, acc.get());
 }
 
-// inside the block: modified Gram-Schmidt (twice) and normalisation; one
-// work-group per problem, coefficients of a member computed by the four waves
+// inside the block: modified Gram-Schmidt (twice) and normalisation; the
+// coefficients of a member are computed by the four waves in parallel
 template <int L>
-__global__ void __launch_bounds__(256) k_ro_intra(RqiProb *probs, const int *plist, int j0)
+__global__ void __launch_bounds__(256) k_gs_intra(const GsCluster *cls, const int *list, RqiProb *probs, PairDesc *pairs, int b)
 {
-    const RqiProb &P = probs[plist[blockIdx.x]];
+    const GsCluster C = cls[blockIdx.x];
+    const int j0 = C.nconv + b * RB, bw = min(RB, C.nact - b * RB);
+    if (bw <= 0) return;
+    const RqiProb &P = probs[C.prob];
     const int n = P.n;
     const size_t nn = (size_t)n * n;
-    const int bw = min(RB, n - j0);
+    const int *lst = list + C.off;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     __shared__ mp<L> red[16];
     __shared__ cmp<L> coef[RB];
     for (int a = 0; a < bw; a++) {
-        const int ka = j0 + a;
-        for (int pass = 0; pass < 2; pass++) {
-            if (a == 0) break;
+        const int ka = lst[j0 + a];
+        for (int pass = 0; pass < 2 && a > 0; pass++) {
             for (int q = wid; q < a; q += 4) {
-                cmp<L> s = c_zero<L>();
+                const int kq = lst[j0 + q];
+                CAcc<L> s;
+                s.init(c_zero<L>());
                 for (int i = lane; i < n; i += 64)
-                    s = c_add(s, c_mulc(ld_cmp<L>(P.vec, nn, (size_t)(j0 + q) * n + i), ld_cmp<L>(P.vec, nn, (size_t)ka * n + i)));
-                s.re = wave_sum_mp<L>(s.re);
-                s.im = wave_sum_mp<L>(s.im);
-                if (lane == 0) coef[q] = s;
+                    s.add_mulc(ld_cmp<L>(P.vec, nn, (size_t)kq * n + i), ld_cmp<L>(P.vec, nn, (size_t)ka * n + i));
+                cmp<L> c = s.get();
+                c.re = wave_sum_mp<L>(c.re);
+                c.im = wave_sum_mp<L>(c.im);
+                if (lane == 0) coef[q] = c;
             }
             __syncthreads();
             for (int i = tid; i < n; i += 256) {
                 const size_t o = (size_t)ka * n + i;
-                cmp<L> x = ld_cmp<L>(P.vec, nn, o);
-                for (int q = 0; q < a; q++) x = c_sub(x, c_mul(coef[q], ld_cmp<L>(P.vec, nn, (size_t)(j0 + q) * n + i)));
-                st_cmp<L>(P.vec, nn, o, x);
+                CAcc<L> x;
+                x.init(ld_cmp<L>(P.vec, nn, o));
+                for (int q = 0; q < a; q++) x.sub_mul(coef[q], ld_cmp<L>(P.vec, nn, (size_t)lst[j0 + q] * n + i));
+                st_cmp<L>(P.vec, nn, o, x.get());
             }
             __syncthreads();
         }
         normalise_vec<L>(P.vec, nn, n, ka, red);
+        if (tid == 0 && C.size > 1 && pairs) pairs[C.pair_base + ka].flags |= 2;
     }
 }
 
 template <int L>
-int stage2_reorth(RqiProb *probs, const int *plist, int nprob, int n, double *scratch, size_t sstride, hipStream_t st)
+int stage2_gs(const GsPlan &G, RqiProb *probs, PairDesc *pairs, hipStream_t st)
 {
-    for (int j0 = 0; j0 < n; j0 += RB) {
-        for (int pass = 0; pass < 2 && j0 > 0; pass++) {
-            hipLaunchKernelGGL(k_ro_dot<L>, dim3((j0 + 15) / 16, RB / 16, nprob), dim3(256), 0, st, probs, plist, j0, scratch, sstride);
-            hipLaunchKernelGGL(k_ro_update<L>, dim3((n + 63) / 64, RB / 4, nprob), dim3(256), 0, st, probs, plist, j0,
-                               (const double *)scratch, sstride);
+    if (G.ncl <= 0) return 0;
+    for (int b = 0; b < G.max_blocks; b++) {
+        const int j0max = G.max_nconv + b * RB;
+        if (j0max > 0) {
+            for (int pass = 0; pass < 2; pass++) {
+                hipLaunchKernelGGL(k_gs_dot<L>, dim3((j0max + 15) / 16, RB / 16, G.ncl), dim3(256), 0, st, G.dev_cls,
+                                   G.dev_list, (const RqiProb *)probs, b, G.scratch);
+                hipLaunchKernelGGL(k_gs_update<L>, dim3((G.max_n + 63) / 64, RB / 4, G.ncl), dim3(256), 0, st, G.dev_cls,
+                                   G.dev_list, probs, b, (const double *)G.scratch);
+            }
         }
-        hipLaunchKernelGGL(k_ro_intra<L>, dim3(nprob), dim3(256), 0, st, probs, plist, j0);
+        hipLaunchKernelGGL(k_gs_intra<L>, dim3(G.ncl), dim3(256), 0, st, G.dev_cls, G.dev_list, probs, pairs, b);
     }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-template int stage2_reorth<2>(RqiProb *, const int *, int, int, double *, size_t, hipStream_t);
-template int stage2_reorth<4>(RqiProb *, const int *, int, int, double *, size_t, hipStream_t);
+template int stage2_gs<2>(const GsPlan &, RqiProb *, PairDesc *, hipStream_t);
+template int stage2_gs<4>(const GsPlan &, RqiProb *, PairDesc *, hipStream_t);
+
+// ====================================================== Rayleigh-Ritz ====
+// For a small cluster (2..RRMAX members, binary64 vectors already made
+// orthonormal in L limbs): C = V^H H V (k x k), its eigendecomposition
+// C = Q diag(theta) Q^H by cyclic two-sided Jacobi in L limbs (round-robin
+// ordering, k/2 rotations per round), then V <- V Q and sigma_j <- theta_j.
+// The Ritz vectors separate the members of the cluster, which the binary64
+// vectors mix when the gaps inside the cluster are near binary64 resolution.
+constexpr int RRMAX = 32;
+
+// Y = H V for every member of the Rayleigh-Ritz clusters; one work-group per
+// member; Y in scratch at cluster offset + member * n (limb-planar, 2L planes
+// of n*RRMAX per cluster).
+template <int L>
+__global__ void __launch_bounds__(256) k_rr_hv(const GsCluster *cls, const int *list, const RqiProb *probs, double *scratch)
+{
+    const GsCluster C = cls[blockIdx.y];
+    const int a = blockIdx.x;
+    if (a >= C.size) return;
+    const RqiProb &P = probs[C.prob];
+    const int n = P.n;
+    const size_t nn = (size_t)n * n;
+    const int ka = list[C.off + a];
+    double *Y = scratch + C.sofs;
+    const size_t yplane = (size_t)n * RRMAX;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        CAcc<L> y;
+        y.init(c_zero<L>());
+        for (int j = 0; j < n; j++) {
+            const cmp<L> h = ld_h<L>(P, i, j);
+            const cmp<L> v = ld_cmp<L>(P.vec, nn, (size_t)ka * n + j);
+            // y += h v  ==  y -= (-h) v
+            y.sub_mul(cmp<L>{mp_neg<L>(h.re), mp_neg<L>(h.im)}, v);
+        }
+        st_cmp<L>(Y, yplane, (size_t)a * n + i, y.get());
+    }
+}
+
+template <int L>
+__device__ void rr_rotate_params(const cmp<L> &b, const mp<L> &a, const mp<L> &d, mp<L> &c, mp<L> &s, cmp<L> &e, mp<L> &tb,
+                                 bool &active)
+{
+    const mp<L> ab2 = c_abs2(b);
+    active = ab2.x[0] > 0.0;
+    if (!active) return;
+    const mp<L> ab = sqrt_mp(ab2);
+    // negligible coupling
+    const double scale = fabs(a.x[0]) + fabs(d.x[0]);
+    if (ab.x[0] <= ldexp(scale, -53 * L - 8)) {
+        active = false;
+        return;
+    }
+    const mp<L> inv = div(mp_from<L>(1.0), ab);
+    e.re = mul(b.re, inv);                 // e = conj(b)/|b|
+    e.im = mp_neg<L>(mul(b.im, inv));
+    mp<L> zeta = mul_d(div(sub(d, a), ab), 0.5);
+    mp<L> t;
+    if (zeta.x[0] == 0.0) {
+        t = mp_from<L>(1.0);
+    } else {
+        const mp<L> az = zeta.x[0] < 0.0 ? mp_neg<L>(zeta) : zeta;
+        const mp<L> den = add(az, sqrt_mp(add_d(mul(zeta, zeta), 1.0)));
+        t = div(mp_from<L>(zeta.x[0] < 0.0 ? -1.0 : 1.0), den);
+    }
+    c = div(mp_from<L>(1.0), sqrt_mp(add_d(mul(t, t), 1.0)));
+    s = mul(t, c);
+    tb = mul(t, ab);
+}
+
+template <int L>
+__global__ void __launch_bounds__(256) k_rr_solve(const GsCluster *cls, const int *list, RqiProb *probs, const double *scratch,
+                                                  int sweeps)
+{
+    const GsCluster C = cls[blockIdx.x];
+    const int k = C.size;
+    const RqiProb &P = probs[C.prob];
+    const int n = P.n;
+    const size_t nn = (size_t)n * n;
+    const int *lst = list + C.off;
+    const double *Y = scratch + C.sofs;
+    const size_t yplane = (size_t)n * RRMAX;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    __shared__ cmp<L> Cm[RRMAX][RRMAX + 1];
+    __shared__ cmp<L> Qm[RRMAX][RRMAX + 1];
+    __shared__ int pp[RRMAX / 2], qq[RRMAX / 2], ord[RRMAX];
+    __shared__ mp<L> rc[RRMAX / 2], rs[RRMAX / 2], rtb[RRMAX / 2], ra[RRMAX / 2], rd[RRMAX / 2];
+    __shared__ cmp<L> re_[RRMAX / 2];
+    __shared__ int ract[RRMAX / 2];
+    // C(i, j) = v_i^H y_j, i <= j, one wave per entry
+    for (int e = wid; e < k * k; e += 4) {
+        const int i = e % k, j = e / k;
+        if (i > j) continue;
+        CAcc<L> acc;
+        acc.init(c_zero<L>());
+        for (int r = lane; r < n; r += 64)
+            acc.add_mulc(ld_cmp<L>(P.vec, nn, (size_t)lst[i] * n + r), ld_cmp<L>(Y, yplane, (size_t)j * n + r));
+        cmp<L> v = acc.get();
+        v.re = wave_sum_mp<L>(v.re);
+        v.im = wave_sum_mp<L>(v.im);
+        if (lane == 0) {
+            if (i == j) v.im = mp_zero<L>();
+            Cm[i][j] = v;
+            Cm[j][i] = c_conj(v);
+        }
+    }
+    for (int e = tid; e < k * k; e += 256) {
+        const int i = e % k, j = e / k;
+        Qm[i][j] = c_zero<L>();
+        if (i == j) Qm[i][j].re = mp_from<L>(1.0);
+    }
+    const int m = k + (k & 1);   // pad odd k with a dummy index k
+    if (tid < m) ord[tid] = tid;
+    __syncthreads();
+    for (int sw = 0; sw < sweeps; sw++) {
+        for (int round = 0; round < m - 1; round++) {
+            const int npair = m / 2;
+            if (tid < npair) {
+                int p = ord[tid], q = ord[m - 1 - tid];
+                if (p > q) { const int tt = p; p = q; q = tt; }
+                pp[tid] = p;
+                qq[tid] = q;
+                bool act = false;
+                if (q < k) {
+                    mp<L> c, s_, tb;
+                    cmp<L> e;
+                    rr_rotate_params<L>(Cm[p][q], Cm[p][p].re, Cm[q][q].re, c, s_, e, tb, act);
+                    if (act) {
+                        rc[tid] = c; rs[tid] = s_; re_[tid] = e; rtb[tid] = tb;
+                        ra[tid] = Cm[p][p].re; rd[tid] = Cm[q][q].re;
+                    }
+                }
+                ract[tid] = act ? 1 : 0;
+            }
+            __syncthreads();
+            // column ops on C and Q: [x, y] <- [c x - s e y, s x + c e y]
+            for (int w = tid; w < npair * k * 2; w += 256) {
+                const int mat = w / (npair * k), rem = w % (npair * k);
+                const int r = rem % npair, i = rem / npair;
+                if (!ract[r]) continue;
+                cmp<L>(*A)[RRMAX + 1] = mat ? Qm : Cm;
+                const int p = pp[r], q = qq[r];
+                const cmp<L> x = A[i][p], y = c_mul(re_[r], A[i][q]);
+                A[i][p] = c_sub(c_scale(x, rc[r]), c_scale(y, rs[r]));
+                A[i][q] = c_add(c_scale(x, rs[r]), c_scale(y, rc[r]));
+            }
+            __syncthreads();
+            // row ops on C: [x; y] <- [c x - s conj(e) y ; s x + c conj(e) y]
+            for (int w = tid; w < npair * k; w += 256) {
+                const int r = w % npair, j = w / npair;
+                if (!ract[r]) continue;
+                const int p = pp[r], q = qq[r];
+                const cmp<L> x = Cm[p][j], y = c_mul(c_conj(re_[r]), Cm[q][j]);
+                Cm[p][j] = c_sub(c_scale(x, rc[r]), c_scale(y, rs[r]));
+                Cm[q][j] = c_add(c_scale(x, rs[r]), c_scale(y, rc[r]));
+            }
+            __syncthreads();
+            if (tid < npair && ract[tid]) {
+                const int p = pp[tid], q = qq[tid];
+                Cm[p][q] = c_zero<L>();
+                Cm[q][p] = c_zero<L>();
+                Cm[p][p].re = sub(ra[tid], rtb[tid]);
+                Cm[p][p].im = mp_zero<L>();
+                Cm[q][q].re = add(rd[tid], rtb[tid]);
+                Cm[q][q].im = mp_zero<L>();
+            }
+            __syncthreads();
+            if (tid == 0) {
+                const int last = ord[m - 1];
+                for (int q = m - 1; q > 1; q--) ord[q] = ord[q - 1];
+                ord[1] = last;
+            }
+            __syncthreads();
+        }
+    }
+    // ascending Ritz values (selection by rank; ties by index)
+    if (tid < k) {
+        int rank = 0;
+        const double ti = Cm[tid][tid].re.x[0], tl = (L > 1) ? Cm[tid][tid].re.x[1] : 0.0;
+        for (int j = 0; j < k; j++) {
+            const double tj = Cm[j][j].re.x[0], tjl = (L > 1) ? Cm[j][j].re.x[1] : 0.0;
+            if (tj < ti || (tj == ti && (tjl < tl || (tjl == tl && j < tid)))) rank++;
+        }
+        ord[rank] = tid;
+    }
+    __syncthreads();
+    // sigma of member j <- Ritz value ord[j]
+    if (tid < k) {
+        const mp<L> th = Cm[ord[tid]][ord[tid]].re;
+        for (int l = 0; l < L; l++) P.sigma[(size_t)l * n + lst[tid]] = th.x[l];
+    }
+    // V <- V Q (columns permuted to ascending order); one row per thread
+    for (int r = tid; r < n; r += 256) {
+        cmp<L> old[RRMAX];
+        for (int i = 0; i < RRMAX; i++)
+            if (i < k) old[i] = ld_cmp<L>(P.vec, nn, (size_t)lst[i] * n + r);
+        for (int j = 0; j < k; j++) {
+            CAcc<L> acc;
+            acc.init(c_zero<L>());
+            for (int i = 0; i < RRMAX; i++)
+                if (i < k) acc.sub_mul(cmp<L>{mp_neg<L>(old[i].re), mp_neg<L>(old[i].im)}, Qm[i][ord[j]]);
+            st_cmp<L>(P.vec, nn, (size_t)lst[j] * n + r, acc.get());
+        }
+    }
+}
+
+template <int L>
+int stage2_rr(const GsPlan &G, RqiProb *probs, int sweeps, hipStream_t st)
+{
+    if (G.ncl <= 0) return 0;
+    hipLaunchKernelGGL(k_rr_hv<L>, dim3(RRMAX, G.ncl), dim3(256), 0, st, G.dev_cls, G.dev_list, (const RqiProb *)probs, G.scratch);
+    hipLaunchKernelGGL(k_rr_solve<L>, dim3(G.ncl), dim3(256), 0, st, G.dev_cls, G.dev_list, probs, (const double *)G.scratch,
+                       sweeps);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template int stage2_rr<2>(const GsPlan &, RqiProb *, int, hipStream_t);
+template int stage2_rr<4>(const GsPlan &, RqiProb *, int, hipStream_t);
 
 // ================================================================ host ====
 static inline unsigned cdiv2(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
@@ -754,19 +976,10 @@ int stage2_init(PairDesc *pairs, RqiProb *probs, int npairs, hipStream_t st)
 }
 
 template <int L>
-int stage2_gs(PairDesc *pairs, RqiProb *probs, const int *heads, int nclusters, hipStream_t st)
-{
-    if (nclusters <= 0) return 0;
-    hipLaunchKernelGGL(k_s2_gs<L>, dim3(nclusters), dim3(256), 0, st, pairs, probs, heads);
-    return hipGetLastError() == hipSuccess ? 0 : -1;
-}
-
-template <int L>
 int stage2_rq(const Stage2Batch &B, hipStream_t st)
 {
     if (B.count <= 0) return 0;
-    hipLaunchKernelGGL(k_s2_rq<L>, dim3(B.count), dim3(256), 0, st, B.dev_pairs, B.dev_probs, B.dev_active, B.max_iter,
-                       B.final_pass);
+    hipLaunchKernelGGL(k_s2_rq<L>, dim3(B.count), dim3(256), 0, st, B.dev_pairs, B.dev_probs, B.dev_active, B.final_pass);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -775,15 +988,25 @@ int stage2_solve(const Stage2Batch &B, hipStream_t st)
 {
     const int n = B.n, cnt = B.count;
     if (cnt <= 0) return 0;
+    KernelTimer dummy;
+    KernelTimer &T = B.timer ? *B.timer : dummy;
+    int id = T.begin(KC_BUILD, 0.0, st);
     hipLaunchKernelGGL(k_s2_build<L>, dim3(cdiv2(n + 1, 8), cnt), dim3(256), 0, st, B);
+    T.end(id, st);
     for (int k0 = 0; k0 < n; k0 += kLuNB) {
         const int nbw = std::min(kLuNB, n - k0);
+        id = T.begin(KC_LU_PANEL, (double)cnt * (n - k0) * nbw * nbw * 0.5, st);
         hipLaunchKernelGGL(k_s2_lu_panel<L>, dim3(cnt), dim3(256), 0, st, B, k0, nbw);
+        T.end(id, st);
         const int r0 = k0 + nbw;
         const int ncols = n + 1 - r0;
-        hipLaunchKernelGGL(k_s2_lu_trsm<L>, dim3(cdiv2(ncols, 64), cnt), dim3(64), 0, st, B, k0, nbw);
+        id = T.begin(KC_LU_TRSM, (double)cnt * ncols * nbw * nbw * 0.5, st);
+        hipLaunchKernelGGL(k_s2_lu_trsm<L>, dim3(cdiv2(ncols, 8), cnt), dim3(256), 0, st, B, k0, nbw);
+        T.end(id, st);
         const int mrows = n - r0;
         if (mrows > 0) {
+            // algorithmic work: complex multi-limb multiply-adds of A22 -= L21 U12
+            id = T.begin(KC_LU_UPDATE, (double)cnt * mrows * ncols * nbw, st);
             if (L == 2) {
                 const unsigned tiles = cdiv2(mrows, 64) * cdiv2(ncols, 64);
                 hipLaunchKernelGGL(k_s2_lu_update_dd, dim3(tiles, cnt), dim3(256), 0, st, B, k0, nbw);
@@ -791,9 +1014,13 @@ int stage2_solve(const Stage2Batch &B, hipStream_t st)
                 const unsigned tiles = cdiv2(mrows, 32) * cdiv2(ncols, 32);
                 hipLaunchKernelGGL(k_s2_lu_update_gen<L>, dim3(tiles, cnt), dim3(256), 0, st, B, k0, nbw);
             }
+            T.end(id, st);
         }
     }
+    id = T.begin(KC_BACKSOLVE, (double)cnt * n * n * 0.5, st);
     hipLaunchKernelGGL(k_s2_backsolve<L>, dim3(cnt), dim3(256), 0, st, B);
+    T.end(id, st);
+    if (!B.timer) dummy.collect();
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -806,8 +1033,6 @@ int stage2_output(PairDesc *pairs, RqiProb *probs, const int *dst, int npairs, h
 
 template int stage2_init<2>(PairDesc *, RqiProb *, int, hipStream_t);
 template int stage2_init<4>(PairDesc *, RqiProb *, int, hipStream_t);
-template int stage2_gs<2>(PairDesc *, RqiProb *, const int *, int, hipStream_t);
-template int stage2_gs<4>(PairDesc *, RqiProb *, const int *, int, hipStream_t);
 template int stage2_rq<2>(const Stage2Batch &, hipStream_t);
 template int stage2_rq<4>(const Stage2Batch &, hipStream_t);
 template int stage2_solve<2>(const Stage2Batch &, hipStream_t);
