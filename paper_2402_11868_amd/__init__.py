@@ -126,6 +126,7 @@ class Context:
         if rc != ZK_OK:
             raise RuntimeError(f"zk_ctx_create failed: {status_str(rc)}")
         self.handle = h
+        self._sessions = []
 
     def prof(self, on: bool = True):
         load().zk_prof_enable(self.handle, int(bool(on)))
@@ -146,6 +147,9 @@ class Context:
         return load().zk_ctx_last_error(self.handle).decode()
 
     def close(self):
+        # sessions run on this context: stop them first
+        for s in getattr(self, "_sessions", []):
+            s.close()
         if getattr(self, "handle", None):
             load().zk_ctx_destroy(self.handle)
             self.handle = None
@@ -302,6 +306,7 @@ class Session:
         self.ctx = ctx
         self.handle = h
         self._req = {}
+        ctx._sessions.append(self)
 
     def submit(self, planes, limbs_out: int = 2, opts: ZkOpts | None = None) -> int:
         """Queue a request; returns its ticket.  Raises on ZK_EINVAL / ZK_ENOMEM / ZK_EAGAIN."""

@@ -51,6 +51,7 @@ struct S2Prob {
     zk_pair_info *info = nullptr;
     std::vector<PairDesc> pairs;   // authoritative host copy of the pair states
     std::vector<int> heads;        // local index of every cluster's first pair
+    std::vector<char> ritz;        // per head: the cluster received a Rayleigh-Ritz step
     void *vecbuf = nullptr;
     size_t vecbytes = 0;
     int status = ZK_OK;
@@ -65,6 +66,10 @@ class Stage2Engine {
     ~Stage2Engine()
     {
         for (S2Prob *p : live) release(p);
+        if (gsbuf) {
+            hipFree(gsbuf);
+            ctx->extra -= gsbytes;
+        }
     }
 
     std::vector<S2Prob *> live;      // matrices still iterating
@@ -127,11 +132,12 @@ class Stage2Engine {
         for (S2Prob *p : batch)
             for (auto &q : p->pairs) q.status = 0;
         if ((rc = run_gs(batch, false)) != ZK_OK) return rc;
-        if ((rc = run_rr(batch)) != ZK_OK) return rc;
+        if ((rc = run_rr(batch, true)) != ZK_OK) return rc;
         std::vector<int> all(total_pairs);
         for (int g = 0; g < total_pairs; g++) all[g] = g;
         if ((rc = run_rq(all, 0)) != ZK_OK) return rc;
         if ((rc = download(batch)) != ZK_OK) return rc;
+        if (std::getenv("ZK_TRACE") && std::atoi(std::getenv("ZK_TRACE")) >= 2) dump(batch, "add");
         for (S2Prob *p : batch) live.push_back(p);
         return settle();
     }
@@ -174,12 +180,14 @@ class Stage2Engine {
                 }
             }
             if ((rc = run_gs(live, false)) != ZK_OK) return rc;
+            if ((rc = run_rr(live, false)) != ZK_OK) return rc;
             std::vector<int> all;
             for (auto &kv : by_n) all.insert(all.end(), kv.second.begin(), kv.second.end());
             if ((rc = run_rq(all, 0)) != ZK_OK) return rc;
             if ((rc = download(live)) != ZK_OK) return rc;
             rounds++;
             if (std::getenv("ZK_TRACE")) trace();
+            if (std::getenv("ZK_TRACE") && std::atoi(std::getenv("ZK_TRACE")) >= 2) dump(live, "round");
         }
         return settle();
     }
@@ -203,6 +211,30 @@ class Stage2Engine {
     int S = 0, slot_n = 0;
 
     int HIPFAIL(hipError_t e, const char *what) { return ctx->fail(ZK_EDEVICE, "%s: %s", what, hipGetErrorString(e)); }
+
+    void *gsbuf = nullptr;
+    size_t gsbytes = 0;
+
+    int ensure_gs(size_t bytes)
+    {
+        if (bytes <= gsbytes) return ZK_OK;
+        if (gsbuf) {
+            hipFree(gsbuf);
+            ctx->extra -= gsbytes;
+            gsbuf = nullptr;
+            gsbytes = 0;
+        }
+        bytes = std::max(bytes, (size_t)1 << 20);
+        if (ctx->held() + bytes > ctx->budget) return ctx->fail(ZK_ENOMEM, "Gram-Schmidt plan exceeds the budget");
+        if (hipMalloc(&gsbuf, bytes) != hipSuccess) {
+            gsbuf = nullptr;
+            hipGetLastError();
+            return ctx->fail(ZK_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
+        }
+        gsbytes = bytes;
+        ctx->extra += bytes;
+        return ZK_OK;
+    }
 
     void release(S2Prob *p)
     {
@@ -352,22 +384,31 @@ class Stage2Engine {
         } else {
             for (size_t pi = 0; pi < set.size(); pi++) {
                 S2Prob *p = set[pi];
-                for (int h : p->heads) {
+                for (size_t hi = 0; hi < p->heads.size(); hi++) {
+                    const int h = p->heads[hi];
                     const int sz = p->pairs[h].cl_size;
                     std::vector<int> fro, act;
                     for (int q = 0; q < sz; q++) (p->pairs[h + q].status == 0 ? act : fro).push_back(p->pairs[h + q].k);
-                    if (!act.empty()) add((int)pi, fro, act);
+                    if (act.empty()) continue;
+                    add((int)pi, fro, act);
                 }
             }
         }
         if (cls.empty()) return ZK_OK;
-        if ((size_t)sofs * 8 > gs_scratch_bytes) return ctx->fail(ZK_EINTERNAL, "Gram-Schmidt scratch too small");
-        HIPCHK_(hipMemcpyAsync(d_gcls, cls.data(), sizeof(GsCluster) * cls.size(), hipMemcpyHostToDevice, st));
-        HIPCHK_(hipMemcpyAsync(d_glist, list.data(), 4 * list.size(), hipMemcpyHostToDevice, st));
+        // plan storage sized from the plan itself: clusters, column lists, coefficient scratch
+        const size_t b_cls = s2_align(sizeof(GsCluster) * cls.size()), b_list = s2_align(4 * list.size());
+        const size_t b_scr = s2_align((size_t)sofs * 8);
+        int rc = ensure_gs(b_cls + b_list + b_scr);
+        if (rc != ZK_OK) return rc;
+        GsCluster *g_cls = (GsCluster *)gsbuf;
+        int *g_list = (int *)((char *)gsbuf + b_cls);
+        double *g_scr = (double *)((char *)gsbuf + b_cls + b_list);
+        HIPCHK_(hipMemcpyAsync(g_cls, cls.data(), sizeof(GsCluster) * cls.size(), hipMemcpyHostToDevice, st));
+        HIPCHK_(hipMemcpyAsync(g_list, list.data(), 4 * list.size(), hipMemcpyHostToDevice, st));
         G.ncl = (int)cls.size();
-        G.dev_cls = d_gcls;
-        G.dev_list = d_glist;
-        G.scratch = d_gscratch;
+        G.dev_cls = g_cls;
+        G.dev_list = g_list;
+        G.scratch = g_scr;
         KernelTimer *tm = ctx->tp();
         const int id = tm ? tm->begin(global ? KC_REORTH : KC_GS, (double)list.size(), st) : -1;
         if (stage2_gs<L>(G, d_probs, global ? nullptr : d_pairs, st)) return ctx->fail(ZK_EDEVICE, "Gram-Schmidt launch failed");
@@ -376,61 +417,62 @@ class Stage2Engine {
         return ZK_OK;
     }
 
-    // Rayleigh-Ritz inside the clusters of 2..32 members of a new batch
-    int run_rr(const std::vector<S2Prob *> &set)
+    // Rayleigh-Ritz inside the clusters of 2..32 members.  first = true: every
+    // member of every such cluster of a new batch (and the clusters are
+    // marked); otherwise the active members of marked clusters, when at least
+    // two are active.  Scratch comes from the engine's own buffer, sized from
+    // the plan, so the step never depends on what other buffers hold.
+    int run_rr(const std::vector<S2Prob *> &set, bool first)
     {
-        int max_n = 1;
-        for (S2Prob *p : set) max_n = std::max(max_n, p->rp.n);
-        int rc = ensure_slots(max_n, 1);   // the slot memory is free here: use it as scratch
-        if (rc != ZK_OK) return rc;
-        const size_t cap = ctx->s2lu.bytes / 8;
         std::vector<GsCluster> cls;
         std::vector<int> list;
         long long sofs = 0;
-        auto flush = [&]() -> int {
-            if (cls.empty()) return ZK_OK;
-            HIPCHK_(hipMemcpyAsync(d_gcls, cls.data(), sizeof(GsCluster) * cls.size(), hipMemcpyHostToDevice, st));
-            HIPCHK_(hipMemcpyAsync(d_glist, list.data(), 4 * list.size(), hipMemcpyHostToDevice, st));
-            GsPlan G;
-            std::memset(&G, 0, sizeof G);
-            G.ncl = (int)cls.size();
-            G.dev_cls = d_gcls;
-            G.dev_list = d_glist;
-            G.scratch = (double *)ctx->s2lu.p;
-            KernelTimer *tm = ctx->tp();
-            const int id = tm ? tm->begin(KC_GS, (double)list.size(), st) : -1;
-            if (stage2_rr<L>(G, d_probs, L == 2 ? 10 : 14, st)) return ctx->fail(ZK_EDEVICE, "Rayleigh-Ritz launch failed");
-            if (tm) tm->end(id, st);
-            HIPCHK_(hipStreamSynchronize(st));
-            cls.clear();
-            list.clear();
-            sofs = 0;
-            return ZK_OK;
-        };
         for (size_t pi = 0; pi < set.size(); pi++) {
             S2Prob *p = set[pi];
-            const size_t need = (size_t)2 * L * p->rp.n * 32;
-            if (need > cap) continue;   // no room: skip the Ritz step
-            for (int h : p->heads) {
+            if (first) p->ritz.assign(p->heads.size(), 0);
+            for (size_t hi = 0; hi < p->heads.size(); hi++) {
+                const int h = p->heads[hi];
                 const int sz = p->pairs[h].cl_size;
                 if (sz < 2 || sz > 32) continue;
-                if ((size_t)sofs + need > cap || cls.size() >= (size_t)total_pairs) {
-                    if ((rc = flush()) != ZK_OK) return rc;
-                }
+                if (!first && !p->ritz[hi]) continue;
+                std::vector<int> mem;
+                for (int q = 0; q < sz; q++)
+                    if (first || p->pairs[h + q].status == 0) mem.push_back(p->pairs[h + q].k);
+                if (mem.size() < 2) continue;
+                if (first) p->ritz[hi] = 1;
                 GsCluster c;
                 c.prob = (int)pi;
                 c.pair_base = base[pi];
                 c.off = (int)list.size();
                 c.nconv = 0;
-                c.nact = sz;
-                c.size = sz;
+                c.nact = (int)mem.size();
+                c.size = (int)mem.size();
                 c.sofs = sofs;
-                sofs += (long long)need;
-                for (int q = 0; q < sz; q++) list.push_back(p->pairs[h + q].k);
+                sofs += (long long)2 * L * p->rp.n * 32;
+                list.insert(list.end(), mem.begin(), mem.end());
                 cls.push_back(c);
             }
         }
-        return flush();
+        if (cls.empty()) return ZK_OK;
+        const size_t b_cls = s2_align(sizeof(GsCluster) * cls.size()), b_list = s2_align(4 * list.size());
+        int rc = ensure_gs(b_cls + b_list + s2_align((size_t)sofs * 8));
+        if (rc != ZK_OK) return rc;
+        GsCluster *g_cls = (GsCluster *)gsbuf;
+        int *g_list = (int *)((char *)gsbuf + b_cls);
+        HIPCHK_(hipMemcpyAsync(g_cls, cls.data(), sizeof(GsCluster) * cls.size(), hipMemcpyHostToDevice, st));
+        HIPCHK_(hipMemcpyAsync(g_list, list.data(), 4 * list.size(), hipMemcpyHostToDevice, st));
+        GsPlan G;
+        std::memset(&G, 0, sizeof G);
+        G.ncl = (int)cls.size();
+        G.dev_cls = g_cls;
+        G.dev_list = g_list;
+        G.scratch = (double *)((char *)gsbuf + b_cls + b_list);
+        KernelTimer *tm = ctx->tp();
+        const int id = tm ? tm->begin(KC_GS, (double)list.size(), st) : -1;
+        if (stage2_rr<L>(G, d_probs, L == 2 ? 10 : 14, st)) return ctx->fail(ZK_EDEVICE, "Rayleigh-Ritz launch failed");
+        if (tm) tm->end(id, st);
+        HIPCHK_(hipStreamSynchronize(st));
+        return ZK_OK;
     }
 
     // finalise the live matrices that have no active pair
@@ -448,12 +490,13 @@ class Stage2Engine {
         std::vector<int> ro;
         for (int pi : fin)
             if (live[pi]->opts.reorth) ro.push_back(pi);
-        if (!ro.empty()) {
+        if (!ro.empty())
             if ((rc = run_gs(live, true, &ro)) != ZK_OK) return rc;
+        {
+            // every finished pair is judged once more against the tolerance
             std::vector<int> idx;
-            for (int pi : ro)
-                if (live[pi]->npairs == live[pi]->rp.n && live[pi]->rp.n > 1)
-                    for (int k = 0; k < live[pi]->npairs; k++) idx.push_back(base[pi] + k);
+            for (int pi : fin)
+                for (int k = 0; k < live[pi]->npairs; k++) idx.push_back(base[pi] + k);
             if ((rc = run_rq(idx, 1)) != ZK_OK) return rc;
             if ((rc = download(live)) != ZK_OK) return rc;
         }
@@ -523,6 +566,17 @@ class Stage2Engine {
         }
         live = keep;
         return ZK_OK;
+    }
+
+    void dump(const std::vector<S2Prob *> &set, const char *what)
+    {
+        for (S2Prob *p : set) {
+            std::vector<double> sig((size_t)L * p->rp.n);
+            hipMemcpy(sig.data(), p->rp.sigma, 8 * sig.size(), hipMemcpyDeviceToHost);
+            for (int k = 0; k < std::min(p->npairs, 8); k++)
+                std::fprintf(stderr, "[zk2] %s n=%d k=%d st=%d it=%d res=%.17e sig=%.17e %.17e\n", what, p->rp.n, k, p->pairs[k].status,
+                             p->pairs[k].iters, p->pairs[k].resid, sig[k], sig[(size_t)p->rp.n + k]);
+        }
     }
 
     void trace()

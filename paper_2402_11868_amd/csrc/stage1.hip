@@ -507,38 +507,57 @@ __global__ void k_transpose(ProbDesc *probs)
     if (k0 + ty < n && i0 + tx < n) P.Z[(size_t)(k0 + ty) * n + i0 + tx] = t[tx][ty];
 }
 
-// Modified Gram-Schmidt inside clusters of the binary64 spectrum, one wave
-// per eigenvalue index; only the wave of a cluster's first index works.
-// Cluster: consecutive eigenvalues closer than gap_rel * ||T||.
-__global__ void k_tri_orth(ProbDesc *probs, double gap_rel)
+// Gram-Schmidt inside clusters of the binary64 spectrum: one work-group (256)
+// per eigenvalue index; only the group of a cluster's first index works.
+// Cluster: consecutive eigenvalues closer than gap_rel * ||T||.  Member j is
+// orthogonalised against members k..j-1 by classical Gram-Schmidt, twice
+// (coefficients of all earlier members computed by the four waves in
+// parallel), then normalised.
+__global__ void __launch_bounds__(256) k_tri_orth(ProbDesc *probs, double gap_rel)
 {
     const ProbDesc &P = probs[blockIdx.y];
     const int n = P.n;
     const int k = blockIdx.x;
     if (k >= n) return;
-    const int lane = threadIdx.x;
-    double tn = fmax(fabs(P.w0[0]), fabs(P.w0[n - 1]));
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const double tn = fmax(fabs(P.w0[0]), fabs(P.w0[n - 1]));
     const double thr = gap_rel * fmax(tn, 1e-300);
     if (k > 0 && P.w0[k] - P.w0[k - 1] <= thr) return;   // not a cluster start
     int end = k + 1;
     while (end < n && P.w0[end] - P.w0[end - 1] <= thr) end++;
+    __shared__ double coef[1024];
+    __shared__ double red[4];
     for (int j = k; j < end; j++) {
         double *zj = P.Z + (size_t)j * n;
-        for (int pass = 0; pass < 2; pass++) {
-            for (int q = k; q < j; q++) {
-                const double *zq = P.Z + (size_t)q * n;
-                double s = 0.0;
-                for (int i = lane; i < n; i += 64) s += zq[i] * zj[i];
-                s = wave_sum(s);
-                for (int i = lane; i < n; i += 64) zj[i] -= s * zq[i];
+        for (int pass = 0; pass < 2 && j > k; pass++) {
+            for (int c0 = k; c0 < j; c0 += 1024) {
+                const int c1 = min(j, c0 + 1024);
+                for (int q = c0 + wid; q < c1; q += 4) {
+                    const double *zq = P.Z + (size_t)q * n;
+                    double s = 0.0;
+                    for (int i = lane; i < n; i += 64) s += zq[i] * zj[i];
+                    s = wave_sum(s);
+                    if (lane == 0) coef[q - c0] = s;
+                }
+                __syncthreads();
+                for (int i = tid; i < n; i += 256) {
+                    double x = zj[i];
+                    for (int q = c0; q < c1; q++) x -= coef[q - c0] * P.Z[(size_t)q * n + i];
+                    zj[i] = x;
+                }
+                __syncthreads();
             }
         }
         double s = 0.0;
-        for (int i = lane; i < n; i += 64) s += zj[i] * zj[i];
+        for (int i = tid; i < n; i += 256) s += zj[i] * zj[i];
         s = wave_sum(s);
+        if (lane == 0) red[wid] = s;
+        __syncthreads();
+        s = red[0] + red[1] + red[2] + red[3];
         const double inv = (s > 0.0) ? 1.0 / sqrt(s) : 0.0;
-        for (int i = lane; i < n; i += 64) zj[i] *= inv;
-        if (s == 0.0 && lane == 0) zj[j] = 1.0;
+        for (int i = tid; i < n; i += 256) zj[i] *= inv;
+        if (s == 0.0 && tid == 0) zj[j] = 1.0;
+        __syncthreads();
     }
 }
 
@@ -707,7 +726,7 @@ int stage1_run(const Stage1Batch &B, hipStream_t st)
     hipLaunchKernelGGL(k_bisect, dim3(cdiv(n, 128), np), dim3(128), 0, st, pd);
     hipLaunchKernelGGL(k_invit, dim3(cdiv(n, 64), np), dim3(64), 0, st, pd);
     hipLaunchKernelGGL(k_transpose, dim3(cdiv(n, 16), cdiv(n, 16), np), dim3(16, 16), 0, st, pd);
-    hipLaunchKernelGGL(k_tri_orth, dim3(n, np), dim3(64), 0, st, pd, B.tri_gap_rel);
+    hipLaunchKernelGGL(k_tri_orth, dim3(n, np), dim3(256), 0, st, pd, B.tri_gap_rel);
     if (B.timer) B.timer->end(idt, st);
     // ---- back-transformation
     const int idb = B.timer ? B.timer->begin(KC_BACKT, 8.0 * (double)n * n * n * np, st) : -1;
