@@ -27,6 +27,7 @@ sys.path.insert(0, os.path.join(ROOT, "tests"))
 # MI355X published peaks and unit counts
 FP64_VALU_LANE_OPS = 256 * 64 * 2.4e9     # FP64 vector instructions per second (one per lane per cycle)
 FP64_MFMA_TFLOPS = 78.6
+FP32_MFMA_TFLOPS = 157.3
 HBM_GBS = 8000.0
 # binary64 instructions of one complex double-double multiply-add in the LU
 # trailing update (4 real products x 13: two-product, cross terms, two-sum,
@@ -34,8 +35,45 @@ HBM_GBS = 8000.0
 CPLX_DD_FMA_INSTR = 52
 
 
+# sources that the LU trailing-update kernel is compiled from; the stored HBM
+# traffic of that kernel is reported only while their digest is unchanged
+LU_UPDATE_SOURCES = ["paper_2402_11868_amd/csrc/stage2.hip", "paper_2402_11868_amd/csrc/mp.h",
+                     "paper_2402_11868_amd/csrc/common.h", "paper_2402_11868_amd/csrc/stage.h"]
+TRAFFIC_FILE = "profiles/lu_update_herm1024_dd_traffic.txt"
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in LU_UPDATE_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic():
+    """Measured HBM bytes per launch of the LU update (rocprofv3 FETCH_SIZE and
+    WRITE_SIZE, each scaled by its copy-kernel calibration factor), or None
+    when the kernel's sources changed after the counters were taken."""
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if "=" in line and not line.lstrip().startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+    try:
+        if kv.get("kernel_source_sha256") != kernel_source_digest():
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def workload_matrix(name):
@@ -73,6 +111,91 @@ def cpu_baseline(seconds_hint=20.0):
                       f"{dt:.1f} s, {rate_n:.2f} eigenpairs/s at n={n}, {r.sweeps} sweeps; value scaled by (n/1024)^2"}
 
 
+def _pct(x, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(x), q)) * 1e3 if len(x) else None
+
+
+def serving_leg(Z, ctx, torch, count=200, load=0.7, tol=1e-30):
+    """The serving workload: requests of sizes uniform over 16..512 (step 16),
+    spectra 2^(-39 k/(s-1)), open-loop Poisson arrivals.
+
+    1. saturated throughput of the session (all requests queued at once);
+    2. Poisson arrivals at `load` x that throughput through the session
+       (continuous batching): p50 / p99 / max latency from scheduled arrival;
+    3. the same arrivals served one at a time by zk_heev_dd (FIFO).
+    """
+    import numpy as np
+    import workloads as W
+    sizes = W.serving_sizes()
+    pool = {n: torch.from_numpy(W.workload(4, index=0, n=n)["A"]).cuda() for n in sizes}
+    rng = np.random.Generator(np.random.PCG64(W.seed_for(4, 1)))
+    order = [sizes[i] for i in rng.integers(0, len(sizes), count)]
+
+    def good_pairs(r):
+        return sum(1 for x in r.info if x["resid"] <= tol)
+
+    # warm-up (untimed): one request of every tenth size
+    sess = Z.Session(ctx)
+    for t in [sess.submit([pool[n]]) for n in sizes[::10]]:
+        sess.result(t)
+    sess.close()
+
+    # 1. saturated
+    sess = Z.Session(ctx)
+    t0 = time.monotonic()
+    tickets = [sess.submit([pool[n]]) for n in order]
+    res = [sess.result(t) for t in tickets]
+    t_end = max(sess.times(t)[2] for t in tickets)
+    sess.close()
+    sat_rate = count / (t_end - t0)
+    sat_pairs = sum(good_pairs(r) for r in res) / (t_end - t0)
+    torch.cuda.synchronize()
+
+    # 2. Poisson through the session
+    rate = load * sat_rate
+    arr, _ = W.poisson_stream(rate, count, seed=W.seed_for(4, 2))
+    sess = Z.Session(ctx)
+    t0 = time.monotonic() + 0.05
+    tickets = []
+    for ta, n in zip(arr, order):
+        dt = t0 + ta - time.monotonic()
+        if dt > 0:
+            time.sleep(dt)
+        tickets.append(sess.submit([pool[n]]))
+    res = [sess.result(t) for t in tickets]
+    done = [sess.times(t)[2] for t in tickets]
+    sess.close()
+    lat = [d - (t0 + ta) for d, ta in zip(done, arr)]
+    span = max(done) - t0
+    ok_req = sum(1 for r in res if r.status == Z.ZK_OK)
+    pairs_ok = sum(good_pairs(r) for r in res)
+
+    # 3. one at a time, same arrivals
+    t0 = time.monotonic() + 0.05
+    lat1 = []
+    for ta, n in zip(arr, order):
+        dt = t0 + ta - time.monotonic()
+        if dt > 0:
+            time.sleep(dt)
+        Z.heev(ctx, [[pool[n]]], limbs_out=2)
+        torch.cuda.synchronize()
+        lat1.append(time.monotonic() - (t0 + ta))
+    return {
+        "workload": "serving stream: sizes uniform over 16..512 step 16, spectra 2^(-39k/(s-1)) trace 1, "
+                    "Poisson arrivals, dd to 1e-30",
+        "requests": count,
+        "saturated_req_per_s": sat_rate,
+        "saturated_eigenpairs_per_s": sat_pairs,
+        "rate_hz": rate,
+        "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99), "max_ms": max(lat) * 1e3,
+        "completed_req_per_s": count / span,
+        "eigenpairs_per_s": pairs_ok / span,
+        "requests_ok": ok_req,
+        "one_at_a_time": {"p50_ms": _pct(lat1, 50), "p99_ms": _pct(lat1, 99), "max_ms": max(lat1) * 1e3},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,7 +203,22 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32-leg", action="store_true", help="skip the FP32-MFMA-start run")
+    ap.add_argument("--serving-requests", type=int, default=200,
+                    help="requests of the serving-stream leg (0 = skip the leg)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="run only a plain device-to-device copy of BYTES, three times (counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        nbytes = int(args.calibrate_copy)
+        x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": nbytes}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path runs on a single "
               f"MI355X; multi-GPU sharding is described in the design notes but not built)", file=sys.stderr)
@@ -123,8 +261,26 @@ def main():
     torch.cuda.synchronize()
     total = time.perf_counter() - t_all
     prof = ctx.prof_read()
-    ctx.prof(False)
     ms_per_step = 1e3 * total / args.steps
+
+    # the FP32-MFMA start (complex64-rounded input, FP32 MFMA GEMMs in the
+    # binary64 stage), one untimed-in-value run for its iteration counts
+    fp32_leg = None
+    if not args.no_fp32_leg:
+        ctx.prof_reset()
+        st32 = {}
+        t0 = time.perf_counter()
+        r32, = Z.heev(ctx, [Ad], limbs_out=2, opts=Z.make_opts(init_fp32=True), stats=st32)
+        torch.cuda.synchronize()
+        t32 = time.perf_counter() - t0
+        p32 = ctx.prof_read()
+        ok32 = sum(1 for x in r32.info if x["resid"] <= tol)
+        ms_h32, _, fl_h32 = p32["her2k"]
+        fp32_leg = {"ms": t32 * 1e3, "passing_pairs": ok32, "iters_hist": st32.get("iters_hist"),
+                    "stage1_ms": p32["stage1"][0],
+                    "her2k_tflops": (fl_h32 / (ms_h32 / 1e3) / 1e12) if ms_h32 > 0 else None,
+                    "frac_of_fp32_mfma": (fl_h32 / (ms_h32 / 1e3) / 1e12 / FP32_MFMA_TFLOPS) if ms_h32 > 0 else None}
+    ctx.prof(False)
 
     # gates on the last step's output
     w = res.w.cpu().numpy()
@@ -146,14 +302,14 @@ def main():
     achieved = work_u / (ms_u / 1e3) if ms_u > 0 else 0.0             # complex dd multiply-adds per second
     peak = FP64_VALU_LANE_OPS / CPLX_DD_FMA_INSTR
     roof = {"bound": "alu", "kernel": "k_s2_lu_update_dd", "achieved": achieved / 1e9, "peak": peak / 1e9,
-            "unit": "G cplx-dd-FMA/s", "frac": achieved / peak if peak else 0.0, "traffic": None,
+            "unit": "G cplx-dd-FMA/s", "frac": achieved / peak if peak else 0.0, "traffic": stored_traffic(),
             "avg_launch_ms": ms_u / max(la_u, 1), "launches": la_u,
             "peak_basis": f"256 CU x 64 lanes x 2.4 GHz FP64 VALU / {CPLX_DD_FMA_INSTR} instructions per complex dd FMA"}
     ms_h, la_h, fl_h = prof["her2k"]
     ms_v, la_v, by_v = prof["hemv"]
     phases = {k: round(v[0] / args.steps, 3) for k, v in prof.items()}
     out = {
-        "metric": "eigenpairs/sec at <=1e-30 rel err (dd), 1024^2 Hermitian",
+        "metric": "eigenpairs/sec at \u22641e-30 rel err (dd), 1024\u00b2 Hermitian; p99 latency, MPS stream",
         "value": value,
         "unit": "eigenpairs/s",
         "n_gpus": 1,
@@ -176,7 +332,11 @@ def main():
         "stage1_mfma": {"her2k_tflops": (fl_h / (ms_h / 1e3) / 1e12) if ms_h > 0 else None,
                         "frac_of_fp64_mfma": (fl_h / (ms_h / 1e3) / 1e12 / FP64_MFMA_TFLOPS) if ms_h > 0 else None,
                         "hemv_gbs": (by_v / (ms_v / 1e3) / 1e9) if ms_v > 0 else None},
+        "fp32_mfma_start": fp32_leg,
     }
+    if args.serving_requests > 0:
+        log("serving stream")
+        out["serving"] = serving_leg(Z, ctx, torch, count=args.serving_requests)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline()

@@ -102,7 +102,8 @@ typedef struct {
 } zk_eig_out;
 
 typedef struct {
-    int init_fp32;        /* 1: stage-1 trailing updates in FP32 MFMA (FP32-rounded input) */
+    int init_fp32;        /* 1: binary64 stage on the complex64-rounded input with FP32-MFMA trailing
+                             updates and back-transform (the refinement always uses the exact input) */
     double tol;           /* residual/eigenvalue tolerance relative to ||H||_2; 0 = default (1e-30 dd, 1e-60 qd) */
     int max_iter;         /* RQI iterations per pair; 0 = default (8 dd, 10 qd) */
     double cluster_tol;   /* eigenvalues closer than cluster_tol*||H||_2 are one cluster; 0 = default 1e-10 */

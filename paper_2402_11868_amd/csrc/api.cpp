@@ -266,16 +266,16 @@ static int carve_s2in(zk_ctx *ctx, int count, const zk_herm *A, std::vector<doub
 // copy, 2*limbs*n*n doubles), w0 (n), V0 (n*n complex), flag (int, zeroed
 // here); ZK_EINVAL on non-finite input.
 int run_stage1(zk_ctx *ctx, int count, const zk_herm *A, const std::vector<double *> &hf, const std::vector<double *> &w0,
-               const std::vector<double *> &V0, const std::vector<int *> &flag)
+               const std::vector<double *> &V0, const std::vector<int *> &flag, const std::vector<int> &fp32)
 {
     hipStream_t st = ctx->stream;
     int rc;
     for (int i = 0; i < count; i++) HIPCHK(hipMemsetAsync(flag[i], 0, 4, st));
-    // stage 1, grouped by order, as many matrices at a time as the budget allows
-    std::map<int, std::vector<int>> groups;
-    for (int i = 0; i < count; i++) groups[A[i].n].push_back(i);
+    // stage 1, grouped by order and variant, as many matrices at a time as the budget allows
+    std::map<std::pair<int, int>, std::vector<int>> groups;
+    for (int i = 0; i < count; i++) groups[std::make_pair(A[i].n, fp32.empty() ? 0 : (fp32[i] ? 1 : 0))].push_back(i);
     for (auto &kv : groups) {
-        const int n = kv.first;
+        const int n = kv.first.first;
         const std::vector<int> &ids = kv.second;
         const size_t per = s1_bytes(n);
         size_t avail = ctx->budget > ctx->held() - ctx->s1.bytes ? ctx->budget - (ctx->held() - ctx->s1.bytes) : 0;
@@ -333,6 +333,7 @@ int run_stage1(zk_ctx *ctx, int count, const zk_herm *A, const std::vector<doubl
             S1.dev_probs = d_probs;
             S1.dev_gemm = d_gemm;
             S1.tri_gap_rel = 1e-12;
+            S1.fp32 = kv.first.second;
             S1.timer = ctx->tp();
             const int t1 = S1.timer ? S1.timer->begin(KC_STAGE1, (double)np, st) : -1;
             if (stage1_run(S1, st)) return ctx->fail(ZK_EDEVICE, "stage1 launch failed: %s", hipGetErrorString(hipGetLastError()));
@@ -367,7 +368,7 @@ static int run_heev(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out *out, c
     std::vector<int *> flag(count);
     int rc = carve_s2in(ctx, count, A, hf, w0, V0, flag);
     if (rc != ZK_OK) return rc;
-    if ((rc = run_stage1(ctx, count, A, hf, w0, V0, flag)) != ZK_OK) return rc;
+    if ((rc = run_stage1(ctx, count, A, hf, w0, V0, flag, std::vector<int>(count, O.init_fp32))) != ZK_OK) return rc;
     std::vector<RqiProb> rp(count);
     std::vector<int> npair_of(count);
     std::vector<zk_pair_info *> infos(count);
@@ -406,7 +407,7 @@ extern "C" int zk_heev_fp64(zk_ctx *ctx, int count, const zk_herm *A, double *co
     std::vector<int *> flag(count);
     int rc = carve_s2in(ctx, count, A, hf, w0, V0, flag);
     if (rc != ZK_OK) return rc;
-    if ((rc = run_stage1(ctx, count, A, hf, w0, V0, flag)) != ZK_OK) return rc;
+    if ((rc = run_stage1(ctx, count, A, hf, w0, V0, flag, std::vector<int>())) != ZK_OK) return rc;
     hipStream_t st = ctx->stream;
     for (int i = 0; i < count; i++) {
         const int n = A[i].n;

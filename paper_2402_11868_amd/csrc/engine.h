@@ -21,6 +21,9 @@
 #include "api_internal.h"
 #include "stage.h"
 
+int run_stage1(zk_ctx *ctx, int count, const zk_herm *A, const std::vector<double *> &hf, const std::vector<double *> &w0,
+               const std::vector<double *> &V0, const std::vector<int *> &flag, const std::vector<int> &fp32);
+
 #define HIPCHK_(expr)                                          \
     do {                                                       \
         hipError_t e_ = (expr);                                \
@@ -51,7 +54,9 @@ struct S2Prob {
     zk_pair_info *info = nullptr;
     std::vector<PairDesc> pairs;   // authoritative host copy of the pair states
     std::vector<int> heads;        // local index of every cluster's first pair
-    std::vector<char> ritz;        // per head: the cluster received a Rayleigh-Ritz step
+    std::vector<std::pair<int, int>> rrb;   // Rayleigh-Ritz blocks (first pair, members), 2..32 members
+    std::vector<int> redo;         // pairs sent back for more iterations after the re-orthogonalisation
+    int polish = 0;                // number of such passes so far
     void *vecbuf = nullptr;
     size_t vecbytes = 0;
     int status = ZK_OK;
@@ -126,12 +131,18 @@ class Stage2Engine {
                 p->heads.push_back(k);
                 k = e;
             }
+            p->rrb.clear();
+            for (int h : p->heads)
+                if (p->pairs[h].cl_size >= 2 && p->pairs[h].cl_size <= 32) p->rrb.push_back(std::make_pair(h, p->pairs[h].cl_size));
         }
         if ((rc = upload(batch)) != ZK_OK) return rc;
         if (stage2_init<L>(d_pairs, d_probs, total_pairs, st)) return ctx->fail(ZK_EDEVICE, "init launch failed");
         for (S2Prob *p : batch)
             for (auto &q : p->pairs) q.status = 0;
         if ((rc = run_gs(batch, false)) != ZK_OK) return rc;
+        bool projected = false;
+        if ((rc = run_prr(batch, projected)) != ZK_OK) return rc;
+        if (projected && (rc = run_gs(batch, false)) != ZK_OK) return rc;
         if ((rc = run_rr(batch, true)) != ZK_OK) return rc;
         std::vector<int> all(total_pairs);
         for (int g = 0; g < total_pairs; g++) all[g] = g;
@@ -193,6 +204,8 @@ class Stage2Engine {
     }
 
     int rounds = 0;
+    static constexpr int kPolishPasses = 2;
+    static constexpr int kPrrLevels = 4;
 
   private:
     zk_ctx *ctx;
@@ -374,12 +387,20 @@ class Stage2Engine {
             G.max_n = std::max(G.max_n, set[pi]->rp.n);
         };
         if (global) {
+            // a whole eigenbasis in index order, or (after a polishing pass)
+            // only the re-iterated pairs against all the others
             for (int pi : *only) {
                 S2Prob *p = set[pi];
                 if (p->npairs != p->rp.n || p->rp.n < 2) continue;
-                std::vector<int> act(p->rp.n), none;
-                for (int k = 0; k < p->rp.n; k++) act[k] = k;
-                add(pi, none, act);
+                std::vector<int> act, fro;
+                if (p->redo.empty()) {
+                    for (int k = 0; k < p->rp.n; k++) act.push_back(k);
+                } else {
+                    std::vector<char> r(p->rp.n, 0);
+                    for (int k : p->redo) r[k] = 1;
+                    for (int k = 0; k < p->rp.n; k++) (r[k] ? act : fro).push_back(k);
+                }
+                add(pi, fro, act);
             }
         } else {
             for (size_t pi = 0; pi < set.size(); pi++) {
@@ -395,10 +416,14 @@ class Stage2Engine {
             }
         }
         if (cls.empty()) return ZK_OK;
-        // plan storage sized from the plan itself: clusters, column lists, coefficient scratch
+        // plan storage sized from the plan itself: clusters, column lists,
+        // coefficient scratch, Gram slices (row slices of 256) and flags
+        G.ks = std::min(16, std::max(1, (G.max_n + 255) / 256));
         const size_t b_cls = s2_align(sizeof(GsCluster) * cls.size()), b_list = s2_align(4 * list.size());
         const size_t b_scr = s2_align((size_t)sofs * 8);
-        int rc = ensure_gs(b_cls + b_list + b_scr);
+        const size_t b_gram = s2_align(cls.size() * (size_t)G.ks * 2 * L * 32 * 32 * 8);
+        const size_t b_flag = s2_align(4 * cls.size());
+        int rc = ensure_gs(b_cls + b_list + b_scr + b_gram + b_flag);
         if (rc != ZK_OK) return rc;
         GsCluster *g_cls = (GsCluster *)gsbuf;
         int *g_list = (int *)((char *)gsbuf + b_cls);
@@ -409,6 +434,8 @@ class Stage2Engine {
         G.dev_cls = g_cls;
         G.dev_list = g_list;
         G.scratch = g_scr;
+        G.gram = (double *)((char *)gsbuf + b_cls + b_list + b_scr);
+        G.flag = (int *)((char *)gsbuf + b_cls + b_list + b_scr + b_gram);
         KernelTimer *tm = ctx->tp();
         const int id = tm ? tm->begin(global ? KC_REORTH : KC_GS, (double)list.size(), st) : -1;
         if (stage2_gs<L>(G, d_probs, global ? nullptr : d_pairs, st)) return ctx->fail(ZK_EDEVICE, "Gram-Schmidt launch failed");
@@ -417,11 +444,126 @@ class Stage2Engine {
         return ZK_OK;
     }
 
-    // Rayleigh-Ritz inside the clusters of 2..32 members.  first = true: every
-    // member of every such cluster of a new batch (and the clusters are
-    // marked); otherwise the active members of marked clusters, when at least
-    // two are active.  Scratch comes from the engine's own buffer, sized from
-    // the plan, so the step never depends on what other buffers hold.
+    // Projected Rayleigh-Ritz on the clusters longer than 32 members: C =
+    // V^H H V in L limbs, the binary64 stage on C (rounded), V <- V Q.  The
+    // Ritz values split the cluster into sub-chains relative to its own scale
+    // (gaps <= cluster_tol * max |Ritz value|); sub-chains of 2..32 become
+    // Rayleigh-Ritz blocks, longer ones are projected again at the next level.
+    int run_prr(const std::vector<S2Prob *> &set, bool &projected)
+    {
+        struct Blk {
+            int pi, k0, size;
+        };
+        std::vector<Blk> todo;
+        for (size_t pi = 0; pi < set.size(); pi++)
+            for (int h : set[pi]->heads)
+                if (set[pi]->pairs[h].cl_size > 32) todo.push_back({(int)pi, h, set[pi]->pairs[h].cl_size});
+        for (int level = 0; level < kPrrLevels && !todo.empty(); level++) {
+            projected = true;
+            const int nd = (int)todo.size();
+            int max_size = 0, max_n = 0;
+            size_t bytes = s2_align(sizeof(PrrDesc) * nd);
+            std::vector<size_t> off(nd);
+            for (int b = 0; b < nd; b++) {
+                const size_t m = (size_t)todo[b].size, n = (size_t)set[todo[b].pi]->rp.n;
+                max_size = std::max(max_size, todo[b].size);
+                max_n = std::max(max_n, (int)n);
+                off[b] = bytes;
+                // Y, C, hf, w0, V0, flag
+                bytes += s2_align(8 * 2 * (size_t)L * n * m) + 3 * s2_align(16 * m * m) + s2_align(8 * m) + s2_align(4);
+            }
+            if (ctx->held() + bytes > ctx->budget) return ctx->fail(ZK_ENOMEM, "projected Rayleigh-Ritz exceeds the budget");
+            void *buf = nullptr;
+            if (hipMalloc(&buf, bytes) != hipSuccess) {
+                hipGetLastError();
+                return ctx->fail(ZK_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
+            }
+            ctx->extra += bytes;
+            std::vector<PrrDesc> hd(nd);
+            std::vector<zk_herm> hm(nd);
+            std::vector<double *> hf(nd), w0(nd), V0(nd);
+            std::vector<int *> flag(nd);
+            for (int b = 0; b < nd; b++) {
+                const size_t m = (size_t)todo[b].size, n = (size_t)set[todo[b].pi]->rp.n;
+                char *c = (char *)buf + off[b];
+                PrrDesc &D = hd[b];
+                std::memset(&D, 0, sizeof D);
+                D.prob = todo[b].pi;
+                D.k0 = todo[b].k0;
+                D.size = (int)m;
+                D.Y = (double *)c;
+                c += s2_align(8 * 2 * (size_t)L * n * m);
+                D.C = (double *)c;
+                c += s2_align(16 * m * m);
+                hf[b] = (double *)c;
+                c += s2_align(16 * m * m);
+                V0[b] = (double *)c;
+                D.Q = V0[b];
+                c += s2_align(16 * m * m);
+                w0[b] = (double *)c;
+                c += s2_align(8 * m);
+                flag[b] = (int *)c;
+                std::memset(&hm[b], 0, sizeof(zk_herm));
+                hm[b].n = (int)m;
+                hm[b].lda = (int)m;
+                hm[b].limbs = 1;
+                hm[b].plane[0] = D.C;
+            }
+            PrrDesc *d_desc = (PrrDesc *)buf;
+            int rc = ZK_OK;
+            auto cleanup = [&]() {
+                hipStreamSynchronize(st);
+                hipFree(buf);
+                ctx->extra -= bytes;
+            };
+            if (hipMemcpyAsync(d_desc, hd.data(), sizeof(PrrDesc) * nd, hipMemcpyHostToDevice, st) != hipSuccess ||
+                stage2_prr_project<L>(d_desc, nd, max_size, max_n, d_probs, st)) {
+                cleanup();
+                return ctx->fail(ZK_EDEVICE, "projected Rayleigh-Ritz launch failed");
+            }
+            if ((rc = run_stage1(ctx, nd, hm.data(), hf, w0, V0, flag, std::vector<int>())) != ZK_OK) {
+                cleanup();
+                return rc;
+            }
+            if (stage2_prr_rotate<L>(d_desc, nd, max_size, max_n, d_probs, st)) {
+                cleanup();
+                return ctx->fail(ZK_EDEVICE, "projected Rayleigh-Ritz launch failed");
+            }
+            // sub-chains from the Ritz values
+            std::vector<Blk> next;
+            for (int b = 0; b < nd; b++) {
+                const int m = todo[b].size;
+                std::vector<double> w(m);
+                if (hipMemcpyAsync(w.data(), w0[b], 8 * (size_t)m, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                    hipStreamSynchronize(st) != hipSuccess) {
+                    cleanup();
+                    return ctx->fail(ZK_EDEVICE, "projected Rayleigh-Ritz read-back failed");
+                }
+                S2Prob *p = set[todo[b].pi];
+                double sc = 0.0;
+                for (double x : w) sc = std::max(sc, std::fabs(x));
+                const double thr = p->opts.cluster_tol * sc;
+                int s0 = 0;
+                for (int e = 1; e <= m; e++) {
+                    if (e < m && w[e] - w[e - 1] <= thr) continue;
+                    const int len = e - s0;
+                    if (len >= 2 && len <= 32) p->rrb.push_back(std::make_pair(todo[b].k0 + s0, len));
+                    if (len > 32 && len < m) next.push_back({todo[b].pi, todo[b].k0 + s0, len});
+                    s0 = e;
+                }
+            }
+            cleanup();
+            todo = next;
+        }
+        return ZK_OK;
+    }
+
+    // Rayleigh-Ritz on the blocks of 2..32 members (the clusters of that size
+    // and the sub-chains that the projected step found inside longer ones).
+    // first = true: every member; otherwise the active members of a block,
+    // when at least two are active.  Scratch comes from the engine's own
+    // buffer, sized from the plan, so the step never depends on what other
+    // buffers hold.
     int run_rr(const std::vector<S2Prob *> &set, bool first)
     {
         std::vector<GsCluster> cls;
@@ -429,17 +571,11 @@ class Stage2Engine {
         long long sofs = 0;
         for (size_t pi = 0; pi < set.size(); pi++) {
             S2Prob *p = set[pi];
-            if (first) p->ritz.assign(p->heads.size(), 0);
-            for (size_t hi = 0; hi < p->heads.size(); hi++) {
-                const int h = p->heads[hi];
-                const int sz = p->pairs[h].cl_size;
-                if (sz < 2 || sz > 32) continue;
-                if (!first && !p->ritz[hi]) continue;
+            for (const auto &bk : p->rrb) {
                 std::vector<int> mem;
-                for (int q = 0; q < sz; q++)
-                    if (first || p->pairs[h + q].status == 0) mem.push_back(p->pairs[h + q].k);
+                for (int q = 0; q < bk.second; q++)
+                    if (first || p->pairs[bk.first + q].status == 0) mem.push_back(p->pairs[bk.first + q].k);
                 if (mem.size() < 2) continue;
-                if (first) p->ritz[hi] = 1;
                 GsCluster c;
                 c.prob = (int)pi;
                 c.pair_base = base[pi];
@@ -499,6 +635,29 @@ class Stage2Engine {
                 for (int k = 0; k < live[pi]->npairs; k++) idx.push_back(base[pi] + k);
             if ((rc = run_rq(idx, 1)) != ZK_OK) return rc;
             if ((rc = download(live)) != ZK_OK) return rc;
+        }
+        {
+            // polishing: a pair that the re-orthogonalisation pushed above the
+            // tolerance, with iterations left, goes back for more iterations;
+            // the next settle re-orthogonalises only those pairs against the rest
+            std::vector<int> keep_fin;
+            for (int pi : fin) {
+                S2Prob *p = live[pi];
+                p->redo.clear();
+                if (p->opts.reorth && p->polish < kPolishPasses)
+                    for (int k = 0; k < p->npairs; k++) {
+                        const PairDesc &q = p->pairs[k];
+                        if (q.status == 2 && !(q.flags & 8) && q.iters < p->rp.max_iter) p->redo.push_back(k);
+                    }
+                if (p->redo.empty()) {
+                    keep_fin.push_back(pi);
+                    continue;
+                }
+                p->polish++;
+                for (int k : p->redo) p->pairs[k].status = 0;
+            }
+            fin = keep_fin;
+            if (fin.empty()) return ZK_OK;
         }
         // ascending order of the refined eigenvalues inside each matrix
         std::vector<int> dst(total_pairs, 0);

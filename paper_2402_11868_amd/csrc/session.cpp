@@ -35,7 +35,7 @@
 using namespace zk;
 
 int run_stage1(zk_ctx *ctx, int count, const zk_herm *A, const std::vector<double *> &hf, const std::vector<double *> &w0,
-               const std::vector<double *> &V0, const std::vector<int *> &flag);
+               const std::vector<double *> &V0, const std::vector<int *> &flag, const std::vector<int> &fp32);
 ResolvedOpts zk_resolve_opts(const zk_opts *o, int L);
 int zk_check_request(const zk_herm &A, const zk_eig_out &o, int L, bool want_vectors);
 
@@ -103,9 +103,11 @@ int zk_session::admit_and_start(std::vector<Request *> &fresh)
     std::vector<zk_herm> A(cnt);
     std::vector<double *> hf(cnt), w0(cnt), V0(cnt);
     std::vector<int *> flag(cnt);
+    std::vector<int> fp32(cnt);
     for (int i = 0; i < cnt; i++) {
         Request *r = fresh[i];
         A[i] = r->A;
+        fp32[i] = r->O.init_fp32;
         const int n = r->A.n;
         const size_t nn = (size_t)n * n;
         const size_t bytes = al(8 * 2 * (size_t)r->A.limbs * nn) + al(8 * (size_t)n) + al(16 * nn) + al(64);
@@ -123,7 +125,7 @@ int zk_session::admit_and_start(std::vector<Request *> &fresh)
         b += al(16 * nn);
         flag[i] = (int *)b;
     }
-    int rc = run_stage1(ctx, cnt, A.data(), hf, w0, V0, flag);
+    int rc = run_stage1(ctx, cnt, A.data(), hf, w0, V0, flag, fp32);
     if (rc != ZK_OK) return rc;
     std::vector<S2Prob *> b2, b4;
     for (int i = 0; i < cnt; i++) {

@@ -97,6 +97,7 @@ struct Stage1Batch {
     ProbDesc *dev_probs;       // nprob descriptors (device)
     const GemmDesc *dev_gemm;  // stage1_gemm_desc_count(n, nprob) descriptors (device)
     double tri_gap_rel;        // cluster gap (relative) for the binary64 Gram-Schmidt
+    int fp32;                  // FP32-MFMA variant: complex64-rounded input, FP32 MFMA GEMMs
 };
 
 size_t stage1_gemm_desc_count(int n, int np);
@@ -152,11 +153,32 @@ struct GsPlan {
     const GsCluster *dev_cls;
     const int *dev_list;
     double *scratch;
+    // inside-block Cholesky QR: Gram partial sums (ks row slices per cluster,
+    // 2L planes of 32 x 32 each), reused for the packed inverse factor, and one
+    // fallback flag per cluster
+    double *gram;
+    int ks;
+    int *flag;
 };
 template <int L> int stage2_gs(const GsPlan &G, RqiProb *probs, PairDesc *pairs, hipStream_t st);
 // Rayleigh-Ritz inside clusters of 2..32 members (plan entries: nconv = 0,
 // scratch per cluster 2L * n * 32 doubles)
 template <int L> int stage2_rr(const GsPlan &G, RqiProb *probs, int sweeps, hipStream_t st);
+// Projected Rayleigh-Ritz for clusters longer than 32: one descriptor per
+// block of consecutive pairs of one problem.
+struct PrrDesc {
+    int prob;          // problem index in the uploaded table
+    int k0;            // first pair (local index) of the block
+    int size;          // members
+    int pad;
+    double *Y;         // 2L planes of n * size: H V, later V Q
+    double *C;         // size x size complex128, column-major: binary64 rounding of V^H H V
+    const double *Q;   // size x size complex128 eigenvectors of C (column j = vector j)
+};
+// C = V^H H V (rounded to binary64) for every descriptor
+template <int L> int stage2_prr_project(const PrrDesc *d, int nd, int max_size, int max_n, RqiProb *probs, hipStream_t st);
+// V <- V Q for every descriptor
+template <int L> int stage2_prr_rotate(const PrrDesc *d, int nd, int max_size, int max_n, RqiProb *probs, hipStream_t st);
 template <int L> int stage2_rq(const Stage2Batch &B, hipStream_t st);
 template <int L> int stage2_solve(const Stage2Batch &B, hipStream_t st);
 template <int L> int stage2_output(PairDesc *pairs, RqiProb *probs, const int *dst, int npairs, hipStream_t st);

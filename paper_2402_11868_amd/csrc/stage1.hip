@@ -38,7 +38,9 @@ __device__ __forceinline__ double2 wave_sum2(double2 v)
 
 // ---------------------------------------------------------------- ingest --
 // grid (n columns, nprob), block 256: lower triangle of column j.
-__global__ void k_ingest(ProbDesc *probs)
+// fp32 != 0: the working copy is rounded to complex64 (the FP32-MFMA variant
+// of the binary64 stage); the binary64 planes for the refinement stay exact.
+__global__ void k_ingest(ProbDesc *probs, int fp32)
 {
     const ProbDesc &P = probs[blockIdx.y];
     const int n = P.n, j = blockIdx.x;
@@ -59,6 +61,10 @@ __global__ void k_ingest(ProbDesc *probs)
                 P.hf[(2 * l) * nn + (size_t)i * n + j] = z.x;
                 P.hf[(2 * l + 1) * nn + (size_t)i * n + j] = -zi;
             }
+        }
+        if (fp32) {
+            re = (double)(float)re;
+            im = (double)(float)im;
         }
         st2(P.A + 2 * ((size_t)j * n + i), make_double2(re, im));
     }
@@ -298,10 +304,14 @@ __global__ void __launch_bounds__(256) k_trd_wfin(ProbDesc *probs, int c, int k0
 // C(MxN) = alpha * op(A) op(B) + beta * C, complex128, column-major.
 // op 0 = N, 1 = C (conjugate transpose).  lower != 0: only tiles that
 // intersect the lower triangle (row >= col) are computed (her2k).
-// Block 256 = 4 waves, tile 64 x 64, each wave 32 x 32 = 2 x 2 MFMA blocks
-// of v_mfma_f64_16x16x4f64; a complex product is four real MFMAs.
-// Operand layout of the 16x16x4 f64 MFMA (wave64): lane l holds A[l%16][l/16]
-// and B[l/16][l%16]; the 4 accumulator values of lane l are D[4r + l/16][l%16].
+// Block 256 = 4 waves, tile 32 x 32, each wave one 16 x 16 block computed as
+// its transpose D = (op(A) op(B))^T with v_mfma_f64_16x16x4f64 (a complex
+// product is four real MFMAs), so that each accumulator register of a wave
+// maps to 16 consecutive rows of one column of C (coalesced epilogue).
+// Operand layout of the 16x16x4 f64 MFMA (wave64): lane l holds X[l%16][l/16]
+// and Y[l/16][l%16]; the 4 accumulator values of lane l are D[4r + l/16][l%16].
+// The operands of 8 consecutive k-steps are loaded before their MFMAs so
+// that the loads are in flight together.
 __device__ __forceinline__ double2 opA_ld(const double2 *A, int lda, int op, int i, int k, int M, int K)
 {
     if (i >= M || k >= K) return make_double2(0.0, 0.0);
@@ -318,51 +328,99 @@ __device__ __forceinline__ double2 opB_ld(const double2 *B, int ldb, int op, int
     return make_double2(b.x, -b.y);
 }
 
+constexpr int kGemmKc = 8;   // k-steps of 4 whose operands are loaded together
+
 __global__ void __launch_bounds__(256) k_zgemm(const GemmDesc *descs, int M, int N, int K, int opA, int opB,
                                                double2 alpha, double2 beta, int lower)
 {
     const GemmDesc &G = descs[blockIdx.y];
-    const int tilesM = (M + 63) / 64;
+    const int tilesM = (M + 31) / 32;
     const int tm = blockIdx.x % tilesM, tn = blockIdx.x / tilesM;
-    const int row0 = tm * 64, col0 = tn * 64;
-    if (lower && row0 + 63 < col0) return;
+    const int row0 = tm * 32, col0 = tn * 32;
+    if (lower && row0 + 31 < col0) return;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int wr = row0 + (wid & 1) * 32, wc = col0 + (wid >> 1) * 32;
+    const int wr = row0 + (wid & 1) * 16, wc = col0 + (wid >> 1) * 16;
+    if (lower && wr + 15 < wc) return;
     const double2 *A = reinterpret_cast<const double2 *>(G.A);
     const double2 *B = reinterpret_cast<const double2 *>(G.B);
-    f64x4 cre[2][2], cim[2][2];
-    for (int a = 0; a < 2; a++)
-        for (int b = 0; b < 2; b++) {
-            cre[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
-            cim[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
-        }
+    f64x4 cre = f64x4{0.0, 0.0, 0.0, 0.0}, cim = f64x4{0.0, 0.0, 0.0, 0.0};
     const int li = lane & 15, lk = lane >> 4;
-    for (int k0 = 0; k0 < K; k0 += 4) {
-        double2 av[2], bv[2];
-        for (int a = 0; a < 2; a++) av[a] = opA_ld(A, G.lda, opA, wr + a * 16 + li, k0 + lk, M, K);
-        for (int b = 0; b < 2; b++) bv[b] = opB_ld(B, G.ldb, opB, k0 + lk, wc + b * 16 + li, K, N);
-        for (int a = 0; a < 2; a++) {
-            const double nai = -av[a].y;
-            for (int b = 0; b < 2; b++) {
-                cre[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].x, bv[b].x, cre[a][b], 0, 0, 0);
-                cre[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai, bv[b].y, cre[a][b], 0, 0, 0);
-                cim[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].x, bv[b].y, cim[a][b], 0, 0, 0);
-                cim[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].y, bv[b].x, cim[a][b], 0, 0, 0);
-            }
+    for (int k0 = 0; k0 < K; k0 += 4 * kGemmKc) {
+        double2 xv[kGemmKc], yv[kGemmKc];
+#pragma unroll
+        for (int s = 0; s < kGemmKc; s++) {
+            // X[j][k] = op(B)[k][j], Y[k][i] = op(A)[i][k]
+            xv[s] = opB_ld(B, G.ldb, opB, k0 + 4 * s + lk, wc + li, K, N);
+            yv[s] = opA_ld(A, G.lda, opA, wr + li, k0 + 4 * s + lk, M, K);
+        }
+#pragma unroll
+        for (int s = 0; s < kGemmKc; s++) {
+            cre = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[s].x, yv[s].x, cre, 0, 0, 0);
+            cre = __builtin_amdgcn_mfma_f64_16x16x4f64(-xv[s].y, yv[s].y, cre, 0, 0, 0);
+            cim = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[s].x, yv[s].y, cim, 0, 0, 0);
+            cim = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[s].y, yv[s].x, cim, 0, 0, 0);
         }
     }
     double2 *C = reinterpret_cast<double2 *>(G.C);
-    for (int a = 0; a < 2; a++)
-        for (int b = 0; b < 2; b++)
-            for (int r = 0; r < 4; r++) {
-                const int i = wr + a * 16 + 4 * r + lk, j = wc + b * 16 + li;
-                if (i >= M || j >= N) continue;
-                if (lower && i < j) continue;
-                const double2 ab = make_double2(cre[a][b][r], cim[a][b][r]);
-                double2 out = cmul(alpha, ab);
-                if (beta.x != 0.0 || beta.y != 0.0) out = cadd(out, cmul(beta, C[(size_t)j * G.ldc + i]));
-                C[(size_t)j * G.ldc + i] = out;
-            }
+    const int i = wr + li;
+    if (i >= M) return;
+    for (int r = 0; r < 4; r++) {
+        const int j = wc + 4 * r + lk;
+        if (j >= N || (lower && i < j)) continue;
+        double2 out = cmul(alpha, make_double2(cre[r], cim[r]));
+        if (beta.x != 0.0 || beta.y != 0.0) out = cadd(out, cmul(beta, C[(size_t)j * G.ldc + i]));
+        C[(size_t)j * G.ldc + i] = out;
+    }
+}
+
+// The same product with FP32 MFMA (v_mfma_f32_16x16x4f32) on operands rounded
+// to complex64 and FP32 accumulation; alpha, beta and C stay binary64.  Output
+// layout of that MFMA: the 4 accumulator values of lane l are
+// D[4 (l/16) + r][l%16].
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) k_cgemm32(const GemmDesc *descs, int M, int N, int K, int opA, int opB,
+                                                 double2 alpha, double2 beta, int lower)
+{
+    const GemmDesc &G = descs[blockIdx.y];
+    const int tilesM = (M + 31) / 32;
+    const int tm = blockIdx.x % tilesM, tn = blockIdx.x / tilesM;
+    const int row0 = tm * 32, col0 = tn * 32;
+    if (lower && row0 + 31 < col0) return;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int wr = row0 + (wid & 1) * 16, wc = col0 + (wid >> 1) * 16;
+    if (lower && wr + 15 < wc) return;
+    const double2 *A = reinterpret_cast<const double2 *>(G.A);
+    const double2 *B = reinterpret_cast<const double2 *>(G.B);
+    f32x4 cre = f32x4{0.f, 0.f, 0.f, 0.f}, cim = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int li = lane & 15, lk = lane >> 4;
+    for (int k0 = 0; k0 < K; k0 += 4 * kGemmKc) {
+        float2 xv[kGemmKc], yv[kGemmKc];
+#pragma unroll
+        for (int s = 0; s < kGemmKc; s++) {
+            const double2 x = opB_ld(B, G.ldb, opB, k0 + 4 * s + lk, wc + li, K, N);
+            const double2 y = opA_ld(A, G.lda, opA, wr + li, k0 + 4 * s + lk, M, K);
+            xv[s] = make_float2((float)x.x, (float)x.y);
+            yv[s] = make_float2((float)y.x, (float)y.y);
+        }
+#pragma unroll
+        for (int s = 0; s < kGemmKc; s++) {
+            cre = __builtin_amdgcn_mfma_f32_16x16x4f32(xv[s].x, yv[s].x, cre, 0, 0, 0);
+            cre = __builtin_amdgcn_mfma_f32_16x16x4f32(-xv[s].y, yv[s].y, cre, 0, 0, 0);
+            cim = __builtin_amdgcn_mfma_f32_16x16x4f32(xv[s].x, yv[s].y, cim, 0, 0, 0);
+            cim = __builtin_amdgcn_mfma_f32_16x16x4f32(xv[s].y, yv[s].x, cim, 0, 0, 0);
+        }
+    }
+    double2 *C = reinterpret_cast<double2 *>(G.C);
+    const int i = wr + li;
+    if (i >= M) return;
+    for (int r = 0; r < 4; r++) {
+        const int j = wc + 4 * lk + r;
+        if (j >= N || (lower && i < j)) continue;
+        double2 out = cmul(alpha, make_double2((double)cre[r], (double)cim[r]));
+        if (beta.x != 0.0 || beta.y != 0.0) out = cadd(out, cmul(beta, C[(size_t)j * G.ldc + i]));
+        C[(size_t)j * G.ldc + i] = out;
+    }
 }
 
 // ------------------------------------------------------------- bisection --
@@ -679,11 +737,13 @@ void stage1_fill_gemm_descs(const ProbDesc *hp, int np, GemmDesc *out)
 
 int stage1_run(const Stage1Batch &B, hipStream_t st)
 {
+    // the binary64 trailing updates and back-transform, or their FP32-MFMA variant
+    auto gemm = B.fp32 ? k_cgemm32 : k_zgemm;
     const int n = B.n, np = B.nprob;
     ProbDesc *pd = B.dev_probs;
     const GemmDesc *gd = B.dev_gemm;
     if (n < 1 || np < 1) return 0;
-    hipLaunchKernelGGL(k_ingest, dim3(n, np), dim3(256), 0, st, pd);
+    hipLaunchKernelGGL(k_ingest, dim3(n, np), dim3(256), 0, st, pd, B.fp32);
     if (n == 1) {
         hipLaunchKernelGGL(k_n1, dim3(cdiv(np, 64)), dim3(64), 0, st, pd, np);
         return hipGetLastError() == hipSuccess ? 0 : -1;
@@ -712,10 +772,10 @@ int stage1_run(const Stage1Batch &B, hipStream_t st)
         const int r0 = k0 + nbw;
         const int m = n - r0;
         if (m > 0) {
-            const unsigned tiles = cdiv(m, 64) * cdiv(m, 64);
+            const unsigned tiles = cdiv(m, 32) * cdiv(m, 32);
             // algorithmic flops of the lower-triangle rank-2*nbw update: 8 nbw m (m+1)
             const int id = B.timer ? B.timer->begin(KC_HER2K, 8.0 * nbw * (double)m * (m + 1) * np, st) : -1;
-            hipLaunchKernelGGL(k_zgemm, dim3(tiles, np), dim3(256), 0, st, gd + (size_t)(4 * p) * np, m, m, 2 * kNB, 0, 1,
+            hipLaunchKernelGGL(gemm, dim3(tiles, np), dim3(256), 0, st, gd + (size_t)(4 * p) * np, m, m, 2 * kNB, 0, 1,
                                make_double2(-1.0, 0.0), make_double2(1.0, 0.0), 1);
             if (B.timer) B.timer->end(id, st);
         }
@@ -736,11 +796,11 @@ int stage1_run(const Stage1Batch &B, hipStream_t st)
         const int k0 = p * kNB;
         const int nbw = std::min(kNB, n - 1 - k0);
         const int m = n - k0 - 1;
-        hipLaunchKernelGGL(k_zgemm, dim3(cdiv(nbw, 64) * cdiv(n, 64), np), dim3(256), 0, st, gd + (size_t)(4 * p + 1) * np,
+        hipLaunchKernelGGL(gemm, dim3(cdiv(nbw, 32) * cdiv(n, 32), np), dim3(256), 0, st, gd + (size_t)(4 * p + 1) * np,
                            nbw, n, m, 1, 0, make_double2(1.0, 0.0), make_double2(0.0, 0.0), 0);
-        hipLaunchKernelGGL(k_zgemm, dim3(cdiv(nbw, 64) * cdiv(n, 64), np), dim3(256), 0, st, gd + (size_t)(4 * p + 2) * np,
+        hipLaunchKernelGGL(gemm, dim3(cdiv(nbw, 32) * cdiv(n, 32), np), dim3(256), 0, st, gd + (size_t)(4 * p + 2) * np,
                            nbw, n, nbw, 0, 0, make_double2(1.0, 0.0), make_double2(0.0, 0.0), 0);
-        hipLaunchKernelGGL(k_zgemm, dim3(cdiv(m, 64) * cdiv(n, 64), np), dim3(256), 0, st, gd + (size_t)(4 * p + 3) * np,
+        hipLaunchKernelGGL(gemm, dim3(cdiv(m, 32) * cdiv(n, 32), np), dim3(256), 0, st, gd + (size_t)(4 * p + 3) * np,
                            m, n, nbw, 0, 0, make_double2(-1.0, 0.0), make_double2(1.0, 0.0), 0);
     }
     if (B.timer) B.timer->end(idb, st);

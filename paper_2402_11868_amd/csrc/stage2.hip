@@ -625,8 +625,16 @@ __global__ void k_s2_output(PairDesc *pairs, RqiProb *probs, const int *dst)
 // list of all columns of a matrix and an empty prefix, re-orthogonalise a
 // whole eigenbasis.  Blocks of RB active members: the block is projected
 // against all earlier entries (coefficients by 16x16 tiles, then the update),
-// then orthonormalised inside the block by modified Gram-Schmidt (twice).
+// then orthonormalised inside the block by Cholesky QR applied twice: the
+// block's Gram matrix (row slices summed in a fixed order), its Cholesky factor
+// R and R^-1 in L limbs, V <- V R^-1.  In exact arithmetic this is the same
+// basis as Gram-Schmidt in index order (R has a positive diagonal).  When a
+// pivot shows a member within 1e-8 (angle) of the span of the earlier ones --
+// two members that converged to the same vector -- the block falls back to
+// modified Gram-Schmidt (twice), which separates such members.
 constexpr int RB = 32;
+constexpr int RBP = RB * (RB + 1) / 2;   // packed upper triangle, column by column
+__device__ __forceinline__ int pk(int a, int c) { return c * (c + 1) / 2 + a; }
 
 template <int L>
 __global__ void __launch_bounds__(256) k_gs_dot(const GsCluster *cls, const int *list, const RqiProb *probs, int b,
@@ -686,12 +694,152 @@ __global__ void __launch_bounds__(256) k_gs_update(const GsCluster *cls, const i
 
 // inside the block: modified Gram-Schmidt (twice) and normalisation; the
 // coefficients of a member are computed by the four waves in parallel
+// Gram matrix of the block, one row slice per blockIdx.x; tiles of 16 x 16
+// (blockIdx.y: 0 = (0,0), 1 = (0,1), 2 = (1,1)); entry (a, c) = v_a^H v_c.
 template <int L>
-__global__ void __launch_bounds__(256) k_gs_intra(const GsCluster *cls, const int *list, RqiProb *probs, PairDesc *pairs, int b)
+__global__ void __launch_bounds__(256) k_gs_gram(const GsCluster *cls, const int *list, const RqiProb *probs, int b,
+                                                 double *gram, int ks)
+{
+    const GsCluster C = cls[blockIdx.z];
+    const int j0 = C.nconv + b * RB, bw = min(RB, C.nact - b * RB);
+    const int ta = blockIdx.y == 2 ? 1 : 0, tc = blockIdx.y == 0 ? 0 : 1;
+    if (bw <= 0 || tc * 16 >= bw) return;
+    const RqiProb &P = probs[C.prob];
+    const int n = P.n;
+    const size_t nn = (size_t)n * n;
+    const int *lst = list + C.off;
+    const int rc = ((n + ks - 1) / ks + 15) / 16 * 16;
+    const int rbeg = blockIdx.x * rc, rend = min(n, rbeg + rc);
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    __shared__ cmp<L> sa[16][16], sc[16][16];   // [row][vector]
+    const int va = ta * 16 + ty, vc = tc * 16 + ty;
+    const int ca = va < bw ? lst[j0 + va] : -1, cc = vc < bw ? lst[j0 + vc] : -1;
+    CAcc<L> acc;
+    acc.init(c_zero<L>());
+    for (int r0 = rbeg; r0 < rend; r0 += 16) {
+        __syncthreads();
+        const int r = r0 + tx;
+        sa[tx][ty] = (r < rend && ca >= 0) ? ld_cmp<L>(P.vec, nn, (size_t)ca * n + r) : c_zero<L>();
+        sc[tx][ty] = (r < rend && cc >= 0) ? ld_cmp<L>(P.vec, nn, (size_t)cc * n + r) : c_zero<L>();
+        __syncthreads();
+        for (int q = 0; q < 16; q++) acc.add_mulc(sa[q][ty], sc[q][tx]);
+    }
+    const int a = ta * 16 + ty, c = tc * 16 + tx;
+    double *g = gram + ((size_t)blockIdx.z * ks + blockIdx.x) * (2 * L * RB * RB);
+    if (a < bw && c < bw) st_cmp<L>(g, (size_t)RB * RB, (size_t)a * RB + c, acc.get());
+}
+
+// Cholesky factor of the block's Gram matrix and its inverse, one wave per
+// cluster.  pass 0 sets the fallback flag; pass 1 is skipped for a flagged
+// cluster.  The packed inverse overwrites the cluster's first Gram slice.
+template <int L>
+__global__ void __launch_bounds__(64) k_gs_chol(const GsCluster *cls, int b, double *gram, int ks, int *flag, int pass)
+{
+    const GsCluster C = cls[blockIdx.x];
+    const int bw = min(RB, C.nact - b * RB);
+    if (bw <= 0) return;
+    if (pass == 1 && flag[blockIdx.x]) return;
+    const int lane = threadIdx.x;
+    __shared__ cmp<L> R[RBP];
+    __shared__ double dg[RB];
+    __shared__ int bad;
+    double *g0 = gram + (size_t)blockIdx.x * ks * (2 * L * RB * RB);
+    for (int c = 0; c < bw; c++)
+        if (lane <= c) {
+            cmp<L> x = c_zero<L>();
+            for (int s = 0; s < ks; s++) x = c_add(x, ld_cmp<L>(g0 + (size_t)s * (2 * L * RB * RB), (size_t)RB * RB, (size_t)lane * RB + c));
+            if (lane == c) {
+                x.im = mp_zero<L>();
+                dg[c] = x.re.x[0];
+            }
+            R[pk(lane, c)] = x;
+        }
+    if (lane == 0) bad = 0;
+    __syncthreads();
+    // right-looking factorisation G = R^H R
+    for (int j = 0; j < bw; j++) {
+        const mp<L> d = R[pk(j, j)].re;
+        if (!(d.x[0] > 1e-16 * dg[j])) {
+            if (lane == 0) bad = 1;
+            break;
+        }
+        const mp<L> rj = sqrt_mp(d), inv = div(mp_from<L>(1.0), rj);
+        __syncthreads();
+        if (lane > j && lane < bw) R[pk(j, lane)] = c_scale(R[pk(j, lane)], inv);
+        if (lane == j) R[pk(j, j)] = cmp<L>{rj, mp_zero<L>()};
+        __syncthreads();
+        for (int c = j + 1; c < bw; c++)
+            if (lane > j && lane <= c) {
+                // R(a,c) -= conj(R(j,a)) R(j,c)
+                const cmp<L> t = c_mulc(R[pk(j, lane)], R[pk(j, c)]);
+                R[pk(lane, c)] = c_sub(R[pk(lane, c)], t);
+            }
+        __syncthreads();
+    }
+    __syncthreads();
+    if (bad) {
+        if (lane == 0) flag[blockIdx.x] = 1;
+        return;
+    }
+    // in-place inverse of the upper triangle, column by column
+    for (int j = 0; j < bw; j++) {
+        const mp<L> dinv = div(mp_from<L>(1.0), R[pk(j, j)].re);
+        cmp<L> val = cmp<L>{dinv, mp_zero<L>()};
+        if (lane < j) {
+            cmp<L> t = c_zero<L>();
+            for (int k = lane; k < j; k++) t = c_add(t, c_mul(R[pk(lane, k)], R[pk(k, j)]));
+            val = c_scale(t, mp_neg<L>(dinv));
+        }
+        __syncthreads();
+        if (lane <= j) R[pk(lane, j)] = val;
+        __syncthreads();
+    }
+    for (int e = lane; e < bw * (bw + 1) / 2; e += 64) st_cmp<L>(g0, (size_t)RBP, (size_t)e, R[e]);
+    if (lane == 0 && pass == 0) flag[blockIdx.x] = 0;
+}
+
+// V_block <- V_block R^-1, rows in slices of 8 per work-group (8 x 32 threads)
+template <int L>
+__global__ void __launch_bounds__(256) k_gs_apply(const GsCluster *cls, const int *list, RqiProb *probs, PairDesc *pairs, int b,
+                                                  const double *gram, int ks, const int *flag)
+{
+    const GsCluster C = cls[blockIdx.y];
+    const int j0 = C.nconv + b * RB, bw = min(RB, C.nact - b * RB);
+    if (bw <= 0 || flag[blockIdx.y]) return;
+    const RqiProb &P = probs[C.prob];
+    const int n = P.n;
+    const size_t nn = (size_t)n * n;
+    const int *lst = list + C.off;
+    const int tid = threadIdx.x, k = tid & 31, ty = tid >> 5;
+    const int r = blockIdx.x * 8 + ty;
+    __shared__ cmp<L> Ri[RBP];
+    __shared__ cmp<L> X[8][RB];
+    const double *g0 = gram + (size_t)blockIdx.y * ks * (2 * L * RB * RB);
+    for (int e = tid; e < bw * (bw + 1) / 2; e += 256) Ri[e] = ld_cmp<L>(g0, (size_t)RBP, (size_t)e);
+    const bool live = r < n && k < bw;
+    X[ty][k] = live ? ld_cmp<L>(P.vec, nn, (size_t)lst[j0 + k] * n + r) : c_zero<L>();
+    __syncthreads();
+    if (!live) return;
+    CAcc<L> acc;
+    acc.init(c_zero<L>());
+    for (int i = 0; i <= k; i++) {
+        const cmp<L> ri = Ri[pk(i, k)];
+        acc.sub_mul(cmp<L>{mp_neg<L>(ri.re), mp_neg<L>(ri.im)}, X[ty][i]);   // += R^-1(i,k) x_i
+    }
+    st_cmp<L>(P.vec, nn, (size_t)lst[j0 + k] * n + r, acc.get());
+    if (pairs && C.size > 1 && r == 0) pairs[C.pair_base + lst[j0 + k]].flags |= 2;
+}
+
+// fallback for flagged clusters: modified Gram-Schmidt (twice) inside the
+// block and normalisation; the coefficients of a member are computed by the
+// four waves in parallel
+template <int L>
+__global__ void __launch_bounds__(256) k_gs_intra(const GsCluster *cls, const int *list, RqiProb *probs, PairDesc *pairs, int b,
+                                                  const int *flag)
 {
     const GsCluster C = cls[blockIdx.x];
     const int j0 = C.nconv + b * RB, bw = min(RB, C.nact - b * RB);
-    if (bw <= 0) return;
+    if (bw <= 0 || !flag[blockIdx.x]) return;
     const RqiProb &P = probs[C.prob];
     const int n = P.n;
     const size_t nn = (size_t)n * n;
@@ -742,13 +890,137 @@ int stage2_gs(const GsPlan &G, RqiProb *probs, PairDesc *pairs, hipStream_t st)
                                    G.dev_list, probs, b, (const double *)G.scratch);
             }
         }
-        hipLaunchKernelGGL(k_gs_intra<L>, dim3(G.ncl), dim3(256), 0, st, G.dev_cls, G.dev_list, probs, pairs, b);
+        for (int pass = 0; pass < 2; pass++) {
+            hipLaunchKernelGGL(k_gs_gram<L>, dim3(G.ks, 3, G.ncl), dim3(256), 0, st, G.dev_cls, G.dev_list,
+                               (const RqiProb *)probs, b, G.gram, G.ks);
+            hipLaunchKernelGGL(k_gs_chol<L>, dim3(G.ncl), dim3(64), 0, st, G.dev_cls, b, G.gram, G.ks, G.flag, pass);
+            hipLaunchKernelGGL(k_gs_apply<L>, dim3((G.max_n + 7) / 8, G.ncl), dim3(256), 0, st, G.dev_cls, G.dev_list, probs,
+                               pairs, b, (const double *)G.gram, G.ks, (const int *)G.flag);
+        }
+        hipLaunchKernelGGL(k_gs_intra<L>, dim3(G.ncl), dim3(256), 0, st, G.dev_cls, G.dev_list, probs, pairs, b,
+                           (const int *)G.flag);
     }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 template int stage2_gs<2>(const GsPlan &, RqiProb *, PairDesc *, hipStream_t);
 template int stage2_gs<4>(const GsPlan &, RqiProb *, PairDesc *, hipStream_t);
+
+// ============================================ projected Rayleigh-Ritz ====
+// A cluster longer than the in-LDS Rayleigh-Ritz holds (chains of eigenvalues
+// closer than the cluster tolerance, typically the tail of tiny eigenvalues
+// that binary64 cannot separate relative to ||H||): C = V^H H V is formed in
+// L limbs, so its entries carry the cluster's own scale, rounded to binary64
+// and eigendecomposed by the binary64 stage on the host side of the engine;
+// V <- V Q then gives Ritz vectors that separate the members relative to the
+// cluster's scale instead of ||H||.
+template <int L>
+__global__ void __launch_bounds__(256) k_prr_hv(const PrrDesc *descs, const RqiProb *probs)
+{
+    const PrrDesc D = descs[blockIdx.y];
+    const int a = blockIdx.x;
+    if (a >= D.size) return;
+    const RqiProb &P = probs[D.prob];
+    const int n = P.n;
+    const size_t nn = (size_t)n * n, yplane = (size_t)n * D.size;
+    const int ka = D.k0 + a;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        CAcc<L> y;
+        y.init(c_zero<L>());
+        for (int j = 0; j < n; j++) {
+            const cmp<L> h = ld_h<L>(P, i, j);
+            y.sub_mul(cmp<L>{mp_neg<L>(h.re), mp_neg<L>(h.im)}, ld_cmp<L>(P.vec, nn, (size_t)ka * n + j));
+        }
+        st_cmp<L>(D.Y, yplane, (size_t)a * n + i, y.get());
+    }
+}
+
+// C(a, c) = v_a^H y_c by 16 x 16 tiles; written as binary64 (the leading limb)
+template <int L>
+__global__ void __launch_bounds__(256) k_prr_c(const PrrDesc *descs, const RqiProb *probs)
+{
+    const PrrDesc D = descs[blockIdx.z];
+    if (blockIdx.x * 16 >= D.size || blockIdx.y * 16 >= D.size) return;
+    const RqiProb &P = probs[D.prob];
+    const int n = P.n, m = D.size;
+    const size_t nn = (size_t)n * n, yplane = (size_t)n * m;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    __shared__ cmp<L> sv[16][16], sy[16][16];   // [row][vector]
+    const int va = blockIdx.x * 16 + ty, vc = blockIdx.y * 16 + ty;
+    CAcc<L> acc;
+    acc.init(c_zero<L>());
+    for (int r0 = 0; r0 < n; r0 += 16) {
+        __syncthreads();
+        const int r = r0 + tx;
+        sv[tx][ty] = (r < n && va < m) ? ld_cmp<L>(P.vec, nn, (size_t)(D.k0 + va) * n + r) : c_zero<L>();
+        sy[tx][ty] = (r < n && vc < m) ? ld_cmp<L>(D.Y, yplane, (size_t)vc * n + r) : c_zero<L>();
+        __syncthreads();
+        for (int q = 0; q < 16; q++) acc.add_mulc(sv[q][ty], sy[q][tx]);
+    }
+    const int a = blockIdx.x * 16 + ty, c = blockIdx.y * 16 + tx;
+    if (a < m && c < m) {
+        const cmp<L> v = acc.get();
+        st2(D.C + 2 * ((size_t)c * m + a), make_double2(v.re.x[0], a == c ? 0.0 : v.im.x[0]));
+    }
+}
+
+// Y(:, j) = sum_i v_i Q(i, j); grid (ceil(n/64), ceil(size/4), nd)
+template <int L>
+__global__ void __launch_bounds__(256) k_prr_rot(const PrrDesc *descs, const RqiProb *probs)
+{
+    const PrrDesc D = descs[blockIdx.z];
+    const RqiProb &P = probs[D.prob];
+    const int n = P.n, m = D.size;
+    const int r = blockIdx.x * 64 + (threadIdx.x & 63), j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (r >= n || j >= m) return;
+    const size_t nn = (size_t)n * n, yplane = (size_t)n * m;
+    CAcc<L> acc;
+    acc.init(c_zero<L>());
+    for (int i = 0; i < m; i++) {
+        const double2 q = ld2(D.Q + 2 * ((size_t)j * m + i));
+        acc.sub_mul(cmp<L>{mp_from<L>(-q.x), mp_from<L>(-q.y)}, ld_cmp<L>(P.vec, nn, (size_t)(D.k0 + i) * n + r));
+    }
+    st_cmp<L>(D.Y, yplane, (size_t)j * n + r, acc.get());
+}
+
+template <int L>
+__global__ void __launch_bounds__(256) k_prr_back(const PrrDesc *descs, RqiProb *probs)
+{
+    const PrrDesc D = descs[blockIdx.z];
+    const int j = blockIdx.y;
+    if (j >= D.size) return;
+    const RqiProb &P = probs[D.prob];
+    const int n = P.n;
+    const size_t nn = (size_t)n * n, yplane = (size_t)n * D.size;
+    for (int r = blockIdx.x * 256 + threadIdx.x; r < n; r += gridDim.x * 256)
+        st_cmp<L>(P.vec, nn, (size_t)(D.k0 + j) * n + r, ld_cmp<L>(D.Y, yplane, (size_t)j * n + r));
+}
+
+template <int L>
+int stage2_prr_project(const PrrDesc *d, int nd, int max_size, int max_n, RqiProb *probs, hipStream_t st)
+{
+    if (nd <= 0) return 0;
+    (void)max_n;
+    hipLaunchKernelGGL(k_prr_hv<L>, dim3(max_size, nd), dim3(256), 0, st, d, (const RqiProb *)probs);
+    hipLaunchKernelGGL(k_prr_c<L>, dim3((max_size + 15) / 16, (max_size + 15) / 16, nd), dim3(256), 0, st, d,
+                       (const RqiProb *)probs);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int L>
+int stage2_prr_rotate(const PrrDesc *d, int nd, int max_size, int max_n, RqiProb *probs, hipStream_t st)
+{
+    if (nd <= 0) return 0;
+    hipLaunchKernelGGL(k_prr_rot<L>, dim3((max_n + 63) / 64, (max_size + 3) / 4, nd), dim3(256), 0, st, d,
+                       (const RqiProb *)probs);
+    hipLaunchKernelGGL(k_prr_back<L>, dim3((max_n + 255) / 256, max_size, nd), dim3(256), 0, st, d, probs);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template int stage2_prr_project<2>(const PrrDesc *, int, int, int, RqiProb *, hipStream_t);
+template int stage2_prr_project<4>(const PrrDesc *, int, int, int, RqiProb *, hipStream_t);
+template int stage2_prr_rotate<2>(const PrrDesc *, int, int, int, RqiProb *, hipStream_t);
+template int stage2_prr_rotate<4>(const PrrDesc *, int, int, int, RqiProb *, hipStream_t);
 
 // ====================================================== Rayleigh-Ritz ====
 // For a small cluster (2..RRMAX members, binary64 vectors already made

@@ -195,6 +195,25 @@ def test_qd_householder_n24(zk):
     judge([A], res, oracle.heev([A], want_vectors=False).w_limbs, QD_TOL, orth_tol=QD_ORTH)
 
 
+# ------------------------------------------------------ FP32-MFMA start ----
+def test_fp32_mfma_start_variant(zk):
+    """Binary64 stage on the complex64-rounded input with FP32-MFMA GEMMs; the
+    refinement reaches the same gates from the coarser start."""
+    Z, ctx, torch = zk
+    import golden_io as G
+    wl = W.workload(1)
+    hdr, gold = G.load("c1")
+    d = _dev(torch, [wl["A"]])
+    r64, = Z.heev(ctx, [d], limbs_out=2)
+    r32, = Z.heev(ctx, [d], limbs_out=2, opts=Z.make_opts(init_fp32=1))
+    out = judge([wl["A"]], r32, gold, DD_TOL, orth_tol=DD_ORTH)
+    log(f"fp32 start: {out}; iterations fp64 start {np.bincount(r64.iters)}, fp32 start {np.bincount(r32.iters)}")
+    assert np.mean(r32.iters) >= np.mean(r64.iters)
+    A = W.householder_hermitian(W.spectrum_c4(130), seed=77)
+    r, = Z.heev(ctx, [_dev(torch, [A])], limbs_out=2, opts=Z.make_opts(init_fp32=1))
+    judge([A], r, oracle.heev([A], want_vectors=False).w_limbs, DD_TOL, orth_tol=DD_ORTH)
+
+
 # ------------------------------------------------------------- errors ----
 def test_errors_nan_and_bad_args(zk):
     Z, ctx, torch = zk

@@ -255,6 +255,16 @@ def spectrum_c5(n: int = 2048, exact: bool = False):
     return np.concatenate([[1.0 - 2.0 ** -59, 2.0 ** -59], geo])
 
 
+def spectrum_c5_dyadic(n: int, bits: int = 40) -> list:
+    """Exact form of the quad-double spectrum for the Hadamard family: {1-2^-59, 2^-59}
+    and 2^(-120 k/(n-2)), k=1..n-2, each rounded to `bits` significant bits (Fractions)."""
+    lam = [Fraction(1) - Fraction(1, 2 ** 59), Fraction(1, 2 ** 59)]
+    for k in range(1, n - 1):
+        m, e = np.frexp(2.0 ** (-120.0 * k / (n - 2)))
+        lam.append(Fraction(int(round(m * 2 ** bits)), 2 ** bits) * Fraction(2) ** int(e))
+    return lam
+
+
 def serving_sizes() -> list[int]:
     return list(range(16, 513, 16))
 
