@@ -55,6 +55,7 @@ struct S2Prob {
     std::vector<PairDesc> pairs;   // authoritative host copy of the pair states
     std::vector<int> heads;        // local index of every cluster's first pair
     std::vector<std::pair<int, int>> rrb;   // Rayleigh-Ritz blocks (first pair, members), 2..32 members
+    std::vector<double> w0h;       // binary64 eigenvalues (ascending) the clusters were planned on
     std::vector<int> redo;         // pairs sent back for more iterations after the re-orthogonalisation
     int polish = 0;                // number of such passes so far
     void *vecbuf = nullptr;
@@ -104,6 +105,7 @@ class Stage2Engine {
             w0h.resize(kp);
             HIPCHK_(hipMemcpyAsync(w0h.data(), P.w0, 8 * (size_t)kp, hipMemcpyDeviceToHost, st));
             HIPCHK_(hipStreamSynchronize(st));
+            p->w0h = w0h;
             double hn = 0.0;
             for (int k = 0; k < kp; k++) hn = std::max(hn, std::fabs(w0h[k]));
             hn = std::max(hn, P.hnorm);
@@ -112,33 +114,41 @@ class Stage2Engine {
             P.tol_abs = p->opts.tol * hn;
             P.piv_tol = std::ldexp(hn, -53 * L);
             P.max_iter = p->opts.max_iter;
-            const double thr = p->opts.cluster_tol * hn;
-            p->pairs.assign(kp, PairDesc());
-            int start = 0;
-            for (int k = 0; k < kp; k++) {
-                if (k > 0 && !(w0h[k] - w0h[k - 1] <= thr)) start = k;
-                PairDesc &q = p->pairs[k];
-                std::memset(&q, 0, sizeof q);
-                q.k = k;
-                q.cl_start = start;
-            }
-            p->heads.clear();
-            int k = 0;
-            while (k < kp) {
-                int e = k + 1;
-                while (e < kp && p->pairs[e].cl_start == k) e++;
-                for (int q = k; q < e; q++) p->pairs[q].cl_size = (q == k) ? e - k : 0;
-                p->heads.push_back(k);
-                k = e;
-            }
-            p->rrb.clear();
-            for (int h : p->heads)
-                if (p->pairs[h].cl_size >= 2 && p->pairs[h].cl_size <= 32) p->rrb.push_back(std::make_pair(h, p->pairs[h].cl_size));
+            plan_clusters(p, w0h, p->opts.init_fp32 ? 2 : 0);
         }
         if ((rc = upload(batch)) != ZK_OK) return rc;
         if (stage2_init<L>(d_pairs, d_probs, total_pairs, st)) return ctx->fail(ZK_EDEVICE, "init launch failed");
         for (S2Prob *p : batch)
             for (auto &q : p->pairs) q.status = 0;
+        // An FP32 start resolves the spectrum only to about 2^-24 ||H||: one
+        // Rayleigh-Ritz step on the whole basis (made orthonormal in L limbs
+        // first) gives binary64-quality pairs, and the clusters are planned
+        // again on its Ritz values.
+        bool any32 = false;
+        for (S2Prob *p : batch) any32 = any32 || p->opts.init_fp32;
+        if (any32) {
+            // only the FP32-start matrices take part (the others' pairs are
+            // frozen for this step), so every result stays independent of
+            // the rest of the batch
+            for (S2Prob *p : batch)
+                if (!p->opts.init_fp32)
+                    for (auto &q : p->pairs) q.status = 1;
+            rc = run_gs(batch, false);
+            for (S2Prob *p : batch)
+                if (!p->opts.init_fp32)
+                    for (auto &q : p->pairs) q.status = 0;
+            if (rc != ZK_OK) return rc;
+            std::vector<PrrBlock> whole;
+            for (size_t pi = 0; pi < batch.size(); pi++)
+                if (batch[pi]->opts.init_fp32 && batch[pi]->npairs >= 2) whole.push_back({(int)pi, 0, batch[pi]->npairs});
+            if ((rc = prr_level(batch, whole, true, nullptr)) != ZK_OK) return rc;
+            for (S2Prob *p : batch) {
+                if (!p->opts.init_fp32) continue;
+                plan_clusters(p, p->w0h, 0);
+                for (auto &q : p->pairs) q.status = 0;
+            }
+            if ((rc = upload(batch)) != ZK_OK) return rc;
+        }
         if ((rc = run_gs(batch, false)) != ZK_OK) return rc;
         bool projected = false;
         if ((rc = run_prr(batch, projected)) != ZK_OK) return rc;
@@ -206,6 +216,7 @@ class Stage2Engine {
     int rounds = 0;
     static constexpr int kPolishPasses = 2;
     static constexpr int kPrrLevels = 4;
+    static constexpr double kReorthWindow = 0.1;
 
   private:
     zk_ctx *ctx;
@@ -387,20 +398,36 @@ class Stage2Engine {
             G.max_n = std::max(G.max_n, set[pi]->rp.n);
         };
         if (global) {
-            // a whole eigenbasis in index order, or (after a polishing pass)
-            // only the re-iterated pairs against all the others
+            // The eigenbasis in windows: consecutive pairs whose binary64
+            // eigenvalues are closer than kReorthWindow * ||H|| share a window.
+            // Pairs further apart are orthogonal to residual / gap <= tol /
+            // kReorthWindow already; re-orthogonalising them against each
+            // other would only add to their residuals (each projection adds
+            // its coefficient times the eigenvalue difference).  Inside a
+            // window: every pair in index order, or (after a polishing pass)
+            // only the re-iterated pairs against the rest of their window.
             for (int pi : *only) {
                 S2Prob *p = set[pi];
-                if (p->npairs != p->rp.n || p->rp.n < 2) continue;
-                std::vector<int> act, fro;
-                if (p->redo.empty()) {
-                    for (int k = 0; k < p->rp.n; k++) act.push_back(k);
-                } else {
-                    std::vector<char> r(p->rp.n, 0);
-                    for (int k : p->redo) r[k] = 1;
-                    for (int k = 0; k < p->rp.n; k++) (r[k] ? act : fro).push_back(k);
+                const int n = p->npairs;
+                if (n < 2 || (int)p->w0h.size() != n) continue;
+                std::vector<char> r(n, 0);
+                for (int k : p->redo) r[k] = 1;
+                const double win = kReorthWindow * p->rp.hnorm;
+                int g0 = 0;
+                for (int e = 1; e <= n; e++) {
+                    if (e < n && p->w0h[e] - p->w0h[e - 1] <= win) continue;
+                    if (e - g0 >= 2) {
+                        std::vector<int> act, fro;
+                        for (int k = g0; k < e; k++) {
+                            if (p->redo.empty() || r[k])
+                                act.push_back(k);
+                            else
+                                fro.push_back(k);
+                        }
+                        if (!act.empty()) add(pi, fro, act);
+                    }
+                    g0 = e;
                 }
-                add(pi, fro, act);
             }
         } else {
             for (size_t pi = 0; pi < set.size(); pi++) {
@@ -444,6 +471,41 @@ class Stage2Engine {
         return ZK_OK;
     }
 
+    // Clusters from ascending binary64 eigenvalues: gaps <= cluster_tol ||H||
+    // (mode 2: the whole spectrum is one cluster, for a start that is about
+    // to be projected as a whole); Rayleigh-Ritz blocks for 2..32 members.
+    void plan_clusters(S2Prob *p, const std::vector<double> &w, int mode)
+    {
+        const int kp = p->npairs;
+        const double thr = p->opts.cluster_tol * p->rp.hnorm;
+        p->pairs.assign(kp, PairDesc());
+        int start = 0;
+        for (int k = 0; k < kp; k++) {
+            if (mode != 2 && k > 0 && !(w[k] - w[k - 1] <= thr)) start = k;
+            PairDesc &q = p->pairs[k];
+            std::memset(&q, 0, sizeof q);
+            q.k = k;
+            q.cl_start = start;
+        }
+        p->heads.clear();
+        int k = 0;
+        while (k < kp) {
+            int e = k + 1;
+            while (e < kp && p->pairs[e].cl_start == k) e++;
+            for (int q = k; q < e; q++) p->pairs[q].cl_size = (q == k) ? e - k : 0;
+            p->heads.push_back(k);
+            k = e;
+        }
+        p->rrb.clear();
+        if (mode != 2)
+            for (int h : p->heads)
+                if (p->pairs[h].cl_size >= 2 && p->pairs[h].cl_size <= 32) p->rrb.push_back(std::make_pair(h, p->pairs[h].cl_size));
+    }
+
+    struct PrrBlock {
+        int pi, k0, size;
+    };
+
     // Projected Rayleigh-Ritz on the clusters longer than 32 members: C =
     // V^H H V in L limbs, the binary64 stage on C (rounded), V <- V Q.  The
     // Ritz values split the cluster into sub-chains relative to its own scale
@@ -451,110 +513,124 @@ class Stage2Engine {
     // Rayleigh-Ritz blocks, longer ones are projected again at the next level.
     int run_prr(const std::vector<S2Prob *> &set, bool &projected)
     {
-        struct Blk {
-            int pi, k0, size;
-        };
-        std::vector<Blk> todo;
+        std::vector<PrrBlock> todo;
         for (size_t pi = 0; pi < set.size(); pi++)
             for (int h : set[pi]->heads)
                 if (set[pi]->pairs[h].cl_size > 32) todo.push_back({(int)pi, h, set[pi]->pairs[h].cl_size});
         for (int level = 0; level < kPrrLevels && !todo.empty(); level++) {
             projected = true;
-            const int nd = (int)todo.size();
-            int max_size = 0, max_n = 0;
-            size_t bytes = s2_align(sizeof(PrrDesc) * nd);
-            std::vector<size_t> off(nd);
-            for (int b = 0; b < nd; b++) {
-                const size_t m = (size_t)todo[b].size, n = (size_t)set[todo[b].pi]->rp.n;
-                max_size = std::max(max_size, todo[b].size);
-                max_n = std::max(max_n, (int)n);
-                off[b] = bytes;
-                // Y, C, hf, w0, V0, flag
-                bytes += s2_align(8 * 2 * (size_t)L * n * m) + 3 * s2_align(16 * m * m) + s2_align(8 * m) + s2_align(4);
-            }
-            if (ctx->held() + bytes > ctx->budget) return ctx->fail(ZK_ENOMEM, "projected Rayleigh-Ritz exceeds the budget");
-            void *buf = nullptr;
-            if (hipMalloc(&buf, bytes) != hipSuccess) {
-                hipGetLastError();
-                return ctx->fail(ZK_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
-            }
-            ctx->extra += bytes;
-            std::vector<PrrDesc> hd(nd);
-            std::vector<zk_herm> hm(nd);
-            std::vector<double *> hf(nd), w0(nd), V0(nd);
-            std::vector<int *> flag(nd);
-            for (int b = 0; b < nd; b++) {
-                const size_t m = (size_t)todo[b].size, n = (size_t)set[todo[b].pi]->rp.n;
-                char *c = (char *)buf + off[b];
-                PrrDesc &D = hd[b];
-                std::memset(&D, 0, sizeof D);
-                D.prob = todo[b].pi;
-                D.k0 = todo[b].k0;
-                D.size = (int)m;
-                D.Y = (double *)c;
-                c += s2_align(8 * 2 * (size_t)L * n * m);
-                D.C = (double *)c;
-                c += s2_align(16 * m * m);
-                hf[b] = (double *)c;
-                c += s2_align(16 * m * m);
-                V0[b] = (double *)c;
-                D.Q = V0[b];
-                c += s2_align(16 * m * m);
-                w0[b] = (double *)c;
-                c += s2_align(8 * m);
-                flag[b] = (int *)c;
-                std::memset(&hm[b], 0, sizeof(zk_herm));
-                hm[b].n = (int)m;
-                hm[b].lda = (int)m;
-                hm[b].limbs = 1;
-                hm[b].plane[0] = D.C;
-            }
-            PrrDesc *d_desc = (PrrDesc *)buf;
-            int rc = ZK_OK;
-            auto cleanup = [&]() {
-                hipStreamSynchronize(st);
-                hipFree(buf);
-                ctx->extra -= bytes;
-            };
-            if (hipMemcpyAsync(d_desc, hd.data(), sizeof(PrrDesc) * nd, hipMemcpyHostToDevice, st) != hipSuccess ||
-                stage2_prr_project<L>(d_desc, nd, max_size, max_n, d_probs, st)) {
-                cleanup();
-                return ctx->fail(ZK_EDEVICE, "projected Rayleigh-Ritz launch failed");
-            }
-            if ((rc = run_stage1(ctx, nd, hm.data(), hf, w0, V0, flag, std::vector<int>())) != ZK_OK) {
-                cleanup();
-                return rc;
-            }
-            if (stage2_prr_rotate<L>(d_desc, nd, max_size, max_n, d_probs, st)) {
-                cleanup();
-                return ctx->fail(ZK_EDEVICE, "projected Rayleigh-Ritz launch failed");
-            }
-            // sub-chains from the Ritz values
-            std::vector<Blk> next;
-            for (int b = 0; b < nd; b++) {
-                const int m = todo[b].size;
-                std::vector<double> w(m);
-                if (hipMemcpyAsync(w.data(), w0[b], 8 * (size_t)m, hipMemcpyDeviceToHost, st) != hipSuccess ||
-                    hipStreamSynchronize(st) != hipSuccess) {
-                    cleanup();
-                    return ctx->fail(ZK_EDEVICE, "projected Rayleigh-Ritz read-back failed");
-                }
-                S2Prob *p = set[todo[b].pi];
-                double sc = 0.0;
-                for (double x : w) sc = std::max(sc, std::fabs(x));
-                const double thr = p->opts.cluster_tol * sc;
-                int s0 = 0;
-                for (int e = 1; e <= m; e++) {
-                    if (e < m && w[e] - w[e - 1] <= thr) continue;
-                    const int len = e - s0;
-                    if (len >= 2 && len <= 32) p->rrb.push_back(std::make_pair(todo[b].k0 + s0, len));
-                    if (len > 32 && len < m) next.push_back({todo[b].pi, todo[b].k0 + s0, len});
-                    s0 = e;
-                }
-            }
-            cleanup();
+            std::vector<PrrBlock> next;
+            int rc = prr_level(set, todo, false, &next);
+            if (rc != ZK_OK) return rc;
             todo = next;
         }
+        return ZK_OK;
+    }
+
+    // One projected Rayleigh-Ritz step on the given blocks.  whole = true:
+    // the Ritz values replace the binary64 eigenvalues of the block (P.w0);
+    // otherwise they split the block into Rayleigh-Ritz blocks (2..32
+    // members, appended to rrb) and sub-chains for the next level (*next).
+    int prr_level(const std::vector<S2Prob *> &set, const std::vector<PrrBlock> &todo, bool whole, std::vector<PrrBlock> *next)
+    {
+        const int nd = (int)todo.size();
+        if (nd == 0) return ZK_OK;
+        int max_size = 0, max_n = 0;
+        size_t bytes = s2_align(sizeof(PrrDesc) * nd);
+        std::vector<size_t> off(nd);
+        for (int b = 0; b < nd; b++) {
+            const size_t m = (size_t)todo[b].size, n = (size_t)set[todo[b].pi]->rp.n;
+            max_size = std::max(max_size, todo[b].size);
+            max_n = std::max(max_n, (int)n);
+            off[b] = bytes;
+            // Y, C, hf, V0, w0, flag
+            bytes += s2_align(8 * 2 * (size_t)L * n * m) + 3 * s2_align(16 * m * m) + s2_align(8 * m) + s2_align(4);
+        }
+        if (ctx->held() + bytes > ctx->budget) return ctx->fail(ZK_ENOMEM, "projected Rayleigh-Ritz exceeds the budget");
+        void *buf = nullptr;
+        if (hipMalloc(&buf, bytes) != hipSuccess) {
+            hipGetLastError();
+            return ctx->fail(ZK_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
+        }
+        ctx->extra += bytes;
+        std::vector<PrrDesc> hd(nd);
+        std::vector<zk_herm> hm(nd);
+        std::vector<double *> hf(nd), w0(nd), V0(nd);
+        std::vector<int *> flag(nd);
+        for (int b = 0; b < nd; b++) {
+            const size_t m = (size_t)todo[b].size, n = (size_t)set[todo[b].pi]->rp.n;
+            char *c = (char *)buf + off[b];
+            PrrDesc &D = hd[b];
+            std::memset(&D, 0, sizeof D);
+            D.prob = todo[b].pi;
+            D.k0 = todo[b].k0;
+            D.size = (int)m;
+            D.Y = (double *)c;
+            c += s2_align(8 * 2 * (size_t)L * n * m);
+            D.C = (double *)c;
+            c += s2_align(16 * m * m);
+            hf[b] = (double *)c;
+            c += s2_align(16 * m * m);
+            V0[b] = (double *)c;
+            D.Q = V0[b];
+            c += s2_align(16 * m * m);
+            w0[b] = (double *)c;
+            c += s2_align(8 * m);
+            flag[b] = (int *)c;
+            std::memset(&hm[b], 0, sizeof(zk_herm));
+            hm[b].n = (int)m;
+            hm[b].lda = (int)m;
+            hm[b].limbs = 1;
+            hm[b].plane[0] = D.C;
+        }
+        PrrDesc *d_desc = (PrrDesc *)buf;
+        int rc = ZK_OK;
+        auto cleanup = [&]() {
+            hipStreamSynchronize(st);
+            hipFree(buf);
+            ctx->extra -= bytes;
+        };
+        if (hipMemcpyAsync(d_desc, hd.data(), sizeof(PrrDesc) * nd, hipMemcpyHostToDevice, st) != hipSuccess ||
+            stage2_prr_project<L>(d_desc, nd, max_size, max_n, d_probs, st)) {
+            cleanup();
+            return ctx->fail(ZK_EDEVICE, "projected Rayleigh-Ritz launch failed");
+        }
+        if ((rc = run_stage1(ctx, nd, hm.data(), hf, w0, V0, flag, std::vector<int>())) != ZK_OK) {
+            cleanup();
+            return rc;
+        }
+        if (stage2_prr_rotate<L>(d_desc, nd, max_size, max_n, d_probs, st)) {
+            cleanup();
+            return ctx->fail(ZK_EDEVICE, "projected Rayleigh-Ritz launch failed");
+        }
+        for (int b = 0; b < nd; b++) {
+            const int m = todo[b].size;
+            S2Prob *p = set[todo[b].pi];
+            std::vector<double> w(m);
+            if (hipMemcpyAsync(w.data(), w0[b], 8 * (size_t)m, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess) {
+                cleanup();
+                return ctx->fail(ZK_EDEVICE, "projected Rayleigh-Ritz read-back failed");
+            }
+            if (whole) {
+                // the Ritz values replace the binary64 eigenvalues of the block
+                if ((int)p->w0h.size() >= todo[b].k0 + m) std::copy(w.begin(), w.end(), p->w0h.begin() + todo[b].k0);
+                continue;
+            }
+            // sub-chains from the Ritz values
+            double sc = 0.0;
+            for (double x : w) sc = std::max(sc, std::fabs(x));
+            const double thr = p->opts.cluster_tol * sc;
+            int s0 = 0;
+            for (int e = 1; e <= m; e++) {
+                if (e < m && w[e] - w[e - 1] <= thr) continue;
+                const int len = e - s0;
+                if (len >= 2 && len <= 32) p->rrb.push_back(std::make_pair(todo[b].k0 + s0, len));
+                if (len > 32 && len < m && next) next->push_back({todo[b].pi, todo[b].k0 + s0, len});
+                s0 = e;
+            }
+        }
+        cleanup();
         return ZK_OK;
     }
 

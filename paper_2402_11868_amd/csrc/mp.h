@@ -55,6 +55,41 @@ MP_HD void two_prod(double a, double b, double &p, double &e)
     e = fma(a, b, -p);
 }
 
+// Three-level cascaded accumulator of products (binary64) x (double-double).
+// The leading product is split exactly (two_prod); its TwoSum error against
+// the running sum S goes to a second level C with TwoSum, and so do the
+// product error and the low product (rounded once, u^2 relative to the
+// term); the second level's TwoSum errors go to a third level D.  The error
+// of S + C + D is then a sum of per-term roundings of size u^2 |term| (about
+// sqrt(n) u^2 t for n terms of size t) instead of u^2 times the running
+// partial sums, which is what limits a plain double-double accumulation.
+struct Casc3 {
+    double S = 0.0, C = 0.0, D = 0.0;
+    MP_HD void add(double x, double yh, double yl)
+    {
+        const double p1 = x * yh;
+        const double e1 = fma(x, yh, -p1);
+        const double p2 = x * yl;
+        double s, c1, c, c2;
+        two_sum(S, p1, s, c1);
+        S = s;
+        two_sum(C, c1, c, c2);
+        C = c;
+        D += c2;
+        two_sum(C, e1 + p2, c, c2);
+        C = c;
+        D += c2;
+    }
+    // the sum as a normalised double-double
+    MP_HD void get(double &hi, double &lo) const
+    {
+        double h, l;
+        two_sum(S, C, h, l);
+        l += D;
+        fast_two_sum(h, l, hi, lo);
+    }
+};
+
 // ------------------------------------------------------------ types ------
 template <int L>
 struct mp {
@@ -227,6 +262,91 @@ MP_HD qd qd_renorm(double t[M])
     r.x[3] = e2;
     return r;
 }
+
+// Cascaded accumulator of quad-double products.  The partial products of
+// x*y are grouped by order (x_i y_j has size ~u^(i+j) |x y|): orders 0..3
+// are split exactly (two_prod), order 4 is summed plainly and orders >= 5
+// are dropped (below the quad-double rounding).  Level k collects the
+// order-k terms, the product errors of order k-1 and the TwoSum errors of
+// level k-1; levels 0..3 are accumulated with TwoSum, level 4 plainly.  About
+// 230 binary64 operations per product, against a full quad-double multiply
+// and add (each renormalising an expansion of 16 or 8 terms by sorting) that
+// cost several times more; the error is below u^4 of the terms.
+struct Casc4 {
+    double S0 = 0.0, S1 = 0.0, S2 = 0.0, S3 = 0.0, S4 = 0.0;
+    MP_HD void init(const qd &x)
+    {
+        S0 = x.x[0];
+        S1 = x.x[1];
+        S2 = x.x[2];
+        S3 = x.x[3];
+        S4 = 0.0;
+    }
+    MP_HD void put3(double v)
+    {
+        double s, e;
+        two_sum(S3, v, s, e);
+        S3 = s;
+        S4 += e;
+    }
+    MP_HD void put2(double v)
+    {
+        double s, e;
+        two_sum(S2, v, s, e);
+        S2 = s;
+        put3(e);
+    }
+    MP_HD void put1(double v)
+    {
+        double s, e;
+        two_sum(S1, v, s, e);
+        S1 = s;
+        put2(e);
+    }
+    // += sg * x * y  (sg = +1 or -1, applied exactly)
+    MP_HD void add(const qd &x, const qd &y, double sg)
+    {
+        const double x0 = sg * x.x[0], x1 = sg * x.x[1], x2 = sg * x.x[2], x3 = sg * x.x[3];
+        const double y0 = y.x[0], y1 = y.x[1], y2 = y.x[2], y3 = y.x[3];
+        double p00, e00, p01, e01, p10, e10, p02, e02, p11, e11, p20, e20;
+        double p03, e03, p12, e12, p21, e21, p30, e30;
+        two_prod(x0, y0, p00, e00);
+        two_prod(x0, y1, p01, e01);
+        two_prod(x1, y0, p10, e10);
+        two_prod(x0, y2, p02, e02);
+        two_prod(x1, y1, p11, e11);
+        two_prod(x2, y0, p20, e20);
+        two_prod(x0, y3, p03, e03);
+        two_prod(x1, y2, p12, e12);
+        two_prod(x2, y1, p21, e21);
+        two_prod(x3, y0, p30, e30);
+        double s, e;
+        two_sum(S0, p00, s, e);
+        S0 = s;
+        put1(e);
+        put1(e00);
+        put1(p01);
+        put1(p10);
+        put2(e01);
+        put2(e10);
+        put2(p02);
+        put2(p11);
+        put2(p20);
+        put3(e02);
+        put3(e11);
+        put3(e20);
+        put3(p03);
+        put3(p12);
+        put3(p21);
+        put3(p30);
+        S4 += ((e03 + e12) + (e21 + e30)) + ((x1 * y3 + x3 * y1) + x2 * y2);
+    }
+    MP_HD qd get() const
+    {
+        double t[5] = {S0, S1, S2, S3, S4};
+        return qd_renorm<5>(t);
+    }
+};
 
 MP_HD qd qd_add(const qd &a, const qd &b)
 {

@@ -565,46 +565,98 @@ __global__ void k_transpose(ProbDesc *probs)
     if (k0 + ty < n && i0 + tx < n) P.Z[(size_t)(k0 + ty) * n + i0 + tx] = t[tx][ty];
 }
 
-// Gram-Schmidt inside clusters of the binary64 spectrum: one work-group (256)
-// per eigenvalue index; only the group of a cluster's first index works.
-// Cluster: consecutive eigenvalues closer than gap_rel * ||T||.  Member j is
-// orthogonalised against members k..j-1 by classical Gram-Schmidt, twice
-// (coefficients of all earlier members computed by the four waves in
-// parallel), then normalised.
-__global__ void __launch_bounds__(256) k_tri_orth(ProbDesc *probs, double gap_rel)
+// Gram-Schmidt inside clusters of the binary64 spectrum.  Cluster:
+// consecutive eigenvalues closer than gap_rel * ||T||.  Members are handled
+// in blocks of kTriRB (block b = positions [kTriRB b, kTriRB (b+1)) inside the
+// cluster): each member of block b is projected against all members of the
+// earlier blocks by classical Gram-Schmidt, twice (one work-group per member,
+// every member of every cluster in parallel), then the block is
+// orthogonalised inside (classical Gram-Schmidt twice, member by member) and
+// normalised.  The same vectors as in-order Gram-Schmidt over the whole
+// cluster, with the long chains of the spectrum's tail spread over the chip.
+constexpr int kTriRB = 32;
+
+// plan: first index of the cluster of every eigenvalue index (kept in the
+// inverse-iteration scratch, free by now); grid (ceil(n/256), nprob)
+__global__ void k_tri_plan(ProbDesc *probs, double gap_rel)
+{
+    const ProbDesc &P = probs[blockIdx.y];
+    const int n = P.n;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double tn = fmax(fabs(P.w0[0]), fabs(P.w0[n - 1]));
+    const double thr = gap_rel * fmax(tn, 1e-300);
+    int cs = k;
+    while (cs > 0 && P.w0[cs] - P.w0[cs - 1] <= thr) cs--;
+    reinterpret_cast<int *>(P.tri)[k] = cs;
+}
+
+// block b > 0: member k (position in [kTriRB b, kTriRB (b+1))) against the
+// members of the earlier blocks; grid (n, nprob), block 256
+__global__ void __launch_bounds__(256) k_tri_proj(ProbDesc *probs, int b)
 {
     const ProbDesc &P = probs[blockIdx.y];
     const int n = P.n;
     const int k = blockIdx.x;
     if (k >= n) return;
+    const int cs = reinterpret_cast<const int *>(P.tri)[k];
+    const int pos = k - cs;
+    if (pos < kTriRB * b || pos >= kTriRB * (b + 1)) return;
+    const int m = kTriRB * b;   // earlier members: cs .. cs + m - 1
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const double tn = fmax(fabs(P.w0[0]), fabs(P.w0[n - 1]));
-    const double thr = gap_rel * fmax(tn, 1e-300);
-    if (k > 0 && P.w0[k] - P.w0[k - 1] <= thr) return;   // not a cluster start
+    __shared__ double coef[4096];
+    double *zk = P.Z + (size_t)k * n;
+    for (int pass = 0; pass < 2; pass++) {
+        for (int q = wid; q < m; q += 4) {
+            const double *zq = P.Z + (size_t)(cs + q) * n;
+            double s = 0.0;
+            for (int i = lane; i < n; i += 64) s += zq[i] * zk[i];
+            s = wave_sum(s);
+            if (lane == 0) coef[q] = s;
+        }
+        __syncthreads();
+        for (int i = tid; i < n; i += 256) {
+            double x = zk[i];
+            for (int q = 0; q < m; q++) x -= coef[q] * P.Z[(size_t)(cs + q) * n + i];
+            zk[i] = x;
+        }
+        __syncthreads();
+    }
+}
+
+// block b inside: the work-group of the block's first member orthogonalises
+// the block's members one after another and normalises them; grid (n, nprob)
+__global__ void __launch_bounds__(256) k_tri_intra(ProbDesc *probs, int b)
+{
+    const ProbDesc &P = probs[blockIdx.y];
+    const int n = P.n;
+    const int k = blockIdx.x;
+    if (k >= n) return;
+    const int *plan = reinterpret_cast<const int *>(P.tri);
+    const int cs = plan[k];
+    if (k - cs != kTriRB * b) return;
     int end = k + 1;
-    while (end < n && P.w0[end] - P.w0[end - 1] <= thr) end++;
-    __shared__ double coef[1024];
+    while (end < n && end < k + kTriRB && plan[end] == cs) end++;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    __shared__ double coef[kTriRB];
     __shared__ double red[4];
     for (int j = k; j < end; j++) {
         double *zj = P.Z + (size_t)j * n;
         for (int pass = 0; pass < 2 && j > k; pass++) {
-            for (int c0 = k; c0 < j; c0 += 1024) {
-                const int c1 = min(j, c0 + 1024);
-                for (int q = c0 + wid; q < c1; q += 4) {
-                    const double *zq = P.Z + (size_t)q * n;
-                    double s = 0.0;
-                    for (int i = lane; i < n; i += 64) s += zq[i] * zj[i];
-                    s = wave_sum(s);
-                    if (lane == 0) coef[q - c0] = s;
-                }
-                __syncthreads();
-                for (int i = tid; i < n; i += 256) {
-                    double x = zj[i];
-                    for (int q = c0; q < c1; q++) x -= coef[q - c0] * P.Z[(size_t)q * n + i];
-                    zj[i] = x;
-                }
-                __syncthreads();
+            for (int q = k + wid; q < j; q += 4) {
+                const double *zq = P.Z + (size_t)q * n;
+                double s = 0.0;
+                for (int i = lane; i < n; i += 64) s += zq[i] * zj[i];
+                s = wave_sum(s);
+                if (lane == 0) coef[q - k] = s;
             }
+            __syncthreads();
+            for (int i = tid; i < n; i += 256) {
+                double x = zj[i];
+                for (int q = k; q < j; q++) x -= coef[q - k] * P.Z[(size_t)q * n + i];
+                zj[i] = x;
+            }
+            __syncthreads();
         }
         double s = 0.0;
         for (int i = tid; i < n; i += 256) s += zj[i] * zj[i];
@@ -786,7 +838,11 @@ int stage1_run(const Stage1Batch &B, hipStream_t st)
     hipLaunchKernelGGL(k_bisect, dim3(cdiv(n, 128), np), dim3(128), 0, st, pd);
     hipLaunchKernelGGL(k_invit, dim3(cdiv(n, 64), np), dim3(64), 0, st, pd);
     hipLaunchKernelGGL(k_transpose, dim3(cdiv(n, 16), cdiv(n, 16), np), dim3(16, 16), 0, st, pd);
-    hipLaunchKernelGGL(k_tri_orth, dim3(n, np), dim3(256), 0, st, pd, B.tri_gap_rel);
+    hipLaunchKernelGGL(k_tri_plan, dim3(cdiv(n, 256), np), dim3(256), 0, st, pd, B.tri_gap_rel);
+    for (int b = 0; b < cdiv(n, kTriRB); b++) {
+        if (b > 0) hipLaunchKernelGGL(k_tri_proj, dim3(n, np), dim3(256), 0, st, pd, b);
+        hipLaunchKernelGGL(k_tri_intra, dim3(n, np), dim3(256), 0, st, pd, b);
+    }
     if (B.timer) B.timer->end(idt, st);
     // ---- back-transformation
     const int idb = B.timer ? B.timer->begin(KC_BACKT, 8.0 * (double)n * n * n * np, st) : -1;

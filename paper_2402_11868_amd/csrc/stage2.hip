@@ -128,6 +128,35 @@ struct CAcc<2> {
     __device__ cmp<2> get() const { return {acc_dd_final(Sr, Cr), acc_dd_final(Si, Ci)}; }
 };
 
+// quad-double form: four-level cascaded sums (Casc4 in mp.h), renormalised
+// once when the value is read
+template <>
+struct CAcc<4> {
+    Casc4 re, im;
+    __device__ void init(const cmp<4> &x)
+    {
+        re.init(x.re);
+        im.init(x.im);
+    }
+    __device__ void add_mulc(const cmp<4> &a, const cmp<4> &b)
+    {
+        // re += ar br + ai bi ; im += ar bi - ai br
+        re.add(a.re, b.re, 1.0);
+        re.add(a.im, b.im, 1.0);
+        im.add(a.re, b.im, 1.0);
+        im.add(a.im, b.re, -1.0);
+    }
+    __device__ void sub_mul(const cmp<4> &a, const cmp<4> &b)
+    {
+        // re -= ar br - ai bi ; im -= ar bi + ai br
+        re.add(a.re, b.re, -1.0);
+        re.add(a.im, b.im, 1.0);
+        im.add(a.re, b.im, -1.0);
+        im.add(a.im, b.re, -1.0);
+    }
+    __device__ cmp<4> get() const { return cmp<4>{re.get(), im.get()}; }
+};
+
 // ================================================================ init ====
 // v_k <- binary64 eigenvector (exact), sigma_k <- binary64 eigenvalue.
 // grid (npairs), block 256.
@@ -173,6 +202,28 @@ __device__ void normalise_vec(double *vec, size_t nn, int n, int k, mp<L> *red)
 }
 
 // ================================================================== RQ ====
+// The double-double residual is accumulated with Casc3 (mp.h): the
+// residual of an eigenvector of the largest eigenvalues (terms of size
+// ||H|| / sqrt(n) cancelling down to 1e-32 ||H||) is then not limited by the
+// ~sqrt(n) * 3 u^2 ||H|| rounding of plain double-double sums (~1e-30 at
+// n = 1024).
+// re/im of sum_j H(i, j) v_j (all input limbs) into two cascaded accumulators
+__device__ __forceinline__ void hv_row_casc(const RqiProb &P, const double *vec, size_t nn, int n, int k, int i, Casc3 &re,
+                                            Casc3 &im)
+{
+    for (int j = 0; j < n; j++) {
+        const cmp<2> v = ld_cmp<2>(vec, nn, (size_t)k * n + j);
+        const size_t o = (size_t)j * n + i;
+        for (int l = 0; l < P.limbs_in; l++) {
+            const double hr = P.hf[(2 * l) * nn + o], hi = P.hf[(2 * l + 1) * nn + o];
+            re.add(hr, v.re.x[0], v.re.x[1]);
+            re.add(-hi, v.im.x[0], v.im.x[1]);
+            im.add(hr, v.im.x[0], v.im.x[1]);
+            im.add(hi, v.re.x[0], v.re.x[1]);
+        }
+    }
+}
+
 // One work-group per active pair: y = H v, sigma = Re(v^H y), r = y - sigma v;
 // convergence, stagnation and iteration-limit decisions.
 template <int L>
@@ -185,23 +236,63 @@ __global__ void __launch_bounds__(256) k_s2_rq(PairDesc *pairs, RqiProb *probs, 
     __shared__ mp<L> red[16];
     __shared__ double redd[16];
     const double *vec = P.vec;
-    // pass 1: sigma = sum_i Re(conj(v_i) y_i)
-    mp<L> sacc = mp_zero<L>();
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        cmp<L> y = c_zero<L>();
-        for (int j = 0; j < n; j++) y = c_add(y, c_mul(ld_h<L>(P, i, j), ld_cmp<L>(vec, nn, (size_t)k * n + j)));
-        const cmp<L> vi = ld_cmp<L>(vec, nn, (size_t)k * n + i);
-        sacc = add(sacc, add(mul(vi.re, y.re), mul(vi.im, y.im)));
-    }
-    const mp<L> sigma = block_sum_mp<L>(sacc, red);
-    // pass 2: ||y - sigma v||^2 (recomputes y to keep registers bounded)
+    mp<L> sigma;
     double r2 = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        cmp<L> y = c_zero<L>();
-        for (int j = 0; j < n; j++) y = c_add(y, c_mul(ld_h<L>(P, i, j), ld_cmp<L>(vec, nn, (size_t)k * n + j)));
-        const cmp<L> vi = ld_cmp<L>(vec, nn, (size_t)k * n + i);
-        const cmp<L> r = c_sub(y, c_scale(vi, sigma));
-        r2 += r.re.x[0] * r.re.x[0] + r.im.x[0] * r.im.x[0];
+    if constexpr (L == 2) {
+        // pass 1: sigma = sum_i Re(conj(v_i) y_i), y_i from the cascaded sums
+        mp<2> sacc = mp_zero<2>();
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            Casc3 yr, yi;
+            hv_row_casc(P, vec, nn, n, k, i, yr, yi);
+            const cmp<2> vi = ld_cmp<2>(vec, nn, (size_t)k * n + i);
+            dd a, b;
+            yr.get(a.x[0], a.x[1]);
+            yi.get(b.x[0], b.x[1]);
+            sacc = add(sacc, add(mul(vi.re, a), mul(vi.im, b)));
+        }
+        sigma = block_sum_mp<2>(sacc, red);
+        // pass 2: r_i = sum_j H(i, j) v_j - sigma v_i in one cascaded sum per component
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            Casc3 rr, ri;
+            hv_row_casc(P, vec, nn, n, k, i, rr, ri);
+            const cmp<2> vi = ld_cmp<2>(vec, nn, (size_t)k * n + i);
+            rr.add(-sigma.x[0], vi.re.x[0], vi.re.x[1]);
+            rr.add(-sigma.x[1], vi.re.x[0], vi.re.x[1]);
+            ri.add(-sigma.x[0], vi.im.x[0], vi.im.x[1]);
+            ri.add(-sigma.x[1], vi.im.x[0], vi.im.x[1]);
+            double a, b, lo;
+            rr.get(a, lo);
+            ri.get(b, lo);
+            r2 += a * a + b * b;
+        }
+    } else {
+        // pass 1: sigma = sum_i Re(conj(v_i) y_i)
+        mp<L> sacc = mp_zero<L>();
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            CAcc<L> ya;
+            ya.init(c_zero<L>());
+            for (int j = 0; j < n; j++) {
+                const cmp<L> h = ld_h<L>(P, i, j);
+                ya.sub_mul(cmp<L>{mp_neg<L>(h.re), mp_neg<L>(h.im)}, ld_cmp<L>(vec, nn, (size_t)k * n + j));
+            }
+            const cmp<L> y = ya.get();
+            const cmp<L> vi = ld_cmp<L>(vec, nn, (size_t)k * n + i);
+            sacc = add(sacc, add(mul(vi.re, y.re), mul(vi.im, y.im)));
+        }
+        sigma = block_sum_mp<L>(sacc, red);
+        // pass 2: ||y - sigma v||^2 (recomputes y to keep registers bounded)
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            // r_i = sum_j H(i, j) v_j - sigma v_i in one accumulation
+            CAcc<L> ra;
+            ra.init(c_zero<L>());
+            for (int j = 0; j < n; j++) {
+                const cmp<L> h = ld_h<L>(P, i, j);
+                ra.sub_mul(cmp<L>{mp_neg<L>(h.re), mp_neg<L>(h.im)}, ld_cmp<L>(vec, nn, (size_t)k * n + j));
+            }
+            ra.sub_mul(cmp<L>{sigma, mp_zero<L>()}, ld_cmp<L>(vec, nn, (size_t)k * n + i));
+            const cmp<L> r = ra.get();
+            r2 += r.re.x[0] * r.re.x[0] + r.im.x[0] * r.im.x[0];
+        }
     }
     r2 = block_sum(r2, redd);
     if (threadIdx.x == 0) {
@@ -337,7 +428,10 @@ __global__ void __launch_bounds__(256) k_s2_lu_panel(Stage2Batch B, int k0, int 
             st_cmp<L>(M, plane, (size_t)c * ldm + r, l);
             for (int q = 1; q < nbw - j; q++) {
                 const size_t o = (size_t)(c + q) * ldm + r;
-                st_cmp<L>(M, plane, o, c_sub(ld_cmp<L>(M, plane, o), c_mul(l, s_row[q])));
+                CAcc<L> x;
+                x.init(ld_cmp<L>(M, plane, o));
+                x.sub_mul(l, s_row[q]);
+                st_cmp<L>(M, plane, o, x.get());
             }
         }
         __syncthreads();
@@ -408,7 +502,9 @@ __global__ void __launch_bounds__(256) k_s2_lu_trsm(Stage2Batch B, int k0, int n
 // =========================================================== LU update ====
 // A22 -= L21 U12 for rows [r0, n), columns [r0, n] (r0 = k0 + nbw).
 // dd: 64x64 tile per work-group of 256, 4x4 outputs per thread (rows
-// ty + 16a, columns tx + 16b), operands staged in LDS in chunks of KC.
+// tx + 16a, columns ty + 16b, so that the 16 lanes of a row group read and
+// write 16 consecutive rows of a column), operands staged in LDS in chunks
+// of KC (U12 staged with consecutive lanes along k, its unit-stride index).
 constexpr int KC = 8;
 
 __global__ void __launch_bounds__(256) k_s2_lu_update_dd(Stage2Batch B, int k0, int nbw)
@@ -431,7 +527,7 @@ __global__ void __launch_bounds__(256) k_s2_lu_update_dd(Stage2Batch B, int k0, 
     double S[4][4][2], C[4][4][2];   // [a][b][re/im]
     for (int a = 0; a < 4; a++)
         for (int b = 0; b < 4; b++) {
-            const int i = i0 + ty + 16 * a, j = j0 + tx + 16 * b;
+            const int i = i0 + tx + 16 * a, j = j0 + ty + 16 * b;
             double rh = 0.0, rl = 0.0, ih = 0.0, il = 0.0;
             if (i < n && j <= n) {
                 const size_t o = (size_t)j * ldm + i;
@@ -444,18 +540,17 @@ __global__ void __launch_bounds__(256) k_s2_lu_update_dd(Stage2Batch B, int k0, 
         __syncthreads();
         // stage L21[i0:i0+64, k0+kc : +KC] and U12[k0+kc : +KC, j0:j0+64]
         for (int q = tid; q < KC * 64; q += 256) {
-            const int kk = q >> 6, ii = q & 63;
-            const int kcol = k0 + kc + kk;
-            const int gi = i0 + ii;
-            for (int pl = 0; pl < 4; pl++) {
-                double lv = 0.0, uv = 0.0;
-                if (kc + kk < nbw) {
-                    if (gi < n) lv = M[pl * plane + (size_t)kcol * ldm + gi];
-                    const int gj = j0 + ii;
-                    if (gj <= n) uv = M[pl * plane + (size_t)gj * ldm + kcol];
-                }
-                sL[pl][kk][ii] = lv;
-                sU[pl][kk][ii] = uv;
+            {
+                const int kk = q >> 6, ii = q & 63;
+                const int kcol = k0 + kc + kk, gi = i0 + ii;
+                for (int pl = 0; pl < 4; pl++)
+                    sL[pl][kk][ii] = (kc + kk < nbw && gi < n) ? M[pl * plane + (size_t)kcol * ldm + gi] : 0.0;
+            }
+            {
+                const int kk = q & (KC - 1), jj = q / KC;
+                const int kcol = k0 + kc + kk, gj = j0 + jj;
+                for (int pl = 0; pl < 4; pl++)
+                    sU[pl][kk][jj] = (kc + kk < nbw && gj <= n) ? M[pl * plane + (size_t)gj * ldm + kcol] : 0.0;
             }
         }
         __syncthreads();
@@ -465,12 +560,12 @@ __global__ void __launch_bounds__(256) k_s2_lu_update_dd(Stage2Batch B, int k0, 
             double urh[4], url[4], uih[4], uil[4];
             for (int a = 0; a < 4; a++) {
                 // negated L: the update subtracts
-                lrh[a] = -sL[0][kk][ty + 16 * a]; lrl[a] = -sL[1][kk][ty + 16 * a];
-                lih[a] = sL[2][kk][ty + 16 * a];  lil[a] = sL[3][kk][ty + 16 * a];
+                lrh[a] = -sL[0][kk][tx + 16 * a]; lrl[a] = -sL[1][kk][tx + 16 * a];
+                lih[a] = sL[2][kk][tx + 16 * a];  lil[a] = sL[3][kk][tx + 16 * a];
             }
             for (int b = 0; b < 4; b++) {
-                urh[b] = sU[0][kk][tx + 16 * b]; url[b] = sU[1][kk][tx + 16 * b];
-                uih[b] = sU[2][kk][tx + 16 * b]; uil[b] = sU[3][kk][tx + 16 * b];
+                urh[b] = sU[0][kk][ty + 16 * b]; url[b] = sU[1][kk][ty + 16 * b];
+                uih[b] = sU[2][kk][ty + 16 * b]; uil[b] = sU[3][kk][ty + 16 * b];
             }
             for (int a = 0; a < 4; a++)
                 for (int b = 0; b < 4; b++) {
@@ -485,7 +580,7 @@ __global__ void __launch_bounds__(256) k_s2_lu_update_dd(Stage2Batch B, int k0, 
     }
     for (int a = 0; a < 4; a++)
         for (int b = 0; b < 4; b++) {
-            const int i = i0 + ty + 16 * a, j = j0 + tx + 16 * b;
+            const int i = i0 + tx + 16 * a, j = j0 + ty + 16 * b;
             if (i < n && j <= n) {
                 const size_t o = (size_t)j * ldm + i;
                 const dd re = acc_dd_final(S[a][b][0], C[a][b][0]);
@@ -514,35 +609,37 @@ __global__ void __launch_bounds__(256) k_s2_lu_update_gen(Stage2Batch B, int k0,
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
     __shared__ cmp<L> sL[KC][32];
     __shared__ cmp<L> sU[KC][32];
-    cmp<L> acc[2][2];
+    // outputs (rows tx + 16a, columns ty + 16b): 16 lanes touch 16 consecutive rows
+    CAcc<L> acc[2][2];
     for (int a = 0; a < 2; a++)
         for (int b = 0; b < 2; b++) {
-            const int i = i0 + ty + 16 * a, j = j0 + tx + 16 * b;
-            acc[a][b] = (i < n && j <= n) ? ld_cmp<L>(M, plane, (size_t)j * ldm + i) : c_zero<L>();
+            const int i = i0 + tx + 16 * a, j = j0 + ty + 16 * b;
+            acc[a][b].init((i < n && j <= n) ? ld_cmp<L>(M, plane, (size_t)j * ldm + i) : c_zero<L>());
         }
     for (int kc = 0; kc < nbw; kc += KC) {
         __syncthreads();
         for (int q = tid; q < KC * 32; q += 256) {
-            const int kk = q >> 5, ii = q & 31;
-            const int kcol = k0 + kc + kk;
-            cmp<L> lv = c_zero<L>(), uv = c_zero<L>();
-            if (kc + kk < nbw) {
-                if (i0 + ii < n) lv = ld_cmp<L>(M, plane, (size_t)kcol * ldm + i0 + ii);
-                if (j0 + ii <= n) uv = ld_cmp<L>(M, plane, (size_t)(j0 + ii) * ldm + kcol);
+            {
+                const int kk = q >> 5, ii = q & 31;
+                const int kcol = k0 + kc + kk;
+                sL[kk][ii] = (kc + kk < nbw && i0 + ii < n) ? ld_cmp<L>(M, plane, (size_t)kcol * ldm + i0 + ii) : c_zero<L>();
             }
-            sL[kk][ii] = lv;
-            sU[kk][ii] = uv;
+            {
+                const int kk = q & (KC - 1), jj = q / KC;
+                const int kcol = k0 + kc + kk;
+                sU[kk][jj] = (kc + kk < nbw && j0 + jj <= n) ? ld_cmp<L>(M, plane, (size_t)(j0 + jj) * ldm + kcol) : c_zero<L>();
+            }
         }
         __syncthreads();
         const int kmax = min(KC, nbw - kc);
         for (int kk = 0; kk < kmax; kk++)
             for (int a = 0; a < 2; a++)
-                for (int b = 0; b < 2; b++) acc[a][b] = c_sub(acc[a][b], c_mul(sL[kk][ty + 16 * a], sU[kk][tx + 16 * b]));
+                for (int b = 0; b < 2; b++) acc[a][b].sub_mul(sL[kk][tx + 16 * a], sU[kk][ty + 16 * b]);
     }
     for (int a = 0; a < 2; a++)
         for (int b = 0; b < 2; b++) {
-            const int i = i0 + ty + 16 * a, j = j0 + tx + 16 * b;
-            if (i < n && j <= n) st_cmp<L>(M, plane, (size_t)j * ldm + i, acc[a][b]);
+            const int i = i0 + tx + 16 * a, j = j0 + ty + 16 * b;
+            if (i < n && j <= n) st_cmp<L>(M, plane, (size_t)j * ldm + i, acc[a][b].get());
         }
 }
 
@@ -573,8 +670,10 @@ __global__ void __launch_bounds__(256) k_s2_backsolve(Stage2Batch B)
         __syncthreads();
         const cmp<L> w = s_w;
         for (int r = threadIdx.x; r < i; r += 256) {
-            const cmp<L> u = ld_cmp<L>(M, plane, (size_t)i * ldm + r);
-            st_cmp<L>(M, plane, ycol + r, c_sub(ld_cmp<L>(M, plane, ycol + r), c_mul(u, w)));
+            CAcc<L> x;
+            x.init(ld_cmp<L>(M, plane, ycol + r));
+            x.sub_mul(ld_cmp<L>(M, plane, (size_t)i * ldm + r), w);
+            st_cmp<L>(M, plane, ycol + r, x.get());
         }
         __syncthreads();
     }

@@ -31,6 +31,23 @@ void t_qd_sqrt(const double *a, double *r)
     qd z = qd_sqrt(x);
     for (int i = 0; i < 4; i++) r[i] = z.x[i];
 }
+void t_casc3(int n, const double *x, const double *yh, const double *yl, double *r)
+{
+    Casc3 a;
+    for (int i = 0; i < n; i++) a.add(x[i], yh[i], yl[i]);
+    a.get(r[0], r[1]);
+}
+void t_casc4(int n, const double *x, const double *y, const double *sg, double *r)
+{
+    Casc4 a;
+    for (int i = 0; i < n; i++) {
+        qd xx, yy;
+        for (int l = 0; l < 4; l++) { xx.x[l] = x[4 * i + l]; yy.x[l] = y[4 * i + l]; }
+        a.add(xx, yy, sg[i]);
+    }
+    qd z = a.get();
+    for (int l = 0; l < 4; l++) r[l] = z.x[l];
+}
 void t_qd_renorm16(const double *t, double *r)
 {
     double w[16];

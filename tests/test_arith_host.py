@@ -29,6 +29,8 @@ def lib():
         getattr(l, name).argtypes = [P, P, P]
     for name in ("t_dd_sqrt", "t_qd_sqrt", "t_qd_renorm16"):
         getattr(l, name).argtypes = [P, P]
+    l.t_casc3.argtypes = [ctypes.c_int, P, P, P, P]
+    l.t_casc4.argtypes = [ctypes.c_int, P, P, P, P]
     l.t_two_sum.argtypes = [D, D, P, P]
     l.t_two_prod.argtypes = [D, D, P, P]
     return l
@@ -133,3 +135,71 @@ def test_renorm_many_terms(lib):
         if exact == 0:
             continue
         assert abs(F(r) - exact) / abs(exact) <= 8 * U ** 4
+
+
+def test_cascaded_accumulator_cancelling_sum(lib):
+    """Casc3: a long sum of binary64 x double-double products that cancels to
+    ~1e-31 of its terms (the residual of an eigenvector of the largest
+    eigenvalue) is accurate to ~u^3 n max|term|, far below the ~1e-30 that
+    double-double accumulation reaches at n = 1024."""
+    rng = np.random.Generator(np.random.PCG64(11))
+    n = 1024
+    x = rng.standard_normal(n) / 32
+    y = [split(Fraction(float(a)) + Fraction(float(b)) * U, 2) for a, b in
+         zip(rng.standard_normal(n) / 32, rng.standard_normal(n) / 32)]
+    yh = np.array([t[0] for t in y])
+    yl = np.array([t[1] for t in y])
+    exact = sum((Fraction(float(a)) * (Fraction(float(b)) + Fraction(float(c))) for a, b, c in zip(x, yh, yl)),
+                Fraction(0))
+    # the last term cancels the sum down to about 1e-31 of the terms
+    target = exact - Fraction(1, 10 ** 34)
+    last = split(-target, 2)
+    xs = np.r_[x, 1.0]
+    yhs = np.r_[yh, last[0]]
+    yls = np.r_[yl, last[1]]
+    total = exact + Fraction(float(last[0])) + Fraction(float(last[1]))
+    r = np.zeros(2)
+    lib.t_casc3(n + 1, xs.ctypes.data, yhs.ctypes.data, yls.ctypes.data, r.ctypes.data)
+    err = abs(F(r) - total)
+    mean_term = Fraction(float(np.mean(np.abs(x * yh))))
+    # per-term roundings of size u^2 |term| add up like a random walk: allow
+    # 16 sqrt(n) u^2 mean|term| (~4e-33 here).  A double-double accumulation
+    # of the same terms rounds at u^2 times the running partial sums
+    # (~3e-32 here), and dropping the product error or the low product
+    # leaves errors of u |term|.
+    assert abs(total) < Fraction(1, 10 ** 33)
+    assert err <= 16 * 32 * U * U * mean_term, float(err)
+
+
+@pytest.mark.parametrize("cancel", [False, True])
+def test_cascaded_qd_accumulator(lib, cancel):
+    """Casc4: sums of +-x*y over quad-double operands (wide exponent spread,
+    optionally cancelling to 1e-50 of the terms) within a few u^4 per term."""
+    rng = np.random.Generator(np.random.PCG64(12 + cancel))
+    n = 64
+    xs = [rand_mp(rng, 4, spread=8) for _ in range(n)]
+    ys = [rand_mp(rng, 4, spread=8) for _ in range(n)]
+    sg = rng.choice([-1.0, 1.0], n)
+    exact = sum((Fraction(int(s)) * F(x) * F(y) for s, x, y in zip(sg, xs, ys)), Fraction(0))
+    if cancel:
+        # one more term cancels the sum down to ~1e-50 of the terms
+        last = split(-(exact - exact * Fraction(1, 10 ** 50)), 4)
+        xs.append(last)
+        ys.append(np.array([1.0, 0.0, 0.0, 0.0]))
+        sg = np.r_[sg, 1.0]
+        exact = exact * Fraction(1, 10 ** 50) + (F(last) + (exact - exact * Fraction(1, 10 ** 50)))
+    m = len(xs)
+    X = np.ascontiguousarray(np.concatenate(xs))
+    Y = np.ascontiguousarray(np.concatenate(ys))
+    S = np.ascontiguousarray(sg)
+    r = np.zeros(4)
+    lib.t_casc4(m, X.ctypes.data, Y.ctypes.data, S.ctypes.data, r.ctypes.data)
+    mag = sum((abs(F(x) * F(y)) for x, y in zip(xs, ys)), Fraction(0))
+    err = abs(F(r) - exact)
+    # levels 0..3 are exact; the plain last level (order-4 products, order-3
+    # product errors, level-3 TwoSum errors) and the dropped order >= 5
+    # products leave about u^5 per term: allow u^4 of the terms' total size.
+    # A dropped order-3 or order-4 partial product leaves errors of u^3 or u^4
+    # per term (the first version of this accumulator stopped at order 3 and
+    # measured 10-100 u^4 here).
+    assert err <= U ** 4 * mag / 4, float(err / mag)

@@ -198,6 +198,6 @@ def test_qd_2048_refine_largest(zk):
     for j in range(k):
         s2 = _angle_sq_to_exact(V, j, E[:, j])
         assert s2 <= Fraction(1, 10 ** 116), f"pair {j}: sin^2(angle) {float(s2):.3e}"
-    r, _ = oracle.residuals(h.planes, w, V[:, :, :4])
+    r, _ = oracle.residuals(h.planes, w[:, :4], V[:, :, :4])
     assert r.max() <= QD_TOL * hn
     log(f"qd 2048: max residual (4 sampled) {r.max() / hn:.3e}, iterations {res.iters}")
