@@ -111,6 +111,36 @@ def cpu_baseline(seconds_hint=20.0):
                       f"{dt:.1f} s, {rate_n:.2f} eigenpairs/s at n={n}, {r.sweeps} sweeps; value scaled by (n/1024)^2"}
 
 
+def batch_leg(Z, ctx, torch, tol=1e-30):
+    """The batch workload: 256 independent 128x128 matrices (spectra 10^(-k/8)
+    down to 1e-16 with four exact 2-fold degeneracies each) in one zk_heev_dd
+    call; eigenpairs/s of pairs within the device residual gate, and the
+    binary64 stage's MFMA rate over the batched trailing updates."""
+    import workloads as W
+    mats = [torch.from_numpy(W.workload(2, index=i)["A"]).cuda() for i in range(256)]
+    Z.heev(ctx, [[m] for m in mats], limbs_out=2)   # warm-up
+    torch.cuda.synchronize()
+    ctx.prof(True)
+    ctx.prof_reset()
+    st = {}
+    t0 = time.perf_counter()
+    res = Z.heev(ctx, [[m] for m in mats], limbs_out=2, stats=st)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    p = ctx.prof_read()
+    ctx.prof(False)
+    ok = sum(1 for r in res for x in r.info if x["resid"] <= tol)
+    ms_h, _, fl_h = p["her2k"]
+    ms_u, _, wk_u = p["lu_update"]
+    return {"workload": "256 x 128x128, spectra 10^(-k/8) to 1e-16, four 2-fold degeneracies each, dd to 1e-30",
+            "ms": dt * 1e3, "pairs": 256 * 128, "passing_pairs": ok, "eigenpairs_per_s": ok / dt,
+            "iters_hist": st.get("iters_hist"),
+            "her2k_tflops": (fl_h / (ms_h / 1e3) / 1e12) if ms_h > 0 else None,
+            "her2k_frac_of_fp64_mfma": (fl_h / (ms_h / 1e3) / 1e12 / FP64_MFMA_TFLOPS) if ms_h > 0 else None,
+            "lu_update_frac_of_alu": (wk_u / (ms_u / 1e3) / (FP64_VALU_LANE_OPS / CPLX_DD_FMA_INSTR)) if ms_u > 0 else None,
+            "phase_ms": {k: round(v[0], 3) for k, v in p.items()}}
+
+
 def _pct(x, q):
     import numpy as np
     return float(np.percentile(np.asarray(x), q)) * 1e3 if len(x) else None
@@ -204,6 +234,7 @@ def main():
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32-leg", action="store_true", help="skip the FP32-MFMA-start run")
+    ap.add_argument("--no-batch-leg", action="store_true", help="skip the 256 x 128^2 batch run")
     ap.add_argument("--serving-requests", type=int, default=200,
                     help="requests of the serving-stream leg (0 = skip the leg)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -334,6 +365,9 @@ def main():
                         "hemv_gbs": (by_v / (ms_v / 1e3) / 1e9) if ms_v > 0 else None},
         "fp32_mfma_start": fp32_leg,
     }
+    if not args.no_batch_leg:
+        log("batch of 256 x 128^2")
+        out["batch"] = batch_leg(Z, ctx, torch)
     if args.serving_requests > 0:
         log("serving stream")
         out["serving"] = serving_leg(Z, ctx, torch, count=args.serving_requests)

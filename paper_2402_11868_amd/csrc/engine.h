@@ -56,6 +56,7 @@ struct S2Prob {
     std::vector<int> heads;        // local index of every cluster's first pair
     std::vector<std::pair<int, int>> rrb;   // Rayleigh-Ritz blocks (first pair, members), 2..32 members
     std::vector<double> w0h;       // binary64 eigenvalues (ascending) the clusters were planned on
+    std::vector<double> ritz0;     // shift for the first solve from the deepest projected level (NaN: none)
     std::vector<int> redo;         // pairs sent back for more iterations after the re-orthogonalisation
     int polish = 0;                // number of such passes so far
     void *vecbuf = nullptr;
@@ -141,9 +142,11 @@ class Stage2Engine {
             std::vector<PrrBlock> whole;
             for (size_t pi = 0; pi < batch.size(); pi++)
                 if (batch[pi]->opts.init_fp32 && batch[pi]->npairs >= 2) whole.push_back({(int)pi, 0, batch[pi]->npairs});
-            if ((rc = prr_level(batch, whole, true, nullptr)) != ZK_OK) return rc;
-            for (S2Prob *p : batch) {
-                if (!p->opts.init_fp32) continue;
+            std::vector<std::vector<double>> rz;
+            if ((rc = prr_project(batch, whole, rz)) != ZK_OK) return rc;
+            for (size_t b = 0; b < whole.size(); b++) {
+                S2Prob *p = batch[whole[b].pi];
+                p->w0h = rz[b];   // the Ritz values replace the binary64 eigenvalues
                 plan_clusters(p, p->w0h, 0);
                 for (auto &q : p->pairs) q.status = 0;
             }
@@ -157,6 +160,7 @@ class Stage2Engine {
         std::vector<int> all(total_pairs);
         for (int g = 0; g < total_pairs; g++) all[g] = g;
         if ((rc = run_rq(all, 0)) != ZK_OK) return rc;
+        if (projected && (rc = first_shifts(batch)) != ZK_OK) return rc;
         if ((rc = download(batch)) != ZK_OK) return rc;
         if (std::getenv("ZK_TRACE") && std::atoi(std::getenv("ZK_TRACE")) >= 2) dump(batch, "add");
         for (S2Prob *p : batch) live.push_back(p);
@@ -181,25 +185,7 @@ class Stage2Engine {
                 }
         if (stats) stats->active_per_iter.push_back(nact);
         if (nact > 0) {
-            int max_n = 0;
-            for (auto &kv : by_n) max_n = std::max(max_n, kv.first);
-            if ((rc = ensure_slots(max_n, nact)) != ZK_OK) return rc;
-            Stage2Batch B = batch_base();
-            for (auto &kv : by_n) {
-                const int n = kv.first;
-                const std::vector<int> &lst = kv.second;
-                for (size_t c0 = 0; c0 < lst.size(); c0 += (size_t)S) {
-                    const int cnt = (int)std::min<size_t>((size_t)S, lst.size() - c0);
-                    HIPCHK_(hipMemcpyAsync(d_active, lst.data() + c0, 4 * (size_t)cnt, hipMemcpyHostToDevice, st));
-                    B.n = n;
-                    B.count = cnt;
-                    B.ldm = s2_lu_ldm(n);
-                    B.lu_stride = s2_lu_slot_doubles(n, L);
-                    B.piv_stride = (size_t)n;
-                    if (stage2_solve<L>(B, st)) return ctx->fail(ZK_EDEVICE, "solve launch failed");
-                    HIPCHK_(hipStreamSynchronize(st));
-                }
-            }
+            if ((rc = solve_pairs(by_n, nact)) != ZK_OK) return rc;
             if ((rc = run_gs(live, false)) != ZK_OK) return rc;
             if ((rc = run_rr(live, false)) != ZK_OK) return rc;
             std::vector<int> all;
@@ -215,7 +201,9 @@ class Stage2Engine {
 
     int rounds = 0;
     static constexpr int kPolishPasses = 2;
-    static constexpr int kPrrLevels = 4;
+    static constexpr int kPrrLevels = 40;
+    static constexpr double kPrrDeep = 1e-3;
+    static constexpr double kPurify = 1e-18;
     static constexpr double kReorthWindow = 0.1;
 
   private:
@@ -471,6 +459,80 @@ class Stage2Engine {
         return ZK_OK;
     }
 
+    struct PrrBlock {
+        int pi, k0, size;
+    };
+
+    // shifted solves of the given pairs (pair-table indices grouped by order)
+    int solve_pairs(const std::map<int, std::vector<int>> &by_n, int nact)
+    {
+        int max_n = 0;
+        for (auto &kv : by_n) max_n = std::max(max_n, kv.first);
+        int rc = ensure_slots(max_n, nact);
+        if (rc != ZK_OK) return rc;
+        Stage2Batch B = batch_base();
+        for (auto &kv : by_n) {
+            const int n = kv.first;
+            const std::vector<int> &lst = kv.second;
+            for (size_t c0 = 0; c0 < lst.size(); c0 += (size_t)S) {
+                const int cnt = (int)std::min<size_t>((size_t)S, lst.size() - c0);
+                HIPCHK_(hipMemcpyAsync(d_active, lst.data() + c0, 4 * (size_t)cnt, hipMemcpyHostToDevice, st));
+                B.n = n;
+                B.count = cnt;
+                B.ldm = s2_lu_ldm(n);
+                B.lu_stride = s2_lu_slot_doubles(n, L);
+                B.piv_stride = (size_t)n;
+                if (stage2_solve<L>(B, st)) return ctx->fail(ZK_EDEVICE, "solve launch failed");
+                HIPCHK_(hipStreamSynchronize(st));
+            }
+        }
+        return ZK_OK;
+    }
+
+    // One inverse-iteration step with shift zero on the given blocks (every
+    // member solves H w = v), then Gram-Schmidt inside their clusters in
+    // index order (the other matrices' pairs frozen).  Components along
+    // eigenvalues outside a chain shrink against the chain's tail by the
+    // ratio of the eigenvalues, which removes the binary64 stage's pollution
+    // of the tail subspace.
+    int purify(const std::vector<S2Prob *> &set, const std::vector<PrrBlock> &blocks)
+    {
+        std::map<int, std::vector<int>> by_n;
+        std::vector<std::vector<char>> mark(set.size());
+        int cnt = 0;
+        for (const auto &b : blocks) {
+            S2Prob *p = set[b.pi];
+            if (mark[b.pi].empty()) mark[b.pi].assign(p->npairs, 0);
+            for (int q = 0; q < b.size; q++) {
+                mark[b.pi][b.k0 + q] = 1;
+                by_n[p->rp.n].push_back(base[b.pi] + b.k0 + q);
+                cnt++;
+            }
+        }
+        for (size_t pi = 0; pi < set.size(); pi++) {
+            if (mark[pi].empty()) continue;
+            S2Prob *p = set[pi];
+            const int n = p->rp.n;
+            std::vector<double> sig((size_t)L * n);
+            HIPCHK_(hipMemcpyAsync(sig.data(), p->rp.sigma, 8 * sig.size(), hipMemcpyDeviceToHost, st));
+            HIPCHK_(hipStreamSynchronize(st));
+            for (int k = 0; k < p->npairs; k++)
+                if (mark[pi][k])
+                    for (int l = 0; l < L; l++) sig[(size_t)l * n + k] = 0.0;
+            HIPCHK_(hipMemcpyAsync(p->rp.sigma, sig.data(), 8 * sig.size(), hipMemcpyHostToDevice, st));
+            HIPCHK_(hipStreamSynchronize(st));
+        }
+        int rc = solve_pairs(by_n, cnt);
+        if (rc != ZK_OK) return rc;
+        for (size_t pi = 0; pi < set.size(); pi++)
+            for (int k = 0; k < set[pi]->npairs; k++)
+                set[pi]->pairs[k].status = (!mark[pi].empty() && mark[pi][k]) ? 0 : 1;
+        rc = run_gs(set, false);
+        for (S2Prob *p : set)
+            for (auto &q : p->pairs) q.status = 0;
+        return rc;
+    }
+
     // Clusters from ascending binary64 eigenvalues: gaps <= cluster_tol ||H||
     // (mode 2: the whole spectrum is one cluster, for a start that is about
     // to be projected as a whole); Rayleigh-Ritz blocks for 2..32 members.
@@ -502,9 +564,38 @@ class Stage2Engine {
                 if (p->pairs[h].cl_size >= 2 && p->pairs[h].cl_size <= 32) p->rrb.push_back(std::make_pair(h, p->pairs[h].cl_size));
     }
 
-    struct PrrBlock {
-        int pi, k0, size;
-    };
+    // A projected level resolves its Ritz values to about u times its own
+    // scale, but its Ritz vectors keep the pollution of the level above (the
+    // enclosing block's resolution over the gap at the block's boundary), and
+    // the Rayleigh quotient of such a vector is off by that pollution squared
+    // times the outside eigenvalues -- far more than the tail eigenvalues
+    // themselves.  So an unconverged pair resolved by a projected level and
+    // not in a Rayleigh-Ritz block starts from its Ritz value: the first
+    // shifted solve then removes the pollution.
+    int first_shifts(const std::vector<S2Prob *> &set)
+    {
+        for (S2Prob *p : set) {
+            if ((int)p->ritz0.size() != p->npairs) continue;
+            std::vector<char> inblk(p->npairs, 0);
+            for (const auto &bk : p->rrb)
+                for (int q = 0; q < bk.second; q++) inblk[bk.first + q] = 1;
+            const int n = p->rp.n;
+            std::vector<double> sig((size_t)L * n);
+            bool any = false;
+            for (int k = 0; k < p->npairs; k++) any = any || (!inblk[k] && p->ritz0[k] == p->ritz0[k]);
+            if (!any) continue;
+            HIPCHK_(hipMemcpyAsync(sig.data(), p->rp.sigma, 8 * sig.size(), hipMemcpyDeviceToHost, st));
+            HIPCHK_(hipStreamSynchronize(st));
+            for (int k = 0; k < p->npairs; k++) {
+                if (inblk[k] || !(p->ritz0[k] == p->ritz0[k])) continue;
+                sig[k] = p->ritz0[k];
+                for (int l = 1; l < L; l++) sig[(size_t)l * n + k] = 0.0;
+            }
+            HIPCHK_(hipMemcpyAsync(p->rp.sigma, sig.data(), 8 * sig.size(), hipMemcpyHostToDevice, st));
+            HIPCHK_(hipStreamSynchronize(st));
+        }
+        return ZK_OK;
+    }
 
     // Projected Rayleigh-Ritz on the clusters longer than 32 members: C =
     // V^H H V in L limbs, the binary64 stage on C (rounded), V <- V Q.  The
@@ -513,27 +604,95 @@ class Stage2Engine {
     // Rayleigh-Ritz blocks, longer ones are projected again at the next level.
     int run_prr(const std::vector<S2Prob *> &set, bool &projected)
     {
+        for (S2Prob *p : set) p->ritz0.assign(p->npairs, std::nan(""));
         std::vector<PrrBlock> todo;
         for (size_t pi = 0; pi < set.size(); pi++)
             for (int h : set[pi]->heads)
                 if (set[pi]->pairs[h].cl_size > 32) todo.push_back({(int)pi, h, set[pi]->pairs[h].cl_size});
-        for (int level = 0; level < kPrrLevels && !todo.empty(); level++) {
-            projected = true;
+        if (todo.empty()) return ZK_OK;
+        projected = true;
+        std::vector<std::vector<double>> ritz;
+        int rc = prr_project(set, todo, ritz);
+        if (rc != ZK_OK) return rc;
+        // Ritz values below the binary64 stage's pollution floor: purify the
+        // chain (one shift-zero inverse-iteration step) and project again
+        std::vector<PrrBlock> pur;
+        std::vector<int> pidx;
+        for (size_t b = 0; b < todo.size(); b++) {
+            double mn = INFINITY;
+            for (double x : ritz[b]) mn = std::min(mn, std::fabs(x));
+            if (mn < kPurify * set[todo[b].pi]->rp.hnorm) {
+                pur.push_back(todo[b]);
+                pidx.push_back((int)b);
+            }
+        }
+        if (!pur.empty()) {
+            if ((rc = purify(set, pur)) != ZK_OK) return rc;
+            std::vector<std::vector<double>> rp;
+            if ((rc = prr_project(set, pur, rp)) != ZK_OK) return rc;
+            for (size_t i = 0; i < pur.size(); i++) ritz[pidx[i]] = rp[i];
+        }
+        for (int level = 0; level < kPrrLevels; level++) {
             std::vector<PrrBlock> next;
-            int rc = prr_level(set, todo, false, &next);
-            if (rc != ZK_OK) return rc;
+            prr_split(set, todo, ritz, next);
+            if (next.empty()) break;
             todo = next;
+            if ((rc = prr_project(set, todo, ritz)) != ZK_OK) return rc;
         }
         return ZK_OK;
     }
 
-    // One projected Rayleigh-Ritz step on the given blocks.  whole = true:
-    // the Ritz values replace the binary64 eigenvalues of the block (P.w0);
-    // otherwise they split the block into Rayleigh-Ritz blocks (2..32
-    // members, appended to rrb) and sub-chains for the next level (*next).
-    int prr_level(const std::vector<S2Prob *> &set, const std::vector<PrrBlock> &todo, bool whole, std::vector<PrrBlock> *next)
+    // Ritz values of a projected level -> first shifts, Rayleigh-Ritz blocks
+    // and the blocks of the next level.  The next level takes the members
+    // whose Ritz values lie below kPrrDeep times the level's scale (if there
+    // are more than 32 of them): the level resolves its Ritz vectors to about
+    // u times its scale, so the pollution of that sub-block by the members
+    // above stays below u / kPrrDeep, and the next level's Ritz values are
+    // accurate far below the scale of the members above.  Members above it
+    // form chains by gaps <= cluster_tol * scale: 2..32 members become
+    // Rayleigh-Ritz blocks, longer chains are projected at the next level.
+    void prr_split(const std::vector<S2Prob *> &set, const std::vector<PrrBlock> &todo,
+                   const std::vector<std::vector<double>> &ritz, std::vector<PrrBlock> &next)
+    {
+        for (size_t b = 0; b < todo.size(); b++) {
+            const std::vector<double> &w = ritz[b];
+            const int m = todo[b].size, k0 = todo[b].k0;
+            S2Prob *p = set[todo[b].pi];
+            if (std::getenv("ZK_TRACE"))
+                std::fprintf(stderr, "[zk] projected level: block %d+%d, Ritz values %.3e .. %.3e\n", k0, m, w[0], w[m - 1]);
+            // the deepest level's Ritz values are the first shifts of its pairs
+            if ((int)p->ritz0.size() >= k0 + m) std::copy(w.begin(), w.end(), p->ritz0.begin() + k0);
+            double sc = 0.0;
+            for (double x : w) sc = std::max(sc, std::fabs(x));
+            const double thr = p->opts.cluster_tol * sc, deep = kPrrDeep * sc;
+            int j0 = 0;
+            while (j0 < m && !(std::fabs(w[j0]) < deep)) j0++;
+            int j1 = j0;
+            while (j1 < m && std::fabs(w[j1]) < deep) j1++;
+            const bool sub = (j1 - j0 > 32) && (j1 - j0 < m);
+            if (sub) next.push_back({todo[b].pi, k0 + j0, j1 - j0});
+            int s0 = 0;
+            for (int e = 1; e <= m; e++) {
+                const bool brk = (e == m) || !(w[e] - w[e - 1] <= thr) || (sub && (e == j0 || e == j1));
+                if (!brk) continue;
+                const int len = e - s0;
+                if (!(sub && s0 >= j0 && s0 < j1)) {
+                    if (len >= 2 && len <= 32) p->rrb.push_back(std::make_pair(k0 + s0, len));
+                    if (len > 32 && len < m) next.push_back({todo[b].pi, k0 + s0, len});
+                }
+                s0 = e;
+            }
+        }
+    }
+
+    // One projected Rayleigh-Ritz step on the given blocks: C = V^H H V in L
+    // limbs, the binary64 stage on C (rounded), V <- V Q; the Ritz values
+    // (ascending) are returned per block.
+    int prr_project(const std::vector<S2Prob *> &set, const std::vector<PrrBlock> &todo,
+                    std::vector<std::vector<double>> &ritz)
     {
         const int nd = (int)todo.size();
+        ritz.assign(nd, std::vector<double>());
         if (nd == 0) return ZK_OK;
         int max_size = 0, max_n = 0;
         size_t bytes = s2_align(sizeof(PrrDesc) * nd);
@@ -604,30 +763,10 @@ class Stage2Engine {
             return ctx->fail(ZK_EDEVICE, "projected Rayleigh-Ritz launch failed");
         }
         for (int b = 0; b < nd; b++) {
-            const int m = todo[b].size;
-            S2Prob *p = set[todo[b].pi];
-            std::vector<double> w(m);
-            if (hipMemcpyAsync(w.data(), w0[b], 8 * (size_t)m, hipMemcpyDeviceToHost, st) != hipSuccess ||
-                hipStreamSynchronize(st) != hipSuccess) {
+            ritz[b].resize(todo[b].size);
+            if (hipMemcpyAsync(ritz[b].data(), w0[b], 8 * (size_t)todo[b].size, hipMemcpyDeviceToHost, st) != hipSuccess) {
                 cleanup();
                 return ctx->fail(ZK_EDEVICE, "projected Rayleigh-Ritz read-back failed");
-            }
-            if (whole) {
-                // the Ritz values replace the binary64 eigenvalues of the block
-                if ((int)p->w0h.size() >= todo[b].k0 + m) std::copy(w.begin(), w.end(), p->w0h.begin() + todo[b].k0);
-                continue;
-            }
-            // sub-chains from the Ritz values
-            double sc = 0.0;
-            for (double x : w) sc = std::max(sc, std::fabs(x));
-            const double thr = p->opts.cluster_tol * sc;
-            int s0 = 0;
-            for (int e = 1; e <= m; e++) {
-                if (e < m && w[e] - w[e - 1] <= thr) continue;
-                const int len = e - s0;
-                if (len >= 2 && len <= 32) p->rrb.push_back(std::make_pair(todo[b].k0 + s0, len));
-                if (len > 32 && len < m && next) next->push_back({todo[b].pi, todo[b].k0 + s0, len});
-                s0 = e;
             }
         }
         cleanup();

@@ -308,9 +308,10 @@ __global__ void __launch_bounds__(256) k_s2_rq(PairDesc *pairs, RqiProb *probs, 
         } else if (!(res == res)) {
             Q.status = 2;
             Q.flags |= 8;
-        } else if (res * P.hnorm <= 0.25 * P.tol_abs) {
-            // internal target a quarter of the tolerance: the final
-            // re-orthogonalisation may add a little to every residual
+        } else if (res * P.hnorm <= 0.5 * P.tol_abs) {
+            // internal target half the tolerance: the final
+            // re-orthogonalisation may add a little to the residuals of the
+            // pairs it touches (a pair pushed above gets polished)
             Q.status = 1;
             Q.flags |= 1;
         } else if (Q.iters >= P.max_iter) {

@@ -146,7 +146,8 @@ def test_qd_companions_session(zk):
     lat = [sess.times(t) for t in tickets]
     log(f"qd companions: latencies (submit->done) {[round(c - a, 3) for a, b, c in lat]}")
     for i, (h, r) in enumerate(zip(comps, mixed)):
-        assert r.status == Z.ZK_OK, f"request {i}: status {r.status}"
+        bad = [(k, float(h.lam[k]), x["resid"], x["iters"], x["flags"]) for k, x in enumerate(r.info) if not (x["flags"] & 1)]
+        assert r.status == Z.ZK_OK, f"request {i}: status {r.status}, unconverged (k, lam, resid, iters, flags) {bad[:8]}"
         ref = _exact_ref_limbs(h.lam)
         sample = None if i == 0 else np.r_[0:4, 124:128, 252:256]
         out = judge(h.planes, r, ref, QD_TOL, orth_tol=QD_ORTH if i == 0 else None, sample=sample)
