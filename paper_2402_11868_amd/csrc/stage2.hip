@@ -316,8 +316,11 @@ __global__ void __launch_bounds__(256) k_s2_rq(PairDesc *pairs, RqiProb *probs, 
             Q.flags |= 1;
         } else if (Q.iters >= P.max_iter) {
             Q.status = 2;
-        } else if (Q.iters >= 3 && res > 0.5 * Q.prev_resid) {
-            Q.status = 2;   // stagnated above the tolerance
+        } else if (Q.iters >= 3 && res > 0.5 * Q.prev_resid && res * P.hnorm <= 64.0 * P.tol_abs) {
+            // stagnated just above the tolerance: the attainable floor.  Far
+            // above it a pair keeps iterating (up to max_iter): inside a long
+            // chain its Gram-Schmidt partners still move
+            Q.status = 2;
         }
     }
 }
