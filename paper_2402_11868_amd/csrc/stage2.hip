@@ -510,8 +510,9 @@ __global__ void __launch_bounds__(256) k_s2_lu_trsm(Stage2Batch B, int k0, int n
 // write 16 consecutive rows of a column), operands staged in LDS in chunks
 // of KC (U12 staged with consecutive lanes along k, its unit-stride index).
 constexpr int KC = 8;
+constexpr int KCD = 4;   // k-chunk of the double-double update (256 threads stage 4 x 64 of L and U)
 
-__global__ void __launch_bounds__(256) k_s2_lu_update_dd(Stage2Batch B, int k0, int nbw)
+__global__ void __launch_bounds__(256, 2) k_s2_lu_update_dd(Stage2Batch B, int k0, int nbw)
 {
     const int t = blockIdx.y;
     const PairDesc &Q = B.dev_pairs[B.dev_active[t]];
@@ -525,9 +526,36 @@ __global__ void __launch_bounds__(256) k_s2_lu_update_dd(Stage2Batch B, int k0, 
     const int i0 = r0 + ti * 64, j0 = r0 + tj * 64;
     if (ti * 64 >= mrows || tj * 64 >= mcols) return;
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-    // planes: 0 re_hi, 1 re_lo, 2 im_hi, 3 im_lo
-    __shared__ double sL[4][KC][64];
-    __shared__ double sU[4][KC][64];
+    // planes: 0 re_hi, 1 re_lo, 2 im_hi, 3 im_lo; two buffers: the next chunk
+    // is loaded from global memory while the current one is multiplied
+    __shared__ double sL[2][4][KCD][64];
+    __shared__ double sU[2][4][KCD][64];
+    double pL[4], pU[4];   // staging registers: one entry x 4 planes each
+    auto fetch = [&](int kc) {
+        {
+            const int q = tid;
+            {
+                const int kk = q >> 6, ii = q & 63;
+                const int kcol = k0 + kc + kk, gi = i0 + ii;
+                const bool ok = kc + kk < nbw && gi < n;
+                for (int pl = 0; pl < 4; pl++) pL[pl] = ok ? M[pl * plane + (size_t)kcol * ldm + gi] : 0.0;
+            }
+            {
+                const int kk = q & (KCD - 1), jj = q / KCD;
+                const int kcol = k0 + kc + kk, gj = j0 + jj;
+                const bool ok = kc + kk < nbw && gj <= n;
+                for (int pl = 0; pl < 4; pl++) pU[pl] = ok ? M[pl * plane + (size_t)gj * ldm + kcol] : 0.0;
+            }
+        }
+    };
+    auto stash = [&](int buf) {
+        const int q = tid;
+        for (int pl = 0; pl < 4; pl++) {
+            sL[buf][pl][q >> 6][q & 63] = pL[pl];
+            sU[buf][pl][q & (KCD - 1)][q / KCD] = pU[pl];
+        }
+    };
+    fetch(0);
     double S[4][4][2], C[4][4][2];   // [a][b][re/im]
     for (int a = 0; a < 4; a++)
         for (int b = 0; b < 4; b++) {
@@ -540,47 +568,36 @@ __global__ void __launch_bounds__(256) k_s2_lu_update_dd(Stage2Batch B, int k0, 
             S[a][b][0] = rh; C[a][b][0] = rl;
             S[a][b][1] = ih; C[a][b][1] = il;
         }
-    for (int kc = 0; kc < nbw; kc += KC) {
-        __syncthreads();
-        // stage L21[i0:i0+64, k0+kc : +KC] and U12[k0+kc : +KC, j0:j0+64]
-        for (int q = tid; q < KC * 64; q += 256) {
-            {
-                const int kk = q >> 6, ii = q & 63;
-                const int kcol = k0 + kc + kk, gi = i0 + ii;
-                for (int pl = 0; pl < 4; pl++)
-                    sL[pl][kk][ii] = (kc + kk < nbw && gi < n) ? M[pl * plane + (size_t)kcol * ldm + gi] : 0.0;
-            }
-            {
-                const int kk = q & (KC - 1), jj = q / KC;
-                const int kcol = k0 + kc + kk, gj = j0 + jj;
-                for (int pl = 0; pl < 4; pl++)
-                    sU[pl][kk][jj] = (kc + kk < nbw && gj <= n) ? M[pl * plane + (size_t)gj * ldm + kcol] : 0.0;
-            }
-        }
-        __syncthreads();
-        const int kmax = min(KC, nbw - kc);
+    stash(0);
+    __syncthreads();
+    int buf = 0;
+    for (int kc = 0; kc < nbw; kc += KCD) {
+        const bool more = kc + KCD < nbw;
+        if (more) fetch(kc + KCD);
+        const int kmax = min(KCD, nbw - kc);
         for (int kk = 0; kk < kmax; kk++) {
-            double lrh[4], lrl[4], lih[4], lil[4];
             double urh[4], url[4], uih[4], uil[4];
+            for (int b = 0; b < 4; b++) {
+                urh[b] = sU[buf][0][kk][ty + 16 * b]; url[b] = sU[buf][1][kk][ty + 16 * b];
+                uih[b] = sU[buf][2][kk][ty + 16 * b]; uil[b] = sU[buf][3][kk][ty + 16 * b];
+            }
             for (int a = 0; a < 4; a++) {
                 // negated L: the update subtracts
-                lrh[a] = -sL[0][kk][tx + 16 * a]; lrl[a] = -sL[1][kk][tx + 16 * a];
-                lih[a] = sL[2][kk][tx + 16 * a];  lil[a] = sL[3][kk][tx + 16 * a];
-            }
-            for (int b = 0; b < 4; b++) {
-                urh[b] = sU[0][kk][ty + 16 * b]; url[b] = sU[1][kk][ty + 16 * b];
-                uih[b] = sU[2][kk][ty + 16 * b]; uil[b] = sU[3][kk][ty + 16 * b];
-            }
-            for (int a = 0; a < 4; a++)
+                const double lrh = -sL[buf][0][kk][tx + 16 * a], lrl = -sL[buf][1][kk][tx + 16 * a];
+                const double lih = sL[buf][2][kk][tx + 16 * a], lil = sL[buf][3][kk][tx + 16 * a];
                 for (int b = 0; b < 4; b++) {
                     // re -= lr ur - li ui  ->  re += (-lr) ur + li ui
-                    acc_dd(S[a][b][0], C[a][b][0], lrh[a], lrl[a], urh[b], url[b]);
-                    acc_dd(S[a][b][0], C[a][b][0], lih[a], lil[a], uih[b], uil[b]);
+                    acc_dd(S[a][b][0], C[a][b][0], lrh, lrl, urh[b], url[b]);
+                    acc_dd(S[a][b][0], C[a][b][0], lih, lil, uih[b], uil[b]);
                     // im -= lr ui + li ur  ->  im += (-lr) ui + (-li) ur
-                    acc_dd(S[a][b][1], C[a][b][1], lrh[a], lrl[a], uih[b], uil[b]);
-                    acc_dd(S[a][b][1], C[a][b][1], -lih[a], -lil[a], urh[b], url[b]);
+                    acc_dd(S[a][b][1], C[a][b][1], lrh, lrl, uih[b], uil[b]);
+                    acc_dd(S[a][b][1], C[a][b][1], -lih, -lil, urh[b], url[b]);
                 }
+            }
         }
+        if (more) stash(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
     }
     for (int a = 0; a < 4; a++)
         for (int b = 0; b < 4; b++) {
@@ -835,70 +852,90 @@ __global__ void __launch_bounds__(256) k_gs_gram(const GsCluster *cls, const int
 // Cholesky factor of the block's Gram matrix and its inverse, one wave per
 // cluster.  pass 0 sets the fallback flag; pass 1 is skipped for a flagged
 // cluster.  The packed inverse overwrites the cluster's first Gram slice.
+__device__ __forceinline__ void unpack_tri(int e, int &a, int &c)
+{
+    c = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+    while (c * (c + 1) / 2 > e) c--;
+    while ((c + 1) * (c + 2) / 2 <= e) c++;
+    a = e - c * (c + 1) / 2;
+}
+
 template <int L>
-__global__ void __launch_bounds__(64) k_gs_chol(const GsCluster *cls, int b, double *gram, int ks, int *flag, int pass)
+__global__ void __launch_bounds__(256) k_gs_chol(const GsCluster *cls, int b, double *gram, int ks, int *flag, int pass)
 {
     const GsCluster C = cls[blockIdx.x];
     const int bw = min(RB, C.nact - b * RB);
     if (bw <= 0) return;
     if (pass == 1 && flag[blockIdx.x]) return;
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x;
     __shared__ cmp<L> R[RBP];
+    __shared__ cmp<L> part[8][RB];
     __shared__ double dg[RB];
-    __shared__ int bad;
     double *g0 = gram + (size_t)blockIdx.x * ks * (2 * L * RB * RB);
-    for (int c = 0; c < bw; c++)
-        if (lane <= c) {
-            cmp<L> x = c_zero<L>();
-            for (int s = 0; s < ks; s++) x = c_add(x, ld_cmp<L>(g0 + (size_t)s * (2 * L * RB * RB), (size_t)RB * RB, (size_t)lane * RB + c));
-            if (lane == c) {
-                x.im = mp_zero<L>();
-                dg[c] = x.re.x[0];
-            }
-            R[pk(lane, c)] = x;
+    const int np = bw * (bw + 1) / 2;
+    for (int e = tid; e < np; e += 256) {
+        int a, c;
+        unpack_tri(e, a, c);
+        cmp<L> x = c_zero<L>();
+        for (int s = 0; s < ks; s++) x = c_add(x, ld_cmp<L>(g0 + (size_t)s * (2 * L * RB * RB), (size_t)RB * RB, (size_t)a * RB + c));
+        if (a == c) {
+            x.im = mp_zero<L>();
+            dg[c] = x.re.x[0];
         }
-    if (lane == 0) bad = 0;
+        R[e] = x;
+    }
     __syncthreads();
-    // right-looking factorisation G = R^H R
+    // right-looking factorisation G = R^H R (entries of the trailing triangle spread over the block)
+    bool bad = false;
     for (int j = 0; j < bw; j++) {
         const mp<L> d = R[pk(j, j)].re;
         if (!(d.x[0] > 1e-16 * dg[j])) {
-            if (lane == 0) bad = 1;
+            bad = true;   // the same decision in every thread
             break;
         }
         const mp<L> rj = sqrt_mp(d), inv = div(mp_from<L>(1.0), rj);
         __syncthreads();
-        if (lane > j && lane < bw) R[pk(j, lane)] = c_scale(R[pk(j, lane)], inv);
-        if (lane == j) R[pk(j, j)] = cmp<L>{rj, mp_zero<L>()};
+        if (tid > j && tid < bw) R[pk(j, tid)] = c_scale(R[pk(j, tid)], inv);
+        if (tid == j) R[pk(j, j)] = cmp<L>{rj, mp_zero<L>()};
         __syncthreads();
-        for (int c = j + 1; c < bw; c++)
-            if (lane > j && lane <= c) {
-                // R(a,c) -= conj(R(j,a)) R(j,c)
-                const cmp<L> t = c_mulc(R[pk(j, lane)], R[pk(j, c)]);
-                R[pk(lane, c)] = c_sub(R[pk(lane, c)], t);
-            }
-        __syncthreads();
-    }
-    __syncthreads();
-    if (bad) {
-        if (lane == 0) flag[blockIdx.x] = 1;
-        return;
-    }
-    // in-place inverse of the upper triangle, column by column
-    for (int j = 0; j < bw; j++) {
-        const mp<L> dinv = div(mp_from<L>(1.0), R[pk(j, j)].re);
-        cmp<L> val = cmp<L>{dinv, mp_zero<L>()};
-        if (lane < j) {
-            cmp<L> t = c_zero<L>();
-            for (int k = lane; k < j; k++) t = c_add(t, c_mul(R[pk(lane, k)], R[pk(k, j)]));
-            val = c_scale(t, mp_neg<L>(dinv));
+        const int m = bw - j - 1;
+        for (int e = tid; e < m * (m + 1) / 2; e += 256) {
+            int a, c;
+            unpack_tri(e, a, c);
+            a += j + 1;
+            c += j + 1;
+            // R(a,c) -= conj(R(j,a)) R(j,c)
+            R[pk(a, c)] = c_sub(R[pk(a, c)], c_mulc(R[pk(j, a)], R[pk(j, c)]));
         }
         __syncthreads();
-        if (lane <= j) R[pk(lane, j)] = val;
+    }
+    if (bad) {
+        if (tid == 0) flag[blockIdx.x] = 1;
+        return;
+    }
+    // in-place inverse of the upper triangle, column by column; the sum of
+    // every entry is split over 8 thread groups and reduced through LDS
+    const int i = tid & (RB - 1), g = tid / RB;
+    for (int j = 0; j < bw; j++) {
+        const mp<L> dinv = div(mp_from<L>(1.0), R[pk(j, j)].re);
+        cmp<L> t = c_zero<L>();
+        if (i < j)
+            for (int k = i + g; k < j; k += 8) t = c_add(t, c_mul(R[pk(i, k)], R[pk(k, j)]));
+        part[g][i] = t;
+        __syncthreads();
+        if (g == 0 && i <= j) {
+            cmp<L> val = cmp<L>{dinv, mp_zero<L>()};
+            if (i < j) {
+                cmp<L> s = part[0][i];
+                for (int q = 1; q < 8; q++) s = c_add(s, part[q][i]);
+                val = c_scale(s, mp_neg<L>(dinv));
+            }
+            R[pk(i, j)] = val;
+        }
         __syncthreads();
     }
-    for (int e = lane; e < bw * (bw + 1) / 2; e += 64) st_cmp<L>(g0, (size_t)RBP, (size_t)e, R[e]);
-    if (lane == 0 && pass == 0) flag[blockIdx.x] = 0;
+    for (int e = tid; e < np; e += 256) st_cmp<L>(g0, (size_t)RBP, (size_t)e, R[e]);
+    if (tid == 0 && pass == 0) flag[blockIdx.x] = 0;
 }
 
 // V_block <- V_block R^-1, rows in slices of 8 per work-group (8 x 32 threads)
@@ -996,7 +1033,7 @@ int stage2_gs(const GsPlan &G, RqiProb *probs, PairDesc *pairs, hipStream_t st)
         for (int pass = 0; pass < 2; pass++) {
             hipLaunchKernelGGL(k_gs_gram<L>, dim3(G.ks, 3, G.ncl), dim3(256), 0, st, G.dev_cls, G.dev_list,
                                (const RqiProb *)probs, b, G.gram, G.ks);
-            hipLaunchKernelGGL(k_gs_chol<L>, dim3(G.ncl), dim3(64), 0, st, G.dev_cls, b, G.gram, G.ks, G.flag, pass);
+            hipLaunchKernelGGL(k_gs_chol<L>, dim3(G.ncl), dim3(256), 0, st, G.dev_cls, b, G.gram, G.ks, G.flag, pass);
             hipLaunchKernelGGL(k_gs_apply<L>, dim3((G.max_n + 7) / 8, G.ncl), dim3(256), 0, st, G.dev_cls, G.dev_list, probs,
                                pairs, b, (const double *)G.gram, G.ks, (const int *)G.flag);
         }
