@@ -357,7 +357,16 @@ __global__ void __launch_bounds__(256) k_s2_build(Stage2Batch B)
 // ============================================================ LU panel ====
 // One work-group (256) per pair: columns [k0, k0+nbw), rows [k0, n).
 // Row interchanges are applied inside the panel only; lu_trsm applies them
-// to the trailing columns.
+// to the trailing columns.  The panel is factorised in sub-panels of
+// kLuSub columns: a sub-panel first receives the deferred update from the
+// columns left of it (its rows in the panel's top block by forward
+// substitution with the unit lower factor, the rows below by one rank-s0
+// update per row), then its columns are factorised right-looking inside
+// the sub-panel only.  Each panel element is then read and written a few
+// times instead of once per column step.  Interchanges swap the rows across
+// all panel columns, so deferred columns are always in the current order.
+constexpr int kLuSub = 8;
+
 template <int L>
 __global__ void __launch_bounds__(256) k_s2_lu_panel(Stage2Batch B, int k0, int nbw)
 {
@@ -373,72 +382,109 @@ __global__ void __launch_bounds__(256) k_s2_lu_panel(Stage2Batch B, int k0, int 
     __shared__ int sidx[4];
     __shared__ int s_piv;
     __shared__ cmp<L> s_inv;
-    __shared__ cmp<L> s_row[kLuNB];
+    __shared__ cmp<L> s_row[kLuSub];
+    __shared__ cmp<L> sU[kLuNB][kLuSub];
     __shared__ int s_guard;
     if (tid == 0) s_guard = 0;
-    for (int j = 0; j < nbw; j++) {
-        const int c = k0 + j;
-        // pivot search
-        double best = -1.0;
-        int bidx = n;
-        for (int r = c + tid; r < n; r += 256) {
-            const double m = c_mag1(ld_cmp<L>(M, plane, (size_t)c * ldm + r));
-            if (m > best) { best = m; bidx = r; }
-        }
-        for (int off = 32; off > 0; off >>= 1) {
-            const double ob = __shfl_xor(best, off, 64);
-            const int oi = __shfl_xor(bidx, off, 64);
-            if (ob > best || (ob == best && oi < bidx)) { best = ob; bidx = oi; }
-        }
-        if (lane == 0) { smax[wid] = best; sidx[wid] = bidx; }
-        __syncthreads();
-        if (tid == 0) {
-            double b = smax[0];
-            int bi = sidx[0];
-            for (int w = 1; w < 4; w++)
-                if (smax[w] > b || (smax[w] == b && sidx[w] < bi)) { b = smax[w]; bi = sidx[w]; }
-            if (bi >= n) bi = c;
-            s_piv = bi;
-            ipiv[c] = bi;
-        }
-        __syncthreads();
-        const int p = s_piv;
-        // swap rows c and p inside the panel
-        if (p != c && tid < nbw) {
-            const size_t oc = (size_t)(k0 + tid) * ldm + c, op = (size_t)(k0 + tid) * ldm + p;
-            const cmp<L> a = ld_cmp<L>(M, plane, oc), b = ld_cmp<L>(M, plane, op);
-            st_cmp<L>(M, plane, oc, b);
-            st_cmp<L>(M, plane, op, a);
-        }
-        __syncthreads();
-        if (tid == 0) {
-            cmp<L> u = ld_cmp<L>(M, plane, (size_t)c * ldm + c);
-            if (c_mag1(u) < P.piv_tol) {
-                // zero-pivot guard: replace by the threshold, keeping the phase
-                const double sr = (u.re.x[0] < 0.0) ? -1.0 : 1.0;
-                u.re = mp_from<L>(sr * P.piv_tol);
-                u.im = mp_zero<L>();
-                st_cmp<L>(M, plane, (size_t)c * ldm + c, u);
-                s_guard = 1;
+    for (int s0 = 0; s0 < nbw; s0 += kLuSub) {
+        const int w = min(kLuSub, nbw - s0);
+        if (s0 > 0) {
+            // (a) rows [k0, k0+s0) of the sub-panel: U = L11^-1 A (unit lower L11)
+            if (tid >= w && tid < kLuSub)
+                for (int i = 0; i < s0; i++) sU[i][tid] = c_zero<L>();
+            if (tid < w) {
+                const size_t col = (size_t)(k0 + s0 + tid) * ldm;
+                for (int i = 0; i < s0; i++) {
+                    CAcc<L> x;
+                    x.init(ld_cmp<L>(M, plane, col + k0 + i));
+                    for (int q = 0; q < i; q++) x.sub_mul(ld_cmp<L>(M, plane, (size_t)(k0 + q) * ldm + k0 + i), sU[q][tid]);
+                    const cmp<L> u = x.get();
+                    sU[i][tid] = u;
+                    st_cmp<L>(M, plane, col + k0 + i, u);
+                }
             }
-            s_inv = c_recip<L>(u);
-        }
-        if (tid > 0 && tid < nbw - j) s_row[tid] = ld_cmp<L>(M, plane, (size_t)(c + tid) * ldm + c);
-        __syncthreads();
-        const cmp<L> inv = s_inv;
-        // scale the column and update the rest of the panel (one row per thread)
-        for (int r = c + 1 + tid; r < n; r += 256) {
-            const cmp<L> l = c_mul(ld_cmp<L>(M, plane, (size_t)c * ldm + r), inv);
-            st_cmp<L>(M, plane, (size_t)c * ldm + r, l);
-            for (int q = 1; q < nbw - j; q++) {
-                const size_t o = (size_t)(c + q) * ldm + r;
-                CAcc<L> x;
-                x.init(ld_cmp<L>(M, plane, o));
-                x.sub_mul(l, s_row[q]);
-                st_cmp<L>(M, plane, o, x.get());
+            __syncthreads();
+            // (b) rows [k0+s0, n): A(r, c) -= sum_q L(r, q) U(q, c)
+            for (int r = k0 + s0 + tid; r < n; r += 256) {
+                CAcc<L> acc[kLuSub];
+#pragma unroll
+                for (int c = 0; c < kLuSub; c++)
+                    acc[c].init(c < w ? ld_cmp<L>(M, plane, (size_t)(k0 + s0 + c) * ldm + r) : c_zero<L>());
+                for (int q = 0; q < s0; q++) {
+                    const cmp<L> l = ld_cmp<L>(M, plane, (size_t)(k0 + q) * ldm + r);
+#pragma unroll
+                    for (int c = 0; c < kLuSub; c++) acc[c].sub_mul(l, sU[q][c]);
+                }
+#pragma unroll
+                for (int c = 0; c < kLuSub; c++)
+                    if (c < w) st_cmp<L>(M, plane, (size_t)(k0 + s0 + c) * ldm + r, acc[c].get());
             }
+            __syncthreads();
         }
-        __syncthreads();
+        for (int jj = 0; jj < w; jj++) {
+            const int c = k0 + s0 + jj;
+            // pivot search
+            double best = -1.0;
+            int bidx = n;
+            for (int r = c + tid; r < n; r += 256) {
+                const double m = c_mag1(ld_cmp<L>(M, plane, (size_t)c * ldm + r));
+                if (m > best) { best = m; bidx = r; }
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ob = __shfl_xor(best, off, 64);
+                const int oi = __shfl_xor(bidx, off, 64);
+                if (ob > best || (ob == best && oi < bidx)) { best = ob; bidx = oi; }
+            }
+            if (lane == 0) { smax[wid] = best; sidx[wid] = bidx; }
+            __syncthreads();
+            if (tid == 0) {
+                double bb = smax[0];
+                int bi = sidx[0];
+                for (int q = 1; q < 4; q++)
+                    if (smax[q] > bb || (smax[q] == bb && sidx[q] < bi)) { bb = smax[q]; bi = sidx[q]; }
+                if (bi >= n) bi = c;
+                s_piv = bi;
+                ipiv[c] = bi;
+            }
+            __syncthreads();
+            const int p = s_piv;
+            // swap rows c and p across the whole panel
+            if (p != c && tid < nbw) {
+                const size_t oc = (size_t)(k0 + tid) * ldm + c, op = (size_t)(k0 + tid) * ldm + p;
+                const cmp<L> x = ld_cmp<L>(M, plane, oc), y = ld_cmp<L>(M, plane, op);
+                st_cmp<L>(M, plane, oc, y);
+                st_cmp<L>(M, plane, op, x);
+            }
+            __syncthreads();
+            if (tid == 0) {
+                cmp<L> u = ld_cmp<L>(M, plane, (size_t)c * ldm + c);
+                if (c_mag1(u) < P.piv_tol) {
+                    // zero-pivot guard: replace by the threshold, keeping the phase
+                    const double sr = (u.re.x[0] < 0.0) ? -1.0 : 1.0;
+                    u.re = mp_from<L>(sr * P.piv_tol);
+                    u.im = mp_zero<L>();
+                    st_cmp<L>(M, plane, (size_t)c * ldm + c, u);
+                    s_guard = 1;
+                }
+                s_inv = c_recip<L>(u);
+            }
+            if (tid > 0 && tid < w - jj) s_row[tid] = ld_cmp<L>(M, plane, (size_t)(c + tid) * ldm + c);
+            __syncthreads();
+            const cmp<L> inv = s_inv;
+            // scale the column and update the rest of the sub-panel (one row per thread)
+            for (int r = c + 1 + tid; r < n; r += 256) {
+                const cmp<L> l = c_mul(ld_cmp<L>(M, plane, (size_t)c * ldm + r), inv);
+                st_cmp<L>(M, plane, (size_t)c * ldm + r, l);
+                for (int q = 1; q < w - jj; q++) {
+                    const size_t o = (size_t)(c + q) * ldm + r;
+                    CAcc<L> x;
+                    x.init(ld_cmp<L>(M, plane, o));
+                    x.sub_mul(l, s_row[q]);
+                    st_cmp<L>(M, plane, o, x.get());
+                }
+            }
+            __syncthreads();
+        }
     }
     if (tid == 0 && s_guard) Q.flags |= 4;
 }
@@ -460,6 +506,8 @@ __device__ __forceinline__ cmp<L> shfl_cmp(const cmp<L> &v, int src)
     return r;
 }
 
+constexpr int kTrsmGroups = 4;   // groups of 8 columns per work-group (L11 loaded once)
+
 template <int L>
 __global__ void __launch_bounds__(256) k_s2_lu_trsm(Stage2Batch B, int k0, int nbw)
 {
@@ -471,36 +519,64 @@ __global__ void __launch_bounds__(256) k_s2_lu_trsm(Stage2Batch B, int k0, int n
     const int *ipiv = B.piv_base + (size_t)t * B.piv_stride;
     const size_t plane = (size_t)ldm * (n + 1);
     __shared__ cmp<L> l11t[kLuNB][kLuNB];   // l11t[q][r] = L11(r, q)
+    // the panel's interchanges as one permutation of at most 2 nbw rows:
+    // row dst[i] receives the value of row src[i]
+    __shared__ int s_dst[2 * kLuNB], s_src[2 * kLuNB];
+    __shared__ int s_m;
     for (int e = threadIdx.x; e < nbw * nbw; e += 256) {
         const int r = e % nbw, q = e / nbw;
         if (r > q) l11t[q][r] = ld_cmp<L>(M, plane, (size_t)(k0 + q) * ldm + k0 + r);
     }
-    const int cl = threadIdx.x >> 5, rr = threadIdx.x & 31, lane = threadIdx.x & 63;
-    const int j = k0 + nbw + blockIdx.x * 8 + cl;
-    const bool valid = j <= n;
-    const size_t col = (size_t)j * ldm;
-    if (valid && rr == 0) {
+    if (threadIdx.x == 0) {
+        int m = 0;
+        // rows touched, with their current content (a row index of the original order)
         for (int r = 0; r < nbw; r++) {
-            const int p = ipiv[k0 + r];
-            if (p != k0 + r) {
-                const cmp<L> a = ld_cmp<L>(M, plane, col + k0 + r), b = ld_cmp<L>(M, plane, col + p);
-                st_cmp<L>(M, plane, col + k0 + r, b);
-                st_cmp<L>(M, plane, col + p, a);
+            const int a = k0 + r, b = ipiv[k0 + r];
+            if (a == b) continue;
+            int ia = -1, ib = -1;
+            for (int i = 0; i < m; i++) {
+                if (s_dst[i] == a) ia = i;
+                if (s_dst[i] == b) ib = i;
             }
+            if (ia < 0) { s_dst[m] = a; s_src[m] = a; ia = m++; }
+            if (ib < 0) { s_dst[m] = b; s_src[m] = b; ib = m++; }
+            const int tmp = s_src[ia];
+            s_src[ia] = s_src[ib];
+            s_src[ib] = tmp;
         }
+        s_m = m;
     }
     __syncthreads();
-    CAcc<L> acc;
-    acc.init((valid && rr < nbw) ? ld_cmp<L>(M, plane, col + k0 + rr) : c_zero<L>());
-    cmp<L> x = c_zero<L>();
+    const int m = s_m;
+    const int cl = threadIdx.x >> 5, rr = threadIdx.x & 31, lane = threadIdx.x & 63;
     const int src0 = lane & 32;
-    for (int q = 0; q < nbw; q++) {
-        const cmp<L> mine = acc.get();
-        const cmp<L> xq = shfl_cmp<L>(mine, src0 + q);
-        if (rr == q) x = mine;
-        if (rr > q) acc.sub_mul(l11t[q][rr], xq);
+    for (int grp = 0; grp < kTrsmGroups; grp++) {
+        const int j = k0 + nbw + (blockIdx.x * kTrsmGroups + grp) * 8 + cl;
+        const bool valid = j <= n;
+        const size_t col = (size_t)j * ldm;
+        // interchanges: gather every touched row's source, then scatter
+        cmp<L> g0 = c_zero<L>(), g1 = c_zero<L>();
+        if (valid) {
+            if (rr < m) g0 = ld_cmp<L>(M, plane, col + s_src[rr]);
+            if (rr + 32 < m) g1 = ld_cmp<L>(M, plane, col + s_src[rr + 32]);
+        }
+        __syncthreads();
+        if (valid) {
+            if (rr < m) st_cmp<L>(M, plane, col + s_dst[rr], g0);
+            if (rr + 32 < m) st_cmp<L>(M, plane, col + s_dst[rr + 32], g1);
+        }
+        __syncthreads();
+        CAcc<L> acc;
+        acc.init((valid && rr < nbw) ? ld_cmp<L>(M, plane, col + k0 + rr) : c_zero<L>());
+        cmp<L> x = c_zero<L>();
+        for (int q = 0; q < nbw; q++) {
+            const cmp<L> mine = acc.get();
+            const cmp<L> xq = shfl_cmp<L>(mine, src0 + q);
+            if (rr == q) x = mine;
+            if (rr > q) acc.sub_mul(l11t[q][rr], xq);
+        }
+        if (valid && rr < nbw) st_cmp<L>(M, plane, col + k0 + rr, x);
     }
-    if (valid && rr < nbw) st_cmp<L>(M, plane, col + k0 + rr, x);
 }
 
 // =========================================================== LU update ====
@@ -1415,7 +1491,7 @@ int stage2_solve(const Stage2Batch &B, hipStream_t st)
         const int r0 = k0 + nbw;
         const int ncols = n + 1 - r0;
         id = T.begin(KC_LU_TRSM, (double)cnt * ncols * nbw * nbw * 0.5, st);
-        hipLaunchKernelGGL(k_s2_lu_trsm<L>, dim3(cdiv2(ncols, 8), cnt), dim3(256), 0, st, B, k0, nbw);
+        hipLaunchKernelGGL(k_s2_lu_trsm<L>, dim3(cdiv2(ncols, 8 * kTrsmGroups), cnt), dim3(256), 0, st, B, k0, nbw);
         T.end(id, st);
         const int mrows = n - r0;
         if (mrows > 0) {
