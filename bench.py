@@ -30,9 +30,9 @@ FP64_MFMA_TFLOPS = 78.6
 FP32_MFMA_TFLOPS = 157.3
 HBM_GBS = 8000.0
 # binary64 instructions of one complex double-double multiply-add in the LU
-# trailing update (4 real products x 13: two-product, cross terms, two-sum,
-# compensation); counted from the kernel source, see the design notes
-CPLX_DD_FMA_INSTR = 52
+# trailing update (4 real products x 12: two-product, two-sum, compensation,
+# cross terms), counted from the kernel source
+CPLX_DD_FMA_INSTR = 48
 
 
 # sources that the LU trailing-update kernel is compiled from; the stored HBM
@@ -252,7 +252,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path runs on a single "
-              f"MI355X; multi-GPU sharding is described in the design notes but not built)", file=sys.stderr)
+              f"MI355X; sharding across GPUs is not built)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -73,18 +73,20 @@ __device__ __forceinline__ mp<L> ld_sigma(const RqiProb &P, int k)
 
 // ----------------------------------------------------- error-free accumulator
 // (S, C): S accumulates the leading products through TwoSum, C the exact
-// product errors, the cross terms and the TwoSum errors.  One real product
-// x*y of two double-doubles costs 13 binary64 operations.
+// product errors, the TwoSum errors and the cross terms.  The small terms of
+// one product are summed first (the cross terms through two fused
+// multiply-adds) and reach C in one addition, so C is rounded once per
+// product.  One real product x*y of two double-doubles costs 12 binary64
+// operations.
 __device__ __forceinline__ void acc_dd(double &S, double &C, double xh, double xl, double yh, double yl)
 {
     const double p = xh * yh;
     const double e = fma(xh, yh, -p);
-    const double c = fma(xh, yl, xl * yh);
     const double s = S + p;
     const double bb = s - S;
     const double t = (S - (s - bb)) + (p - bb);
     S = s;
-    C += t + (e + c);
+    C += fma(xh, yl, fma(xl, yh, t + e));
 }
 
 __device__ __forceinline__ dd acc_dd_final(double S, double C)
@@ -95,7 +97,7 @@ __device__ __forceinline__ dd acc_dd_final(double S, double C)
 }
 
 // complex multi-limb accumulator; the double-double form keeps (sum,
-// compensation) pairs and costs 13 binary64 operations per real product
+// compensation) pairs and costs 12 binary64 operations per real product
 template <int L>
 struct CAcc {
     cmp<L> v;
