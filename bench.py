@@ -141,6 +141,54 @@ def batch_leg(Z, ctx, torch, tol=1e-30):
             "phase_ms": {k: round(v[0], 3) for k, v in p.items()}}
 
 
+def allpairs_leg(Z, ctx, torch, Ad, gold, steps=3, tol=1e-30):
+    """The same workload through zk_heev_dd_allpairs (the O(n^3)-total
+    all-pairs refinement in place of the per-pair Rayleigh quotient
+    iteration): eigenpairs/s of pairs within the residual and eigenvalue
+    gates, phase times, and the batch workload through the same entry."""
+    import numpy as np
+    import workloads as W
+    Z.heev_allpairs(ctx, [[Ad]])   # warm-up
+    torch.cuda.synchronize()
+    ctx.prof(True)
+    ctx.prof_reset()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res, = Z.heev_allpairs(ctx, [[Ad]])
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    p = ctx.prof_read()
+    w = res.w.cpu().numpy()
+    resid = np.array([i["resid"] for i in res.info])
+    ok = resid <= tol
+    eig_err = None
+    if gold is not None:
+        hn = float(np.max(np.abs(gold[0])))
+        err = np.abs((w[0] - gold[0]) + (w[1] - gold[1]) - gold[2] - gold[3]) / hn
+        ok &= err <= tol
+        eig_err = float(err.max())
+    ms_g, la_g, wk_g = p["ap_ddgemm"]
+    ms_r, la_r, wk_r = p["ap_resid"]
+    out = {"ms": dt * 1e3, "eigenpairs_per_s": int(ok.sum()) / dt, "passing_pairs": int(ok.sum()),
+           "status": res.status, "iterations": int(res.info[0]["iters"]), "max_eig_err_rel": eig_err,
+           "max_resid_rel": float(resid.max()),
+           "phase_ms": {k: round(v[0] / steps, 3) for k, v in p.items() if v[0] > 0},
+           "ddgemm_g_cplx_dd_fma_per_s": (wk_g / (ms_g / 1e3) / 1e9) if ms_g > 0 else None,
+           "resid_g_cplx_products_per_s": (wk_r / (ms_r / 1e3) / 1e9) if ms_r > 0 else None}
+    mats = [torch.from_numpy(W.workload(2, index=i)["A"]).cuda() for i in range(256)]
+    Z.heev_allpairs(ctx, [[m] for m in mats])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rb = Z.heev_allpairs(ctx, [[m] for m in mats])
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    okb = sum(1 for r in rb for x in r.info if x["resid"] <= tol)
+    out["batch"] = {"ms": tb * 1e3, "passing_pairs": okb, "eigenpairs_per_s": okb / tb,
+                    "iterations": sorted(set(int(r.info[0]["iters"]) for r in rb))}
+    ctx.prof(False)
+    return out
+
+
 def _pct(x, q):
     import numpy as np
     return float(np.percentile(np.asarray(x), q)) * 1e3 if len(x) else None
@@ -235,6 +283,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32-leg", action="store_true", help="skip the FP32-MFMA-start run")
     ap.add_argument("--no-batch-leg", action="store_true", help="skip the 256 x 128^2 batch run")
+    ap.add_argument("--no-allpairs-leg", action="store_true", help="skip the all-pairs refinement runs")
     ap.add_argument("--serving-requests", type=int, default=200,
                     help="requests of the serving-stream leg (0 = skip the leg)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -365,6 +414,9 @@ def main():
                         "hemv_gbs": (by_v / (ms_v / 1e3) / 1e9) if ms_v > 0 else None},
         "fp32_mfma_start": fp32_leg,
     }
+    if not args.no_allpairs_leg:
+        log("all-pairs refinement")
+        out["allpairs"] = allpairs_leg(Z, ctx, torch, Ad, gold)
     if not args.no_batch_leg:
         log("batch of 256 x 128^2")
         out["batch"] = batch_leg(Z, ctx, torch)

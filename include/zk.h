@@ -149,6 +149,27 @@ int zk_heev_dd(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out *out, const 
 int zk_heev_qd(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out *out, const zk_opts *opts);
 
 /*
+ * zk_heev_dd_allpairs: the same double-double decomposition as zk_heev_dd,
+ * with stage 2 replaced by an all-pairs refinement of O(n^3) work per matrix
+ * instead of one O(n^3) shifted LU factorisation per pair and iteration.  It
+ * is not the paper's method (Sec. 2 names only Rayleigh quotient iteration):
+ * every iteration forms the residual matrix R = H X - X diag(lam) with exact
+ * products and cascaded sums, F = X^H R in binary64, and corrects all pairs
+ * at once by the first-order formula of Ogita and Aishima's refinement of
+ * symmetric eigendecompositions (Japan J. Indust. Appl. Math. 35, 2018), in
+ * its Hermitian form; pairs too close for that formula form blocks that are
+ * rotated by the binary64 eigenvectors of their projected matrix, at the
+ * block's own scale, before the correction.  Arguments, layouts, ownership,
+ * outputs and errors are those of zk_heev_dd (out[i].limbs == 2).  opts:
+ * tol, want_vectors and init_fp32 as for zk_heev_dd; max_iter bounds the
+ * whole-basis iterations (0 = default 12); cluster_tol and reorth are not
+ * used.  info[k].iters is the number of whole-basis iterations of the matrix,
+ * info[k].cluster the first index of the block of the pair in the last
+ * iteration.  Synchronous.
+ */
+int zk_heev_dd_allpairs(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out *out, const zk_opts *opts);
+
+/*
  * zk_heev_fp64: stage 1 alone (the binary64 eigendecomposition that seeds the
  * Rayleigh quotient iteration).  For each matrix i: w[i] (device, n doubles,
  * ascending) and V[i] (device, n x n complex128 column-major, leading
@@ -178,7 +199,10 @@ int zk_rqi_refine(zk_ctx *ctx, int limbs_out, const zk_herm *A, int k, const dou
  * tridiagonalisation (work: bytes), 10 shifted-matrix build, 11 column update,
  * reflector and W-vector of the tridiagonalisation, 12 tridiagonal
  * eigen-solver (bisection, inverse iteration, Gram-Schmidt), 13
- * back-transformation (work: flops).
+ * back-transformation (work: flops), 14 residual matrix of the all-pairs
+ * refinement (work: complex products of H and X), 15 its binary64 GEMM
+ * X^H R (work: flops), 16 its double-double GEMMs (work: complex
+ * double-double multiply-adds), 17 its other kernels.
  * zk_prof_read waits for the recorded events.
  */
 int zk_prof_enable(zk_ctx *ctx, int on);

@@ -45,10 +45,10 @@ class ZkOpts(ctypes.Structure):
 
 
 KERNEL_CLASSES = ["lu_update", "lu_panel", "lu_trsm", "backsolve", "rq", "gs", "reorth", "stage1", "her2k", "hemv",
-                  "build", "trd_vec", "tridiag", "backt"]
+                  "build", "trd_vec", "tridiag", "backt", "ap_resid", "ap_fgemm", "ap_ddgemm", "ap_other"]
 
 EXPORTED = ["zk_prof_enable", "zk_prof_reset", "zk_prof_read", "zk_opts_default", "zk_ctx_create", "zk_ctx_destroy", "zk_status_str", "zk_ctx_last_error",
-            "zk_workspace_bytes", "zk_heev_dd", "zk_heev_qd", "zk_heev_fp64", "zk_rqi_refine",
+            "zk_workspace_bytes", "zk_heev_dd", "zk_heev_qd", "zk_heev_dd_allpairs", "zk_heev_fp64", "zk_rqi_refine",
             "zk_session_create", "zk_session_submit", "zk_session_poll", "zk_session_times", "zk_session_destroy"]
 
 _lib = None
@@ -73,7 +73,7 @@ def load(path: str = LIB_PATH):
     lib.zk_ctx_last_error.restype = ctypes.c_char_p
     lib.zk_workspace_bytes.argtypes = [I, I, I]
     lib.zk_workspace_bytes.restype = ctypes.c_size_t
-    for f in ("zk_heev_dd", "zk_heev_qd"):
+    for f in ("zk_heev_dd", "zk_heev_qd", "zk_heev_dd_allpairs"):
         getattr(lib, f).argtypes = [P, I, ctypes.POINTER(ZkHerm), ctypes.POINTER(ZkEigOut), ctypes.POINTER(ZkOpts)]
     lib.zk_heev_fp64.argtypes = [P, I, ctypes.POINTER(ZkHerm), ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(I)]
     lib.zk_rqi_refine.argtypes = [P, I, ctypes.POINTER(ZkHerm), I, P, P, I, ctypes.POINTER(ZkEigOut), ctypes.POINTER(ZkOpts)]
@@ -242,6 +242,29 @@ def heev(ctx: Context, mats, limbs_out: int = 2, opts: ZkOpts | None = None, sta
         rc = f(ctx.handle, count, H, O, op)
     if rc not in (ZK_OK, ZK_ENOCONV):
         raise RuntimeError(f"zk_heev failed: {status_str(rc)}: {ctx.last_error()}")
+    return [EigResult(w, V, _info_list(info, n), rc) for (w, V, info, n) in outs]
+
+
+def heev_allpairs(ctx: Context, mats, opts: ZkOpts | None = None):
+    """Double-double eigendecomposition with the all-pairs refinement
+    (zk_heev_dd_allpairs) in place of the per-pair Rayleigh quotient
+    iteration.  Same inputs and results as heev(..., limbs_out=2)."""
+    lib = load()
+    keep: list = []
+    count = len(mats)
+    H = (ZkHerm * count)()
+    O = (ZkEigOut * count)()
+    outs = []
+    want = True if opts is None else bool(opts.want_vectors)
+    for i, m in enumerate(mats):
+        H[i] = herm(m, keep)
+        o, w, V, info = _alloc_out(H[i].n, 2, want, ctx_device(m), keep)
+        O[i] = o
+        outs.append((w, V, info, H[i].n))
+    op = ctypes.byref(opts) if opts is not None else None
+    rc = lib.zk_heev_dd_allpairs(ctx.handle, count, H, O, op)
+    if rc not in (ZK_OK, ZK_ENOCONV):
+        raise RuntimeError(f"zk_heev_dd_allpairs failed: {status_str(rc)}: {ctx.last_error()}")
     return [EigResult(w, V, _info_list(info, n), rc) for (w, V, info, n) in outs]
 
 

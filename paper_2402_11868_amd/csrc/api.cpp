@@ -393,6 +393,53 @@ static int run_heev(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out *out, c
     return run_stage2<L>(ctx, rp, npair_of, infos, O, stats);
 }
 
+namespace zk {
+int allpairs_run(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out *out, double tol, int max_iter, int want_vectors,
+                 const std::vector<double *> &hf, const std::vector<double *> &w0, const std::vector<double *> &V0,
+                 int *iters_used);
+}
+
+extern "C" int zk_heev_dd_allpairs(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out *out, const zk_opts *opts)
+{
+    if (!ctx) return ZK_EINVAL;
+    if (ctx->poisoned) return ctx->fail(ZK_EDEVICE, "context poisoned by an earlier device error");
+    if (count < 1 || !A || !out) return ctx->fail(ZK_EINVAL, "count < 1 or NULL arrays");
+    const ResolvedOpts O = zk_resolve_opts(opts, 2);
+    for (int i = 0; i < count; i++) {
+        if (check_herm(A[i]) != ZK_OK) return ctx->fail(ZK_EINVAL, "matrix %d: bad n/lda/limbs/planes", i);
+        if (check_out(out[i], A[i].n, A[i].n, 2, O.want_vectors) != ZK_OK)
+            return ctx->fail(ZK_EINVAL, "output %d: bad n/limbs/ldv or NULL pointers", i);
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess) return ctx->fail(ZK_EDEVICE, "hipSetDevice failed");
+    std::vector<double *> hf(count), w0(count), V0(count);
+    std::vector<int *> flag(count);
+    int rc = carve_s2in(ctx, count, A, hf, w0, V0, flag);
+    if (rc != ZK_OK) return rc;
+    if ((rc = run_stage1(ctx, count, A, hf, w0, V0, flag, std::vector<int>(count, O.init_fp32))) != ZK_OK) return rc;
+    const int max_iter = (opts && opts->max_iter > 0) ? opts->max_iter : 12;
+    // matrices of equal order are refined together
+    std::map<int, std::vector<int>> groups;
+    for (int i = 0; i < count; i++) groups[A[i].n].push_back(i);
+    int status = ZK_OK;
+    for (auto &kv : groups) {
+        const std::vector<int> &ids = kv.second;
+        std::vector<zk_herm> a;
+        std::vector<zk_eig_out> o;
+        std::vector<double *> h, w, v;
+        for (int i : ids) {
+            a.push_back(A[i]);
+            o.push_back(out[i]);
+            h.push_back(hf[i]);
+            w.push_back(w0[i]);
+            v.push_back(V0[i]);
+        }
+        rc = zk::allpairs_run(ctx, (int)ids.size(), a.data(), o.data(), O.tol, max_iter, O.want_vectors, h, w, v, nullptr);
+        if (rc < 0) return rc;
+        if (rc == ZK_ENOCONV) status = ZK_ENOCONV;
+    }
+    return status;
+}
+
 extern "C" int zk_heev_fp64(zk_ctx *ctx, int count, const zk_herm *A, double *const *w, void *const *V, const int *ldv)
 {
     if (!ctx) return ZK_EINVAL;

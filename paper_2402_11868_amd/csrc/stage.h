@@ -17,7 +17,8 @@ constexpr int kMaxN = 4096;   // largest matrix order accepted
 // Per-kernel-class timing with HIP events recorded on the launch stream
 // around each launch (instrumentation; off unless enabled on the context).
 enum KernelClass { KC_LU_UPDATE = 0, KC_LU_PANEL, KC_LU_TRSM, KC_BACKSOLVE, KC_RQ, KC_GS, KC_REORTH, KC_STAGE1,
-                   KC_HER2K, KC_HEMV, KC_BUILD, KC_TRD_VEC, KC_TRIDIAG, KC_BACKT, KC_COUNT };
+                   KC_HER2K, KC_HEMV, KC_BUILD, KC_TRD_VEC, KC_TRIDIAG, KC_BACKT, KC_AP_RESID, KC_AP_FGEMM,
+                   KC_AP_DDGEMM, KC_AP_OTHER, KC_COUNT };
 
 struct KernelTimer {
     bool on = false;

@@ -373,6 +373,16 @@ __global__ void __launch_bounds__(256) k_zgemm(const GemmDesc *descs, int M, int
     }
 }
 
+// C = op(A) op(B) for `count` descriptors of equal shape (M x N, inner K).
+int zgemm_batched(const GemmDesc *d_descs, int count, int M, int N, int K, int opA, int opB, hipStream_t st)
+{
+    if (count <= 0 || M <= 0 || N <= 0) return 0;
+    const unsigned tiles = (unsigned)(((M + 31) / 32) * ((N + 31) / 32));
+    hipLaunchKernelGGL(k_zgemm, dim3(tiles, count), dim3(256), 0, st, d_descs, M, N, K, opA, opB, make_double2(1.0, 0.0),
+                       make_double2(0.0, 0.0), 0);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 // The same product with FP32 MFMA (v_mfma_f32_16x16x4f32) on operands rounded
 // to complex64 and FP32 accumulation; alpha, beta and C stay binary64.  Output
 // layout of that MFMA: the 4 accumulator values of lane l are
