@@ -105,6 +105,7 @@ struct CAcc {
     __device__ void add_mulc(const cmp<L> &a, const cmp<L> &b) { v = c_add(v, c_mulc(a, b)); }   // += conj(a) b
     __device__ void sub_mul(const cmp<L> &a, const cmp<L> &b) { v = c_sub(v, c_mul(a, b)); }     // -= a b
     __device__ cmp<L> get() const { return v; }
+    __device__ void renorm() {}
 };
 
 template <>
@@ -128,6 +129,20 @@ struct CAcc<2> {
         acc_dd(Si, Ci, -a.im.x[0], -a.im.x[1], b.re.x[0], b.re.x[1]);
     }
     __device__ cmp<2> get() const { return {acc_dd_final(Sr, Cr), acc_dd_final(Si, Ci)}; }
+    // fold the compensation back into (sum, rounding error of the sum): in a
+    // long sum with cancellation the compensation would otherwise grow with
+    // the number of products, and so would its own rounding errors (about
+    // K u^2 times the largest partial sum after K products)
+    __device__ void renorm()
+    {
+        double h, l;
+        two_sum(Sr, Cr, h, l);
+        Sr = h;
+        Cr = l;
+        two_sum(Si, Ci, h, l);
+        Si = h;
+        Ci = l;
+    }
 };
 
 // quad-double form: four-level cascaded sums (Casc4 in mp.h), renormalised
@@ -157,6 +172,7 @@ struct CAcc<4> {
         im.add(a.im, b.re, -1.0);
     }
     __device__ cmp<4> get() const { return cmp<4>{re.get(), im.get()}; }
+    __device__ void renorm() {}
 };
 
 // ================================================================ init ====
@@ -862,6 +878,7 @@ __global__ void __launch_bounds__(256) k_gs_dot(const GsCluster *cls, const int 
         sj[tx][ty] = (r < n && cj >= 0) ? ld_cmp<L>(P.vec, nn, (size_t)cj * n + r) : c_zero<L>();
         __syncthreads();
         for (int q = 0; q < 16; q++) acc.add_mulc(si[q][ty], sj[q][tx]);
+        acc.renorm();
     }
     if (i < j0 && jb < bw) st_cmp<L>(Cm, cplane, (size_t)jb * C.size + i, acc.get());
 }
@@ -885,8 +902,10 @@ __global__ void __launch_bounds__(256) k_gs_update(const GsCluster *cls, const i
     const int cj = lst[j0 + jb];
     CAcc<L> acc;
     acc.init(ld_cmp<L>(P.vec, nn, (size_t)cj * n + r));
-    for (int i = 0; i < j0; i++)
+    for (int i = 0; i < j0; i++) {
         acc.sub_mul(ld_cmp<L>(Cm, cplane, (size_t)jb * C.size + i), ld_cmp<L>(P.vec, nn, (size_t)lst[i] * n + r));
+        if ((i & 15) == 15) acc.renorm();
+    }
     st_cmp<L>(P.vec, nn, (size_t)cj * n + r, acc.get());
 }
 
@@ -921,6 +940,7 @@ __global__ void __launch_bounds__(256) k_gs_gram(const GsCluster *cls, const int
         sc[tx][ty] = (r < rend && cc >= 0) ? ld_cmp<L>(P.vec, nn, (size_t)cc * n + r) : c_zero<L>();
         __syncthreads();
         for (int q = 0; q < 16; q++) acc.add_mulc(sa[q][ty], sc[q][tx]);
+        acc.renorm();
     }
     const int a = ta * 16 + ty, c = tc * 16 + tx;
     double *g = gram + ((size_t)blockIdx.z * ks + blockIdx.x) * (2 * L * RB * RB);
@@ -1148,6 +1168,7 @@ __global__ void __launch_bounds__(256) k_prr_hv(const PrrDesc *descs, const RqiP
         for (int j = 0; j < n; j++) {
             const cmp<L> h = ld_h<L>(P, i, j);
             y.sub_mul(cmp<L>{mp_neg<L>(h.re), mp_neg<L>(h.im)}, ld_cmp<L>(P.vec, nn, (size_t)ka * n + j));
+            if ((j & 15) == 15) y.renorm();
         }
         st_cmp<L>(D.Y, yplane, (size_t)a * n + i, y.get());
     }
@@ -1174,6 +1195,7 @@ __global__ void __launch_bounds__(256) k_prr_c(const PrrDesc *descs, const RqiPr
         sy[tx][ty] = (r < n && vc < m) ? ld_cmp<L>(D.Y, yplane, (size_t)vc * n + r) : c_zero<L>();
         __syncthreads();
         for (int q = 0; q < 16; q++) acc.add_mulc(sv[q][ty], sy[q][tx]);
+        acc.renorm();
     }
     const int a = blockIdx.x * 16 + ty, c = blockIdx.y * 16 + tx;
     if (a < m && c < m) {
@@ -1197,6 +1219,7 @@ __global__ void __launch_bounds__(256) k_prr_rot(const PrrDesc *descs, const Rqi
     for (int i = 0; i < m; i++) {
         const double2 q = ld2(D.Q + 2 * ((size_t)j * m + i));
         acc.sub_mul(cmp<L>{mp_from<L>(-q.x), mp_from<L>(-q.y)}, ld_cmp<L>(P.vec, nn, (size_t)(D.k0 + i) * n + r));
+        if ((i & 15) == 15) acc.renorm();
     }
     st_cmp<L>(D.Y, yplane, (size_t)j * n + r, acc.get());
 }
@@ -1272,6 +1295,7 @@ __global__ void __launch_bounds__(256) k_rr_hv(const GsCluster *cls, const int *
             const cmp<L> v = ld_cmp<L>(P.vec, nn, (size_t)ka * n + j);
             // y += h v  ==  y -= (-h) v
             y.sub_mul(cmp<L>{mp_neg<L>(h.re), mp_neg<L>(h.im)}, v);
+            if ((j & 15) == 15) y.renorm();
         }
         st_cmp<L>(Y, yplane, (size_t)a * n + i, y.get());
     }
