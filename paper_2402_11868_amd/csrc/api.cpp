@@ -137,7 +137,8 @@ static size_t s1_bytes(int n)
     b += align_up(16 * 2 * ntile * n);      // part
     b += align_up(8 * 5 * nn);              // tri
     b += align_up(8 * nn);                  // Zt
-    b += 3 * align_up(8 * (size_t)n);       // d, e, (spare)
+    b += 3 * align_up(8 * (size_t)n);       // d, e, cnt
+    b += align_up(8 * (ntile * (4 + 4 * (size_t)kNB) + 2));   // scr
     b += align_up(8 * nn);                  // Z
     b += align_up(16 * npan * kNB * kNB);   // T
     b += 2 * align_up(16 * (size_t)kNB * n);   // X, X2
@@ -311,7 +312,8 @@ int run_stage1(zk_ctx *ctx, int count, const zk_herm *A, const std::vector<doubl
                 P.Zt = (double *)b; b += align_up(8 * nn);
                 P.d = (double *)b; b += align_up(8 * (size_t)n);
                 P.e = (double *)b; b += align_up(8 * (size_t)n);
-                b += align_up(8 * (size_t)n);
+                P.cnt = (int *)b; b += align_up(8 * (size_t)n);
+                P.scr = (double *)b; b += align_up(8 * (ntile * (4 + 4 * (size_t)kNB) + 2));
                 P.Z = (double *)b; b += align_up(8 * nn);
                 P.T = (double *)b; b += align_up(16 * npan * kNB * kNB);
                 P.X = (double *)b; b += align_up(16 * (size_t)kNB * n);

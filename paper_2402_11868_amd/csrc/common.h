@@ -39,6 +39,8 @@ struct ProbDesc {
     double *X;             // NB x n complex128 scratch
     double *X2;            // NB x n complex128 scratch
     int *flag;             // [0]: NaN/Inf seen in the input
+    int *cnt;              // 2n finishing counters (column update, W finish), zeroed at ingest
+    double *scr;           // per row chunk: partial norm (dd), panel dot products, w^H v; reflector scale
 };
 
 // Pair (eigenvector) state of the Rayleigh quotient stage.

@@ -46,6 +46,7 @@ __global__ void k_ingest(ProbDesc *probs, int fp32)
     const int n = P.n, j = blockIdx.x;
     if (j >= n) return;
     const size_t nn = (size_t)n * n;
+    if (threadIdx.x < 2) P.cnt[2 * j + threadIdx.x] = 0;   // finishing counters of column j
     int bad = 0;
     for (int i = j + threadIdx.x; i < n; i += blockDim.x) {
         double re = 0.0, im = 0.0;
@@ -83,42 +84,115 @@ __global__ void k_zero_panel(ProbDesc *probs)
 }
 
 // ------------------------------------------------- column update + larfg --
-// One block (256 threads) per problem.  Column c = k0 + i of the panel.
-__global__ void __launch_bounds__(256) k_trd_col(ProbDesc *probs, int c, int k0)
+// Column c = k0 + i of the panel, in chunks of kColRows rows (grid
+// (chunks, problems)): each chunk applies the panel's earlier reflectors to
+// its rows and writes a partial norm; the last chunk to finish forms the
+// reflector and writes it for every row.
+constexpr int kColRows = 64;
+
+__global__ void __launch_bounds__(256) k_trd_col(ProbDesc *probs, int c, int k0, int crows)
 {
-    const ProbDesc &P = probs[blockIdx.x];
+    const ProbDesc &P = probs[blockIdx.y];
     const int n = P.n, i = c - k0;
+    const int G = (n - c + crows - 1) / crows;   // row chunks of column c (rows c .. n-1)
+    const int g = blockIdx.x;
+    if (g >= G) return;
+    const int ntile = (n + 63) / 64;
     __shared__ double2 sVc[kNB], sWc[kNB];   // row c of V and W (conjugated later)
+    __shared__ double2 sacc[4][64];
+    __shared__ double2 sx[64];
+    __shared__ double2 sdot[2 * kNB];
     __shared__ dd red_dd[16];
     __shared__ double2 s_scale;
-    const int tid = threadIdx.x;
+    __shared__ int s_last;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     if (tid < i) {
         sVc[tid] = ld2(P.P + 2 * ((size_t)tid * n + c));
         sWc[tid] = ld2(P.P + 2 * ((size_t)(kNB + tid) * n + c));
     }
+    if (tid < 2 * kNB) sdot[tid] = make_double2(0.0, 0.0);
     __syncthreads();
-    // 1. a[r,c] -= sum_j V[r,j] conj(W[c,j]) + W[r,j] conj(V[c,j]),  r >= c
+    // 1. a[r,c] -= sum_j V[r,j] conj(W[c,j]) + W[r,j] conj(V[c,j]) for the chunk's rows (the four
+    //    waves split the j terms), then the chunk's share of ||x||^2 and of the panel dot
+    //    products W_j^H x, V_j^H x over rows >= c+2 (x: the updated column; the reflector
+    //    is x times a scale, applied by k_trd_wfin)
     dd nrm = mp_zero<2>();
-    for (int r = c + tid; r < n; r += blockDim.x) {
-        double2 a = ld2(P.A + 2 * ((size_t)c * n + r));
-        for (int j = 0; j < i; j++) {
-            const double2 v = ld2(P.P + 2 * ((size_t)j * n + r));
-            const double2 w = ld2(P.P + 2 * ((size_t)(kNB + j) * n + r));
-            a = csub(a, cadd(cmul(v, make_double2(sWc[j].x, -sWc[j].y)), cmul(w, make_double2(sVc[j].x, -sVc[j].y))));
+    const int rend = min(n, c + (g + 1) * crows);
+    for (int r0 = c + g * crows; r0 < rend; r0 += 64) {
+        const int r = r0 + lane;
+        double2 s = make_double2(0.0, 0.0);
+        if (r < rend) {
+            for (int j = wid; j < i; j += 4) {
+                const double2 v = ld2(P.P + 2 * ((size_t)j * n + r));
+                const double2 w = ld2(P.P + 2 * ((size_t)(kNB + j) * n + r));
+                s = cadd(s, cadd(cmul(v, make_double2(sWc[j].x, -sWc[j].y)), cmul(w, make_double2(sVc[j].x, -sVc[j].y))));
+            }
         }
-        if (r == c) a.y = 0.0;
-        st2(P.A + 2 * ((size_t)c * n + r), a);
-        if (r >= c + 2) {
-            // |x_r|^2 in double-double (exact squares)
-            double p, e;
-            two_prod(a.x, a.x, p, e);
-            nrm = dd_add(nrm, dd{{p, e}});
-            two_prod(a.y, a.y, p, e);
-            nrm = dd_add(nrm, dd{{p, e}});
+        sacc[wid][lane] = s;
+        __syncthreads();
+        if (wid == 0) {
+            double2 a = make_double2(0.0, 0.0);
+            if (r < rend) {
+                a = ld2(P.A + 2 * ((size_t)c * n + r));
+                a = csub(a, cadd(cadd(sacc[0][lane], sacc[1][lane]), cadd(sacc[2][lane], sacc[3][lane])));
+                if (r == c) a.y = 0.0;
+                st2(P.A + 2 * ((size_t)c * n + r), a);
+                if (r >= c + 2) {
+                    // |x_r|^2 in double-double (exact squares)
+                    double p, e;
+                    two_prod(a.x, a.x, p, e);
+                    nrm = dd_add(nrm, dd{{p, e}});
+                    two_prod(a.y, a.y, p, e);
+                    nrm = dd_add(nrm, dd{{p, e}});
+                }
+            }
+            sx[lane] = (r < rend && r >= c + 2) ? a : make_double2(0.0, 0.0);
         }
+        __syncthreads();
+        {
+            // every lane takes part in the wave sums (zero outside the chunk)
+            const double2 x = sx[lane];
+            for (int j = wid; j < i; j += 4) {
+                double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+                if (r < rend) {
+                    a = cmulc(ld2(P.P + 2 * ((size_t)(kNB + j) * n + r)), x);
+                    b = cmulc(ld2(P.P + 2 * ((size_t)j * n + r)), x);
+                }
+                a = wave_sum2(a);
+                b = wave_sum2(b);
+                if (lane == 0) {
+                    sdot[j] = cadd(sdot[j], a);
+                    sdot[kNB + j] = cadd(sdot[kNB + j], b);
+                }
+            }
+        }
+        __syncthreads();
     }
-    const dd xn2 = block_sum_mp<2>(nrm, red_dd);   // includes a barrier: column c is written
+    const dd part = block_sum_mp<2>(nrm, red_dd);
+    double *snorm = P.scr;
+    double2 *sd = reinterpret_cast<double2 *>(P.scr + 2 * ntile) + (size_t)g * 2 * kNB;
     if (tid == 0) {
+        snorm[2 * g] = part.x[0];
+        snorm[2 * g + 1] = part.x[1];
+    }
+    if (tid < 2 * i) sd[tid < i ? tid : kNB + tid - i] = sdot[tid < i ? tid : kNB + tid - i];
+    // the last chunk to finish forms the reflector (device-scope fences around
+    // the counter make every chunk's column entries and partial sums visible)
+    bool last = true;
+    if (G > 1) {
+        __threadfence();
+        __syncthreads();
+        if (tid == 0) s_last = atomicAdd(P.cnt + 2 * c, 1) == G - 1;
+        __syncthreads();
+        last = s_last;
+        if (last) __threadfence();
+    } else {
+        __syncthreads();
+    }
+    if (!last) return;
+    if (tid == 0) {
+        dd xn2 = mp_zero<2>();
+        for (int q = 0; q < G; q++) xn2 = dd_add(xn2, dd{{snorm[2 * q], snorm[2 * q + 1]}});
         const double2 diag = ld2(P.A + 2 * ((size_t)c * n + c));
         P.d[c] = diag.x;
         const double2 alpha = ld2(P.A + 2 * ((size_t)c * n + c + 1));
@@ -128,12 +202,12 @@ __global__ void __launch_bounds__(256) k_trd_col(ProbDesc *probs, int c, int k0)
         if (!(xn2.x[0] == 0.0 && alpha.y == 0.0)) {
             // beta = -sign(Re alpha) * sqrt(|alpha|^2 + ||x||^2), the norm in double-double
             double p, e;
-            dd s = xn2;
+            dd sq = xn2;
             two_prod(alpha.x, alpha.x, p, e);
-            s = dd_add(s, dd{{p, e}});
+            sq = dd_add(sq, dd{{p, e}});
             two_prod(alpha.y, alpha.y, p, e);
-            s = dd_add(s, dd{{p, e}});
-            const dd rt = dd_sqrt(s);
+            sq = dd_add(sq, dd{{p, e}});
+            const dd rt = dd_sqrt(sq);
             beta = (alpha.x >= 0.0) ? -rt.x[0] : rt.x[0];
             tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
             // scale = 1 / (alpha - beta)
@@ -143,26 +217,22 @@ __global__ void __launch_bounds__(256) k_trd_col(ProbDesc *probs, int c, int k0)
         }
         P.e[c] = beta;
         st2(P.tau + 2 * c, tau);
+        st2(P.scr + 2 * ntile + 4 * kNB * ntile + 2 * ntile, scale);   // for k_trd_wfin
         s_scale = scale;
     }
     __syncthreads();
     const double2 sc = s_scale;
     // 2. reflector v (v[c+1] = 1) into Y[:, c], V column i of P, V column NB+i of Q
-    for (int r = c + 1 + tid; r < n; r += blockDim.x) {
+    for (int r2 = c + 1 + tid; r2 < n; r2 += blockDim.x) {
         double2 v;
-        if (r == c + 1) v = make_double2(1.0, 0.0);
-        else v = cmul(ld2(P.A + 2 * ((size_t)c * n + r)), sc);
-        st2(P.Y + 2 * ((size_t)c * n + r), v);
-        st2(P.P + 2 * ((size_t)i * n + r), v);
-        st2(P.Q + 2 * ((size_t)(kNB + i) * n + r), v);
+        if (r2 == c + 1) v = make_double2(1.0, 0.0);
+        else v = cmul(ld2(P.A + 2 * ((size_t)c * n + r2)), sc);
+        st2(P.Y + 2 * ((size_t)c * n + r2), v);
+        st2(P.P + 2 * ((size_t)i * n + r2), v);
+        st2(P.Q + 2 * ((size_t)(kNB + i) * n + r2), v);
     }
 }
 
-// --------------------------------------------------------------- hemv -----
-// y = A22 v with A22 = A[c+1:, c+1:] (lower triangle), v = Y[c+1:, c].
-// grid (T(T+1)/2 tiles, nprob), block 256; tile (I, J), I >= J, 64 x 64,
-// staged once in LDS and used for the direct (A) and mirrored (A^H) parts.
-// Partial sums: part[J][row] (direct) and part[T + I][col] (mirror).
 __global__ void __launch_bounds__(256) k_trd_hemv(ProbDesc *probs, int c)
 {
     const ProbDesc &P = probs[blockIdx.y];
@@ -233,70 +303,97 @@ __global__ void __launch_bounds__(256) k_trd_hemv(ProbDesc *probs, int c)
 }
 
 // ------------------------------------------------------------- w finish ---
-// One block (256) per problem: y = sum of partials - V (W^H v) - W (V^H v);
-// w = tau y; w += (-tau/2 w^H v) v; store W column i into P[:, NB+i] and Q[:, i].
-__global__ void __launch_bounds__(256) k_trd_wfin(ProbDesc *probs, int c, int k0)
+// Row chunks of wrows rows (grid (chunks, problems)): y = sum of the hemv
+// partials - V (W^H v) - W (V^H v) for the chunk's rows, w = tau y, and the
+// chunk's share of w^H v; the dot products W_j^H v, V_j^H v come from the
+// column kernel's chunk sums (taken on the unscaled column, times the
+// reflector's scale, plus the v[c+1] = 1 term).  The last chunk to finish adds
+// (-tau/2 w^H v) v to every row and stores W column i into P[:, NB+i] and Q[:, i].
+__global__ void __launch_bounds__(256) k_trd_wfin(ProbDesc *probs, int c, int k0, int crows, int wrows)
 {
-    const ProbDesc &P = probs[blockIdx.x];
+    const ProbDesc &P = probs[blockIdx.y];
     const int n = P.n, base = c + 1, m = n - base, i = c - k0;
     if (m <= 0) return;
-    const int T = (m + 63) / 64;
+    const int T = (m + 63) / 64;             // hemv row blocks
+    const int G = (m + wrows - 1) / wrows;   // chunks of this kernel
+    const int Gc = (n - c + crows - 1) / crows;   // chunks of the column kernel
+    const int g = blockIdx.x;
+    if (g >= G) return;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int ntile = (n + 63) / 64;
     __shared__ double2 t1[kNB], t2[kNB];
-    __shared__ double2 redc[4];
+    __shared__ double2 sacc[4][64];
+    __shared__ double2 s_alpha;
+    __shared__ int s_last;
     const double2 *Pv = reinterpret_cast<const double2 *>(P.P);
     double2 *Pw = reinterpret_cast<double2 *>(P.P);
     const double2 *Yc = reinterpret_cast<const double2 *>(P.Y) + (size_t)c * n;
-    // dot products t1_j = W_j^H v, t2_j = V_j^H v (j < i); wave wid handles j = wid, wid+4, ...
-    for (int j = wid; j < i; j += 4) {
-        double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
-        for (int r = base + lane; r < n; r += 64) {
-            const double2 v = Yc[r];
-            a = cadd(a, cmulc(Pv[(size_t)(kNB + j) * n + r], v));
-            b = cadd(b, cmulc(Pv[(size_t)j * n + r], v));
-        }
-        a = wave_sum2(a);
-        b = wave_sum2(b);
-        if (lane == 0) {
-            t1[j] = a;
-            t2[j] = b;
-        }
+    const double2 *sd = reinterpret_cast<const double2 *>(P.scr + 2 * ntile);
+    double2 *swv = reinterpret_cast<double2 *>(P.scr + 2 * ntile + 4 * kNB * ntile);
+    const double2 scale = ld2(P.scr + 2 * ntile + 4 * kNB * ntile + 2 * ntile);
+    // t1_j = W_j^H v, t2_j = V_j^H v (j < i)
+    if (tid < 2 * i) {
+        const int j = tid < i ? tid : tid - i, o = tid < i ? j : kNB + j;
+        double2 a = make_double2(0.0, 0.0);
+        for (int q = 0; q < Gc; q++) a = cadd(a, sd[(size_t)q * 2 * kNB + o]);
+        const double2 top = Pv[(size_t)(tid < i ? kNB + j : j) * n + base];   // row c+1, where v = 1
+        a = cadd(make_double2(top.x, -top.y), cmul(scale, a));
+        if (tid < i) t1[j] = a;
+        else t2[j] = a;
     }
     __syncthreads();
     const double2 tau = ld2(P.tau + 2 * c);
-    // y and w^H v
-    double2 acc = make_double2(0.0, 0.0);
-    const int per = (m + 255) / 256;   // rows per thread (<= 16 for n <= 4096)
-    double2 wloc[16];
-    for (int q = 0; q < per && q < 16; q++) {
-        const int r = base + tid + 256 * q;
-        double2 y = make_double2(0.0, 0.0);
-        if (r < n) {
+    double2 wv = make_double2(0.0, 0.0);
+    const int rend = min(n, base + (g + 1) * wrows);
+    for (int r0 = base + g * wrows; r0 < rend; r0 += 64) {
+        const int r = r0 + lane;
+        double2 s = make_double2(0.0, 0.0);
+        if (r < rend)
+            for (int j = wid; j < i; j += 4) {
+                s = cadd(s, cmul(Pv[(size_t)j * n + r], t1[j]));
+                s = cadd(s, cmul(Pv[(size_t)(kNB + j) * n + r], t2[j]));
+            }
+        sacc[wid][lane] = s;
+        __syncthreads();
+        if (wid == 0 && r < rend) {
             const int b = (r - base) / 64;
+            double2 y = make_double2(0.0, 0.0);
             for (int J = 0; J <= b; J++) y = cadd(y, ld2(P.part + 2 * ((size_t)J * n + r)));
             for (int I2 = b; I2 < T; I2++) y = cadd(y, ld2(P.part + 2 * ((size_t)(T + I2) * n + r)));
-            for (int j = 0; j < i; j++) {
-                y = csub(y, cmul(Pv[(size_t)j * n + r], t1[j]));
-                y = csub(y, cmul(Pv[(size_t)(kNB + j) * n + r], t2[j]));
-            }
+            y = csub(y, cadd(cadd(sacc[0][lane], sacc[1][lane]), cadd(sacc[2][lane], sacc[3][lane])));
             y = cmul(tau, y);
-            acc = cadd(acc, cmulc(y, Yc[r]));
+            Pw[(size_t)(kNB + i) * n + r] = y;
+            wv = cadd(wv, cmulc(y, Yc[r]));
         }
-        wloc[q] = y;
+        __syncthreads();
     }
-    acc = wave_sum2(acc);
+    if (wid == 0) {
+        wv = wave_sum2(wv);
+        if (lane == 0) swv[g] = wv;
+    }
+    bool last = true;
+    if (G > 1) {
+        __threadfence();
+        __syncthreads();
+        if (tid == 0) s_last = atomicAdd(P.cnt + 2 * c + 1, 1) == G - 1;
+        __syncthreads();
+        last = s_last;
+        if (last) __threadfence();
+    } else {
+        __syncthreads();
+    }
+    if (!last) return;
+    if (tid == 0) {
+        double2 t = make_double2(0.0, 0.0);
+        for (int q = 0; q < G; q++) t = cadd(t, swv[q]);
+        s_alpha = cmul(make_double2(-0.5 * tau.x, -0.5 * tau.y), t);
+    }
     __syncthreads();
-    if (lane == 0) redc[wid] = acc;
-    __syncthreads();
-    const double2 wv = cadd(cadd(redc[0], redc[1]), cadd(redc[2], redc[3]));
-    const double2 alpha = cmul(make_double2(-0.5 * tau.x, -0.5 * tau.y), wv);
-    for (int q = 0; q < per && q < 16; q++) {
-        const int r = base + tid + 256 * q;
-        if (r < n) {
-            const double2 w = cadd(wloc[q], cmul(alpha, Yc[r]));
-            Pw[(size_t)(kNB + i) * n + r] = w;
-            reinterpret_cast<double2 *>(P.Q)[(size_t)i * n + r] = w;
-        }
+    const double2 alpha = s_alpha;
+    for (int r2 = base + tid; r2 < n; r2 += blockDim.x) {
+        const double2 w = cadd(Pw[(size_t)(kNB + i) * n + r2], cmul(alpha, Yc[r2]));
+        Pw[(size_t)(kNB + i) * n + r2] = w;
+        reinterpret_cast<double2 *>(P.Q)[(size_t)i * n + r2] = w;
     }
 }
 
@@ -811,6 +908,10 @@ int stage1_run(const Stage1Batch &B, hipStream_t st)
         return hipGetLastError() == hipSuccess ? 0 : -1;
     }
     // ---- tridiagonalisation
+    // a few large matrices: the per-column kernels spread each column over
+    // chunks of 64 rows; a batch: one chunk per matrix (the batch fills the chip)
+    const int crows = np <= 4 ? kColRows : ((n + 63) / 64) * 64;
+    const int wrows = crows;
     const int npan = (n - 1 + kNB - 1) / kNB;
     for (int p = 0; p < npan; p++) {
         const int k0 = p * kNB;
@@ -819,7 +920,7 @@ int stage1_run(const Stage1Batch &B, hipStream_t st)
         for (int i = 0; i < nbw; i++) {
             const int c = k0 + i;
             int idv = B.timer ? B.timer->begin(KC_TRD_VEC, 0.0, st) : -1;
-            hipLaunchKernelGGL(k_trd_col, dim3(np), dim3(256), 0, st, pd, c, k0);
+            hipLaunchKernelGGL(k_trd_col, dim3(cdiv(n - c, crows), np), dim3(256), 0, st, pd, c, k0, crows);
             if (B.timer) B.timer->end(idv, st);
             const int m = n - c - 1;
             const int T = (m + 63) / 64;
@@ -828,7 +929,7 @@ int stage1_run(const Stage1Batch &B, hipStream_t st)
             hipLaunchKernelGGL(k_trd_hemv, dim3(T * (T + 1) / 2, np), dim3(256), 0, st, pd, c);
             if (B.timer) B.timer->end(id, st);
             idv = B.timer ? B.timer->begin(KC_TRD_VEC, 0.0, st) : -1;
-            hipLaunchKernelGGL(k_trd_wfin, dim3(np), dim3(256), 0, st, pd, c, k0);
+            hipLaunchKernelGGL(k_trd_wfin, dim3(cdiv(m, wrows), np), dim3(256), 0, st, pd, c, k0, crows, wrows);
             if (B.timer) B.timer->end(idv, st);
         }
         const int r0 = k0 + nbw;
