@@ -818,6 +818,7 @@ struct HostProb {
     bool done = false, rotated_last = true, converged = false;
     int iters = 0;
     std::vector<double> theta, rnorm, orth;   // theta: 2n
+    std::vector<int> pos, srt, reach;         // sorted positions, sorted order, coupling reach
     std::vector<int> cluster;           // sorted index of the first member of each pair's block
     // block tables of this iteration
     std::vector<int> blk, loc, bcol, boff, brot, qoff;
@@ -931,12 +932,13 @@ int allpairs_run(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out *out, doub
     };
     // binary64 eigenvalues give ||H||_2
     {
-        std::vector<double> wv(n);
+        std::vector<double> wv((size_t)count * n);
+        for (int p = 0; p < count; p++)
+            APCHK(hipMemcpyAsync(wv.data() + (size_t)p * n, w0[p], 8 * (size_t)n, hipMemcpyDeviceToHost, st));
+        APCHK(hipStreamSynchronize(st));
         for (int p = 0; p < count; p++) {
-            APCHK(hipMemcpyAsync(wv.data(), w0[p], 8 * (size_t)n, hipMemcpyDeviceToHost, st));
-            APCHK(hipStreamSynchronize(st));
             double h = 0.0;
-            for (double x : wv) h = std::max(h, std::fabs(x));
+            for (int k = 0; k < n; k++) h = std::max(h, std::fabs(wv[(size_t)p * n + k]));
             hp[p].hnorm = h > 0.0 ? h : 1.0;
         }
     }
@@ -1071,11 +1073,10 @@ int allpairs_run(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out *out, doub
             std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
                 return th[a] < th[b] || (th[a] == th[b] && th[n + a] < th[n + b]);
             });
-            std::vector<int> pos(n);
-            for (int k = 0; k < n; k++) pos[order[k]] = k;
-            APCHK(hipMemcpyAsync(H.d.pos, pos.data(), 4 * (size_t)n, hipMemcpyHostToDevice, st));
-            APCHK(hipStreamSynchronize(st));
-            H.bcol = order;   // kept for the block construction below
+            H.pos.resize(n);
+            for (int k = 0; k < n; k++) H.pos[order[k]] = k;
+            APCHK(hipMemcpyAsync(H.d.pos, H.pos.data(), 4 * (size_t)n, hipMemcpyHostToDevice, st));
+            H.srt = order;
         }
         APCHK(hipMemcpyAsync(d_probs, act.data(), sizeof(ApProb) * nl, hipMemcpyHostToDevice, st));
         {
@@ -1091,10 +1092,14 @@ int allpairs_run(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out *out, doub
         int maxm = 0, nbc_max = 0;
         for (int q = 0; q < nl; q++) {
             HostProb &H = hp[ids[q]];
-            std::vector<int> reach(n);
-            APCHK(hipMemcpyAsync(reach.data(), H.d.reach, 4 * (size_t)n, hipMemcpyDeviceToHost, st));
-            APCHK(hipStreamSynchronize(st));
-            const std::vector<int> srt = H.bcol;
+            H.reach.resize(n);
+            APCHK(hipMemcpyAsync(H.reach.data(), H.d.reach, 4 * (size_t)n, hipMemcpyDeviceToHost, st));
+        }
+        APCHK(hipStreamSynchronize(st));
+        for (int q = 0; q < nl; q++) {
+            HostProb &H = hp[ids[q]];
+            const std::vector<int> &reach = H.reach;
+            const std::vector<int> &srt = H.srt;
             // runs of the sorted order: a break before position p when nothing at or after p reaches below p
             std::vector<std::pair<int, int>> runs;   // [start, end) in sorted positions
             int end = n, runmin = n;
@@ -1171,8 +1176,8 @@ int allpairs_run(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out *out, doub
                 APCHK(hipMemcpyAsync(H.d.qoff, H.qoff.data(), 4 * H.qoff.size(), hipMemcpyHostToDevice, st));
             }
             APCHK(hipMemcpyAsync(H.d.boff, H.boff.data(), 4 * H.boff.size(), hipMemcpyHostToDevice, st));
-            APCHK(hipStreamSynchronize(st));   // host tables are reused by the next matrix
         }
+        APCHK(hipStreamSynchronize(st));   // the host tables stay untouched until the copies are done
         APCHK(hipMemcpyAsync(d_probs, act.data(), sizeof(ApProb) * nl, hipMemcpyHostToDevice, st));
         const int nrot = (int)rots.size();
         if (nrot > 0) {
