@@ -908,9 +908,11 @@ int stage1_run(const Stage1Batch &B, hipStream_t st)
         return hipGetLastError() == hipSuccess ? 0 : -1;
     }
     // ---- tridiagonalisation
-    // a few large matrices: the per-column kernels spread each column over
-    // chunks of 64 rows; a batch: one chunk per matrix (the batch fills the chip)
-    const int crows = np <= 4 ? kColRows : ((n + 63) / 64) * 64;
+    // large matrices: the per-column kernels spread each column over chunks of
+    // 64 rows; smaller ones: one chunk per matrix (batches of them fill the
+    // chip).  The choice depends on n only, so that a matrix's result does not
+    // depend on the batch it runs in.
+    const int crows = n >= 512 ? kColRows : ((n + 63) / 64) * 64;
     const int wrows = crows;
     const int npan = (n - 1 + kNB - 1) / kNB;
     for (int p = 0; p < npan; p++) {
