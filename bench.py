@@ -194,7 +194,7 @@ def _pct(x, q):
     return float(np.percentile(np.asarray(x), q)) * 1e3 if len(x) else None
 
 
-def serving_leg(Z, ctx, torch, count=200, load=0.7, tol=1e-30):
+def serving_leg(Z, ctx, torch, count=200, load=0.7, tol=1e-30, refine=0):
     """The serving workload: requests of sizes uniform over 16..512 (step 16),
     spectra 2^(-39 k/(s-1)), open-loop Poisson arrivals.
 
@@ -207,6 +207,7 @@ def serving_leg(Z, ctx, torch, count=200, load=0.7, tol=1e-30):
     import workloads as W
     sizes = W.serving_sizes()
     pool = {n: torch.from_numpy(W.workload(4, index=0, n=n)["A"]).cuda() for n in sizes}
+    opts = Z.make_opts(refine=refine)
     rng = np.random.Generator(np.random.PCG64(W.seed_for(4, 1)))
     order = [sizes[i] for i in rng.integers(0, len(sizes), count)]
 
@@ -215,14 +216,14 @@ def serving_leg(Z, ctx, torch, count=200, load=0.7, tol=1e-30):
 
     # warm-up (untimed): one request of every tenth size
     sess = Z.Session(ctx)
-    for t in [sess.submit([pool[n]]) for n in sizes[::10]]:
+    for t in [sess.submit([pool[n]], opts=opts) for n in sizes[::10]]:
         sess.result(t)
     sess.close()
 
     # 1. saturated
     sess = Z.Session(ctx)
     t0 = time.monotonic()
-    tickets = [sess.submit([pool[n]]) for n in order]
+    tickets = [sess.submit([pool[n]], opts=opts) for n in order]
     res = [sess.result(t) for t in tickets]
     t_end = max(sess.times(t)[2] for t in tickets)
     sess.close()
@@ -240,7 +241,7 @@ def serving_leg(Z, ctx, torch, count=200, load=0.7, tol=1e-30):
         dt = t0 + ta - time.monotonic()
         if dt > 0:
             time.sleep(dt)
-        tickets.append(sess.submit([pool[n]]))
+        tickets.append(sess.submit([pool[n]], opts=opts))
     res = [sess.result(t) for t in tickets]
     done = [sess.times(t)[2] for t in tickets]
     sess.close()
@@ -256,7 +257,7 @@ def serving_leg(Z, ctx, torch, count=200, load=0.7, tol=1e-30):
         dt = t0 + ta - time.monotonic()
         if dt > 0:
             time.sleep(dt)
-        Z.heev(ctx, [[pool[n]]], limbs_out=2)
+        Z.heev(ctx, [[pool[n]]], limbs_out=2, opts=opts)
         torch.cuda.synchronize()
         lat1.append(time.monotonic() - (t0 + ta))
     return {
@@ -423,6 +424,9 @@ def main():
     if args.serving_requests > 0:
         log("serving stream")
         out["serving"] = serving_leg(Z, ctx, torch, count=args.serving_requests)
+        if not args.no_allpairs_leg:
+            log("serving stream, all-pairs refinement")
+            out["serving_allpairs"] = serving_leg(Z, ctx, torch, count=args.serving_requests, refine=1)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline()

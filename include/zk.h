@@ -111,9 +111,13 @@ typedef struct {
     int reorth;           /* 1 (default): after the iteration, re-orthogonalise all eigenvectors of a
                              matrix (classical Gram-Schmidt twice, in the output precision) and
                              recompute every Rayleigh quotient and residual; 0: only inside clusters */
+    int refine;           /* 0 (default): per-pair Rayleigh quotient iteration (the paper's method);
+                             1: the all-pairs refinement of zk_heev_dd_allpairs (double-double output
+                             only; ZK_EINVAL with 4 output limbs).  Honoured by zk_heev_dd and by
+                             session requests; zk_rqi_refine always iterates per pair. */
 } zk_opts;
 
-/* Fill *o with the defaults (init_fp32 0, tol 0, max_iter 0, cluster_tol 0, want_vectors 1, reorth 1). */
+/* Fill *o with the defaults (init_fp32 0, tol 0, max_iter 0, cluster_tol 0, want_vectors 1, reorth 1, refine 0). */
 void zk_opts_default(zk_opts *o);
 
 /* Create a context on HIP device `device`.  hip_stream: a hipStream_t of the

@@ -41,7 +41,8 @@ class ZkEigOut(ctypes.Structure):
 
 class ZkOpts(ctypes.Structure):
     _fields_ = [("init_fp32", ctypes.c_int), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
-                ("cluster_tol", ctypes.c_double), ("want_vectors", ctypes.c_int), ("reorth", ctypes.c_int)]
+                ("cluster_tol", ctypes.c_double), ("want_vectors", ctypes.c_int), ("reorth", ctypes.c_int),
+                ("refine", ctypes.c_int)]
 
 
 KERNEL_CLASSES = ["lu_update", "lu_panel", "lu_trsm", "backsolve", "rq", "gs", "reorth", "stage1", "her2k", "hemv",
@@ -98,7 +99,8 @@ def status_str(s: int) -> str:
     return load().zk_status_str(int(s)).decode()
 
 
-def make_opts(tol=0.0, max_iter=0, cluster_tol=0.0, want_vectors=True, init_fp32=False, reorth=True) -> ZkOpts:
+def make_opts(tol=0.0, max_iter=0, cluster_tol=0.0, want_vectors=True, init_fp32=False, reorth=True,
+              refine=0) -> ZkOpts:
     o = ZkOpts()
     load().zk_opts_default(ctypes.byref(o))
     o.tol = float(tol)
@@ -107,6 +109,7 @@ def make_opts(tol=0.0, max_iter=0, cluster_tol=0.0, want_vectors=True, init_fp32
     o.want_vectors = int(bool(want_vectors))
     o.init_fp32 = int(bool(init_fp32))
     o.reorth = int(bool(reorth))
+    o.refine = int(refine)
     return o
 
 

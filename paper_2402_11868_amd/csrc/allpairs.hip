@@ -747,42 +747,6 @@ __global__ void __launch_bounds__(256) k_ap_output(const ApProb *pp, const ApOut
 inline unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
 inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Grow-only device buffer owned by one call.
-struct Scratch {
-    zk_ctx *ctx;
-    void *p = nullptr;
-    size_t bytes = 0;
-    explicit Scratch(zk_ctx *c) : ctx(c) {}
-    ~Scratch()
-    {
-        if (p) {
-            hipStreamSynchronize(ctx->stream);
-            hipFree(p);
-            ctx->extra -= bytes;
-        }
-    }
-    int ensure(size_t b)
-    {
-        if (b <= bytes) return ZK_OK;
-        if (p) {
-            hipStreamSynchronize(ctx->stream);
-            hipFree(p);
-            ctx->extra -= bytes;
-            p = nullptr;
-            bytes = 0;
-        }
-        if (ctx->held() + b > ctx->budget) return ctx->fail(ZK_ENOMEM, "all-pairs refinement needs %zu more bytes", b);
-        if (hipMalloc(&p, b) != hipSuccess) {
-            hipGetLastError();
-            p = nullptr;
-            return ctx->fail(ZK_ENOMEM, "hipMalloc of %zu bytes failed", b);
-        }
-        bytes = b;
-        ctx->extra += b;
-        return ZK_OK;
-    }
-};
-
 #define APCHK(expr)                                                                                   \
     do {                                                                                              \
         hipError_t e_ = (expr);                                                                       \
@@ -813,13 +777,18 @@ size_t ap_matrix_bytes(int n)
 
 struct HostProb {
     ApProb d;             // device pointers
-    int n;
-    double hnorm;
-    bool done = false, rotated_last = true, converged = false;
+    int n = 0, limbs_in = 1;
+    double hnorm = 1.0;
+    bool rotated_last = true, converged = false, inited = false, fin = false;
     int iters = 0;
+    double tol = 1e-30;
+    int max_iter = 12, want_vectors = 1;
+    zk_eig_out out;
+    void *cookie = nullptr;
+    int chunk = -1;
     std::vector<double> theta, rnorm, orth;   // theta: 2n
     std::vector<int> pos, srt, reach;         // sorted positions, sorted order, coupling reach
-    std::vector<int> cluster;           // sorted index of the first member of each pair's block
+    std::vector<int> cluster;                 // sorted index of the first member of each pair's block
     // block tables of this iteration
     std::vector<int> blk, loc, bcol, boff, brot, qoff;
     int nrot_cols = 0;
@@ -830,39 +799,141 @@ struct HostProb {
 
 }  // namespace
 
-// Runs the refinement for `count` matrices of equal order n whose binary64
-// stage is done (hf, w0, V0 as produced by run_stage1).  Writes out[] and the
-// per-pair info.  Returns ZK_OK, ZK_ENOCONV or an error status.
-int allpairs_run(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out *out, double tol, int max_iter, int want_vectors,
-                 const std::vector<double *> &hf, const std::vector<double *> &w0, const std::vector<double *> &V0,
-                 int *iters_used)
+// All-pairs refinement engine: matrices join with add() (their binary64 stage
+// done), every round() runs one whole-basis iteration for each live matrix
+// (matrices of equal order and input limbs share launches); a matrix that
+// meets the stopping rule, or reaches its iteration limit, is written to its
+// output in that round and listed in `finished`.  Device memory: one block per
+// add() call, released when its last matrix finishes.
+struct ApEngine::Impl {
+    zk_ctx *ctx;
+    std::vector<HostProb *> live;
+    struct Chunk {
+        void *p = nullptr;
+        size_t bytes = 0;
+        int left = 0;
+    };
+    std::vector<Chunk> chunks;
+    void *meta = nullptr;
+    size_t meta_bytes = 0;
+    bool trace = false;
+    explicit Impl(zk_ctx *c) : ctx(c) { trace = std::getenv("ZK_TRACE") != nullptr; }
+    ~Impl()
+    {
+        hipStreamSynchronize(ctx->stream);
+        for (HostProb *h : live) delete h;
+        for (Chunk &c : chunks)
+            if (c.p) {
+                hipFree(c.p);
+                ctx->extra -= c.bytes;
+            }
+        if (meta) {
+            hipFree(meta);
+            ctx->extra -= meta_bytes;
+        }
+    }
+    // room for b more bytes under the context budget; the shifted-LU slots of
+    // the Rayleigh-quotient engine are scratch between its rounds (it sizes
+    // them again, from what is left, at its next round), so they are given
+    // back when the budget is short
+    bool room(size_t b)
+    {
+        if (ctx->held() + b <= ctx->budget) return true;
+        if (ctx->s2lu.p) {
+            hipStreamSynchronize(ctx->stream);
+            ctx->s2lu.release();
+        }
+        return ctx->held() + b <= ctx->budget;
+    }
+    int ensure_meta(size_t b)
+    {
+        if (b <= meta_bytes) return ZK_OK;
+        if (meta) {
+            hipStreamSynchronize(ctx->stream);
+            hipFree(meta);
+            ctx->extra -= meta_bytes;
+            meta = nullptr;
+            meta_bytes = 0;
+        }
+        if (!room(b)) return ctx->fail(ZK_ENOMEM, "all-pairs descriptors need %zu more bytes", b);
+        if (hipMalloc(&meta, b) != hipSuccess) {
+            hipGetLastError();
+            meta = nullptr;
+            return ctx->fail(ZK_ENOMEM, "hipMalloc of %zu bytes failed", b);
+        }
+        meta_bytes = b;
+        ctx->extra += b;
+        return ZK_OK;
+    }
+    void release(HostProb *h)
+    {
+        Chunk &c = chunks[h->chunk];
+        if (--c.left == 0 && c.p) {
+            hipStreamSynchronize(ctx->stream);
+            hipFree(c.p);
+            ctx->extra -= c.bytes;
+            c.p = nullptr;
+            c.bytes = 0;
+        }
+        delete h;
+    }
+    int add(const std::vector<ApReq> &reqs);
+    int round(std::vector<ApDone> &finished);
+    int iterate(std::vector<HostProb *> &grp, std::vector<ApDone> &finished);
+    int output(std::vector<HostProb *> &done, std::vector<ApDone> &finished);
+};
+
+ApEngine::ApEngine(zk_ctx *ctx) : impl(new Impl(ctx)) {}
+ApEngine::~ApEngine() { delete impl; }
+bool ApEngine::any_live() const { return !impl->live.empty(); }
+int ApEngine::add(const std::vector<ApReq> &reqs) { return impl->add(reqs); }
+int ApEngine::round() { return impl->round(finished); }
+
+int ApEngine::Impl::add(const std::vector<ApReq> &reqs)
 {
+    if (reqs.empty()) return ZK_OK;
     hipStream_t st = ctx->stream;
-    const int n = A[0].n;
-    const size_t nn = (size_t)n * n;
-    int rc;
-    // one buffer: per-matrix arrays, then descriptor tables
-    const size_t per = ap_matrix_bytes(n);
-    const size_t s1per = al256(16 * nn) + al256(8 * (size_t)n) + al256(4 * (size_t)n);
-    const size_t meta = al256(sizeof(ApProb) * count) + al256(sizeof(DdGemm) * count) + al256(sizeof(GemmDesc) * count) +
-                        al256(sizeof(RotBlk) * (size_t)count * n) + al256(sizeof(ApOut) * count) + al256(4 * (size_t)count * n);
-    Scratch buf(ctx);
-    if ((rc = buf.ensure(per * count + s1per * count + meta)) != ZK_OK) return rc;
-    char *base = (char *)buf.p;
-    std::vector<HostProb> hp(count);
-    for (int p = 0; p < count; p++) {
-        char *c = base + per * p;
-        ApProb &D = hp[p].d;
+    size_t total = 0;
+    for (const ApReq &r : reqs) {
+        const size_t n = r.A.n, nn = n * n;
+        total += ap_matrix_bytes((int)n) + al256(16 * nn) + al256(8 * n) + al256(4 * n);
+    }
+    if (!room(total)) return ctx->fail(ZK_ENOMEM, "all-pairs refinement needs %zu more bytes", total);
+    Chunk ch;
+    if (hipMalloc(&ch.p, total) != hipSuccess) {
+        hipGetLastError();
+        return ctx->fail(ZK_ENOMEM, "hipMalloc of %zu bytes failed", total);
+    }
+    ch.bytes = total;
+    ch.left = (int)reqs.size();
+    ctx->extra += total;
+    chunks.push_back(ch);
+    const int cid = (int)chunks.size() - 1;
+    char *c = (char *)ch.p;
+    std::vector<HostProb *> fresh;
+    for (const ApReq &r : reqs) {
+        HostProb *H = new HostProb;
+        const int n = r.A.n;
+        const size_t nn = (size_t)n * n;
+        H->n = n;
+        H->limbs_in = r.A.limbs;
+        H->tol = r.tol;
+        H->max_iter = r.max_iter;
+        H->want_vectors = r.want_vectors;
+        H->out = r.out;
+        H->cookie = r.cookie;
+        H->chunk = cid;
+        ApProb &D = H->d;
         std::memset(&D, 0, sizeof D);
         D.n = n;
-        D.limbs_in = A[p].limbs;
-        D.hf = hf[p];
-        D.w0 = w0[p];
-        D.V0 = (const double2 *)V0[p];
+        D.limbs_in = r.A.limbs;
+        D.hf = r.hf;
+        D.w0 = r.w0;
+        D.V0 = (const double2 *)r.V0;
         auto take = [&](size_t b) {
-            char *r = c;
+            char *q = c;
             c += al256(b);
-            return r;
+            return q;
         };
         D.X = (double *)take(32 * nn);
         D.Xn = (double *)take(32 * nn);
@@ -891,13 +962,76 @@ int allpairs_run(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out *out, doub
         D.boff = (int *)take(4 * (size_t)n + 4);
         D.brot = (int *)take(4 * (size_t)n + 4);
         D.qoff = (int *)take(4 * (size_t)n + 4);
-        char *s = base + per * count + s1per * p;
-        hp[p].hf_s1 = (double *)s;
-        hp[p].w_s1 = (double *)(s + al256(16 * nn));
-        hp[p].flag_s1 = (int *)(s + al256(16 * nn) + al256(8 * (size_t)n));
-        hp[p].n = n;
+        H->hf_s1 = (double *)take(16 * nn);
+        H->w_s1 = (double *)take(8 * (size_t)n);
+        H->flag_s1 = (int *)take(4 * (size_t)n);
+        H->cluster.assign(n, -1);
+        fresh.push_back(H);
     }
-    char *mb = base + (per + s1per) * count;
+    // ||H||_2 from the binary64 eigenvalues
+    size_t tot_n = 0;
+    for (HostProb *H : fresh) tot_n += H->n;
+    std::vector<double> wv(tot_n);
+    size_t o = 0;
+    for (HostProb *H : fresh) {
+        APCHK(hipMemcpyAsync(wv.data() + o, H->d.w0, 8 * (size_t)H->n, hipMemcpyDeviceToHost, st));
+        o += H->n;
+    }
+    APCHK(hipStreamSynchronize(st));
+    o = 0;
+    for (HostProb *H : fresh) {
+        double h = 0.0;
+        for (int k = 0; k < H->n; k++) h = std::max(h, std::fabs(wv[o + k]));
+        H->hnorm = h > 0.0 ? h : 1.0;
+        o += H->n;
+        live.push_back(H);
+    }
+    return ZK_OK;
+}
+
+int ApEngine::Impl::round(std::vector<ApDone> &finished)
+{
+    // one group per number of input limbs (the residual kernel is specialised
+    // on it); matrices of different orders share every launch
+    std::vector<std::vector<HostProb *>> groups;
+    for (HostProb *H : live) {
+        bool placed = false;
+        for (auto &g : groups)
+            if (g[0]->limbs_in == H->limbs_in) {
+                g.push_back(H);
+                placed = true;
+                break;
+            }
+        if (!placed) groups.push_back(std::vector<HostProb *>(1, H));
+    }
+    for (auto &g : groups) {
+        int rc = iterate(g, finished);
+        if (rc != ZK_OK) return rc;
+    }
+    std::vector<HostProb *> keep;
+    for (HostProb *H : live) {
+        if (H->fin) release(H);
+        else keep.push_back(H);
+    }
+    live = keep;
+    return ZK_OK;
+}
+
+// one whole-basis iteration for matrices of equal input limbs (any orders):
+// grids are sized for the largest order, each block reads its matrix's order
+int ApEngine::Impl::iterate(std::vector<HostProb *> &grp, std::vector<ApDone> &finished)
+{
+    hipStream_t st = ctx->stream;
+    int n = 0;   // the largest order of the group
+    for (HostProb *H : grp) n = std::max(n, H->n);
+    const size_t nn = (size_t)n * n;
+    const int count = (int)grp.size();
+    int rc;
+    const size_t meta_need = al256(sizeof(ApProb) * count) + al256(sizeof(DdGemm) * count) + al256(sizeof(GemmDesc) * count) +
+                             al256(sizeof(RotBlk) * (size_t)count * n) + al256(sizeof(ApOut) * count) +
+                             al256(4 * (size_t)count * n);
+    if ((rc = ensure_meta(meta_need)) != ZK_OK) return rc;
+    char *mb = (char *)meta;
     ApProb *d_probs = (ApProb *)mb;
     mb += al256(sizeof(ApProb) * count);
     DdGemm *d_gemm = (DdGemm *)mb;
@@ -910,366 +1044,365 @@ int allpairs_run(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out *out, doub
     mb += al256(sizeof(ApOut) * count);
     int *d_perm = (int *)mb;
 
-    const bool trace = std::getenv("ZK_TRACE") != nullptr;
     KernelTimer *T = ctx->tp();
     auto tb = [&](int cls, double w) { return T ? T->begin(cls, w, st) : -1; };
     auto te = [&](int id) {
         if (T) T->end(id, st);
     };
-
-    std::vector<ApProb> act;
-    std::vector<int> ids;
-    auto upload_active = [&]() -> int {
-        act.clear();
-        ids.clear();
-        for (int p = 0; p < count; p++)
-            if (!hp[p].done) {
-                act.push_back(hp[p].d);
-                ids.push_back(p);
-            }
-        if (!act.empty()) APCHK(hipMemcpyAsync(d_probs, act.data(), sizeof(ApProb) * act.size(), hipMemcpyHostToDevice, st));
-        return ZK_OK;
-    };
-    // binary64 eigenvalues give ||H||_2
+    // start the matrices that joined since the last round
     {
-        std::vector<double> wv((size_t)count * n);
-        for (int p = 0; p < count; p++)
-            APCHK(hipMemcpyAsync(wv.data() + (size_t)p * n, w0[p], 8 * (size_t)n, hipMemcpyDeviceToHost, st));
-        APCHK(hipStreamSynchronize(st));
-        for (int p = 0; p < count; p++) {
-            double h = 0.0;
-            for (int k = 0; k < n; k++) h = std::max(h, std::fabs(wv[(size_t)p * n + k]));
-            hp[p].hnorm = h > 0.0 ? h : 1.0;
-        }
-    }
-    if ((rc = upload_active()) != ZK_OK) return rc;
-    {
-        const int id = tb(KC_AP_OTHER, 0.0);
-        hipLaunchKernelGGL(k_ap_init, dim3(std::min<unsigned>(cdiv(nn, 256), 4096), count), dim3(256), 0, st, d_probs);
-        te(id);
-        APLAUNCH();
-    }
-    const int tilesR = (int)(cdiv(n, 64) * cdiv(n, 16));
-    const int tilesG = (int)(cdiv(n, 64) * cdiv(n, 64));
-    std::vector<int> order(n);
-    for (int it = 0;; it++) {
-        if ((rc = upload_active()) != ZK_OK) return rc;
-        const int na = (int)act.size();
-        if (na == 0) break;
-        // residual matrix, column statistics, F, Rayleigh quotients
-        {
-            const int id = tb(KC_AP_RESID, (double)na * nn * n);
-            const int lin = A[0].limbs;
-            if (lin == 1)
-                hipLaunchKernelGGL(k_ap_resid<1>, dim3(tilesR, na), dim3(256), 0, st, d_probs);
-            else if (lin == 2)
-                hipLaunchKernelGGL(k_ap_resid<2>, dim3(tilesR, na), dim3(256), 0, st, d_probs);
-            else
-                hipLaunchKernelGGL(k_ap_resid<4>, dim3(tilesR, na), dim3(256), 0, st, d_probs);
-            te(id);
-            APLAUNCH();
-        }
-        {
+        std::vector<ApProb> fresh;
+        for (HostProb *H : grp)
+            if (!H->inited) fresh.push_back(H->d);
+        if (!fresh.empty()) {
+            APCHK(hipMemcpyAsync(d_probs, fresh.data(), sizeof(ApProb) * fresh.size(), hipMemcpyHostToDevice, st));
             const int id = tb(KC_AP_OTHER, 0.0);
-            hipLaunchKernelGGL(k_ap_colstats, dim3(n, na), dim3(256), 0, st, d_probs);
-            te(id);
-            APLAUNCH();
-        }
-        {
-            std::vector<GemmDesc> zg(na);
-            for (int q = 0; q < na; q++) {
-                zg[q].A = (const double *)act[q].Xh;
-                zg[q].B = (const double *)act[q].R;
-                zg[q].C = (double *)act[q].F;
-                zg[q].lda = zg[q].ldb = zg[q].ldc = n;
-                zg[q].pad = 0;
-            }
-            APCHK(hipMemcpyAsync(d_zg, zg.data(), sizeof(GemmDesc) * na, hipMemcpyHostToDevice, st));
-            const int id = tb(KC_AP_FGEMM, 8.0 * na * nn * n);
-            if (zgemm_batched(d_zg, na, n, n, n, 1, 0, st)) return ctx->fail(ZK_EDEVICE, "binary64 GEMM launch failed");
-            te(id);
-            APCHK(hipStreamSynchronize(st));   // zg goes out of scope
-        }
-        // G = X^H X in double-double, rounded to binary64 (its off-diagonal
-        // entries are small, so the rounding is relative to their own size)
-        {
-            std::vector<DdGemm> gd(na);
-            for (int q = 0; q < na; q++) {
-                DdGemm &G = gd[q];
-                std::memset(&G, 0, sizeof G);
-                G.A = act[q].X;
-                G.B = act[q].X;
-                G.Cz = act[q].Gf;
-                G.pa = G.pb = nn;
-                G.lda = G.ldb = G.ldc = n;
-                G.M = G.N = G.K = n;
-            }
-            APCHK(hipMemcpyAsync(d_gemm, gd.data(), sizeof(DdGemm) * na, hipMemcpyHostToDevice, st));
-            const int id = tb(KC_AP_DDGEMM, (double)na * nn * n);
-            hipLaunchKernelGGL((k_ap_ddgemm<true, true, false>), dim3(tilesG, na), dim3(256), 0, st, d_gemm);
+            hipLaunchKernelGGL(k_ap_init, dim3(std::min<unsigned>(cdiv(nn, 256), 4096), (unsigned)fresh.size()), dim3(256),
+                               0, st, d_probs);
             te(id);
             APLAUNCH();
             APCHK(hipStreamSynchronize(st));
-        }
-        {
-            const int id = tb(KC_AP_OTHER, 0.0);
-            hipLaunchKernelGGL(k_ap_theta, dim3(cdiv(n, 256), na), dim3(256), 0, st, d_probs);
-            hipLaunchKernelGGL(k_ap_orth, dim3(n, na), dim3(256), 0, st, d_probs);
-            te(id);
-            APLAUNCH();
-        }
-        // convergence
-        std::vector<int> live;
-        for (int q = 0; q < na; q++) {
-            HostProb &H = hp[ids[q]];
-            H.theta.resize(2 * (size_t)n);
-            H.rnorm.resize(n);
-            APCHK(hipMemcpyAsync(H.theta.data(), H.d.theta, 16 * (size_t)n, hipMemcpyDeviceToHost, st));
-            APCHK(hipMemcpyAsync(H.rnorm.data(), H.d.rnorm, 8 * (size_t)n, hipMemcpyDeviceToHost, st));
-            H.orth.resize(n);
-            APCHK(hipMemcpyAsync(H.orth.data(), H.d.orth, 8 * (size_t)n, hipMemcpyDeviceToHost, st));
-        }
-        APCHK(hipStreamSynchronize(st));
-        for (int q = 0; q < na; q++) {
-            HostProb &H = hp[ids[q]];
-            double rmax = 0.0, omax = 0.0;
-            bool finite = true;
-            for (int j = 0; j < n; j++) {
-                rmax = std::max(rmax, H.rnorm[j]);
-                omax = std::max(omax, H.orth[j]);
-                if (!(H.rnorm[j] == H.rnorm[j]) || !(H.orth[j] == H.orth[j])) finite = false;
-            }
-            if (trace)
-                std::fprintf(stderr, "[zk] all-pairs matrix %d iteration %d: max resid %.3e, max orth %.3e%s\n", ids[q], it,
-                             rmax / H.hnorm, omax, H.rotated_last ? " (after rotation)" : "");
-            if (finite && rmax <= 0.5 * tol * H.hnorm && omax <= tol && !H.rotated_last) {
-                H.done = true;
-                H.converged = true;
-            } else if (!finite || it >= max_iter) {
-                H.done = true;
-            } else {
-                live.push_back(q);
-            }
-            if (H.cluster.empty()) {
-                H.cluster.resize(n);
-                for (int j = 0; j < n; j++) H.cluster[j] = -1;
-            }
-        }
-        if (live.empty()) break;
-        // the problems that iterate: sorted positions, coupling, blocks
-        {
-            std::vector<ApProb> lv;
-            for (int q : live) lv.push_back(act[q]);
-            act = lv;
-            std::vector<int> lid;
-            for (int q : live) lid.push_back(ids[q]);
-            ids = lid;
-        }
-        const int nl = (int)act.size();
-        for (int q = 0; q < nl; q++) {
-            HostProb &H = hp[ids[q]];
-            std::iota(order.begin(), order.end(), 0);
-            const double *th = H.theta.data();
-            std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-                return th[a] < th[b] || (th[a] == th[b] && th[n + a] < th[n + b]);
-            });
-            H.pos.resize(n);
-            for (int k = 0; k < n; k++) H.pos[order[k]] = k;
-            APCHK(hipMemcpyAsync(H.d.pos, H.pos.data(), 4 * (size_t)n, hipMemcpyHostToDevice, st));
-            H.srt = order;
-        }
-        APCHK(hipMemcpyAsync(d_probs, act.data(), sizeof(ApProb) * nl, hipMemcpyHostToDevice, st));
-        {
-            const int id = tb(KC_AP_OTHER, 0.0);
-            hipLaunchKernelGGL(k_ap_couple, dim3(n, nl), dim3(256), 0, st, d_probs, kApEta);
-            te(id);
-            APLAUNCH();
-        }
-        std::vector<RotBlk> rots;
-        std::vector<zk_herm> s1h;
-        std::vector<double *> s1hf, s1w, s1V;
-        std::vector<int *> s1f;
-        int maxm = 0, nbc_max = 0;
-        for (int q = 0; q < nl; q++) {
-            HostProb &H = hp[ids[q]];
-            H.reach.resize(n);
-            APCHK(hipMemcpyAsync(H.reach.data(), H.d.reach, 4 * (size_t)n, hipMemcpyDeviceToHost, st));
-        }
-        APCHK(hipStreamSynchronize(st));
-        for (int q = 0; q < nl; q++) {
-            HostProb &H = hp[ids[q]];
-            const std::vector<int> &reach = H.reach;
-            const std::vector<int> &srt = H.srt;
-            // runs of the sorted order: a break before position p when nothing at or after p reaches below p
-            std::vector<std::pair<int, int>> runs;   // [start, end) in sorted positions
-            int end = n, runmin = n;
-            for (int p = n - 1; p >= 0; p--) {
-                runmin = std::min(runmin, reach[p]);
-                if (runmin >= p) {
-                    runs.push_back(std::make_pair(p, end));
-                    end = p;
-                }
-            }
-            std::reverse(runs.begin(), runs.end());
-            H.blk.assign(n, -1);
-            H.loc.assign(n, 0);
-            H.bcol.clear();
-            H.boff.clear();
-            H.brot.clear();
-            H.qoff.clear();
-            int qo = 0, nb = 0;
-            H.nrot_cols = 0;
-            for (const auto &r : runs) {
-                for (int p = r.first; p < r.second; p++) H.cluster[srt[p]] = r.first;
-                const int m = r.second - r.first;
-                if (m < 2) continue;
-                double rm = 0.0;
-                for (int p = r.first; p < r.second; p++) rm = std::max(rm, H.rnorm[srt[p]]);
-                const bool rot = rm > 0.25 * tol * H.hnorm;
-                H.boff.push_back((int)H.bcol.size());
-                for (int p = r.first; p < r.second; p++) {
-                    H.blk[srt[p]] = nb;
-                    H.loc[srt[p]] = p - r.first;
-                    H.bcol.push_back(srt[p]);
-                }
-                H.brot.push_back(rot ? 1 : 0);
-                H.qoff.push_back(rot ? qo : -1);
-                if (rot) {
-                    RotBlk rb;
-                    rb.prob = q;
-                    rb.b = nb;
-                    rots.push_back(rb);
-                    zk_herm h;
-                    std::memset(&h, 0, sizeof h);
-                    h.n = m;
-                    h.lda = m;
-                    h.limbs = 1;
-                    h.plane[0] = H.d.T + qo;
-                    s1h.push_back(h);
-                    // binary64-stage outputs: eigenvectors into Q, eigenvalues into th (by slot)
-                    s1V.push_back((double *)(H.d.Q + qo));
-                    s1w.push_back(H.d.th + H.bcol.size() - m);
-                    s1hf.push_back(H.hf_s1 + 2 * (size_t)qo);
-                    s1f.push_back(H.flag_s1 + (int)(H.boff.size() - 1) % n);
-                    qo += m * m;
-                    H.nrot_cols += m;
-                    maxm = std::max(maxm, m);
-                }
-                nb++;
-            }
-            H.boff.push_back((int)H.bcol.size());
-            H.d.nbc = (int)H.bcol.size();
-            if (trace) {
-                int mx = 0;
-                for (size_t b = 0; b + 1 < H.boff.size(); b++) mx = std::max(mx, H.boff[b + 1] - H.boff[b]);
-                std::fprintf(stderr, "[zk]   blocks %zu (largest %d, %d columns), rotated columns %d\n", H.brot.size(), mx,
-                             H.d.nbc, H.nrot_cols);
-            }
-            nbc_max = std::max(nbc_max, H.d.nbc);
-            maxm = std::max(maxm, 1);
-            act[q].nbc = H.d.nbc;
-            APCHK(hipMemcpyAsync(H.d.blk, H.blk.data(), 4 * (size_t)n, hipMemcpyHostToDevice, st));
-            APCHK(hipMemcpyAsync(H.d.loc, H.loc.data(), 4 * (size_t)n, hipMemcpyHostToDevice, st));
-            if (!H.bcol.empty()) {
-                APCHK(hipMemcpyAsync(H.d.bcol, H.bcol.data(), 4 * H.bcol.size(), hipMemcpyHostToDevice, st));
-                APCHK(hipMemcpyAsync(H.d.brot, H.brot.data(), 4 * H.brot.size(), hipMemcpyHostToDevice, st));
-                APCHK(hipMemcpyAsync(H.d.qoff, H.qoff.data(), 4 * H.qoff.size(), hipMemcpyHostToDevice, st));
-            }
-            APCHK(hipMemcpyAsync(H.d.boff, H.boff.data(), 4 * H.boff.size(), hipMemcpyHostToDevice, st));
-        }
-        APCHK(hipStreamSynchronize(st));   // the host tables stay untouched until the copies are done
-        APCHK(hipMemcpyAsync(d_probs, act.data(), sizeof(ApProb) * nl, hipMemcpyHostToDevice, st));
-        const int nrot = (int)rots.size();
-        if (nrot > 0) {
-            APCHK(hipMemcpyAsync(d_rot, rots.data(), sizeof(RotBlk) * nrot, hipMemcpyHostToDevice, st));
-            const int id = tb(KC_AP_OTHER, 0.0);
-            hipLaunchKernelGGL(k_ap_tbuild, dim3(cdiv((size_t)maxm * maxm, 256), nrot), dim3(256), 0, st, d_probs, d_rot);
-            te(id);
-            APLAUNCH();
-            // binary64 eigendecomposition of every projected block
-            if ((rc = run_stage1(ctx, nrot, s1h.data(), s1hf, s1w, s1V, s1f, std::vector<int>())) != ZK_OK) return rc;
-            const int id2 = tb(KC_AP_OTHER, 0.0);
-            hipLaunchKernelGGL(k_ap_fcols, dim3(cdiv(n, 256), maxm, nrot), dim3(256), 0, st, d_probs, d_rot, maxm);
-            hipLaunchKernelGGL(k_ap_gq, dim3(cdiv((size_t)maxm * maxm, 256), nrot), dim3(256), 0, st, d_probs, d_rot);
-            hipLaunchKernelGGL(k_ap_qhw, dim3(cdiv((size_t)maxm * maxm, 256), nrot), dim3(256), 0, st, d_probs, d_rot);
-            te(id2);
-            APLAUNCH();
-        }
-        {
-            const int id = tb(KC_AP_OTHER, 0.0);
-            hipLaunchKernelGGL(k_ap_ehat, dim3(cdiv(n, 256), n, nl), dim3(256), 0, st, d_probs);
-            hipLaunchKernelGGL(k_ap_mbuild, dim3(cdiv(n, 256), n, nl), dim3(256), 0, st, d_probs);
-            te(id);
-            APLAUNCH();
-        }
-        // X <- X + X M
-        {
-            std::vector<DdGemm> gd(nl);
-            for (int q = 0; q < nl; q++) {
-                DdGemm &G = gd[q];
-                std::memset(&G, 0, sizeof G);
-                G.A = act[q].X;
-                G.B = (const double *)act[q].M;
-                G.C0 = act[q].X;
-                G.C = act[q].Xn;
-                G.Cz = act[q].Xh;
-                G.pa = G.pc = nn;
-                G.lda = G.ldb = G.ldc = n;
-                G.M = G.N = G.K = n;
-            }
-            APCHK(hipMemcpyAsync(d_gemm, gd.data(), sizeof(DdGemm) * nl, hipMemcpyHostToDevice, st));
-            const int id = tb(KC_AP_DDGEMM, (double)nl * nn * n);
-            hipLaunchKernelGGL((k_ap_ddgemm<false, false, true>), dim3(tilesG, nl), dim3(256), 0, st, d_gemm);
-            te(id);
-            APLAUNCH();
-        }
-        {
-            const int id = tb(KC_AP_OTHER, 0.0);
-            hipLaunchKernelGGL(k_ap_lamset, dim3(cdiv(n, 256), nl), dim3(256), 0, st, d_probs);
-            te(id);
-            APLAUNCH();
-        }
-        APCHK(hipStreamSynchronize(st));
-        for (int q = 0; q < nl; q++) {
-            HostProb &H = hp[ids[q]];
-            std::swap(H.d.X, H.d.Xn);
-            H.rotated_last = nrot > 0 && H.nrot_cols > 0;
-            H.iters++;
+            for (HostProb *H : grp) H->inited = true;
         }
     }
-    // sorted outputs and per-pair information
-    int status = ZK_OK;
+    std::vector<ApProb> act;
+    for (HostProb *H : grp) act.push_back(H->d);
+    APCHK(hipMemcpyAsync(d_probs, act.data(), sizeof(ApProb) * count, hipMemcpyHostToDevice, st));
+    const int tilesR = (int)(cdiv(n, 64) * cdiv(n, 16));
+    const int tilesG = (int)(cdiv(n, 64) * cdiv(n, 64));
+    const int na = count;
+    // residual matrix, column statistics, F, G, Rayleigh quotients, orthonormality
+    {
+        double wk = 0.0;
+        for (int q = 0; q < na; q++) wk += (double)act[q].n * act[q].n * act[q].n;
+        const int id = tb(KC_AP_RESID, wk);
+        const int lin = grp[0]->limbs_in;
+        if (lin == 1)
+            hipLaunchKernelGGL(k_ap_resid<1>, dim3(tilesR, na), dim3(256), 0, st, d_probs);
+        else if (lin == 2)
+            hipLaunchKernelGGL(k_ap_resid<2>, dim3(tilesR, na), dim3(256), 0, st, d_probs);
+        else
+            hipLaunchKernelGGL(k_ap_resid<4>, dim3(tilesR, na), dim3(256), 0, st, d_probs);
+        te(id);
+        APLAUNCH();
+    }
+    {
+        const int id = tb(KC_AP_OTHER, 0.0);
+        hipLaunchKernelGGL(k_ap_colstats, dim3(n, na), dim3(256), 0, st, d_probs);
+        te(id);
+        APLAUNCH();
+    }
+    {
+        // F = X_hi^H R: one launch per order (the GEMM takes one shape per launch)
+        std::vector<GemmDesc> zg(na);
+        std::vector<int> ords;
+        for (int q = 0; q < na; q++)
+            if (std::find(ords.begin(), ords.end(), act[q].n) == ords.end()) ords.push_back(act[q].n);
+        int zo = 0;
+        double fl = 0.0;
+        std::vector<std::pair<int, int>> zr;   // (offset, count) per order
+        for (int m : ords) {
+            const int z0 = zo;
+            for (int q = 0; q < na; q++)
+                if (act[q].n == m) {
+                    GemmDesc &Z = zg[zo++];
+                    Z.A = (const double *)act[q].Xh;
+                    Z.B = (const double *)act[q].R;
+                    Z.C = (double *)act[q].F;
+                    Z.lda = Z.ldb = Z.ldc = m;
+                    Z.pad = 0;
+                    fl += 8.0 * m * (double)m * m;
+                }
+            zr.push_back(std::make_pair(z0, zo - z0));
+        }
+        APCHK(hipMemcpyAsync(d_zg, zg.data(), sizeof(GemmDesc) * na, hipMemcpyHostToDevice, st));
+        const int id = tb(KC_AP_FGEMM, fl);
+        for (size_t k = 0; k < ords.size(); k++)
+            if (zgemm_batched(d_zg + zr[k].first, zr[k].second, ords[k], ords[k], ords[k], 1, 0, st))
+                return ctx->fail(ZK_EDEVICE, "binary64 GEMM launch failed");
+        te(id);
+        // G = X^H X in double-double, rounded to binary64 (its off-diagonal
+        // entries are small, so the rounding is relative to their own size)
+        std::vector<DdGemm> gd(na);
+        double wk = 0.0;
+        for (int q = 0; q < na; q++) {
+            DdGemm &G = gd[q];
+            std::memset(&G, 0, sizeof G);
+            const int m = act[q].n;
+            G.A = act[q].X;
+            G.B = act[q].X;
+            G.Cz = act[q].Gf;
+            G.pa = G.pb = (size_t)m * m;
+            G.lda = G.ldb = G.ldc = m;
+            G.M = G.N = G.K = m;
+            wk += (double)m * m * m;
+        }
+        APCHK(hipMemcpyAsync(d_gemm, gd.data(), sizeof(DdGemm) * na, hipMemcpyHostToDevice, st));
+        const int id2 = tb(KC_AP_DDGEMM, wk);
+        hipLaunchKernelGGL((k_ap_ddgemm<true, true, false>), dim3(tilesG, na), dim3(256), 0, st, d_gemm);
+        te(id2);
+        APLAUNCH();
+        const int id3 = tb(KC_AP_OTHER, 0.0);
+        hipLaunchKernelGGL(k_ap_theta, dim3(cdiv(n, 256), na), dim3(256), 0, st, d_probs);
+        hipLaunchKernelGGL(k_ap_orth, dim3(n, na), dim3(256), 0, st, d_probs);
+        te(id3);
+        APLAUNCH();
+        for (HostProb *H : grp) {
+            const int m = H->n;
+            H->theta.resize(2 * (size_t)m);
+            H->rnorm.resize(m);
+            H->orth.resize(m);
+            APCHK(hipMemcpyAsync(H->theta.data(), H->d.theta, 16 * (size_t)m, hipMemcpyDeviceToHost, st));
+            APCHK(hipMemcpyAsync(H->rnorm.data(), H->d.rnorm, 8 * (size_t)m, hipMemcpyDeviceToHost, st));
+            APCHK(hipMemcpyAsync(H->orth.data(), H->d.orth, 8 * (size_t)m, hipMemcpyDeviceToHost, st));
+        }
+        APCHK(hipStreamSynchronize(st));   // zg, gd go out of scope; the statistics are on the host
+    }
+    // stopping rule
+    std::vector<HostProb *> done, lv;
+    for (HostProb *H : grp) {
+        double rmax = 0.0, omax = 0.0;
+        bool finite = true;
+        for (int j = 0; j < H->n; j++) {
+            rmax = std::max(rmax, H->rnorm[j]);
+            omax = std::max(omax, H->orth[j]);
+            if (!(H->rnorm[j] == H->rnorm[j]) || !(H->orth[j] == H->orth[j])) finite = false;
+        }
+        if (trace)
+            std::fprintf(stderr, "[zk] all-pairs n=%d iteration %d: max resid %.3e, max orth %.3e%s\n", H->n, H->iters,
+                         rmax / H->hnorm, omax, H->rotated_last ? " (after rotation)" : "");
+        if (finite && rmax <= 0.5 * H->tol * H->hnorm && omax <= H->tol && !H->rotated_last) {
+            H->converged = true;
+            done.push_back(H);
+        } else if (!finite || H->iters >= H->max_iter) {
+            done.push_back(H);
+        } else {
+            lv.push_back(H);
+        }
+    }
+    if (!done.empty() && (rc = output(done, finished)) != ZK_OK) return rc;
+    if (lv.empty()) return ZK_OK;
+    // the matrices that iterate: sorted positions, coupling, blocks
+    act.clear();
+    for (HostProb *H : lv) act.push_back(H->d);
+    const int nl = (int)lv.size();
+    for (HostProb *H : lv) {
+        const int m = H->n;
+        std::vector<int> order(m);
+        std::iota(order.begin(), order.end(), 0);
+        const double *th = H->theta.data();
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            return th[a] < th[b] || (th[a] == th[b] && th[m + a] < th[m + b]);
+        });
+        H->pos.resize(m);
+        for (int k = 0; k < m; k++) H->pos[order[k]] = k;
+        APCHK(hipMemcpyAsync(H->d.pos, H->pos.data(), 4 * (size_t)m, hipMemcpyHostToDevice, st));
+        H->srt = order;
+    }
+    APCHK(hipMemcpyAsync(d_probs, act.data(), sizeof(ApProb) * nl, hipMemcpyHostToDevice, st));
+    {
+        const int id = tb(KC_AP_OTHER, 0.0);
+        hipLaunchKernelGGL(k_ap_couple, dim3(n, nl), dim3(256), 0, st, d_probs, kApEta);
+        te(id);
+        APLAUNCH();
+    }
+    for (HostProb *H : lv) {
+        H->reach.resize(H->n);
+        APCHK(hipMemcpyAsync(H->reach.data(), H->d.reach, 4 * (size_t)H->n, hipMemcpyDeviceToHost, st));
+    }
+    APCHK(hipStreamSynchronize(st));
+    std::vector<RotBlk> rots;
+    std::vector<zk_herm> s1h;
+    std::vector<double *> s1hf, s1w, s1V;
+    std::vector<int *> s1f;
+    int maxm = 1;
+    for (int q = 0; q < nl; q++) {
+        HostProb &H = *lv[q];
+        const int n = H.n;   // this matrix's order (shadows the group's largest)
+        const std::vector<int> &reach = H.reach;
+        const std::vector<int> &srt = H.srt;
+        // runs of the sorted order: a break before position p when nothing at or after p reaches below p
+        std::vector<std::pair<int, int>> runs;   // [start, end) in sorted positions
+        int end = n, runmin = n;
+        for (int p = n - 1; p >= 0; p--) {
+            runmin = std::min(runmin, reach[p]);
+            if (runmin >= p) {
+                runs.push_back(std::make_pair(p, end));
+                end = p;
+            }
+        }
+        std::reverse(runs.begin(), runs.end());
+        H.blk.assign(n, -1);
+        H.loc.assign(n, 0);
+        H.bcol.clear();
+        H.boff.clear();
+        H.brot.clear();
+        H.qoff.clear();
+        int qo = 0, nb = 0, nblk_rot = 0;
+        H.nrot_cols = 0;
+        for (const auto &r : runs) {
+            for (int p = r.first; p < r.second; p++) H.cluster[srt[p]] = r.first;
+            const int m = r.second - r.first;
+            if (m < 2) continue;
+            double rm = 0.0;
+            for (int p = r.first; p < r.second; p++) rm = std::max(rm, H.rnorm[srt[p]]);
+            const bool rot = rm > 0.25 * H.tol * H.hnorm;
+            H.boff.push_back((int)H.bcol.size());
+            for (int p = r.first; p < r.second; p++) {
+                H.blk[srt[p]] = nb;
+                H.loc[srt[p]] = p - r.first;
+                H.bcol.push_back(srt[p]);
+            }
+            H.brot.push_back(rot ? 1 : 0);
+            H.qoff.push_back(rot ? qo : -1);
+            if (rot) {
+                RotBlk rb;
+                rb.prob = q;
+                rb.b = nb;
+                rots.push_back(rb);
+                zk_herm h;
+                std::memset(&h, 0, sizeof h);
+                h.n = m;
+                h.lda = m;
+                h.limbs = 1;
+                h.plane[0] = H.d.T + qo;
+                s1h.push_back(h);
+                // binary64-stage outputs: eigenvectors into Q, eigenvalues into th (by slot)
+                s1V.push_back((double *)(H.d.Q + qo));
+                s1w.push_back(H.d.th + H.bcol.size() - m);
+                s1hf.push_back(H.hf_s1 + 2 * (size_t)qo);
+                s1f.push_back(H.flag_s1 + (nblk_rot++ % n));
+                qo += m * m;
+                H.nrot_cols += m;
+                maxm = std::max(maxm, m);
+            }
+            nb++;
+        }
+        H.boff.push_back((int)H.bcol.size());
+        H.d.nbc = (int)H.bcol.size();
+        act[q].nbc = H.d.nbc;
+        if (trace) {
+            int mx = 0;
+            for (size_t b = 0; b + 1 < H.boff.size(); b++) mx = std::max(mx, H.boff[b + 1] - H.boff[b]);
+            std::fprintf(stderr, "[zk]   blocks %zu (largest %d, %d columns), rotated columns %d\n", H.brot.size(), mx,
+                         H.d.nbc, H.nrot_cols);
+        }
+        APCHK(hipMemcpyAsync(H.d.blk, H.blk.data(), 4 * (size_t)n, hipMemcpyHostToDevice, st));
+        APCHK(hipMemcpyAsync(H.d.loc, H.loc.data(), 4 * (size_t)n, hipMemcpyHostToDevice, st));
+        if (!H.bcol.empty()) {
+            APCHK(hipMemcpyAsync(H.d.bcol, H.bcol.data(), 4 * H.bcol.size(), hipMemcpyHostToDevice, st));
+            APCHK(hipMemcpyAsync(H.d.brot, H.brot.data(), 4 * H.brot.size(), hipMemcpyHostToDevice, st));
+            APCHK(hipMemcpyAsync(H.d.qoff, H.qoff.data(), 4 * H.qoff.size(), hipMemcpyHostToDevice, st));
+        }
+        APCHK(hipMemcpyAsync(H.d.boff, H.boff.data(), 4 * H.boff.size(), hipMemcpyHostToDevice, st));
+    }
+    APCHK(hipMemcpyAsync(d_probs, act.data(), sizeof(ApProb) * nl, hipMemcpyHostToDevice, st));
+    APCHK(hipStreamSynchronize(st));   // the host tables stay untouched until the copies are done
+    const int nrot = (int)rots.size();
+    if (nrot > 0) {
+        APCHK(hipMemcpyAsync(d_rot, rots.data(), sizeof(RotBlk) * nrot, hipMemcpyHostToDevice, st));
+        const int id = tb(KC_AP_OTHER, 0.0);
+        hipLaunchKernelGGL(k_ap_tbuild, dim3(cdiv((size_t)maxm * maxm, 256), nrot), dim3(256), 0, st, d_probs, d_rot);
+        te(id);
+        APLAUNCH();
+        // binary64 eigendecomposition of every projected block
+        if ((rc = run_stage1(ctx, nrot, s1h.data(), s1hf, s1w, s1V, s1f, std::vector<int>())) != ZK_OK) return rc;
+        const int id2 = tb(KC_AP_OTHER, 0.0);
+        hipLaunchKernelGGL(k_ap_fcols, dim3(cdiv(n, 256), maxm, nrot), dim3(256), 0, st, d_probs, d_rot, maxm);
+        hipLaunchKernelGGL(k_ap_gq, dim3(cdiv((size_t)maxm * maxm, 256), nrot), dim3(256), 0, st, d_probs, d_rot);
+        hipLaunchKernelGGL(k_ap_qhw, dim3(cdiv((size_t)maxm * maxm, 256), nrot), dim3(256), 0, st, d_probs, d_rot);
+        te(id2);
+        APLAUNCH();
+    }
+    {
+        const int id = tb(KC_AP_OTHER, 0.0);
+        hipLaunchKernelGGL(k_ap_ehat, dim3(cdiv(n, 256), n, nl), dim3(256), 0, st, d_probs);
+        hipLaunchKernelGGL(k_ap_mbuild, dim3(cdiv(n, 256), n, nl), dim3(256), 0, st, d_probs);
+        te(id);
+        APLAUNCH();
+    }
+    // X <- X + X M
+    {
+        std::vector<DdGemm> gd(nl);
+        double wk = 0.0;
+        for (int q = 0; q < nl; q++) {
+            DdGemm &G = gd[q];
+            std::memset(&G, 0, sizeof G);
+            const int m = act[q].n;
+            G.A = act[q].X;
+            G.B = (const double *)act[q].M;
+            G.C0 = act[q].X;
+            G.C = act[q].Xn;
+            G.Cz = act[q].Xh;
+            G.pa = G.pc = (size_t)m * m;
+            G.lda = G.ldb = G.ldc = m;
+            G.M = G.N = G.K = m;
+            wk += (double)m * m * m;
+        }
+        APCHK(hipMemcpyAsync(d_gemm, gd.data(), sizeof(DdGemm) * nl, hipMemcpyHostToDevice, st));
+        const int id = tb(KC_AP_DDGEMM, wk);
+        hipLaunchKernelGGL((k_ap_ddgemm<false, false, true>), dim3(tilesG, nl), dim3(256), 0, st, d_gemm);
+        te(id);
+        APLAUNCH();
+        const int id2 = tb(KC_AP_OTHER, 0.0);
+        hipLaunchKernelGGL(k_ap_lamset, dim3(cdiv(n, 256), nl), dim3(256), 0, st, d_probs);
+        te(id2);
+        APLAUNCH();
+        APCHK(hipStreamSynchronize(st));   // gd goes out of scope
+    }
+    for (HostProb *H : lv) {
+        std::swap(H->d.X, H->d.Xn);
+        H->rotated_last = H->nrot_cols > 0;
+        H->iters++;
+    }
+    return ZK_OK;
+}
+
+// sorted outputs and per-pair information of the matrices that stop
+int ApEngine::Impl::output(std::vector<HostProb *> &done, std::vector<ApDone> &finished)
+{
+    hipStream_t st = ctx->stream;
+    const int count = (int)done.size();
+    int n = 0;   // the largest order (permutation rows are n apart)
+    for (HostProb *H : done) n = std::max(n, H->n);
+    char *mb = (char *)meta;
+    ApProb *d_probs = (ApProb *)mb;   // rewritten below (the round's launches that used it are enqueued before)
+    mb += al256(sizeof(ApProb) * count);
+    (void)mb;
+    // the output descriptors go after the round's other tables (sized for the group)
+    const size_t off_out = meta_bytes - al256(sizeof(ApOut) * count) - al256(4 * (size_t)count * n);
+    ApOut *d_out = (ApOut *)((char *)meta + off_out);
+    int *d_perm = (int *)((char *)meta + off_out + al256(sizeof(ApOut) * count));
     std::vector<ApProb> all(count);
     std::vector<ApOut> ao(count);
     std::vector<int> perm_all((size_t)count * n);
     for (int p = 0; p < count; p++) {
-        HostProb &H = hp[p];
+        HostProb &H = *done[p];
+        const int m = H.n;
         all[p] = H.d;
-        std::vector<int> ord(n);
+        std::vector<int> ord(m);
         std::iota(ord.begin(), ord.end(), 0);
         const double *th = H.theta.data();
         std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
-            return th[a] < th[b] || (th[a] == th[b] && th[n + a] < th[n + b]);
+            return th[a] < th[b] || (th[a] == th[b] && th[m + a] < th[m + b]);
         });
-        std::vector<int> spos(n);
-        for (int k = 0; k < n; k++) spos[ord[k]] = k;
-        std::memcpy(&perm_all[(size_t)p * n], ord.data(), 4 * (size_t)n);
+        std::memcpy(&perm_all[(size_t)p * n], ord.data(), 4 * (size_t)m);
         ApOut &O = ao[p];
         std::memset(&O, 0, sizeof O);
-        O.w[0] = out[p].w[0];
-        O.w[1] = out[p].w[1];
-        O.v[0] = want_vectors ? (double2 *)out[p].v[0] : nullptr;
-        O.v[1] = want_vectors ? (double2 *)out[p].v[1] : nullptr;
-        O.ldv = out[p].ldv;
+        O.w[0] = H.out.w[0];
+        O.w[1] = H.out.w[1];
+        O.v[0] = H.want_vectors ? (double2 *)H.out.v[0] : nullptr;
+        O.v[1] = H.want_vectors ? (double2 *)H.out.v[1] : nullptr;
+        O.ldv = H.out.ldv;
         O.perm = d_perm + (size_t)p * n;
         bool all_ok = true;
-        for (int k = 0; k < n; k++) {
+        for (int k = 0; k < m; k++) {
             const int j = ord[k];
             const double r = H.rnorm[j] / H.hnorm;
-            const bool ok = (r == r) && H.rnorm[j] <= tol * H.hnorm;
+            const bool ok = (r == r) && H.rnorm[j] <= H.tol * H.hnorm;
             all_ok = all_ok && ok;
-            if (out[p].info) {
-                zk_pair_info &I = out[p].info[k];
+            if (H.out.info) {
+                zk_pair_info &I = H.out.info[k];
                 I.iters = H.iters;
                 I.flags = ok ? ZK_PAIR_CONVERGED : 0;
                 I.cluster = H.cluster[j] >= 0 ? H.cluster[j] : k;
@@ -1277,15 +1410,60 @@ int allpairs_run(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out *out, doub
                 I.resid = r;
             }
         }
-        if (!all_ok || !H.converged) status = ZK_ENOCONV;
-        if (iters_used) iters_used[p] = H.iters;
+        ApDone d;
+        d.cookie = H.cookie;
+        d.status = (all_ok && H.converged) ? ZK_OK : ZK_ENOCONV;
+        H.fin = true;
+        d.iters = H.iters;
+        finished.push_back(d);
     }
+    APCHK(hipStreamSynchronize(st));   // earlier launches of the round read the descriptor area
     APCHK(hipMemcpyAsync(d_perm, perm_all.data(), 4 * perm_all.size(), hipMemcpyHostToDevice, st));
     APCHK(hipMemcpyAsync(d_probs, all.data(), sizeof(ApProb) * count, hipMemcpyHostToDevice, st));
     APCHK(hipMemcpyAsync(d_out, ao.data(), sizeof(ApOut) * count, hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_ap_output, dim3(cdiv(n, 256), n, count), dim3(256), 0, st, d_probs, d_out);
     APLAUNCH();
     APCHK(hipStreamSynchronize(st));
+    return ZK_OK;
+}
+
+// device bytes the engine holds for one matrix of order n
+size_t ap_bytes(int n)
+{
+    const size_t nn = (size_t)n * n;
+    return ap_matrix_bytes(n) + al256(16 * nn) + al256(8 * (size_t)n) + al256(4 * (size_t)n);
+}
+
+// Synchronous use: `count` matrices whose binary64 stage is done (hf, w0, V0
+// as produced by run_stage1), refined until every one has stopped.  Returns
+// ZK_OK, ZK_ENOCONV or an error status.
+int allpairs_run(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out *out, double tol, int max_iter, int want_vectors,
+                 const std::vector<double *> &hf, const std::vector<double *> &w0, const std::vector<double *> &V0,
+                 int *iters_used)
+{
+    ApEngine eng(ctx);
+    std::vector<ApReq> reqs(count);
+    for (int p = 0; p < count; p++) {
+        ApReq &r = reqs[p];
+        r.A = A[p];
+        r.out = out[p];
+        r.hf = hf[p];
+        r.w0 = w0[p];
+        r.V0 = V0[p];
+        r.tol = tol;
+        r.max_iter = max_iter;
+        r.want_vectors = want_vectors;
+        r.cookie = (void *)(size_t)(p + 1);
+    }
+    int rc = eng.add(reqs);
+    if (rc != ZK_OK) return rc;
+    while (eng.any_live())
+        if ((rc = eng.round()) != ZK_OK) return rc;
+    int status = ZK_OK;
+    for (const ApDone &d : eng.finished) {
+        if (d.status != ZK_OK) status = ZK_ENOCONV;
+        if (iters_used) iters_used[(size_t)d.cookie - 1] = d.iters;
+    }
     return status;
 }
 

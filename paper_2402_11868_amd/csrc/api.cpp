@@ -44,6 +44,7 @@ extern "C" void zk_opts_default(zk_opts *o)
     o->cluster_tol = 0.0;
     o->want_vectors = 1;
     o->reorth = 1;
+    o->refine = 0;
 }
 
 extern "C" const char *zk_ctx_last_error(const zk_ctx *ctx) { return ctx ? ctx->err.c_str() : ""; }
@@ -80,6 +81,13 @@ extern "C" int zk_ctx_destroy(zk_ctx *ctx)
     hipSetDevice(ctx->device);
     hipStreamSynchronize(ctx->stream);
     for (DevBuf *b : {&ctx->s1, &ctx->s2in, &ctx->s2vec, &ctx->s2lu, &ctx->meta}) b->release();
+    for (hipStream_t &x : ctx->side)
+        if (x) {
+            hipStreamSynchronize(x);
+            hipStreamDestroy(x);
+        }
+    for (hipEvent_t &e : ctx->ev)
+        if (e) hipEventDestroy(e);
     if (ctx->own_stream) hipStreamDestroy(ctx->stream);
     delete ctx;
     return ZK_OK;
@@ -204,6 +212,8 @@ ResolvedOpts zk_resolve_opts(const zk_opts *o, int L)
     r.want_vectors = o ? (o->want_vectors != 0) : 1;
     r.init_fp32 = o ? o->init_fp32 : 0;
     r.reorth = o ? (o->reorth != 0) : 1;
+    r.refine = o ? o->refine : 0;
+    r.max_iter_set = (o && o->max_iter > 0) ? o->max_iter : 0;
     return r;
 }
 
@@ -263,72 +273,106 @@ static int carve_s2in(zk_ctx *ctx, int count, const zk_herm *A, std::vector<doub
     return ZK_OK;
 }
 
+// Descriptors of one stage-1 batch: np matrices of order n carved from `b`
+// (per-matrix scratch, then the descriptor tables), host copies in hp / hg.
+static char *carve_stage1(char *b, int n, const std::vector<int> &ids, size_t c0, int np, const zk_herm *A,
+                          const std::vector<double *> &hf, const std::vector<double *> &w0, const std::vector<double *> &V0,
+                          const std::vector<int *> &flag, std::vector<ProbDesc> &hp, std::vector<GemmDesc> &hg,
+                          ProbDesc *&d_probs, GemmDesc *&d_gemm)
+{
+    hp.assign(np, ProbDesc());
+    const size_t nn = (size_t)n * n, ntile = (size_t)(n + 63) / 64, npan = (size_t)(n + kNB - 1) / kNB + 1;
+    for (int q = 0; q < np; q++) {
+        const int i = ids[c0 + q];
+        ProbDesc &P = hp[q];
+        std::memset(&P, 0, sizeof P);
+        P.n = n;
+        P.lda_in = A[i].lda;
+        P.limbs_in = A[i].limbs;
+        for (int l = 0; l < A[i].limbs; l++) P.in[l] = (const double *)A[i].plane[l];
+        P.hf = hf[i];
+        P.w0 = w0[i];
+        P.V0 = V0[i];
+        P.flag = flag[i];
+        P.A = (double *)b; b += align_up(16 * nn);
+        P.Y = (double *)b; b += align_up(16 * nn);
+        P.tau = (double *)b; b += align_up(16 * (size_t)n);
+        P.P = (double *)b; b += align_up(16 * (size_t)n * 2 * kNB);
+        P.Q = (double *)b; b += align_up(16 * (size_t)n * 2 * kNB);
+        P.part = (double *)b; b += align_up(16 * 2 * ntile * n);
+        P.tri = (double *)b; b += align_up(8 * 5 * nn);
+        P.Zt = (double *)b; b += align_up(8 * nn);
+        P.d = (double *)b; b += align_up(8 * (size_t)n);
+        P.e = (double *)b; b += align_up(8 * (size_t)n);
+        P.cnt = (int *)b; b += align_up(8 * (size_t)n);
+        P.scr = (double *)b; b += align_up(8 * (ntile * (4 + 4 * (size_t)kNB) + 2));
+        P.Z = (double *)b; b += align_up(8 * nn);
+        P.T = (double *)b; b += align_up(16 * npan * kNB * kNB);
+        P.X = (double *)b; b += align_up(16 * (size_t)kNB * n);
+        P.X2 = (double *)b; b += align_up(16 * (size_t)kNB * n);
+        b += align_up(64);
+    }
+    d_probs = (ProbDesc *)b;
+    b += align_up(sizeof(ProbDesc) * np);
+    d_gemm = (GemmDesc *)b;
+    hg.assign(stage1_gemm_desc_count(n, np), GemmDesc());
+    if (n > 1) stage1_fill_gemm_descs(hp.data(), np, hg.data());
+    b += align_up(sizeof(GemmDesc) * hg.size());
+    return b;
+}
+
+static size_t stage1_batch_bytes(int n, int np)
+{
+    return (size_t)np * s1_bytes(n) + align_up(sizeof(ProbDesc) * np) + align_up(sizeof(GemmDesc) * stage1_gemm_desc_count(n, np));
+}
+
 // Stage 1 for `count` matrices into caller-chosen buffers: hf (limb-planar
 // copy, 2*limbs*n*n doubles), w0 (n), V0 (n*n complex), flag (int, zeroed
-// here); ZK_EINVAL on non-finite input.
+// here); ZK_EINVAL on non-finite input.  Matrices are batched by order; when
+// every batch fits the budget at once, batches of different orders run
+// concurrently on the context stream and up to three side streams (each
+// batch is a chain of small per-column launches, so they overlap well).
 int run_stage1(zk_ctx *ctx, int count, const zk_herm *A, const std::vector<double *> &hf, const std::vector<double *> &w0,
                const std::vector<double *> &V0, const std::vector<int *> &flag, const std::vector<int> &fp32)
 {
     hipStream_t st = ctx->stream;
     int rc;
     for (int i = 0; i < count; i++) HIPCHK(hipMemsetAsync(flag[i], 0, 4, st));
-    // stage 1, grouped by order and variant, as many matrices at a time as the budget allows
     std::map<std::pair<int, int>, std::vector<int>> groups;
     for (int i = 0; i < count; i++) groups[std::make_pair(A[i].n, fp32.empty() ? 0 : (fp32[i] ? 1 : 0))].push_back(i);
-    for (auto &kv : groups) {
-        const int n = kv.first.first;
-        const std::vector<int> &ids = kv.second;
-        const size_t per = s1_bytes(n);
-        size_t avail = ctx->budget > ctx->held() - ctx->s1.bytes ? ctx->budget - (ctx->held() - ctx->s1.bytes) : 0;
-        int chunk = (int)std::min<size_t>(ids.size(), avail / std::max<size_t>(per, 1));
-        if (chunk < 1) return ctx->fail(ZK_ENOMEM, "binary64 stage of order %d needs %zu bytes", n, per);
-        if ((rc = ctx->ensure(ctx->s1, (size_t)chunk * per + align_up(sizeof(ProbDesc) * chunk) +
-                                           align_up(sizeof(GemmDesc) * stage1_gemm_desc_count(n, chunk)))) != ZK_OK)
-            return rc;
-        for (size_t c0 = 0; c0 < ids.size(); c0 += (size_t)chunk) {
-            const int np = (int)std::min<size_t>((size_t)chunk, ids.size() - c0);
-            std::vector<ProbDesc> hp(np);
-            char *b = (char *)ctx->s1.p;
-            const size_t nn = (size_t)n * n, ntile = (size_t)(n + 63) / 64, npan = (size_t)(n + kNB - 1) / kNB + 1;
-            for (int q = 0; q < np; q++) {
-                const int i = ids[c0 + q];
-                ProbDesc &P = hp[q];
-                std::memset(&P, 0, sizeof P);
-                P.n = n;
-                P.lda_in = A[i].lda;
-                P.limbs_in = A[i].limbs;
-                for (int l = 0; l < A[i].limbs; l++) P.in[l] = (const double *)A[i].plane[l];
-                P.hf = hf[i];
-                P.w0 = w0[i];
-                P.V0 = V0[i];
-                P.flag = flag[i];
-                P.A = (double *)b; b += align_up(16 * nn);
-                P.Y = (double *)b; b += align_up(16 * nn);
-                P.tau = (double *)b; b += align_up(16 * (size_t)n);
-                P.P = (double *)b; b += align_up(16 * (size_t)n * 2 * kNB);
-                P.Q = (double *)b; b += align_up(16 * (size_t)n * 2 * kNB);
-                P.part = (double *)b; b += align_up(16 * 2 * ntile * n);
-                P.tri = (double *)b; b += align_up(8 * 5 * nn);
-                P.Zt = (double *)b; b += align_up(8 * nn);
-                P.d = (double *)b; b += align_up(8 * (size_t)n);
-                P.e = (double *)b; b += align_up(8 * (size_t)n);
-                P.cnt = (int *)b; b += align_up(8 * (size_t)n);
-                P.scr = (double *)b; b += align_up(8 * (ntile * (4 + 4 * (size_t)kNB) + 2));
-                P.Z = (double *)b; b += align_up(8 * nn);
-                P.T = (double *)b; b += align_up(16 * npan * kNB * kNB);
-                P.X = (double *)b; b += align_up(16 * (size_t)kNB * n);
-                P.X2 = (double *)b; b += align_up(16 * (size_t)kNB * n);
-                b += align_up(64);
-            }
+    size_t total = 0;
+    for (auto &kv : groups) total += stage1_batch_bytes(kv.first.first, (int)kv.second.size());
+    const size_t avail = ctx->budget > ctx->held() - ctx->s1.bytes ? ctx->budget - (ctx->held() - ctx->s1.bytes) : 0;
+    if (groups.size() > 1 && total <= avail) {
+        if ((rc = ctx->ensure(ctx->s1, total)) != ZK_OK) return rc;
+        for (int k = 0; k < 3; k++)
+            if (!ctx->side[k]) HIPCHK(hipStreamCreateWithFlags(&ctx->side[k], hipStreamNonBlocking));
+        for (int k = 0; k < 4; k++)
+            if (!ctx->ev[k]) HIPCHK(hipEventCreateWithFlags(&ctx->ev[k], hipEventDisableTiming));
+        // the side streams start after everything already enqueued on the context stream
+        HIPCHK(hipEventRecord(ctx->ev[0], st));
+        for (int k = 0; k < 3; k++) HIPCHK(hipStreamWaitEvent(ctx->side[k], ctx->ev[0], 0));
+        std::vector<std::vector<ProbDesc>> hps(groups.size());
+        std::vector<std::vector<GemmDesc>> hgs(groups.size());
+        char *b = (char *)ctx->s1.p;
+        int gi = 0;
+        bool used[3] = {false, false, false};
+        for (auto &kv : groups) {
+            const int n = kv.first.first;
+            const std::vector<int> &ids = kv.second;
+            const int np = (int)ids.size();
+            const int lane = gi % 4;
+            hipStream_t sg = lane == 0 ? st : ctx->side[lane - 1];
+            if (lane > 0) used[lane - 1] = true;
+            ProbDesc *d_probs;
+            GemmDesc *d_gemm;
+            std::vector<ProbDesc> &hp = hps[gi];
+            std::vector<GemmDesc> &hg = hgs[gi];
+            b = carve_stage1(b, n, ids, 0, np, A, hf, w0, V0, flag, hp, hg, d_probs, d_gemm);
             // the reflector array must start zero (entries above row c+1 are read as zeros)
-            for (int q = 0; q < np; q++) HIPCHK(hipMemsetAsync(hp[q].Y, 0, 16 * nn, st));
-            ProbDesc *d_probs = (ProbDesc *)b;
-            b += align_up(sizeof(ProbDesc) * np);
-            GemmDesc *d_gemm = (GemmDesc *)b;
-            std::vector<GemmDesc> hg(stage1_gemm_desc_count(n, np));
-            if (n > 1) stage1_fill_gemm_descs(hp.data(), np, hg.data());
-            HIPCHK(hipMemcpyAsync(d_probs, hp.data(), sizeof(ProbDesc) * np, hipMemcpyHostToDevice, st));
-            if (!hg.empty()) HIPCHK(hipMemcpyAsync(d_gemm, hg.data(), sizeof(GemmDesc) * hg.size(), hipMemcpyHostToDevice, st));
+            for (int q = 0; q < np; q++) HIPCHK(hipMemsetAsync(hp[q].Y, 0, 16 * (size_t)n * n, sg));
+            HIPCHK(hipMemcpyAsync(d_probs, hp.data(), sizeof(ProbDesc) * np, hipMemcpyHostToDevice, sg));
+            if (!hg.empty()) HIPCHK(hipMemcpyAsync(d_gemm, hg.data(), sizeof(GemmDesc) * hg.size(), hipMemcpyHostToDevice, sg));
             Stage1Batch S1;
             S1.n = n;
             S1.nprob = np;
@@ -337,19 +381,59 @@ int run_stage1(zk_ctx *ctx, int count, const zk_herm *A, const std::vector<doubl
             S1.tri_gap_rel = 1e-12;
             S1.fp32 = kv.first.second;
             S1.timer = ctx->tp();
-            const int t1 = S1.timer ? S1.timer->begin(KC_STAGE1, (double)np, st) : -1;
-            if (stage1_run(S1, st)) return ctx->fail(ZK_EDEVICE, "stage1 launch failed: %s", hipGetErrorString(hipGetLastError()));
-            if (S1.timer) S1.timer->end(t1, st);
-            HIPCHK(hipStreamSynchronize(st));   // host descriptor arrays go out of scope
+            const int t1 = S1.timer ? S1.timer->begin(KC_STAGE1, (double)np, sg) : -1;
+            if (stage1_run(S1, sg)) return ctx->fail(ZK_EDEVICE, "stage1 launch failed: %s", hipGetErrorString(hipGetLastError()));
+            if (S1.timer) S1.timer->end(t1, sg);
+            gi++;
+        }
+        // join: the context stream waits for every side stream that ran a batch
+        for (int k = 0; k < 3; k++)
+            if (used[k]) {
+                HIPCHK(hipEventRecord(ctx->ev[k + 1], ctx->side[k]));
+                HIPCHK(hipStreamWaitEvent(st, ctx->ev[k + 1], 0));
+            }
+        HIPCHK(hipStreamSynchronize(st));   // host descriptor arrays go out of scope
+    } else {
+        // one batch at a time, as many matrices of a batch as the budget allows
+        for (auto &kv : groups) {
+            const int n = kv.first.first;
+            const std::vector<int> &ids = kv.second;
+            const size_t per = s1_bytes(n);
+            const size_t av = ctx->budget > ctx->held() - ctx->s1.bytes ? ctx->budget - (ctx->held() - ctx->s1.bytes) : 0;
+            int chunk = (int)std::min<size_t>(ids.size(), av / std::max<size_t>(per, 1));
+            if (chunk < 1) return ctx->fail(ZK_ENOMEM, "binary64 stage of order %d needs %zu bytes", n, per);
+            if ((rc = ctx->ensure(ctx->s1, stage1_batch_bytes(n, chunk))) != ZK_OK) return rc;
+            for (size_t c0 = 0; c0 < ids.size(); c0 += (size_t)chunk) {
+                const int np = (int)std::min<size_t>((size_t)chunk, ids.size() - c0);
+                std::vector<ProbDesc> hp;
+                std::vector<GemmDesc> hg;
+                ProbDesc *d_probs;
+                GemmDesc *d_gemm;
+                carve_stage1((char *)ctx->s1.p, n, ids, c0, np, A, hf, w0, V0, flag, hp, hg, d_probs, d_gemm);
+                for (int q = 0; q < np; q++) HIPCHK(hipMemsetAsync(hp[q].Y, 0, 16 * (size_t)n * n, st));
+                HIPCHK(hipMemcpyAsync(d_probs, hp.data(), sizeof(ProbDesc) * np, hipMemcpyHostToDevice, st));
+                if (!hg.empty()) HIPCHK(hipMemcpyAsync(d_gemm, hg.data(), sizeof(GemmDesc) * hg.size(), hipMemcpyHostToDevice, st));
+                Stage1Batch S1;
+                S1.n = n;
+                S1.nprob = np;
+                S1.dev_probs = d_probs;
+                S1.dev_gemm = d_gemm;
+                S1.tri_gap_rel = 1e-12;
+                S1.fp32 = kv.first.second;
+                S1.timer = ctx->tp();
+                const int t1 = S1.timer ? S1.timer->begin(KC_STAGE1, (double)np, st) : -1;
+                if (stage1_run(S1, st)) return ctx->fail(ZK_EDEVICE, "stage1 launch failed: %s", hipGetErrorString(hipGetLastError()));
+                if (S1.timer) S1.timer->end(t1, st);
+                HIPCHK(hipStreamSynchronize(st));   // host descriptor arrays go out of scope
+            }
         }
     }
     // non-finite input?
-    for (int i = 0; i < count; i++) {
-        int f = 0;
-        HIPCHK(hipMemcpyAsync(&f, flag[i], 4, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        if (f) return ctx->fail(ZK_EINVAL, "matrix %d has NaN/Inf entries", i);
-    }
+    std::vector<int> fl(count, 0);
+    for (int i = 0; i < count; i++) HIPCHK(hipMemcpyAsync(&fl[i], flag[i], 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int i = 0; i < count; i++)
+        if (fl[i]) return ctx->fail(ZK_EINVAL, "matrix %d has NaN/Inf entries", i);
     return ZK_OK;
 }
 
@@ -401,7 +485,7 @@ int allpairs_run(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out *out, doub
                  int *iters_used);
 }
 
-extern "C" int zk_heev_dd_allpairs(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out *out, const zk_opts *opts)
+static int run_heev_allpairs(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out *out, const zk_opts *opts)
 {
     if (!ctx) return ZK_EINVAL;
     if (ctx->poisoned) return ctx->fail(ZK_EDEVICE, "context poisoned by an earlier device error");
@@ -442,6 +526,11 @@ extern "C" int zk_heev_dd_allpairs(zk_ctx *ctx, int count, const zk_herm *A, zk_
     return status;
 }
 
+extern "C" int zk_heev_dd_allpairs(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out *out, const zk_opts *opts)
+{
+    return run_heev_allpairs(ctx, count, A, out, opts);
+}
+
 extern "C" int zk_heev_fp64(zk_ctx *ctx, int count, const zk_herm *A, double *const *w, void *const *V, const int *ldv)
 {
     if (!ctx) return ZK_EINVAL;
@@ -469,11 +558,13 @@ extern "C" int zk_heev_fp64(zk_ctx *ctx, int count, const zk_herm *A, double *co
 
 extern "C" int zk_heev_dd(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out *out, const zk_opts *opts)
 {
+    if (opts && opts->refine == 1) return run_heev_allpairs(ctx, count, A, out, opts);
     return run_heev<2>(ctx, count, A, out, opts, nullptr);
 }
 
 extern "C" int zk_heev_qd(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out *out, const zk_opts *opts)
 {
+    if (opts && opts->refine != 0) return ctx ? ctx->fail(ZK_EINVAL, "the all-pairs refinement gives double-double output only") : ZK_EINVAL;
     return run_heev<4>(ctx, count, A, out, opts, nullptr);
 }
 

@@ -7,6 +7,7 @@
 #include <string>
 #include <vector>
 
+#include "../../include/zk.h"
 #include "stage.h"
 
 struct DevBuf {
@@ -34,6 +35,10 @@ struct zk_ctx {
     DevBuf s2lu;    // shifted-LU slots
     DevBuf meta;    // descriptor tables
     size_t extra = 0;        // per-matrix iterate buffers held by stage-2 engines
+    // side streams (default priority) on which the binary64 stage runs groups
+    // of different orders concurrently, and the events that join them
+    hipStream_t side[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     zk::KernelTimer timer;   // per-kernel-class HIP-event timing (instrumentation)
     zk::KernelTimer *tp() { return timer.on ? &timer : nullptr; }
     size_t held() const;
@@ -48,3 +53,41 @@ struct Stage2Stats {
     long long solves = 0;
     std::vector<int> active_per_iter;
 };
+
+namespace zk {
+// One matrix for the all-pairs refinement (its binary64 stage done: hf, w0,
+// V0 as produced by run_stage1), and the record of a finished one.
+struct ApReq {
+    zk_herm A;
+    zk_eig_out out;
+    const double *hf, *w0, *V0;
+    double tol;
+    int max_iter, want_vectors;
+    void *cookie;
+};
+struct ApDone {
+    void *cookie;
+    int status;
+    int iters;
+};
+// device bytes the all-pairs engine holds for one matrix of order n
+size_t ap_bytes(int n);
+// The all-pairs refinement engine (allpairs.hip): add() matrices, round()
+// runs one whole-basis iteration for every live one; stopped matrices are
+// written to their outputs and appended to `finished` (cleared by the caller).
+class ApEngine {
+public:
+    explicit ApEngine(zk_ctx *ctx);
+    ~ApEngine();
+    ApEngine(const ApEngine &) = delete;
+    ApEngine &operator=(const ApEngine &) = delete;
+    int add(const std::vector<ApReq> &reqs);
+    bool any_live() const;
+    int round();
+    std::vector<ApDone> finished;
+    struct Impl;
+
+private:
+    Impl *impl;
+};
+}  // namespace zk

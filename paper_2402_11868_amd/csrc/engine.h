@@ -39,6 +39,8 @@ struct ResolvedOpts {
     int want_vectors;
     int init_fp32;
     int reorth;
+    int refine;
+    int max_iter_set;   // the caller's max_iter (0: default)
 };
 
 inline size_t s2_align(size_t x) { return (x + 255) & ~(size_t)255; }

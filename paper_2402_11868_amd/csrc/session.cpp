@@ -65,11 +65,12 @@ struct Request {
     S2Prob prob;
 };
 
-size_t footprint(int n, int limbs_in, int L)
+size_t footprint(int n, int limbs_in, int L, int refine)
 {
     const size_t nn = (size_t)n * n;
-    return al(8 * 2 * (size_t)limbs_in * nn) + al(8 * (size_t)n) + al(16 * nn) + al(64) +   // inputs of stage 2
-           al(8 * 2 * (size_t)L * nn) + al(8 * (size_t)L * n);                              // iterates
+    const size_t in = al(8 * 2 * (size_t)limbs_in * nn) + al(8 * (size_t)n) + al(16 * nn) + al(64);   // inputs of stage 2
+    if (refine == 1) return in + zk::ap_bytes(n);                                               // all-pairs state
+    return in + al(8 * 2 * (size_t)L * nn) + al(8 * (size_t)L * n);                             // iterates
 }
 
 }  // namespace
@@ -89,11 +90,13 @@ struct zk_session {
     int fatal = ZK_OK;
     Stage2Engine<2> *e2 = nullptr;
     Stage2Engine<4> *e4 = nullptr;
+    zk::ApEngine *ap = nullptr;   // requests with the all-pairs refinement
     std::vector<Request *> running;
 
     void loop();
     int admit_and_start(std::vector<Request *> &fresh);
     template <int L> void finish(Stage2Engine<L> *e);
+    void finish_ap();
 };
 
 int zk_session::admit_and_start(std::vector<Request *> &fresh)
@@ -128,8 +131,23 @@ int zk_session::admit_and_start(std::vector<Request *> &fresh)
     int rc = run_stage1(ctx, cnt, A.data(), hf, w0, V0, flag, fp32);
     if (rc != ZK_OK) return rc;
     std::vector<S2Prob *> b2, b4;
+    std::vector<zk::ApReq> ba;
     for (int i = 0; i < cnt; i++) {
         Request *r = fresh[i];
+        if (r->O.refine == 1) {
+            zk::ApReq q;
+            q.A = r->A;
+            q.out = r->out;
+            q.hf = hf[i];
+            q.w0 = w0[i];
+            q.V0 = V0[i];
+            q.tol = r->O.tol;
+            q.max_iter = r->O.max_iter_set > 0 ? r->O.max_iter_set : 12;
+            q.want_vectors = r->O.want_vectors;
+            q.cookie = r;
+            ba.push_back(q);
+            continue;
+        }
         S2Prob &p = r->prob;
         std::memset(&p.rp, 0, sizeof p.rp);
         p.rp.n = r->A.n;
@@ -151,7 +169,28 @@ int zk_session::admit_and_start(std::vector<Request *> &fresh)
     }
     if (!b2.empty() && (rc = e2->add(b2)) != ZK_OK) return rc;
     if (!b4.empty() && (rc = e4->add(b4)) != ZK_OK) return rc;
+    if (!ba.empty() && (rc = ap->add(ba)) != ZK_OK) return rc;
     return ZK_OK;
+}
+
+void zk_session::finish_ap()
+{
+    if (ap->finished.empty()) return;
+    const double t = now_s();
+    std::lock_guard<std::mutex> g(mu);
+    for (const zk::ApDone &d : ap->finished) {
+        Request *r = (Request *)d.cookie;
+        if (r->inbuf) {
+            hipFree(r->inbuf);
+            r->inbuf = nullptr;
+        }
+        r->status = d.status;
+        r->state = RQ_DONE;
+        r->t_done = t;
+        inflight -= r->foot;
+    }
+    ap->finished.clear();
+    cv_done.notify_all();
 }
 
 template <int L>
@@ -182,7 +221,7 @@ void zk_session::loop()
         std::vector<Request *> fresh;
         {
             std::unique_lock<std::mutex> lk(mu);
-            if (!stop && queue.empty() && !e2->any_live() && !e4->any_live())
+            if (!stop && queue.empty() && !e2->any_live() && !e4->any_live() && !ap->any_live())
                 cv_work.wait(lk, [&] { return stop || !queue.empty(); });
             if (stop) break;
             // admission by footprint, in arrival order
@@ -199,8 +238,10 @@ void zk_session::loop()
         if (!fresh.empty()) rc = admit_and_start(fresh);
         if (rc == ZK_OK && e2->any_live()) rc = e2->round();
         if (rc == ZK_OK && e4->any_live()) rc = e4->round();
+        if (rc == ZK_OK && ap->any_live()) rc = ap->round();
         finish<2>(e2);
         finish<4>(e4);
+        finish_ap();
         if (rc != ZK_OK) {
             // a device or resource failure ends every admitted request
             std::lock_guard<std::mutex> g(mu);
@@ -217,8 +258,10 @@ void zk_session::loop()
             cv_done.notify_all();
             delete e2;
             delete e4;
+            delete ap;
             e2 = new Stage2Engine<2>(ctx, zk_resolve_opts(nullptr, 2), nullptr);
             e4 = new Stage2Engine<4>(ctx, zk_resolve_opts(nullptr, 4), nullptr);
+            ap = new zk::ApEngine(ctx);
         }
     }
 }
@@ -234,6 +277,7 @@ extern "C" int zk_session_create(zk_ctx *ctx, size_t budget, int max_queue, zk_s
     s->max_queue = max_queue > 0 ? max_queue : 1 << 20;
     s->e2 = new Stage2Engine<2>(ctx, zk_resolve_opts(nullptr, 2), nullptr);
     s->e4 = new Stage2Engine<4>(ctx, zk_resolve_opts(nullptr, 4), nullptr);
+    s->ap = new zk::ApEngine(ctx);
     s->th = std::thread([s] { s->loop(); });
     *out = s;
     return ZK_OK;
@@ -245,7 +289,8 @@ extern "C" int zk_session_submit(zk_session *s, const zk_herm *A, zk_eig_out *ou
     if (!s || !A || !out || !ticket || (limbs_out != 2 && limbs_out != 4)) return ZK_EINVAL;
     const ResolvedOpts O = zk_resolve_opts(opts, limbs_out);
     if (zk_check_request(*A, *out, limbs_out, O.want_vectors) != ZK_OK) return ZK_EINVAL;
-    const size_t foot = footprint(A->n, A->limbs, limbs_out);
+    if (O.refine != 0 && (O.refine != 1 || limbs_out != 2)) return ZK_EINVAL;
+    const size_t foot = footprint(A->n, A->limbs, limbs_out, O.refine);
     if (foot > s->budget) return ZK_ENOMEM;
     Request *r = new Request();
     r->A = *A;
@@ -311,6 +356,7 @@ extern "C" int zk_session_destroy(zk_session *s)
     hipStreamSynchronize(s->ctx->stream);
     delete s->e2;   // releases the iterate storage of unfinished requests
     delete s->e4;
+    delete s->ap;
     {
         std::lock_guard<std::mutex> g(s->mu);
         for (auto &kv : s->all) {

@@ -7,6 +7,7 @@ the clustered 1024x1024 workload (clusters of 8 at relative separation 1e-12
 with centres down to 2^-50), the batch of 256 matrices of order 128, exact
 degeneracies and zero eigenvalues, limb inputs, n = 1 and mixed orders.
 """
+import time
 from fractions import Fraction
 
 import numpy as np
@@ -153,3 +154,37 @@ def test_allpairs_clustered_1024_against_golden(zk):
     sample = np.r_[0:8, 336:352, 500:508, 1016:1024]
     out = judge([A], res, gold, DD_TOL, orth_tol=DD_ORTH, sample=sample)
     log(f"all-pairs clustered 1024: {out}")
+
+
+def test_allpairs_refine_option_and_session(zk):
+    """zk_heev_dd with opts.refine = 1 is the all-pairs entry point; session
+    requests with refine = 1 run in the all-pairs engine with continuous
+    batching (a request that arrives while others iterate joins at the next
+    whole-basis iteration) and give the same bits as alone."""
+    Z, ctx, torch = zk
+    mats = [W.householder_hermitian(W.spectrum_c4(n), seed=W.seed_for(4, n) + 13 * i)
+            for i, n in enumerate([16, 48, 32, 80, 16, 64, 24, 96])]
+    dev = [torch.from_numpy(A).cuda() for A in mats]
+    opts = Z.make_opts(refine=1)
+    alone = [Z.heev_allpairs(ctx, [[d]])[0] for d in dev]
+    via_opt, = Z.heev(ctx, [[dev[3]]], limbs_out=2, opts=opts)
+    torch.cuda.synchronize()
+    assert torch.equal(via_opt.w, alone[3].w) and torch.equal(via_opt.V, alone[3].V)
+    sess = Z.Session(ctx, budget=256 << 20)
+    tickets = []
+    for d in dev[:4]:
+        tickets.append(sess.submit([d], opts=opts))
+    time.sleep(0.02)
+    for d in dev[4:]:
+        tickets.append(sess.submit([d], opts=opts))
+        time.sleep(0.005)
+    mixed = [sess.result(t) for t in tickets]
+    sess.close()
+    for i, (a, m) in enumerate(zip(alone, mixed)):
+        assert m.status == Z.ZK_OK, f"request {i}: status {m.status}"
+        assert torch.equal(a.w, m.w), f"request {i}: eigenvalues differ alone vs mix"
+        assert torch.equal(a.V, m.V), f"request {i}: eigenvectors differ alone vs mix"
+    for i in (0, 7):
+        judge([mats[i]], mixed[i], oracle.heev([mats[i]], want_vectors=False).w_limbs, DD_TOL, orth_tol=DD_ORTH)
+    with pytest.raises(RuntimeError):
+        Z.heev(ctx, [[dev[0]]], limbs_out=4, opts=opts)
