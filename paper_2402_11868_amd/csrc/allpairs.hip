@@ -40,6 +40,7 @@
 #include <vector>
 
 #include "../../include/zk.h"
+#include "ap_host.h"
 #include "api_internal.h"
 #include "common.h"
 #include "stage.h"
@@ -1188,12 +1189,8 @@ int ApEngine::Impl::iterate(std::vector<HostProb *> &grp, std::vector<ApDone> &f
     const int nl = (int)lv.size();
     for (HostProb *H : lv) {
         const int m = H->n;
-        std::vector<int> order(m);
-        std::iota(order.begin(), order.end(), 0);
-        const double *th = H->theta.data();
-        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-            return th[a] < th[b] || (th[a] == th[b] && th[m + a] < th[m + b]);
-        });
+        std::vector<int> order;
+        ap_sorted_order(H->theta.data(), m, order);
         H->pos.resize(m);
         for (int k = 0; k < m; k++) H->pos[order[k]] = k;
         APCHK(hipMemcpyAsync(H->d.pos, H->pos.data(), 4 * (size_t)m, hipMemcpyHostToDevice, st));
@@ -1221,17 +1218,8 @@ int ApEngine::Impl::iterate(std::vector<HostProb *> &grp, std::vector<ApDone> &f
         const int n = H.n;   // this matrix's order (shadows the group's largest)
         const std::vector<int> &reach = H.reach;
         const std::vector<int> &srt = H.srt;
-        // runs of the sorted order: a break before position p when nothing at or after p reaches below p
         std::vector<std::pair<int, int>> runs;   // [start, end) in sorted positions
-        int end = n, runmin = n;
-        for (int p = n - 1; p >= 0; p--) {
-            runmin = std::min(runmin, reach[p]);
-            if (runmin >= p) {
-                runs.push_back(std::make_pair(p, end));
-                end = p;
-            }
-        }
-        std::reverse(runs.begin(), runs.end());
+        ap_runs(reach.data(), n, runs);
         H.blk.assign(n, -1);
         H.loc.assign(n, 0);
         H.bcol.clear();
@@ -1380,12 +1368,8 @@ int ApEngine::Impl::output(std::vector<HostProb *> &done, std::vector<ApDone> &f
         HostProb &H = *done[p];
         const int m = H.n;
         all[p] = H.d;
-        std::vector<int> ord(m);
-        std::iota(ord.begin(), ord.end(), 0);
-        const double *th = H.theta.data();
-        std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
-            return th[a] < th[b] || (th[a] == th[b] && th[m + a] < th[m + b]);
-        });
+        std::vector<int> ord;
+        ap_sorted_order(H.theta.data(), m, ord);
         std::memcpy(&perm_all[(size_t)p * n], ord.data(), 4 * (size_t)m);
         ApOut &O = ao[p];
         std::memset(&O, 0, sizeof O);
