@@ -14,6 +14,12 @@ Contents
   V^H V on returned limbs exactly as returned.
 * ``exact`` -- closed forms and exact rational pins used to check the Jacobi
   solver itself (characteristic polynomial roots at n <= 4, invariants).
+* ``svd`` / ``svd_residuals`` -- singular values of a general matrix as the
+  nonnegative eigenvalues of its Hermitian dilation [[0, A], [A^H, 0]]
+  (eigenvalues +-s_j and |m - n| zeros; Golub & Van Loan, Matrix
+  Computations, Sec. 8.6), by the same MPFR Jacobi solver, and the MPFR
+  residuals ||A v - s u||, ||A^H u - s v|| of returned triplets.  The paper
+  lists the SVD beside the eigendecomposition (Sec. 2).
 """
 from __future__ import annotations
 
@@ -158,3 +164,39 @@ def gram(v_limbs, prec: int = DEFAULT_PREC, nthreads=None, full: bool = False):
     if rc != 0:
         raise RuntimeError(f"oracle or_gram failed: {rc}")
     return (mo.value, md.value, g) if full else (mo.value, md.value)
+
+
+def _dilation(planes):
+    """Limb planes of K = [[0, A], [A^H, 0]] for A given as limb planes (m x n)."""
+    out = []
+    for A in planes:
+        A = np.asarray(A, dtype=np.complex128)
+        m, n = A.shape
+        K = np.zeros((m + n, m + n), dtype=np.complex128)
+        K[:m, m:] = A
+        K[m:, :m] = A.conj().T
+        out.append(K)
+    return out
+
+
+def svd(planes, prec: int = DEFAULT_PREC, nthreads=None) -> np.ndarray:
+    """(4, k) limbs of the k = min(m, n) singular values of sum(planes), descending."""
+    planes = [np.asarray(p, dtype=np.complex128) for p in planes]
+    m, n = planes[0].shape
+    k = min(m, n)
+    r = heev(_dilation(planes), want_vectors=False, prec=prec, nthreads=nthreads)
+    # the k largest eigenvalues of the dilation, descending
+    return np.ascontiguousarray(r.w_limbs[:, ::-1][:, :k])
+
+
+def svd_residuals(planes, s_limbs, u_limbs, v_limbs, prec: int = DEFAULT_PREC, nthreads=None):
+    """For each returned triplet: sqrt(||A v - s u||^2 + ||A^H u - s v||^2) / ||[u; v]||
+    (the residual of [u; v] as an eigenvector of the dilation for +s), in MPFR,
+    and ||[u; v]||.  u_limbs: (L, m, k), v_limbs: (L, n, k), s_limbs: (Ls, k)."""
+    u_limbs = np.asarray(u_limbs, dtype=np.complex128)
+    v_limbs = np.asarray(v_limbs, dtype=np.complex128)
+    if u_limbs.ndim == 2:
+        u_limbs, v_limbs = u_limbs[None], v_limbs[None]
+    x = np.concatenate([u_limbs, v_limbs], axis=1)
+    return residuals(_dilation(planes), s_limbs, x, prec=prec, nthreads=nthreads)
+
