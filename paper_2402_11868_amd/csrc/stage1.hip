@@ -620,8 +620,14 @@ __global__ void k_invit(ProbDesc *probs)
             a = na - l * b;
             b = nb;
         } else {
-            const double l = a / sub;
-            U0[o] = sub; U1[o] = na; U2[o] = nb; LM[o] = l; FL[o] = 1.0;
+            // rows exchanged: the pivot is the subdiagonal entry, which can be
+            // far below the guard (a split or nearly split T); unclamped, its
+            // direction would be amplified by 1 / |sub| instead of 1 / guard
+            // and every member of a cluster would collapse onto it
+            double piv = sub;
+            if (fabs(piv) < guard) piv = (piv < 0.0) ? -guard : guard;
+            const double l = a / piv;
+            U0[o] = piv; U1[o] = na; U2[o] = nb; LM[o] = l; FL[o] = 1.0;
             a = b - l * na;
             b = -l * nb;
         }
