@@ -173,6 +173,52 @@ int zk_heev_qd(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out *out, const 
  */
 int zk_heev_dd_allpairs(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out *out, const zk_opts *opts);
 
+/* A general complex matrix: plane[0..limbs-1] are device pointers to m x n
+ * complex128 column-major arrays with leading dimension lda (elements). */
+typedef struct {
+    int m;
+    int n;
+    int lda;
+    int limbs;            /* 1, 2 or 4 */
+    const void *plane[4];
+} zk_mat;
+
+/* Output of one singular value decomposition, k = min(m, n): s[l] (device)
+ * limb l of the k singular values in DESCENDING order; u[l] (device) limb l of
+ * the left singular vectors, m x k complex128 column-major, leading dimension
+ * ldu; v[l] likewise for the right singular vectors (n x k, ldv); u, v may be
+ * NULL when opts->want_vectors == 0.  info: HOST array of k entries (the
+ * information of the eigenpair each triplet comes from), or NULL. */
+typedef struct {
+    int m;
+    int n;
+    int limbs;            /* 2 (double-double) */
+    double *s[4];
+    void *u[4];
+    int ldu;
+    void *v[4];
+    int ldv;
+    zk_pair_info *info;
+} zk_svd_out;
+
+/*
+ * zk_svd_dd: singular value decomposition A = U diag(s) V^H of `count`
+ * general complex matrices to double-double accuracy.  The paper lists the
+ * SVD beside the eigendecomposition for its GPU extension, with the same
+ * precision recovery (Sec. 2).  Method: the Hermitian dilation
+ * K = [[0, A], [A^H, 0]] of order m + n is eigendecomposed exactly as by
+ * zk_heev_dd (binary64 stage, then the Rayleigh quotient iteration, or the
+ * all-pairs refinement with opts->refine = 1); its eigenvalues are +-s_j and
+ * |m - n| zeros, the eigenvector of +s_j is [u_j; v_j] / sqrt(2).  No
+ * squaring: the bound is |s_j - s~_j| <= tol * s_1 and
+ * ||A v_j - s_j u_j||, ||A^H u_j - s_j v_j|| <= tol * s_1 (tol as in
+ * zk_heev_dd).  Singular vectors of singular values below tol * s_1 are not
+ * unique (they span the null spaces) and are not specified.  Synchronous.
+ * Errors: as zk_heev_dd, and ZK_EINVAL for m < 1, n < 1, lda < m, out->limbs
+ * != 2, ldu < m or ldv < n.
+ */
+int zk_svd_dd(zk_ctx *ctx, int count, const zk_mat *A, zk_svd_out *out, const zk_opts *opts);
+
 /*
  * zk_heev_fp64: stage 1 alone (the binary64 eigendecomposition that seeds the
  * Rayleigh quotient iteration).  For each matrix i: w[i] (device, n doubles,

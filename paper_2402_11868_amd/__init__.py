@@ -39,6 +39,17 @@ class ZkEigOut(ctypes.Structure):
                 ("w", ctypes.c_void_p * 4), ("v", ctypes.c_void_p * 4), ("info", ctypes.POINTER(ZkPairInfo))]
 
 
+class ZkMat(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int), ("n", ctypes.c_int), ("lda", ctypes.c_int), ("limbs", ctypes.c_int),
+                ("plane", ctypes.c_void_p * 4)]
+
+
+class ZkSvdOut(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int), ("n", ctypes.c_int), ("limbs", ctypes.c_int), ("s", ctypes.c_void_p * 4),
+                ("u", ctypes.c_void_p * 4), ("ldu", ctypes.c_int), ("v", ctypes.c_void_p * 4), ("ldv", ctypes.c_int),
+                ("info", ctypes.POINTER(ZkPairInfo))]
+
+
 class ZkOpts(ctypes.Structure):
     _fields_ = [("init_fp32", ctypes.c_int), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("cluster_tol", ctypes.c_double), ("want_vectors", ctypes.c_int), ("reorth", ctypes.c_int),
@@ -49,7 +60,7 @@ KERNEL_CLASSES = ["lu_update", "lu_panel", "lu_trsm", "backsolve", "rq", "gs", "
                   "build", "trd_vec", "tridiag", "backt", "ap_resid", "ap_fgemm", "ap_ddgemm", "ap_other"]
 
 EXPORTED = ["zk_prof_enable", "zk_prof_reset", "zk_prof_read", "zk_opts_default", "zk_ctx_create", "zk_ctx_destroy", "zk_status_str", "zk_ctx_last_error",
-            "zk_workspace_bytes", "zk_heev_dd", "zk_heev_qd", "zk_heev_dd_allpairs", "zk_heev_fp64", "zk_rqi_refine",
+            "zk_workspace_bytes", "zk_heev_dd", "zk_heev_qd", "zk_heev_dd_allpairs", "zk_svd_dd", "zk_heev_fp64", "zk_rqi_refine",
             "zk_session_create", "zk_session_submit", "zk_session_poll", "zk_session_times", "zk_session_destroy"]
 
 _lib = None
@@ -76,6 +87,7 @@ def load(path: str = LIB_PATH):
     lib.zk_workspace_bytes.restype = ctypes.c_size_t
     for f in ("zk_heev_dd", "zk_heev_qd", "zk_heev_dd_allpairs"):
         getattr(lib, f).argtypes = [P, I, ctypes.POINTER(ZkHerm), ctypes.POINTER(ZkEigOut), ctypes.POINTER(ZkOpts)]
+    lib.zk_svd_dd.argtypes = [P, I, ctypes.POINTER(ZkMat), ctypes.POINTER(ZkSvdOut), ctypes.POINTER(ZkOpts)]
     lib.zk_heev_fp64.argtypes = [P, I, ctypes.POINTER(ZkHerm), ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(I)]
     lib.zk_rqi_refine.argtypes = [P, I, ctypes.POINTER(ZkHerm), I, P, P, I, ctypes.POINTER(ZkEigOut), ctypes.POINTER(ZkOpts)]
     if hasattr(lib, "zk_heev_stats"):
@@ -269,6 +281,55 @@ def heev_allpairs(ctx: Context, mats, opts: ZkOpts | None = None):
     if rc not in (ZK_OK, ZK_ENOCONV):
         raise RuntimeError(f"zk_heev_dd_allpairs failed: {status_str(rc)}: {ctx.last_error()}")
     return [EigResult(w, V, _info_list(info, n), rc) for (w, V, info, n) in outs]
+
+
+class SvdResult:
+    """s: (2, k) float64 limbs (descending); U: (2, m, k), V: (2, n, k) complex128 limbs; info: list of dicts."""
+
+    def __init__(self, s, U, V, info, status):
+        self.s, self.U, self.V, self.info, self.status = s, U, V, info, status
+
+
+def svd(ctx: Context, mats, opts: ZkOpts | None = None):
+    """Double-double singular value decomposition (zk_svd_dd) of a list of
+    general matrices, each an (m, n) tensor or a list of limb tensors."""
+    lib = load()
+    keep: list = []
+    count = len(mats)
+    A = (ZkMat * count)()
+    O = (ZkSvdOut * count)()
+    outs = []
+    want = True if opts is None else bool(opts.want_vectors)
+    for i, mat in enumerate(mats):
+        planes = [mat] if isinstance(mat, torch.Tensor) else list(mat)
+        m, n = planes[0].shape
+        dev = planes[0].device
+        A[i].m, A[i].n, A[i].lda, A[i].limbs = m, n, m, len(planes)
+        for l, p in enumerate(planes):
+            if p.dtype != torch.complex128 or not p.is_cuda or p.dim() != 2 or tuple(p.shape) != (m, n):
+                raise ValueError("matrices must be complex128 CUDA tensors of one shape per matrix")
+            c = p.transpose(0, 1).contiguous()   # column-major storage
+            keep.append(c)
+            A[i].plane[l] = c.data_ptr()
+        k = min(m, n)
+        s = torch.zeros((2, k), dtype=torch.float64, device=dev)
+        ub = torch.zeros((2, k, m), dtype=torch.complex128, device=dev) if want else None
+        vb = torch.zeros((2, k, n), dtype=torch.complex128, device=dev) if want else None
+        o = O[i]
+        o.m, o.n, o.limbs, o.ldu, o.ldv = m, n, 2, m, n
+        for l in range(2):
+            o.s[l] = s[l].data_ptr()
+            o.u[l] = ub[l].data_ptr() if want else None
+            o.v[l] = vb[l].data_ptr() if want else None
+        info = (ZkPairInfo * k)()
+        o.info = ctypes.cast(info, ctypes.POINTER(ZkPairInfo))
+        keep += [s, ub, vb, info]
+        outs.append((s, ub.transpose(1, 2) if want else None, vb.transpose(1, 2) if want else None, info, k))
+    op = ctypes.byref(opts) if opts is not None else None
+    rc = lib.zk_svd_dd(ctx.handle, count, A, O, op)
+    if rc not in (ZK_OK, ZK_ENOCONV):
+        raise RuntimeError(f"zk_svd_dd failed: {status_str(rc)}: {ctx.last_error()}")
+    return [SvdResult(s, U, V, _info_list(info, k), rc) for (s, U, V, info, k) in outs]
 
 
 def ctx_device(m):

@@ -531,6 +531,121 @@ extern "C" int zk_heev_dd_allpairs(zk_ctx *ctx, int count, const zk_herm *A, zk_
     return run_heev_allpairs(ctx, count, A, out, opts);
 }
 
+extern "C" int zk_svd_dd(zk_ctx *ctx, int count, const zk_mat *A, zk_svd_out *out, const zk_opts *opts)
+{
+    if (!ctx) return ZK_EINVAL;
+    if (ctx->poisoned) return ctx->fail(ZK_EDEVICE, "context poisoned by an earlier device error");
+    if (count < 1 || !A || !out) return ctx->fail(ZK_EINVAL, "count < 1 or NULL arrays");
+    const ResolvedOpts O = zk_resolve_opts(opts, 2);
+    for (int i = 0; i < count; i++) {
+        const zk_mat &a = A[i];
+        const zk_svd_out &o = out[i];
+        bool bad = a.m < 1 || a.n < 1 || a.lda < a.m || (a.limbs != 1 && a.limbs != 2 && a.limbs != 4);
+        for (int l = 0; !bad && l < a.limbs; l++) bad = !a.plane[l];
+        bad = bad || o.m != a.m || o.n != a.n || o.limbs != 2 || !o.s[0] || !o.s[1];
+        if (!bad && O.want_vectors) bad = !o.u[0] || !o.u[1] || !o.v[0] || !o.v[1] || o.ldu < a.m || o.ldv < a.n;
+        if (bad) return ctx->fail(ZK_EINVAL, "matrix %d: bad m/n/lda/limbs/planes or output descriptor", i);
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess) return ctx->fail(ZK_EDEVICE, "hipSetDevice failed");
+    hipStream_t st = ctx->stream;
+    // per matrix: K (limbs planes), eigenvalues (2 limbs), eigenvectors (2 limb planes)
+    std::vector<size_t> off(count + 1, 0);
+    for (int i = 0; i < count; i++) {
+        const size_t N = (size_t)A[i].m + A[i].n;
+        off[i + 1] = off[i] + align_up(16 * N * N * A[i].limbs) + 2 * align_up(8 * N) + 2 * align_up(16 * N * N);
+    }
+    if (ctx->held() + off[count] > ctx->budget) return ctx->fail(ZK_ENOMEM, "the dilations need %zu bytes", off[count]);
+    void *buf = nullptr;
+    if (hipMalloc(&buf, off[count]) != hipSuccess) {
+        hipGetLastError();
+        return ctx->fail(ZK_ENOMEM, "hipMalloc of %zu bytes failed", off[count]);
+    }
+    ctx->extra += off[count];
+    std::vector<SvdDesc> D(count);
+    std::vector<zk_herm> K(count);
+    std::vector<zk_eig_out> E(count);
+    std::vector<std::vector<zk_pair_info>> inf(count);
+    int rc = ZK_OK;
+    for (int i = 0; i < count && rc == ZK_OK; i++) {
+        const int m = A[i].m, n = A[i].n, N = m + n;
+        const size_t NN = (size_t)N * N;
+        char *b = (char *)buf + off[i];
+        SvdDesc &d = D[i];
+        std::memset(&d, 0, sizeof d);
+        d.m = m;
+        d.n = n;
+        d.lda = A[i].lda;
+        d.limbs = A[i].limbs;
+        for (int l = 0; l < A[i].limbs; l++) d.A[l] = (const double *)A[i].plane[l];
+        d.K = (double *)b;
+        b += align_up(16 * NN * A[i].limbs);
+        double *w0 = (double *)b;
+        b += align_up(8 * (size_t)N);
+        double *w1 = (double *)b;
+        b += align_up(8 * (size_t)N);
+        double *v0 = (double *)b;
+        b += align_up(16 * NN);
+        double *v1 = (double *)b;
+        d.w[0] = w0;
+        d.w[1] = w1;
+        d.V[0] = v0;
+        d.V[1] = v1;
+        d.s[0] = out[i].s[0];
+        d.s[1] = out[i].s[1];
+        if (O.want_vectors) {
+            d.u[0] = (double *)out[i].u[0];
+            d.u[1] = (double *)out[i].u[1];
+            d.v[0] = (double *)out[i].v[0];
+            d.v[1] = (double *)out[i].v[1];
+            d.ldu = out[i].ldu;
+            d.ldv = out[i].ldv;
+        }
+        if (svd_build(d, st)) rc = ctx->fail(ZK_EDEVICE, "dilation build failed");
+        zk_herm &h = K[i];
+        std::memset(&h, 0, sizeof h);
+        h.n = N;
+        h.lda = N;
+        h.limbs = A[i].limbs;
+        for (int l = 0; l < A[i].limbs; l++) h.plane[l] = d.K + 2 * NN * l;
+        zk_eig_out &e = E[i];
+        std::memset(&e, 0, sizeof e);
+        e.n = N;
+        e.ldv = N;
+        e.limbs = 2;
+        e.w[0] = w0;
+        e.w[1] = w1;
+        e.v[0] = v0;
+        e.v[1] = v1;
+        inf[i].resize(N);
+        e.info = inf[i].data();
+    }
+    if (rc == ZK_OK) {
+        // the eigenvectors are needed for the singular vectors; the dilation's
+        // pairs iterate like any other matrix's
+        zk_opts oo;
+        zk_opts_default(&oo);
+        if (opts) oo = *opts;
+        oo.want_vectors = 1;
+        rc = oo.refine == 1 ? run_heev_allpairs(ctx, count, K.data(), E.data(), &oo)
+                            : run_heev<2>(ctx, count, K.data(), E.data(), &oo, nullptr);
+    }
+    if (rc >= 0) {
+        for (int i = 0; i < count; i++) {
+            if (svd_extract(D[i], st)) {
+                rc = ctx->fail(ZK_EDEVICE, "singular triplet extraction failed");
+                break;
+            }
+            const int N = A[i].m + A[i].n, k = std::min(A[i].m, A[i].n);
+            if (out[i].info)
+                for (int j = 0; j < k; j++) out[i].info[j] = inf[i][N - 1 - j];
+        }
+    }
+    hipStreamSynchronize(st);
+    hipFree(buf);
+    ctx->extra -= off[count];
+    return rc;
+}
+
 extern "C" int zk_heev_fp64(zk_ctx *ctx, int count, const zk_herm *A, double *const *w, void *const *V, const int *ldv)
 {
     if (!ctx) return ZK_EINVAL;

@@ -105,6 +105,21 @@ size_t stage1_gemm_desc_count(int n, int np);
 void stage1_fill_gemm_descs(const ProbDesc *host_probs, int np, GemmDesc *out);
 int stage1_run(const Stage1Batch &B, hipStream_t st);
 
+// ------------------------------------------------------------------- SVD
+// One singular value decomposition through the Hermitian dilation (svd.hip).
+struct SvdDesc {
+    int m, n, lda, limbs, ldu, ldv;
+    const double *A[4];   // input limb planes, complex128 m x n (leading dimension lda)
+    double *K;            // limbs planes of (m+n) x (m+n) complex128, leading dimension m+n
+    const double *w[2];   // eigenvalue limbs of K (ascending)
+    double *V[2];         // eigenvector limb planes of K (complex128, leading dimension m+n); scratch after extraction
+    double *s[2];         // singular value limbs (min(m, n), descending)
+    double *u[2];         // left singular vector limb planes (m x min(m,n), leading dimension ldu), or null
+    double *v[2];         // right singular vector limb planes (n x min(m,n), leading dimension ldv)
+};
+int svd_build(const SvdDesc &D, hipStream_t st);
+int svd_extract(const SvdDesc &D, hipStream_t st);
+
 // ---------------------------------------------------------------- stage 2
 // Workspace of one concurrently factorised pair (shifted LU of order n,
 // augmented with the right-hand side as column n).

@@ -1,0 +1,118 @@
+"""Double-double SVD through the Hermitian dilation (zk_svd_dd) against the oracle.
+
+Bar: |s_j - s~_j| <= 1e-30 s_1; the residual of [u_j; v_j] as an eigenvector
+of the dilation (MPFR, on the returned limbs) <= 1e-30 s_1; U and V columns
+orthonormal to 1e-28.  Cases: exactly known singular values (products of
+exactly unitary phase-Hadamard matrices and a dyadic diagonal), tall and wide
+matrices with graded column scales against the oracle, both refinement modes
+(per-pair Rayleigh quotient iteration and the all-pairs refinement), a batch
+of mixed shapes, and argument errors.
+"""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+
+from gpu_helpers import log
+
+pytestmark = pytest.mark.gpu
+
+TOL, ORTH = 1e-30, 1e-28
+
+
+@pytest.fixture(scope="module")
+def zk():
+    import torch
+    import paper_2402_11868_amd as Z
+    Z.load()
+    ctx = Z.Context(0)
+    yield Z, ctx, torch
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def _fr(limbs):
+    return sum((Fraction(float(x)) for x in limbs), Fraction(0))
+
+
+def _hadamard_unitary(n, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    H = np.array([[1.0]])
+    while H.shape[0] < n:
+        H = np.block([[H, H], [H, -H]])
+    ph = np.array([1, 1j, -1, -1j])[rng.integers(0, 4, n)]
+    return (ph[:, None] * H[rng.permutation(n)]) / np.sqrt(n)
+
+
+def _graded(m, n, seed):
+    rng = np.random.default_rng(seed)
+    G = rng.standard_normal((m, n)) + 1j * rng.standard_normal((m, n))
+    return G * (2.0 ** (-1.5 * np.arange(n)))[None, :]
+
+
+def _judge(A, r, ref_s=None):
+    s = r.s.cpu().numpy()
+    U = r.U.cpu().numpy()
+    V = r.V.cpu().numpy()
+    if ref_s is None:
+        ref = oracle.svd([A])
+        ref_s = [_fr(ref[:, j]) for j in range(ref.shape[1])]
+    s1 = ref_s[0]
+    err = max(abs(_fr(s[:, j]) - ref_s[j]) for j in range(len(ref_s)))
+    assert err <= Fraction(TOL) * s1, f"singular value error {float(err):.3e}"
+    res, xn = oracle.svd_residuals([A], s, U, V)
+    assert res.max() <= TOL * float(s1), f"residual {res.max():.3e}"
+    for X in (U, V):
+        mo, md = oracle.gram(X)
+        assert mo <= ORTH and md <= ORTH, f"orthogonality {mo:.3e} / {md:.3e}"
+    return float(err) / float(s1), res.max() / float(s1)
+
+
+@pytest.mark.parametrize("refine", [0, 1])
+def test_svd_exact_singular_values(zk, refine):
+    Z, ctx, torch = zk
+    n = 16
+    rng = np.random.Generator(np.random.PCG64(77))
+    # 20-bit numerators over 2^0..2^29: every entry of A (a sum of 16 such
+    # terms / 16) is exact in binary64, so svals are A's singular values
+    svals = sorted([Fraction(int(rng.integers(1, 2 ** 20)), 2 ** int(rng.integers(0, 30))) for _ in range(n)], reverse=True)
+    A = (_hadamard_unitary(n, 5) * np.array([float(x) for x in svals])) @ _hadamard_unitary(n, 6).conj().T
+    ref = oracle.svd([A])
+    assert all(abs(_fr(ref[:, j]) - svals[j]) <= Fraction(1, 10 ** 55) * svals[0] for j in range(n))
+    r, = Z.svd(ctx, [torch.from_numpy(A).cuda()], opts=Z.make_opts(refine=refine))
+    assert r.status == Z.ZK_OK
+    e, res = _judge(A, r, ref_s=svals)
+    log(f"svd exact n=16 refine={refine}: err {e:.2e} resid {res:.2e}")
+
+
+@pytest.mark.parametrize("refine", [0, 1])
+@pytest.mark.parametrize("shape", [(48, 32), (32, 48), (40, 40)])
+def test_svd_graded_against_oracle(zk, shape, refine):
+    Z, ctx, torch = zk
+    A = _graded(*shape, seed=shape[0] * 100 + shape[1])
+    r, = Z.svd(ctx, [torch.from_numpy(A).cuda()], opts=Z.make_opts(refine=refine))
+    assert r.status == Z.ZK_OK
+    e, res = _judge(A, r)
+    log(f"svd {shape} refine={refine}: err {e:.2e} resid {res:.2e} iters {sorted(set(x['iters'] for x in r.info))}")
+
+
+def test_svd_batch_mixed_shapes(zk):
+    Z, ctx, torch = zk
+    mats = [_graded(m, n, seed=7 * m + n) for m, n in ((12, 20), (20, 12), (16, 16), (1, 5), (5, 1))]
+    res = Z.svd(ctx, [torch.from_numpy(A).cuda() for A in mats])
+    for A, r in zip(mats, res):
+        assert r.status == Z.ZK_OK
+        _judge(A, r)
+
+
+def test_svd_errors(zk):
+    Z, ctx, torch = zk
+    A = torch.from_numpy(_graded(8, 6, 1)).cuda()
+    bad = Z.ZkMat()
+    bad.m, bad.n, bad.lda, bad.limbs = 8, 6, 4, 1   # lda < m
+    bad.plane[0] = A.data_ptr()
+    out = Z.ZkSvdOut()
+    rc = Z.load().zk_svd_dd(ctx.handle, 1, bad, out, None)
+    assert rc == Z.ZK_EINVAL
