@@ -189,6 +189,33 @@ def allpairs_leg(Z, ctx, torch, Ad, gold, steps=3, tol=1e-30):
     return out
 
 
+def svd_leg(Z, ctx, torch, m=512, n=512, tol=1e-30):
+    """Singular triplets/s of zk_svd_dd on one 512 x 512 matrix (dilation of
+    order 1024) with column scales graded over 2^0 .. 2^-60, under both
+    refinements: triplets whose dilation residual meets the gate, per second."""
+    import numpy as np
+    rng = np.random.default_rng(512512)
+    G = rng.standard_normal((m, n)) + 1j * rng.standard_normal((m, n))
+    Ad = torch.from_numpy(G * (2.0 ** (-60.0 * np.arange(n) / (n - 1)))[None, :]).cuda()
+    out = {"shape": [m, n]}
+    for refine, steps in ((1, 2), (0, 1)):
+        opts = Z.make_opts(refine=refine)
+        if refine == 1:
+            Z.svd(ctx, [Ad], opts=opts)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r, = Z.svd(ctx, [Ad], opts=opts)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        resid = np.array([x["resid"] for x in r.info])
+        ok = int((resid <= tol).sum())
+        out["allpairs" if refine else "rqi"] = {
+            "ms": dt * 1e3, "triplets_per_s": ok / dt, "passing_triplets": ok, "status": r.status,
+            "max_resid_rel": float(resid.max()), "iterations": sorted(set(int(x["iters"]) for x in r.info))}
+    return out
+
+
 def _pct(x, q):
     import numpy as np
     return float(np.percentile(np.asarray(x), q)) * 1e3 if len(x) else None
@@ -285,6 +312,7 @@ def main():
     ap.add_argument("--no-fp32-leg", action="store_true", help="skip the FP32-MFMA-start run")
     ap.add_argument("--no-batch-leg", action="store_true", help="skip the 256 x 128^2 batch run")
     ap.add_argument("--no-allpairs-leg", action="store_true", help="skip the all-pairs refinement runs")
+    ap.add_argument("--no-svd-leg", action="store_true", help="skip the 512 x 512 SVD runs")
     ap.add_argument("--serving-requests", type=int, default=200,
                     help="requests of the serving-stream leg (0 = skip the leg)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -418,6 +446,9 @@ def main():
     if not args.no_allpairs_leg:
         log("all-pairs refinement")
         out["allpairs"] = allpairs_leg(Z, ctx, torch, Ad, gold)
+    if not args.no_svd_leg:
+        log("svd 512 x 512")
+        out["svd"] = svd_leg(Z, ctx, torch)
     if not args.no_batch_leg:
         log("batch of 256 x 128^2")
         out["batch"] = batch_leg(Z, ctx, torch)

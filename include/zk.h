@@ -212,8 +212,15 @@ typedef struct {
  * |m - n| zeros, the eigenvector of +s_j is [u_j; v_j] / sqrt(2).  No
  * squaring: the bound is |s_j - s~_j| <= tol * s_1 and
  * ||A v_j - s_j u_j||, ||A^H u_j - s_j v_j|| <= tol * s_1 (tol as in
- * zk_heev_dd).  Singular vectors of singular values below tol * s_1 are not
- * unique (they span the null spaces) and are not specified.  Synchronous.
+ * zk_heev_dd); U and V each get one first-order orthonormalisation step, so
+ * their columns are orthonormal to about tol.  Singular vectors of singular
+ * values below tol * s_1 are not unique (they span the null spaces) and are
+ * not specified.  The status counts the k returned triplets only
+ * (ZK_ENOCONV when one of them misses the tolerance; the dilation's other
+ * pairs are not outputs).  With m != n the dilation has |m - n| exact zeros,
+ * which fall into one cluster with every singular value below about
+ * 1e-10 s_1: for matrices with many such values the all-pairs refinement
+ * (opts->refine = 1) is the one that converges.  Synchronous.
  * Errors: as zk_heev_dd, and ZK_EINVAL for m < 1, n < 1, lda < m, out->limbs
  * != 2, ldu < m or ldv < n.
  */

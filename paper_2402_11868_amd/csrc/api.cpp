@@ -630,15 +630,22 @@ extern "C" int zk_svd_dd(zk_ctx *ctx, int count, const zk_mat *A, zk_svd_out *ou
                             : run_heev<2>(ctx, count, K.data(), E.data(), &oo, nullptr);
     }
     if (rc >= 0) {
+        // only the k returned triplets decide the status: the dilation's
+        // -s_j and |m - n| zero pairs are not outputs
+        bool all_ok = true;
         for (int i = 0; i < count; i++) {
             if (svd_extract(D[i], st)) {
                 rc = ctx->fail(ZK_EDEVICE, "singular triplet extraction failed");
                 break;
             }
             const int N = A[i].m + A[i].n, k = std::min(A[i].m, A[i].n);
-            if (out[i].info)
-                for (int j = 0; j < k; j++) out[i].info[j] = inf[i][N - 1 - j];
+            for (int j = 0; j < k; j++) {
+                const zk_pair_info &p = inf[i][N - 1 - j];
+                all_ok = all_ok && (p.flags & ZK_PAIR_CONVERGED);
+                if (out[i].info) out[i].info[j] = p;
+            }
         }
+        if (rc >= 0) rc = all_ok ? ZK_OK : ZK_ENOCONV;
     }
     hipStreamSynchronize(st);
     hipFree(buf);

@@ -116,3 +116,42 @@ def test_svd_errors(zk):
     out = Z.ZkSvdOut()
     rc = Z.load().zk_svd_dd(ctx.handle, 1, bad, out, None)
     assert rc == Z.ZK_EINVAL
+
+
+@pytest.mark.parametrize("m,n,span,refine", [(512, 384, 60, 1), (384, 512, 60, 1), (448, 448, 40, 0), (448, 448, 40, 1)])
+def test_svd_large_sampled(zk, m, n, span, refine):
+    """Shapes whose dilations (order 896) span many tiles of every kernel,
+    column scales graded over 2^0 .. 2^-span.  The tall and wide shapes put
+    |m - n| = 128 exact zeros and the tiny singular values into one cluster
+    of several hundred members, which the all-pairs refinement resolves and
+    the per-pair iteration does not (its members converge onto nearly the
+    same vectors and the Gram-Schmidt that separates them leaves residuals
+    near 1e-29); the square shape runs under both.  Checked on sampled triplets
+    by what holds at any size: the MPFR residual of [u; v] on the dilation
+    (<= 1e-30 s_1, so an eigenvalue of the dilation lies within it of s_j),
+    agreement with LAPACK to binary64 accuracy (which, with gaps far above
+    the residual, names that eigenvalue as the j-th largest), descending
+    order, and MPFR orthonormality of the sampled U and V columns."""
+    Z, ctx, torch = zk
+    rng = np.random.default_rng(1000 * m + n)
+    G = rng.standard_normal((m, n)) + 1j * rng.standard_normal((m, n))
+    A = G * (2.0 ** (-span * np.arange(n) / (n - 1)))[None, :]
+    log(f"svd {m}x{n} refine={refine}")
+    r, = Z.svd(ctx, [torch.from_numpy(A).cuda()], opts=Z.make_opts(refine=refine))
+    assert r.status == Z.ZK_OK
+    s = r.s.cpu().numpy()
+    U = r.U.cpu().numpy()
+    V = r.V.cpu().numpy()
+    lap = np.linalg.svd(A, compute_uv=False)
+    s1 = lap[0]
+    assert np.all(np.abs(s[0] - lap) <= 1e-13 * s1)
+    k = min(m, n)
+    sv = [_fr(s[:, j]) for j in range(k)]
+    assert all(sv[j] >= sv[j + 1] for j in range(k - 1))
+    sample = np.r_[0:4, 100:104, 250:254, k - 4:k]
+    res, _ = oracle.svd_residuals([A], s[:, sample], U[:, :, sample], V[:, :, sample])
+    assert res.max() <= TOL * s1, f"residual {res.max():.3e}"
+    for X in (U, V):
+        mo, md = oracle.gram(X[:, :, sample])
+        assert mo <= ORTH and md <= ORTH, f"orthogonality {mo:.3e} / {md:.3e}"
+    log(f"svd {m}x{n} refine={refine}: sampled resid {res.max() / s1:.2e}, iters {sorted(set(x['iters'] for x in r.info))}")
