@@ -217,10 +217,7 @@ typedef struct {
  * values below tol * s_1 are not unique (they span the null spaces) and are
  * not specified.  The status counts the k returned triplets only
  * (ZK_ENOCONV when one of them misses the tolerance; the dilation's other
- * pairs are not outputs).  With m != n the dilation has |m - n| exact zeros,
- * which fall into one cluster with every singular value below about
- * 1e-10 s_1: for matrices with many such values the all-pairs refinement
- * (opts->refine = 1) is the one that converges.  Synchronous.
+ * pairs are not outputs).  Synchronous.
  * Errors: as zk_heev_dd, and ZK_EINVAL for m < 1, n < 1, lda < m, out->limbs
  * != 2, ldu < m or ldv < n.
  */

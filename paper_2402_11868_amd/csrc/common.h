@@ -53,6 +53,8 @@ struct PairDesc {
     int iters;
     int flags;
     int slot;      // LU workspace slot while active
+    int tiny;      // pivots below 2^11 guard thresholds in the pair's last shifted factorisation
+    int pad0;
     double resid;  // ||H v - sigma v|| / hnorm
     double prev_resid;
 };

@@ -198,6 +198,7 @@ __global__ void k_s2_init(PairDesc *pairs, RqiProb *probs)
         Q.status = 0;
         Q.iters = 0;
         Q.flags = 0;
+        Q.tiny = 0;
         Q.resid = INFINITY;
         Q.prev_resid = INFINITY;
     }
@@ -326,10 +327,14 @@ __global__ void __launch_bounds__(256) k_s2_rq(PairDesc *pairs, RqiProb *probs, 
         } else if (!(res == res)) {
             Q.status = 2;
             Q.flags |= 8;
-        } else if (res * P.hnorm <= 0.5 * P.tol_abs) {
+        } else if (res * P.hnorm <= 0.5 * P.tol_abs && Q.tiny < 2) {
             // internal target half the tolerance: the final
             // re-orthogonalisation may add a little to the residuals of the
-            // pairs it touches (a pair pushed above gets polished)
+            // pairs it touches (a pair pushed above gets polished).  A solve
+            // with two or more tiny pivots (a degenerate eigenvalue) is never
+            // the last: its vector can be good on its own yet nearly parallel
+            // to its cluster partners, so the offset shift of k_s2_build
+            // takes one more solve
             Q.status = 1;
             Q.flags |= 1;
         } else if (Q.iters >= P.max_iter) {
@@ -355,7 +360,18 @@ __global__ void __launch_bounds__(256) k_s2_build(Stage2Batch B)
     double *M = B.lu_base + (size_t)t * B.lu_stride;
     const size_t plane = (size_t)ldm * (n + 1);
     const size_t nn = (size_t)n * n;
-    const mp<L> sigma = ld_sigma<L>(P, k);
+    mp<L> sigma = ld_sigma<L>(P, k);
+    // Two or more tiny pivots in the pair's last factorisation: sigma sits on
+    // an eigenvalue that is degenerate at working precision, and the pivots
+    // of its eigenspace were rounding noise.  The solve then inverted a
+    // random block (the LU's rounding, not the iterate, fixed the map on the
+    // eigenspace), so the cluster's members collapse onto a few directions
+    // and Gram-Schmidt has to separate nearly parallel vectors.  A shift
+    // 2^20 guard thresholds away (far above that noise) makes the inverse on
+    // the eigenspace the scalar -1/delta: each member keeps its own
+    // orthogonal projection, and the rest of the spectrum is still damped by
+    // delta / gap per solve.
+    if (Q.tiny >= 2) sigma = add_d<L>(sigma, 1048576.0 * P.piv_tol);
     for (int jj = 0; jj < 8; jj++) {
         const int j = blockIdx.x * 8 + jj;
         if (j > n) break;
@@ -403,7 +419,8 @@ __global__ void __launch_bounds__(256) k_s2_lu_panel(Stage2Batch B, int k0, int 
     __shared__ cmp<L> s_row[kLuSub];
     __shared__ cmp<L> sU[kLuNB][kLuSub];
     __shared__ int s_guard;
-    if (tid == 0) s_guard = 0;
+    __shared__ int s_tiny;
+    if (tid == 0) s_guard = s_tiny = 0;
     for (int s0 = 0; s0 < nbw; s0 += kLuSub) {
         const int w = min(kLuSub, nbw - s0);
         if (s0 > 0) {
@@ -476,6 +493,7 @@ __global__ void __launch_bounds__(256) k_s2_lu_panel(Stage2Batch B, int k0, int 
             __syncthreads();
             if (tid == 0) {
                 cmp<L> u = ld_cmp<L>(M, plane, (size_t)c * ldm + c);
+                if (c_mag1(u) < 2048.0 * P.piv_tol) s_tiny++;
                 if (c_mag1(u) < P.piv_tol) {
                     // zero-pivot guard: replace by the threshold, keeping the phase
                     const double sr = (u.re.x[0] < 0.0) ? -1.0 : 1.0;
@@ -504,7 +522,11 @@ __global__ void __launch_bounds__(256) k_s2_lu_panel(Stage2Batch B, int k0, int 
             __syncthreads();
         }
     }
-    if (tid == 0 && s_guard) Q.flags |= 4;
+    if (tid == 0) {
+        if (s_guard) Q.flags |= 4;
+        // count of the whole factorisation (its first panel starts at zero)
+        Q.tiny = (k0 == 0 ? 0 : Q.tiny) + s_tiny;
+    }
 }
 
 // ============================================================= LU trsm ====

@@ -60,8 +60,11 @@ def _exact_trace_frob(rho):
     return tr, fr
 
 
-@pytest.mark.parametrize("m,r,span,refine", [(256, 128, 0, 1), (256, 128, 40, 0), (256, 128, 40, 1)])
+@pytest.mark.parametrize("refine", [0, 1])
+@pytest.mark.parametrize("m,r,span", [(256, 128, 0), (256, 128, 40), (384, 96, 0)])
 def test_psd_rank_deficient(zk, m, r, span, refine):
+    """An exact null space of dimension m - r is one degenerate cluster: the
+    per-pair iteration needs the offset shift after its first solve there."""
     Z, ctx, torch = zk
     rho = _rho(m, r, span, seed=1000 * m + r + span)
     log(f"psd m={m} r={r} span={span} refine={refine}")
@@ -94,32 +97,3 @@ def test_psd_rank_deficient(zk, m, r, span, refine):
     log(f"psd m={m} r={r} span={span} refine={refine}: trace {float(dtr) / hn:.2e}, "
         f"frob {float(dfr) / hn ** 2:.2e}, sampled resid {rs.max() / hn:.2e}")
 
-
-def test_psd_exact_rank_deficient_rqi_reports(zk):
-    """Per-pair Rayleigh quotient iteration on the exactly rank-deficient rho
-    (128 exact zeros): a known limit.  Every pair converges in the iteration
-    rounds, but the final re-orthogonalisation leaves some pairs a few times
-    above the tolerance (1e-30 .. 1e-28 ||rho||_2), so the call reports
-    ZK_ENOCONV.  The all-pairs refinement meets the bar on the same matrix
-    (test_psd_rank_deficient[256-128-0-1]).  Checked here: the status agrees
-    with the per-pair flags and residuals, the near misses stay within 1e-27,
-    and the eigenvalues (the exact zeros included) still meet the bar."""
-    Z, ctx, torch = zk
-    m, r = 256, 128
-    rho = _rho(m, r, 0, seed=1000 * m + r)
-    res, = Z.heev(ctx, [[torch.from_numpy(rho).cuda()]], limbs_out=2, opts=Z.make_opts(refine=0))
-    torch.cuda.synchronize()
-    assert res.status in (Z.ZK_OK, Z.ZK_ENOCONV)
-    conv = [bool(x["flags"] & 1) for x in res.info]
-    rs = np.array([x["resid"] for x in res.info])
-    assert (res.status == Z.ZK_OK) == all(conv)
-    assert all((rs[k] <= TOL) == conv[k] for k in range(m))
-    assert rs.max() <= 1e-27
-    w = res.w.cpu().numpy()
-    hn = float(np.max(np.abs(np.linalg.eigvalsh(rho))))
-    lam = [limb_sum_fraction(w[:, k]) for k in range(m)]
-    assert max(abs(x) for x in lam[:m - r]) <= Fraction(TOL) * Fraction(hn)
-    tr, fr = _exact_trace_frob(rho)
-    assert abs(sum(lam, Fraction(0)) - tr) <= m * Fraction(TOL) * Fraction(hn)
-    log(f"psd exact, per-pair RQI: status {res.status}, {m - sum(conv)} pairs above the tolerance, "
-        f"max resid {rs.max():.2e}")
