@@ -97,3 +97,30 @@ def test_psd_rank_deficient(zk, m, r, span, refine):
     log(f"psd m={m} r={r} span={span} refine={refine}: trace {float(dtr) / hn:.2e}, "
         f"frob {float(dfr) / hn ** 2:.2e}, sampled resid {rs.max() / hn:.2e}")
 
+
+
+def test_psd_exact_rank_deficient_qd(zk):
+    """The same exact null space in quad-double (bar 1e-60 ||rho||_2): the
+    exact zeros, the trace identity, sampled MPFR residuals and
+    orthonormality."""
+    Z, ctx, torch = zk
+    m, r = 128, 48
+    qtol, qorth = 1e-60, 1e-58
+    rho = _rho(m, r, 0, seed=1000 * m + r)
+    log(f"psd qd m={m} r={r}")
+    res, = Z.heev(ctx, [[torch.from_numpy(rho).cuda()]], limbs_out=4)
+    torch.cuda.synchronize()
+    assert res.status == Z.ZK_OK
+    w = res.w.cpu().numpy()
+    V = res.V.cpu().numpy()
+    hn = float(np.max(np.abs(np.linalg.eigvalsh(rho))))
+    lam = [limb_sum_fraction(w[:, k]) for k in range(m)]
+    assert max(abs(x) for x in lam[:m - r]) <= Fraction(qtol) * Fraction(hn)
+    tr, _ = _exact_trace_frob(rho)
+    assert abs(sum(lam, Fraction(0)) - tr) <= m * Fraction(qtol) * Fraction(hn)
+    sample = np.r_[0:4, m - r - 2:m - r + 4, m - 4:m]
+    rs, _ = oracle.residuals([rho], w[:, sample], V[:, :, sample])
+    assert rs.max() <= qtol * hn, f"residual {rs.max() / hn:.3e} ||rho||"
+    mo, md = oracle.gram(V[:, :, sample])
+    assert mo <= qorth and md <= qorth, f"orthogonality {mo:.3e} / {md:.3e}"
+    log(f"psd qd m={m} r={r}: sampled resid {rs.max() / hn:.2e}, iterations {sorted(set(x['iters'] for x in res.info))}")
