@@ -243,6 +243,8 @@ __device__ __forceinline__ void hv_row_casc(const RqiProb &P, const double *vec,
     }
 }
 
+constexpr int kRqRows = 4;   // rows per thread whose cascaded sums k_s2_rq keeps between its passes
+
 // One work-group per active pair: y = H v, sigma = Re(v^H y), r = y - sigma v;
 // convergence, stagnation and iteration-limit decisions.
 template <int L>
@@ -258,31 +260,67 @@ __global__ void __launch_bounds__(256) k_s2_rq(PairDesc *pairs, RqiProb *probs, 
     mp<L> sigma;
     double r2 = 0.0;
     if constexpr (L == 2) {
-        // pass 1: sigma = sum_i Re(conj(v_i) y_i), y_i from the cascaded sums
-        mp<2> sacc = mp_zero<2>();
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            Casc3 yr, yi;
-            hv_row_casc(P, vec, nn, n, k, i, yr, yi);
-            const cmp<2> vi = ld_cmp<2>(vec, nn, (size_t)k * n + i);
-            dd a, b;
-            yr.get(a.x[0], a.x[1]);
-            yi.get(b.x[0], b.x[1]);
-            sacc = add(sacc, add(mul(vi.re, a), mul(vi.im, b)));
-        }
-        sigma = block_sum_mp<2>(sacc, red);
-        // pass 2: r_i = sum_j H(i, j) v_j - sigma v_i in one cascaded sum per component
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            Casc3 rr, ri;
-            hv_row_casc(P, vec, nn, n, k, i, rr, ri);
-            const cmp<2> vi = ld_cmp<2>(vec, nn, (size_t)k * n + i);
-            rr.add(-sigma.x[0], vi.re.x[0], vi.re.x[1]);
-            rr.add(-sigma.x[1], vi.re.x[0], vi.re.x[1]);
-            ri.add(-sigma.x[0], vi.im.x[0], vi.im.x[1]);
-            ri.add(-sigma.x[1], vi.im.x[0], vi.im.x[1]);
-            double a, b, lo;
-            rr.get(a, lo);
-            ri.get(b, lo);
-            r2 += a * a + b * b;
+        if (n <= 256 * kRqRows) {
+            // the cascaded sums of pass 1 stay in registers (at most kRqRows rows
+            // per thread) and pass 2 continues them: the same operations as the
+            // recomputing form below, with one product H v instead of two
+            Casc3 yr[kRqRows], yi[kRqRows];
+            mp<2> sacc = mp_zero<2>();
+#pragma unroll
+            for (int q = 0; q < kRqRows; q++) {
+                const int i = threadIdx.x + 256 * q;
+                if (i < n) {
+                    hv_row_casc(P, vec, nn, n, k, i, yr[q], yi[q]);
+                    const cmp<2> vi = ld_cmp<2>(vec, nn, (size_t)k * n + i);
+                    dd a, b;
+                    yr[q].get(a.x[0], a.x[1]);
+                    yi[q].get(b.x[0], b.x[1]);
+                    sacc = add(sacc, add(mul(vi.re, a), mul(vi.im, b)));
+                }
+            }
+            sigma = block_sum_mp<2>(sacc, red);
+#pragma unroll
+            for (int q = 0; q < kRqRows; q++) {
+                const int i = threadIdx.x + 256 * q;
+                if (i < n) {
+                    const cmp<2> vi = ld_cmp<2>(vec, nn, (size_t)k * n + i);
+                    yr[q].add(-sigma.x[0], vi.re.x[0], vi.re.x[1]);
+                    yr[q].add(-sigma.x[1], vi.re.x[0], vi.re.x[1]);
+                    yi[q].add(-sigma.x[0], vi.im.x[0], vi.im.x[1]);
+                    yi[q].add(-sigma.x[1], vi.im.x[0], vi.im.x[1]);
+                    double a, b, lo;
+                    yr[q].get(a, lo);
+                    yi[q].get(b, lo);
+                    r2 += a * a + b * b;
+                }
+            }
+        } else {
+            // pass 1: sigma = sum_i Re(conj(v_i) y_i), y_i from the cascaded sums
+            mp<2> sacc = mp_zero<2>();
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                Casc3 yr, yi;
+                hv_row_casc(P, vec, nn, n, k, i, yr, yi);
+                const cmp<2> vi = ld_cmp<2>(vec, nn, (size_t)k * n + i);
+                dd a, b;
+                yr.get(a.x[0], a.x[1]);
+                yi.get(b.x[0], b.x[1]);
+                sacc = add(sacc, add(mul(vi.re, a), mul(vi.im, b)));
+            }
+            sigma = block_sum_mp<2>(sacc, red);
+            // pass 2: r_i = sum_j H(i, j) v_j - sigma v_i in one cascaded sum per component
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                Casc3 rr, ri;
+                hv_row_casc(P, vec, nn, n, k, i, rr, ri);
+                const cmp<2> vi = ld_cmp<2>(vec, nn, (size_t)k * n + i);
+                rr.add(-sigma.x[0], vi.re.x[0], vi.re.x[1]);
+                rr.add(-sigma.x[1], vi.re.x[0], vi.re.x[1]);
+                ri.add(-sigma.x[0], vi.im.x[0], vi.im.x[1]);
+                ri.add(-sigma.x[1], vi.im.x[0], vi.im.x[1]);
+                double a, b, lo;
+                rr.get(a, lo);
+                ri.get(b, lo);
+                r2 += a * a + b * b;
+            }
         }
     } else {
         // pass 1: sigma = sum_i Re(conj(v_i) y_i)
