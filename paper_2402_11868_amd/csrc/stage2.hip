@@ -377,16 +377,14 @@ __global__ void __launch_bounds__(256) k_s2_rq(PairDesc *pairs, RqiProb *probs, 
             Q.flags |= 1;
         } else if (Q.iters >= P.max_iter) {
             Q.status = 2;
-        } else if (Q.iters >= 2 && res > 0.5 * Q.prev_resid && res * P.hnorm <= P.tol_abs && Q.tiny < 2) {
-            // within the tolerance, above the internal target, and the last
-            // solve did not halve the residual: the vector is at its rounding
-            // floor and more solves would not move it (the final judgement
-            // and the polishing passes still apply)
-            Q.status = 2;
-        } else if (Q.iters >= 3 && res > 0.5 * Q.prev_resid && res * P.hnorm <= 64.0 * P.tol_abs) {
-            // stagnated just above the tolerance: the attainable floor.  Far
-            // above it a pair keeps iterating (up to max_iter): inside a long
-            // chain its Gram-Schmidt partners still move
+        } else if (Q.iters >= 2 && res > 0.5 * Q.prev_resid && res * P.hnorm <= 64.0 * P.tol_abs && Q.tiny < 2) {
+            // the last solve did not halve the residual, which is near the
+            // tolerance: the vector is at its rounding floor and more solves
+            // would not move it (the final judgement decides, and a pair
+            // that the re-orthogonalisation left above the tolerance is
+            // polished).  Far above it a pair keeps iterating (up to
+            // max_iter): inside a long chain its Gram-Schmidt partners still
+            // move
             Q.status = 2;
         }
     }
