@@ -1,4 +1,4 @@
-"""Shared helpers of the GPU tests: run the HIP path, judge it with the oracle."""
+"""Shared helpers of the GPU tests: run the HIP path, check it against the oracle."""
 from __future__ import annotations
 
 import sys
@@ -32,7 +32,7 @@ def eig_errors(w_limbs: np.ndarray, ref_limbs: np.ndarray) -> np.ndarray:
     return out
 
 
-def judge(planes, res, ref_w_limbs, tol: float, check_vectors: bool = True, orth_tol: float | None = None,
+def gate(planes, res, ref_w_limbs, tol: float, check_vectors: bool = True, orth_tol: float | None = None,
           sample=None):
     """Gate a GPU result against the oracle.
 

@@ -16,7 +16,7 @@ import pytest
 import oracle
 import workloads as W
 
-from gpu_helpers import judge, log, to_np
+from gpu_helpers import gate, log, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -51,7 +51,7 @@ def test_allpairs_c1_against_golden(zk):
     log("all-pairs c1")
     res, = Z.heev_allpairs(ctx, [_dev(torch, [wl["A"]])])
     assert res.status == Z.ZK_OK
-    out = judge([wl["A"]], res, gold, DD_TOL, orth_tol=DD_ORTH)
+    out = gate([wl["A"]], res, gold, DD_TOL, orth_tol=DD_ORTH)
     log(f"all-pairs c1: {out} iterations {_iters(res)}")
 
 
@@ -62,7 +62,7 @@ def test_allpairs_householder_family(zk, n):
     log(f"all-pairs householder n={n}")
     res, = Z.heev_allpairs(ctx, [_dev(torch, [A])])
     assert res.status == Z.ZK_OK
-    judge([A], res, oracle.heev([A], want_vectors=False).w_limbs, DD_TOL, orth_tol=DD_ORTH)
+    gate([A], res, oracle.heev([A], want_vectors=False).w_limbs, DD_TOL, orth_tol=DD_ORTH)
 
 
 def test_allpairs_n1(zk):
@@ -105,7 +105,7 @@ def test_allpairs_hadamard_exact(zk, n, limbs, span):
         ref[0, k] = f
         ref[1, k] = float(x - Fraction(f))
     assert res.status == Z.ZK_OK
-    out = judge(h.planes, res, ref, DD_TOL, orth_tol=DD_ORTH)
+    out = gate(h.planes, res, ref, DD_TOL, orth_tol=DD_ORTH)
     log(f"all-pairs hadamard n={n}: {out} iterations {_iters(res)}")
 
 
@@ -115,7 +115,7 @@ def test_allpairs_mixed_orders(zk):
     res = Z.heev_allpairs(ctx, [_dev(torch, [A]) for A in mats])
     for A, r in zip(mats, res):
         assert r.status == Z.ZK_OK
-        judge([A], r, oracle.heev([A], want_vectors=False).w_limbs, DD_TOL, orth_tol=DD_ORTH)
+        gate([A], r, oracle.heev([A], want_vectors=False).w_limbs, DD_TOL, orth_tol=DD_ORTH)
 
 
 def test_allpairs_batch_256_of_128(zk):
@@ -135,7 +135,7 @@ def test_allpairs_batch_256_of_128(zk):
     for i in (0, 255):
         hdr, gold = G.load(f"c2:{i}")
         assert hdr["sha256"] == G.sha(mats[i])
-        out = judge([mats[i]], res[i], gold, DD_TOL, orth_tol=DD_ORTH)
+        out = gate([mats[i]], res[i], gold, DD_TOL, orth_tol=DD_ORTH)
         log(f"all-pairs batch member {i}: {out}")
 
 
@@ -152,7 +152,7 @@ def test_allpairs_clustered_1024_against_golden(zk):
     log(f"all-pairs clustered 1024: status {res.status}, iterations {_iters(res)}, max device residual {rs.max():.3e}")
     assert res.status == Z.ZK_OK
     sample = np.r_[0:8, 336:352, 500:508, 1016:1024]
-    out = judge([A], res, gold, DD_TOL, orth_tol=DD_ORTH, sample=sample)
+    out = gate([A], res, gold, DD_TOL, orth_tol=DD_ORTH, sample=sample)
     log(f"all-pairs clustered 1024: {out}")
 
 
@@ -185,6 +185,6 @@ def test_allpairs_refine_option_and_session(zk):
         assert torch.equal(a.w, m.w), f"request {i}: eigenvalues differ alone vs mix"
         assert torch.equal(a.V, m.V), f"request {i}: eigenvectors differ alone vs mix"
     for i in (0, 7):
-        judge([mats[i]], mixed[i], oracle.heev([mats[i]], want_vectors=False).w_limbs, DD_TOL, orth_tol=DD_ORTH)
+        gate([mats[i]], mixed[i], oracle.heev([mats[i]], want_vectors=False).w_limbs, DD_TOL, orth_tol=DD_ORTH)
     with pytest.raises(RuntimeError):
         Z.heev(ctx, [[dev[0]]], limbs_out=4, opts=opts)

@@ -14,7 +14,7 @@ import pytest
 import oracle
 import workloads as W
 
-from gpu_helpers import judge, log, to_np
+from gpu_helpers import gate, log, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -72,7 +72,7 @@ def test_c1_dd_against_golden(zk):
     assert hdr["sha256"] == G.sha(wl["A"])
     log("c1 dd")
     res, = Z.heev(ctx, [_dev(torch, [wl["A"]])], limbs_out=2)
-    out = judge([wl["A"]], res, gold, DD_TOL, orth_tol=DD_ORTH)
+    out = gate([wl["A"]], res, gold, DD_TOL, orth_tol=DD_ORTH)
     log(f"c1: {out} iters={np.bincount(res.iters)}")
 
 
@@ -83,7 +83,7 @@ def test_dd_householder_family(zk, n):
     log(f"dd householder n={n}")
     ref = oracle.heev([A], want_vectors=False)
     res, = Z.heev(ctx, [_dev(torch, [A])], limbs_out=2)
-    judge([A], res, ref.w_limbs, DD_TOL, orth_tol=DD_ORTH)
+    gate([A], res, ref.w_limbs, DD_TOL, orth_tol=DD_ORTH)
 
 
 def test_dd_n1(zk):
@@ -135,7 +135,7 @@ def test_dd_hadamard_exact(zk, n, limbs, span):
         f = float(x)
         ref[0, k] = f
         ref[1, k] = float(x - Fraction(f))
-    judge(h.planes, res, ref, DD_TOL, orth_tol=DD_ORTH)
+    gate(h.planes, res, ref, DD_TOL, orth_tol=DD_ORTH)
 
 
 def test_dd_batch_mixed_sizes(zk):
@@ -143,7 +143,7 @@ def test_dd_batch_mixed_sizes(zk):
     mats = [W.householder_hermitian(W.spectrum_c4(n), seed=W.seed_for(4, n) + 7) for n in (16, 48, 16, 32)]
     res = Z.heev(ctx, [_dev(torch, [A]) for A in mats], limbs_out=2)
     for A, r in zip(mats, res):
-        judge([A], r, oracle.heev([A], want_vectors=False).w_limbs, DD_TOL, orth_tol=DD_ORTH)
+        gate([A], r, oracle.heev([A], want_vectors=False).w_limbs, DD_TOL, orth_tol=DD_ORTH)
 
 
 def test_rqi_refine_from_lapack_pairs(zk):
@@ -153,7 +153,7 @@ def test_rqi_refine_from_lapack_pairs(zk):
     A = W.householder_hermitian(W.spectrum_c4(n), seed=99)
     w0, V0 = np.linalg.eigh(A)
     res = Z.rqi_refine(ctx, _dev(torch, [A]), torch.from_numpy(w0).cuda(), torch.from_numpy(V0).cuda(), limbs_out=2)
-    judge([A], res, oracle.heev([A], want_vectors=False).w_limbs, DD_TOL, orth_tol=DD_ORTH)
+    gate([A], res, oracle.heev([A], want_vectors=False).w_limbs, DD_TOL, orth_tol=DD_ORTH)
 
 
 # ---------------------------------------------------------------- qd -----
@@ -185,14 +185,14 @@ def test_qd_hadamard_exact(zk, n, limbs, span):
             f = float(r)
             ref[l, k] = f
             r -= Fraction(f)
-    judge(h.planes, res, ref, QD_TOL, orth_tol=QD_ORTH)
+    gate(h.planes, res, ref, QD_TOL, orth_tol=QD_ORTH)
 
 
 def test_qd_householder_n24(zk):
     Z, ctx, torch = zk
     A = W.householder_hermitian(W.spectrum_c4(24), seed=31)
     res, = Z.heev(ctx, [_dev(torch, [A])], limbs_out=4)
-    judge([A], res, oracle.heev([A], want_vectors=False).w_limbs, QD_TOL, orth_tol=QD_ORTH)
+    gate([A], res, oracle.heev([A], want_vectors=False).w_limbs, QD_TOL, orth_tol=QD_ORTH)
 
 
 # ------------------------------------------------------ FP32-MFMA start ----
@@ -206,12 +206,12 @@ def test_fp32_mfma_start_variant(zk):
     d = _dev(torch, [wl["A"]])
     r64, = Z.heev(ctx, [d], limbs_out=2)
     r32, = Z.heev(ctx, [d], limbs_out=2, opts=Z.make_opts(init_fp32=1))
-    out = judge([wl["A"]], r32, gold, DD_TOL, orth_tol=DD_ORTH)
+    out = gate([wl["A"]], r32, gold, DD_TOL, orth_tol=DD_ORTH)
     log(f"fp32 start: {out}; iterations fp64 start {np.bincount(r64.iters)}, fp32 start {np.bincount(r32.iters)}")
     assert np.mean(r32.iters) >= np.mean(r64.iters)
     A = W.householder_hermitian(W.spectrum_c4(130), seed=77)
     r, = Z.heev(ctx, [_dev(torch, [A])], limbs_out=2, opts=Z.make_opts(init_fp32=1))
-    judge([A], r, oracle.heev([A], want_vectors=False).w_limbs, DD_TOL, orth_tol=DD_ORTH)
+    gate([A], r, oracle.heev([A], want_vectors=False).w_limbs, DD_TOL, orth_tol=DD_ORTH)
 
 
 # ------------------------------------------------------------- errors ----

@@ -14,7 +14,7 @@ import pytest
 import oracle
 import workloads as W
 
-from gpu_helpers import judge, log
+from gpu_helpers import gate, log
 
 pytestmark = pytest.mark.gpu
 
@@ -62,7 +62,7 @@ def test_session_alone_vs_mix_bitwise(zk):
     assert all(s <= ad <= d for (s, ad, d) in ts)
     log(f"latencies ms: {[round(1e3 * (d - s), 1) for (s, ad, d) in ts]}")
     # tolerance against the oracle for one member of the mix
-    judge([mats[3]], mixed[3], oracle.heev([mats[3]], want_vectors=False).w_limbs, 1e-30, orth_tol=1e-28)
+    gate([mats[3]], mixed[3], oracle.heev([mats[3]], want_vectors=False).w_limbs, 1e-30, orth_tol=1e-28)
     sess.close()
 
 

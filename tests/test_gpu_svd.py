@@ -52,7 +52,7 @@ def _graded(m, n, seed):
     return G * (2.0 ** (-1.5 * np.arange(n)))[None, :]
 
 
-def _judge(A, r, ref_s=None):
+def _gate(A, r, ref_s=None):
     s = r.s.cpu().numpy()
     U = r.U.cpu().numpy()
     V = r.V.cpu().numpy()
@@ -83,7 +83,7 @@ def test_svd_exact_singular_values(zk, refine):
     assert all(abs(_fr(ref[:, j]) - svals[j]) <= Fraction(1, 10 ** 55) * svals[0] for j in range(n))
     r, = Z.svd(ctx, [torch.from_numpy(A).cuda()], opts=Z.make_opts(refine=refine))
     assert r.status == Z.ZK_OK
-    e, res = _judge(A, r, ref_s=svals)
+    e, res = _gate(A, r, ref_s=svals)
     log(f"svd exact n=16 refine={refine}: err {e:.2e} resid {res:.2e}")
 
 
@@ -94,7 +94,7 @@ def test_svd_graded_against_oracle(zk, shape, refine):
     A = _graded(*shape, seed=shape[0] * 100 + shape[1])
     r, = Z.svd(ctx, [torch.from_numpy(A).cuda()], opts=Z.make_opts(refine=refine))
     assert r.status == Z.ZK_OK
-    e, res = _judge(A, r)
+    e, res = _gate(A, r)
     log(f"svd {shape} refine={refine}: err {e:.2e} resid {res:.2e} iters {sorted(set(x['iters'] for x in r.info))}")
 
 
@@ -104,7 +104,7 @@ def test_svd_batch_mixed_shapes(zk):
     res = Z.svd(ctx, [torch.from_numpy(A).cuda() for A in mats])
     for A, r in zip(mats, res):
         assert r.status == Z.ZK_OK
-        _judge(A, r)
+        _gate(A, r)
 
 
 def test_svd_errors(zk):

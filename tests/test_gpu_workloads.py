@@ -26,7 +26,7 @@ import pytest
 import oracle
 import workloads as W
 
-from gpu_helpers import judge, log
+from gpu_helpers import gate, log
 
 pytestmark = pytest.mark.gpu
 
@@ -97,7 +97,7 @@ def test_clustered_1024_against_golden(zk):
     log(f"clustered 1024: device residual > tol for {(rs > DD_TOL).sum()} pairs, max {rs.max():.3e}")
     # every eigenvalue; vectors on a sample spread over the spectrum (both ends, the tiny tail)
     sample = np.r_[0:8, 336:352, 500:508, 1016:1024]
-    out = judge([A], res, gold, DD_TOL, orth_tol=DD_ORTH, sample=sample)
+    out = gate([A], res, gold, DD_TOL, orth_tol=DD_ORTH, sample=sample)
     log(f"clustered 1024: {out}")
 
 
@@ -126,7 +126,7 @@ def test_batch_256_of_128(zk):
     for i in sampled:
         hdr, gold = G.load(f"c2:{i}")
         assert hdr["sha256"] == G.sha(mats[i])
-        out = judge([mats[i]], res[i], gold, DD_TOL, orth_tol=DD_ORTH)
+        out = gate([mats[i]], res[i], gold, DD_TOL, orth_tol=DD_ORTH)
         log(f"batch member {i}: {out}")
 
 
@@ -150,7 +150,7 @@ def test_qd_companions_session(zk):
         assert r.status == Z.ZK_OK, f"request {i}: status {r.status}, unconverged (k, lam, resid, iters, flags) {bad[:8]}"
         ref = _exact_ref_limbs(h.lam)
         sample = None if i == 0 else np.r_[0:4, 124:128, 252:256]
-        out = judge(h.planes, r, ref, QD_TOL, orth_tol=QD_ORTH if i == 0 else None, sample=sample)
+        out = gate(h.planes, r, ref, QD_TOL, orth_tol=QD_ORTH if i == 0 else None, sample=sample)
         log(f"companion {i}: {out}")
     sess.close()
     # the first request alone gives the same bits
@@ -169,7 +169,7 @@ def test_qd_companion_binary64_input(zk):
     assert hdr["sha256"] == G.sha(wl["A"])
     log("qd companion, binary64 input")
     res, = Z.heev(ctx, [[torch.from_numpy(wl["A"]).cuda()]], limbs_out=4)
-    out = judge([wl["A"]], res, gold, QD_TOL, orth_tol=QD_ORTH)
+    out = gate([wl["A"]], res, gold, QD_TOL, orth_tol=QD_ORTH)
     log(f"companion L=1: {out} iters={np.bincount(res.iters)}")
 
 

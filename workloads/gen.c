@@ -10,7 +10,7 @@
  *   operations (no BLAS, no reassociation, -ffp-contract=off at build time), so
  *   the stored matrix is bit-for-bit reproducible on any x86-64 host and with any
  *   thread count.  The stored matrix, not the design, is the ground truth the
- *   solvers are judged against.
+ *   solvers are checked against.
  *
  * Storage: column-major complex128 (re, im interleaved), leading dimension n.
  */
