@@ -409,20 +409,49 @@ __global__ void __launch_bounds__(256) k_trd_wfin(ProbDesc *probs, int c, int k0
 // and Y[l/16][l%16]; the 4 accumulator values of lane l are D[4r + l/16][l%16].
 // The operands of 8 consecutive k-steps are loaded before their MFMAs so
 // that the loads are in flight together.
+// Operand loads without branches: an index outside the operand is clamped to
+// element (0, 0) (always present when a load runs, M, N, K >= 1), the load is
+// issued unconditionally and its bits are cleared afterwards with an integer
+// mask; op (uniform per launch) selects the address.  A load under a branch
+// ends in a wait for that load, so the loads of a k-chunk would be issued one
+// after another instead of together.
+struct OpLd {
+    size_t off;
+    unsigned long long mask;   // all ones inside the operand, zero outside
+};
+
+__device__ __forceinline__ OpLd opA_at(int lda, int op, int i, int k, int M, int K)
+{
+    const bool ok = i < M && k < K;
+    const int ii = ok ? i : 0, kk = ok ? k : 0;
+    return OpLd{op == 0 ? (size_t)kk * lda + ii : (size_t)ii * lda + kk, ok ? ~0ull : 0ull};
+}
+
+__device__ __forceinline__ OpLd opB_at(int ldb, int op, int k, int j, int K, int N)
+{
+    const bool ok = k < K && j < N;
+    const int kk = ok ? k : 0, jj = ok ? j : 0;
+    return OpLd{op == 0 ? (size_t)jj * ldb + kk : (size_t)kk * ldb + jj, ok ? ~0ull : 0ull};
+}
+
+// the loaded value with the mask applied and the conjugate taken for op != 0
+__device__ __forceinline__ double2 op_val(double2 v, unsigned long long mask, int op)
+{
+    const unsigned long long sgn = op == 0 ? 0ull : 0x8000000000000000ull;
+    return make_double2(__longlong_as_double(__double_as_longlong(v.x) & mask),
+                        __longlong_as_double((__double_as_longlong(v.y) ^ sgn) & mask));
+}
+
 __device__ __forceinline__ double2 opA_ld(const double2 *A, int lda, int op, int i, int k, int M, int K)
 {
-    if (i >= M || k >= K) return make_double2(0.0, 0.0);
-    if (op == 0) return A[(size_t)k * lda + i];
-    const double2 a = A[(size_t)i * lda + k];
-    return make_double2(a.x, -a.y);
+    const OpLd a = opA_at(lda, op, i, k, M, K);
+    return op_val(A[a.off], a.mask, op);
 }
 
 __device__ __forceinline__ double2 opB_ld(const double2 *B, int ldb, int op, int k, int j, int K, int N)
 {
-    if (k >= K || j >= N) return make_double2(0.0, 0.0);
-    if (op == 0) return B[(size_t)j * ldb + k];
-    const double2 b = B[(size_t)k * ldb + j];
-    return make_double2(b.x, -b.y);
+    const OpLd b = opB_at(ldb, op, k, j, K, N);
+    return op_val(B[b.off], b.mask, op);
 }
 
 constexpr int kGemmKc = 8;   // k-steps of 4 whose operands are loaded together
@@ -442,13 +471,25 @@ __global__ void __launch_bounds__(256) k_zgemm(const GemmDesc *descs, int M, int
     const double2 *B = reinterpret_cast<const double2 *>(G.B);
     f64x4 cre = f64x4{0.0, 0.0, 0.0, 0.0}, cim = f64x4{0.0, 0.0, 0.0, 0.0};
     const int li = lane & 15, lk = lane >> 4;
+    const int lda = G.lda, ldb = G.ldb;
     for (int k0 = 0; k0 < K; k0 += 4 * kGemmKc) {
         double2 xv[kGemmKc], yv[kGemmKc];
+        unsigned long long xm[kGemmKc], ym[kGemmKc];
+        // X[j][k] = op(B)[k][j], Y[k][i] = op(A)[i][k]: every load of the
+        // chunk issued before any is used
 #pragma unroll
         for (int s = 0; s < kGemmKc; s++) {
-            // X[j][k] = op(B)[k][j], Y[k][i] = op(A)[i][k]
-            xv[s] = opB_ld(B, G.ldb, opB, k0 + 4 * s + lk, wc + li, K, N);
-            yv[s] = opA_ld(A, G.lda, opA, wr + li, k0 + 4 * s + lk, M, K);
+            const OpLd b = opB_at(ldb, opB, k0 + 4 * s + lk, wc + li, K, N);
+            const OpLd a = opA_at(lda, opA, wr + li, k0 + 4 * s + lk, M, K);
+            xv[s] = B[b.off];
+            yv[s] = A[a.off];
+            xm[s] = b.mask;
+            ym[s] = a.mask;
+        }
+#pragma unroll
+        for (int s = 0; s < kGemmKc; s++) {
+            xv[s] = op_val(xv[s], xm[s], opB);
+            yv[s] = op_val(yv[s], ym[s], opA);
         }
 #pragma unroll
         for (int s = 0; s < kGemmKc; s++) {
