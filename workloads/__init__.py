@@ -20,6 +20,12 @@ Matrix families
   the paper's introduction (footnote 1, eps = 2^(-n+1)).
 * ``random_elements`` -- Hermitian matrix with i.i.d. U(-1,1) real/imag parts,
   the "random elements" matrices of the paper's diagonalisation timing (Sec. 2.1).
+* ``circuit_bond_matrices`` -- the reduced density matrices at every cut of the
+  n-qubit state of the paper's introductory circuit (footnote 1): n - 1
+  control qubits in |+>, the target in |->, and a multi-controlled Z on one
+  seeded control pattern.  Entries are exact dyadic rationals, every matrix
+  has rank <= 2 (exact zero eigenvalues), and the target's cut carries the
+  Schmidt pair 1 - eps, eps with eps = 2^(-n+1).
 
 Layout convention everywhere: a matrix is a numpy complex128 array ``A`` of
 shape (n, n); limb inputs are a list of such arrays whose *exact* sum is the
@@ -303,3 +309,33 @@ def workload(config: int, index: int = 0, n: int | None = None) -> dict:
         raise ValueError(config)
     A = householder_hermitian(lam, seed)
     return {"A": A, "design": np.sort(lam), "seed": seed}
+
+
+def circuit_bond_matrices(n: int, seed: int = 0):
+    """Bond matrices of the state C^(n-1)-Z (|+>^(n-1) |->) (paper, Sec. 1,
+    footnote 1, with the rotation U = Z, which maps |-> to the orthogonal |+>).
+
+    The qubits form a chain: n - 1 controls, then the target.  For each cut
+    after the first k qubits (k = 1 .. n-1) the reduced density matrix of the
+    smaller side is returned (order min(2^k, 2^(n-k))) as a dict with keys
+    ``k``, ``rho`` (complex128, exact), ``R`` (integer matrix, rho = R / 2^n)
+    and ``scale`` = n.  Amplitudes are s(x) / 2^(n/2) with s(x) = +-1: the
+    target bit t gives (-1)^t, except on the control pattern, where the
+    target is |+> and s = +1.  The state is a product state plus a product
+    correction, so every cut has Schmidt rank <= 2; across the last cut the
+    Schmidt coefficients squared are exactly 1 - 2^(-n+1) and 2^(-n+1).
+    """
+    if n < 2 or n > 24:
+        raise ValueError("2 <= n <= 24")
+    rng = np.random.Generator(np.random.PCG64(seed + 7919 * n))
+    pattern = int(rng.integers(0, 2 ** (n - 1)))
+    x = np.arange(2 ** n, dtype=np.int64)
+    s = np.where((x & 1) == 1, -1, 1).astype(np.int64)
+    s[(x >> 1) == pattern] = 1
+    out = []
+    for k in range(1, n):
+        S = s.reshape(2 ** k, 2 ** (n - k))   # rows: the first k qubits of the chain
+        R = S @ S.T if k <= n - k else S.T @ S
+        rho = (R.astype(np.float64) / float(2 ** n)).astype(np.complex128)
+        out.append({"k": k, "rho": rho, "R": R, "scale": n})
+    return out
