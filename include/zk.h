@@ -224,6 +224,35 @@ typedef struct {
 int zk_svd_dd(zk_ctx *ctx, int count, const zk_mat *A, zk_svd_out *out, const zk_opts *opts);
 
 /*
+ * zk_mps_two_site_dd: one two-site update of a matrix product state in
+ * double-double, the step of the paper's MPS simulation (Sec. 1) whose cost is
+ * the decomposition of the bond (Sec. 2.1).  Site tensors A (chi_l x 2 x chi)
+ * and B (chi x 2 x chi_r) and a two-qubit gate G give
+ *   theta = G . (A B)      (contraction over the shared bond, G on (s1, s2))
+ *   theta = U diag(s) V^H  (zk_svd_dd, either refinement by opts->refine)
+ *   A' = U[:, :chi'],  B' = diag(s[:chi']) V[:, :chi']^H,
+ * chi' = the number of singular values s_j > cutoff * s_1, at most chi_max
+ * (and at least 1).
+ * Layout: every operand is two device planes (hi, lo) of complex128,
+ * column-major.  A: (2 chi_l) x chi, leading dimension 2 chi_l, row index
+ * s1 chi_l + l.  B: chi x (2 chi_r), leading dimension chi, column index
+ * s2 chi_r + r.  gate: 4 x 4, row and column index 2 s1 + s2.
+ * A_out: room for (2 chi_l) x chi_max, written with leading dimension
+ * 2 chi_l; B_out: room for chi_max x (2 chi_r), written chi' x (2 chi_r) with
+ * leading dimension chi'; s_out: room for chi_max doubles per plane (singular
+ * value limbs, descending); *chi_out (host) receives chi'.  The library
+ * allocates its scratch (theta and the SVD's buffers) within the context
+ * budget.  Synchronous.
+ * Errors: ZK_EINVAL for chi_l, chi, chi_r < 1, 2 chi_l + 2 chi_r above the
+ * largest order, chi_max outside 1 .. min(2 chi_l, 2 chi_r), a negative or
+ * NaN cutoff, or a NULL pointer; ZK_ENOMEM; then as zk_svd_dd (ZK_ENOCONV
+ * when a kept triplet misses the tolerance).
+ */
+int zk_mps_two_site_dd(zk_ctx *ctx, int chi_l, int chi, int chi_r, const void *const *A, const void *const *B,
+                       const void *const *gate, int chi_max, double cutoff, void *const *A_out, void *const *B_out,
+                       double *const *s_out, int *chi_out, const zk_opts *opts);
+
+/*
  * zk_heev_fp64: stage 1 alone (the binary64 eigendecomposition that seeds the
  * Rayleigh quotient iteration).  For each matrix i: w[i] (device, n doubles,
  * ascending) and V[i] (device, n x n complex128 column-major, leading

@@ -20,6 +20,11 @@ Contents
   Computations, Sec. 8.6), by the same MPFR Jacobi solver, and the MPFR
   residuals ||A v - s u||, ||A^H u - s v|| of returned triplets.  The paper
   lists the SVD beside the eigendecomposition (Sec. 2).
+* ``two_site_theta`` / ``apply_gate`` / ``limb_planes`` -- exact rational
+  references for the MPS two-site update (Sec. 1): the contraction
+  theta = G (A B) of two site tensors and a two-qubit gate, and the state
+  vector of a chain evolved by two-qubit gates, both in Python Fractions,
+  plus the greedy split of an exact complex matrix into binary64 limbs.
 """
 from __future__ import annotations
 
@@ -200,3 +205,98 @@ def svd_residuals(planes, s_limbs, u_limbs, v_limbs, prec: int = DEFAULT_PREC, n
     x = np.concatenate([u_limbs, v_limbs], axis=1)
     return residuals(_dilation(planes), s_limbs, x, prec=prec, nthreads=nthreads)
 
+
+
+# ------------------------------------------------ MPS two-site references --
+# Exact complex rationals are (re, im) pairs of Fractions.
+
+def _cfr(z):
+    from fractions import Fraction
+    return (Fraction(float(z.real)), Fraction(float(z.imag)))
+
+
+def _cmul(a, b):
+    return (a[0] * b[0] - a[1] * b[1], a[0] * b[1] + a[1] * b[0])
+
+
+def _cadd(a, b):
+    return (a[0] + b[0], a[1] + b[1])
+
+
+def limb_sum_matrix(planes):
+    """Exact complex rationals of the limb sum of binary64 complex planes."""
+    planes = [np.asarray(p, dtype=np.complex128) for p in planes]
+    m, n = planes[0].shape
+    out = [[None] * n for _ in range(m)]
+    for i in range(m):
+        for j in range(n):
+            re, im = _cfr(planes[0][i, j])
+            for p in planes[1:]:
+                r2, i2 = _cfr(p[i, j])
+                re, im = re + r2, im + i2
+            out[i][j] = (re, im)
+    return out
+
+
+def two_site_theta(A_planes, B_planes, G):
+    """theta'[(s1, l), (s2, r)] = sum G[2 s1 + s2, 2 t1 + t2] sum_m A[t1 chi_l + l, m] B[m, t2 chi_r + r]
+    exactly: A (2 chi_l x chi) and B (chi x 2 chi_r) as binary64 limb planes, G a 4 x 4
+    nested list of exact (re, im) Fractions.  Returns a nested list of (re, im)."""
+    from fractions import Fraction
+    A = limb_sum_matrix(A_planes)
+    B = limb_sum_matrix(B_planes)
+    M, K, N = len(A), len(B), len(B[0])
+    zero = (Fraction(0), Fraction(0))
+    T = [[zero] * N for _ in range(M)]
+    for i in range(M):
+        for j in range(N):
+            acc = zero
+            for m in range(K):
+                acc = _cadd(acc, _cmul(A[i][m], B[m][j]))
+            T[i][j] = acc
+    cl, cr = M // 2, N // 2
+    out = [[zero] * N for _ in range(M)]
+    for l in range(cl):
+        for r in range(cr):
+            x = [T[t1 * cl + l][t2 * cr + r] for t1 in range(2) for t2 in range(2)]
+            for s1 in range(2):
+                for s2 in range(2):
+                    acc = zero
+                    for c in range(4):
+                        acc = _cadd(acc, _cmul(G[2 * s1 + s2][c], x[c]))
+                    out[s1 * cl + l][s2 * cr + r] = acc
+    return out
+
+
+def limb_planes(T, L=4):
+    """Greedy round-to-nearest split of an exact complex matrix into L binary64 limb planes."""
+    from fractions import Fraction
+    m, n = len(T), len(T[0])
+    planes = [np.zeros((m, n), dtype=np.complex128) for _ in range(L)]
+    for i in range(m):
+        for j in range(n):
+            re, im = T[i][j]
+            for l in range(L):
+                fr, fi = float(re), float(im)
+                planes[l][i, j] = complex(fr, fi)
+                re -= Fraction(fr)
+                im -= Fraction(fi)
+    return planes
+
+
+def apply_gate(psi, n, q, G):
+    """Exact state vector of an n-site chain (amplitude index sum s_k 2^(n-1-k), site 0
+    most significant) after the gate G (4 x 4, index 2 s_q + s_(q+1)) on sites q, q+1."""
+    out = list(psi)
+    hi, lo = n - 1 - q, n - 2 - q
+    for x in range(2 ** n):
+        if (x >> hi) & 1 or (x >> lo) & 1:
+            continue
+        idx = [x | (a << hi) | (b << lo) for a in range(2) for b in range(2)]
+        vals = [psi[i] for i in idx]
+        for r in range(4):
+            acc = (vals[0][0] * 0, vals[0][1] * 0)
+            for c in range(4):
+                acc = _cadd(acc, _cmul(G[r][c], vals[c]))
+            out[idx[r]] = acc
+    return out

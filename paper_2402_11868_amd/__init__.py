@@ -60,7 +60,7 @@ KERNEL_CLASSES = ["lu_update", "lu_panel", "lu_trsm", "backsolve", "rq", "gs", "
                   "build", "trd_vec", "tridiag", "backt", "ap_resid", "ap_fgemm", "ap_ddgemm", "ap_other"]
 
 EXPORTED = ["zk_prof_enable", "zk_prof_reset", "zk_prof_read", "zk_opts_default", "zk_ctx_create", "zk_ctx_destroy", "zk_status_str", "zk_ctx_last_error",
-            "zk_workspace_bytes", "zk_heev_dd", "zk_heev_qd", "zk_heev_dd_allpairs", "zk_svd_dd", "zk_heev_fp64", "zk_rqi_refine",
+            "zk_workspace_bytes", "zk_heev_dd", "zk_heev_qd", "zk_heev_dd_allpairs", "zk_svd_dd", "zk_mps_two_site_dd", "zk_heev_fp64", "zk_rqi_refine",
             "zk_session_create", "zk_session_submit", "zk_session_poll", "zk_session_times", "zk_session_destroy"]
 
 _lib = None
@@ -88,6 +88,9 @@ def load(path: str = LIB_PATH):
     for f in ("zk_heev_dd", "zk_heev_qd", "zk_heev_dd_allpairs"):
         getattr(lib, f).argtypes = [P, I, ctypes.POINTER(ZkHerm), ctypes.POINTER(ZkEigOut), ctypes.POINTER(ZkOpts)]
     lib.zk_svd_dd.argtypes = [P, I, ctypes.POINTER(ZkMat), ctypes.POINTER(ZkSvdOut), ctypes.POINTER(ZkOpts)]
+    P2 = P * 2
+    lib.zk_mps_two_site_dd.argtypes = [P, I, I, I, P2, P2, P2, I, ctypes.c_double, P2, P2, P2,
+                                       ctypes.POINTER(I), ctypes.POINTER(ZkOpts)]
     lib.zk_heev_fp64.argtypes = [P, I, ctypes.POINTER(ZkHerm), ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(I)]
     lib.zk_rqi_refine.argtypes = [P, I, ctypes.POINTER(ZkHerm), I, P, P, I, ctypes.POINTER(ZkEigOut), ctypes.POINTER(ZkOpts)]
     if hasattr(lib, "zk_heev_stats"):
@@ -330,6 +333,60 @@ def svd(ctx: Context, mats, opts: ZkOpts | None = None):
     if rc not in (ZK_OK, ZK_ENOCONV):
         raise RuntimeError(f"zk_svd_dd failed: {status_str(rc)}: {ctx.last_error()}")
     return [SvdResult(s, U, V, _info_list(info, k), rc) for (s, U, V, info, k) in outs]
+
+
+class MpsResult:
+    """A: (2, 2 chi_l, chi') and B: (2, chi', 2 chi_r) complex128 limbs, s: (2, chi') float64 limbs."""
+
+    def __init__(self, A, s, B, chi, status):
+        self.A, self.s, self.B, self.chi, self.status = A, s, B, chi, status
+
+
+def _limb_pair(x):
+    """Two complex128 limb tensors (hi, lo) from a tensor or a list of one or two."""
+    planes = [x] if isinstance(x, torch.Tensor) else list(x)
+    if len(planes) == 1:
+        planes = planes + [torch.zeros_like(planes[0])]
+    if len(planes) != 2:
+        raise ValueError("expected one or two limb tensors")
+    for p in planes:
+        if p.dtype != torch.complex128 or not p.is_cuda or p.dim() != 2 or p.shape != planes[0].shape:
+            raise ValueError("limbs must be complex128 CUDA matrices of one shape")
+    return planes
+
+
+def mps_two_site(ctx: Context, A, B, gate, chi_max: int, cutoff: float = 0.0, opts: ZkOpts | None = None):
+    """One double-double two-site update (zk_mps_two_site_dd).
+
+    A: (2 chi_l, chi) with row index s1 chi_l + l; B: (chi, 2 chi_r) with
+    column index s2 chi_r + r; gate: (4, 4) with index 2 s1 + s2; each a
+    complex128 CUDA tensor or a list of (hi, lo) limb tensors."""
+    lib = load()
+    Ap, Bp, Gp = _limb_pair(A), _limb_pair(B), _limb_pair(gate)
+    M, chi = Ap[0].shape
+    chi2, N = Bp[0].shape
+    if chi2 != chi or M % 2 or N % 2 or tuple(Gp[0].shape) != (4, 4):
+        raise ValueError("shapes: A (2 chi_l, chi), B (chi, 2 chi_r), gate (4, 4)")
+    keep = [p.transpose(0, 1).contiguous() for p in Ap + Bp + Gp]   # column-major storage
+    dev = Ap[0].device
+    Ao = [torch.zeros((chi_max, M), dtype=torch.complex128, device=dev) for _ in range(2)]
+    Bo = [torch.zeros((chi_max * N,), dtype=torch.complex128, device=dev) for _ in range(2)]
+    so = [torch.zeros((chi_max,), dtype=torch.float64, device=dev) for _ in range(2)]
+    P2 = ctypes.c_void_p * 2
+    chi_out = ctypes.c_int(0)
+    torch.cuda.current_stream().synchronize()
+    rc = lib.zk_mps_two_site_dd(ctx.handle, M // 2, chi, N // 2, P2(keep[0].data_ptr(), keep[1].data_ptr()),
+                                P2(keep[2].data_ptr(), keep[3].data_ptr()), P2(keep[4].data_ptr(), keep[5].data_ptr()),
+                                chi_max, float(cutoff), P2(Ao[0].data_ptr(), Ao[1].data_ptr()),
+                                P2(Bo[0].data_ptr(), Bo[1].data_ptr()), P2(so[0].data_ptr(), so[1].data_ptr()),
+                                ctypes.byref(chi_out), ctypes.byref(opts) if opts is not None else None)
+    if rc not in (ZK_OK, ZK_ENOCONV):
+        raise RuntimeError(f"zk_mps_two_site_dd failed: {status_str(rc)}: {ctx.last_error()}")
+    c = chi_out.value
+    A_new = torch.stack([a[:c].transpose(0, 1) for a in Ao])
+    B_new = torch.stack([b[:c * N].reshape(N, c).transpose(0, 1) for b in Bo])
+    s_new = torch.stack([x[:c] for x in so])
+    return MpsResult(A_new, s_new, B_new, c, rc)
 
 
 def ctx_device(m):

@@ -653,6 +653,110 @@ extern "C" int zk_svd_dd(zk_ctx *ctx, int count, const zk_mat *A, zk_svd_out *ou
     return rc;
 }
 
+extern "C" int zk_mps_two_site_dd(zk_ctx *ctx, int chi_l, int chi, int chi_r, const void *const *A,
+                                  const void *const *B, const void *const *gate, int chi_max, double cutoff,
+                                  void *const *A_out, void *const *B_out, double *const *s_out, int *chi_out,
+                                  const zk_opts *opts)
+{
+    if (!ctx) return ZK_EINVAL;
+    if (ctx->poisoned) return ctx->fail(ZK_EDEVICE, "context poisoned by an earlier device error");
+    if (chi_l < 1 || chi < 1 || chi_r < 1) return ctx->fail(ZK_EINVAL, "bond dimensions must be >= 1");
+    const int M = 2 * chi_l, N = 2 * chi_r, k = std::min(M, N);
+    if (M + N > kMaxN) return ctx->fail(ZK_EINVAL, "2 chi_l + 2 chi_r = %d above the largest order %d", M + N, kMaxN);
+    if (chi_max < 1 || chi_max > k) return ctx->fail(ZK_EINVAL, "chi_max %d outside 1 .. %d", chi_max, k);
+    if (!(cutoff >= 0.0)) return ctx->fail(ZK_EINVAL, "cutoff must be >= 0");
+    if (!A || !B || !gate || !A_out || !B_out || !s_out || !chi_out) return ctx->fail(ZK_EINVAL, "NULL argument");
+    for (int l = 0; l < 2; l++)
+        if (!A[l] || !B[l] || !gate[l] || !A_out[l] || !B_out[l] || !s_out[l])
+            return ctx->fail(ZK_EINVAL, "NULL plane");
+    if (hipSetDevice(ctx->device) != hipSuccess) return ctx->fail(ZK_EDEVICE, "hipSetDevice failed");
+    hipStream_t st = ctx->stream;
+    // scratch: theta, U, V (two planes each) and the singular value limbs
+    const size_t bT = align_up(16 * (size_t)M * N), bU = align_up(16 * (size_t)M * k), bV = align_up(16 * (size_t)N * k),
+                 bS = align_up(8 * (size_t)k);
+    const size_t bytes = 2 * (bT + bU + bV + bS);
+    if (ctx->held() + bytes > ctx->budget) return ctx->fail(ZK_ENOMEM, "the two-site update needs %zu bytes", bytes);
+    void *buf = nullptr;
+    if (hipMalloc(&buf, bytes) != hipSuccess) {
+        hipGetLastError();
+        return ctx->fail(ZK_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
+    }
+    ctx->extra += bytes;
+    char *b = (char *)buf;
+    double *T[2], *U[2], *V[2], *S[2];
+    for (int l = 0; l < 2; l++) { T[l] = (double *)b; b += bT; }
+    for (int l = 0; l < 2; l++) { U[l] = (double *)b; b += bU; }
+    for (int l = 0; l < 2; l++) { V[l] = (double *)b; b += bV; }
+    for (int l = 0; l < 2; l++) { S[l] = (double *)b; b += bS; }
+    MpsDesc D;
+    std::memset(&D, 0, sizeof D);
+    D.M = M;
+    D.K = chi;
+    D.N = N;
+    D.chil = chi_l;
+    D.chir = chi_r;
+    D.lda = M;
+    D.ldb = chi;
+    for (int l = 0; l < 2; l++) {
+        D.A[l] = (const double *)A[l];
+        D.B[l] = (const double *)B[l];
+        D.T[l] = T[l];
+        D.G[l] = (const double *)gate[l];
+        D.V[l] = V[l];
+        D.s[l] = S[l];
+        D.Bo[l] = (double *)B_out[l];
+    }
+    int rc = ZK_OK;
+    if (mps_theta(D, st)) rc = ctx->fail(ZK_EDEVICE, "two-site contraction launch failed");
+    if (rc == ZK_OK) {
+        zk_mat mat;
+        std::memset(&mat, 0, sizeof mat);
+        mat.m = M;
+        mat.n = N;
+        mat.lda = M;
+        mat.limbs = 2;
+        mat.plane[0] = T[0];
+        mat.plane[1] = T[1];
+        zk_svd_out so;
+        std::memset(&so, 0, sizeof so);
+        so.m = M;
+        so.n = N;
+        so.limbs = 2;
+        for (int l = 0; l < 2; l++) {
+            so.s[l] = S[l];
+            so.u[l] = U[l];
+            so.v[l] = V[l];
+        }
+        so.ldu = M;
+        so.ldv = N;
+        rc = zk_svd_dd(ctx, 1, &mat, &so, opts);
+    }
+    if (rc >= 0) {
+        std::vector<double> sh(k);
+        if (hipMemcpyAsync(sh.data(), S[0], 8 * (size_t)k, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            rc = ctx->fail(ZK_EDEVICE, "singular value download failed");
+        int kept = 0;
+        if (rc >= 0) {
+            while (kept < chi_max && sh[kept] > 0.0 && sh[kept] > cutoff * sh[0]) kept++;
+            kept = std::max(kept, 1);
+            D.chi = kept;
+            D.ldv = N;
+            for (int l = 0; l < 2 && rc >= 0; l++) {
+                if (hipMemcpyAsync(A_out[l], U[l], 16 * (size_t)M * kept, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+                    hipMemcpyAsync(s_out[l], S[l], 8 * (size_t)kept, hipMemcpyDeviceToDevice, st) != hipSuccess)
+                    rc = ctx->fail(ZK_EDEVICE, "output copy failed");
+            }
+            if (rc >= 0 && mps_bout(D, st)) rc = ctx->fail(ZK_EDEVICE, "B' launch failed");
+            *chi_out = kept;
+        }
+    }
+    hipStreamSynchronize(st);
+    hipFree(buf);
+    ctx->extra -= bytes;
+    return rc;
+}
+
 extern "C" int zk_heev_fp64(zk_ctx *ctx, int count, const zk_herm *A, double *const *w, void *const *V, const int *ldv)
 {
     if (!ctx) return ZK_EINVAL;

@@ -120,6 +120,27 @@ struct SvdDesc {
 int svd_build(const SvdDesc &D, hipStream_t st);
 int svd_extract(const SvdDesc &D, hipStream_t st);
 
+// ------------------------------------------------------------------- MPS
+// One two-site update (mps.hip).  All pointers are device pointers to
+// complex128 limb planes (hi, lo), column-major.
+struct MpsDesc {
+    int M, K, N;          // theta is M x N (M = 2 chi_l, N = 2 chi_r), inner dimension K = chi
+    int chil, chir;
+    int lda, ldb;         // A: M x K (lda >= M), B: K x N (ldb >= K)
+    int chi, ldv, pad;    // kept bond dimension chi'; V leading dimension
+    const double *A[2];
+    const double *B[2];
+    double *T[2];         // theta (M x N, leading dimension M), the gate applied in place
+    const double *G[2];   // 4 x 4 gate, row and column index 2 s1 + s2
+    const double *V[2];   // right singular vectors of theta (N x min(M, N), leading dimension ldv)
+    const double *s[2];   // singular value limbs
+    double *Bo[2];        // B' (chi' x N, leading dimension chi')
+};
+// theta = A B, then the gate on the physical indices
+int mps_theta(const MpsDesc &D, hipStream_t st);
+// B' = diag(s[:chi']) V[:, :chi']^H
+int mps_bout(const MpsDesc &D, hipStream_t st);
+
 // ---------------------------------------------------------------- stage 2
 // Workspace of one concurrently factorised pair (shifted LU of order n,
 // augmented with the right-hand side as column n).

@@ -18,7 +18,7 @@ def declared():
 def test_header_declares_the_entry_points():
     names = declared()
     for n in ("zk_heev_dd", "zk_heev_qd", "zk_rqi_refine", "zk_session_submit", "zk_session_poll",
-              "zk_ctx_create", "zk_heev_fp64", "zk_heev_dd_allpairs"):
+              "zk_ctx_create", "zk_heev_fp64", "zk_heev_dd_allpairs", "zk_svd_dd", "zk_mps_two_site_dd"):
         assert n in names
 
 
@@ -45,5 +45,8 @@ def test_static_entry_points_without_device():
     # NULL handles are rejected before any device work
     assert lib.zk_heev_dd(None, 1, None, None, None) == -1
     assert lib.zk_heev_dd_allpairs(None, 1, None, None, None) == -1
+    assert lib.zk_svd_dd(None, 1, None, None, None) == -1
+    assert lib.zk_mps_two_site_dd(None, 1, 1, 1, None, None, None, 1, ctypes.c_double(0.0), None, None, None,
+                                  None, None) == -1
     assert lib.zk_session_submit(None, None, None, 2, None, None) == -1
     assert lib.zk_ctx_destroy(None) == 0
