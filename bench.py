@@ -216,6 +216,33 @@ def svd_leg(Z, ctx, torch, m=512, n=512, tol=1e-30):
     return out
 
 
+def mps_leg(Z, ctx, torch, chi=128):
+    """Two-site updates (zk_mps_two_site_dd) of random site tensors with
+    chi_l = chi = chi_r = 128 (a 256 x 256 two-site matrix, dilation of order
+    512) and an entangling gate, no truncation below the full rank: ms per
+    update under both refinements."""
+    import numpy as np
+    rng = np.random.default_rng(128128)
+    M = 2 * chi
+    A = torch.from_numpy(rng.standard_normal((M, chi)) + 1j * rng.standard_normal((M, chi))).cuda()
+    B = torch.from_numpy(rng.standard_normal((chi, M)) + 1j * rng.standard_normal((chi, M))).cuda()
+    W = 0.5 * np.array([[1, 1, 1, 1], [1, -1, 1, -1], [1, 1, -1, -1], [1, -1, -1, 1]], dtype=np.complex128)
+    G = torch.from_numpy(np.eye(4, dtype=np.complex128)[[0, 1, 3, 2]] @ W).cuda()
+    out = {"chi": chi}
+    for refine, steps in ((1, 2), (0, 1)):
+        opts = Z.make_opts(refine=refine)
+        if refine == 1:
+            Z.mps_two_site(ctx, A, B, G, chi_max=M, opts=opts)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = Z.mps_two_site(ctx, A, B, G, chi_max=M, opts=opts)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        out["allpairs" if refine else "rqi"] = {"ms_per_update": dt * 1e3, "kept": r.chi, "status": r.status}
+    return out
+
+
 def _pct(x, q):
     import numpy as np
     return float(np.percentile(np.asarray(x), q)) * 1e3 if len(x) else None
@@ -449,6 +476,9 @@ def main():
     if not args.no_svd_leg:
         log("svd 512 x 512")
         out["svd"] = svd_leg(Z, ctx, torch)
+    if not args.no_svd_leg:
+        log("mps two-site update chi 128")
+        out["mps_two_site"] = mps_leg(Z, ctx, torch)
     if not args.no_batch_leg:
         log("batch of 256 x 128^2")
         out["batch"] = batch_leg(Z, ctx, torch)
