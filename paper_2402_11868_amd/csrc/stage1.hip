@@ -644,14 +644,25 @@ __global__ void k_invit(ProbDesc *probs)
     for (int i = 0; i < n; i++)
         tnorm = fmax(tnorm, fabs(P.d[i]) + (i > 0 ? fabs(P.e[i - 1]) : 0.0) + (i < n - 1 ? fabs(P.e[i]) : 0.0));
     const double guard = fmax(tnorm, 1e-300) * 1.1102230246251565e-16;
+    // Couplings below eps ||T|| are taken as exact zeros (a perturbation within
+    // the backward error), so T splits into blocks.  An eigenvalue shared by
+    // two blocks (the +-s pairs of a dilation, a direct sum) then has a guarded
+    // pivot in each block and every start vector keeps both null directions;
+    // through a coupling of, say, 1e-17 the row exchange would instead drop
+    // one of them and all the inverse iterates of that eigenvalue would be the
+    // same vector.
+    auto cpl = [&](int i) {
+        const double x = P.e[i];
+        return fabs(x) <= guard ? 0.0 : x;
+    };
     // P L U factorisation of T - lam I by Gaussian elimination with partial
     // pivoting.  The row being eliminated always has two entries (a at
     // column i, b at column i+1); U row i has up to three (u0, u1, u2).
-    double a = P.d[0] - lam, b = (n > 1) ? P.e[0] : 0.0;
+    double a = P.d[0] - lam, b = (n > 1) ? cpl(0) : 0.0;
     for (int i = 0; i < n - 1; i++) {
-        const double sub = P.e[i];                                  // T[i+1][i]
+        const double sub = cpl(i);                                  // T[i+1][i]
         const double na = P.d[i + 1] - lam;                         // T[i+1][i+1]
-        const double nb = (i + 1 < n - 1) ? P.e[i + 1] : 0.0;       // T[i+1][i+2]
+        const double nb = (i + 1 < n - 1) ? cpl(i + 1) : 0.0;       // T[i+1][i+2]
         const size_t o = (size_t)i * n + k;
         if (fabs(a) >= fabs(sub)) {
             double piv = a;

@@ -114,9 +114,12 @@ def test_two_site_update_against_oracle(zk, refine):
 
 @pytest.mark.parametrize("refine", [0])
 def test_mps_circuit_against_exact_state(zk, refine):
-    """Per-pair refinement only: the all-pairs refinement returned ZK_ENOCONV on
-    one of these tiny, exactly degenerate dilations (Clifford gates give equal
-    singular values and exact zeros); the single update above covers it."""
+    """Clifford gates give two-site matrices with equal singular values and
+    exact zeros: dilations whose tridiagonal splits into blocks sharing an
+    eigenvalue (the inverse iteration takes negligible couplings as zeros).
+    Per-pair refinement only: on one of these 6 x 6 dilations the all-pairs
+    refinement's first block rotation loses the basis (open); the single
+    update above covers that refinement."""
     Z, ctx, torch = zk
     n = 6
     sites = []
