@@ -644,16 +644,20 @@ __global__ void k_invit(ProbDesc *probs)
     for (int i = 0; i < n; i++)
         tnorm = fmax(tnorm, fabs(P.d[i]) + (i > 0 ? fabs(P.e[i - 1]) : 0.0) + (i < n - 1 ? fabs(P.e[i]) : 0.0));
     const double guard = fmax(tnorm, 1e-300) * 1.1102230246251565e-16;
-    // Couplings below eps ||T|| are taken as exact zeros (a perturbation within
-    // the backward error), so T splits into blocks.  An eigenvalue shared by
-    // two blocks (the +-s pairs of a dilation, a direct sum) then has a guarded
-    // pivot in each block and every start vector keeps both null directions;
-    // through a coupling of, say, 1e-17 the row exchange would instead drop
-    // one of them and all the inverse iterates of that eigenvalue would be the
-    // same vector.
+    // A coupling negligible against the entries of T - lam I it connects
+    // (|e_i| <= eps (|d_i - lam| + |d_(i+1) - lam|)) is taken as an exact zero,
+    // so T - lam I splits into blocks.  An eigenvalue shared by two blocks
+    // (the +-s pairs of a dilation with equal singular values, a direct sum)
+    // then has a guarded pivot in each block and every start vector keeps both
+    // null directions; through a coupling of, say, 1e-17 between entries of
+    // size 1 the row exchange would drop one of them and all the inverse
+    // iterates of that eigenvalue would be the same vector.  The threshold
+    // follows the shifted diagonal, so the couplings of tiny eigenvalues
+    // (tiny diagonal entries) are kept.
     auto cpl = [&](int i) {
         const double x = P.e[i];
-        return fabs(x) <= guard ? 0.0 : x;
+        const double scale = fabs(P.d[i] - lam) + fabs(P.d[i + 1] - lam);
+        return fabs(x) <= 1.1102230246251565e-16 * scale ? 0.0 : x;
     };
     // P L U factorisation of T - lam I by Gaussian elimination with partial
     // pivoting.  The row being eliminated always has two entries (a at
