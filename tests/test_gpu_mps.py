@@ -112,14 +112,11 @@ def test_two_site_update_against_oracle(zk, refine):
     log(f"two-site update refine={refine}: s err {float(err / s1):.2e}, reconstruction {float(worst / s1):.2e}")
 
 
-@pytest.mark.parametrize("refine", [0])
+@pytest.mark.parametrize("refine", [0, 1])
 def test_mps_circuit_against_exact_state(zk, refine):
     """Clifford gates give two-site matrices with equal singular values and
     exact zeros: dilations whose tridiagonal splits into blocks sharing an
-    eigenvalue (the inverse iteration takes negligible couplings as zeros).
-    Per-pair refinement only: on one of these 6 x 6 dilations the all-pairs
-    refinement's first block rotation loses the basis (open); the single
-    update above covers that refinement."""
+    eigenvalue (the inverse iteration takes negligible couplings as zeros)."""
     Z, ctx, torch = zk
     n = 6
     sites = []
