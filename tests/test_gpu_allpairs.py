@@ -188,3 +188,26 @@ def test_allpairs_refine_option_and_session(zk):
         gate([mats[i]], mixed[i], oracle.heev([mats[i]], want_vectors=False).w_limbs, DD_TOL, orth_tol=DD_ORTH)
     with pytest.raises(RuntimeError):
         Z.heev(ctx, [[dev[0]]], limbs_out=4, opts=opts)
+
+
+def test_dilation_shared_eigenvalues_both_refinements(zk):
+    """K = [[0, T], [T^H, 0]] with T (2 x 4) of orthonormal dyadic rows: the
+    eigenvalues are exactly -1, -1, 0, 0, 1, 1, and the tridiagonal of such
+    dilations splits into blocks that share an eigenvalue.  The binary64
+    stage must return independent vectors (it once returned one vector twice
+    there), and both refinements must reach the exact spectrum."""
+    Z, ctx, torch = zk
+    T = 0.5 * np.array([[1, 1j, -1, 1j], [1, -1j, 1, 1j]])
+    K = np.zeros((6, 6), dtype=np.complex128)
+    K[:2, 2:] = T
+    K[2:, :2] = T.conj().T
+    Kd = torch.from_numpy(K).cuda()
+    (w0, V0), = Z.heev_fp64(ctx, [[Kd]])
+    V0 = V0.cpu().numpy()
+    assert np.abs(V0.conj().T @ V0 - np.eye(6)).max() <= 1e-13
+    ref = np.zeros((4, 6))
+    ref[0] = [-1, -1, 0, 0, 1, 1]
+    for opts in (Z.make_opts(refine=0), Z.make_opts(refine=1)):
+        r, = Z.heev(ctx, [[Kd]], limbs_out=2, opts=opts)
+        assert r.status == Z.ZK_OK
+        gate([K], r, ref, DD_TOL, orth_tol=DD_ORTH)
