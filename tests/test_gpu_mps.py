@@ -162,3 +162,23 @@ def test_mps_circuit_against_exact_state(zk, refine):
         worst = max(worst, abs(vec[0][0] - psi[x][0]), abs(vec[0][1] - psi[x][1]))
     assert worst <= Fraction(1, 10 ** 29), f"amplitude error {float(worst):.3e}"
     log(f"mps circuit n={n} refine={refine}: bond dimensions per layer {chis}, max amplitude error {float(worst):.2e}")
+
+
+def test_two_site_update_errors(zk):
+    """Argument errors are rejected before any device work (ZK_EINVAL, raised by
+    the binding as RuntimeError; shape mismatches as ValueError)."""
+    Z, ctx, torch = zk
+    A = torch.zeros((4, 3), dtype=torch.complex128, device="cuda")
+    B = torch.zeros((3, 6), dtype=torch.complex128, device="cuda")
+    G = torch.eye(4, dtype=torch.complex128, device="cuda")
+    with pytest.raises(RuntimeError):
+        Z.mps_two_site(ctx, A, B, G, chi_max=0)
+    with pytest.raises(RuntimeError):
+        Z.mps_two_site(ctx, A, B, G, chi_max=5)       # above min(2 chi_l, 2 chi_r) = 4
+    with pytest.raises(RuntimeError):
+        Z.mps_two_site(ctx, A, B, G, chi_max=2, cutoff=float("nan"))
+    with pytest.raises(ValueError):
+        Z.mps_two_site(ctx, A, torch.zeros((2, 6), dtype=torch.complex128, device="cuda"), G, chi_max=2)
+    r = Z.mps_two_site(ctx, A, B, G, chi_max=2)          # the zero state: chi' = 1, s = 0
+    assert r.status == Z.ZK_OK and r.chi == 1
+    assert float(r.s[0, 0]) == 0.0
