@@ -587,31 +587,46 @@ __device__ int sturm_count(const double *d, const double *e, int n, double x, do
     return cnt;
 }
 
-__global__ void k_bisect(ProbDesc *probs)
+// Multisection: one wave per eigenvalue k.  Each round the 64 lanes count the
+// eigenvalues below 64 points spread evenly over the current interval and the
+// interval shrinks to the gap that holds eigenvalue k: about 6 bits per round
+// with the round's counts in parallel, where bisection gains one bit per
+// count.  Same bracket, stopping rule and final midpoint as bisection.
+__global__ void __launch_bounds__(256) k_bisect(ProbDesc *probs)
 {
     const ProbDesc &P = probs[blockIdx.y];
     const int n = P.n;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    double gl = P.d[0], gu = P.d[0], emax = 0.0;
-    for (int i = 0; i < n; i++) {
+    const int lane = threadIdx.x & 63;
+    const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (k >= n) return;   // uniform per wave; no barriers below
+    double gl = INFINITY, gu = -INFINITY, emax = 0.0;
+    for (int i = lane; i < n; i += 64) {
         const double r = (i > 0 ? fabs(P.e[i - 1]) : 0.0) + (i < n - 1 ? fabs(P.e[i]) : 0.0);
         gl = fmin(gl, P.d[i] - r);
         gu = fmax(gu, P.d[i] + r);
         if (i < n - 1) emax = fmax(emax, fabs(P.e[i]));
     }
+    for (int off = 32; off > 0; off >>= 1) {
+        gl = fmin(gl, __shfl_xor(gl, off, 64));
+        gu = fmax(gu, __shfl_xor(gu, off, 64));
+        emax = fmax(emax, __shfl_xor(emax, off, 64));
+    }
     const double tnorm = fmax(fabs(gl), fabs(gu));
     const double pivmin = fmax(2.2250738585072014e-308, 2.2250738585072014e-308 * emax * emax);
     const double eps = 1.1102230246251565e-16;
     double lo = gl - 2.0 * eps * tnorm - 2.0 * pivmin, hi = gu + 2.0 * eps * tnorm + 2.0 * pivmin;
-    for (int it = 0; it < 200; it++) {
-        const double mid = 0.5 * (lo + hi);
-        if (mid == lo || mid == hi) break;
+    for (int it = 0; it < 64; it++) {
         if (hi - lo <= 2.0 * eps * fmax(fabs(lo), fabs(hi)) + pivmin) break;
-        if (sturm_count(P.d, P.e, n, mid, pivmin) > k) hi = mid;
-        else lo = mid;
+        const double x = lo + (hi - lo) * ((double)(lane + 1) / 65.0);
+        const unsigned long long above = __ballot(sturm_count(P.d, P.e, n, x, pivmin) > k);
+        const int f = above ? __ffsll((long long)above) - 1 : 64;   // first point above eigenvalue k
+        const double xl = __shfl(x, f > 0 ? f - 1 : 0, 64), xh = __shfl(x, f < 64 ? f : 63, 64);
+        const double nlo = f > 0 ? xl : lo, nhi = f < 64 ? xh : hi;
+        if (nlo == lo && nhi == hi) break;
+        lo = nlo;
+        hi = nhi;
     }
-    P.w0[k] = 0.5 * (lo + hi);
+    if (lane == 0) P.w0[k] = 0.5 * (lo + hi);
 }
 
 // ------------------------------------------------------ inverse iteration --
@@ -1010,7 +1025,7 @@ int stage1_run(const Stage1Batch &B, hipStream_t st)
     hipLaunchKernelGGL(k_last_diag, dim3(cdiv(np, 64)), dim3(64), 0, st, pd, np);
     // ---- tridiagonal eigen-solver
     const int idt = B.timer ? B.timer->begin(KC_TRIDIAG, 0.0, st) : -1;
-    hipLaunchKernelGGL(k_bisect, dim3(cdiv(n, 128), np), dim3(128), 0, st, pd);
+    hipLaunchKernelGGL(k_bisect, dim3(cdiv(n, 4), np), dim3(256), 0, st, pd);
     hipLaunchKernelGGL(k_invit, dim3(cdiv(n, 64), np), dim3(64), 0, st, pd);
     hipLaunchKernelGGL(k_transpose, dim3(cdiv(n, 16), cdiv(n, 16), np), dim3(16, 16), 0, st, pd);
     hipLaunchKernelGGL(k_tri_plan, dim3(cdiv(n, 256), np), dim3(256), 0, st, pd, B.tri_gap_rel);
