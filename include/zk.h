@@ -139,6 +139,23 @@ const char *zk_ctx_last_error(const zk_ctx *ctx);
  * needs when `concurrent_pairs` shifted LU factorisations run at once. */
 size_t zk_workspace_bytes(int n, int limbs, int concurrent_pairs);
 
+/* Device workspace of the context: *held = bytes it holds now, *budget = its
+ * HBM budget, *high_water = the most it has held at once since creation,
+ * *transient = the part of *held that belongs to matrices in flight
+ * (iterate storage and plans of the refinement engines; 0 between
+ * synchronous calls, whether they succeeded or failed; the rest are
+ * grow-only workspaces kept for the next call).  Any pointer may be NULL.
+ * ZK_EINVAL for a NULL ctx. */
+int zk_ctx_memory(const zk_ctx *ctx, size_t *held, size_t *budget, size_t *high_water, size_t *transient);
+
+/* Counters of the per-pair Rayleigh quotient iteration of the last
+ * zk_heev_dd / zk_heev_qd call on ctx (all matrices of the call):
+ * iters_hist16[i] = number of pairs that took i shifted solves (i >= 15
+ * counted in the last bin), *rounds = iteration rounds, *solves = shifted
+ * solves in total.  Zeros after a call with opts->refine = 1.  Any pointer
+ * may be NULL.  ZK_EINVAL for a NULL ctx. */
+int zk_ctx_last_stats(const zk_ctx *ctx, int *iters_hist16, int *rounds, long long *solves);
+
 /*
  * zk_heev_dd / zk_heev_qd: eigendecompose `count` independent Hermitian
  * matrices A[0..count-1] (sizes may differ) to double-double (out[i].limbs ==
@@ -289,6 +306,9 @@ int zk_rqi_refine(zk_ctx *ctx, int limbs_out, const zk_herm *A, int k, const dou
  * zk_prof_read waits for the recorded events.
  */
 int zk_prof_enable(zk_ctx *ctx, int on);
+/* Restrict the timing to the classes whose bit (1u << class) is set in mask
+ * (default: all); the others record no events. */
+int zk_prof_classes(zk_ctx *ctx, unsigned mask);
 int zk_prof_reset(zk_ctx *ctx);
 int zk_prof_read(zk_ctx *ctx, int kernel_class, double *ms, long long *launches, double *work);
 
@@ -298,6 +318,12 @@ int zk_prof_read(zk_ctx *ctx, int kernel_class, double *ms, long long *launches,
  * stage of requests of equal order, and runs the Rayleigh quotient iterations
  * of every admitted request together in shared launches (continuous
  * batching).  Results are bitwise identical to a request run alone.
+ * budget: bytes of admitted footprints at once (0 = 16 GiB); a request's
+ * footprint is its stage-2 inputs plus its iterates and one shifted-LU slot
+ * (or the all-pairs state).  max_queue: requests waiting for admission at
+ * once (0 = unbounded); all work runs on the context's stream.  The session
+ * uses the context from its own thread: do not call other entry points on
+ * the same context while it lives.
  */
 int zk_session_create(zk_ctx *ctx, size_t budget, int max_queue, zk_session **out);
 
@@ -309,13 +335,17 @@ int zk_session_submit(zk_session *s, const zk_herm *A, zk_eig_out *out, int limb
 
 /* Wait up to timeout_us microseconds (0: do not wait, <0: forever) for the
  * request.  Returns ZK_OK when done (*req_status = its status), ZK_EAGAIN if
- * still pending, ZK_ECANCELED if cancelled, ZK_EINVAL for an unknown ticket. */
+ * still pending, ZK_ECANCELED if the session is being destroyed (a poll
+ * blocked at that moment wakes with it), ZK_EINVAL for an unknown ticket. */
 int zk_session_poll(zk_session *s, zk_ticket ticket, int timeout_us, int *req_status);
 
 /* Host-clock stamps of a finished request: submit, admission, completion (seconds). */
 int zk_session_times(zk_session *s, zk_ticket ticket, double *t_submit, double *t_admit, double *t_done);
 
-/* Stop the scheduler; pending requests become ZK_ECANCELED. */
+/* Stop the scheduler; pending requests (queued or running) are cancelled:
+ * threads blocked in zk_session_poll return ZK_ECANCELED, and destroy
+ * returns only after they have left.  The session handle is invalid after
+ * the call. */
 int zk_session_destroy(zk_session *s);
 
 #ifdef __cplusplus

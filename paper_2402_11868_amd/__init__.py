@@ -59,9 +59,10 @@ class ZkOpts(ctypes.Structure):
 KERNEL_CLASSES = ["lu_update", "lu_panel", "lu_trsm", "backsolve", "rq", "gs", "reorth", "stage1", "her2k", "hemv",
                   "build", "trd_vec", "tridiag", "backt", "ap_resid", "ap_fgemm", "ap_ddgemm", "ap_other"]
 
-EXPORTED = ["zk_prof_enable", "zk_prof_reset", "zk_prof_read", "zk_opts_default", "zk_ctx_create", "zk_ctx_destroy", "zk_status_str", "zk_ctx_last_error",
+EXPORTED = ["zk_prof_enable", "zk_prof_classes", "zk_prof_reset", "zk_prof_read", "zk_opts_default", "zk_ctx_create", "zk_ctx_destroy", "zk_status_str", "zk_ctx_last_error",
             "zk_workspace_bytes", "zk_heev_dd", "zk_heev_qd", "zk_heev_dd_allpairs", "zk_svd_dd", "zk_mps_two_site_dd", "zk_heev_fp64", "zk_rqi_refine",
-            "zk_session_create", "zk_session_submit", "zk_session_poll", "zk_session_times", "zk_session_destroy"]
+            "zk_session_create", "zk_session_submit", "zk_session_poll", "zk_session_times", "zk_session_destroy",
+            "zk_ctx_memory", "zk_ctx_last_stats"]
 
 _lib = None
 
@@ -93,11 +94,12 @@ def load(path: str = LIB_PATH):
                                        ctypes.POINTER(I), ctypes.POINTER(ZkOpts)]
     lib.zk_heev_fp64.argtypes = [P, I, ctypes.POINTER(ZkHerm), ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(I)]
     lib.zk_rqi_refine.argtypes = [P, I, ctypes.POINTER(ZkHerm), I, P, P, I, ctypes.POINTER(ZkEigOut), ctypes.POINTER(ZkOpts)]
-    if hasattr(lib, "zk_heev_stats"):
-        lib.zk_heev_stats.argtypes = [P, I, I, ctypes.POINTER(ZkHerm), ctypes.POINTER(ZkEigOut), ctypes.POINTER(ZkOpts),
-                                      ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(ctypes.c_longlong)]
+    lib.zk_ctx_last_stats.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(ctypes.c_longlong)]
+    SZ = ctypes.POINTER(ctypes.c_size_t)
+    lib.zk_ctx_memory.argtypes = [P, SZ, SZ, SZ, SZ]
     lib.zk_prof_enable.argtypes = [P, I]
     lib.zk_prof_reset.argtypes = [P]
+    lib.zk_prof_classes.argtypes = [P, ctypes.c_uint]
     lib.zk_prof_read.argtypes = [P, I, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(D)]
     if hasattr(lib, "zk_session_create"):
         lib.zk_session_create.argtypes = [P, ctypes.c_size_t, I, ctypes.POINTER(P)]
@@ -152,6 +154,11 @@ class Context:
     def prof_reset(self):
         load().zk_prof_reset(self.handle)
 
+    def prof_classes(self, names=None):
+        """Time only the named kernel classes (None: all)."""
+        mask = 0xFFFFFFFF if names is None else sum(1 << KERNEL_CLASSES.index(n) for n in names)
+        load().zk_prof_classes(self.handle, mask)
+
     def prof_read(self) -> dict:
         """{class name: (total ms, launches, algorithmic work)} of the recorded launches."""
         out = {}
@@ -163,6 +170,21 @@ class Context:
 
     def last_error(self) -> str:
         return load().zk_ctx_last_error(self.handle).decode()
+
+    def memory(self) -> dict:
+        """Workspace bytes: held now, the budget, the high-water mark, and the
+        part held for matrices in flight (zk_ctx_memory)."""
+        h, b, hw, tr = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+        load().zk_ctx_memory(self.handle, ctypes.byref(h), ctypes.byref(b), ctypes.byref(hw), ctypes.byref(tr))
+        return {"held": h.value, "budget": b.value, "high_water": hw.value, "transient": tr.value}
+
+    def last_stats(self) -> dict:
+        """Counters of the last heev call's per-pair iteration (zk_ctx_last_stats)."""
+        hist = (ctypes.c_int * 16)()
+        rounds = ctypes.c_int()
+        solves = ctypes.c_longlong()
+        load().zk_ctx_last_stats(self.handle, hist, ctypes.byref(rounds), ctypes.byref(solves))
+        return {"iters_hist": list(hist), "rounds": rounds.value, "solves": solves.value}
 
     def close(self):
         # sessions run on this context: stop them first
@@ -249,15 +271,10 @@ def heev(ctx: Context, mats, limbs_out: int = 2, opts: ZkOpts | None = None, sta
         O[i] = o
         outs.append((w, V, info, H[i].n))
     op = ctypes.byref(opts) if opts is not None else None
+    f = lib.zk_heev_dd if limbs_out == 2 else lib.zk_heev_qd
+    rc = f(ctx.handle, count, H, O, op)
     if stats is not None:
-        hist = (ctypes.c_int * 16)()
-        rounds = ctypes.c_int()
-        solves = ctypes.c_longlong()
-        rc = lib.zk_heev_stats(ctx.handle, limbs_out, count, H, O, op, hist, ctypes.byref(rounds), ctypes.byref(solves))
-        stats.update(iters_hist=list(hist), rounds=rounds.value, solves=solves.value)
-    else:
-        f = lib.zk_heev_dd if limbs_out == 2 else lib.zk_heev_qd
-        rc = f(ctx.handle, count, H, O, op)
+        stats.update(ctx.last_stats())
     if rc not in (ZK_OK, ZK_ENOCONV):
         raise RuntimeError(f"zk_heev failed: {status_str(rc)}: {ctx.last_error()}")
     return [EigResult(w, V, _info_list(info, n), rc) for (w, V, info, n) in outs]

@@ -864,6 +864,7 @@ struct ApEngine::Impl {
         }
         meta_bytes = b;
         ctx->extra += b;
+        ctx->note_held();
         return ZK_OK;
     }
     void release(HostProb *h)
@@ -908,6 +909,7 @@ int ApEngine::Impl::add(const std::vector<ApReq> &reqs)
     ch.bytes = total;
     ch.left = (int)reqs.size();
     ctx->extra += total;
+    ctx->note_held();
     chunks.push_back(ch);
     const int cid = (int)chunks.size() - 1;
     char *c = (char *)ch.p;

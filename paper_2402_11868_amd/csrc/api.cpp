@@ -109,6 +109,7 @@ int zk_ctx::ensure(DevBuf &b, size_t bytes)
         return fail(ZK_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
     }
     b.bytes = bytes;
+    note_held();
     return ZK_OK;
 }
 
@@ -561,6 +562,7 @@ extern "C" int zk_svd_dd(zk_ctx *ctx, int count, const zk_mat *A, zk_svd_out *ou
         return ctx->fail(ZK_ENOMEM, "hipMalloc of %zu bytes failed", off[count]);
     }
     ctx->extra += off[count];
+    ctx->note_held();
     std::vector<SvdDesc> D(count);
     std::vector<zk_herm> K(count);
     std::vector<zk_eig_out> E(count);
@@ -682,6 +684,7 @@ extern "C" int zk_mps_two_site_dd(zk_ctx *ctx, int chi_l, int chi, int chi_r, co
         return ctx->fail(ZK_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
     }
     ctx->extra += bytes;
+    ctx->note_held();
     char *b = (char *)buf;
     double *T[2], *U[2], *V[2], *S[2];
     for (int l = 0; l < 2; l++) { T[l] = (double *)b; b += bT; }
@@ -782,16 +785,40 @@ extern "C" int zk_heev_fp64(zk_ctx *ctx, int count, const zk_herm *A, double *co
     return ZK_OK;
 }
 
+// The per-pair iteration's counters of the call are kept in the context
+// (zk_ctx_last_stats); collecting them is host bookkeeping only.
 extern "C" int zk_heev_dd(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out *out, const zk_opts *opts)
 {
+    if (ctx) ctx->last = Stage2Stats();
     if (opts && opts->refine == 1) return run_heev_allpairs(ctx, count, A, out, opts);
-    return run_heev<2>(ctx, count, A, out, opts, nullptr);
+    return run_heev<2>(ctx, count, A, out, opts, ctx ? &ctx->last : nullptr);
 }
 
 extern "C" int zk_heev_qd(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out *out, const zk_opts *opts)
 {
+    if (ctx) ctx->last = Stage2Stats();
     if (opts && opts->refine != 0) return ctx ? ctx->fail(ZK_EINVAL, "the all-pairs refinement gives double-double output only") : ZK_EINVAL;
-    return run_heev<4>(ctx, count, A, out, opts, nullptr);
+    return run_heev<4>(ctx, count, A, out, opts, ctx ? &ctx->last : nullptr);
+}
+
+extern "C" int zk_ctx_last_stats(const zk_ctx *ctx, int *iters_hist16, int *rounds, long long *solves)
+{
+    if (!ctx) return ZK_EINVAL;
+    if (iters_hist16)
+        for (int i = 0; i < 16; i++) iters_hist16[i] = ctx->last.iters_hist[i];
+    if (rounds) *rounds = ctx->last.rounds;
+    if (solves) *solves = ctx->last.solves;
+    return ZK_OK;
+}
+
+extern "C" int zk_ctx_memory(const zk_ctx *ctx, size_t *held, size_t *budget, size_t *high_water, size_t *transient)
+{
+    if (!ctx) return ZK_EINVAL;
+    if (held) *held = ctx->held();
+    if (budget) *budget = ctx->budget;
+    if (high_water) *high_water = std::max(ctx->high_water, ctx->held());
+    if (transient) *transient = ctx->extra;
+    return ZK_OK;
 }
 
 // ====================================================== rqi_refine ========
@@ -861,6 +888,14 @@ extern "C" int zk_prof_enable(zk_ctx *ctx, int on)
     return ZK_OK;
 }
 
+extern "C" int zk_prof_classes(zk_ctx *ctx, unsigned mask)
+{
+    if (!ctx) return ZK_EINVAL;
+    ctx->timer.collect();
+    ctx->timer.mask = mask;
+    return ZK_OK;
+}
+
 extern "C" int zk_prof_reset(zk_ctx *ctx)
 {
     if (!ctx) return ZK_EINVAL;
@@ -878,15 +913,3 @@ extern "C" int zk_prof_read(zk_ctx *ctx, int cls, double *ms, long long *launche
     return ZK_OK;
 }
 
-// statistics entry used by the benchmark (not part of the public header)
-extern "C" int zk_heev_stats(zk_ctx *ctx, int limbs_out, int count, const zk_herm *A, zk_eig_out *out,
-                             const zk_opts *opts, int *iters_hist16, int *rounds, long long *solves)
-{
-    Stage2Stats s;
-    int rc = (limbs_out == 4) ? run_heev<4>(ctx, count, A, out, opts, &s) : run_heev<2>(ctx, count, A, out, opts, &s);
-    if (iters_hist16)
-        for (int i = 0; i < 16; i++) iters_hist16[i] = s.iters_hist[i];
-    if (rounds) *rounds = s.rounds;
-    if (solves) *solves = s.solves;
-    return rc;
-}

@@ -21,6 +21,14 @@ struct DevBuf {
     }
 };
 
+// Counters of the per-pair iteration of one call (zk_ctx_last_stats).
+struct Stage2Stats {
+    int iters_hist[16] = {0};
+    int rounds = 0;
+    long long solves = 0;
+    std::vector<int> active_per_iter;
+};
+
 struct zk_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -39,19 +47,18 @@ struct zk_ctx {
     // of different orders concurrently, and the events that join them
     hipStream_t side[3] = {nullptr, nullptr, nullptr};
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    Stage2Stats last;        // counters of the last zk_heev_dd / zk_heev_qd call
     zk::KernelTimer timer;   // per-kernel-class HIP-event timing (instrumentation)
     zk::KernelTimer *tp() { return timer.on ? &timer : nullptr; }
     size_t held() const;
+    size_t high_water = 0;   // largest held() seen at a growth
+    void note_held()
+    {
+        const size_t h = held();
+        if (h > high_water) high_water = h;
+    }
     int ensure(DevBuf &b, size_t bytes);
     int fail(int status, const char *fmt, ...);
-};
-
-// Counters the benchmark reads through zk_heev_stats().
-struct Stage2Stats {
-    int iters_hist[16] = {0};
-    int rounds = 0;
-    long long solves = 0;
-    std::vector<int> active_per_iter;
 };
 
 namespace zk {

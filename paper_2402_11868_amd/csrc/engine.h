@@ -87,8 +87,20 @@ class Stage2Engine {
     bool any_live() const { return !live.empty(); }
 
     // Prepare new matrices (clusters, start vectors, Gram-Schmidt, Rayleigh-Ritz,
-    // first Rayleigh quotients) and let them join the iteration.
+    // first Rayleigh quotients) and let them join the iteration.  On failure,
+    // the iterate storage of every batch member that did not join is given
+    // back, so a failed add leaves the context's budget as it found it.
     int add(const std::vector<S2Prob *> &batch)
+    {
+        const int rc = add_batch(batch);
+        if (rc != ZK_OK)
+            for (S2Prob *p : batch)
+                if (std::find(live.begin(), live.end(), p) == live.end()) release(p);
+        return rc;
+    }
+
+  private:
+    int add_batch(const std::vector<S2Prob *> &batch)
     {
         int rc;
         std::vector<double> w0h;
@@ -103,6 +115,7 @@ class Stage2Engine {
                 return ctx->fail(ZK_ENOMEM, "hipMalloc of %zu bytes failed", p->vecbytes);
             }
             ctx->extra += p->vecbytes;
+            ctx->note_held();
             P.vec = (double *)p->vecbuf;
             P.sigma = (double *)((char *)p->vecbuf + s2_align(8 * 2 * (size_t)L * n * n));
             w0h.resize(kp);
@@ -169,6 +182,7 @@ class Stage2Engine {
         return settle();
     }
 
+  public:
     // One round over every live matrix: shifted solves of all active pairs,
     // Gram-Schmidt in their clusters, Rayleigh quotients and convergence.
     // Matrices whose pairs have all stopped are finalised and moved to `finished`.
@@ -223,6 +237,8 @@ class Stage2Engine {
     double *d_gscratch = nullptr;
     size_t gs_scratch_bytes = 0;
     int S = 0, slot_n = 0;
+    void *slots_p = nullptr;   // the slot buffer (and its size) S and slot_n were laid out in
+    size_t slots_bytes = 0;
 
     int HIPFAIL(hipError_t e, const char *what) { return ctx->fail(ZK_EDEVICE, "%s: %s", what, hipGetErrorString(e)); }
 
@@ -247,6 +263,7 @@ class Stage2Engine {
         }
         gsbytes = bytes;
         ctx->extra += bytes;
+        ctx->note_held();
         return ZK_OK;
     }
 
@@ -274,9 +291,18 @@ class Stage2Engine {
         return B;
     }
 
-    // LU slots for orders up to n: as many as the budget allows (<= wanted)
+    // LU slots for orders up to n: as many as the budget allows (<= wanted).
+    // The slot buffer belongs to the context and is shared with the other
+    // engines of the context (the double-double and quad-double engines size
+    // it for their own limbs, the all-pairs engine may give it back when the
+    // budget is short), so the layout S x slot_n is trusted only while the
+    // buffer is the very one this engine laid out.
     int ensure_slots(int n, int wanted)
     {
+        if (ctx->s2lu.p != slots_p || ctx->s2lu.bytes != slots_bytes) {
+            S = 0;
+            slot_n = 0;
+        }
         if (n <= slot_n && S >= std::min(wanted, 64) && ctx->s2lu.p) return ZK_OK;
         const int nn = std::max(n, slot_n);
         const size_t per = s2_align(8 * s2_lu_slot_doubles(nn, L)) + s2_align(4 * (size_t)nn);
@@ -289,6 +315,8 @@ class Stage2Engine {
         if (rc != ZK_OK) return rc;
         S = s;
         slot_n = nn;
+        slots_p = ctx->s2lu.p;
+        slots_bytes = ctx->s2lu.bytes;
         return ZK_OK;
     }
 
@@ -714,6 +742,7 @@ class Stage2Engine {
             return ctx->fail(ZK_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
         }
         ctx->extra += bytes;
+        ctx->note_held();
         std::vector<PrrDesc> hd(nd);
         std::vector<zk_herm> hm(nd);
         std::vector<double *> hf(nd), w0(nd), V0(nd);

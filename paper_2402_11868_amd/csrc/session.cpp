@@ -65,13 +65,74 @@ struct Request {
     S2Prob prob;
 };
 
+// Bytes of the stage-2 inputs of one request (limb-planar copy, binary64 pairs, flag).
+size_t in_bytes(int n, int limbs_in)
+{
+    const size_t nn = (size_t)n * n;
+    return al(8 * 2 * (size_t)limbs_in * nn) + al(8 * (size_t)n) + al(16 * nn) + al(64);
+}
+
+// Admission footprint: the inputs, then either the all-pairs state or the
+// iterates plus one shifted-LU slot with its pivots (the least a request
+// needs to make progress; the engine adds slots as the context budget allows).
 size_t footprint(int n, int limbs_in, int L, int refine)
 {
     const size_t nn = (size_t)n * n;
-    const size_t in = al(8 * 2 * (size_t)limbs_in * nn) + al(8 * (size_t)n) + al(16 * nn) + al(64);   // inputs of stage 2
-    if (refine == 1) return in + zk::ap_bytes(n);                                               // all-pairs state
-    return in + al(8 * 2 * (size_t)L * nn) + al(8 * (size_t)L * n);                             // iterates
+    const size_t in = in_bytes(n, limbs_in);
+    if (refine == 1) return in + zk::ap_bytes(n);
+    const size_t slot = al(8 * zk::s2_lu_slot_doubles(n, L)) + al(4 * (size_t)n);
+    return in + al(8 * 2 * (size_t)L * nn) + al(8 * (size_t)L * n) + slot;
 }
+
+// Device memory for request inputs, recycled across requests: blocks are
+// kept in free lists by size class (powers of two from 64 KiB) and given back
+// to HIP only when the session ends, so the scheduler does not call hipMalloc
+// once the stream's sizes have been seen.
+class InPool {
+  public:
+    ~InPool() { clear(); }
+    void *get(size_t bytes)
+    {
+        const size_t c = cls(bytes);
+        auto it = free_.find(c);
+        if (it != free_.end() && !it->second.empty()) {
+            void *p = it->second.back();
+            it->second.pop_back();
+            return p;
+        }
+        void *p = nullptr;
+        if (hipMalloc(&p, c) != hipSuccess) {
+            hipGetLastError();
+            return nullptr;
+        }
+        size_[p] = c;
+        total_ += c;
+        return p;
+    }
+    void put(void *p)
+    {
+        if (p) free_[size_.at(p)].push_back(p);
+    }
+    void clear()
+    {
+        for (auto &kv : size_) hipFree(kv.first);
+        size_.clear();
+        free_.clear();
+        total_ = 0;
+    }
+    size_t total() const { return total_; }
+
+  private:
+    static size_t cls(size_t b)
+    {
+        size_t c = (size_t)64 << 10;
+        while (c < b) c <<= 1;
+        return c;
+    }
+    std::map<size_t, std::vector<void *>> free_;
+    std::map<void *, size_t> size_;
+    size_t total_ = 0;
+};
 
 }  // namespace
 
@@ -92,6 +153,10 @@ struct zk_session {
     Stage2Engine<4> *e4 = nullptr;
     zk::ApEngine *ap = nullptr;   // requests with the all-pairs refinement
     std::vector<Request *> running;
+    InPool pool;          // request input buffers (scheduler thread only)
+    int waiters = 0;      // threads inside zk_session_poll (guarded by mu)
+    bool closing = false; // zk_session_destroy has begun
+    std::condition_variable cv_left;
 
     void loop();
     int admit_and_start(std::vector<Request *> &fresh);
@@ -113,12 +178,8 @@ int zk_session::admit_and_start(std::vector<Request *> &fresh)
         fp32[i] = r->O.init_fp32;
         const int n = r->A.n;
         const size_t nn = (size_t)n * n;
-        const size_t bytes = al(8 * 2 * (size_t)r->A.limbs * nn) + al(8 * (size_t)n) + al(16 * nn) + al(64);
-        if (hipMalloc(&r->inbuf, bytes) != hipSuccess) {
-            r->inbuf = nullptr;
-            hipGetLastError();
-            return ZK_ENOMEM;
-        }
+        r->inbuf = pool.get(in_bytes(n, r->A.limbs));
+        if (!r->inbuf) return ZK_ENOMEM;
         char *b = (char *)r->inbuf;
         hf[i] = (double *)b;
         b += al(8 * 2 * (size_t)r->A.limbs * nn);
@@ -180,10 +241,8 @@ void zk_session::finish_ap()
     std::lock_guard<std::mutex> g(mu);
     for (const zk::ApDone &d : ap->finished) {
         Request *r = (Request *)d.cookie;
-        if (r->inbuf) {
-            hipFree(r->inbuf);
-            r->inbuf = nullptr;
-        }
+        pool.put(r->inbuf);
+        r->inbuf = nullptr;
         r->status = d.status;
         r->state = RQ_DONE;
         r->t_done = t;
@@ -201,10 +260,8 @@ void zk_session::finish(Stage2Engine<L> *e)
     std::lock_guard<std::mutex> g(mu);
     for (S2Prob *p : e->finished) {
         Request *r = (Request *)p->cookie;
-        if (r->inbuf) {
-            hipFree(r->inbuf);
-            r->inbuf = nullptr;
-        }
+        pool.put(r->inbuf);
+        r->inbuf = nullptr;
         r->status = p->status;
         r->state = RQ_DONE;
         r->t_done = t;
@@ -252,6 +309,8 @@ void zk_session::loop()
                     r->state = RQ_DONE;
                     r->status = rc;
                     r->t_done = now_s();
+                    pool.put(r->inbuf);
+                    r->inbuf = nullptr;
                 }
             }
             inflight = 0;
@@ -318,13 +377,19 @@ extern "C" int zk_session_poll(zk_session *s, zk_ticket ticket, int timeout_us, 
 {
     if (!s) return ZK_EINVAL;
     std::unique_lock<std::mutex> lk(s->mu);
+    if (s->closing) return ZK_ECANCELED;
     auto it = s->all.find(ticket);
     if (it == s->all.end()) return ZK_EINVAL;
     Request *r = it->second;
     auto ready = [&] { return r->state == RQ_DONE || r->state == RQ_CANCELLED; };
     if (!ready()) {
+        // zk_session_destroy waits for every waiter to leave before it frees
+        // the request and the session, so r and the condition variables
+        // stay valid for the whole wait
+        s->waiters++;
         if (timeout_us < 0) s->cv_done.wait(lk, ready);
         else if (timeout_us > 0) s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready);
+        if (--s->waiters == 0 && s->closing) s->cv_left.notify_all();
     }
     if (r->state == RQ_CANCELLED) return ZK_ECANCELED;
     if (r->state != RQ_DONE) return ZK_EAGAIN;
@@ -358,16 +423,21 @@ extern "C" int zk_session_destroy(zk_session *s)
     delete s->e4;
     delete s->ap;
     {
-        std::lock_guard<std::mutex> g(s->mu);
+        // pending requests are cancelled: a thread blocked in zk_session_poll
+        // wakes with ZK_ECANCELED, and the session is freed only after every
+        // such thread has left
+        std::unique_lock<std::mutex> lk(s->mu);
+        s->closing = true;
         for (auto &kv : s->all) {
             Request *r = kv.second;
             if (r->state == RQ_QUEUED || r->state == RQ_RUNNING) r->state = RQ_CANCELLED;
-            if (r->inbuf) hipFree(r->inbuf);
-            delete r;
         }
+        s->cv_done.notify_all();
+        s->cv_left.wait(lk, [&] { return s->waiters == 0; });
+        for (auto &kv : s->all) delete kv.second;
         s->all.clear();
     }
-    s->cv_done.notify_all();
+    s->pool.clear();
     delete s;
     return ZK_OK;
 }

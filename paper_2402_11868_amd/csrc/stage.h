@@ -22,6 +22,7 @@ enum KernelClass { KC_LU_UPDATE = 0, KC_LU_PANEL, KC_LU_TRSM, KC_BACKSOLVE, KC_R
 
 struct KernelTimer {
     bool on = false;
+    unsigned mask = ~0u;   // kernel classes that are timed (bit c = class c)
     struct Rec {
         int cls;
         hipEvent_t a, b;
@@ -46,7 +47,7 @@ struct KernelTimer {
     // returns the index of the record to close with end()
     int begin(int cls, double w, hipStream_t st)
     {
-        if (!on) return -1;
+        if (!on || !((mask >> cls) & 1u)) return -1;
         Rec r{cls, get(), get(), w};
         hipEventRecord(r.a, st);
         open.push_back(r);

@@ -50,3 +50,9 @@ def test_static_entry_points_without_device():
                                   None, None) == -1
     assert lib.zk_session_submit(None, None, None, 2, None, None) == -1
     assert lib.zk_ctx_destroy(None) == 0
+
+
+def test_context_queries_reject_null():
+    lib = ctypes.CDLL(LIB)
+    assert lib.zk_ctx_memory(None, None, None, None, None) == -1
+    assert lib.zk_ctx_last_stats(None, None, None, None) == -1

@@ -6,8 +6,7 @@ eigenvalues are exact zeros; the other two have the closed form
 (1 +- sqrt(2F - 1)) / 2 (F = ||rho||_F^2, exact), pinned against the oracle in
 test_workloads_circuit.py; across the last cut they are 1 - 2^-15 and 2^-15.
 Bar: eigenvalues within 1e-30, MPFR residuals within 1e-30 and
-orthonormality within 1e-28 on sampled pairs (the two nonzero ones and zeros
-from both ends)."""
+orthonormality within 1e-28 on every pair of every cut."""
 from decimal import Decimal
 from fractions import Fraction
 
@@ -60,15 +59,14 @@ def test_circuit_bond_stream(zk, refine):
         assert abs(dec(lam[-2]) - lo) <= Decimal(TOL), f"cut {m['k']}: second eigenvalue"
         for x in lam[:-2]:
             assert abs(x) <= Fraction(TOL), f"cut {m['k']}: zero eigenvalue off by {float(x):.3e}"
-        sample = sorted(set([0, 1, d // 2, d - 2, d - 1]))
-        rs, _ = oracle.residuals([m["rho"]], w[:, sample], V[:, :, sample])
+        rs, _ = oracle.residuals([m["rho"]], w, V)
         assert rs.max() <= TOL, f"cut {m['k']}: residual {rs.max():.3e}"
-        mo, md = oracle.gram(V[:, :, sample])
+        mo, md = oracle.gram(V)
         assert mo <= ORTH and md <= ORTH, f"cut {m['k']}: orthogonality {mo:.3e} / {md:.3e}"
         worst = max(worst, rs.max())
     eps = Fraction(1, 2 ** (n - 1))
     last = res[-1].w.cpu().numpy()
     got = sorted(limb_sum_fraction(last[:, j]) for j in range(2))
     assert abs(got[0] - eps) <= Fraction(TOL) and abs(got[1] - (1 - eps)) <= Fraction(TOL)
-    log(f"circuit stream n={n} refine={refine}: {len(mats)} bond matrices, sampled resid {worst:.2e}, "
+    log(f"circuit stream n={n} refine={refine}: {len(mats)} bond matrices, resid {worst:.2e}, "
         f"iterations {sorted(set(x['iters'] for r in res for x in r.info))}")

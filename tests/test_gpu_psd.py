@@ -13,8 +13,8 @@ Jacobi at order 256 takes minutes:
   2 m 1e-30 ||rho||_2^2 (a collective double-double pin of the spectrum);
 * agreement with LAPACK to binary64 accuracy; for the exact rho, no
   eigenvalue below -1e-30 ||rho||_2;
-* MPFR residuals and orthonormality on a sample of pairs taken from the zero
-  cluster, the tiny eigenvalues and the top of the spectrum.
+* MPFR residuals of every pair, each pair's device-reported residual against
+  its MPFR value, and the MPFR Gram matrix of all vectors.
 """
 from fractions import Fraction
 
@@ -23,7 +23,7 @@ import pytest
 
 import oracle
 
-from gpu_helpers import limb_sum_fraction, log
+from gpu_helpers import check_device_residuals, limb_sum_fraction, log
 
 pytestmark = pytest.mark.gpu
 
@@ -89,20 +89,22 @@ def test_psd_rank_deficient(zk, m, r, span, refine):
     dfr = abs(sum((x * x for x in lam), Fraction(0)) - fr)
     assert dtr <= m * Fraction(TOL) * Fraction(hn), f"trace off by {float(dtr) / hn:.3e} ||rho||"
     assert dfr <= 2 * m * Fraction(TOL) * Fraction(hn) ** 2, f"Frobenius norm off by {float(dfr) / hn ** 2:.3e} ||rho||^2"
-    sample = np.r_[0:4, m - r - 2:m - r + 6, m - 4:m]
-    rs, _ = oracle.residuals([rho], w[:, sample], V[:, :, sample])
-    assert rs.max() <= TOL * hn, f"residual {rs.max() / hn:.3e} ||rho||"
-    mo, md = oracle.gram(V[:, :, sample])
+    # every pair: MPFR residual, device residual against it, whole Gram matrix
+    rs, _ = oracle.residuals([rho], w, V)
+    assert rs.max() <= TOL * hn, f"residual {rs.max() / hn:.3e} ||rho|| (k={int(rs.argmax())})"
+    dd = check_device_residuals(res, np.arange(m), rs, hn, mode="agree" if refine == 0 else "bound")
+    mo, md = oracle.gram(V)
     assert mo <= ORTH and md <= ORTH, f"orthogonality {mo:.3e} / {md:.3e}"
     log(f"psd m={m} r={r} span={span} refine={refine}: trace {float(dtr) / hn:.2e}, "
-        f"frob {float(dfr) / hn ** 2:.2e}, sampled resid {rs.max() / hn:.2e}")
+        f"frob {float(dfr) / hn ** 2:.2e}, resid {rs.max() / hn:.2e}, device-vs-MPFR {dd:.1e}, "
+        f"orth {max(mo, md):.1e}")
 
 
 
 def test_psd_exact_rank_deficient_qd(zk):
     """The same exact null space in quad-double (bar 1e-60 ||rho||_2): the
-    exact zeros, the trace identity, sampled MPFR residuals and
-    orthonormality."""
+    exact zeros, the trace identity, MPFR residuals of every pair and
+    orthonormality of all vectors."""
     Z, ctx, torch = zk
     m, r = 128, 48
     qtol, qorth = 1e-60, 1e-58
@@ -118,9 +120,9 @@ def test_psd_exact_rank_deficient_qd(zk):
     assert max(abs(x) for x in lam[:m - r]) <= Fraction(qtol) * Fraction(hn)
     tr, _ = _exact_trace_frob(rho)
     assert abs(sum(lam, Fraction(0)) - tr) <= m * Fraction(qtol) * Fraction(hn)
-    sample = np.r_[0:4, m - r - 2:m - r + 4, m - 4:m]
-    rs, _ = oracle.residuals([rho], w[:, sample], V[:, :, sample])
+    rs, _ = oracle.residuals([rho], w, V)
     assert rs.max() <= qtol * hn, f"residual {rs.max() / hn:.3e} ||rho||"
-    mo, md = oracle.gram(V[:, :, sample])
+    check_device_residuals(res, np.arange(m), rs, hn, mode="agree", slack=1e-62)
+    mo, md = oracle.gram(V)
     assert mo <= qorth and md <= qorth, f"orthogonality {mo:.3e} / {md:.3e}"
-    log(f"psd qd m={m} r={r}: sampled resid {rs.max() / hn:.2e}, iterations {sorted(set(x['iters'] for x in res.info))}")
+    log(f"psd qd m={m} r={r}: resid {rs.max() / hn:.2e}, iterations {sorted(set(x['iters'] for x in res.info))}")

@@ -104,3 +104,107 @@ def test_session_qd_and_dd_mixed(zk):
     assert torch.equal(r1.w, alone.w)
     assert r2.status == Z.ZK_OK
     sess.close()
+
+
+def test_session_queue_full_and_cancel_on_destroy(zk):
+    """A bounded queue refuses with ZK_EAGAIN when full; destroying the session
+    cancels what is pending, and a thread blocked in zk_session_poll at that
+    moment wakes with ZK_ECANCELED (the session stays alive until it has left)."""
+    Z, ctx, torch = zk
+    import threading
+    mats = [torch.from_numpy(W.householder_hermitian(W.spectrum_c4(512), seed=21 + i)).cuda() for i in range(7)]
+    # each order-512 request's footprint is about 25 MB: the budget admits one
+    # at a time, the queue holds two more
+    sess = Z.Session(ctx, budget=40 << 20, max_queue=2)
+    sess.submit([mats[0]])
+    time.sleep(0.01)
+    refused = 0
+    waiting = []
+    for d in mats[1:]:
+        try:
+            waiting.append(sess.submit([d]))
+        except RuntimeError as e:
+            assert "EAGAIN" in str(e)
+            refused += 1
+    assert refused >= 1, "a queue bounded at 2 accepted 6 requests while one was running"
+    got = {}
+    entering = threading.Event()
+
+    def poller():
+        entering.set()
+        got["rc"] = sess.poll(waiting[-1], -1)[0]
+
+    th = threading.Thread(target=poller)
+    th.start()
+    assert entering.wait(10)
+    time.sleep(0.05)   # the poller is blocked inside zk_session_poll (ctypes drops the GIL)
+    sess.close()
+    th.join(timeout=60)
+    assert not th.is_alive(), "poller still blocked after destroy"
+    assert got["rc"] == Z.ZK_ECANCELED, f"poller woke with {Z.status_str(got['rc'])}"
+    log(f"queue-full refusals {refused}, poller woke with {Z.status_str(got['rc'])}")
+
+
+def test_failed_call_gives_back_its_memory(zk):
+    """A call that runs out of budget part-way (for instance after the
+    iterate storage of its matrix was taken, before a shifted-LU slot or the
+    Gram-Schmidt plan fits) must give that storage back: after the failed
+    call the context holds no per-call memory, and a repeated failure does
+    not grow what it holds."""
+    Z, ctx, torch = zk
+    n = 64
+    A = torch.from_numpy(W.householder_hermitian(W.spectrum_c4(n), seed=31)).cuda()
+    lib = Z.load()
+    full = lib.zk_workspace_bytes(n, 2, 1) + (1 << 20)
+    seen = 0
+    for cut in range(0, 1600 << 10, 32 << 10):
+        c = Z.Context(0, budget=full - cut)
+        try:
+            try:
+                Z.heev(c, [[A]], limbs_out=2)
+                assert c.memory()["transient"] == 0
+                continue
+            except RuntimeError as e:
+                assert "ENOMEM" in str(e), str(e)
+            m1 = c.memory()
+            assert m1["transient"] == 0, f"budget {full - cut}: {m1['transient']} bytes kept after a failed call"
+            with pytest.raises(RuntimeError, match="ENOMEM"):
+                Z.heev(c, [[A]], limbs_out=2)
+            m2 = c.memory()
+            assert m2["held"] == m1["held"] and m2["transient"] == 0, f"budget {full - cut}: {m1} -> {m2}"
+            seen += 1
+        finally:
+            c.close()
+    assert seen >= 1
+    log(f"failed-call budgets checked: {seen}")
+
+
+def test_engines_share_lu_slots_under_tight_budget(zk):
+    """Double-double, quad-double and all-pairs requests in one session whose
+    context budget is tight, so the all-pairs engine gives back the shifted-LU
+    slots that the two Rayleigh-quotient engines laid out for their own
+    limbs: every result still equals the one computed alone."""
+    Z, ctx, torch = zk
+    mats = [W.householder_hermitian(W.spectrum_c4(n), seed=W.seed_for(4, n) + 41 * i)
+            for i, n in enumerate([96, 64, 80, 96, 48, 64])]
+    dev = [torch.from_numpy(A).cuda() for A in mats]
+    kinds = [(2, 0), (4, 0), (2, 1), (2, 0), (4, 0), (2, 1)]
+    big = Z.Context(0)
+    alone = []
+    for d, (L, rf) in zip(dev, kinds):
+        alone.append(Z.heev(big, [[d]], limbs_out=L, opts=Z.make_opts(refine=rf))[0])
+    torch.cuda.synchronize()
+    big.close()
+    tight = Z.Context(0, budget=24 << 20)
+    sess = Z.Session(tight, budget=24 << 20)
+    tickets = []
+    for d, (L, rf) in zip(dev, kinds):
+        tickets.append(sess.submit([d], limbs_out=L, opts=Z.make_opts(refine=rf)))
+        time.sleep(0.003)
+    mixed = [sess.result(t) for t in tickets]
+    sess.close()
+    for i, (a, m) in enumerate(zip(alone, mixed)):
+        assert m.status == a.status, f"request {i}: status {m.status} vs {a.status}"
+        assert torch.equal(a.w, m.w) and torch.equal(a.V, m.V), f"request {i}: result differs under the tight budget"
+    log(f"tight budget: high water {tight.memory()['high_water']} of {24 << 20}")
+    tight.close()

@@ -3,11 +3,14 @@
 * clustered 1024: one 1024x1024 matrix with eigenvalues in clusters of 8
   (relative separation 1e-12, centres 1 .. 2^-50), in the launch
   configuration the benchmark times: all 1024 eigenvalues against stored
-  oracle values, MPFR residuals and orthogonality on sampled pairs.
+  oracle values, MPFR residuals of all 1024 pairs, the MPFR Gram matrix of all
+  1024 vectors, and every pair's device-reported residual (the one the
+  benchmark counts passing pairs by) against its MPFR residual.
 * batch: 256 independent 128x128 matrices (geometric spectra 10^(-k/8) down to
   1e-16 with four exact 2-fold degeneracies each) in ONE zk_heev_dd call;
-  every pair's device residual is gated, sampled members are gated against
-  stored oracle eigenvalues and MPFR residuals / orthogonality.
+  every pair's device residual is gated; 16 members spread over the batch are
+  gated in full against stored oracle eigenvalues, MPFR residuals and
+  orthogonality of every pair, and device-vs-MPFR residual agreement.
 * quad-double companions: 16 concurrent 256x256 requests through a session
   (4-limb Hadamard-family inputs carrying the quad-double spectrum {1-2^-59,
   2^-59} U 2^(-120k/254), exact in four binary64 limbs, so the true
@@ -95,9 +98,10 @@ def test_clustered_1024_against_golden(zk):
     log(f"clustered 1024: iterations {stats['iters_hist'][:10]}, status {res.status}")
     rs = np.array([x["resid"] for x in res.info])
     log(f"clustered 1024: device residual > tol for {(rs > DD_TOL).sum()} pairs, max {rs.max():.3e}")
-    # every eigenvalue; vectors on a sample spread over the spectrum (both ends, the tiny tail)
-    sample = np.r_[0:8, 336:352, 500:508, 1016:1024]
-    out = gate([A], res, gold, DD_TOL, orth_tol=DD_ORTH, sample=sample)
+    # every eigenvalue, every vector: MPFR residuals, the whole Gram matrix and
+    # the device residual of each pair against its MPFR value
+    out = gate([A], res, gold, DD_TOL, orth_tol=DD_ORTH, dev_resid="agree")
+    assert out["checked"] == 1024
     log(f"clustered 1024: {out}")
 
 
@@ -121,12 +125,12 @@ def test_batch_256_of_128(zk):
         assert rs <= DD_TOL, f"matrix {i}: device residual {rs:.3e}"
         assert hn > 0.0
     log(f"batch: max device residual {worst:.3e}")
-    sampled = [i for i in (0, 255) if G.exists(f"c2:{i}")]
-    assert sampled, "stored oracle values for the batch are missing"
-    for i in sampled:
+    members = list(range(0, 256, 17))
+    assert len(members) == 16 and all(G.exists(f"c2:{i}") for i in members), "stored batch oracle values missing"
+    for i in members:
         hdr, gold = G.load(f"c2:{i}")
         assert hdr["sha256"] == G.sha(mats[i])
-        out = gate([mats[i]], res[i], gold, DD_TOL, orth_tol=DD_ORTH)
+        out = gate([mats[i]], res[i], gold, DD_TOL, orth_tol=DD_ORTH, dev_resid="agree")
         log(f"batch member {i}: {out}")
 
 
@@ -149,8 +153,7 @@ def test_qd_companions_session(zk):
         bad = [(k, float(h.lam[k]), x["resid"], x["iters"], x["flags"]) for k, x in enumerate(r.info) if not (x["flags"] & 1)]
         assert r.status == Z.ZK_OK, f"request {i}: status {r.status}, unconverged (k, lam, resid, iters, flags) {bad[:8]}"
         ref = _exact_ref_limbs(h.lam)
-        sample = None if i == 0 else np.r_[0:4, 124:128, 252:256]
-        out = gate(h.planes, r, ref, QD_TOL, orth_tol=QD_ORTH if i == 0 else None, sample=sample)
+        out = gate(h.planes, r, ref, QD_TOL, orth_tol=QD_ORTH)
         log(f"companion {i}: {out}")
     sess.close()
     # the first request alone gives the same bits

@@ -68,3 +68,31 @@ def test_limb_planes_split():
     im = sum((Fraction(float(p[0, 0].imag)) for p in P), Fraction(0))
     assert abs(re - Fraction(1, 3)) < Fraction(1, 2 ** 210)
     assert abs(im + Fraction(2, 7)) < Fraction(1, 2 ** 210)
+
+
+def test_limb_sum_matrix_two_and_four_planes():
+    """limb_sum_matrix on more than one plane: values that binary64 cannot
+    hold (1 + 2^-60, -3 + 2^-70 i, a four-limb 2^-200 tail, limbs of opposite
+    signs that cancel) must come back exactly, in both the real and the
+    imaginary part and at every position of a non-square matrix."""
+    P0 = np.array([[1.0, 1j * -3.0, 2.0 ** 40], [0.25j, -1.0, 0.0]], dtype=np.complex128)
+    P1 = np.array([[2.0 ** -60, 1j * 2.0 ** -70, -1.0], [2.0 ** -80, 2.0 ** -53 * 1j, -(2.0 ** -90)]], dtype=np.complex128)
+    S = oracle.limb_sum_matrix([P0, P1])
+    assert len(S) == 2 and len(S[0]) == 3
+    assert S[0][0] == (1 + Fraction(1, 2 ** 60), F0)
+    assert S[0][1] == (F0, -3 + Fraction(1, 2 ** 70))
+    assert S[0][2] == (Fraction(2 ** 40 - 1), F0)
+    assert S[1][0] == (Fraction(1, 2 ** 80), Fraction(1, 4))
+    assert S[1][1] == (Fraction(-1), Fraction(1, 2 ** 53))
+    assert S[1][2] == (-Fraction(1, 2 ** 90), F0)
+    # four planes: 1 + 2^-60 + 2^-130 i + 2^-200, and a full cancellation
+    Q = [np.array([[1.0, 1.0]]), np.array([[2.0 ** -60, -1.0]]), np.array([[2.0 ** -130 * 1j, 0.0]]),
+         np.array([[2.0 ** -200, 0.0]])]
+    S4 = oracle.limb_sum_matrix([q.astype(np.complex128) for q in Q])
+    assert S4[0][0] == (1 + Fraction(1, 2 ** 60) + Fraction(1, 2 ** 200), Fraction(1, 2 ** 130))
+    assert S4[0][1] == (F0, F0)
+    # round trip through the greedy split of exact dyadic values needing four limbs
+    rng = np.random.default_rng(9)
+    T = [[(Fraction(int(rng.integers(-2 ** 40, 2 ** 40)), 1) + Fraction(int(rng.integers(1, 2 ** 40)), 2 ** 150),
+           Fraction(int(rng.integers(-2 ** 40, 2 ** 40)), 2 ** 100)) for _ in range(3)] for _ in range(2)]
+    assert oracle.limb_sum_matrix(oracle.limb_planes(T, L=4)) == T
