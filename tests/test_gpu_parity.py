@@ -1,6 +1,7 @@
 """Parity of the HIP path (through the C-ABI) with the MPFR oracle.
 
-Bar (the paper's target accuracy, Sec. 4): eigenvalue error and residual
+Bar (the accuracy the workloads are specified with; the paper fixes no
+tolerance): eigenvalue error and residual
 ||H v - lam v|| / ||v|| both <= 1e-30 ||H||_2 for double-double output and
 <= 1e-60 ||H||_2 for quad-double output; orthogonality max |v_i^H v_j| <=
 1e-28 (dd) / 1e-58 (qd).  Every check is evaluated on the returned limbs

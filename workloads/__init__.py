@@ -218,8 +218,9 @@ def schmidt_pair(k: int, omega: complex = 1.0, limbs: int = 2):
 
 
 # ----------------------------------------------------------------- spectra --
-# The readings below fix details that the workload descriptions of the paper
-# (Sec. 4) leave open.
+# The readings below fix details that the named workload specifications leave
+# open (the paper itself describes its test matrices only as Hermitian with
+# random elements, Sec. 2.1).
 
 def spectrum_c1() -> np.ndarray:
     """n=64: one eigenvalue exactly 2^-20; 63 values prop. to 2^(-k/2), k=0..62, summing to 1-2^-20."""
