@@ -33,6 +33,10 @@ HBM_GBS = 8000.0
 # trailing update (4 real products x 12: two-product, two-sum, compensation,
 # cross terms), counted from the kernel source
 CPLX_DD_FMA_INSTR = 48
+# binary64 instructions of one complex quad-double multiply-add in the LU
+# update (4 real products into five-level cascaded sums, about 247 each,
+# counted from the source)
+CPLX_QD_FMA_INSTR = 988
 
 
 # sources that the LU trailing-update kernel is compiled from; the stored HBM
@@ -282,41 +286,134 @@ def mps_leg(Z, ctx, torch, chi=128):
     return out
 
 
+def c1_leg(Z, ctx, torch, runs=100, warm=10, tol=1e-30):
+    """The 64 x 64 workload (one eigenvalue exactly 2^-20, the rest 2^(-k/2),
+    trace 1): median wall time of `runs` zk_heev_dd calls after `warm`
+    warm-ups, eigenpairs/s of pairs within both gates (stored oracle values,
+    device residual), iteration histogram."""
+    import numpy as np
+    import golden_io as G
+    import workloads as W
+    wl = W.workload(1)
+    Ad = torch.from_numpy(wl["A"]).cuda()
+    hdr, gold = G.load("c1")
+    assert hdr["sha256"] == G.sha(wl["A"])
+    for _ in range(warm):
+        Z.heev(ctx, [Ad], limbs_out=2)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        res, = Z.heev(ctx, [Ad], limbs_out=2)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    st = ctx.last_stats()
+    w = res.w.cpu().numpy()
+    hn = float(np.max(np.abs(gold[0])))
+    err = np.abs((w[0] - gold[0]) + (w[1] - gold[1]) - gold[2] - gold[3]) / hn
+    resid = np.array([i["resid"] for i in res.info])
+    ok = int(((err <= tol) & (resid <= tol)).sum())
+    med = float(np.median(ts))
+    return {"workload": "herm64_dd: 64x64, one eigenvalue 2^-20, 63 values 2^(-k/2), trace 1",
+            "runs": runs, "median_ms": med * 1e3, "p90_ms": float(np.percentile(ts, 90)) * 1e3,
+            "passing_pairs": ok, "eigenpairs_per_s": ok / med, "max_eig_err_rel": float(err.max()),
+            "max_resid_rel": float(resid.max()), "iters_hist": st["iters_hist"][:8]}
+
+
+def qd_companions_leg(Z, ctx, torch, count=16, n=256, tol=1e-60):
+    """The quad-double companions: `count` concurrent 256 x 256 requests
+    (4-limb inputs of the Hadamard family carrying {1-2^-59, 2^-59} and a
+    geometric tail to 2^-120, exact, so the true eigenvalues are known)
+    through one session: each request's latency, the total time, pairs within
+    the 1e-60 gates (exact eigenvalues, device residual), and the rate of the
+    quad-double LU update (HIP events) against its VALU peak."""
+    import numpy as np
+    from fractions import Fraction
+    import workloads as W
+    comps = [W.hadamard_exact(W.spectrum_c5_dyadic(n), seed=W.seed_for(5, 100 + i), limbs=4) for i in range(count)]
+    dev = [[torch.from_numpy(np.ascontiguousarray(p)).cuda() for p in h.planes] for h in comps]
+    sess = Z.Session(ctx)   # warm-up
+    sess.result(sess.submit(dev[0], limbs_out=4))
+    sess.close()
+    torch.cuda.synchronize()
+    ctx.prof_classes(["lu_update"])
+    ctx.prof(True)
+    ctx.prof_reset()
+    sess = Z.Session(ctx)
+    t0 = time.monotonic()
+    tickets = [sess.submit(d, limbs_out=4) for d in dev]
+    res = [sess.result(t) for t in tickets]
+    times = [sess.times(t) for t in tickets]
+    sess.close()
+    total = max(t[2] for t in times) - t0
+    ms_u, la_u, wk_u = ctx.prof_read()["lu_update"]
+    ctx.prof(False)
+    ctx.prof_classes(None)
+    ok = 0
+    worst = 0.0
+    for h, r in zip(comps, res):
+        w = r.w.cpu().numpy()
+        hn = float(h.lam[-1])
+        for k in range(n):
+            got = sum((Fraction(float(w[l, k])) for l in range(4)), Fraction(0))
+            e = float(abs(got - h.lam[k])) / hn
+            worst = max(worst, e)
+            ok += int(e <= tol and r.info[k]["resid"] <= tol)
+    peak = FP64_VALU_LANE_OPS / CPLX_QD_FMA_INSTR
+    lat = [t[2] - t[0] for t in times]
+    return {"workload": f"{count} concurrent {n}x{n} quad-double requests, 4-limb exact inputs, spectrum "
+                        "{1-2^-59, 2^-59} and 2^(-120k/254), qd to 1e-60",
+            "total_ms": total * 1e3, "latency_ms": [round(x * 1e3, 1) for x in lat],
+            "p50_ms": _pct(lat, 50), "max_ms": max(lat) * 1e3, "passing_pairs": ok, "pairs": count * n,
+            "eigenpairs_per_s": ok / total, "max_eig_err_rel": worst,
+            "max_resid_rel": max(x["resid"] for r in res for x in r.info),
+            "lu_update_qd": {"kernel": "k_s2_lu_update_gen<4>", "achieved": (wk_u / (ms_u / 1e3)) / 1e9 if ms_u else None,
+                             "peak": peak / 1e9, "unit": "G cplx-qd-FMA/s",
+                             "frac": (wk_u / (ms_u / 1e3)) / peak if ms_u else None, "launches": la_u,
+                             "avg_launch_ms": ms_u / max(la_u, 1)}}
+
+
 def _pct(x, q):
     import numpy as np
     return float(np.percentile(np.asarray(x), q)) * 1e3 if len(x) else None
 
 
-def serving_leg(Z, ctx, torch, count=200, load=0.7, tol=1e-30, refine=0):
+def serving_leg(Z, ctx, torch, count=1000, load=0.7, tol=1e-30, refine=0, search_count=300):
     """The serving workload: requests of sizes uniform over 16..512 (step 16),
-    spectra 2^(-39 k/(s-1)), open-loop Poisson arrivals.
+    a pool of 4 matrices per size with spectra 2^(-39 k/(s-1)), open-loop
+    Poisson arrivals.
 
     1. saturated throughput of the session (all requests queued at once);
-    2. Poisson arrivals at `load` x that throughput through the session
-       (continuous batching): p50 / p99 / max latency from scheduled arrival;
-    3. the same arrivals served one at a time by zk_heev_dd (FIFO).
+    2. the largest sustainable Poisson rate, by bisection over offered rates
+       (sustainable: completions keep up with arrivals, >= 95 % of the
+       offered rate, and the latency does not grow over the run, p90 of the
+       last third <= 2 x p90 of the first third);
+    3. Poisson arrivals at `load` x the saturated throughput through the
+       session (continuous batching): p50 / p99 / max latency from the
+       scheduled arrival over `count` requests;
+    4. the same arrivals served one at a time by zk_heev_dd (FIFO).
     """
     import numpy as np
     import workloads as W
     sizes = W.serving_sizes()
-    pool = {n: torch.from_numpy(W.workload(4, index=0, n=n)["A"]).cuda() for n in sizes}
+    pool = {(n, i): torch.from_numpy(W.workload(4, index=i, n=n)["A"]).cuda() for n in sizes for i in range(4)}
     opts = Z.make_opts(refine=refine)
     rng = np.random.Generator(np.random.PCG64(W.seed_for(4, 1)))
-    order = [sizes[i] for i in rng.integers(0, len(sizes), count)]
+    order = [(sizes[a], int(b)) for a, b in zip(rng.integers(0, len(sizes), count), rng.integers(0, 4, count))]
 
     def good_pairs(r):
         return sum(1 for x in r.info if x["resid"] <= tol)
 
-    # warm-up (untimed): one request of every tenth size
+    # warm-up (untimed): one request of every fourth size
     sess = Z.Session(ctx)
-    for t in [sess.submit([pool[n]], opts=opts) for n in sizes[::10]]:
+    for t in [sess.submit([pool[(n, 0)]], opts=opts) for n in sizes[::4]]:
         sess.result(t)
     sess.close()
 
     # 1. saturated
     sess = Z.Session(ctx)
     t0 = time.monotonic()
-    tickets = [sess.submit([pool[n]], opts=opts) for n in order]
+    tickets = [sess.submit([pool[key]], opts=opts) for key in order]
     res = [sess.result(t) for t in tickets]
     t_end = max(sess.times(t)[2] for t in tickets)
     sess.close()
@@ -324,46 +421,76 @@ def serving_leg(Z, ctx, torch, count=200, load=0.7, tol=1e-30, refine=0):
     sat_pairs = sum(good_pairs(r) for r in res) / (t_end - t0)
     torch.cuda.synchronize()
 
-    # 2. Poisson through the session
+    def poisson(rate, keys, seed):
+        arr, _ = W.poisson_stream(rate, len(keys), seed=seed)
+        sess = Z.Session(ctx)
+        t0 = time.monotonic() + 0.05
+        tickets = []
+        for ta, key in zip(arr, keys):
+            dt = t0 + ta - time.monotonic()
+            if dt > 0:
+                time.sleep(dt)
+            tickets.append(sess.submit([pool[key]], opts=opts))
+        res = [sess.result(t) for t in tickets]
+        done = [sess.times(t)[2] for t in tickets]
+        sess.close()
+        lat = [d - (t0 + ta) for d, ta in zip(done, arr)]
+        return res, lat, max(done) - t0, arr
+
+    # 2. sustainable rate
+    def sustainable(rate):
+        keys = order[:search_count]
+        _, lat, span, arr = poisson(rate, keys, W.seed_for(4, 3))
+        third = len(lat) // 3
+        p_first, p_last = np.percentile(lat[:third], 90), np.percentile(lat[-third:], 90)
+        keeps_up = len(keys) / span >= 0.95 * (len(keys) / arr[-1])
+        return keeps_up and p_last <= 2.0 * p_first, float(p_first), float(p_last)
+
+    lo, hi = 0.3 * sat_rate, 1.2 * sat_rate
+    search = []
+    ok_lo, a, b = sustainable(lo)
+    search.append({"rate_hz": lo, "sustainable": ok_lo, "p90_first_ms": a * 1e3, "p90_last_ms": b * 1e3})
+    best = lo if ok_lo else None
+    for _ in range(4):
+        mid = 0.5 * (lo + hi)
+        ok, a, b = sustainable(mid)
+        search.append({"rate_hz": mid, "sustainable": ok, "p90_first_ms": a * 1e3, "p90_last_ms": b * 1e3})
+        if ok:
+            best, lo = mid, mid
+        else:
+            hi = mid
+
+    # 3. Poisson through the session at `load` x saturated
     rate = load * sat_rate
-    arr, _ = W.poisson_stream(rate, count, seed=W.seed_for(4, 2))
-    sess = Z.Session(ctx)
-    t0 = time.monotonic() + 0.05
-    tickets = []
-    for ta, n in zip(arr, order):
-        dt = t0 + ta - time.monotonic()
-        if dt > 0:
-            time.sleep(dt)
-        tickets.append(sess.submit([pool[n]], opts=opts))
-    res = [sess.result(t) for t in tickets]
-    done = [sess.times(t)[2] for t in tickets]
-    sess.close()
-    lat = [d - (t0 + ta) for d, ta in zip(done, arr)]
-    span = max(done) - t0
+    res, lat, span, arr = poisson(rate, order, W.seed_for(4, 2))
     ok_req = sum(1 for r in res if r.status == Z.ZK_OK)
     pairs_ok = sum(good_pairs(r) for r in res)
 
-    # 3. one at a time, same arrivals
+    # 4. one at a time, same arrivals
     t0 = time.monotonic() + 0.05
     lat1 = []
-    for ta, n in zip(arr, order):
+    for ta, key in zip(arr, order):
         dt = t0 + ta - time.monotonic()
         if dt > 0:
             time.sleep(dt)
-        Z.heev(ctx, [[pool[n]]], limbs_out=2, opts=opts)
+        Z.heev(ctx, [[pool[key]]], limbs_out=2, opts=opts)
         torch.cuda.synchronize()
         lat1.append(time.monotonic() - (t0 + ta))
+    mem = ctx.memory()
     return {
-        "workload": "serving stream: sizes uniform over 16..512 step 16, spectra 2^(-39k/(s-1)) trace 1, "
-                    "Poisson arrivals, dd to 1e-30",
+        "workload": "serving stream: sizes uniform over 16..512 step 16, 4 matrices per size, spectra "
+                    "2^(-39k/(s-1)) trace 1, Poisson arrivals, dd to 1e-30",
         "requests": count,
         "saturated_req_per_s": sat_rate,
         "saturated_eigenpairs_per_s": sat_pairs,
+        "max_sustainable_rate_hz": best,
+        "rate_search": search,
         "rate_hz": rate,
         "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99), "max_ms": max(lat) * 1e3,
         "completed_req_per_s": count / span,
         "eigenpairs_per_s": pairs_ok / span,
         "requests_ok": ok_req,
+        "hbm_high_water_bytes": mem["high_water"],
         "one_at_a_time": {"p50_ms": _pct(lat1, 50), "p99_ms": _pct(lat1, 99), "max_ms": max(lat1) * 1e3},
     }
 
@@ -379,8 +506,8 @@ def main():
     ap.add_argument("--no-batch-leg", action="store_true", help="skip the 256 x 128^2 batch run")
     ap.add_argument("--no-allpairs-leg", action="store_true", help="skip the all-pairs refinement runs")
     ap.add_argument("--no-svd-leg", action="store_true", help="skip the 512 x 512 SVD runs")
-    ap.add_argument("--serving-requests", type=int, default=200,
-                    help="requests of the serving-stream leg (0 = skip the leg)")
+    ap.add_argument("--serving-requests", type=int, default=1000,
+                    help="requests of the serving-stream leg (0 = skip the leg; the all-pairs leg serves twice as many)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="run only a plain device-to-device copy of BYTES, three times (counter calibration)")
     args = ap.parse_args()
@@ -543,12 +670,17 @@ def main():
     if not args.no_batch_leg:
         log("batch of 256 x 128^2")
         out["batch"] = batch_leg(Z, ctx, torch)
+    log("64 x 64 workload")
+    out["c1"] = c1_leg(Z, ctx, torch)
+    log("quad-double companions")
+    out["qd_companions"] = qd_companions_leg(Z, ctx, torch)
     if args.serving_requests > 0:
         log("serving stream")
         out["serving"] = serving_leg(Z, ctx, torch, count=args.serving_requests)
         if not args.no_allpairs_leg:
             log("serving stream, all-pairs refinement")
-            out["serving_allpairs"] = serving_leg(Z, ctx, torch, count=args.serving_requests, refine=1)
+            out["serving_allpairs"] = serving_leg(Z, ctx, torch, count=2 * args.serving_requests, refine=1,
+                                                  search_count=600)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline()

@@ -837,15 +837,7 @@ struct ApEngine::Impl {
     // the Rayleigh-quotient engine are scratch between its rounds (it sizes
     // them again, from what is left, at its next round), so they are given
     // back when the budget is short
-    bool room(size_t b)
-    {
-        if (ctx->held() + b <= ctx->budget) return true;
-        if (ctx->s2lu.p) {
-            hipStreamSynchronize(ctx->stream);
-            ctx->s2lu.release();
-        }
-        return ctx->held() + b <= ctx->budget;
-    }
+    bool room(size_t b) { return ctx->make_room(b); }
     int ensure_meta(size_t b)
     {
         if (b <= meta_bytes) return ZK_OK;

@@ -97,10 +97,21 @@ size_t zk_ctx::held() const { return s1.bytes + s2in.bytes + s2vec.bytes + s2lu.
 
 // Grow a workspace buffer (contents are not preserved).  ZK_ENOMEM if the
 // budget would be exceeded.
+bool zk_ctx::make_room(size_t bytes)
+{
+    if (held() + bytes <= budget) return true;
+    if (s2lu.p) {
+        hipStreamSynchronize(stream);
+        s2lu.release();
+    }
+    return held() + bytes <= budget;
+}
+
 int zk_ctx::ensure(DevBuf &b, size_t bytes)
 {
     bytes = (bytes + 255) & ~(size_t)255;
     if (bytes <= b.bytes) return ZK_OK;
+    if (&b != &s2lu && held() - b.bytes + bytes > budget) make_room(bytes - b.bytes);
     if (held() - b.bytes + bytes > budget) return fail(ZK_ENOMEM, "workspace of %zu bytes exceeds the budget", bytes);
     b.release();
     if (hipMalloc(&b.p, bytes) != hipSuccess) {
@@ -343,6 +354,7 @@ int run_stage1(zk_ctx *ctx, int count, const zk_herm *A, const std::vector<doubl
     for (int i = 0; i < count; i++) groups[std::make_pair(A[i].n, fp32.empty() ? 0 : (fp32[i] ? 1 : 0))].push_back(i);
     size_t total = 0;
     for (auto &kv : groups) total += stage1_batch_bytes(kv.first.first, (int)kv.second.size());
+    if (total > ctx->s1.bytes) ctx->make_room(total - ctx->s1.bytes);
     const size_t avail = ctx->budget > ctx->held() - ctx->s1.bytes ? ctx->budget - (ctx->held() - ctx->s1.bytes) : 0;
     if (groups.size() > 1 && total <= avail) {
         if ((rc = ctx->ensure(ctx->s1, total)) != ZK_OK) return rc;
@@ -555,7 +567,7 @@ extern "C" int zk_svd_dd(zk_ctx *ctx, int count, const zk_mat *A, zk_svd_out *ou
         const size_t N = (size_t)A[i].m + A[i].n;
         off[i + 1] = off[i] + align_up(16 * N * N * A[i].limbs) + 2 * align_up(8 * N) + 2 * align_up(16 * N * N);
     }
-    if (ctx->held() + off[count] > ctx->budget) return ctx->fail(ZK_ENOMEM, "the dilations need %zu bytes", off[count]);
+    if (!ctx->make_room(off[count])) return ctx->fail(ZK_ENOMEM, "the dilations need %zu bytes", off[count]);
     void *buf = nullptr;
     if (hipMalloc(&buf, off[count]) != hipSuccess) {
         hipGetLastError();
@@ -677,7 +689,7 @@ extern "C" int zk_mps_two_site_dd(zk_ctx *ctx, int chi_l, int chi, int chi_r, co
     const size_t bT = align_up(16 * (size_t)M * N), bU = align_up(16 * (size_t)M * k), bV = align_up(16 * (size_t)N * k),
                  bS = align_up(8 * (size_t)k);
     const size_t bytes = 2 * (bT + bU + bV + bS);
-    if (ctx->held() + bytes > ctx->budget) return ctx->fail(ZK_ENOMEM, "the two-site update needs %zu bytes", bytes);
+    if (!ctx->make_room(bytes)) return ctx->fail(ZK_ENOMEM, "the two-site update needs %zu bytes", bytes);
     void *buf = nullptr;
     if (hipMalloc(&buf, bytes) != hipSuccess) {
         hipGetLastError();

@@ -58,6 +58,10 @@ struct zk_ctx {
         if (h > high_water) high_water = h;
     }
     int ensure(DevBuf &b, size_t bytes);
+    // Room for `bytes` more under the budget: the shifted-LU slots are
+    // scratch between iteration rounds (every engine lays them out again when
+    // the buffer changed), so they are given back when the budget is short.
+    bool make_room(size_t bytes);
     int fail(int status, const char *fmt, ...);
 };
 

@@ -108,7 +108,7 @@ class Stage2Engine {
             RqiProb &P = p->rp;
             const int n = P.n, kp = p->npairs;
             p->vecbytes = s2_align(8 * 2 * (size_t)L * n * n) + s2_align(8 * (size_t)L * n);
-            if (ctx->held() + p->vecbytes > ctx->budget) return ctx->fail(ZK_ENOMEM, "iterate storage exceeds the budget");
+            if (!ctx->make_room(p->vecbytes)) return ctx->fail(ZK_ENOMEM, "iterate storage exceeds the budget");
             if (hipMalloc(&p->vecbuf, p->vecbytes) != hipSuccess) {
                 p->vecbuf = nullptr;
                 hipGetLastError();
@@ -255,7 +255,7 @@ class Stage2Engine {
             gsbytes = 0;
         }
         bytes = std::max(bytes, (size_t)1 << 20);
-        if (ctx->held() + bytes > ctx->budget) return ctx->fail(ZK_ENOMEM, "Gram-Schmidt plan exceeds the budget");
+        if (!ctx->make_room(bytes)) return ctx->fail(ZK_ENOMEM, "Gram-Schmidt plan exceeds the budget");
         if (hipMalloc(&gsbuf, bytes) != hipSuccess) {
             gsbuf = nullptr;
             hipGetLastError();
@@ -493,29 +493,35 @@ class Stage2Engine {
         int pi, k0, size;
     };
 
-    // shifted solves of the given pairs (pair-table indices grouped by order)
+    // shifted solves of the given pairs (pair-table indices grouped by order):
+    // every order in the same launches, largest orders first, in chunks of
+    // as many pairs as there are LU slots; one host synchronisation at the end
     int solve_pairs(const std::map<int, std::vector<int>> &by_n, int nact)
     {
         int max_n = 0;
         for (auto &kv : by_n) max_n = std::max(max_n, kv.first);
         int rc = ensure_slots(max_n, nact);
         if (rc != ZK_OK) return rc;
-        Stage2Batch B = batch_base();
-        for (auto &kv : by_n) {
-            const int n = kv.first;
-            const std::vector<int> &lst = kv.second;
-            for (size_t c0 = 0; c0 < lst.size(); c0 += (size_t)S) {
-                const int cnt = (int)std::min<size_t>((size_t)S, lst.size() - c0);
-                HIPCHK_(hipMemcpyAsync(d_active, lst.data() + c0, 4 * (size_t)cnt, hipMemcpyHostToDevice, st));
-                B.n = n;
-                B.count = cnt;
-                B.ldm = s2_lu_ldm(n);
-                B.lu_stride = s2_lu_slot_doubles(n, L);
-                B.piv_stride = (size_t)n;
-                if (stage2_solve<L>(B, st)) return ctx->fail(ZK_EDEVICE, "solve launch failed");
-                HIPCHK_(hipStreamSynchronize(st));
+        std::vector<int> lst, ord;
+        for (auto it = by_n.rbegin(); it != by_n.rend(); ++it)
+            for (int g : it->second) {
+                lst.push_back(g);
+                ord.push_back(it->first);
             }
+        HIPCHK_(hipMemcpyAsync(d_active, lst.data(), 4 * lst.size(), hipMemcpyHostToDevice, st));
+        Stage2Batch B = batch_base();
+        for (size_t c0 = 0; c0 < lst.size(); c0 += (size_t)S) {
+            const int cnt = (int)std::min<size_t>((size_t)S, lst.size() - c0);
+            const int n = ord[c0];
+            B.dev_active = d_active + c0;
+            B.n = n;
+            B.count = cnt;
+            B.ldm = s2_lu_ldm(n);
+            B.lu_stride = s2_lu_slot_doubles(n, L);
+            B.piv_stride = (size_t)n;
+            if (stage2_solve<L>(B, ord.data() + c0, st)) return ctx->fail(ZK_EDEVICE, "solve launch failed");
         }
+        HIPCHK_(hipStreamSynchronize(st));
         return ZK_OK;
     }
 
@@ -735,7 +741,7 @@ class Stage2Engine {
             // Y, C, hf, V0, w0, flag
             bytes += s2_align(8 * 2 * (size_t)L * n * m) + 3 * s2_align(16 * m * m) + s2_align(8 * m) + s2_align(4);
         }
-        if (ctx->held() + bytes > ctx->budget) return ctx->fail(ZK_ENOMEM, "projected Rayleigh-Ritz exceeds the budget");
+        if (!ctx->make_room(bytes)) return ctx->fail(ZK_ENOMEM, "projected Rayleigh-Ritz exceeds the budget");
         void *buf = nullptr;
         if (hipMalloc(&buf, bytes) != hipSuccess) {
             hipGetLastError();

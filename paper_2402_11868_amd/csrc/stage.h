@@ -151,9 +151,12 @@ struct LuSlot {
 };
 
 // Stage-2 launch table: `count` active pairs (indices into the pair table).
+// leading dimension of a pair's LU planes (each plane ldm x (n+1) doubles)
+__host__ __device__ inline int lu_ldm_of(int n) { return (n + 7) & ~7; }
+
 struct Stage2Batch {
     int L;                  // 2 (dd) or 4 (qd)
-    int n;                  // order shared by the pairs of this launch group
+    int n;                  // largest order of the pairs of this launch (grid extents)
     int count;
     const int *dev_active;  // pair indices (device)
     PairDesc *dev_pairs;
@@ -162,7 +165,7 @@ struct Stage2Batch {
     size_t lu_stride;       // doubles
     int *piv_base;          // slot s at piv_base + s * piv_stride
     size_t piv_stride;
-    int ldm;                // leading dimension of the LU planes
+    int ldm;                // unused by the solve (each pair's planes use lu_ldm_of(its order))
     int max_iter;
     int final_pass;         // rq: re-judge converged pairs after re-orthogonalisation
     KernelTimer *timer;     // host object, may be null
@@ -218,7 +221,9 @@ template <int L> int stage2_prr_project(const PrrDesc *d, int nd, int max_size, 
 // V <- V Q for every descriptor
 template <int L> int stage2_prr_rotate(const PrrDesc *d, int nd, int max_size, int max_n, RqiProb *probs, hipStream_t st);
 template <int L> int stage2_rq(const Stage2Batch &B, hipStream_t st);
-template <int L> int stage2_solve(const Stage2Batch &B, hipStream_t st);
+// orders: the pairs' matrix orders (host, count entries, non-increasing);
+// B.n = orders[0] sets the grid extents, the LU slots are B.lu_stride apart
+template <int L> int stage2_solve(const Stage2Batch &B, const int *orders, hipStream_t st);
 template <int L> int stage2_output(PairDesc *pairs, RqiProb *probs, const int *dst, int npairs, hipStream_t st);
 
 }  // namespace zk

@@ -398,7 +398,7 @@ __global__ void __launch_bounds__(256) k_s2_build(Stage2Batch B)
     const int t = blockIdx.y;
     const PairDesc &Q = B.dev_pairs[B.dev_active[t]];
     const RqiProb &P = B.dev_probs[Q.prob];
-    const int n = P.n, k = Q.k, ldm = B.ldm;
+    const int n = P.n, k = Q.k, ldm = lu_ldm_of(n);
     double *M = B.lu_base + (size_t)t * B.lu_stride;
     const size_t plane = (size_t)ldm * (n + 1);
     const size_t nn = (size_t)n * n;
@@ -449,7 +449,9 @@ __global__ void __launch_bounds__(256) k_s2_lu_panel(Stage2Batch B, int k0, int 
     const int t = blockIdx.x;
     PairDesc &Q = B.dev_pairs[B.dev_active[t]];
     const RqiProb &P = B.dev_probs[Q.prob];
-    const int n = P.n, ldm = B.ldm;
+    const int n = P.n, ldm = lu_ldm_of(n);
+    if (k0 >= n) return;        // a launch of mixed orders: this pair's factorisation has ended
+    nbw = min(nbw, n - k0);     // the pair's own panel width at this step
     double *M = B.lu_base + (size_t)t * B.lu_stride;
     int *ipiv = B.piv_base + (size_t)t * B.piv_stride;
     const size_t plane = (size_t)ldm * (n + 1);
@@ -596,7 +598,9 @@ __global__ void __launch_bounds__(256) k_s2_lu_trsm(Stage2Batch B, int k0, int n
     const int t = blockIdx.y;
     const PairDesc &Q = B.dev_pairs[B.dev_active[t]];
     const RqiProb &P = B.dev_probs[Q.prob];
-    const int n = P.n, ldm = B.ldm;
+    const int n = P.n, ldm = lu_ldm_of(n);
+    if (k0 >= n) return;
+    nbw = min(nbw, n - k0);
     double *M = B.lu_base + (size_t)t * B.lu_stride;
     const int *ipiv = B.piv_base + (size_t)t * B.piv_stride;
     const size_t plane = (size_t)ldm * (n + 1);
@@ -674,11 +678,14 @@ __global__ void __launch_bounds__(256, 2) k_s2_lu_update_dd(Stage2Batch B, int k
 {
     const int t = blockIdx.y;
     const PairDesc &Q = B.dev_pairs[B.dev_active[t]];
-    const int n = B.dev_probs[Q.prob].n, ldm = B.ldm;
+    const int n = B.dev_probs[Q.prob].n, ldm = lu_ldm_of(n);
+    if (k0 >= n) return;
+    nbw = min(nbw, n - k0);
     double *M = B.lu_base + (size_t)t * B.lu_stride;
     const size_t plane = (size_t)ldm * (n + 1);
     const int r0 = k0 + nbw;
     const int mrows = n - r0, mcols = n + 1 - r0;
+    if (mrows <= 0) return;
     const int tilesI = (mrows + 63) / 64;
     const int ti = blockIdx.x % tilesI, tj = blockIdx.x / tilesI;
     const int i0 = r0 + ti * 64, j0 = r0 + tj * 64;
@@ -776,11 +783,14 @@ __global__ void __launch_bounds__(256) k_s2_lu_update_gen(Stage2Batch B, int k0,
 {
     const int t = blockIdx.y;
     const PairDesc &Q = B.dev_pairs[B.dev_active[t]];
-    const int n = B.dev_probs[Q.prob].n, ldm = B.ldm;
+    const int n = B.dev_probs[Q.prob].n, ldm = lu_ldm_of(n);
+    if (k0 >= n) return;
+    nbw = min(nbw, n - k0);
     double *M = B.lu_base + (size_t)t * B.lu_stride;
     const size_t plane = (size_t)ldm * (n + 1);
     const int r0 = k0 + nbw;
     const int mrows = n - r0, mcols = n + 1 - r0;
+    if (mrows <= 0) return;
     const int tilesI = (mrows + 31) / 32;
     const int ti = blockIdx.x % tilesI, tj = blockIdx.x / tilesI;
     const int i0 = r0 + ti * 32, j0 = r0 + tj * 32;
@@ -832,7 +842,7 @@ __global__ void __launch_bounds__(256) k_s2_backsolve(Stage2Batch B)
     const int t = blockIdx.x;
     PairDesc &Q = B.dev_pairs[B.dev_active[t]];
     const RqiProb &P = B.dev_probs[Q.prob];
-    const int n = P.n, ldm = B.ldm, k = Q.k;
+    const int n = P.n, ldm = lu_ldm_of(n), k = Q.k;
     double *M = B.lu_base + (size_t)t * B.lu_stride;
     const size_t plane = (size_t)ldm * (n + 1);
     const size_t nn = (size_t)n * n;
@@ -1564,8 +1574,14 @@ int stage2_rq(const Stage2Batch &B, hipStream_t st)
 }
 
 template <int L>
-int stage2_solve(const Stage2Batch &B, hipStream_t st)
+int stage2_solve(const Stage2Batch &B, const int *orders, hipStream_t st)
 {
+    // orders[0..count-1]: the pairs' matrix orders, non-increasing (host).
+    // Pairs of different orders share every launch: at panel step k0 only the
+    // leading pairs with order > k0 take part (grid.y), each kernel works with
+    // its pair's own order and panel width, and the grid.x extents follow the
+    // largest order (smaller pairs' extra work-groups exit at once), so a
+    // pair's arithmetic is the same in any mix.
     const int n = B.n, cnt = B.count;
     if (cnt <= 0) return 0;
     KernelTimer dummy;
@@ -1574,30 +1590,40 @@ int stage2_solve(const Stage2Batch &B, hipStream_t st)
     hipLaunchKernelGGL(k_s2_build<L>, dim3(cdiv2(n + 1, 8), cnt), dim3(256), 0, st, B);
     T.end(id, st);
     for (int k0 = 0; k0 < n; k0 += kLuNB) {
+        int c = cnt;
+        while (c > 0 && orders[c - 1] <= k0) c--;
         const int nbw = std::min(kLuNB, n - k0);
-        id = T.begin(KC_LU_PANEL, (double)cnt * (n - k0) * nbw * nbw * 0.5, st);
-        hipLaunchKernelGGL(k_s2_lu_panel<L>, dim3(cnt), dim3(256), 0, st, B, k0, nbw);
+        double wp = 0.0, wt = 0.0, wu = 0.0;
+        for (int q = 0; q < c; q++) {
+            const int m = orders[q], b = std::min(kLuNB, m - k0), r0 = k0 + b;
+            wp += 0.5 * (double)(m - k0) * b * b;
+            wt += 0.5 * (double)(m + 1 - r0) * b * b;
+            wu += (double)(m - r0) * (m + 1 - r0) * b;   // complex multi-limb multiply-adds of A22 -= L21 U12
+        }
+        id = T.begin(KC_LU_PANEL, wp, st);
+        hipLaunchKernelGGL(k_s2_lu_panel<L>, dim3(c), dim3(256), 0, st, B, k0, nbw);
         T.end(id, st);
         const int r0 = k0 + nbw;
         const int ncols = n + 1 - r0;
-        id = T.begin(KC_LU_TRSM, (double)cnt * ncols * nbw * nbw * 0.5, st);
-        hipLaunchKernelGGL(k_s2_lu_trsm<L>, dim3(cdiv2(ncols, 8 * kTrsmGroups), cnt), dim3(256), 0, st, B, k0, nbw);
+        id = T.begin(KC_LU_TRSM, wt, st);
+        hipLaunchKernelGGL(k_s2_lu_trsm<L>, dim3(cdiv2(ncols, 8 * kTrsmGroups), c), dim3(256), 0, st, B, k0, nbw);
         T.end(id, st);
         const int mrows = n - r0;
         if (mrows > 0) {
-            // algorithmic work: complex multi-limb multiply-adds of A22 -= L21 U12
-            id = T.begin(KC_LU_UPDATE, (double)cnt * mrows * ncols * nbw, st);
+            id = T.begin(KC_LU_UPDATE, wu, st);
             if (L == 2) {
                 const unsigned tiles = cdiv2(mrows, 64) * cdiv2(ncols, 64);
-                hipLaunchKernelGGL(k_s2_lu_update_dd, dim3(tiles, cnt), dim3(256), 0, st, B, k0, nbw);
+                hipLaunchKernelGGL(k_s2_lu_update_dd, dim3(tiles, c), dim3(256), 0, st, B, k0, nbw);
             } else {
                 const unsigned tiles = cdiv2(mrows, 32) * cdiv2(ncols, 32);
-                hipLaunchKernelGGL(k_s2_lu_update_gen<L>, dim3(tiles, cnt), dim3(256), 0, st, B, k0, nbw);
+                hipLaunchKernelGGL(k_s2_lu_update_gen<L>, dim3(tiles, c), dim3(256), 0, st, B, k0, nbw);
             }
             T.end(id, st);
         }
     }
-    id = T.begin(KC_BACKSOLVE, (double)cnt * n * n * 0.5, st);
+    double wb = 0.0;
+    for (int q = 0; q < cnt; q++) wb += 0.5 * (double)orders[q] * orders[q];
+    id = T.begin(KC_BACKSOLVE, wb, st);
     hipLaunchKernelGGL(k_s2_backsolve<L>, dim3(cnt), dim3(256), 0, st, B);
     T.end(id, st);
     if (!B.timer) dummy.collect();
@@ -1615,8 +1641,8 @@ template int stage2_init<2>(PairDesc *, RqiProb *, int, hipStream_t);
 template int stage2_init<4>(PairDesc *, RqiProb *, int, hipStream_t);
 template int stage2_rq<2>(const Stage2Batch &, hipStream_t);
 template int stage2_rq<4>(const Stage2Batch &, hipStream_t);
-template int stage2_solve<2>(const Stage2Batch &, hipStream_t);
-template int stage2_solve<4>(const Stage2Batch &, hipStream_t);
+template int stage2_solve<2>(const Stage2Batch &, const int *, hipStream_t);
+template int stage2_solve<4>(const Stage2Batch &, const int *, hipStream_t);
 template int stage2_output<2>(PairDesc *, RqiProb *, const int *, int, hipStream_t);
 template int stage2_output<4>(PairDesc *, RqiProb *, const int *, int, hipStream_t);
 
