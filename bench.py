@@ -685,7 +685,17 @@ def main():
         log("cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline()
     ctx.close()
-    print(json.dumps(out), flush=True)
+    print(json.dumps(out, default=_plain), flush=True)
+
+
+def _plain(x):
+    """numpy scalars and arrays as plain JSON values"""
+    import numpy as np
+    if isinstance(x, np.generic):
+        return x.item()
+    if isinstance(x, np.ndarray):
+        return x.tolist()
+    raise TypeError(f"not JSON serialisable: {type(x).__name__}")
 
 
 if __name__ == "__main__":
