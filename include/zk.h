@@ -270,6 +270,31 @@ int zk_mps_two_site_dd(zk_ctx *ctx, int chi_l, int chi, int chi_r, const void *c
                        double *const *s_out, int *chi_out, const zk_opts *opts);
 
 /*
+ * zk_heev_dd_noalloc: for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The same decomposition as zk_heev_dd (same arguments, layouts,
+ * options, outputs, ownership and errors; bitwise the same results), but no
+ * device memory is allocated or freed during the call: all of its workspace
+ * comes from one static device array of ZK_NOALLOC_SCRATCH_BYTES per GPU,
+ * which the library holds from its first use on a device until the process
+ * ends, and the context's own workspace is neither used nor grown.  The
+ * caller still passes the inputs and outputs.  The binary64 stage runs on the
+ * context stream only, and kernel-class timing (zk_prof_*) records nothing
+ * during the call.
+ * Limit: ZK_ENOMEM, before any work, when the call needs more than the array
+ * holds (the binary64 stage, inputs and iterates of all `count` matrices at
+ * once plus one shifted-LU slot of the largest order, as zk_workspace_bytes
+ * counts them: one matrix of order up to 649, or e.g. 6 matrices of order
+ * 256, 26 of order 128), and ZK_ENOMEM if the array runs out during the call.
+ * Concurrency: the array is shared by every call on that GPU and keeps the
+ * last call's contents (nothing reads them).  Calls from threads of one
+ * process are serialised per device; calls that overlap on one GPU through
+ * another copy of the library would race.  Synchronous.
+ */
+#define ZK_NOALLOC_SCRATCH_BYTES ((size_t)96 << 20)
+int zk_heev_dd_noalloc(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out *out, const zk_opts *opts);
+
+/*
  * zk_heev_fp64: stage 1 alone (the binary64 eigendecomposition that seeds the
  * Rayleigh quotient iteration).  For each matrix i: w[i] (device, n doubles,
  * ascending) and V[i] (device, n x n complex128 column-major, leading

@@ -62,7 +62,7 @@ KERNEL_CLASSES = ["lu_update", "lu_panel", "lu_trsm", "backsolve", "rq", "gs", "
 EXPORTED = ["zk_prof_enable", "zk_prof_classes", "zk_prof_reset", "zk_prof_read", "zk_opts_default", "zk_ctx_create", "zk_ctx_destroy", "zk_status_str", "zk_ctx_last_error",
             "zk_workspace_bytes", "zk_heev_dd", "zk_heev_qd", "zk_heev_dd_allpairs", "zk_svd_dd", "zk_mps_two_site_dd", "zk_heev_fp64", "zk_rqi_refine",
             "zk_session_create", "zk_session_submit", "zk_session_poll", "zk_session_times", "zk_session_destroy",
-            "zk_ctx_memory", "zk_ctx_last_stats"]
+            "zk_ctx_memory", "zk_ctx_last_stats", "zk_heev_dd_noalloc"]
 
 _lib = None
 
@@ -86,7 +86,7 @@ def load(path: str = LIB_PATH):
     lib.zk_ctx_last_error.restype = ctypes.c_char_p
     lib.zk_workspace_bytes.argtypes = [I, I, I]
     lib.zk_workspace_bytes.restype = ctypes.c_size_t
-    for f in ("zk_heev_dd", "zk_heev_qd", "zk_heev_dd_allpairs"):
+    for f in ("zk_heev_dd", "zk_heev_qd", "zk_heev_dd_allpairs", "zk_heev_dd_noalloc"):
         getattr(lib, f).argtypes = [P, I, ctypes.POINTER(ZkHerm), ctypes.POINTER(ZkEigOut), ctypes.POINTER(ZkOpts)]
     lib.zk_svd_dd.argtypes = [P, I, ctypes.POINTER(ZkMat), ctypes.POINTER(ZkSvdOut), ctypes.POINTER(ZkOpts)]
     P2 = P * 2
@@ -253,11 +253,16 @@ def _info_list(info, k):
             for i in range(k)]
 
 
-def heev(ctx: Context, mats, limbs_out: int = 2, opts: ZkOpts | None = None, stats: dict | None = None):
+def heev(ctx: Context, mats, limbs_out: int = 2, opts: ZkOpts | None = None, stats: dict | None = None,
+         noalloc: bool = False):
     """Eigendecompose a list of matrices (each a tensor or list of limb tensors).
 
+    noalloc=True (double-double only) calls zk_heev_dd_noalloc, whose
+    workspace is the library's static scratch array instead of the context's.
     Returns a list of EigResult (status is shared by the batch call).
     """
+    if noalloc and limbs_out != 2:
+        raise ValueError("the no-allocation entry point gives double-double output only")
     lib = load()
     keep: list = []
     count = len(mats)
@@ -271,7 +276,7 @@ def heev(ctx: Context, mats, limbs_out: int = 2, opts: ZkOpts | None = None, sta
         O[i] = o
         outs.append((w, V, info, H[i].n))
     op = ctypes.byref(opts) if opts is not None else None
-    f = lib.zk_heev_dd if limbs_out == 2 else lib.zk_heev_qd
+    f = (lib.zk_heev_dd_noalloc if noalloc else lib.zk_heev_dd) if limbs_out == 2 else lib.zk_heev_qd
     rc = f(ctx.handle, count, H, O, op)
     if stats is not None:
         stats.update(ctx.last_stats())

@@ -825,11 +825,11 @@ struct ApEngine::Impl {
         for (HostProb *h : live) delete h;
         for (Chunk &c : chunks)
             if (c.p) {
-                hipFree(c.p);
+                ctx->dev_free(c.p);
                 ctx->extra -= c.bytes;
             }
         if (meta) {
-            hipFree(meta);
+            ctx->dev_free(meta);
             ctx->extra -= meta_bytes;
         }
     }
@@ -843,17 +843,13 @@ struct ApEngine::Impl {
         if (b <= meta_bytes) return ZK_OK;
         if (meta) {
             hipStreamSynchronize(ctx->stream);
-            hipFree(meta);
+            ctx->dev_free(meta);
             ctx->extra -= meta_bytes;
             meta = nullptr;
             meta_bytes = 0;
         }
         if (!room(b)) return ctx->fail(ZK_ENOMEM, "all-pairs descriptors need %zu more bytes", b);
-        if (hipMalloc(&meta, b) != hipSuccess) {
-            hipGetLastError();
-            meta = nullptr;
-            return ctx->fail(ZK_ENOMEM, "hipMalloc of %zu bytes failed", b);
-        }
+        if (ctx->dev_alloc(&meta, b) != ZK_OK) return ZK_ENOMEM;
         meta_bytes = b;
         ctx->extra += b;
         ctx->note_held();
@@ -864,7 +860,7 @@ struct ApEngine::Impl {
         Chunk &c = chunks[h->chunk];
         if (--c.left == 0 && c.p) {
             hipStreamSynchronize(ctx->stream);
-            hipFree(c.p);
+            ctx->dev_free(c.p);
             ctx->extra -= c.bytes;
             c.p = nullptr;
             c.bytes = 0;
@@ -894,10 +890,7 @@ int ApEngine::Impl::add(const std::vector<ApReq> &reqs)
     }
     if (!room(total)) return ctx->fail(ZK_ENOMEM, "all-pairs refinement needs %zu more bytes", total);
     Chunk ch;
-    if (hipMalloc(&ch.p, total) != hipSuccess) {
-        hipGetLastError();
-        return ctx->fail(ZK_ENOMEM, "hipMalloc of %zu bytes failed", total);
-    }
+    if (ctx->dev_alloc(&ch.p, total) != ZK_OK) return ZK_ENOMEM;
     ch.bytes = total;
     ch.left = (int)reqs.size();
     ctx->extra += total;

@@ -102,7 +102,7 @@ bool zk_ctx::make_room(size_t bytes)
     if (held() + bytes <= budget) return true;
     if (s2lu.p) {
         hipStreamSynchronize(stream);
-        s2lu.release();
+        drop(s2lu);
     }
     return held() + bytes <= budget;
 }
@@ -113,15 +113,46 @@ int zk_ctx::ensure(DevBuf &b, size_t bytes)
     if (bytes <= b.bytes) return ZK_OK;
     if (&b != &s2lu && held() - b.bytes + bytes > budget) make_room(bytes - b.bytes);
     if (held() - b.bytes + bytes > budget) return fail(ZK_ENOMEM, "workspace of %zu bytes exceeds the budget", bytes);
-    b.release();
-    if (hipMalloc(&b.p, bytes) != hipSuccess) {
-        b.p = nullptr;
-        hipGetLastError();
-        return fail(ZK_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
-    }
+    drop(b);
+    int rc = dev_alloc(&b.p, bytes);
+    if (rc != ZK_OK) return rc;
     b.bytes = bytes;
     note_held();
     return ZK_OK;
+}
+
+int zk_ctx::dev_alloc(void **p, size_t bytes)
+{
+    *p = nullptr;
+    if (arena) {
+        *p = arena->take(bytes);
+        if (!*p)
+            return fail(ZK_ENOMEM, "scratch array exhausted: %zu bytes wanted, %zu of %zu in use", bytes, arena->in_use,
+                        arena->size);
+        return ZK_OK;
+    }
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        *p = nullptr;
+        hipGetLastError();
+        return fail(ZK_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
+    }
+    return ZK_OK;
+}
+
+void zk_ctx::dev_free(void *p)
+{
+    if (!p) return;
+    if (arena && arena->owns(p))
+        arena->give(p);
+    else
+        hipFree(p);
+}
+
+void zk_ctx::drop(DevBuf &b)
+{
+    dev_free(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
 }
 
 int zk_ctx::fail(int status, const char *fmt, ...)
@@ -356,7 +387,9 @@ int run_stage1(zk_ctx *ctx, int count, const zk_herm *A, const std::vector<doubl
     for (auto &kv : groups) total += stage1_batch_bytes(kv.first.first, (int)kv.second.size());
     if (total > ctx->s1.bytes) ctx->make_room(total - ctx->s1.bytes);
     const size_t avail = ctx->budget > ctx->held() - ctx->s1.bytes ? ctx->budget - (ctx->held() - ctx->s1.bytes) : 0;
-    if (groups.size() > 1 && total <= avail) {
+    // (inside the no-allocation entry point the side streams and events are
+    // not created: every batch runs on the context stream)
+    if (groups.size() > 1 && total <= avail && !ctx->arena) {
         if ((rc = ctx->ensure(ctx->s1, total)) != ZK_OK) return rc;
         for (int k = 0; k < 3; k++)
             if (!ctx->side[k]) HIPCHK(hipStreamCreateWithFlags(&ctx->side[k], hipStreamNonBlocking));
@@ -569,10 +602,7 @@ extern "C" int zk_svd_dd(zk_ctx *ctx, int count, const zk_mat *A, zk_svd_out *ou
     }
     if (!ctx->make_room(off[count])) return ctx->fail(ZK_ENOMEM, "the dilations need %zu bytes", off[count]);
     void *buf = nullptr;
-    if (hipMalloc(&buf, off[count]) != hipSuccess) {
-        hipGetLastError();
-        return ctx->fail(ZK_ENOMEM, "hipMalloc of %zu bytes failed", off[count]);
-    }
+    if (ctx->dev_alloc(&buf, off[count]) != ZK_OK) return ZK_ENOMEM;
     ctx->extra += off[count];
     ctx->note_held();
     std::vector<SvdDesc> D(count);
@@ -662,7 +692,7 @@ extern "C" int zk_svd_dd(zk_ctx *ctx, int count, const zk_mat *A, zk_svd_out *ou
         if (rc >= 0) rc = all_ok ? ZK_OK : ZK_ENOCONV;
     }
     hipStreamSynchronize(st);
-    hipFree(buf);
+    ctx->dev_free(buf);
     ctx->extra -= off[count];
     return rc;
 }
@@ -691,10 +721,7 @@ extern "C" int zk_mps_two_site_dd(zk_ctx *ctx, int chi_l, int chi, int chi_r, co
     const size_t bytes = 2 * (bT + bU + bV + bS);
     if (!ctx->make_room(bytes)) return ctx->fail(ZK_ENOMEM, "the two-site update needs %zu bytes", bytes);
     void *buf = nullptr;
-    if (hipMalloc(&buf, bytes) != hipSuccess) {
-        hipGetLastError();
-        return ctx->fail(ZK_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
-    }
+    if (ctx->dev_alloc(&buf, bytes) != ZK_OK) return ZK_ENOMEM;
     ctx->extra += bytes;
     ctx->note_held();
     char *b = (char *)buf;
@@ -767,7 +794,7 @@ extern "C" int zk_mps_two_site_dd(zk_ctx *ctx, int chi_l, int chi, int chi_r, co
         }
     }
     hipStreamSynchronize(st);
-    hipFree(buf);
+    ctx->dev_free(buf);
     ctx->extra -= bytes;
     return rc;
 }

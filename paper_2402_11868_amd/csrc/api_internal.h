@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdarg>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -18,6 +19,65 @@ struct DevBuf {
         if (p) hipFree(p);
         p = nullptr;
         bytes = 0;
+    }
+};
+
+// First-fit sub-allocator over one device region that the library does not
+// own (the static scratch array of the no-allocation entry point): blocks are
+// 256-byte aligned, freed blocks merge with free neighbours.  Host-side
+// bookkeeping only; it never calls the HIP allocator.
+struct Arena {
+    char *base = nullptr;
+    size_t size = 0;
+    std::map<size_t, size_t> free_;   // offset -> length of free runs
+    std::map<size_t, size_t> used_;   // offset -> length of taken blocks
+    size_t in_use = 0, peak = 0;
+    void reset(char *b, size_t s)
+    {
+        base = b;
+        size = s;
+        free_.clear();
+        used_.clear();
+        if (s) free_[0] = s;
+        in_use = peak = 0;
+    }
+    void *take(size_t bytes)
+    {
+        bytes = (bytes + 255) & ~(size_t)255;
+        if (bytes == 0) bytes = 256;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            const size_t off = it->first, len = it->second;
+            free_.erase(it);
+            if (len > bytes) free_[off + bytes] = len - bytes;
+            used_[off] = bytes;
+            in_use += bytes;
+            if (in_use > peak) peak = in_use;
+            return base + off;
+        }
+        return nullptr;
+    }
+    bool owns(const void *p) const { return base && (const char *)p >= base && (const char *)p < base + size; }
+    void give(void *p)
+    {
+        auto u = used_.find((size_t)((char *)p - base));
+        if (u == used_.end()) return;
+        size_t off = u->first, len = u->second;
+        used_.erase(u);
+        in_use -= len;
+        auto nx = free_.lower_bound(off);
+        if (nx != free_.end() && nx->first == off + len) {
+            len += nx->second;
+            nx = free_.erase(nx);
+        }
+        if (nx != free_.begin()) {
+            auto pv = std::prev(nx);
+            if (pv->first + pv->second == off) {
+                pv->second += len;
+                return;
+            }
+        }
+        free_[off] = len;
     }
 };
 
@@ -58,6 +118,12 @@ struct zk_ctx {
         if (h > high_water) high_water = h;
     }
     int ensure(DevBuf &b, size_t bytes);
+    // Device workspace: from the HIP allocator, or, while `arena` is set
+    // (inside the no-allocation entry point), from the arena alone.
+    Arena *arena = nullptr;
+    int dev_alloc(void **p, size_t bytes);
+    void dev_free(void *p);
+    void drop(DevBuf &b);
     // Room for `bytes` more under the budget: the shifted-LU slots are
     // scratch between iteration rounds (every engine lays them out again when
     // the buffer changed), so they are given back when the budget is short.

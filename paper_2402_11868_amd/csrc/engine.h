@@ -76,7 +76,7 @@ class Stage2Engine {
     {
         for (S2Prob *p : live) release(p);
         if (gsbuf) {
-            hipFree(gsbuf);
+            ctx->dev_free(gsbuf);
             ctx->extra -= gsbytes;
         }
     }
@@ -109,11 +109,7 @@ class Stage2Engine {
             const int n = P.n, kp = p->npairs;
             p->vecbytes = s2_align(8 * 2 * (size_t)L * n * n) + s2_align(8 * (size_t)L * n);
             if (!ctx->make_room(p->vecbytes)) return ctx->fail(ZK_ENOMEM, "iterate storage exceeds the budget");
-            if (hipMalloc(&p->vecbuf, p->vecbytes) != hipSuccess) {
-                p->vecbuf = nullptr;
-                hipGetLastError();
-                return ctx->fail(ZK_ENOMEM, "hipMalloc of %zu bytes failed", p->vecbytes);
-            }
+            if (ctx->dev_alloc(&p->vecbuf, p->vecbytes) != ZK_OK) return ZK_ENOMEM;
             ctx->extra += p->vecbytes;
             ctx->note_held();
             P.vec = (double *)p->vecbuf;
@@ -249,18 +245,14 @@ class Stage2Engine {
     {
         if (bytes <= gsbytes) return ZK_OK;
         if (gsbuf) {
-            hipFree(gsbuf);
+            ctx->dev_free(gsbuf);
             ctx->extra -= gsbytes;
             gsbuf = nullptr;
             gsbytes = 0;
         }
         bytes = std::max(bytes, (size_t)1 << 20);
         if (!ctx->make_room(bytes)) return ctx->fail(ZK_ENOMEM, "Gram-Schmidt plan exceeds the budget");
-        if (hipMalloc(&gsbuf, bytes) != hipSuccess) {
-            gsbuf = nullptr;
-            hipGetLastError();
-            return ctx->fail(ZK_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
-        }
+        if (ctx->dev_alloc(&gsbuf, bytes) != ZK_OK) return ZK_ENOMEM;
         gsbytes = bytes;
         ctx->extra += bytes;
         ctx->note_held();
@@ -270,7 +262,7 @@ class Stage2Engine {
     void release(S2Prob *p)
     {
         if (p->vecbuf) {
-            hipFree(p->vecbuf);
+            ctx->dev_free(p->vecbuf);
             ctx->extra -= p->vecbytes;
             p->vecbuf = nullptr;
         }
@@ -312,6 +304,12 @@ class Stage2Engine {
         int s = (int)std::min<size_t>((size_t)want, avail / per);
         if (s < 1) return ctx->fail(ZK_ENOMEM, "one shifted LU of order %d needs %zu bytes", nn, per);
         int rc = ctx->ensure(ctx->s2lu, (size_t)s * per);
+        // a fixed scratch region may be too fragmented for the count the
+        // budget allows: fewer slots then
+        while (rc != ZK_OK && ctx->arena && s > 1) {
+            s /= 2;
+            rc = ctx->ensure(ctx->s2lu, (size_t)s * per);
+        }
         if (rc != ZK_OK) return rc;
         S = s;
         slot_n = nn;
@@ -743,10 +741,7 @@ class Stage2Engine {
         }
         if (!ctx->make_room(bytes)) return ctx->fail(ZK_ENOMEM, "projected Rayleigh-Ritz exceeds the budget");
         void *buf = nullptr;
-        if (hipMalloc(&buf, bytes) != hipSuccess) {
-            hipGetLastError();
-            return ctx->fail(ZK_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
-        }
+        if (ctx->dev_alloc(&buf, bytes) != ZK_OK) return ZK_ENOMEM;
         ctx->extra += bytes;
         ctx->note_held();
         std::vector<PrrDesc> hd(nd);
@@ -783,7 +778,7 @@ class Stage2Engine {
         int rc = ZK_OK;
         auto cleanup = [&]() {
             hipStreamSynchronize(st);
-            hipFree(buf);
+            ctx->dev_free(buf);
             ctx->extra -= bytes;
         };
         if (hipMemcpyAsync(d_desc, hd.data(), sizeof(PrrDesc) * nd, hipMemcpyHostToDevice, st) != hipSuccess ||

@@ -45,6 +45,7 @@ def test_static_entry_points_without_device():
     # NULL handles are rejected before any device work
     assert lib.zk_heev_dd(None, 1, None, None, None) == -1
     assert lib.zk_heev_dd_allpairs(None, 1, None, None, None) == -1
+    assert lib.zk_heev_dd_noalloc(None, 1, None, None, None) == -1
     assert lib.zk_svd_dd(None, 1, None, None, None) == -1
     assert lib.zk_mps_two_site_dd(None, 1, 1, 1, None, None, None, 1, ctypes.c_double(0.0), None, None, None,
                                   None, None) == -1
