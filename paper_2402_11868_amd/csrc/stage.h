@@ -105,6 +105,13 @@ struct Stage1Batch {
 size_t stage1_gemm_desc_count(int n, int np);
 void stage1_fill_gemm_descs(const ProbDesc *host_probs, int np, GemmDesc *out);
 int stage1_run(const Stage1Batch &B, hipStream_t st);
+// the three parts of stage1_run: ingest (and the order-1 case), the
+// per-column tridiagonalisation launches, the tridiagonal solver and
+// back-transformation
+int stage1_ingest(const Stage1Batch &B, hipStream_t st);
+int stage1_trd(const Stage1Batch &B, hipStream_t st);
+int stage1_solve(const Stage1Batch &B, hipStream_t st);
+
 
 // ------------------------------------------------------------------- SVD
 // One singular value decomposition through the Hermitian dilation (svd.hip).

@@ -18,6 +18,8 @@
 //              three FP64-MFMA GEMMs per panel
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "common.h"
 #include "stage.h"
 
@@ -456,12 +458,10 @@ __device__ __forceinline__ double2 opB_ld(const double2 *B, int ldb, int op, int
 
 constexpr int kGemmKc = 8;   // k-steps of 4 whose operands are loaded together
 
-__global__ void __launch_bounds__(256) k_zgemm(const GemmDesc *descs, int M, int N, int K, int opA, int opB,
-                                               double2 alpha, double2 beta, int lower)
+// One 32 x 32 tile (tm, tn) of C by the four waves of a work-group.
+__device__ __forceinline__ void zgemm_tile(const GemmDesc &G, int M, int N, int K, int opA, int opB, double2 alpha,
+                                           double2 beta, int lower, int tm, int tn)
 {
-    const GemmDesc &G = descs[blockIdx.y];
-    const int tilesM = (M + 31) / 32;
-    const int tm = blockIdx.x % tilesM, tn = blockIdx.x / tilesM;
     const int row0 = tm * 32, col0 = tn * 32;
     if (lower && row0 + 31 < col0) return;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -469,7 +469,10 @@ __global__ void __launch_bounds__(256) k_zgemm(const GemmDesc *descs, int M, int
     if (lower && wr + 15 < wc) return;
     const double2 *A = reinterpret_cast<const double2 *>(G.A);
     const double2 *B = reinterpret_cast<const double2 *>(G.B);
-    f64x4 cre = f64x4{0.0, 0.0, 0.0, 0.0}, cim = f64x4{0.0, 0.0, 0.0, 0.0};
+    // four independent accumulator chains (the real and imaginary parts of
+    // the two real products each), so that consecutive MFMAs do not wait on
+    // each other's results
+    f64x4 crr = f64x4{0.0, 0.0, 0.0, 0.0}, cii = crr, cri = crr, cir = crr;
     const int li = lane & 15, lk = lane >> 4;
     const int lda = G.lda, ldb = G.ldb;
     for (int k0 = 0; k0 < K; k0 += 4 * kGemmKc) {
@@ -493,10 +496,10 @@ __global__ void __launch_bounds__(256) k_zgemm(const GemmDesc *descs, int M, int
         }
 #pragma unroll
         for (int s = 0; s < kGemmKc; s++) {
-            cre = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[s].x, yv[s].x, cre, 0, 0, 0);
-            cre = __builtin_amdgcn_mfma_f64_16x16x4f64(-xv[s].y, yv[s].y, cre, 0, 0, 0);
-            cim = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[s].x, yv[s].y, cim, 0, 0, 0);
-            cim = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[s].y, yv[s].x, cim, 0, 0, 0);
+            crr = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[s].x, yv[s].x, crr, 0, 0, 0);
+            cii = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[s].y, yv[s].y, cii, 0, 0, 0);
+            cri = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[s].x, yv[s].y, cri, 0, 0, 0);
+            cir = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[s].y, yv[s].x, cir, 0, 0, 0);
         }
     }
     double2 *C = reinterpret_cast<double2 *>(G.C);
@@ -505,10 +508,17 @@ __global__ void __launch_bounds__(256) k_zgemm(const GemmDesc *descs, int M, int
     for (int r = 0; r < 4; r++) {
         const int j = wc + 4 * r + lk;
         if (j >= N || (lower && i < j)) continue;
-        double2 out = cmul(alpha, make_double2(cre[r], cim[r]));
+        double2 out = cmul(alpha, make_double2(crr[r] - cii[r], cri[r] + cir[r]));
         if (beta.x != 0.0 || beta.y != 0.0) out = cadd(out, cmul(beta, C[(size_t)j * G.ldc + i]));
         C[(size_t)j * G.ldc + i] = out;
     }
+}
+
+__global__ void __launch_bounds__(256) k_zgemm(const GemmDesc *descs, int M, int N, int K, int opA, int opB,
+                                               double2 alpha, double2 beta, int lower)
+{
+    const int tilesM = (M + 31) / 32;
+    zgemm_tile(descs[blockIdx.y], M, N, K, opA, opB, alpha, beta, lower, blockIdx.x % tilesM, blockIdx.x / tilesM);
 }
 
 // C = op(A) op(B) for `count` descriptors of equal shape (M x N, inner K).
@@ -971,19 +981,27 @@ void stage1_fill_gemm_descs(const ProbDesc *hp, int np, GemmDesc *out)
     }
 }
 
-int stage1_run(const Stage1Batch &B, hipStream_t st)
+int stage1_ingest(const Stage1Batch &B, hipStream_t st)
 {
-    // the binary64 trailing updates and back-transform, or their FP32-MFMA variant
-    auto gemm = B.fp32 ? k_cgemm32 : k_zgemm;
     const int n = B.n, np = B.nprob;
     ProbDesc *pd = B.dev_probs;
-    const GemmDesc *gd = B.dev_gemm;
     if (n < 1 || np < 1) return 0;
     hipLaunchKernelGGL(k_ingest, dim3(n, np), dim3(256), 0, st, pd, B.fp32);
     if (n == 1) {
         hipLaunchKernelGGL(k_n1, dim3(cdiv(np, 64)), dim3(64), 0, st, pd, np);
         return hipGetLastError() == hipSuccess ? 0 : -1;
     }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// the per-column launches of the tridiagonalisation (n >= 2)
+int stage1_trd(const Stage1Batch &B, hipStream_t st)
+{
+    auto gemm = B.fp32 ? k_cgemm32 : k_zgemm;
+    const int n = B.n, np = B.nprob;
+    ProbDesc *pd = B.dev_probs;
+    const GemmDesc *gd = B.dev_gemm;
+    if (n < 2 || np < 1) return 0;
     // ---- tridiagonalisation
     // large matrices: the per-column kernels spread each column over chunks of
     // 64 rows; smaller ones: one chunk per matrix (batches of them fill the
@@ -1023,6 +1041,18 @@ int stage1_run(const Stage1Batch &B, hipStream_t st)
         }
     }
     hipLaunchKernelGGL(k_last_diag, dim3(cdiv(np, 64)), dim3(64), 0, st, pd, np);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// tridiagonal eigen-solver and back-transformation (n >= 2, after the tridiagonalisation)
+int stage1_solve(const Stage1Batch &B, hipStream_t st)
+{
+    auto gemm = B.fp32 ? k_cgemm32 : k_zgemm;
+    const int n = B.n, np = B.nprob;
+    ProbDesc *pd = B.dev_probs;
+    const GemmDesc *gd = B.dev_gemm;
+    if (n < 2 || np < 1) return 0;
+    const int npan = (n - 1 + kNB - 1) / kNB;
     // ---- tridiagonal eigen-solver
     const int idt = B.timer ? B.timer->begin(KC_TRIDIAG, 0.0, st) : -1;
     hipLaunchKernelGGL(k_bisect, dim3(cdiv(n, 4), np), dim3(256), 0, st, pd);
@@ -1051,6 +1081,14 @@ int stage1_run(const Stage1Batch &B, hipStream_t st)
     }
     if (B.timer) B.timer->end(idb, st);
     return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int stage1_run(const Stage1Batch &B, hipStream_t st)
+{
+    if (stage1_ingest(B, st)) return -1;
+    if (B.n < 2) return 0;
+    if (stage1_trd(B, st)) return -1;
+    return stage1_solve(B, st);
 }
 
 }  // namespace zk

@@ -63,6 +63,25 @@ def test_stage1_batch_of_equal_order(zk):
         assert np.abs(w.cpu().numpy() - np.linalg.eigvalsh(A)).max() <= 1e-12 * np.abs(A).sum()
 
 
+def test_stage1_mixed_orders_one_call(zk):
+    """Matrices of many orders in one call (orders around the 64-row chunk
+    and 32-column panel edges; batches of different orders run concurrently
+    on several streams), each checked against LAPACK."""
+    Z, ctx, torch = zk
+    orders = [2, 5, 31, 33, 64, 65, 97, 130, 200, 257]
+    mats = [W.random_elements(n, 300 + n) for n in orders]
+    res = Z.heev_fp64(ctx, [_dev(torch, [A])[0] for A in mats])
+    u = 2.0 ** -53
+    for n, A, (w, V) in zip(orders, mats, res):
+        w, V = w.cpu().numpy(), V.cpu().numpy()
+        ref = np.linalg.eigvalsh(A)
+        nrm = np.abs(ref).max()
+        log(f"mixed orders: n={n} |w - lapack| {np.abs(w - ref).max() / nrm:.2e}")
+        assert np.abs(w - ref).max() <= 16 * n * u * nrm
+        assert np.abs(A @ V - V * w).max() <= 64 * n * u * nrm
+        assert np.abs(V.conj().T @ V - np.eye(n)).max() <= 1e-8
+
+
 # ---------------------------------------------------------- dd, oracle ---
 def test_c1_dd_against_golden(zk):
     """64x64 workload (designed spectrum, one eigenvalue 2^-20): all pairs vs stored oracle values."""
