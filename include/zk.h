@@ -190,6 +190,49 @@ int zk_heev_qd(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out *out, const 
  */
 int zk_heev_dd_allpairs(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out *out, const zk_opts *opts);
 
+/* Output of zk_heev_mp: `limbs` binary64 limbs per value (4, 8 or 16).
+ * w (device): limbs x n doubles, limb l of eigenvalue k at w[l * n + k].
+ * v (device): `limbs` planes of complex128, plane l starting at element
+ * l * ldv * n; each plane n x n column-major with leading dimension ldv
+ * (column k = eigenvector k); NULL when opts->want_vectors == 0.
+ * info: HOST array of n entries, or NULL. */
+typedef struct {
+    int n;
+    int ldv;
+    int limbs;
+    double *w;
+    void *v;
+    zk_pair_info *info;
+} zk_eig_out_mp;
+
+/*
+ * zk_heev_mp: eigendecomposition beyond double-double: quad-double (limbs 4,
+ * about 212 bits), 8 limbs (about 424 bits) or 16 limbs (about 848 bits;
+ * the paper's multiple-precision diagonalisations run at up to 768 bits,
+ * Sec. 2.1, Fig. 1).  Stage 1 in binary64, the all-pairs refinement of
+ * zk_heev_dd_allpairs to double-double, then whole-basis polishing in L
+ * limbs: residual matrix and Gram matrix with exact products and L-level
+ * cascaded sums, the first-order correction of every pair from them in
+ * binary64 (pairs whose correction would exceed 1e-4 of their gap, or whose
+ * gap is zero, are only re-orthogonalised; runs of such pairs with distinct
+ * eigenvalues are rotated by the eigenvectors of their projected matrix),
+ * about sixteen more binary digits per iteration.  The iteration scales H by
+ * a power of two internally; the outputs are binary64 limb expansions, so an
+ * eigenvalue near 2^e resolves 2^(e - 1074) at best (at ||H||_2 = 2^e the
+ * 16-limb default tolerance needs e above about -270).
+ * All out[i].limbs must be equal.  opts: tol (default 1e-60,
+ * 1e-120, 1e-240 for 4, 8, 16 limbs; relative to ||H||_2, for every residual;
+ * the departure from orthonormality is brought within tol too), max_iter
+ * (polishing iterations, default 8 + 3 limbs), want_vectors.  info[k].iters =
+ * polishing iterations of the matrix, info[k].resid = residual before the
+ * last Rayleigh-quotient update (an upper bound).  Eigenvalues ascending.
+ * Synchronous.  ZK_ENOCONV if max_iter iterations leave a residual or the
+ * departure from orthonormality above tol (the outputs are still written).
+ * Errors: as zk_heev_dd; ZK_EINVAL for limbs not in {4, 8, 16} or unequal
+ * across the call, ldv < n, or NULL w / v.
+ */
+int zk_heev_mp(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out_mp *out, const zk_opts *opts);
+
 /* A general complex matrix: plane[0..limbs-1] are device pointers to m x n
  * complex128 column-major arrays with leading dimension lda (elements). */
 typedef struct {
@@ -293,6 +336,48 @@ int zk_mps_two_site_dd(zk_ctx *ctx, int chi_l, int chi, int chi_r, const void *c
  */
 #define ZK_NOALLOC_SCRATCH_BYTES ((size_t)96 << 20)
 int zk_heev_dd_noalloc(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out *out, const zk_opts *opts);
+
+/*
+ * MPS simulation.  A chain of nq qubits as a matrix product state in
+ * double-double (sites in right-canonical form with the Schmidt values of
+ * every bond, Hastings' form of the Vidal decomposition), the paper's MPS
+ * method (Sec. 1) whose cost is the diagonalisation of the bond matrices
+ * (Sec. 2.1).  A two-qubit gate G on qubits (q, q+1) forms
+ * theta = G (B_q B_{q+1}) and the Hermitian PSD bond matrix
+ * rho = theta^H diag(lambda_{q-1}^2) theta of order 2 chi_{q+1}; rho is
+ * eigendecomposed in double-double through a serving session (the gates of
+ * one call share its launches); the chi' largest eigenvalues w above
+ * cutoff^2 w_max (at most chi_max) are kept: B_{q+1} = V^H, B_q = theta V,
+ * lambda_q = sqrt(w).  No Schmidt value is ever inverted.
+ * Gates are HOST arrays of two limb planes (hi, lo) of complex128,
+ * column-major: 2 x 2 (8 doubles per plane) for zk_mps_apply1, 4 x 4 with
+ * row and column index 2 s_q + s_{q+1} (32 doubles per plane) for
+ * zk_mps_apply2.  The MPS holds its own session on a second context of the
+ * same device; the caller's context runs the other kernels and holds the
+ * sites (budget-counted).  All calls are synchronous.
+ */
+typedef struct zk_mps zk_mps;
+
+/* |0...0> on nq qubits (2 <= nq <= 4096); chi_max <= 256, cutoff >= 0.
+ * ZK_EINVAL, ZK_ENOMEM, ZK_EDEVICE. */
+int zk_mps_create(zk_ctx *ctx, int nq, int chi_max, double cutoff, zk_mps **out);
+int zk_mps_destroy(zk_mps *m);
+/* One-qubit gate on qubit q. */
+int zk_mps_apply1(zk_mps *m, int q, const double *gate);
+/* `count` two-qubit gates, gate k on (q[k], q[k] + 1); the pairs must be
+ * disjoint (ZK_EINVAL otherwise).  ZK_ENOCONV if a bond matrix missed the
+ * double-double tolerance (the state is updated all the same). */
+int zk_mps_apply2(zk_mps *m, int count, const int *q, const double *const *gates);
+/* Bond b (between qubits b-1 and b; 0 and nq are the ends): *chi = its
+ * dimension; eig (host, 2 * max doubles, may be NULL) receives the limbs of
+ * the first min(max, chi) squared Schmidt values, descending: limb 0 at
+ * eig[j], limb 1 at eig[max + j]. */
+int zk_mps_bond(zk_mps *m, int b, int max, double *eig, int *chi);
+/* Site q as two limb planes (host, capacity doubles in total) of the
+ * chi_l x (2 chi_r) complex128 matrix B_q[l, s, r] at column s chi_r + r. */
+int zk_mps_site(zk_mps *m, int q, int *chi_l, int *chi_r, double *out, size_t capacity);
+/* Every bond matrix diagonalised so far: submit-to-done seconds and order. */
+int zk_mps_latencies(zk_mps *m, int max, double *seconds, int *orders, int *count);
 
 /*
  * zk_heev_fp64: stage 1 alone (the binary64 eigendecomposition that seeds the

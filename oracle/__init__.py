@@ -6,8 +6,9 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 
 Contents
 --------
-* ``heev`` -- 256-bit MPFR cyclic-Jacobi eigen-solver (``jacobi.c``) on the
-  exact limb sum of the input: the plain definition H = V diag(lam) V^H that
+* ``heev`` -- MPFR cyclic-Jacobi eigen-solver (``jacobi.c``; 256 bits by
+  default, 1024 and more for precisions beyond quad-double) on the exact limb
+  sum of the input: the plain definition H = V diag(lam) V^H that
   the paper's FP64-eig + Rayleigh-quotient-iteration method converges to
   (Sec. 2, ZKCM_CUS paragraph).
 * ``residuals`` / ``gram`` -- MPFR evaluations of ||H v - lam v|| / ||v|| and
@@ -64,6 +65,8 @@ def _load():
         I = ctypes.c_int
         lib.or_heev.restype = I
         lib.or_heev.argtypes = [I, I, P, I, I, I, I, P, P, P]
+        lib.or_heev_limbs.restype = I
+        lib.or_heev_limbs.argtypes = [I, I, P, I, I, I, I, I, P, P, P]
         lib.or_residuals.restype = I
         lib.or_residuals.argtypes = [I, I, P, I, I, I, P, I, I, P, I, I, P, P]
         lib.or_gram.restype = I
@@ -98,8 +101,8 @@ def _threads(nthreads):
 
 class HeevResult:
     def __init__(self, w_limbs, v_limbs, info):
-        self.w_limbs = w_limbs          # (4, n) limbs of the ascending eigenvalues
-        self.v_limbs = v_limbs          # (4, n, n) limbs, column k = eigenvector k, or None
+        self.w_limbs = w_limbs          # (limbs, n) limbs of the ascending eigenvalues
+        self.v_limbs = v_limbs          # (limbs, n, n) limbs, column k = eigenvector k, or None
         self.sweeps = int(info[0])
         self.rotations = int(info[1])
         self.off_rel = float(info[2])
@@ -113,15 +116,18 @@ class HeevResult:
         return None if self.v_limbs is None else self.v_limbs[0]
 
 
-def heev(planes, want_vectors: bool = True, prec: int = DEFAULT_PREC, nthreads=None) -> HeevResult:
-    """Eigen-decomposition of sum(planes) (lower triangles read) at `prec` bits."""
+def heev(planes, want_vectors: bool = True, prec: int = DEFAULT_PREC, nthreads=None, limbs: int = 4) -> HeevResult:
+    """Eigen-decomposition of sum(planes) (lower triangles read) at `prec` bits;
+    results rounded to `limbs` binary64 limbs per value (4 by default, up to 16
+    for precisions beyond quad-double; prec must cover 53 * limbs bits)."""
     buf, n = _planes_colmajor(planes)
     L = buf.shape[0]
-    w = np.zeros((4, n), dtype=np.float64)
-    v = np.zeros((4, n, n), dtype=np.complex128) if want_vectors else None
+    w = np.zeros((limbs, n), dtype=np.float64)
+    v = np.zeros((limbs, n, n), dtype=np.complex128) if want_vectors else None
     info = np.zeros(3, dtype=np.float64)
-    rc = _load().or_heev(n, L, buf.ctypes.data, n, int(prec), int(bool(want_vectors)), _threads(nthreads),
-                         w.ctypes.data, v.ctypes.data if v is not None else None, info.ctypes.data)
+    rc = _load().or_heev_limbs(n, L, buf.ctypes.data, n, int(prec), int(bool(want_vectors)), _threads(nthreads),
+                               int(limbs), w.ctypes.data, v.ctypes.data if v is not None else None,
+                               info.ctypes.data)
     if rc != 0:
         raise RuntimeError(f"oracle or_heev failed: {rc}")
     if v is not None:

@@ -253,10 +253,10 @@ static int cmp_diag(const void *x, const void *y)
  *   info[0] = sweeps, info[1] = rotations applied (double), info[2] = off(A)/||A||_F.
  * Returns 0, -1 (bad args), -2 (alloc), -3 (no convergence in 40 sweeps).
  */
-int or_heev(int n, int L, const double *planes, int lda, int prec, int want_vectors, int nthreads,
-            double *w_out, double *v_out, double *info)
+static int heev_impl(int n, int L, const double *planes, int lda, int prec, int want_vectors, int nthreads,
+                     int nlimbs, double *w_out, double *v_out, double *info)
 {
-    if (n < 1 || L < 1 || L > 8 || lda < n || prec < 64) return -1;
+    if (n < 1 || L < 1 || L > 16 || lda < n || prec < 64 || nlimbs < 1 || nlimbs > 16) return -1;
     if (nthreads > 0) omp_set_num_threads(nthreads);
     const int m = n + (n & 1);   /* pad to even with a dummy index n (never rotated) */
     cmp_t *A = c_alloc((size_t)n * n, prec);
@@ -357,7 +357,7 @@ int or_heev(int n, int L, const double *planes, int lda, int prec, int want_vect
     qsort(keys, n, sizeof(sortkey_t), cmp_diag);
     mpfr_t tmp;
     mpfr_init2(tmp, prec);
-    for (int k = 0; k < n; k++) split_limbs(A[(size_t)keys[k].idx * n + keys[k].idx].re, 4, w_out + k, n, tmp);
+    for (int k = 0; k < n; k++) split_limbs(A[(size_t)keys[k].idx * n + keys[k].idx].re, nlimbs, w_out + k, n, tmp);
     if (V && v_out) {
         const size_t ps = (size_t)n * n;
         #pragma omp parallel
@@ -369,8 +369,8 @@ int or_heev(int n, int L, const double *planes, int lda, int prec, int want_vect
                 for (int i = 0; i < n; i++) {
                     cmp_t *z = &V[(size_t)i * n + keys[k].idx];
                     size_t off = 2 * ((size_t)k * n + i);
-                    split_limbs(z->re, 4, v_out + off, 2 * ps, t2);
-                    split_limbs(z->im, 4, v_out + off + 1, 2 * ps, t2);
+                    split_limbs(z->re, nlimbs, v_out + off, 2 * ps, t2);
+                    split_limbs(z->im, nlimbs, v_out + off + 1, 2 * ps, t2);
                 }
             mpfr_clear(t2);
         }
@@ -391,6 +391,20 @@ int or_heev(int n, int L, const double *planes, int lda, int prec, int want_vect
     c_free(A, (size_t)n * n);
     c_free(V, (size_t)n * n);
     return converged ? 0 : -3;
+}
+
+int or_heev(int n, int L, const double *planes, int lda, int prec, int want_vectors, int nthreads,
+            double *w_out, double *v_out, double *info)
+{
+    return heev_impl(n, L, planes, lda, prec, want_vectors, nthreads, 4, w_out, v_out, info);
+}
+
+/* or_heev with `nlimbs` (1..16) output limbs per value (w_out: nlimbs x n,
+ * v_out: nlimbs planes), for precisions beyond quad-double. */
+int or_heev_limbs(int n, int L, const double *planes, int lda, int prec, int want_vectors, int nthreads,
+                  int nlimbs, double *w_out, double *v_out, double *info)
+{
+    return heev_impl(n, L, planes, lda, prec, want_vectors, nthreads, nlimbs, w_out, v_out, info);
 }
 
 /*

@@ -15,6 +15,8 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
+
 import torch  # noqa: F401  -- loads torch's HIP runtime first; libzk binds to the same one
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -37,6 +39,11 @@ class ZkPairInfo(ctypes.Structure):
 class ZkEigOut(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("ldv", ctypes.c_int), ("limbs", ctypes.c_int),
                 ("w", ctypes.c_void_p * 4), ("v", ctypes.c_void_p * 4), ("info", ctypes.POINTER(ZkPairInfo))]
+
+
+class ZkEigOutMp(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("ldv", ctypes.c_int), ("limbs", ctypes.c_int),
+                ("w", ctypes.c_void_p), ("v", ctypes.c_void_p), ("info", ctypes.POINTER(ZkPairInfo))]
 
 
 class ZkMat(ctypes.Structure):
@@ -62,7 +69,9 @@ KERNEL_CLASSES = ["lu_update", "lu_panel", "lu_trsm", "backsolve", "rq", "gs", "
 EXPORTED = ["zk_prof_enable", "zk_prof_classes", "zk_prof_reset", "zk_prof_read", "zk_opts_default", "zk_ctx_create", "zk_ctx_destroy", "zk_status_str", "zk_ctx_last_error",
             "zk_workspace_bytes", "zk_heev_dd", "zk_heev_qd", "zk_heev_dd_allpairs", "zk_svd_dd", "zk_mps_two_site_dd", "zk_heev_fp64", "zk_rqi_refine",
             "zk_session_create", "zk_session_submit", "zk_session_poll", "zk_session_times", "zk_session_destroy",
-            "zk_ctx_memory", "zk_ctx_last_stats", "zk_heev_dd_noalloc"]
+            "zk_ctx_memory", "zk_ctx_last_stats", "zk_heev_dd_noalloc", "zk_heev_mp",
+            "zk_mps_create", "zk_mps_destroy", "zk_mps_apply1", "zk_mps_apply2", "zk_mps_bond", "zk_mps_site",
+            "zk_mps_latencies"]
 
 _lib = None
 
@@ -89,6 +98,14 @@ def load(path: str = LIB_PATH):
     for f in ("zk_heev_dd", "zk_heev_qd", "zk_heev_dd_allpairs", "zk_heev_dd_noalloc"):
         getattr(lib, f).argtypes = [P, I, ctypes.POINTER(ZkHerm), ctypes.POINTER(ZkEigOut), ctypes.POINTER(ZkOpts)]
     lib.zk_svd_dd.argtypes = [P, I, ctypes.POINTER(ZkMat), ctypes.POINTER(ZkSvdOut), ctypes.POINTER(ZkOpts)]
+    lib.zk_mps_create.argtypes = [P, I, I, D, ctypes.POINTER(P)]
+    lib.zk_mps_destroy.argtypes = [P]
+    lib.zk_mps_apply1.argtypes = [P, I, P]
+    lib.zk_mps_apply2.argtypes = [P, I, P, P]
+    lib.zk_mps_bond.argtypes = [P, I, I, P, ctypes.POINTER(I)]
+    lib.zk_mps_site.argtypes = [P, I, ctypes.POINTER(I), ctypes.POINTER(I), P, ctypes.c_size_t]
+    lib.zk_mps_latencies.argtypes = [P, I, P, P, ctypes.POINTER(I)]
+    lib.zk_heev_mp.argtypes = [P, I, ctypes.POINTER(ZkHerm), ctypes.POINTER(ZkEigOutMp), ctypes.POINTER(ZkOpts)]
     P2 = P * 2
     lib.zk_mps_two_site_dd.argtypes = [P, I, I, I, P2, P2, P2, I, ctypes.c_double, P2, P2, P2,
                                        ctypes.POINTER(I), ctypes.POINTER(ZkOpts)]
@@ -306,6 +323,127 @@ def heev_allpairs(ctx: Context, mats, opts: ZkOpts | None = None):
     if rc not in (ZK_OK, ZK_ENOCONV):
         raise RuntimeError(f"zk_heev_dd_allpairs failed: {status_str(rc)}: {ctx.last_error()}")
     return [EigResult(w, V, _info_list(info, n), rc) for (w, V, info, n) in outs]
+
+
+def heev_mp(ctx: Context, mats, limbs: int = 8, opts: ZkOpts | None = None):
+    """Eigendecomposition to `limbs` (4, 8 or 16) binary64 limbs per value
+    (zk_heev_mp): w (limbs, n), V (limbs, n, n) with V[l][:, k] limb l of
+    eigenvector k."""
+    lib = load()
+    keep: list = []
+    count = len(mats)
+    H = (ZkHerm * count)()
+    O = (ZkEigOutMp * count)()
+    outs = []
+    want = True if opts is None else bool(opts.want_vectors)
+    for i, m in enumerate(mats):
+        H[i] = herm(m, keep)
+        n = H[i].n
+        w = torch.zeros((limbs, n), dtype=torch.float64, device=ctx_device(m))
+        vb = torch.zeros((limbs, n, n), dtype=torch.complex128, device=ctx_device(m)) if want else None
+        info = (ZkPairInfo * n)()
+        O[i].n, O[i].ldv, O[i].limbs = n, n, limbs
+        O[i].w = w.data_ptr()
+        O[i].v = vb.data_ptr() if vb is not None else None
+        O[i].info = ctypes.cast(info, ctypes.POINTER(ZkPairInfo))
+        keep += [w, vb, info]
+        outs.append((w, vb.transpose(1, 2) if vb is not None else None, info, n))
+    op = ctypes.byref(opts) if opts is not None else None
+    rc = lib.zk_heev_mp(ctx.handle, count, H, O, op)
+    if rc not in (ZK_OK, ZK_ENOCONV):
+        raise RuntimeError(f"zk_heev_mp failed: {status_str(rc)}: {ctx.last_error()}")
+    return [EigResult(w, V, _info_list(info, n), rc) for (w, V, info, n) in outs]
+
+
+def _gate_planes(G, dim):
+    """Two limb planes (hi, lo) of a dim x dim complex gate, column-major, as
+    one float64 array: G is a complex array or a pair of them (limbs)."""
+    limbs = list(G) if isinstance(G, (list, tuple)) else [np.asarray(G, dtype=np.complex128), None]
+    if len(limbs) == 1:
+        limbs.append(None)
+    out = np.zeros(2 * 2 * dim * dim, dtype=np.float64)
+    for p, g in enumerate(limbs[:2]):
+        if g is None:
+            continue
+        g = np.asarray(g, dtype=np.complex128)
+        if g.shape != (dim, dim):
+            raise ValueError(f"gate must be {dim} x {dim}")
+        out[p * 2 * dim * dim:(p + 1) * 2 * dim * dim] = np.ascontiguousarray(g.T).view(np.float64).ravel()
+    return out
+
+
+class Mps:
+    """A chain of qubits as a double-double matrix product state (zk_mps_*):
+    two-qubit gates emit Hermitian bond matrices that a serving session
+    eigendecomposes, one layer of disjoint gates at a time."""
+
+    def __init__(self, ctx: Context, nq: int, chi_max: int = 64, cutoff: float = 0.0):
+        self.lib = load()
+        self.ctx = ctx
+        self.nq = nq
+        h = ctypes.c_void_p()
+        rc = self.lib.zk_mps_create(ctx.handle, nq, chi_max, float(cutoff), ctypes.byref(h))
+        if rc != ZK_OK:
+            raise RuntimeError(f"zk_mps_create failed: {status_str(rc)}: {ctx.last_error()}")
+        self.handle = h
+
+    def apply1(self, q: int, G):
+        g = _gate_planes(G, 2)
+        rc = self.lib.zk_mps_apply1(self.handle, q, g.ctypes.data)
+        if rc != ZK_OK:
+            raise RuntimeError(f"zk_mps_apply1 failed: {status_str(rc)}: {self.ctx.last_error()}")
+
+    def apply2(self, qs, gates) -> int:
+        """Gates on the disjoint pairs (q, q+1) for q in qs; returns the status."""
+        arrs = [_gate_planes(G, 4) for G in gates]
+        ptrs = (ctypes.c_void_p * max(1, len(arrs)))(*[a.ctypes.data for a in arrs])
+        qa = (ctypes.c_int * max(1, len(qs)))(*qs)
+        rc = self.lib.zk_mps_apply2(self.handle, len(qs), qa, ptrs)
+        if rc not in (ZK_OK, ZK_ENOCONV):
+            raise RuntimeError(f"zk_mps_apply2 failed: {status_str(rc)}: {self.ctx.last_error()}")
+        return rc
+
+    def bond(self, b: int) -> np.ndarray:
+        """(2, chi) limbs of the squared Schmidt values of bond b, descending."""
+        chi = ctypes.c_int()
+        self.lib.zk_mps_bond(self.handle, b, 0, None, ctypes.byref(chi))
+        out = np.zeros(2 * chi.value, dtype=np.float64)
+        rc = self.lib.zk_mps_bond(self.handle, b, chi.value, out.ctypes.data, ctypes.byref(chi))
+        if rc != ZK_OK:
+            raise RuntimeError(f"zk_mps_bond failed: {status_str(rc)}")
+        return out.reshape(2, chi.value)
+
+    def site(self, q: int):
+        """(2, chi_l, 2, chi_r) complex limbs of B_q[l, s, r]."""
+        cl, cr = ctypes.c_int(), ctypes.c_int()
+        self.lib.zk_mps_site(self.handle, q, ctypes.byref(cl), ctypes.byref(cr), None, 0)
+        n = 2 * cl.value * 2 * cr.value
+        out = np.zeros(2 * n, dtype=np.float64)
+        rc = self.lib.zk_mps_site(self.handle, q, ctypes.byref(cl), ctypes.byref(cr), out.ctypes.data, out.size)
+        if rc != ZK_OK:
+            raise RuntimeError(f"zk_mps_site failed: {status_str(rc)}")
+        z = out.view(np.complex128).reshape(2, 2 * cr.value, cl.value)   # plane, column (s r), row l
+        return np.ascontiguousarray(z.reshape(2, 2, cr.value, cl.value).transpose(0, 3, 1, 2))
+
+    def latencies(self):
+        """(seconds, orders) of every bond matrix diagonalised so far."""
+        cnt = ctypes.c_int()
+        self.lib.zk_mps_latencies(self.handle, 0, None, None, ctypes.byref(cnt))
+        sec = np.zeros(max(1, cnt.value))
+        ords = np.zeros(max(1, cnt.value), dtype=np.int32)
+        self.lib.zk_mps_latencies(self.handle, cnt.value, sec.ctypes.data, ords.ctypes.data, ctypes.byref(cnt))
+        return sec[:cnt.value], ords[:cnt.value]
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.zk_mps_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class SvdResult:

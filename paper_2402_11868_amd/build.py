@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libzk.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["stage1.hip", "stage2.hip", "allpairs.hip", "svd.hip", "mps.hip", "api.cpp", "session.cpp", "noalloc.hip"]
+SOURCES = ["stage1.hip", "stage2.hip", "allpairs.hip", "svd.hip", "mps.hip", "api.cpp", "session.cpp", "noalloc.hip", "mp_polish.hip", "mps_sim.cpp"]
 ARCH = os.environ.get("ZK_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -577,6 +577,121 @@ extern "C" int zk_heev_dd_allpairs(zk_ctx *ctx, int count, const zk_herm *A, zk_
     return run_heev_allpairs(ctx, count, A, out, opts);
 }
 
+namespace zk {
+template <int L>
+int mp_polish_run(zk_ctx *ctx, int np, int n, const int *limbs_in, const double *const *hf,
+                  const double *const *w_dd, const double2 *const *v_dd, double *const *w_out, double2 *const *v_out,
+                  const int *ldv, zk_pair_info *const *info, double tol, int max_iter, int *iters_used);
+}
+
+// Eigendecomposition beyond double-double: the double-double all-pairs
+// refinement, then the L-limb polishing (mp_polish.hip).
+extern "C" int zk_heev_mp(zk_ctx *ctx, int count, const zk_herm *A, zk_eig_out_mp *out, const zk_opts *opts)
+{
+    if (!ctx) return ZK_EINVAL;
+    if (ctx->poisoned) return ctx->fail(ZK_EDEVICE, "context poisoned by an earlier device error");
+    if (count < 1 || !A || !out) return ctx->fail(ZK_EINVAL, "count < 1 or NULL arrays");
+    const int L = out[0].limbs;
+    if (L != 4 && L != 8 && L != 16) return ctx->fail(ZK_EINVAL, "limbs must be 4, 8 or 16");
+    const bool want = opts ? (opts->want_vectors != 0) : true;
+    for (int i = 0; i < count; i++) {
+        if (check_herm(A[i]) != ZK_OK) return ctx->fail(ZK_EINVAL, "matrix %d: bad n/lda/limbs/planes", i);
+        const zk_eig_out_mp &o = out[i];
+        if (o.limbs != L || o.n != A[i].n || !o.w || (want && (!o.v || o.ldv < A[i].n)))
+            return ctx->fail(ZK_EINVAL, "output %d: bad n/limbs/ldv or NULL pointers", i);
+    }
+    const double tol = (opts && opts->tol > 0.0) ? opts->tol : (L == 4 ? 1e-60 : (L == 8 ? 1e-120 : 1e-240));
+    const int max_iter = (opts && opts->max_iter > 0) ? opts->max_iter : 8 + 3 * L;
+    if (hipSetDevice(ctx->device) != hipSuccess) return ctx->fail(ZK_EDEVICE, "hipSetDevice failed");
+    std::vector<double *> hf(count), w0(count), V0(count);
+    std::vector<int *> flag(count);
+    int rc = carve_s2in(ctx, count, A, hf, w0, V0, flag);
+    if (rc != ZK_OK) return rc;
+    if ((rc = run_stage1(ctx, count, A, hf, w0, V0, flag, std::vector<int>(count, 0))) != ZK_OK) return rc;
+    // double-double start of every matrix: eigenvalue limbs and eigenvector limb planes
+    std::vector<size_t> off(count + 1, 0);
+    for (int i = 0; i < count; i++) {
+        const size_t n = A[i].n;
+        off[i + 1] = off[i] + align_up(16 * n) + 2 * align_up(16 * n * n);
+    }
+    if (!ctx->make_room(off[count])) return ctx->fail(ZK_ENOMEM, "the double-double start needs %zu bytes", off[count]);
+    void *buf = nullptr;
+    if (ctx->dev_alloc(&buf, off[count]) != ZK_OK) return ZK_ENOMEM;
+    ctx->extra += off[count];
+    ctx->note_held();
+    auto release = [&](int r) {
+        hipStreamSynchronize(ctx->stream);
+        ctx->dev_free(buf);
+        ctx->extra -= off[count];
+        return r;
+    };
+    std::vector<zk_eig_out> dd(count);
+    for (int i = 0; i < count; i++) {
+        const size_t n = A[i].n;
+        char *b = (char *)buf + off[i];
+        zk_eig_out &o = dd[i];
+        std::memset(&o, 0, sizeof o);
+        o.n = A[i].n;
+        o.ldv = A[i].n;
+        o.limbs = 2;
+        o.w[0] = (double *)b;
+        o.w[1] = (double *)b + n;
+        o.v[0] = b + align_up(16 * n);
+        o.v[1] = b + align_up(16 * n) + align_up(16 * n * n);
+        o.info = nullptr;
+    }
+    std::map<int, std::vector<int>> groups;
+    for (int i = 0; i < count; i++) groups[A[i].n].push_back(i);
+    int status = ZK_OK;
+    for (auto &kv : groups) {
+        const int n = kv.first;
+        const std::vector<int> &ids = kv.second;
+        std::vector<zk_herm> a;
+        std::vector<zk_eig_out> o;
+        std::vector<double *> h, w, v;
+        for (int i : ids) {
+            a.push_back(A[i]);
+            o.push_back(dd[i]);
+            h.push_back(hf[i]);
+            w.push_back(w0[i]);
+            v.push_back(V0[i]);
+        }
+        rc = zk::allpairs_run(ctx, (int)ids.size(), a.data(), o.data(), 1e-31, 12, 1, h, w, v, nullptr);
+        if (rc < 0) return release(rc);
+        std::vector<int> lin;
+        std::vector<const double *> hfp, wdd;
+        std::vector<const double2 *> vdd;
+        std::vector<double *> wo;
+        std::vector<double2 *> vo;
+        std::vector<int> ldv;
+        std::vector<zk_pair_info *> inf;
+        for (int i : ids) {
+            lin.push_back(A[i].limbs);
+            hfp.push_back(hf[i]);
+            wdd.push_back(dd[i].w[0]);
+            vdd.push_back((const double2 *)dd[i].v[0]);
+            vdd.push_back((const double2 *)dd[i].v[1]);
+            wo.push_back(out[i].w);
+            vo.push_back(want ? (double2 *)out[i].v : nullptr);
+            ldv.push_back(want ? out[i].ldv : n);
+            inf.push_back(out[i].info);
+        }
+        const int np = (int)ids.size();
+        if (L == 4)
+            rc = zk::mp_polish_run<4>(ctx, np, n, lin.data(), hfp.data(), wdd.data(), vdd.data(), wo.data(), vo.data(),
+                                      ldv.data(), inf.data(), tol, max_iter, nullptr);
+        else if (L == 8)
+            rc = zk::mp_polish_run<8>(ctx, np, n, lin.data(), hfp.data(), wdd.data(), vdd.data(), wo.data(), vo.data(),
+                                      ldv.data(), inf.data(), tol, max_iter, nullptr);
+        else
+            rc = zk::mp_polish_run<16>(ctx, np, n, lin.data(), hfp.data(), wdd.data(), vdd.data(), wo.data(), vo.data(),
+                                       ldv.data(), inf.data(), tol, max_iter, nullptr);
+        if (rc < 0) return release(rc);
+        if (rc == ZK_ENOCONV) status = ZK_ENOCONV;
+    }
+    return release(status);
+}
+
 extern "C" int zk_svd_dd(zk_ctx *ctx, int count, const zk_mat *A, zk_svd_out *out, const zk_opts *opts)
 {
     if (!ctx) return ZK_EINVAL;

@@ -416,6 +416,137 @@ MP_HD qd qd_sqrt(const qd &a)
     return x;
 }
 
+// ====================================================== L limbs, generic ====
+// Precision beyond quad-double: values of L binary64 limbs (L = 8: about 424
+// bits, L = 16: about 848 bits), built from the same error-free transforms.
+// Only what the precision polishing needs is provided: exact products of a
+// binary64 by an L-limb value, their cascaded accumulation, and the
+// renormalisation of a set of terms into L limbs.
+
+// Renormalise M terms into L limbs: the quad-double procedure above (sort by
+// magnitude, two VecSum passes, extraction of the leading non-overlapping
+// terms) for any L, then a bottom-up and a top-down Fast2Sum pass over the
+// limbs.
+template <int L, int M>
+MP_HD mp<L> renorm_n(double t[M])
+{
+    sort_desc_mag<M>(t);
+#pragma unroll
+    for (int pass = 0; pass < 2; pass++) {
+        double s = t[M - 1];
+#pragma unroll
+        for (int i = M - 2; i >= 0; i--) {
+            double e;
+            two_sum(t[i], s, s, e);
+            t[i + 1] = e;
+        }
+        t[0] = s;
+    }
+    mp<L> r;
+#pragma unroll
+    for (int k = 0; k < L; k++) r.x[k] = 0.0;
+    int j = 0;
+    double eps = t[0];
+#pragma unroll
+    for (int i = 1; i < M; i++) {
+        double s, e;
+        fast_two_sum(eps, t[i], s, e);
+        if (e != 0.0) {
+#pragma unroll
+            for (int k = 0; k < L; k++)
+                if (k == j) r.x[k] = s;
+            j++;
+            eps = e;
+        } else {
+            eps = s;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < L; k++)
+        if (k == j) r.x[k] = eps;
+    double s = r.x[L - 1];
+#pragma unroll
+    for (int k = L - 2; k >= 0; k--) {
+        double e;
+        fast_two_sum(r.x[k], s, s, e);
+        r.x[k + 1] = e;
+    }
+    r.x[0] = s;
+#pragma unroll
+    for (int k = 0; k + 1 < L; k++) fast_two_sum(r.x[k], r.x[k + 1], r.x[k], r.x[k + 1]);
+    return r;
+}
+
+// Cascaded accumulator at L-limb precision.  Level k (0 <= k < L) collects
+// terms of order k (about u^k times the largest term) with TwoSum; the error
+// of a TwoSum at level k goes on to level k + 1, and level L is a plain sum
+// (below the L-limb rounding).  An exact product x y_b of a binary64 x of
+// order o and limb b of y is p + e with p of order o + b and e of order
+// o + b + 1; orders above L are dropped.  The accumulated value is exact to
+// about u^L times the sum of the magnitudes of the terms.
+template <int L>
+struct CascN {
+    double S[L + 1];
+    MP_HD void zero()
+    {
+#pragma unroll
+        for (int k = 0; k <= L; k++) S[k] = 0.0;
+    }
+    MP_HD void put(int k, double v)
+    {
+#pragma unroll
+        for (int q = 0; q < L; q++)
+            if (q >= k) {
+                double s, e;
+                two_sum(S[q], v, s, e);
+                S[q] = s;
+                v = e;
+            }
+        S[L] += v;
+    }
+    // += x * y, x binary64 of order `off`, y an L-limb value
+    MP_HD void add(double x, const double *y, int off)
+    {
+#pragma unroll
+        for (int b = 0; b < L; b++) {
+            const int k = off + b;
+            if (k < L) {
+                double p, e;
+                two_prod(x, y[b], p, e);
+                put(k, p);
+                if (k + 1 < L) put(k + 1, e);
+                else S[L] += e;
+            } else if (k == L) {
+                S[L] += x * y[b];
+            }
+        }
+    }
+    // += x * y, both L-limb values (limb a of x has order a)
+    MP_HD void add_mm(const double *x, const double *y)
+    {
+#pragma unroll
+        for (int a = 0; a < L; a++) add(x[a], y, a);
+    }
+    MP_HD mp<L> get() const
+    {
+        double t[L + 1];
+#pragma unroll
+        for (int k = 0; k <= L; k++) t[k] = S[k];
+        return renorm_n<L, L + 1>(t);
+    }
+};
+
+// a + b for L-limb a and binary64 b
+template <int L>
+MP_HD mp<L> add_n_d(const mp<L> &a, double b)
+{
+    double t[L + 1];
+#pragma unroll
+    for (int k = 0; k < L; k++) t[k] = a.x[k];
+    t[L] = b;
+    return renorm_n<L, L + 1>(t);
+}
+
 // ================================================= generic dispatch =====
 template <int L> struct ops;
 

@@ -149,6 +149,32 @@ int mps_theta(const MpsDesc &D, hipStream_t st);
 // B' = diag(s[:chi']) V[:, :chi']^H
 int mps_bout(const MpsDesc &D, hipStream_t st);
 
+// One bond of the MPS simulation (mps.hip): sites q (cl x (2 cm)) and q+1
+// (cm x (2 cr)) in right-canonical form, column index s chi + r; all matrices
+// are two complex128 limb planes (hi, lo), column-major.
+struct MpsSimDesc {
+    int cl, cm, cr;       // chi_{q-1}, chi_q, chi_{q+1}
+    int chi;              // kept bond dimension (split)
+    const double *Bq[2];  // site q
+    const double *Bq1[2]; // site q+1
+    const double *lam[2]; // lambda_{q-1} (cl values, limb planes), or null (all ones)
+    double *T[2];         // theta (2 cl) x (2 cr), row s1 cl + l, column s2 cr + r; the site for gate1
+    const double *G[2];   // gate: 4 x 4 (index 2 s1 + s2) or 2 x 2, column-major
+    double *rho[2];       // bond matrix (2 cr) x (2 cr)
+    const double *V[2];   // its eigenvectors (ld 2 cr), ascending eigenvalues
+    const double *w[2];   // its eigenvalues
+    double *Bq_out[2];    // cl x (2 chi)
+    double *Bq1_out[2];   // chi x (2 cr)
+    double *lam_out[2];   // chi Schmidt values
+    double *eig_out[2];   // chi Schmidt values squared (the kept eigenvalues)
+};
+// theta = G (B_q B_{q+1}), rho = theta^H diag(lambda_{q-1}^2) theta
+int mps_sim_bond(const MpsSimDesc &D, hipStream_t st);
+// the new sites and bond from rho's eigendecomposition
+int mps_sim_split(const MpsSimDesc &D, hipStream_t st);
+// one-qubit gate on a site (D.T = the site, D.cl x (2 D.cm))
+int mps_sim_gate1(const MpsSimDesc &D, hipStream_t st);
+
 // ---------------------------------------------------------------- stage 2
 // Workspace of one concurrently factorised pair (shifted LU of order n,
 // augmented with the right-hand side as column n).

@@ -55,4 +55,34 @@ void t_qd_renorm16(const double *t, double *r)
     qd z = qd_renorm<16>(w);
     for (int i = 0; i < 4; i++) r[i] = z.x[i];
 }
+
+// L-limb cascades: sum_i x_i y_i with both factors L-limb (mm = 1) or x_i binary64 (mm = 0)
+#define CASCN(name, L)                                                         \
+    void name(int n, int mm, const double *x, const double *y, double *r)     \
+    {                                                                          \
+        CascN<L> a;                                                            \
+        a.zero();                                                              \
+        for (int i = 0; i < n; i++) {                                          \
+            if (mm) a.add_mm(x + L * i, y + L * i);                           \
+            else a.add(x[i], y + L * i, 0);                                    \
+        }                                                                      \
+        mp<L> z = a.get();                                                     \
+        for (int l = 0; l < L; l++) r[l] = z.x[l];                             \
+    }
+CASCN(t_casc_n8, 8)
+CASCN(t_casc_n16, 16)
+void t_renorm_n8_24(const double *t, double *r)
+{
+    double w[24];
+    for (int i = 0; i < 24; i++) w[i] = t[i];
+    mp<8> z = renorm_n<8, 24>(w);
+    for (int i = 0; i < 8; i++) r[i] = z.x[i];
+}
+void t_add_n16_d(const double *a, double b, double *r)
+{
+    mp<16> x;
+    for (int i = 0; i < 16; i++) x.x[i] = a[i];
+    mp<16> z = add_n_d<16>(x, b);
+    for (int i = 0; i < 16; i++) r[i] = z.x[i];
+}
 }

@@ -15,13 +15,15 @@ import pytest
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "host", "ap_shim.cpp")
-LIB = os.path.join(HERE, "host", "libap_shim.so")
+# one library per process: parallel test workers must not load a file another is still writing
+LIB = os.path.join(HERE, "host", f"libap_shim.{os.getpid()}.so")
 
 
 @pytest.fixture(scope="module")
 def lib():
     subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", SRC, "-o", LIB])
     l = ctypes.CDLL(LIB)
+    os.unlink(LIB)
     P = ctypes.c_void_p
     l.t_ap_runs.argtypes = [P, ctypes.c_int, P, P]
     l.t_ap_runs.restype = ctypes.c_int

@@ -15,7 +15,8 @@ import pytest
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "host", "arith_shim.cpp")
-LIB = os.path.join(HERE, "host", "libarith_shim.so")
+# one library per process: parallel test workers must not load a file another is still writing
+LIB = os.path.join(HERE, "host", f"libarith_shim.{os.getpid()}.so")
 
 U = Fraction(1, 2 ** 53)
 
@@ -24,6 +25,7 @@ U = Fraction(1, 2 ** 53)
 def lib():
     subprocess.check_call(["g++", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", SRC, "-o", LIB])
     l = ctypes.CDLL(LIB)
+    os.unlink(LIB)
     P, D = ctypes.c_void_p, ctypes.c_double
     for name in ("t_dd_add", "t_dd_mul", "t_dd_div", "t_qd_add", "t_qd_mul", "t_qd_div"):
         getattr(l, name).argtypes = [P, P, P]
@@ -31,6 +33,10 @@ def lib():
         getattr(l, name).argtypes = [P, P]
     l.t_casc3.argtypes = [ctypes.c_int, P, P, P, P]
     l.t_casc4.argtypes = [ctypes.c_int, P, P, P, P]
+    l.t_casc_n8.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P]
+    l.t_casc_n16.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P]
+    l.t_renorm_n8_24.argtypes = [P, P]
+    l.t_add_n16_d.argtypes = [P, D, P]
     l.t_two_sum.argtypes = [D, D, P, P]
     l.t_two_prod.argtypes = [D, D, P, P]
     return l
@@ -203,3 +209,84 @@ def test_cascaded_qd_accumulator(lib, cancel):
     # per term (the first version of this accumulator stopped at order 3 and
     # measured 10-100 u^4 here).
     assert err <= U ** 4 * mag / 4, float(err / mag)
+
+
+# ---------------------------------------------- beyond quad-double (L limbs) --
+def rand_long(rng, L, e):
+    """A value with about 53 L significant bits at exponent e, split into L limbs."""
+    x = Fraction(0)
+    for q in range(L + 1):
+        x += Fraction(int(rng.integers(-2 ** 62, 2 ** 62))) * Fraction(2) ** (e - 62 - 60 * q)
+    return split(x, L)
+
+
+def _nonoverlap(r):
+    """each limb at most half an ulp of the one before (or zero after a zero)"""
+    for a, b in zip(r[:-1], r[1:]):
+        if a == 0.0:
+            assert b == 0.0
+        else:
+            assert abs(b) <= np.spacing(abs(a)) / 2 * (1 + 1e-15)
+
+
+@pytest.mark.parametrize("L", [8, 16])
+@pytest.mark.parametrize("mm", [0, 1])
+def test_cascade_n_limbs(lib, L, mm):
+    """Sums of exact products at L-limb precision (the precision polishing's
+    accumulator): error <= 8 n u^L sum |x_i y_i|, limbs non-overlapping, with
+    cancelling terms and a spread of exponents."""
+    rng = np.random.default_rng(40 + L + mm)
+    f = lib.t_casc_n8 if L == 8 else lib.t_casc_n16
+    for trial in range(6):
+        n = int(rng.integers(1, 40))
+        xs = [rand_long(rng, L, int(rng.integers(-30, 30))) for _ in range(n)]
+        ys = [rand_long(rng, L, int(rng.integers(-30, 30))) for _ in range(n)]
+        if trial % 2:
+            # heavy cancellation: the second half repeats the first with the sign
+            # flipped and a tiny relative perturbation (2^-300) of y, renormalised
+            h = n // 2
+            for i in range(h):
+                xs[h + i] = -xs[i]
+                ys[h + i] = split(F(ys[i]) * (1 + Fraction(1, 2 ** 300)), L)
+        if mm:
+            x = np.concatenate(xs)
+            exact = sum((F(a) * F(b) for a, b in zip(xs, ys)), Fraction(0))
+            mag = sum((abs(F(a) * F(b)) for a, b in zip(xs, ys)), Fraction(0))
+        else:
+            x = np.array([a[0] for a in xs])
+            exact = sum((Fraction(float(a)) * F(b) for a, b in zip(x, ys)), Fraction(0))
+            mag = sum((abs(Fraction(float(a)) * F(b)) for a, b in zip(x, ys)), Fraction(0))
+        y = np.concatenate(ys)
+        r = np.zeros(L)
+        f(n, mm, x.ctypes.data, y.ctypes.data, r.ctypes.data)
+        err = abs(F(r) - exact)
+        assert err <= 8 * n * U ** L * mag, (L, mm, trial, float(err / mag))
+        _nonoverlap(r)
+
+
+def test_renorm_n_exact_sum(lib):
+    """24 overlapping terms into 8 limbs: the sum kept to u^8 relative, limbs
+    non-overlapping."""
+    rng = np.random.default_rng(77)
+    for _ in range(20):
+        t = np.array([float(rng.standard_normal()) * 2.0 ** int(rng.integers(-200, 10)) for _ in range(24)])
+        r = np.zeros(8)
+        lib.t_renorm_n8_24(t.ctypes.data, r.ctypes.data)
+        exact = F(t)
+        mag = sum((abs(Fraction(float(v))) for v in t), Fraction(0))
+        assert abs(F(r) - exact) <= 4 * U ** 8 * mag
+        _nonoverlap(r)
+
+
+def test_add_n_d_16(lib):
+    """a + b with a 16-limb value exact to u^16 of |a| + |b|."""
+    rng = np.random.default_rng(78)
+    for _ in range(20):
+        a = rand_long(rng, 16, int(rng.integers(-20, 20)))
+        b = float(rng.standard_normal()) * 2.0 ** int(rng.integers(-40, 40))
+        r = np.zeros(16)
+        lib.t_add_n16_d(a.ctypes.data, b, r.ctypes.data)
+        exact = F(a) + Fraction(b)
+        assert abs(F(r) - exact) <= 4 * U ** 16 * (abs(F(a)) + abs(Fraction(b)))
+        _nonoverlap(r)
+

@@ -340,3 +340,101 @@ def circuit_bond_matrices(n: int, seed: int = 0):
         rho = (R.astype(np.float64) / float(2 ** n)).astype(np.complex128)
         out.append({"k": k, "rho": rho, "R": R, "scale": n})
     return out
+
+
+def cnz_staircase(n: int, dps: int = 80):
+    """A nearest-neighbour circuit that prepares the state of the paper's
+    introductory circuit, C^(n-1)-Z on |+>^(n-1) |-> (Sec. 1, footnote 1), from
+    |0...0>:  psi = |+>^(n-1) |-> + 2^(-(n-2)/2) |1...1>, a sum of two product
+    states (bond dimension 2 at every cut).
+
+    Sequential generation of a matrix product state: psi is written in
+    right-canonical form B_0 .. B_{n-1} (LQ steps from the right, in mpmath at
+    `dps` digits); gate k acts on qubits (k, k+1) and maps |a>_k |0>_{k+1} to
+    sum_{s, b} B_k[a, s, b] |s>_k |b>_{k+1} (the last gate folds B_{n-1} in),
+    completed to a unitary by Gram-Schmidt.  Returns a list of (k, G_hi, G_lo):
+    4 x 4 complex gates (row and column index 2 s_k + s_{k+1}) as two binary64
+    limbs.  Applied in order to |0...0>, they give psi to the gates' rounding.
+    """
+    import mpmath as mp
+    if n < 3:
+        raise ValueError("n >= 3")
+    mp.mp.dps = dps
+    r2 = 1 / mp.sqrt(2)
+    plus, one, minus = [r2, r2], [mp.mpf(0), mp.mpf(1)], [r2, -r2]
+    c = mp.mpf(2) ** (-(n - 2) / mp.mpf(2))
+    # raw MPS: M[k][a][s][b]
+    M = []
+    M.append([[[plus[s], c * one[s]] for s in range(2)]])                      # 1 x 2 x 2
+    for _ in range(1, n - 1):
+        M.append([[[plus[s] if a == b == 0 else (one[s] if a == b == 1 else mp.mpf(0)) for b in range(2)]
+                   for s in range(2)] for a in range(2)])                       # 2 x 2 x 2
+    M.append([[[minus[s]] for s in range(2)], [[one[s]] for s in range(2)]])   # 2 x 2 x 1
+
+    def lq(mat):
+        """mat (r x c, r <= c) = L Q, Q with orthonormal rows (Gram-Schmidt on rows)."""
+        r, cc = len(mat), len(mat[0])
+        Q, L = [], [[mp.mpf(0)] * r for _ in range(r)]
+        for i in range(r):
+            v = list(mat[i])
+            for j in range(i):
+                d = mp.fsum(v[k] * mp.conj(Q[j][k]) for k in range(cc))
+                L[i][j] = d
+                v = [v[k] - d * Q[j][k] for k in range(cc)]
+            nv = mp.sqrt(mp.fsum(abs(x) ** 2 for x in v))
+            L[i][i] = nv
+            Q.append([x / nv for x in v])
+        return L, Q
+
+    B = [None] * n
+    for k in range(n - 1, 0, -1):
+        cl, cr = len(M[k]), len(M[k][0][0])
+        mat = [[M[k][a][s][b] for s in range(2) for b in range(cr)] for a in range(cl)]
+        L, Q = lq(mat)
+        B[k] = [[[Q[a][s * cr + b] for b in range(cr)] for s in range(2)] for a in range(cl)]
+        # absorb L into site k-1
+        pl = len(M[k - 1])
+        M[k - 1] = [[[mp.fsum(M[k - 1][a][s][m] * L[m][b] for m in range(cl)) for b in range(cl)]
+                     for s in range(2)] for a in range(pl)]
+    nrm = mp.sqrt(mp.fsum(abs(M[0][0][s][b]) ** 2 for s in range(2) for b in range(2)))
+    B[0] = [[[M[0][0][s][b] / nrm for b in range(2)] for s in range(2)]]
+
+    def complete(cols):
+        """4 x 4 unitary whose columns 0 and 2 are the given orthonormal columns."""
+        basis = [list(cols[0]), None, list(cols[1]), None] if len(cols) == 2 else [list(cols[0]), None, None, None]
+        have = [v for v in basis if v is not None]
+        extra = []
+        for e in range(4):
+            v = [mp.mpf(1) if i == e else mp.mpf(0) for i in range(4)]
+            for u in have + extra:
+                d = mp.fsum(mp.conj(u[i]) * v[i] for i in range(4))
+                v = [v[i] - d * u[i] for i in range(4)]
+            nv = mp.sqrt(mp.fsum(abs(x) ** 2 for x in v))
+            if nv > mp.mpf(10) ** (-dps // 2):
+                extra.append([x / nv for x in v])
+        slots = [i for i in range(4) if basis[i] is None]
+        for i, v in zip(slots, extra):
+            basis[i] = v
+        return basis   # list of columns
+
+    gates = []
+    for k in range(n - 1):
+        if k == 0:
+            cols = [[B[0][0][s][b] for s in range(2) for b in range(2)]]
+        elif k < n - 2:
+            cols = [[B[k][a][s][b] for s in range(2) for b in range(2)] for a in range(2)]
+        else:
+            cols = [[mp.fsum(B[k][a][s][m] * B[k + 1][m][t][0] for m in range(2)) for s in range(2) for t in range(2)]
+                    for a in range(2)]
+        U = complete(cols)
+        hi = np.zeros((4, 4), dtype=np.complex128)
+        lo = np.zeros((4, 4), dtype=np.complex128)
+        for col in range(4):
+            for row in range(4):
+                z = mp.mpc(U[col][row])
+                h = complex(float(z.real), float(z.imag))
+                l = complex(float(z.real - h.real), float(z.imag - h.imag))
+                hi[row, col], lo[row, col] = h, l
+        gates.append((k, hi, lo))
+    return gates
+
