@@ -373,6 +373,97 @@ def qd_companions_leg(Z, ctx, torch, count=16, n=256, tol=1e-60):
                              "avg_launch_ms": ms_u / max(la_u, 1)}}
 
 
+def _haar_unitary(rng, d=4):
+    """A seeded random d x d unitary (QR of a complex Gaussian, phases fixed)."""
+    import numpy as np
+    z = rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d))
+    q, r = np.linalg.qr(z)
+    return q * (np.diag(r) / np.abs(np.diag(r)))
+
+
+def mps_stream_leg(Z, ctx, torch, nq=40, layers=12, chi_max=64):
+    """The MPS stream: a 40-qubit brickwork of seeded random two-qubit
+    unitaries (binary64 gates) simulated in double-double by the MPS driver;
+    every gate's Hermitian bond matrix (order up to 2 chi_max) goes through
+    the session, one layer of disjoint gates at a time.  Reports the bond
+    matrices' submit-to-done latencies (p50 / p99), their orders and the
+    throughput; beside it, the 60-qubit state of the paper's introductory
+    circuit (C^(n-1)-Z on |+>^(n-1) |->) prepared by a nearest-neighbour
+    staircase, with its last-cut Schmidt pair 1 - eps, eps = 2^-59."""
+    import numpy as np
+    from fractions import Fraction
+    import workloads as W
+    rng = np.random.default_rng(240211868)
+    m = Z.Mps(ctx, nq, chi_max=chi_max, cutoff=1e-14)
+    t0 = time.monotonic()
+    for layer in range(layers):
+        qs = list(range(layer % 2, nq - 1, 2))
+        m.apply2(qs, [_haar_unitary(rng) for _ in qs])
+    wall = time.monotonic() - t0
+    lat, orders = m.latencies()
+    chis = [m.bond(b).shape[1] for b in range(1, nq)]
+    m.close()
+    gates = W.cnz_staircase(60)
+    m = Z.Mps(ctx, 60, chi_max=8, cutoff=1e-14)
+    t1 = time.monotonic()
+    for k, hi, lo in gates:
+        m.apply2([k], [(hi, lo)])
+    wall2 = time.monotonic() - t1
+    e = m.bond(59)
+    m.close()
+    eps = Fraction(1, 2 ** 59)
+    got = sum((Fraction(float(x)) for x in e[:, 1]), Fraction(0))
+    one = sum((Fraction(float(x)) for x in e[:, 0]), Fraction(0))
+    return {"workload": f"{nq}-qubit brickwork, {layers} layers of seeded random two-qubit unitaries, chi_max {chi_max}, "
+                        "double-double MPS; bond matrices rho = theta^H diag(lambda^2) theta through the session",
+            "bond_matrices": int(len(lat)), "orders_max": int(orders.max()), "orders_mean": float(orders.mean()),
+            "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99), "max_ms": float(lat.max() * 1e3),
+            "wall_s": wall, "bond_matrices_per_s": len(lat) / wall, "final_bond_dims_max": int(max(chis)),
+            "cnz60": {"gates": len(gates), "wall_s": wall2, "eps_rel_err": float(abs(got - eps) / eps),
+                      "one_minus_eps_err": float(abs(one - (1 - eps)))}}
+
+
+def mp_leg(Z, ctx, torch):
+    """Beyond double-double (zk_heev_mp): the paper's multiple-precision
+    workload shape (Hermitian matrices with random elements) at 8 and 16
+    limbs, and the whole 2048 x 2048 quad-double workload (4-limb exact
+    input, {1-2^-59, 2^-59} and a geometric tail to 2^-120) through the
+    all-pairs + quad-double polishing path, checked against its exact
+    spectrum."""
+    import numpy as np
+    from fractions import Fraction
+    import workloads as W
+    out = {}
+    A = torch.from_numpy(W.random_elements(64, 964)).cuda()
+    for L in (8, 16):
+        Z.heev_mp(ctx, [[A]], limbs=L)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(3):
+            t0 = time.monotonic()
+            r, = Z.heev_mp(ctx, [[A]], limbs=L)
+            torch.cuda.synchronize()
+            ts.append(time.monotonic() - t0)
+        out[f"random64_L{L}"] = {"ms": float(np.median(ts) * 1e3), "iterations": r.iters[0], "status": r.status,
+                                 "max_resid_rel": max(x["resid"] for x in r.info)}
+    n = 2048
+    h = W.hadamard_exact(W.spectrum_c5_dyadic(n), seed=W.seed_for(5, 0), limbs=4)
+    planes = [torch.from_numpy(np.ascontiguousarray(p)).cuda() for p in h.planes]
+    torch.cuda.synchronize()
+    t0 = time.monotonic()
+    r, = Z.heev_mp(ctx, [planes], limbs=4)
+    torch.cuda.synchronize()
+    ms = (time.monotonic() - t0) * 1e3
+    w = r.w.cpu().numpy()
+    hn = h.lam[-1]
+    errs = [float(abs(sum((Fraction(float(w[l, k])) for l in range(4)), Fraction(0)) - h.lam[k]) / hn) for k in range(n)]
+    ok = sum(1 for k in range(n) if errs[k] <= 1e-60 and r.info[k]["resid"] <= 1e-60)
+    out["qd2048"] = {"ms": ms, "passing_pairs": ok, "pairs": n, "eigenpairs_per_s": ok / (ms / 1e3),
+                     "max_eig_err_rel": max(errs), "max_resid_rel": max(x["resid"] for x in r.info),
+                     "iterations": r.iters[0], "status": r.status}
+    return out
+
+
 def _pct(x, q):
     import numpy as np
     return float(np.percentile(np.asarray(x), q)) * 1e3 if len(x) else None
@@ -505,6 +596,7 @@ def main():
     ap.add_argument("--no-fp32-leg", action="store_true", help="skip the FP32-MFMA-start run")
     ap.add_argument("--no-batch-leg", action="store_true", help="skip the 256 x 128^2 batch run")
     ap.add_argument("--no-allpairs-leg", action="store_true", help="skip the all-pairs refinement runs")
+    ap.add_argument("--no-mp-leg", action="store_true", help="skip the beyond-double-double runs")
     ap.add_argument("--no-svd-leg", action="store_true", help="skip the 512 x 512 SVD runs")
     ap.add_argument("--serving-requests", type=int, default=1000,
                     help="requests of the serving-stream leg (0 = skip the leg; the all-pairs leg serves twice as many)")
@@ -674,6 +766,11 @@ def main():
     out["c1"] = c1_leg(Z, ctx, torch)
     log("quad-double companions")
     out["qd_companions"] = qd_companions_leg(Z, ctx, torch)
+    log("MPS stream")
+    out["mps_stream"] = mps_stream_leg(Z, ctx, torch)
+    if not args.no_mp_leg:
+        log("beyond double-double")
+        out["mp"] = mp_leg(Z, ctx, torch)
     if args.serving_requests > 0:
         log("serving stream")
         out["serving"] = serving_leg(Z, ctx, torch, count=args.serving_requests)

@@ -115,9 +115,14 @@ typedef struct {
                              1: the all-pairs refinement of zk_heev_dd_allpairs (double-double output
                              only; ZK_EINVAL with 4 output limbs).  Honoured by zk_heev_dd and by
                              session requests; zk_rqi_refine always iterates per pair. */
+    int shifted_solve;    /* factorisation of the shifted systems (H - sigma I) w = v of the Rayleigh
+                             quotient iteration: 0 = default (LDL^H), 1 = LU with partial pivoting,
+                             2 = Hermitian LDL^H with Bunch-Kaufman pivoting (half the multiply-adds
+                             of LU in the trailing updates).  Sessions use the default. */
 } zk_opts;
 
-/* Fill *o with the defaults (init_fp32 0, tol 0, max_iter 0, cluster_tol 0, want_vectors 1, reorth 1, refine 0). */
+/* Fill *o with the defaults (init_fp32 0, tol 0, max_iter 0, cluster_tol 0, want_vectors 1, reorth 1, refine 0,
+ * shifted_solve 0). */
 void zk_opts_default(zk_opts *o);
 
 /* Create a context on HIP device `device`.  hip_stream: a hipStream_t of the
@@ -327,7 +332,7 @@ int zk_mps_two_site_dd(zk_ctx *ctx, int chi_l, int chi, int chi_r, const void *c
  * Limit: ZK_ENOMEM, before any work, when the call needs more than the array
  * holds (the binary64 stage, inputs and iterates of all `count` matrices at
  * once plus one shifted-LU slot of the largest order, as zk_workspace_bytes
- * counts them: one matrix of order up to 649, or e.g. 6 matrices of order
+ * counts them: one matrix of order up to 647, or e.g. 6 matrices of order
  * 256, 26 of order 128), and ZK_ENOMEM if the array runs out during the call.
  * Concurrency: the array is shared by every call on that GPU and keeps the
  * last call's contents (nothing reads them).  Calls from threads of one

@@ -60,7 +60,7 @@ class ZkSvdOut(ctypes.Structure):
 class ZkOpts(ctypes.Structure):
     _fields_ = [("init_fp32", ctypes.c_int), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("cluster_tol", ctypes.c_double), ("want_vectors", ctypes.c_int), ("reorth", ctypes.c_int),
-                ("refine", ctypes.c_int)]
+                ("refine", ctypes.c_int), ("shifted_solve", ctypes.c_int)]
 
 
 KERNEL_CLASSES = ["lu_update", "lu_panel", "lu_trsm", "backsolve", "rq", "gs", "reorth", "stage1", "her2k", "hemv",
@@ -134,7 +134,7 @@ def status_str(s: int) -> str:
 
 
 def make_opts(tol=0.0, max_iter=0, cluster_tol=0.0, want_vectors=True, init_fp32=False, reorth=True,
-              refine=0) -> ZkOpts:
+              refine=0, shifted_solve=0) -> ZkOpts:
     o = ZkOpts()
     load().zk_opts_default(ctypes.byref(o))
     o.tol = float(tol)
@@ -144,6 +144,7 @@ def make_opts(tol=0.0, max_iter=0, cluster_tol=0.0, want_vectors=True, init_fp32
     o.init_fp32 = int(bool(init_fp32))
     o.reorth = int(bool(reorth))
     o.refine = int(refine)
+    o.shifted_solve = int(shifted_solve)
     return o
 
 

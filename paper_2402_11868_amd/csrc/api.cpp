@@ -45,6 +45,7 @@ extern "C" void zk_opts_default(zk_opts *o)
     o->want_vectors = 1;
     o->reorth = 1;
     o->refine = 0;
+    o->shifted_solve = 0;
 }
 
 extern "C" const char *zk_ctx_last_error(const zk_ctx *ctx) { return ctx ? ctx->err.c_str() : ""; }
@@ -213,12 +214,12 @@ static size_t s2vec_bytes(int n, int L)
 
 static int lu_ldm(int n) { return (n + 7) & ~7; }
 
-static size_t lu_slot_doubles(int n, int L) { return (size_t)2 * L * lu_ldm(n) * (size_t)(n + 1); }
+static size_t lu_slot_doubles(int n, int L) { return (size_t)2 * L * lu_ldm(n) * (size_t)(n + 3 + zk::kLuNB); }
 
 extern "C" size_t zk_workspace_bytes(int n, int limbs, int concurrent_pairs)
 {
     if (n < 1 || (limbs != 2 && limbs != 4) || concurrent_pairs < 0) return 0;
-    const size_t lu = align_up(8 * lu_slot_doubles(n, limbs)) + align_up(4 * (size_t)n);
+    const size_t lu = align_up(8 * lu_slot_doubles(n, limbs)) + align_up(8 * (size_t)n);
     return s1_bytes(n) + s2in_bytes(n, 4) + s2vec_bytes(n, limbs) + (size_t)concurrent_pairs * lu + align_up(64 * (size_t)n + 4096);
 }
 
@@ -256,6 +257,7 @@ ResolvedOpts zk_resolve_opts(const zk_opts *o, int L)
     r.init_fp32 = o ? o->init_fp32 : 0;
     r.reorth = o ? (o->reorth != 0) : 1;
     r.refine = o ? o->refine : 0;
+    r.ldl = (o && o->shifted_solve == 1) ? 0 : 1;
     r.max_iter_set = (o && o->max_iter > 0) ? o->max_iter : 0;
     return r;
 }

@@ -54,6 +54,7 @@ struct PairDesc {
     int flags;
     int slot;      // LU workspace slot while active
     int tiny;      // pivots below 2^11 guard thresholds in the pair's last shifted factorisation
+    int lk0, lkb;  // LDL^H: first column and width of the pair's current panel
     int pad0;
     double resid;  // ||H v - sigma v|| / hnorm
     double prev_resid;

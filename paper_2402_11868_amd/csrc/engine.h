@@ -40,12 +40,13 @@ struct ResolvedOpts {
     int init_fp32;
     int reorth;
     int refine;
+    int ldl;            // shifted solves by LDL^H (Bunch-Kaufman) instead of LU
     int max_iter_set;   // the caller's max_iter (0: default)
 };
 
 inline size_t s2_align(size_t x) { return (x + 255) & ~(size_t)255; }
 inline int s2_lu_ldm(int n) { return (n + 7) & ~7; }
-inline size_t s2_lu_slot_doubles(int n, int L) { return (size_t)2 * L * s2_lu_ldm(n) * (size_t)(n + 1); }
+inline size_t s2_lu_slot_doubles(int n, int L) { return (size_t)2 * L * s2_lu_ldm(n) * (size_t)(n + 3 + kLuNB); }
 
 // One matrix in the engine.  The caller sets rp (n, limbs_in, hf, w0, V0,
 // ldv0, ldv_out, w_out, v_out, hnorm lower bound), npairs and info.
@@ -277,6 +278,7 @@ class Stage2Engine {
         B.dev_probs = d_probs;
         B.dev_active = d_active;
         B.max_iter = O.max_iter;
+        B.ldl = O.ldl;
         B.lu_base = (double *)ctx->s2lu.p;
         B.piv_base = (int *)((char *)ctx->s2lu.p + (size_t)S * s2_align(8 * s2_lu_slot_doubles(std::max(slot_n, 1), L)));
         B.timer = ctx->tp();
@@ -297,7 +299,7 @@ class Stage2Engine {
         }
         if (n <= slot_n && S >= std::min(wanted, 64) && ctx->s2lu.p) return ZK_OK;
         const int nn = std::max(n, slot_n);
-        const size_t per = s2_align(8 * s2_lu_slot_doubles(nn, L)) + s2_align(4 * (size_t)nn);
+        const size_t per = s2_align(8 * s2_lu_slot_doubles(nn, L)) + s2_align(8 * (size_t)nn);
         const size_t others = ctx->held() - ctx->s2lu.bytes;
         const size_t avail = ctx->budget > others ? ctx->budget - others : 0;
         int want = std::max(wanted, S);
@@ -516,7 +518,7 @@ class Stage2Engine {
             B.count = cnt;
             B.ldm = s2_lu_ldm(n);
             B.lu_stride = s2_lu_slot_doubles(n, L);
-            B.piv_stride = (size_t)n;
+            B.piv_stride = 2 * (size_t)n;
             if (stage2_solve<L>(B, ord.data() + c0, st)) return ctx->fail(ZK_EDEVICE, "solve launch failed");
         }
         HIPCHK_(hipStreamSynchronize(st));

@@ -176,16 +176,21 @@ int mps_sim_split(const MpsSimDesc &D, hipStream_t st);
 int mps_sim_gate1(const MpsSimDesc &D, hipStream_t st);
 
 // ---------------------------------------------------------------- stage 2
-// Workspace of one concurrently factorised pair (shifted LU of order n,
-// augmented with the right-hand side as column n).
+// Workspace of one concurrently factorised pair (shifted factorisation of
+// order n, augmented with the right-hand side as column n; columns n+1 and
+// n+2 are the LDL^H panel's working columns, columns n+3 .. n+3+kLuNB-1 its
+// W = L D of the panel last factorised).
 struct LuSlot {
-    double *M;      // 2L planes of ldm x (n+1) doubles
-    int *ipiv;      // n
+    double *M;      // 2L planes of ldm x (n+3+kLuNB) doubles
+    int *ipiv;      // 2n: interchanges, then the LDL^H panel-start marks
 };
 
 // Stage-2 launch table: `count` active pairs (indices into the pair table).
-// leading dimension of a pair's LU planes (each plane ldm x (n+1) doubles)
+// leading dimension of a pair's factorisation planes, and the plane size
+// (ldm x (n+3+kLuNB) doubles: the matrix, the right-hand side, two working
+// columns, the panel's W)
 __host__ __device__ inline int lu_ldm_of(int n) { return (n + 7) & ~7; }
+__host__ __device__ inline size_t lu_plane_of(int n) { return (size_t)lu_ldm_of(n) * (size_t)(n + 3 + kLuNB); }
 
 struct Stage2Batch {
     int L;                  // 2 (dd) or 4 (qd)
@@ -199,6 +204,7 @@ struct Stage2Batch {
     int *piv_base;          // slot s at piv_base + s * piv_stride
     size_t piv_stride;
     int ldm;                // unused by the solve (each pair's planes use lu_ldm_of(its order))
+    int ldl;                // 1: Hermitian LDL^H with Bunch-Kaufman pivoting, 0: LU with partial pivoting
     int max_iter;
     int final_pass;         // rq: re-judge converged pairs after re-orthogonalisation
     KernelTimer *timer;     // host object, may be null

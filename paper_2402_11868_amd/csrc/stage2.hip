@@ -1,10 +1,12 @@
 // Stage 2 of the method: Rayleigh quotient iteration in double-double (L=2)
-// or quad-double (L=4) arithmetic that recovers the precision of the binary64
-// eigenpairs (Sec. 2, ZKCM_CUS paragraph: RQI is used "to recover the
-// precision" after the double-precision solver).  For each pair k:
+// or quad-double (L=4) arithmetic that brings the binary64 eigenpairs to the
+// working precision (Sec. 2, ZKCM_CUS paragraph: the iteration runs after the
+// double-precision solver to regain the precision it lacks).  For each pair k:
 //
 //   v <- binary64 eigenvector, sigma <- v^H H v
-//   repeat:  solve (H - sigma I) w = v     shifted LU, partial pivoting, L limbs
+//   repeat:  solve (H - sigma I) w = v     L limbs: Hermitian LDL^H with
+//                                          Bunch-Kaufman pivoting (default) or
+//                                          LU with partial pivoting
 //            Gram-Schmidt w against the converged members of its eigenvalue
 //            cluster and the lower-index members of the same iteration (twice)
 //            v <- w / ||w||,  y = H v,  sigma <- v^H y,  r = y - sigma v
@@ -12,13 +14,18 @@
 //
 // Kernels (each launch covers every active pair of the batch):
 //   build      M = [H - sigma I | v], limb-planar
-//   lu_panel   one work-group per pair factorises an n x NB panel
-//   lu_trsm    applies the panel's row interchanges to the trailing columns
-//              and computes U12 = L11^{-1} A12, one thread per column
-//   lu_update  A22 -= L21 U12: the O(n^3) part; a 64x64 (dd) or 32x32 (qd)
-//              output tile per work-group, operands staged in LDS, every
+//   ldl_panel  one work-group per pair factorises its next panel (at most NB
+//              columns, left-looking, symmetric interchanges), writes W = L D
+//              column-major and forward-substitutes the right-hand side
+//   lu_panel   (LU) one work-group per pair factorises an n x NB panel
+//   lu_trsm    (LU) applies the panel's row interchanges to the trailing
+//              columns and computes U12 = L11^{-1} A12
+//   lu_update  the O(n^3) part: A22 -= L21 W21^H on the lower triangle of
+//              tiles (LDL^H) or A22 -= L21 U12 (LU); a 64x64 (dd) or 32x32
+//              (qd) output tile per work-group, operands staged in LDS, every
 //              product accumulated error-free into a (sum, compensation) pair
-//   backsolve  w = U^{-1} y (y = transformed right-hand side, column n)
+//   backsolve  w = P^T L^{-H} D^{-1} y (LDL^H) or w = U^{-1} y (LU), y the
+//              transformed right-hand side (column n)
 //   gs, rq     as above; rq also decides convergence on the device
 #include <hip/hip_runtime.h>
 
@@ -396,13 +403,17 @@ template <int L>
 __global__ void __launch_bounds__(256) k_s2_build(Stage2Batch B)
 {
     const int t = blockIdx.y;
-    const PairDesc &Q = B.dev_pairs[B.dev_active[t]];
+    PairDesc &Q = B.dev_pairs[B.dev_active[t]];
     const RqiProb &P = B.dev_probs[Q.prob];
     const int n = P.n, k = Q.k, ldm = lu_ldm_of(n);
     double *M = B.lu_base + (size_t)t * B.lu_stride;
-    const size_t plane = (size_t)ldm * (n + 1);
+    const size_t plane = lu_plane_of(n);
     const size_t nn = (size_t)n * n;
     mp<L> sigma = ld_sigma<L>(P, k);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {   // LDL^H: no panel factorised yet
+        Q.lk0 = 0;
+        Q.lkb = 0;
+    }
     // Two or more tiny pivots in the pair's last factorisation: sigma sits on
     // an eigenvalue that is degenerate at working precision, and the pivots
     // of its eigenspace were rounding noise.  The solve then inverted a
@@ -454,7 +465,7 @@ __global__ void __launch_bounds__(256) k_s2_lu_panel(Stage2Batch B, int k0, int 
     nbw = min(nbw, n - k0);     // the pair's own panel width at this step
     double *M = B.lu_base + (size_t)t * B.lu_stride;
     int *ipiv = B.piv_base + (size_t)t * B.piv_stride;
-    const size_t plane = (size_t)ldm * (n + 1);
+    const size_t plane = lu_plane_of(n);
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     __shared__ double smax[4];
     __shared__ int sidx[4];
@@ -603,7 +614,7 @@ __global__ void __launch_bounds__(256) k_s2_lu_trsm(Stage2Batch B, int k0, int n
     nbw = min(nbw, n - k0);
     double *M = B.lu_base + (size_t)t * B.lu_stride;
     const int *ipiv = B.piv_base + (size_t)t * B.piv_stride;
-    const size_t plane = (size_t)ldm * (n + 1);
+    const size_t plane = lu_plane_of(n);
     __shared__ cmp<L> l11t[kLuNB][kLuNB];   // l11t[q][r] = L11(r, q)
     // the panel's interchanges as one permutation of at most 2 nbw rows:
     // row dst[i] receives the value of row src[i]
@@ -666,6 +677,28 @@ __global__ void __launch_bounds__(256) k_s2_lu_trsm(Stage2Batch B, int k0, int n
 }
 
 // =========================================================== LU update ====
+// Output tile of a work-group: the LU covers the trailing block row-tile
+// fastest (ti = x mod tilesI); the LDL^H only its lower triangle of tiles,
+// enumerated row by row (tile q: ti (ti + 1) / 2 <= q < (ti + 1) (ti + 2) / 2).
+template <bool LDL>
+__device__ __forceinline__ bool tile_of(int mrows, int tsz, int &ti, int &tj)
+{
+    const int T = (mrows + tsz - 1) / tsz;
+    const int q = blockIdx.x;
+    if (!LDL) {
+        ti = q % T;
+        tj = q / T;
+        return true;
+    }
+    if (q >= T * (T + 1) / 2) return false;
+    int a = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
+    while ((a + 1) * (a + 2) / 2 <= q) a++;
+    while (a * (a + 1) / 2 > q) a--;
+    ti = a;
+    tj = q - a * (a + 1) / 2;
+    return true;
+}
+
 // A22 -= L21 U12 for rows [r0, n), columns [r0, n] (r0 = k0 + nbw).
 // dd: 64x64 tile per work-group of 256, 4x4 outputs per thread (rows
 // tx + 16a, columns ty + 16b, so that the 16 lanes of a row group read and
@@ -674,22 +707,32 @@ __global__ void __launch_bounds__(256) k_s2_lu_trsm(Stage2Batch B, int k0, int n
 constexpr int KC = 8;
 constexpr int KCD = 4;   // k-chunk of the double-double update (256 threads stage 4 x 64 of L and U)
 
+template <bool LDL>
 __global__ void __launch_bounds__(256, 2) k_s2_lu_update_dd(Stage2Batch B, int k0, int nbw)
 {
     const int t = blockIdx.y;
     const PairDesc &Q = B.dev_pairs[B.dev_active[t]];
     const int n = B.dev_probs[Q.prob].n, ldm = lu_ldm_of(n);
-    if (k0 >= n) return;
-    nbw = min(nbw, n - k0);
+    if (LDL) {
+        k0 = Q.lk0;
+        nbw = Q.lkb;
+        if (nbw <= 0) return;
+    } else {
+        if (k0 >= n) return;
+        nbw = min(nbw, n - k0);
+    }
     double *M = B.lu_base + (size_t)t * B.lu_stride;
-    const size_t plane = (size_t)ldm * (n + 1);
+    const size_t plane = lu_plane_of(n);
     const int r0 = k0 + nbw;
-    const int mrows = n - r0, mcols = n + 1 - r0;
+    const int jend = LDL ? n : n + 1;   // LU: the right-hand side column too
+    const int mrows = n - r0, mcols = jend - r0;
     if (mrows <= 0) return;
-    const int tilesI = (mrows + 63) / 64;
-    const int ti = blockIdx.x % tilesI, tj = blockIdx.x / tilesI;
+    int ti, tj;
+    if (!tile_of<LDL>(mrows, 64, ti, tj)) return;
     const int i0 = r0 + ti * 64, j0 = r0 + tj * 64;
     if (ti * 64 >= mrows || tj * 64 >= mcols) return;
+    // LDL^H diagonal tile: its 16x16 sub-blocks above the diagonal (b > a) are not needed
+    const bool diag = LDL && ti == tj;
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
     // planes: 0 re_hi, 1 re_lo, 2 im_hi, 3 im_lo; two buffers: the next chunk
     // is loaded from global memory while the current one is multiplied
@@ -705,10 +748,19 @@ __global__ void __launch_bounds__(256, 2) k_s2_lu_update_dd(Stage2Batch B, int k
                 const bool ok = kc + kk < nbw && gi < n;
                 for (int pl = 0; pl < 4; pl++) pL[pl] = ok ? M[pl * plane + (size_t)kcol * ldm + gi] : 0.0;
             }
-            {
+            if (LDL) {
+                // U(c, j) = conj W(j, c), W column-major after the slot's working columns
+                const int kk = q >> 6, jj = q & 63;
+                const int gj = j0 + jj;
+                const bool ok = kc + kk < nbw && gj < jend;
+                const size_t o = (size_t)(n + 3 + kc + kk) * ldm + gj;
+                for (int pl = 0; pl < 4; pl++) pU[pl] = ok ? M[pl * plane + o] : 0.0;
+                pU[2] = -pU[2];
+                pU[3] = -pU[3];
+            } else {
                 const int kk = q & (KCD - 1), jj = q / KCD;
                 const int kcol = k0 + kc + kk, gj = j0 + jj;
-                const bool ok = kc + kk < nbw && gj <= n;
+                const bool ok = kc + kk < nbw && gj < jend;
                 for (int pl = 0; pl < 4; pl++) pU[pl] = ok ? M[pl * plane + (size_t)gj * ldm + kcol] : 0.0;
             }
         }
@@ -717,7 +769,8 @@ __global__ void __launch_bounds__(256, 2) k_s2_lu_update_dd(Stage2Batch B, int k
         const int q = tid;
         for (int pl = 0; pl < 4; pl++) {
             sL[buf][pl][q >> 6][q & 63] = pL[pl];
-            sU[buf][pl][q & (KCD - 1)][q / KCD] = pU[pl];
+            if (LDL) sU[buf][pl][q >> 6][q & 63] = pU[pl];
+            else sU[buf][pl][q & (KCD - 1)][q / KCD] = pU[pl];
         }
     };
     fetch(0);
@@ -726,7 +779,7 @@ __global__ void __launch_bounds__(256, 2) k_s2_lu_update_dd(Stage2Batch B, int k
         for (int b = 0; b < 4; b++) {
             const int i = i0 + tx + 16 * a, j = j0 + ty + 16 * b;
             double rh = 0.0, rl = 0.0, ih = 0.0, il = 0.0;
-            if (i < n && j <= n) {
+            if (i < n && j < jend && !(diag && b > a)) {
                 const size_t o = (size_t)j * ldm + i;
                 rh = M[o]; rl = M[plane + o]; ih = M[2 * plane + o]; il = M[3 * plane + o];
             }
@@ -751,6 +804,7 @@ __global__ void __launch_bounds__(256, 2) k_s2_lu_update_dd(Stage2Batch B, int k
                 const double lrh = -sL[buf][0][kk][tx + 16 * a], lrl = -sL[buf][1][kk][tx + 16 * a];
                 const double lih = sL[buf][2][kk][tx + 16 * a], lil = sL[buf][3][kk][tx + 16 * a];
                 for (int b = 0; b < 4; b++) {
+                    if (diag && b > a) continue;
                     // re -= lr ur - li ui  ->  re += (-lr) ur + li ui
                     acc_dd(S[a][b][0], C[a][b][0], lrh, lrl, urh[b], url[b]);
                     acc_dd(S[a][b][0], C[a][b][0], lih, lil, uih[b], uil[b]);
@@ -767,7 +821,7 @@ __global__ void __launch_bounds__(256, 2) k_s2_lu_update_dd(Stage2Batch B, int k
     for (int a = 0; a < 4; a++)
         for (int b = 0; b < 4; b++) {
             const int i = i0 + tx + 16 * a, j = j0 + ty + 16 * b;
-            if (i < n && j <= n) {
+            if (i < n && j < jend && !(diag && b > a)) {
                 const size_t o = (size_t)j * ldm + i;
                 const dd re = acc_dd_final(S[a][b][0], C[a][b][0]);
                 const dd im = acc_dd_final(S[a][b][1], C[a][b][1]);
@@ -778,21 +832,28 @@ __global__ void __launch_bounds__(256, 2) k_s2_lu_update_dd(Stage2Batch B, int k
 }
 
 // Generic (quad-double) update: 32x32 tile, 2x2 outputs per thread.
-template <int L>
+template <int L, bool LDL>
 __global__ void __launch_bounds__(256) k_s2_lu_update_gen(Stage2Batch B, int k0, int nbw)
 {
     const int t = blockIdx.y;
     const PairDesc &Q = B.dev_pairs[B.dev_active[t]];
     const int n = B.dev_probs[Q.prob].n, ldm = lu_ldm_of(n);
-    if (k0 >= n) return;
-    nbw = min(nbw, n - k0);
+    if (LDL) {
+        k0 = Q.lk0;
+        nbw = Q.lkb;
+        if (nbw <= 0) return;
+    } else {
+        if (k0 >= n) return;
+        nbw = min(nbw, n - k0);
+    }
     double *M = B.lu_base + (size_t)t * B.lu_stride;
-    const size_t plane = (size_t)ldm * (n + 1);
+    const size_t plane = lu_plane_of(n);
     const int r0 = k0 + nbw;
-    const int mrows = n - r0, mcols = n + 1 - r0;
+    const int jend = LDL ? n : n + 1;
+    const int mrows = n - r0, mcols = jend - r0;
     if (mrows <= 0) return;
-    const int tilesI = (mrows + 31) / 32;
-    const int ti = blockIdx.x % tilesI, tj = blockIdx.x / tilesI;
+    int ti, tj;
+    if (!tile_of<LDL>(mrows, 32, ti, tj)) return;
     const int i0 = r0 + ti * 32, j0 = r0 + tj * 32;
     if (ti * 32 >= mrows || tj * 32 >= mcols) return;
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
@@ -803,7 +864,7 @@ __global__ void __launch_bounds__(256) k_s2_lu_update_gen(Stage2Batch B, int k0,
     for (int a = 0; a < 2; a++)
         for (int b = 0; b < 2; b++) {
             const int i = i0 + tx + 16 * a, j = j0 + ty + 16 * b;
-            acc[a][b].init((i < n && j <= n) ? ld_cmp<L>(M, plane, (size_t)j * ldm + i) : c_zero<L>());
+            acc[a][b].init((i < n && j < jend) ? ld_cmp<L>(M, plane, (size_t)j * ldm + i) : c_zero<L>());
         }
     for (int kc = 0; kc < nbw; kc += KC) {
         __syncthreads();
@@ -813,10 +874,15 @@ __global__ void __launch_bounds__(256) k_s2_lu_update_gen(Stage2Batch B, int k0,
                 const int kcol = k0 + kc + kk;
                 sL[kk][ii] = (kc + kk < nbw && i0 + ii < n) ? ld_cmp<L>(M, plane, (size_t)kcol * ldm + i0 + ii) : c_zero<L>();
             }
-            {
+            if (LDL) {
+                const int kk = q >> 5, jj = q & 31;
+                sU[kk][jj] = (kc + kk < nbw && j0 + jj < jend)
+                                 ? c_conj<L>(ld_cmp<L>(M, plane, (size_t)(n + 3 + kc + kk) * ldm + j0 + jj))
+                                 : c_zero<L>();
+            } else {
                 const int kk = q & (KC - 1), jj = q / KC;
                 const int kcol = k0 + kc + kk;
-                sU[kk][jj] = (kc + kk < nbw && j0 + jj <= n) ? ld_cmp<L>(M, plane, (size_t)(j0 + jj) * ldm + kcol) : c_zero<L>();
+                sU[kk][jj] = (kc + kk < nbw && j0 + jj < jend) ? ld_cmp<L>(M, plane, (size_t)(j0 + jj) * ldm + kcol) : c_zero<L>();
             }
         }
         __syncthreads();
@@ -828,7 +894,7 @@ __global__ void __launch_bounds__(256) k_s2_lu_update_gen(Stage2Batch B, int k0,
     for (int a = 0; a < 2; a++)
         for (int b = 0; b < 2; b++) {
             const int i = i0 + tx + 16 * a, j = j0 + ty + 16 * b;
-            if (i < n && j <= n) st_cmp<L>(M, plane, (size_t)j * ldm + i, acc[a][b].get());
+            if (i < n && j < jend) st_cmp<L>(M, plane, (size_t)j * ldm + i, acc[a][b].get());
         }
 }
 
@@ -844,7 +910,7 @@ __global__ void __launch_bounds__(256) k_s2_backsolve(Stage2Batch B)
     const RqiProb &P = B.dev_probs[Q.prob];
     const int n = P.n, ldm = lu_ldm_of(n), k = Q.k;
     double *M = B.lu_base + (size_t)t * B.lu_stride;
-    const size_t plane = (size_t)ldm * (n + 1);
+    const size_t plane = lu_plane_of(n);
     const size_t nn = (size_t)n * n;
     const size_t ycol = (size_t)n * ldm;
     __shared__ cmp<L> s_w;
@@ -877,6 +943,389 @@ __global__ void __launch_bounds__(256) k_s2_backsolve(Stage2Batch B)
     if (mx > 0.0 && isfinite(mx)) frexp(mx, &e);
     for (int r = threadIdx.x; r < n; r += 256) {
         cmp<L> w = ld_cmp<L>(M, plane, ycol + r);
+        w.re = ldexp_mp(w.re, -e);
+        w.im = ldexp_mp(w.im, -e);
+        st_cmp<L>(P.vec, nn, (size_t)k * n + r, w);
+    }
+    if (threadIdx.x == 0) Q.iters++;
+}
+
+// =========================================================== LDL^H ====
+// Hermitian indefinite factorisation P (H - sigma I) P^T = L D L^H with
+// Bunch-Kaufman pivoting (diagonal blocks of order 1 and 2; Bunch and
+// Kaufman, Math. Comp. 31 (1977), with the |re| + |im| magnitude), blocked:
+// one work-group factorises a panel of at most kLuNB columns left-looking,
+// then the trailing update A22 -= L21 W21^H (W = L D) covers the lower
+// triangle only, half the multiply-adds of the LU's A22 -= L21 U12.
+// Storage of a pair's slot (n rows; columns 0 .. n+2):
+//   lower triangle  A, then L below the diagonal blocks;
+//   diagonal        D (2x2 blocks keep d21 at (k+1, k), where their unit L
+//                   has a structural zero);
+//   column n        right-hand side, forward-substituted as the columns are
+//                   factorised (every row below a new column at once);
+//   columns n+1,n+2 the panel's working columns (w_k, candidate pivot column);
+//   columns n+3 ..  W = L D of the panel last factorised, column-major (its
+//                   rows r > c for column c), read by the trailing update;
+//   upper triangle  unused (the update's diagonal tiles write there).
+// ipiv[k] >= 0: 1x1 block at k with rows k and ipiv[k] interchanged;
+// ipiv[k] = -(p+1), ipiv[k+1] = kIpiv2nd: 2x2 block at (k, k+1) with rows
+// k+1 and p interchanged.  An interchange reaches the current panel's
+// columns, the right-hand side and the not yet factorised part only (rows of
+// earlier panels' L keep their order), so the back-substitution undoes each
+// panel's interchanges after that panel's columns; ipiv[n + k] = 1 marks the
+// first column of a panel.  A panel never ends inside a 2x2 block: it stops
+// one column short instead, so panel widths are per pair (PairDesc lk0, lkb).
+constexpr int kIpiv2nd = -2147483647 - 1;
+constexpr double kBkAlpha = 0.64038820320220756872767623199676;   // (1 + sqrt 17) / 8
+
+// work-group arg-max over 256 threads (largest value, smallest index on
+// ties); every thread returns the result
+__device__ __forceinline__ void wg_argmax256(double &v, int &i, double *sv, int *si)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(v, off, 64);
+        const int oi = __shfl_xor(i, off, 64);
+        if (ov > v || (ov == v && oi < i)) {
+            v = ov;
+            i = oi;
+        }
+    }
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        sv[threadIdx.x >> 6] = v;
+        si[threadIdx.x >> 6] = i;
+    }
+    __syncthreads();
+    v = sv[0];
+    i = si[0];
+    for (int q = 1; q < 4; q++)
+        if (sv[q] > v || (sv[q] == v && si[q] < i)) {
+            v = sv[q];
+            i = si[q];
+        }
+}
+
+template <int L>
+__device__ __forceinline__ void swap_cmp(double *M, size_t plane, size_t a, size_t b)
+{
+    const cmp<L> x = ld_cmp<L>(M, plane, a), y = ld_cmp<L>(M, plane, b);
+    st_cmp<L>(M, plane, a, y);
+    st_cmp<L>(M, plane, b, x);
+}
+
+// one work-group (256) per pair: the pair's next panel, from column lk0 + lkb
+template <int L>
+__global__ void __launch_bounds__(256) k_s2_ldl_panel(Stage2Batch B)
+{
+    const int t = blockIdx.x;
+    PairDesc &Q = B.dev_pairs[B.dev_active[t]];
+    const RqiProb &P = B.dev_probs[Q.prob];
+    const int n = P.n, ldm = lu_ldm_of(n);
+    const int k0 = Q.lk0 + Q.lkb;
+    __syncthreads();   // every thread has read the panel state before it changes
+    if (k0 >= n) {
+        if (threadIdx.x == 0) {
+            Q.lk0 = n;
+            Q.lkb = 0;
+        }
+        return;
+    }
+    double *M = B.lu_base + (size_t)t * B.lu_stride;
+    int *ipiv = B.piv_base + (size_t)t * B.piv_stride;
+    const size_t plane = lu_plane_of(n);
+    const size_t bc = (size_t)n * ldm, wc = (size_t)(n + 1) * ldm, xc = (size_t)(n + 2) * ldm;
+    const size_t wb = (size_t)(n + 3) * ldm;   // W column c - k0 at wb + (c - k0) ldm
+    const int kend = min(k0 + kLuNB, n);
+    const int tid = threadIdx.x;
+    const double ptol = P.piv_tol;
+    __shared__ cmp<L> s_wt[kLuNB];
+    __shared__ double s_v[4];
+    __shared__ int s_i[4];
+    __shared__ int s_kstep, s_kp, s_stop;
+    __shared__ mp<L> s_inv;
+    __shared__ cmp<L> s_d21;
+    __shared__ mp<L> s_d11, s_d22, s_idet;
+    __shared__ cmp<L> s_y[2];
+    int guard = 0, tiny = 0;   // thread 0's counts
+    int k = k0;
+    while (k < kend) {
+        const int nk = k - k0;
+        // w_k = column k of the Schur complement, rows [k, n)
+        if (tid < nk) s_wt[tid] = c_conj<L>(ld_cmp<L>(M, plane, wb + (size_t)tid * ldm + k));
+        __syncthreads();
+        double best = -1.0;
+        int bi = n;
+        for (int r = k + tid; r < n; r += 256) {
+            CAcc<L> a;
+            a.init(ld_cmp<L>(M, plane, (size_t)k * ldm + r));
+            for (int c = 0; c < nk; c++) a.sub_mul(ld_cmp<L>(M, plane, (size_t)(k0 + c) * ldm + r), s_wt[c]);
+            const cmp<L> w = a.get();
+            st_cmp<L>(M, plane, wc + r, w);
+            if (r > k) {
+                const double m = c_mag1(w);
+                if (m > best) {
+                    best = m;
+                    bi = r;
+                }
+            }
+        }
+        wg_argmax256(best, bi, s_v, s_i);
+        const double colmax = fmax(best, 0.0);
+        const int imax = bi;
+        const double absakk = fabs(ld_cmp<L>(M, plane, wc + k).re.x[0]);   // written by this thread (r = k)
+        const bool cand = !(colmax < fmax(ptol, 1e-300) || absakk >= kBkAlpha * colmax);
+        double rowmax = 0.0, absimax = 0.0;
+        if (cand) {
+            // the candidate pivot column imax of the Schur complement, rows [k, n)
+            __syncthreads();
+            if (tid < nk) s_wt[tid] = c_conj<L>(ld_cmp<L>(M, plane, wb + (size_t)tid * ldm + imax));
+            __syncthreads();
+            double rb = 0.0;
+            int ri = 0;
+            for (int r = k + tid; r < n; r += 256) {
+                CAcc<L> a;
+                a.init(r >= imax ? ld_cmp<L>(M, plane, (size_t)imax * ldm + r)
+                                 : c_conj<L>(ld_cmp<L>(M, plane, (size_t)r * ldm + imax)));
+                for (int c = 0; c < nk; c++) a.sub_mul(ld_cmp<L>(M, plane, (size_t)(k0 + c) * ldm + r), s_wt[c]);
+                const cmp<L> w = a.get();
+                st_cmp<L>(M, plane, xc + r, w);
+                if (r != imax) rb = fmax(rb, c_mag1(w));
+            }
+            wg_argmax256(rb, ri, s_v, s_i);
+            rowmax = rb;
+            absimax = fabs(ld_cmp<L>(M, plane, xc + imax).re.x[0]);   // visible after the barriers above
+        }
+        if (tid == 0) {
+            int kstep = 1, kp = k;
+            if (cand) {
+                if (absakk >= kBkAlpha * colmax * (colmax / rowmax)) kp = k;
+                else if (absimax >= kBkAlpha * rowmax) kp = imax;
+                else {
+                    kstep = 2;
+                    kp = imax;
+                }
+            }
+            s_kstep = kstep;
+            s_kp = kp;
+            s_stop = (kstep == 2 && k + 1 >= kend) ? 1 : 0;
+        }
+        __syncthreads();
+        const int kstep = s_kstep, kp = s_kp;
+        if (s_stop) break;   // the 2x2 block opens the next panel
+        const int kk = k + kstep - 1;
+        if (kp != kk) {
+            // symmetric interchange kk <-> kp: the panel's L rows and W rows,
+            // the right-hand side, and the stored part of the matrix (column
+            // kk, about to be overwritten, moves to row / column kp)
+            for (int c = tid; c < nk; c += 256) {
+                swap_cmp<L>(M, plane, (size_t)(k0 + c) * ldm + kk, (size_t)(k0 + c) * ldm + kp);
+                swap_cmp<L>(M, plane, wb + (size_t)c * ldm + kk, wb + (size_t)c * ldm + kp);
+            }
+            for (int r = kk + 1 + tid; r < n; r += 256) {
+                if (r < kp) st_cmp<L>(M, plane, (size_t)r * ldm + kp, c_conj<L>(ld_cmp<L>(M, plane, (size_t)kk * ldm + r)));
+                else if (r > kp) st_cmp<L>(M, plane, (size_t)kp * ldm + r, ld_cmp<L>(M, plane, (size_t)kk * ldm + r));
+            }
+            if (tid == 0) {
+                swap_cmp<L>(M, plane, bc + kk, bc + kp);
+                st_cmp<L>(M, plane, (size_t)kp * ldm + kp, ld_cmp<L>(M, plane, (size_t)kk * ldm + kk));
+                if (kstep == 1) {
+                    swap_cmp<L>(M, plane, xc + k, xc + kp);   // the pivot column is the candidate's
+                } else {
+                    swap_cmp<L>(M, plane, wc + kk, wc + kp);
+                    swap_cmp<L>(M, plane, xc + kk, xc + kp);
+                }
+            }
+            __syncthreads();
+        }
+        const size_t pc = (kstep == 1 && kp != k) ? xc : wc;   // 1x1 pivot column
+        if (tid == 0) {
+            if (kstep == 1) {
+                mp<L> d = ld_cmp<L>(M, plane, pc + k).re;
+                if (fabs(d.x[0]) < 2048.0 * ptol) tiny++;
+                if (fabs(d.x[0]) < ptol) {
+                    d = mp_from<L>(d.x[0] < 0.0 ? -ptol : ptol);
+                    guard = 1;
+                }
+                s_inv = div(mp_from<L>(1.0), d);
+                cmp<L> dz;
+                dz.re = d;
+                dz.im = mp_zero<L>();
+                st_cmp<L>(M, plane, (size_t)k * ldm + k, dz);
+                ipiv[k] = kp;
+                s_y[0] = ld_cmp<L>(M, plane, bc + k);
+            } else {
+                const mp<L> d11 = ld_cmp<L>(M, plane, wc + k).re;
+                const mp<L> d22 = ld_cmp<L>(M, plane, xc + k + 1).re;
+                const cmp<L> d21 = ld_cmp<L>(M, plane, wc + k + 1);
+                const mp<L> det = sub(mul(d11, d22), c_abs2(d21));
+                s_d11 = d11;
+                s_d22 = d22;
+                s_d21 = d21;
+                s_idet = div(mp_from<L>(1.0), det);
+                // tiny-eigenvalue count of the block (binary64 estimate)
+                const double a = d11.x[0], b = d22.x[0];
+                const double big = fabs(0.5 * (a + b)) + sqrt(0.25 * (a - b) * (a - b) + c_mag1(d21) * c_mag1(d21));
+                if (big > 0.0 && fabs(det.x[0]) / big < 2048.0 * ptol) tiny++;
+                cmp<L> z;
+                z.re = d11;
+                z.im = mp_zero<L>();
+                st_cmp<L>(M, plane, (size_t)k * ldm + k, z);
+                z.re = d22;
+                st_cmp<L>(M, plane, (size_t)(k + 1) * ldm + k + 1, z);
+                st_cmp<L>(M, plane, (size_t)k * ldm + k + 1, d21);
+                ipiv[k] = -(kp + 1);
+                ipiv[k + 1] = kIpiv2nd;
+                s_y[0] = ld_cmp<L>(M, plane, bc + k);
+                s_y[1] = ld_cmp<L>(M, plane, bc + k + 1);
+            }
+            for (int q = 0; q < kstep; q++) ipiv[n + k + q] = (k + q == k0) ? 1 : 0;
+        }
+        __syncthreads();
+        if (kstep == 1) {
+            const mp<L> inv = s_inv;
+            const cmp<L> y = s_y[0];
+            for (int r = k + 1 + tid; r < n; r += 256) {
+                const cmp<L> w = ld_cmp<L>(M, plane, pc + r);
+                const cmp<L> l = c_scale(w, inv);
+                st_cmp<L>(M, plane, (size_t)k * ldm + r, l);
+                st_cmp<L>(M, plane, wb + (size_t)nk * ldm + r, w);
+                CAcc<L> b;
+                b.init(ld_cmp<L>(M, plane, bc + r));
+                b.sub_mul(l, y);
+                st_cmp<L>(M, plane, bc + r, b.get());
+            }
+        } else {
+            const mp<L> d11 = s_d11, d22 = s_d22, idet = s_idet;
+            const cmp<L> d21 = s_d21, y0 = s_y[0], y1 = s_y[1];
+            for (int r = k + 2 + tid; r < n; r += 256) {
+                const cmp<L> a = ld_cmp<L>(M, plane, wc + r), b2 = ld_cmp<L>(M, plane, xc + r);
+                // [L(r,k) L(r,k+1)] = [a b2] D^{-1},  D^{-1} = [[d22, -conj d21], [-d21, d11]] / det
+                const cmp<L> l0 = c_scale(c_sub(c_scale(a, d22), c_mul(b2, d21)), idet);
+                const cmp<L> l1 = c_scale(c_sub(c_scale(b2, d11), c_mul(a, c_conj<L>(d21))), idet);
+                st_cmp<L>(M, plane, (size_t)k * ldm + r, l0);
+                st_cmp<L>(M, plane, (size_t)(k + 1) * ldm + r, l1);
+                st_cmp<L>(M, plane, wb + (size_t)nk * ldm + r, a);
+                st_cmp<L>(M, plane, wb + (size_t)(nk + 1) * ldm + r, b2);
+                CAcc<L> b;
+                b.init(ld_cmp<L>(M, plane, bc + r));
+                b.sub_mul(l0, y0);
+                b.sub_mul(l1, y1);
+                st_cmp<L>(M, plane, bc + r, b.get());
+            }
+        }
+        k += kstep;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        Q.lk0 = k0;
+        Q.lkb = k - k0;
+        if (guard) Q.flags |= 4;
+        Q.tiny = (k0 == 0 ? 0 : Q.tiny) + tiny;
+    }
+}
+
+// work-group sum of a complex multi-limb value over 256 threads (thread 0
+// returns it)
+template <int L>
+__device__ __forceinline__ cmp<L> wg_sum256(cmp<L> v, cmp<L> *red)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        cmp<L> o;
+        for (int l = 0; l < L; l++) {
+            o.re.x[l] = __shfl_xor(v.re.x[l], off, 64);
+            o.im.x[l] = __shfl_xor(v.im.x[l], off, 64);
+        }
+        v = c_add(v, o);
+    }
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return c_add(c_add(red[0], red[1]), c_add(red[2], red[3]));
+}
+
+// x = P^T L^{-H} D^{-1} y (y = column n after the factorisation), scaled by a
+// power of two to max-norm ~1 and written as the pair's new iterate.  One
+// work-group (256) per pair; column n is overwritten.
+template <int L>
+__global__ void __launch_bounds__(256) k_s2_ldl_backsolve(Stage2Batch B)
+{
+    const int t = blockIdx.x;
+    PairDesc &Q = B.dev_pairs[B.dev_active[t]];
+    const RqiProb &P = B.dev_probs[Q.prob];
+    const int n = P.n, ldm = lu_ldm_of(n), k = Q.k;
+    double *M = B.lu_base + (size_t)t * B.lu_stride;
+    const int *ipiv = B.piv_base + (size_t)t * B.piv_stride;
+    const size_t plane = lu_plane_of(n);
+    const size_t nn = (size_t)n * n;
+    const size_t yc = (size_t)n * ldm;
+    __shared__ cmp<L> red[4];
+    __shared__ double redd[4];
+    // z = D^{-1} y
+    for (int i = threadIdx.x; i < n; i += 256) {
+        const int p = ipiv[i];
+        if (p >= 0) {
+            const mp<L> d = ld_cmp<L>(M, plane, (size_t)i * ldm + i).re;
+            st_cmp<L>(M, plane, yc + i, c_scale(ld_cmp<L>(M, plane, yc + i), div(mp_from<L>(1.0), d)));
+        } else if (p != kIpiv2nd) {
+            const mp<L> d11 = ld_cmp<L>(M, plane, (size_t)i * ldm + i).re;
+            const mp<L> d22 = ld_cmp<L>(M, plane, (size_t)(i + 1) * ldm + i + 1).re;
+            const cmp<L> d21 = ld_cmp<L>(M, plane, (size_t)i * ldm + i + 1);
+            const mp<L> idet = div(mp_from<L>(1.0), sub(mul(d11, d22), c_abs2(d21)));
+            const cmp<L> y0 = ld_cmp<L>(M, plane, yc + i), y1 = ld_cmp<L>(M, plane, yc + i + 1);
+            st_cmp<L>(M, plane, yc + i, c_scale(c_sub(c_scale(y0, d22), c_mul(c_conj<L>(d21), y1)), idet));
+            st_cmp<L>(M, plane, yc + i + 1, c_scale(c_sub(c_scale(y1, d11), c_mul(d21, y0)), idet));
+        }
+    }
+    __syncthreads();
+    // L^H x = z, last column first; a panel's interchanges are undone once
+    // its first column is done
+    int pend = n;
+    for (int i = n - 1; i >= 0;) {
+        const bool two = ipiv[i] == kIpiv2nd;   // (i-1, i) is a 2x2 block: L(i, i-1) = 0
+        const int c0 = two ? i - 1 : i;
+        CAcc<L> a0, a1;
+        a0.init(c_zero<L>());
+        a1.init(c_zero<L>());
+        for (int r = i + 1 + threadIdx.x; r < n; r += 256) {
+            const cmp<L> x = ld_cmp<L>(M, plane, yc + r);
+            a0.add_mulc(ld_cmp<L>(M, plane, (size_t)i * ldm + r), x);
+            if (two) a1.add_mulc(ld_cmp<L>(M, plane, (size_t)c0 * ldm + r), x);
+        }
+        const cmp<L> s0 = wg_sum256<L>(a0.get(), red);
+        cmp<L> s1 = c_zero<L>();
+        if (two) {
+            __syncthreads();
+            s1 = wg_sum256<L>(a1.get(), red);
+        }
+        if (threadIdx.x == 0) {
+            st_cmp<L>(M, plane, yc + i, c_sub(ld_cmp<L>(M, plane, yc + i), s0));
+            if (two) st_cmp<L>(M, plane, yc + c0, c_sub(ld_cmp<L>(M, plane, yc + c0), s1));
+            if (ipiv[n + c0] == 1) {
+                for (int j = pend - 1; j >= c0; j--) {
+                    const int p = ipiv[j];
+                    if (p == kIpiv2nd) {
+                        swap_cmp<L>(M, plane, yc + j, yc + (-ipiv[j - 1] - 1));
+                        j--;
+                    } else if (p >= 0 && p != j) {
+                        swap_cmp<L>(M, plane, yc + j, yc + p);
+                    }
+                }
+            }
+        }
+        if (ipiv[n + c0] == 1) pend = c0;
+        __syncthreads();
+        i = c0 - 1;
+    }
+    double mx = 0.0;
+    for (int r = threadIdx.x; r < n; r += 256) mx = fmax(mx, c_mag1(ld_cmp<L>(M, plane, yc + r)));
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+    if ((threadIdx.x & 63) == 0) redd[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    mx = fmax(fmax(redd[0], redd[1]), fmax(redd[2], redd[3]));
+    int e = 0;
+    if (mx > 0.0 && isfinite(mx)) frexp(mx, &e);
+    for (int r = threadIdx.x; r < n; r += 256) {
+        cmp<L> w = ld_cmp<L>(M, plane, yc + r);
         w.re = ldexp_mp(w.re, -e);
         w.im = ldexp_mp(w.im, -e);
         st_cmp<L>(P.vec, nn, (size_t)k * n + r, w);
@@ -1589,6 +2038,45 @@ int stage2_solve(const Stage2Batch &B, const int *orders, hipStream_t st)
     int id = T.begin(KC_BUILD, 0.0, st);
     hipLaunchKernelGGL(k_s2_build<L>, dim3(cdiv2(n + 1, 8), cnt), dim3(256), 0, st, B);
     T.end(id, st);
+    if (B.ldl) {
+        // Panels of kLuNB - 1 or kLuNB columns (per pair): after s steps every
+        // pair has factorised at least min(order, s (kLuNB - 1)) columns.
+        const int w = kLuNB - 1;
+        const int steps = (n + w - 1) / w;
+        for (int s = 0; s < steps; s++) {
+            int c = cnt;
+            while (c > 0 && orders[c - 1] <= s * w) c--;
+            if (c == 0) break;
+            double wp = 0.0, wu = 0.0;
+            for (int q = 0; q < c; q++) {
+                const int m = orders[q], k0 = std::min(m, s * kLuNB), r0 = std::min(m, k0 + kLuNB);
+                wp += 0.5 * (double)(m - k0) * kLuNB * kLuNB;
+                wu += 0.5 * (double)(m - r0) * (m - r0 + 1) * (r0 - k0);   // complex multi-limb multiply-adds of the lower triangle
+            }
+            id = T.begin(KC_LU_PANEL, wp, st);
+            hipLaunchKernelGGL(k_s2_ldl_panel<L>, dim3(c), dim3(256), 0, st, B);
+            T.end(id, st);
+            // the largest trailing block any pair can have after this step
+            const int mrows = n - std::min(n, (s + 1) * w);
+            if (mrows <= 0) continue;
+            id = T.begin(KC_LU_UPDATE, wu, st);
+            if (L == 2) {
+                const unsigned tt = cdiv2(mrows, 64);
+                hipLaunchKernelGGL(k_s2_lu_update_dd<true>, dim3(tt * (tt + 1) / 2, c), dim3(256), 0, st, B, 0, 0);
+            } else {
+                const unsigned tt = cdiv2(mrows, 32);
+                hipLaunchKernelGGL((k_s2_lu_update_gen<L, true>), dim3(tt * (tt + 1) / 2, c), dim3(256), 0, st, B, 0, 0);
+            }
+            T.end(id, st);
+        }
+        double wb = 0.0;
+        for (int q = 0; q < cnt; q++) wb += 0.5 * (double)orders[q] * orders[q];
+        id = T.begin(KC_BACKSOLVE, wb, st);
+        hipLaunchKernelGGL(k_s2_ldl_backsolve<L>, dim3(cnt), dim3(256), 0, st, B);
+        T.end(id, st);
+        if (!B.timer) dummy.collect();
+        return hipGetLastError() == hipSuccess ? 0 : -1;
+    }
     for (int k0 = 0; k0 < n; k0 += kLuNB) {
         int c = cnt;
         while (c > 0 && orders[c - 1] <= k0) c--;
@@ -1613,10 +2101,10 @@ int stage2_solve(const Stage2Batch &B, const int *orders, hipStream_t st)
             id = T.begin(KC_LU_UPDATE, wu, st);
             if (L == 2) {
                 const unsigned tiles = cdiv2(mrows, 64) * cdiv2(ncols, 64);
-                hipLaunchKernelGGL(k_s2_lu_update_dd, dim3(tiles, c), dim3(256), 0, st, B, k0, nbw);
+                hipLaunchKernelGGL(k_s2_lu_update_dd<false>, dim3(tiles, c), dim3(256), 0, st, B, k0, nbw);
             } else {
                 const unsigned tiles = cdiv2(mrows, 32) * cdiv2(ncols, 32);
-                hipLaunchKernelGGL(k_s2_lu_update_gen<L>, dim3(tiles, c), dim3(256), 0, st, B, k0, nbw);
+                hipLaunchKernelGGL((k_s2_lu_update_gen<L, false>), dim3(tiles, c), dim3(256), 0, st, B, k0, nbw);
             }
             T.end(id, st);
         }

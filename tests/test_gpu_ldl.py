@@ -1,0 +1,173 @@
+"""Shifted solves of the Rayleigh quotient iteration: the Hermitian LDL^H
+factorisation with Bunch-Kaufman pivoting (zk_opts.shifted_solve = 2, the
+default) and LU with partial pivoting (shifted_solve = 1), each under the
+same gates against the MPFR oracle.
+
+The inputs exercise what differs from LU: indefinite matrices (random
+elements: 2x2 pivots and symmetric interchanges), orders that are not a
+multiple of the panel width and several orders in one call (every pair has
+its own panel widths, since a panel never ends inside a 2x2 block), exact
+degeneracies and zero eigenvalues (tiny pivots), the paper's Schmidt pair
+(Sec. 1, footnote 1), quad-double, and the clustered 1024 workload whole.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+from gpu_helpers import gate, log
+
+pytestmark = pytest.mark.gpu
+
+DD_TOL, QD_TOL = 1e-30, 1e-60
+DD_ORTH, QD_ORTH = 1e-28, 1e-58
+
+
+@pytest.fixture(scope="module")
+def zk():
+    import torch
+    import paper_2402_11868_amd as Z
+    Z.load()
+    ctx = Z.Context(0)
+    yield Z, ctx, torch
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def _dev(torch, planes):
+    return [torch.from_numpy(np.ascontiguousarray(p)).to("cuda") for p in planes]
+
+
+def _ldl(Z, **kw):
+    return Z.make_opts(shifted_solve=2, **kw)
+
+
+def _lu(Z, **kw):
+    return Z.make_opts(shifted_solve=1, **kw)
+
+
+@pytest.mark.parametrize("n", [3, 33, 96])
+def test_lu_householder_family(zk, n):
+    Z, ctx, torch = zk
+    A = W.householder_hermitian(W.spectrum_c4(n), seed=W.seed_for(4, n))
+    res, = Z.heev(ctx, [_dev(torch, [A])], limbs_out=2, opts=_lu(Z))
+    gate([A], res, oracle.heev([A], want_vectors=False).w_limbs, DD_TOL, orth_tol=DD_ORTH)
+
+
+def test_lu_indefinite_mixed_orders_and_qd(zk):
+    Z, ctx, torch = zk
+    mats = [W.random_elements(n, 4600 + n) for n in (40, 97, 17)]
+    res = Z.heev(ctx, [_dev(torch, [A]) for A in mats], limbs_out=2, opts=_lu(Z))
+    for A, r in zip(mats, res):
+        gate([A], r, oracle.heev([A], want_vectors=False).w_limbs, DD_TOL, orth_tol=DD_ORTH)
+    B = W.householder_hermitian(W.spectrum_c4(24), seed=31)
+    res, = Z.heev(ctx, [_dev(torch, [B])], limbs_out=4, opts=_lu(Z))
+    gate([B], res, oracle.heev([B], want_vectors=False).w_limbs, QD_TOL, orth_tol=QD_ORTH)
+
+
+@pytest.mark.parametrize("n", [2, 3, 17, 33, 75, 96])
+def test_ldl_householder_family(zk, n):
+    Z, ctx, torch = zk
+    log(f"ldl dd householder n={n}")
+    A = W.householder_hermitian(W.spectrum_c4(n), seed=W.seed_for(4, n))
+    res, = Z.heev(ctx, [_dev(torch, [A])], limbs_out=2, opts=_ldl(Z))
+    gate([A], res, oracle.heev([A], want_vectors=False).w_limbs, DD_TOL, orth_tol=DD_ORTH)
+
+
+@pytest.mark.parametrize("n", [5, 40, 97, 130])
+def test_ldl_indefinite_random_elements(zk, n):
+    """Hermitian matrices with random elements: eigenvalues of both signs, so
+    the shifted matrices are strongly indefinite (2x2 pivots)."""
+    Z, ctx, torch = zk
+    log(f"ldl dd random elements n={n}")
+    A = W.random_elements(n, 4100 + n)
+    res, = Z.heev(ctx, [_dev(torch, [A])], limbs_out=2, opts=_ldl(Z))
+    out = gate([A], res, oracle.heev([A], want_vectors=False).w_limbs, DD_TOL, orth_tol=DD_ORTH,
+               dev_resid="agree")
+    log(f"ldl random n={n}: {out}, iterations {np.bincount(res.iters)}")
+
+
+def test_ldl_mixed_orders_one_call(zk):
+    """Orders around the panel width in one call: pairs of different orders
+    share every launch with their own panel boundaries."""
+    Z, ctx, torch = zk
+    orders = [16, 31, 32, 33, 48, 63, 97]
+    mats = [W.random_elements(n, 4300 + n) if n % 2 else W.householder_hermitian(W.spectrum_c4(n), seed=4400 + n)
+            for n in orders]
+    res = Z.heev(ctx, [_dev(torch, [A]) for A in mats], limbs_out=2, opts=_ldl(Z))
+    for n, A, r in zip(orders, mats, res):
+        out = gate([A], r, oracle.heev([A], want_vectors=False).w_limbs, DD_TOL, orth_tol=DD_ORTH)
+        log(f"ldl mixed orders n={n}: {out}")
+
+
+@pytest.mark.parametrize("n,limbs,span", [(16, 1, 20), (64, 2, 60)])
+def test_ldl_hadamard_exact(zk, n, limbs, span):
+    """Exact spectrum with exact degeneracies and two zero eigenvalues."""
+    from fractions import Fraction
+    Z, ctx, torch = zk
+    rng = np.random.Generator(np.random.PCG64(5000 + n))
+    vals = [Fraction(int(rng.integers(1, 2 ** 12)), 2 ** (12 + int(rng.integers(0, span)))) for _ in range(n - 6)]
+    vals += vals[:4] + [Fraction(0)] * 2
+    h = W.hadamard_exact(vals, seed=n, limbs=limbs)
+    res, = Z.heev(ctx, [_dev(torch, h.planes)], limbs_out=2, opts=_ldl(Z))
+    ref = np.zeros((4, n))
+    for k, x in enumerate(h.lam):
+        f = float(x)
+        ref[0, k] = f
+        ref[1, k] = float(x - Fraction(f))
+    out = gate(h.planes, res, ref, DD_TOL, orth_tol=DD_ORTH)
+    log(f"ldl hadamard n={n}: {out}")
+
+
+@pytest.mark.parametrize("k,omega", [(59, 1j), (100, -1)])
+def test_ldl_schmidt_pair(zk, k, omega):
+    from fractions import Fraction
+    Z, ctx, torch = zk
+    planes, (eps, one_minus) = W.schmidt_pair(k, omega, limbs=2)
+    res, = Z.heev(ctx, [_dev(torch, planes)], limbs_out=2, opts=_ldl(Z))
+    w = res.w.cpu().numpy()
+    got = [Fraction(float(w[0, i])) + Fraction(float(w[1, i])) for i in range(2)]
+    assert abs(got[0] - eps) <= Fraction(1, 10 ** 30)
+    assert abs(got[1] - one_minus) <= Fraction(1, 10 ** 30)
+    r, _ = oracle.residuals(planes, w, res.V.cpu().numpy())
+    assert r.max() <= DD_TOL
+
+
+def test_ldl_qd(zk):
+    Z, ctx, torch = zk
+    A = W.householder_hermitian(W.spectrum_c4(24), seed=31)
+    res, = Z.heev(ctx, [_dev(torch, [A])], limbs_out=4, opts=_ldl(Z))
+    gate([A], res, oracle.heev([A], want_vectors=False).w_limbs, QD_TOL, orth_tol=QD_ORTH)
+    B = W.random_elements(45, 4500)
+    res, = Z.heev(ctx, [_dev(torch, [B])], limbs_out=4, opts=_ldl(Z))
+    out = gate([B], res, oracle.heev([B], want_vectors=False).w_limbs, QD_TOL, orth_tol=QD_ORTH)
+    log(f"ldl qd random n=45: {out}")
+
+
+def test_ldl_clustered_1024_against_golden(zk):
+    """The clustered 1024 workload whole under LDL^H: every eigenvalue against
+    the stored oracle values, every vector's MPFR residual, the whole Gram
+    matrix, the device residuals; beside it the LU path's time on the same
+    matrix (logged)."""
+    import golden_io as G
+    Z, ctx, torch = zk
+    A = W.workload(3)["A"]
+    hdr, gold = G.load("c3")
+    assert hdr["sha256"] == G.sha(A)
+    dA = [torch.from_numpy(A).cuda()]
+    times = {}
+    for name, opts in (("lu", _lu(Z)), ("ldl", _ldl(Z))):
+        torch.cuda.synchronize()
+        t0 = time.monotonic()
+        stats = {}
+        res, = Z.heev(ctx, [dA], limbs_out=2, opts=opts, stats=stats)
+        torch.cuda.synchronize()
+        times[name] = time.monotonic() - t0
+        log(f"clustered 1024 {name}: {1e3 * times[name]:.1f} ms, iterations {stats['iters_hist'][:6]}")
+        out = gate([A], res, gold, DD_TOL, orth_tol=DD_ORTH, dev_resid="agree")
+        assert out["checked"] == 1024
+        log(f"clustered 1024 {name}: {out}")
+    log(f"clustered 1024: LU {1e3 * times['lu']:.1f} ms, LDL^H {1e3 * times['ldl']:.1f} ms")
