@@ -212,9 +212,8 @@ static size_t s2vec_bytes(int n, int L)
     return align_up(8 * 2 * (size_t)L * nn) + align_up(8 * (size_t)L * n);
 }
 
-static int lu_ldm(int n) { return (n + 7) & ~7; }
 
-static size_t lu_slot_doubles(int n, int L) { return (size_t)2 * L * lu_ldm(n) * (size_t)(n + 3 + zk::kLuNB); }
+static size_t lu_slot_doubles(int n, int L) { return (size_t)2 * L * zk::lu_plane_of(n); }
 
 extern "C" size_t zk_workspace_bytes(int n, int limbs, int concurrent_pairs)
 {

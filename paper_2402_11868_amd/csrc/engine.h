@@ -46,7 +46,7 @@ struct ResolvedOpts {
 
 inline size_t s2_align(size_t x) { return (x + 255) & ~(size_t)255; }
 inline int s2_lu_ldm(int n) { return (n + 7) & ~7; }
-inline size_t s2_lu_slot_doubles(int n, int L) { return (size_t)2 * L * s2_lu_ldm(n) * (size_t)(n + 3 + kLuNB); }
+inline size_t s2_lu_slot_doubles(int n, int L) { return (size_t)2 * L * lu_plane_of(n); }
 
 // One matrix in the engine.  The caller sets rp (n, limbs_in, hf, w0, V0,
 // ldv0, ldv_out, w_out, v_out, hnorm lower bound), npairs and info.

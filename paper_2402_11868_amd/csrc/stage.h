@@ -177,20 +177,23 @@ int mps_sim_gate1(const MpsSimDesc &D, hipStream_t st);
 
 // ---------------------------------------------------------------- stage 2
 // Workspace of one concurrently factorised pair (shifted factorisation of
-// order n, augmented with the right-hand side as column n; columns n+1 and
-// n+2 are the LDL^H panel's working columns, columns n+3 .. n+3+kLuNB-1 its
-// W = L D of the panel last factorised).
+// order n, augmented with the right-hand side as column n; columns n+1 ..
+// n+5 are the LDL^H panel's working columns (candidate pivot column, the
+// look-ahead window), columns n+6 .. n+5+kLuNB its W = L D of the panel last
+// factorised).
+constexpr int kLdlLA = 4;   // look-ahead window of the LDL^H panel
+__host__ __device__ inline int ldl_wcol(int n) { return n + 2 + kLdlLA; }
 struct LuSlot {
-    double *M;      // 2L planes of ldm x (n+3+kLuNB) doubles
+    double *M;      // 2L planes of ldm x (n+6+kLuNB) doubles
     int *ipiv;      // 2n: interchanges, then the LDL^H panel-start marks
 };
 
 // Stage-2 launch table: `count` active pairs (indices into the pair table).
 // leading dimension of a pair's factorisation planes, and the plane size
-// (ldm x (n+3+kLuNB) doubles: the matrix, the right-hand side, two working
+// (ldm x (n+6+kLuNB) doubles: the matrix, the right-hand side, the working
 // columns, the panel's W)
 __host__ __device__ inline int lu_ldm_of(int n) { return (n + 7) & ~7; }
-__host__ __device__ inline size_t lu_plane_of(int n) { return (size_t)lu_ldm_of(n) * (size_t)(n + 3 + kLuNB); }
+__host__ __device__ inline size_t lu_plane_of(int n) { return (size_t)lu_ldm_of(n) * (size_t)(ldl_wcol(n) + kLuNB); }
 
 struct Stage2Batch {
     int L;                  // 2 (dd) or 4 (qd)

@@ -753,7 +753,7 @@ __global__ void __launch_bounds__(256, 2) k_s2_lu_update_dd(Stage2Batch B, int k
                 const int kk = q >> 6, jj = q & 63;
                 const int gj = j0 + jj;
                 const bool ok = kc + kk < nbw && gj < jend;
-                const size_t o = (size_t)(n + 3 + kc + kk) * ldm + gj;
+                const size_t o = (size_t)(ldl_wcol(n) + kc + kk) * ldm + gj;
                 for (int pl = 0; pl < 4; pl++) pU[pl] = ok ? M[pl * plane + o] : 0.0;
                 pU[2] = -pU[2];
                 pU[3] = -pU[3];
@@ -877,7 +877,7 @@ __global__ void __launch_bounds__(256) k_s2_lu_update_gen(Stage2Batch B, int k0,
             if (LDL) {
                 const int kk = q >> 5, jj = q & 31;
                 sU[kk][jj] = (kc + kk < nbw && j0 + jj < jend)
-                                 ? c_conj<L>(ld_cmp<L>(M, plane, (size_t)(n + 3 + kc + kk) * ldm + j0 + jj))
+                                 ? c_conj<L>(ld_cmp<L>(M, plane, (size_t)(ldl_wcol(n) + kc + kk) * ldm + j0 + jj))
                                  : c_zero<L>();
             } else {
                 const int kk = q & (KC - 1), jj = q / KC;
@@ -957,14 +957,15 @@ __global__ void __launch_bounds__(256) k_s2_backsolve(Stage2Batch B)
 // one work-group factorises a panel of at most kLuNB columns left-looking,
 // then the trailing update A22 -= L21 W21^H (W = L D) covers the lower
 // triangle only, half the multiply-adds of the LU's A22 -= L21 U12.
-// Storage of a pair's slot (n rows; columns 0 .. n+2):
+// Storage of a pair's slot (n rows; columns 0 .. n+5+kLuNB):
 //   lower triangle  A, then L below the diagonal blocks;
 //   diagonal        D (2x2 blocks keep d21 at (k+1, k), where their unit L
 //                   has a structural zero);
 //   column n        right-hand side, forward-substituted as the columns are
 //                   factorised (every row below a new column at once);
-//   columns n+1,n+2 the panel's working columns (w_k, candidate pivot column);
-//   columns n+3 ..  W = L D of the panel last factorised, column-major (its
+//   column n+1      the candidate pivot column when it is outside the window;
+//   n+2 .. n+5      the panel's look-ahead window (Schur-complement columns);
+//   n+6 ..          W = L D of the panel last factorised, column-major (its
 //                   rows r > c for column c), read by the trailing update;
 //   upper triangle  unused (the update's diagonal tiles write there).
 // ipiv[k] >= 0: 1x1 block at k with rows k and ipiv[k] interchanged;
@@ -1013,7 +1014,14 @@ __device__ __forceinline__ void swap_cmp(double *M, size_t plane, size_t a, size
     st_cmp<L>(M, plane, b, x);
 }
 
-// one work-group (256) per pair: the pair's next panel, from column lk0 + lkb
+// one work-group (256) per pair: the pair's next panel, from column lk0 + lkb.
+// Left-looking with a look-ahead window: one pass over the panel's L columns
+// forms the Schur-complement columns of the next kLdlLA columns at once
+// (window vectors, rows [k, n)); each factorised column then updates the
+// window's remaining vectors right-looking, so the panel's L is read about
+// kLdlLA times less often than column by column.  A candidate pivot column
+// inside the window is its window vector; one outside is formed from the
+// stored matrix and the panel's L and W.
 template <int L>
 __global__ void __launch_bounds__(256) k_s2_ldl_panel(Stage2Batch B)
 {
@@ -1033,12 +1041,13 @@ __global__ void __launch_bounds__(256) k_s2_ldl_panel(Stage2Batch B)
     double *M = B.lu_base + (size_t)t * B.lu_stride;
     int *ipiv = B.piv_base + (size_t)t * B.piv_stride;
     const size_t plane = lu_plane_of(n);
-    const size_t bc = (size_t)n * ldm, wc = (size_t)(n + 1) * ldm, xc = (size_t)(n + 2) * ldm;
-    const size_t wb = (size_t)(n + 3) * ldm;   // W column c - k0 at wb + (c - k0) ldm
+    const size_t bc = (size_t)n * ldm, xc = (size_t)(n + 1) * ldm, vc0 = (size_t)(n + 2) * ldm;
+    const size_t wb = (size_t)ldl_wcol(n) * ldm;   // W column c - k0 at wb + (c - k0) ldm
     const int kend = min(k0 + kLuNB, n);
     const int tid = threadIdx.x;
     const double ptol = P.piv_tol;
-    __shared__ cmp<L> s_wt[kLuNB];
+    __shared__ cmp<L> s_wt[kLdlLA][kLuNB];
+    __shared__ cmp<L> s_pj[2][kLdlLA];   // conj W(j, k) (and W(j, k+1)) of the window's later columns
     __shared__ double s_v[4];
     __shared__ int s_i[4];
     __shared__ int s_kstep, s_kp, s_stop;
@@ -1047,53 +1056,83 @@ __global__ void __launch_bounds__(256) k_s2_ldl_panel(Stage2Batch B)
     __shared__ mp<L> s_d11, s_d22, s_idet;
     __shared__ cmp<L> s_y[2];
     int guard = 0, tiny = 0;   // thread 0's counts
+    int wbase = k0, wend = k0;   // the window [wbase, wend); vector of column j at vc0 + (j - wbase) ldm
     int k = k0;
     while (k < kend) {
         const int nk = k - k0;
-        // w_k = column k of the Schur complement, rows [k, n)
-        if (tid < nk) s_wt[tid] = c_conj<L>(ld_cmp<L>(M, plane, wb + (size_t)tid * ldm + k));
-        __syncthreads();
+        if (k >= wend) {
+            // refill: window vectors of columns [k, min(k + kLdlLA, kend)), rows [k, n)
+            wbase = k;
+            wend = min(k + kLdlLA, kend);
+            const int nw = wend - wbase;
+            for (int e = tid; e < nw * nk; e += 256) {
+                const int j = e / nk, c = e - j * nk;
+                s_wt[j][c] = c_conj<L>(ld_cmp<L>(M, plane, wb + (size_t)c * ldm + wbase + j));
+            }
+            __syncthreads();
+            for (int r = k + tid; r < n; r += 256) {
+                CAcc<L> a[kLdlLA];
+#pragma unroll
+                for (int j = 0; j < kLdlLA; j++) {
+                    const int col = wbase + j;
+                    cmp<L> z = c_zero<L>();
+                    if (j < nw)
+                        z = r >= col ? ld_cmp<L>(M, plane, (size_t)col * ldm + r)
+                                     : c_conj<L>(ld_cmp<L>(M, plane, (size_t)r * ldm + col));
+                    a[j].init(z);
+                }
+                for (int c = 0; c < nk; c++) {
+                    const cmp<L> l = ld_cmp<L>(M, plane, (size_t)(k0 + c) * ldm + r);
+#pragma unroll
+                    for (int j = 0; j < kLdlLA; j++)
+                        if (j < nw) a[j].sub_mul(l, s_wt[j][c]);
+                }
+#pragma unroll
+                for (int j = 0; j < kLdlLA; j++)
+                    if (j < nw) st_cmp<L>(M, plane, vc0 + (size_t)j * ldm + r, a[j].get());
+            }
+            __syncthreads();
+        }
+        const size_t vk = vc0 + (size_t)(k - wbase) * ldm;
+        // pivot search in column k
         double best = -1.0;
         int bi = n;
-        for (int r = k + tid; r < n; r += 256) {
-            CAcc<L> a;
-            a.init(ld_cmp<L>(M, plane, (size_t)k * ldm + r));
-            for (int c = 0; c < nk; c++) a.sub_mul(ld_cmp<L>(M, plane, (size_t)(k0 + c) * ldm + r), s_wt[c]);
-            const cmp<L> w = a.get();
-            st_cmp<L>(M, plane, wc + r, w);
-            if (r > k) {
-                const double m = c_mag1(w);
-                if (m > best) {
-                    best = m;
-                    bi = r;
-                }
+        for (int r = k + 1 + tid; r < n; r += 256) {
+            const double m = c_mag1(ld_cmp<L>(M, plane, vk + r));
+            if (m > best) {
+                best = m;
+                bi = r;
             }
         }
         wg_argmax256(best, bi, s_v, s_i);
         const double colmax = fmax(best, 0.0);
         const int imax = bi;
-        const double absakk = fabs(ld_cmp<L>(M, plane, wc + k).re.x[0]);   // written by this thread (r = k)
+        const double absakk = fabs(ld_cmp<L>(M, plane, vk + k).re.x[0]);
         const bool cand = !(colmax < fmax(ptol, 1e-300) || absakk >= kBkAlpha * colmax);
         double rowmax = 0.0, absimax = 0.0;
+        // the candidate's column: its window vector, or formed into column n+1
+        const size_t xv = (cand && imax < wend) ? vc0 + (size_t)(imax - wbase) * ldm : xc;
         if (cand) {
-            // the candidate pivot column imax of the Schur complement, rows [k, n)
-            __syncthreads();
-            if (tid < nk) s_wt[tid] = c_conj<L>(ld_cmp<L>(M, plane, wb + (size_t)tid * ldm + imax));
-            __syncthreads();
+            if (imax >= wend) {
+                __syncthreads();
+                if (tid < nk) s_wt[0][tid] = c_conj<L>(ld_cmp<L>(M, plane, wb + (size_t)tid * ldm + imax));
+                __syncthreads();
+                for (int r = k + tid; r < n; r += 256) {
+                    CAcc<L> a;
+                    a.init(r >= imax ? ld_cmp<L>(M, plane, (size_t)imax * ldm + r)
+                                     : c_conj<L>(ld_cmp<L>(M, plane, (size_t)r * ldm + imax)));
+                    for (int c = 0; c < nk; c++) a.sub_mul(ld_cmp<L>(M, plane, (size_t)(k0 + c) * ldm + r), s_wt[0][c]);
+                    st_cmp<L>(M, plane, xc + r, a.get());
+                }
+                __syncthreads();
+            }
             double rb = 0.0;
             int ri = 0;
-            for (int r = k + tid; r < n; r += 256) {
-                CAcc<L> a;
-                a.init(r >= imax ? ld_cmp<L>(M, plane, (size_t)imax * ldm + r)
-                                 : c_conj<L>(ld_cmp<L>(M, plane, (size_t)r * ldm + imax)));
-                for (int c = 0; c < nk; c++) a.sub_mul(ld_cmp<L>(M, plane, (size_t)(k0 + c) * ldm + r), s_wt[c]);
-                const cmp<L> w = a.get();
-                st_cmp<L>(M, plane, xc + r, w);
-                if (r != imax) rb = fmax(rb, c_mag1(w));
-            }
+            for (int r = k + tid; r < n; r += 256)
+                if (r != imax) rb = fmax(rb, c_mag1(ld_cmp<L>(M, plane, xv + r)));
             wg_argmax256(rb, ri, s_v, s_i);
             rowmax = rb;
-            absimax = fabs(ld_cmp<L>(M, plane, xc + imax).re.x[0]);   // visible after the barriers above
+            absimax = fabs(ld_cmp<L>(M, plane, xv + imax).re.x[0]);
         }
         if (tid == 0) {
             int kstep = 1, kp = k;
@@ -1113,34 +1152,50 @@ __global__ void __launch_bounds__(256) k_s2_ldl_panel(Stage2Batch B)
         const int kstep = s_kstep, kp = s_kp;
         if (s_stop) break;   // the 2x2 block opens the next panel
         const int kk = k + kstep - 1;
+        // the block's pivot columns: v0 = column k, v1 = column k+1 (2x2)
+        const size_t v0 = vk;
+        const size_t v1 = (kstep == 2) ? (k + 1 < wend ? vk + ldm : xc) : vk;
         if (kp != kk) {
-            // symmetric interchange kk <-> kp: the panel's L rows and W rows,
-            // the right-hand side, and the stored part of the matrix (column
-            // kk, about to be overwritten, moves to row / column kp)
+            const bool kp_in = kp < wend;
+            // the panel's L rows and W rows, the right-hand side
             for (int c = tid; c < nk; c += 256) {
                 swap_cmp<L>(M, plane, (size_t)(k0 + c) * ldm + kk, (size_t)(k0 + c) * ldm + kp);
                 swap_cmp<L>(M, plane, wb + (size_t)c * ldm + kk, wb + (size_t)c * ldm + kp);
             }
+            // stored part: column kk moves to row / column kp.  Needed for a
+            // kp inside the window too: a candidate column formed later from
+            // the stored matrix reads the window columns' stored rows
             for (int r = kk + 1 + tid; r < n; r += 256) {
                 if (r < kp) st_cmp<L>(M, plane, (size_t)r * ldm + kp, c_conj<L>(ld_cmp<L>(M, plane, (size_t)kk * ldm + r)));
                 else if (r > kp) st_cmp<L>(M, plane, (size_t)kp * ldm + r, ld_cmp<L>(M, plane, (size_t)kk * ldm + r));
             }
+            // window vectors: column kk takes the candidate's vector, and a
+            // candidate inside the window takes column kk's
+            const size_t vkk = vc0 + (size_t)(kk - wbase) * ldm;
+            if (kk < wend) {
+                if (kp_in) {
+                    const size_t vkp = vc0 + (size_t)(kp - wbase) * ldm;
+                    for (int r = k + tid; r < n; r += 256) swap_cmp<L>(M, plane, vkk + r, vkp + r);
+                } else {
+                    for (int r = k + tid; r < n; r += 256) st_cmp<L>(M, plane, vkk + r, ld_cmp<L>(M, plane, xc + r));
+                }
+            }
             if (tid == 0) {
                 swap_cmp<L>(M, plane, bc + kk, bc + kp);
                 st_cmp<L>(M, plane, (size_t)kp * ldm + kp, ld_cmp<L>(M, plane, (size_t)kk * ldm + kk));
-                if (kstep == 1) {
-                    swap_cmp<L>(M, plane, xc + k, xc + kp);   // the pivot column is the candidate's
-                } else {
-                    swap_cmp<L>(M, plane, wc + kk, wc + kp);
-                    swap_cmp<L>(M, plane, xc + kk, xc + kp);
-                }
             }
             __syncthreads();
+            // rows kk and kp of every live window vector (and of column n+1
+            // when it is the 2x2 block's second column)
+            const int nlive = wend - k;
+            if (tid < nlive) swap_cmp<L>(M, plane, vk + (size_t)tid * ldm + kk, vk + (size_t)tid * ldm + kp);
+            if (tid == nlive && v1 == xc && kstep == 2) swap_cmp<L>(M, plane, xc + kk, xc + kp);
+            __syncthreads();
         }
-        const size_t pc = (kstep == 1 && kp != k) ? xc : wc;   // 1x1 pivot column
+        const int j1 = k + kstep;   // first window column after the block
         if (tid == 0) {
             if (kstep == 1) {
-                mp<L> d = ld_cmp<L>(M, plane, pc + k).re;
+                mp<L> d = ld_cmp<L>(M, plane, v0 + k).re;
                 if (fabs(d.x[0]) < 2048.0 * ptol) tiny++;
                 if (fabs(d.x[0]) < ptol) {
                     d = mp_from<L>(d.x[0] < 0.0 ? -ptol : ptol);
@@ -1154,9 +1209,9 @@ __global__ void __launch_bounds__(256) k_s2_ldl_panel(Stage2Batch B)
                 ipiv[k] = kp;
                 s_y[0] = ld_cmp<L>(M, plane, bc + k);
             } else {
-                const mp<L> d11 = ld_cmp<L>(M, plane, wc + k).re;
-                const mp<L> d22 = ld_cmp<L>(M, plane, xc + k + 1).re;
-                const cmp<L> d21 = ld_cmp<L>(M, plane, wc + k + 1);
+                const mp<L> d11 = ld_cmp<L>(M, plane, v0 + k).re;
+                const mp<L> d22 = ld_cmp<L>(M, plane, v1 + k + 1).re;
+                const cmp<L> d21 = ld_cmp<L>(M, plane, v0 + k + 1);
                 const mp<L> det = sub(mul(d11, d22), c_abs2(d21));
                 s_d11 = d11;
                 s_d22 = d22;
@@ -1180,12 +1235,19 @@ __global__ void __launch_bounds__(256) k_s2_ldl_panel(Stage2Batch B)
             }
             for (int q = 0; q < kstep; q++) ipiv[n + k + q] = (k + q == k0) ? 1 : 0;
         }
+        // W(j, k) (and W(j, k+1)) of the window's later columns j
+        if (tid < wend - j1) {
+            s_pj[0][tid] = c_conj<L>(ld_cmp<L>(M, plane, v0 + j1 + tid));
+            if (kstep == 2) s_pj[1][tid] = c_conj<L>(ld_cmp<L>(M, plane, v1 + j1 + tid));
+        }
         __syncthreads();
+        const int nl = max(0, wend - j1);
+        const size_t vj1 = vc0 + (size_t)(j1 - wbase) * ldm;
         if (kstep == 1) {
             const mp<L> inv = s_inv;
             const cmp<L> y = s_y[0];
-            for (int r = k + 1 + tid; r < n; r += 256) {
-                const cmp<L> w = ld_cmp<L>(M, plane, pc + r);
+            for (int r = j1 + tid; r < n; r += 256) {
+                const cmp<L> w = ld_cmp<L>(M, plane, v0 + r);
                 const cmp<L> l = c_scale(w, inv);
                 st_cmp<L>(M, plane, (size_t)k * ldm + r, l);
                 st_cmp<L>(M, plane, wb + (size_t)nk * ldm + r, w);
@@ -1193,12 +1255,19 @@ __global__ void __launch_bounds__(256) k_s2_ldl_panel(Stage2Batch B)
                 b.init(ld_cmp<L>(M, plane, bc + r));
                 b.sub_mul(l, y);
                 st_cmp<L>(M, plane, bc + r, b.get());
+                for (int j = 0; j < nl; j++) {
+                    const size_t o = vj1 + (size_t)j * ldm + r;
+                    CAcc<L> v;
+                    v.init(ld_cmp<L>(M, plane, o));
+                    v.sub_mul(l, s_pj[0][j]);
+                    st_cmp<L>(M, plane, o, v.get());
+                }
             }
         } else {
             const mp<L> d11 = s_d11, d22 = s_d22, idet = s_idet;
             const cmp<L> d21 = s_d21, y0 = s_y[0], y1 = s_y[1];
-            for (int r = k + 2 + tid; r < n; r += 256) {
-                const cmp<L> a = ld_cmp<L>(M, plane, wc + r), b2 = ld_cmp<L>(M, plane, xc + r);
+            for (int r = j1 + tid; r < n; r += 256) {
+                const cmp<L> a = ld_cmp<L>(M, plane, v0 + r), b2 = ld_cmp<L>(M, plane, v1 + r);
                 // [L(r,k) L(r,k+1)] = [a b2] D^{-1},  D^{-1} = [[d22, -conj d21], [-d21, d11]] / det
                 const cmp<L> l0 = c_scale(c_sub(c_scale(a, d22), c_mul(b2, d21)), idet);
                 const cmp<L> l1 = c_scale(c_sub(c_scale(b2, d11), c_mul(a, c_conj<L>(d21))), idet);
@@ -1211,6 +1280,14 @@ __global__ void __launch_bounds__(256) k_s2_ldl_panel(Stage2Batch B)
                 b.sub_mul(l0, y0);
                 b.sub_mul(l1, y1);
                 st_cmp<L>(M, plane, bc + r, b.get());
+                for (int j = 0; j < nl; j++) {
+                    const size_t o = vj1 + (size_t)j * ldm + r;
+                    CAcc<L> v;
+                    v.init(ld_cmp<L>(M, plane, o));
+                    v.sub_mul(l0, s_pj[0][j]);
+                    v.sub_mul(l1, s_pj[1][j]);
+                    st_cmp<L>(M, plane, o, v.get());
+                }
             }
         }
         k += kstep;
