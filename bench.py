@@ -43,7 +43,7 @@ CPLX_QD_FMA_INSTR = 988
 # traffic of that kernel is reported only while their digest is unchanged
 LU_UPDATE_SOURCES = ["paper_2402_11868_amd/csrc/stage2.hip", "paper_2402_11868_amd/csrc/mp.h",
                      "paper_2402_11868_amd/csrc/common.h", "paper_2402_11868_amd/csrc/stage.h"]
-TRAFFIC_FILE = "profiles/lu_update_herm1024_dd_traffic.txt"
+TRAFFIC_FILE = "profiles/ldl_update_herm1024_dd_traffic.txt"
 
 
 def log(msg):
@@ -60,7 +60,7 @@ def kernel_source_digest():
 
 
 def stored_traffic():
-    """Measured HBM bytes per launch of the LU update (rocprofv3 FETCH_SIZE and
+    """Measured HBM bytes per launch of the trailing update (rocprofv3 FETCH_SIZE and
     WRITE_SIZE, each scaled by its copy-kernel calibration factor), or None
     when the kernel's sources changed after the counters were taken."""
     path = os.path.join(ROOT, TRAFFIC_FILE)
@@ -641,7 +641,7 @@ def main():
     torch.cuda.synchronize()
     # timed region: plain zk_heev_dd calls; the only instrumentation is a
     # pair of HIP events around each launch of the dominant kernel (the
-    # shifted-LU trailing update, about 60 launches per call) for the roofline
+    # trailing update of the shifted factorisations, about 66 launches per call) for the roofline
     ctx.prof_classes(["lu_update"])
     ctx.prof(True)
     ctx.prof_reset()
@@ -709,14 +709,17 @@ def main():
     passing = int(ok.sum())
     value = passing / (ms_per_step / 1e3)
 
-    # roofline of the dominant kernel: the shifted-LU trailing update (FP64 VALU
-    # bound), from the HIP events of the timed region
+    # roofline of the dominant kernel: the trailing update of the shifted
+    # LDL^H factorisations (FP64 VALU bound), from the HIP events of the timed
+    # region; its work is the lower triangle of every trailing block (with the
+    # diagonal) times the panel width, counted for panels of 32 columns (the
+    # factorisation ends a panel one column early before a 2x2 block)
     ms_u, la_u, work_u = prof_u
     achieved = work_u / (ms_u / 1e3) if ms_u > 0 else 0.0             # complex dd multiply-adds per second
     peak = FP64_VALU_LANE_OPS / CPLX_DD_FMA_INSTR
-    roof = {"bound": "alu", "kernel": "k_s2_lu_update_dd", "achieved": achieved / 1e9, "peak": peak / 1e9,
+    roof = {"bound": "alu", "kernel": "k_s2_lu_update_dd<true>", "achieved": achieved / 1e9, "peak": peak / 1e9,
             "unit": "G cplx-dd-FMA/s", "frac": achieved / peak if peak else 0.0, "traffic": stored_traffic(),
-            "avg_launch_ms": ms_u / max(la_u, 1), "launches": la_u,
+            "avg_launch_ms": ms_u / max(la_u, 1), "launches": la_u, "work_per_call": work_u / max(args.steps, 1),
             "peak_basis": f"256 CU x 64 lanes x 2.4 GHz FP64 VALU / {CPLX_DD_FMA_INSTR} instructions per complex dd FMA"}
     ms_h, la_h, fl_h = prof["her2k"]
     ms_v, la_v, by_v = prof["hemv"]

@@ -562,6 +562,7 @@ struct DdGemm {
     double2 *Cz;
     size_t pa, pb, pc;
     int lda, ldb, ldc, M, N, K, pad;
+    size_t pc0;   // plane stride of C0 (0: that of C)
 };
 
 constexpr int kGK = 4;
@@ -698,8 +699,9 @@ __global__ void __launch_bounds__(256, 2) k_ap_ddgemm(const DdGemm *gd)
             two_sum(S[a][b][1], C[a][b][1], ih, il);
             const size_t o = (size_t)j * G.ldc + i;
             if (G.C0) {
-                const dd r = dd_add(dd{{G.C0[o], G.C0[G.pc + o]}}, dd{{rh, rl}});
-                const dd m = dd_add(dd{{G.C0[2 * G.pc + o], G.C0[3 * G.pc + o]}}, dd{{ih, il}});
+                const size_t p0 = G.pc0 ? G.pc0 : G.pc;
+                const dd r = dd_add(dd{{G.C0[o], G.C0[p0 + o]}}, dd{{rh, rl}});
+                const dd m = dd_add(dd{{G.C0[2 * p0 + o], G.C0[3 * p0 + o]}}, dd{{ih, il}});
                 rh = r.x[0];
                 rl = r.x[1];
                 ih = m.x[0];
@@ -715,6 +717,50 @@ __global__ void __launch_bounds__(256, 2) k_ap_ddgemm(const DdGemm *gd)
                 G.Cz[o] = make_double2(rh, ih);
             }
         }
+}
+
+// ------------------------------------------- Lowdin orthonormalisation ----
+// One step X <- X (3 I - X^H X) / 2 = X - X (G - I) / 2 on column windows of
+// double-double limb-planar matrices: G by one dd GEMM, the coefficients in
+// place, X + X C into a packed copy by a second dd GEMM, and the copy back.
+// A window orthonormal to d leaves the step orthonormal to about d^2 (the
+// symmetric, smallest correction of the basis).
+struct LowdinDesc {
+    double *X;     // first column of the window, plane 0
+    double *G;     // 4 planes of m x m
+    double *T;     // 4 planes of n x m
+    size_t px;     // plane stride of X
+    int n, m;
+};
+
+__global__ void __launch_bounds__(256) k_lowdin_coef(const LowdinDesc *d)
+{
+    const LowdinDesc D = d[blockIdx.y];
+    const size_t mm = (size_t)D.m * D.m;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < mm; e += (size_t)gridDim.x * 256) {
+        // C = (I - G) / 2: halving is exact on both limbs
+        double rh = -0.5 * D.G[e], rl = -0.5 * D.G[mm + e];
+        double ih = -0.5 * D.G[2 * mm + e], il = -0.5 * D.G[3 * mm + e];
+        if (e % D.m == e / D.m) {
+            const dd r = dd_add(dd{{rh, rl}}, dd{{0.5, 0.0}});
+            rh = r.x[0];
+            rl = r.x[1];
+            ih = il = 0.0;
+        }
+        D.G[e] = rh;
+        D.G[mm + e] = rl;
+        D.G[2 * mm + e] = ih;
+        D.G[3 * mm + e] = il;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_lowdin_copy(const LowdinDesc *d)
+{
+    const LowdinDesc D = d[blockIdx.y];
+    const size_t nm = (size_t)D.n * D.m;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < nm; e += (size_t)gridDim.x * 256)
+#pragma unroll
+        for (int pl = 0; pl < 4; pl++) D.X[pl * D.px + e] = D.T[pl * nm + e];
 }
 
 // sorted output: w[l][k] = limb l of the eigenvalue of column perm[k], v[l](:, k) likewise
@@ -799,6 +845,81 @@ struct HostProb {
 };
 
 }  // namespace
+
+size_t dd_lowdin_bytes(const std::vector<DdWindow> &w)
+{
+    size_t b = 0;
+    for (const DdWindow &x : w) b += al256(32 * (size_t)x.m * x.m) + al256(32 * (size_t)x.n * x.m);
+    return b + al256(sizeof(LowdinDesc) * w.size()) + 2 * al256(sizeof(DdGemm) * w.size());
+}
+
+int dd_lowdin(const std::vector<DdWindow> &w, int steps, void *scratch, hipStream_t st)
+{
+    const int cnt = (int)w.size();
+    if (cnt == 0) return 0;
+    char *b = (char *)scratch;
+    std::vector<LowdinDesc> ld(cnt);
+    std::vector<DdGemm> g1(cnt), g2(cnt);
+    int max_m = 0, max_n = 0;
+    for (int q = 0; q < cnt; q++) {
+        LowdinDesc &D = ld[q];
+        D.X = w[q].X;
+        D.px = w[q].px;
+        D.n = w[q].n;
+        D.m = w[q].m;
+        D.G = (double *)b;
+        b += al256(32 * (size_t)D.m * D.m);
+        D.T = (double *)b;
+        b += al256(32 * (size_t)D.n * D.m);
+        max_m = std::max(max_m, D.m);
+        max_n = std::max(max_n, D.n);
+        DdGemm &G = g1[q];   // G = X^H X
+        std::memset(&G, 0, sizeof G);
+        G.A = G.B = D.X;
+        G.C = D.G;
+        G.pa = G.pb = D.px;
+        G.pc = (size_t)D.m * D.m;
+        G.lda = G.ldb = D.n;
+        G.ldc = D.m;
+        G.M = G.N = D.m;
+        G.K = D.n;
+        DdGemm &H = g2[q];   // T = X + X C
+        std::memset(&H, 0, sizeof H);
+        H.A = D.X;
+        H.B = D.G;
+        H.C0 = D.X;
+        H.C = D.T;
+        H.pa = D.px;
+        H.pb = (size_t)D.m * D.m;
+        H.pc = (size_t)D.n * D.m;
+        H.pc0 = D.px;
+        H.lda = H.ldc = D.n;
+        H.ldb = D.m;
+        H.M = D.n;
+        H.N = D.m;
+        H.K = D.m;
+    }
+    LowdinDesc *d_ld = (LowdinDesc *)b;
+    b += al256(sizeof(LowdinDesc) * cnt);
+    DdGemm *d_g1 = (DdGemm *)b;
+    b += al256(sizeof(DdGemm) * cnt);
+    DdGemm *d_g2 = (DdGemm *)b;
+    if (hipMemcpyAsync(d_ld, ld.data(), sizeof(LowdinDesc) * cnt, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(d_g1, g1.data(), sizeof(DdGemm) * cnt, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(d_g2, g2.data(), sizeof(DdGemm) * cnt, hipMemcpyHostToDevice, st) != hipSuccess)
+        return -1;
+    const unsigned t1 = cdiv(max_m, 64) * cdiv(max_m, 64), t2 = cdiv(max_n, 64) * cdiv(max_m, 64);
+    const unsigned e1 = std::min<unsigned>(cdiv((size_t)max_m * max_m, 256), 4096u);
+    const unsigned e2 = std::min<unsigned>(cdiv((size_t)max_n * max_m, 256), 4096u);
+    for (int s = 0; s < steps; s++) {
+        hipLaunchKernelGGL((k_ap_ddgemm<true, true, true>), dim3(t1, cnt), dim3(256), 0, st, d_g1);
+        hipLaunchKernelGGL(k_lowdin_coef, dim3(e1, cnt), dim3(256), 0, st, d_ld);
+        hipLaunchKernelGGL((k_ap_ddgemm<false, true, true>), dim3(t2, cnt), dim3(256), 0, st, d_g2);
+        hipLaunchKernelGGL(k_lowdin_copy, dim3(e2, cnt), dim3(256), 0, st, d_ld);
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 
 // All-pairs refinement engine: matrices join with add() (their binary64 stage
 // done), every round() runs one whole-basis iteration for each live matrix

@@ -188,17 +188,27 @@ class Stage2Engine {
         int rc;
         if (live.empty()) return ZK_OK;
         if ((rc = upload(live)) != ZK_OK) return rc;
-        std::map<int, std::vector<int>> by_n;
-        int nact = 0;
+        // A pair's first solve uses the LDL^H factorisation (when selected),
+        // its later solves LU: the pairs that need a second solve are the ones
+        // whose residual sits closest to the tolerance, where LU's smaller
+        // backward error decides (the SVD dilations of random matrices: their
+        // smallest singular values stall at 2e-30 with LDL^H alone)
+        std::map<int, std::vector<int>> by_n, first, later;
+        int nact = 0, nfirst = 0;
         for (size_t pi = 0; pi < live.size(); pi++)
             for (int k = 0; k < live[pi]->npairs; k++)
                 if (live[pi]->pairs[k].status == 0) {
-                    by_n[live[pi]->rp.n].push_back(base[pi] + k);
+                    const int g = base[pi] + k, n = live[pi]->rp.n;
+                    by_n[n].push_back(g);
+                    const bool f = O.ldl && live[pi]->pairs[k].iters == 0;
+                    (f ? first : later)[n].push_back(g);
+                    nfirst += f ? 1 : 0;
                     nact++;
                 }
         if (stats) stats->active_per_iter.push_back(nact);
         if (nact > 0) {
-            if ((rc = solve_pairs(by_n, nact)) != ZK_OK) return rc;
+            if (!first.empty() && (rc = solve_pairs(first, nfirst, true)) != ZK_OK) return rc;
+            if (!later.empty() && (rc = solve_pairs(later, nact - nfirst, false)) != ZK_OK) return rc;
             if ((rc = run_gs(live, false)) != ZK_OK) return rc;
             if ((rc = run_rr(live, false)) != ZK_OK) return rc;
             std::vector<int> all;
@@ -241,6 +251,30 @@ class Stage2Engine {
 
     void *gsbuf = nullptr;
     size_t gsbytes = 0;
+
+    // ensure_gs without recording a failure (the caller has a fallback)
+    bool try_ensure_gs(size_t bytes)
+    {
+        if (bytes <= gsbytes) return true;
+        if (gsbuf) {
+            ctx->dev_free(gsbuf);
+            ctx->extra -= gsbytes;
+            gsbuf = nullptr;
+            gsbytes = 0;
+        }
+        bytes = std::max(bytes, (size_t)1 << 20);
+        if (!ctx->make_room(bytes)) return false;
+        const std::string err = ctx->err;   // a refused allocation is not the call's error
+        if (ctx->dev_alloc(&gsbuf, bytes) != ZK_OK) {
+            gsbuf = nullptr;
+            ctx->err = err;
+            return false;
+        }
+        gsbytes = bytes;
+        ctx->extra += bytes;
+        ctx->note_held();
+        return true;
+    }
 
     int ensure_gs(size_t bytes)
     {
@@ -415,6 +449,11 @@ class Stage2Engine {
             G.max_nconv = std::max(G.max_nconv, c.nconv);
             G.max_n = std::max(G.max_n, set[pi]->rp.n);
         };
+        // double-double windows re-orthogonalised whole (nobody frozen): two
+        // Lowdin steps by dd GEMMs instead of block Gram-Schmidt
+        std::vector<DdWindow> lw;
+        std::vector<std::pair<int, std::vector<int>>> lw_act;   // the same windows for block Gram-Schmidt
+        double lw_cols = 0.0;
         if (global) {
             // The eigenbasis in windows: consecutive pairs whose binary64
             // eigenvalues are closer than kReorthWindow * ||H|| share a window.
@@ -442,7 +481,18 @@ class Stage2Engine {
                             else
                                 fro.push_back(k);
                         }
-                        if (!act.empty()) add(pi, fro, act);
+                        if (L == 2 && fro.empty()) {
+                            DdWindow x;
+                            x.X = p->rp.vec + (size_t)g0 * p->rp.n;
+                            x.px = (size_t)p->rp.n * p->rp.n;
+                            x.n = p->rp.n;
+                            x.m = e - g0;
+                            lw.push_back(x);
+                            lw_act.emplace_back(pi, act);
+                            lw_cols += x.m;
+                        } else if (!act.empty()) {
+                            add(pi, fro, act);
+                        }
                     }
                     g0 = e;
                 }
@@ -459,6 +509,18 @@ class Stage2Engine {
                     add((int)pi, fro, act);
                 }
             }
+        }
+        if (!lw.empty() && !try_ensure_gs(dd_lowdin_bytes(lw))) {
+            // the GEMMs' workspace does not fit: block Gram-Schmidt instead
+            for (const auto &wa : lw_act) add(wa.first, std::vector<int>(), wa.second);
+            lw.clear();
+        }
+        if (!lw.empty()) {
+            KernelTimer *tm = ctx->tp();
+            const int id = tm ? tm->begin(KC_REORTH, lw_cols, st) : -1;
+            if (dd_lowdin(lw, 2, gsbuf, st)) return ctx->fail(ZK_EDEVICE, "re-orthogonalisation launch failed");
+            if (tm) tm->end(id, st);
+            HIPCHK_(hipStreamSynchronize(st));
         }
         if (cls.empty()) return ZK_OK;
         // plan storage sized from the plan itself: clusters, column lists,
@@ -496,7 +558,7 @@ class Stage2Engine {
     // shifted solves of the given pairs (pair-table indices grouped by order):
     // every order in the same launches, largest orders first, in chunks of
     // as many pairs as there are LU slots; one host synchronisation at the end
-    int solve_pairs(const std::map<int, std::vector<int>> &by_n, int nact)
+    int solve_pairs(const std::map<int, std::vector<int>> &by_n, int nact, bool ldl)
     {
         int max_n = 0;
         for (auto &kv : by_n) max_n = std::max(max_n, kv.first);
@@ -510,6 +572,7 @@ class Stage2Engine {
             }
         HIPCHK_(hipMemcpyAsync(d_active, lst.data(), 4 * lst.size(), hipMemcpyHostToDevice, st));
         Stage2Batch B = batch_base();
+        B.ldl = ldl ? 1 : 0;
         for (size_t c0 = 0; c0 < lst.size(); c0 += (size_t)S) {
             const int cnt = (int)std::min<size_t>((size_t)S, lst.size() - c0);
             const int n = ord[c0];
@@ -558,7 +621,7 @@ class Stage2Engine {
             HIPCHK_(hipMemcpyAsync(p->rp.sigma, sig.data(), 8 * sig.size(), hipMemcpyHostToDevice, st));
             HIPCHK_(hipStreamSynchronize(st));
         }
-        int rc = solve_pairs(by_n, cnt);
+        int rc = solve_pairs(by_n, cnt, false);
         if (rc != ZK_OK) return rc;
         for (size_t pi = 0; pi < set.size(); pi++)
             for (int k = 0; k < set[pi]->npairs; k++)

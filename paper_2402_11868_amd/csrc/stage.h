@@ -5,10 +5,9 @@
 
 #include <algorithm>
 #include <cstddef>
+#include <vector>
 
 #include "common.h"
-
-#include <vector>
 
 namespace zk {
 
@@ -262,6 +261,17 @@ struct PrrDesc {
 template <int L> int stage2_prr_project(const PrrDesc *d, int nd, int max_size, int max_n, RqiProb *probs, hipStream_t st);
 // V <- V Q for every descriptor
 template <int L> int stage2_prr_rotate(const PrrDesc *d, int nd, int max_size, int max_n, RqiProb *probs, hipStream_t st);
+// Lowdin orthonormalisation of column windows of double-double limb-planar
+// matrices (planes re_hi, re_lo, im_hi, im_lo, px apart; columns of n rows
+// consecutive): `steps` steps X <- X - X (X^H X - I) / 2 by dd GEMMs;
+// scratch of dd_lowdin_bytes(windows) bytes
+struct DdWindow {
+    double *X;    // first column of the window, plane 0
+    size_t px;    // plane stride
+    int n, m;     // rows, columns
+};
+size_t dd_lowdin_bytes(const std::vector<DdWindow> &w);
+int dd_lowdin(const std::vector<DdWindow> &w, int steps, void *scratch, hipStream_t st);
 template <int L> int stage2_rq(const Stage2Batch &B, hipStream_t st);
 // orders: the pairs' matrix orders (host, count entries, non-increasing);
 // B.n = orders[0] sets the grid extents, the LU slots are B.lu_stride apart

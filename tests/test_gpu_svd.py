@@ -119,10 +119,13 @@ def test_svd_errors(zk):
 
 
 @pytest.mark.parametrize("m,n,span,refine", [(512, 384, 60, 0), (512, 384, 60, 1), (384, 512, 60, 0), (384, 512, 60, 1),
-                                               (448, 448, 40, 0), (448, 448, 40, 1)])
+                                               (448, 448, 40, 0), (448, 448, 40, 1), (256, 256, 0, 0), (256, 256, 0, 1)])
 def test_svd_large(zk, m, n, span, refine):
     """Shapes whose dilations (order 896) span many tiles of every kernel,
-    column scales graded over 2^0 .. 2^-span, under both refinements.  The
+    column scales graded over 2^0 .. 2^-span, under both refinements (span 0:
+    an ungraded square matrix, the two-site matrix of an MPS update with
+    random tensors, whose smallest singular values put the per-pair
+    iteration's residuals closest to the tolerance).  The
     tall and wide shapes put |m - n| = 128 exact zeros and the tiny singular
     values into one cluster of several hundred members (for the per-pair
     iteration: the degenerate eigenvalue takes the offset shift).  Checked on
