@@ -67,7 +67,8 @@ enum {
     ZK_PAIR_CONVERGED = 1,   /* residual <= tol * ||H||_2 */
     ZK_PAIR_REORTH = 2,      /* Gram-Schmidt against cluster members was applied */
     ZK_PAIR_PIVOT_GUARD = 4, /* a zero pivot was replaced in some shifted LU */
-    ZK_PAIR_NAN = 8
+    ZK_PAIR_NAN = 8,
+    ZK_PAIR_LU_SOLVES = 16   /* the residual stalled with LDL^H solves; the later solves used LU */
 };
 
 /* A Hermitian input.  plane[0..limbs-1] are device pointers to n x n

@@ -188,11 +188,11 @@ class Stage2Engine {
         int rc;
         if (live.empty()) return ZK_OK;
         if ((rc = upload(live)) != ZK_OK) return rc;
-        // A pair's first solve uses the LDL^H factorisation (when selected),
-        // its later solves LU: the pairs that need a second solve are the ones
-        // whose residual sits closest to the tolerance, where LU's smaller
-        // backward error decides (the SVD dilations of random matrices: their
-        // smallest singular values stall at 2e-30 with LDL^H alone)
+        // Solves use the LDL^H factorisation (when selected) until a pair's
+        // residual stalls near the tolerance (flag 16, set by the Rayleigh
+        // quotient step), then LU, whose smaller backward error decides there
+        // (the SVD dilations of random matrices: some of their smallest
+        // singular values stall at 2e-30 with LDL^H alone)
         std::map<int, std::vector<int>> by_n, first, later;
         int nact = 0, nfirst = 0;
         for (size_t pi = 0; pi < live.size(); pi++)
@@ -200,7 +200,7 @@ class Stage2Engine {
                 if (live[pi]->pairs[k].status == 0) {
                     const int g = base[pi] + k, n = live[pi]->rp.n;
                     by_n[n].push_back(g);
-                    const bool f = O.ldl && live[pi]->pairs[k].iters == 0;
+                    const bool f = O.ldl && !(live[pi]->pairs[k].flags & 16);
                     (f ? first : later)[n].push_back(g);
                     nfirst += f ? 1 : 0;
                     nact++;

@@ -255,7 +255,7 @@ constexpr int kRqRows = 4;   // rows per thread whose cascaded sums k_s2_rq keep
 // One work-group per active pair: y = H v, sigma = Re(v^H y), r = y - sigma v;
 // convergence, stagnation and iteration-limit decisions.
 template <int L>
-__global__ void __launch_bounds__(256) k_s2_rq(PairDesc *pairs, RqiProb *probs, const int *active, int final_pass)
+__global__ void __launch_bounds__(256) k_s2_rq(PairDesc *pairs, RqiProb *probs, const int *active, int final_pass, int ldl)
 {
     PairDesc &Q = pairs[active[blockIdx.x]];
     const RqiProb &P = probs[Q.prob];
@@ -391,8 +391,11 @@ __global__ void __launch_bounds__(256) k_s2_rq(PairDesc *pairs, RqiProb *probs, 
             // that the re-orthogonalisation left above the tolerance is
             // polished).  Far above it a pair keeps iterating (up to
             // max_iter): inside a long chain its Gram-Schmidt partners still
-            // move
-            Q.status = 2;
+            // move.  A pair whose LDL^H solves stalled above the tolerance
+            // gets LU solves first (ZK_PAIR_LU_SOLVES): Bunch-Kaufman's
+            // backward error, a few times LU's, can hold a residual just above
+            if (ldl && !(Q.flags & 16) && res * P.hnorm > P.tol_abs) Q.flags |= 16;
+            else Q.status = 2;
         }
     }
 }
@@ -979,9 +982,10 @@ __global__ void __launch_bounds__(256) k_s2_backsolve(Stage2Batch B)
 constexpr int kIpiv2nd = -2147483647 - 1;
 constexpr double kBkAlpha = 0.64038820320220756872767623199676;   // (1 + sqrt 17) / 8
 
-// work-group arg-max over 256 threads (largest value, smallest index on
+// work-group arg-max over NT threads (largest value, smallest index on
 // ties); every thread returns the result
-__device__ __forceinline__ void wg_argmax256(double &v, int &i, double *sv, int *si)
+template <int NT>
+__device__ __forceinline__ void wg_argmax(double &v, int &i, double *sv, int *si)
 {
     for (int off = 32; off > 0; off >>= 1) {
         const double ov = __shfl_xor(v, off, 64);
@@ -991,6 +995,7 @@ __device__ __forceinline__ void wg_argmax256(double &v, int &i, double *sv, int 
             i = oi;
         }
     }
+    if (NT == 64) return;
     __syncthreads();
     if ((threadIdx.x & 63) == 0) {
         sv[threadIdx.x >> 6] = v;
@@ -999,7 +1004,7 @@ __device__ __forceinline__ void wg_argmax256(double &v, int &i, double *sv, int 
     __syncthreads();
     v = sv[0];
     i = si[0];
-    for (int q = 1; q < 4; q++)
+    for (int q = 1; q < NT / 64; q++)
         if (sv[q] > v || (sv[q] == v && si[q] < i)) {
             v = sv[q];
             i = si[q];
@@ -1014,7 +1019,8 @@ __device__ __forceinline__ void swap_cmp(double *M, size_t plane, size_t a, size
     st_cmp<L>(M, plane, b, x);
 }
 
-// one work-group (256) per pair: the pair's next panel, from column lk0 + lkb.
+// one work-group (NT threads: 256, or one wave for small orders) per pair:
+// the pair's next panel, from column lk0 + lkb.
 // Left-looking with a look-ahead window: one pass over the panel's L columns
 // forms the Schur-complement columns of the next kLdlLA columns at once
 // (window vectors, rows [k, n)); each factorised column then updates the
@@ -1022,8 +1028,8 @@ __device__ __forceinline__ void swap_cmp(double *M, size_t plane, size_t a, size
 // kLdlLA times less often than column by column.  A candidate pivot column
 // inside the window is its window vector; one outside is formed from the
 // stored matrix and the panel's L and W.
-template <int L>
-__global__ void __launch_bounds__(256) k_s2_ldl_panel(Stage2Batch B)
+template <int L, int NT>
+__global__ void __launch_bounds__(NT) k_s2_ldl_panel(Stage2Batch B)
 {
     const int t = blockIdx.x;
     PairDesc &Q = B.dev_pairs[B.dev_active[t]];
@@ -1065,12 +1071,12 @@ __global__ void __launch_bounds__(256) k_s2_ldl_panel(Stage2Batch B)
             wbase = k;
             wend = min(k + kLdlLA, kend);
             const int nw = wend - wbase;
-            for (int e = tid; e < nw * nk; e += 256) {
+            for (int e = tid; e < nw * nk; e += NT) {
                 const int j = e / nk, c = e - j * nk;
                 s_wt[j][c] = c_conj<L>(ld_cmp<L>(M, plane, wb + (size_t)c * ldm + wbase + j));
             }
             __syncthreads();
-            for (int r = k + tid; r < n; r += 256) {
+            for (int r = k + tid; r < n; r += NT) {
                 CAcc<L> a[kLdlLA];
 #pragma unroll
                 for (int j = 0; j < kLdlLA; j++) {
@@ -1097,14 +1103,14 @@ __global__ void __launch_bounds__(256) k_s2_ldl_panel(Stage2Batch B)
         // pivot search in column k
         double best = -1.0;
         int bi = n;
-        for (int r = k + 1 + tid; r < n; r += 256) {
+        for (int r = k + 1 + tid; r < n; r += NT) {
             const double m = c_mag1(ld_cmp<L>(M, plane, vk + r));
             if (m > best) {
                 best = m;
                 bi = r;
             }
         }
-        wg_argmax256(best, bi, s_v, s_i);
+        wg_argmax<NT>(best, bi, s_v, s_i);
         const double colmax = fmax(best, 0.0);
         const int imax = bi;
         const double absakk = fabs(ld_cmp<L>(M, plane, vk + k).re.x[0]);
@@ -1117,7 +1123,7 @@ __global__ void __launch_bounds__(256) k_s2_ldl_panel(Stage2Batch B)
                 __syncthreads();
                 if (tid < nk) s_wt[0][tid] = c_conj<L>(ld_cmp<L>(M, plane, wb + (size_t)tid * ldm + imax));
                 __syncthreads();
-                for (int r = k + tid; r < n; r += 256) {
+                for (int r = k + tid; r < n; r += NT) {
                     CAcc<L> a;
                     a.init(r >= imax ? ld_cmp<L>(M, plane, (size_t)imax * ldm + r)
                                      : c_conj<L>(ld_cmp<L>(M, plane, (size_t)r * ldm + imax)));
@@ -1128,9 +1134,9 @@ __global__ void __launch_bounds__(256) k_s2_ldl_panel(Stage2Batch B)
             }
             double rb = 0.0;
             int ri = 0;
-            for (int r = k + tid; r < n; r += 256)
+            for (int r = k + tid; r < n; r += NT)
                 if (r != imax) rb = fmax(rb, c_mag1(ld_cmp<L>(M, plane, xv + r)));
-            wg_argmax256(rb, ri, s_v, s_i);
+            wg_argmax<NT>(rb, ri, s_v, s_i);
             rowmax = rb;
             absimax = fabs(ld_cmp<L>(M, plane, xv + imax).re.x[0]);
         }
@@ -1158,14 +1164,14 @@ __global__ void __launch_bounds__(256) k_s2_ldl_panel(Stage2Batch B)
         if (kp != kk) {
             const bool kp_in = kp < wend;
             // the panel's L rows and W rows, the right-hand side
-            for (int c = tid; c < nk; c += 256) {
+            for (int c = tid; c < nk; c += NT) {
                 swap_cmp<L>(M, plane, (size_t)(k0 + c) * ldm + kk, (size_t)(k0 + c) * ldm + kp);
                 swap_cmp<L>(M, plane, wb + (size_t)c * ldm + kk, wb + (size_t)c * ldm + kp);
             }
             // stored part: column kk moves to row / column kp.  Needed for a
             // kp inside the window too: a candidate column formed later from
             // the stored matrix reads the window columns' stored rows
-            for (int r = kk + 1 + tid; r < n; r += 256) {
+            for (int r = kk + 1 + tid; r < n; r += NT) {
                 if (r < kp) st_cmp<L>(M, plane, (size_t)r * ldm + kp, c_conj<L>(ld_cmp<L>(M, plane, (size_t)kk * ldm + r)));
                 else if (r > kp) st_cmp<L>(M, plane, (size_t)kp * ldm + r, ld_cmp<L>(M, plane, (size_t)kk * ldm + r));
             }
@@ -1175,9 +1181,9 @@ __global__ void __launch_bounds__(256) k_s2_ldl_panel(Stage2Batch B)
             if (kk < wend) {
                 if (kp_in) {
                     const size_t vkp = vc0 + (size_t)(kp - wbase) * ldm;
-                    for (int r = k + tid; r < n; r += 256) swap_cmp<L>(M, plane, vkk + r, vkp + r);
+                    for (int r = k + tid; r < n; r += NT) swap_cmp<L>(M, plane, vkk + r, vkp + r);
                 } else {
-                    for (int r = k + tid; r < n; r += 256) st_cmp<L>(M, plane, vkk + r, ld_cmp<L>(M, plane, xc + r));
+                    for (int r = k + tid; r < n; r += NT) st_cmp<L>(M, plane, vkk + r, ld_cmp<L>(M, plane, xc + r));
                 }
             }
             if (tid == 0) {
@@ -1246,7 +1252,7 @@ __global__ void __launch_bounds__(256) k_s2_ldl_panel(Stage2Batch B)
         if (kstep == 1) {
             const mp<L> inv = s_inv;
             const cmp<L> y = s_y[0];
-            for (int r = j1 + tid; r < n; r += 256) {
+            for (int r = j1 + tid; r < n; r += NT) {
                 const cmp<L> w = ld_cmp<L>(M, plane, v0 + r);
                 const cmp<L> l = c_scale(w, inv);
                 st_cmp<L>(M, plane, (size_t)k * ldm + r, l);
@@ -1266,7 +1272,7 @@ __global__ void __launch_bounds__(256) k_s2_ldl_panel(Stage2Batch B)
         } else {
             const mp<L> d11 = s_d11, d22 = s_d22, idet = s_idet;
             const cmp<L> d21 = s_d21, y0 = s_y[0], y1 = s_y[1];
-            for (int r = j1 + tid; r < n; r += 256) {
+            for (int r = j1 + tid; r < n; r += NT) {
                 const cmp<L> a = ld_cmp<L>(M, plane, v0 + r), b2 = ld_cmp<L>(M, plane, v1 + r);
                 // [L(r,k) L(r,k+1)] = [a b2] D^{-1},  D^{-1} = [[d22, -conj d21], [-d21, d11]] / det
                 const cmp<L> l0 = c_scale(c_sub(c_scale(a, d22), c_mul(b2, d21)), idet);
@@ -1301,10 +1307,397 @@ __global__ void __launch_bounds__(256) k_s2_ldl_panel(Stage2Batch B)
     }
 }
 
-// work-group sum of a complex multi-limb value over 256 threads (thread 0
+// Register-resident form of k_s2_ldl_panel (double-double, n - k0 <= NT R):
+// the look-ahead window lives in registers.  Row r of the window is held by
+// thread (r - wbase) % NT in slot (r - wbase) / NT, and after every block the
+// window is shifted so that the current column is always vector 0: its
+// right-looking updates, whole-column swaps and the pivot-column reads then
+// touch no memory, and single elements (the pivot, interchanged rows, the
+// window's W entries) pass through LDS.  Same steps and results as the
+// memory form.
+template <int NT, int R>
+__global__ void __launch_bounds__(NT) k_s2_ldl_panel_reg(Stage2Batch B)
+{
+    constexpr int L = 2;
+    const int t = blockIdx.x;
+    PairDesc &Q = B.dev_pairs[B.dev_active[t]];
+    const RqiProb &P = B.dev_probs[Q.prob];
+    const int n = P.n, ldm = lu_ldm_of(n);
+    const int k0 = Q.lk0 + Q.lkb;
+    __syncthreads();   // every thread has read the panel state before it changes
+    if (k0 >= n) {
+        if (threadIdx.x == 0) {
+            Q.lk0 = n;
+            Q.lkb = 0;
+        }
+        return;
+    }
+    double *M = B.lu_base + (size_t)t * B.lu_stride;
+    int *ipiv = B.piv_base + (size_t)t * B.piv_stride;
+    const size_t plane = lu_plane_of(n);
+    const size_t bc = (size_t)n * ldm, xc = (size_t)(n + 1) * ldm;
+    const size_t wb = (size_t)ldl_wcol(n) * ldm;   // W column c - k0 at wb + (c - k0) ldm
+    const int kend = min(k0 + kLuNB, n);
+    const int tid = threadIdx.x;
+    const double ptol = P.piv_tol;
+    __shared__ cmp<L> s_wt[kLdlLA][kLuNB];
+    __shared__ cmp<L> s_pj[2][kLdlLA];
+    __shared__ cmp<L> s_ex[2][kLdlLA];   // rows kk and kp of the live window vectors
+    __shared__ cmp<L> s_el[4];           // V0(k), V0(k+1), V1(k+1), candidate(imax)
+    __shared__ double s_v[4];
+    __shared__ int s_i[4];
+    __shared__ int s_kstep, s_kp, s_stop;
+    __shared__ mp<L> s_inv;
+    __shared__ cmp<L> s_d21;
+    __shared__ mp<L> s_d11, s_d22, s_idet;
+    __shared__ cmp<L> s_y[2];
+    int guard = 0, tiny = 0;   // thread 0's counts
+    cmp<L> V[kLdlLA][R];
+#pragma unroll
+    for (int j = 0; j < kLdlLA; j++)
+#pragma unroll
+        for (int q = 0; q < R; q++) V[j][q] = c_zero<L>();
+    int wbase = k0, wend = k0;
+    // element (window vector j, slot q) with run-time j and q, for the owner thread
+    auto vget = [&](int j, int q) {
+        cmp<L> x = c_zero<L>();
+#pragma unroll
+        for (int jj = 0; jj < kLdlLA; jj++)
+#pragma unroll
+            for (int qq = 0; qq < R; qq++)
+                if (jj == j && qq == q) x = V[jj][qq];
+        return x;
+    };
+    auto vput = [&](int j, int q, const cmp<L> &x) {
+#pragma unroll
+        for (int jj = 0; jj < kLdlLA; jj++)
+#pragma unroll
+            for (int qq = 0; qq < R; qq++)
+                if (jj == j && qq == q) V[jj][qq] = x;
+    };
+    int k = k0;
+    while (k < kend) {
+        const int nk = k - k0;
+        if (k >= wend) {
+            // refill: window vectors of columns [k, min(k + kLdlLA, kend)), rows [k, n)
+            wbase = k;
+            wend = min(k + kLdlLA, kend);
+            const int nw = wend - wbase;
+            for (int e = tid; e < nw * nk; e += NT) {
+                const int j = e / nk, c = e - j * nk;
+                s_wt[j][c] = c_conj<L>(ld_cmp<L>(M, plane, wb + (size_t)c * ldm + wbase + j));
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < R; q++) {
+                const int r = wbase + tid + NT * q;
+                CAcc<L> a[kLdlLA];
+#pragma unroll
+                for (int j = 0; j < kLdlLA; j++) {
+                    const int col = wbase + j;
+                    cmp<L> z = c_zero<L>();
+                    if (r < n && j < nw)
+                        z = r >= col ? ld_cmp<L>(M, plane, (size_t)col * ldm + r)
+                                     : c_conj<L>(ld_cmp<L>(M, plane, (size_t)r * ldm + col));
+                    a[j].init(z);
+                }
+                if (r < n)
+                    for (int c = 0; c < nk; c++) {
+                        const cmp<L> l = ld_cmp<L>(M, plane, (size_t)(k0 + c) * ldm + r);
+#pragma unroll
+                        for (int j = 0; j < kLdlLA; j++)
+                            if (j < nw) a[j].sub_mul(l, s_wt[j][c]);
+                    }
+#pragma unroll
+                for (int j = 0; j < kLdlLA; j++) V[j][q] = a[j].get();
+            }
+            __syncthreads();
+        }
+        const int live = wend - k;
+        // pivot search in column k (vector 0)
+        double best = -1.0;
+        int bi = n;
+#pragma unroll
+        for (int q = 0; q < R; q++) {
+            const int r = wbase + tid + NT * q;
+            if (r > k && r < n) {
+                const double m = c_mag1(V[0][q]);
+                if (m > best) {
+                    best = m;
+                    bi = r;
+                }
+            }
+        }
+        if ((k - wbase) % NT == tid) s_el[0] = vget(0, (k - wbase) / NT);
+        wg_argmax<NT>(best, bi, s_v, s_i);
+        __syncthreads();
+        const double colmax = fmax(best, 0.0);
+        const int imax = bi;
+        const double absakk = fabs(s_el[0].re.x[0]);
+        const bool cand = !(colmax < fmax(ptol, 1e-300) || absakk >= kBkAlpha * colmax);
+        const int jx = (cand && imax < wend) ? imax - k : -1;   // candidate in the window: vector jx
+        double rowmax = 0.0, absimax = 0.0;
+        if (cand) {
+            if (jx < 0) {
+                // the candidate column, formed into column n+1 from the stored matrix
+                if (tid < nk) s_wt[0][tid] = c_conj<L>(ld_cmp<L>(M, plane, wb + (size_t)tid * ldm + imax));
+                __syncthreads();
+                for (int r = k + tid; r < n; r += NT) {
+                    CAcc<L> a;
+                    a.init(r >= imax ? ld_cmp<L>(M, plane, (size_t)imax * ldm + r)
+                                     : c_conj<L>(ld_cmp<L>(M, plane, (size_t)r * ldm + imax)));
+                    for (int c = 0; c < nk; c++) a.sub_mul(ld_cmp<L>(M, plane, (size_t)(k0 + c) * ldm + r), s_wt[0][c]);
+                    st_cmp<L>(M, plane, xc + r, a.get());
+                }
+                __syncthreads();
+            }
+            double rb = 0.0;
+            int ri = 0;
+#pragma unroll
+            for (int q = 0; q < R; q++) {
+                const int r = wbase + tid + NT * q;
+                if (r >= k && r < n && r != imax) {
+                    cmp<L> x;
+                    if (jx >= 0) {
+                        x = c_zero<L>();
+#pragma unroll
+                        for (int jj = 1; jj < kLdlLA; jj++)
+                            if (jj == jx) x = V[jj][q];
+                    } else {
+                        x = ld_cmp<L>(M, plane, xc + r);
+                    }
+                    rb = fmax(rb, c_mag1(x));
+                }
+            }
+            if (jx >= 0 && (imax - wbase) % NT == tid) s_el[3] = vget(jx, (imax - wbase) / NT);
+            if (jx < 0 && tid == 0) s_el[3] = ld_cmp<L>(M, plane, xc + imax);
+            wg_argmax<NT>(rb, ri, s_v, s_i);
+            __syncthreads();
+            rowmax = rb;
+            absimax = fabs(s_el[3].re.x[0]);
+        }
+        if (tid == 0) {
+            int kstep = 1, kp = k;
+            if (cand) {
+                if (absakk >= kBkAlpha * colmax * (colmax / rowmax)) kp = k;
+                else if (absimax >= kBkAlpha * rowmax) kp = imax;
+                else {
+                    kstep = 2;
+                    kp = imax;
+                }
+            }
+            s_kstep = kstep;
+            s_kp = kp;
+            s_stop = (kstep == 2 && k + 1 >= kend) ? 1 : 0;
+        }
+        __syncthreads();
+        const int kstep = s_kstep, kp = s_kp;
+        if (s_stop) break;   // the 2x2 block opens the next panel
+        const int kk = k + kstep - 1;
+        const bool v1_in = k + 1 < wend;   // the 2x2 block's second column is window vector 1 (else column n+1)
+        if (kp != kk) {
+            const bool kp_in = kp < wend;
+            // the panel's L rows and W rows; the stored part: column kk moves to
+            // row / column kp (also for kp inside the window: a candidate formed
+            // later from the stored matrix reads the window columns' stored rows)
+            for (int c = tid; c < nk; c += NT) {
+                swap_cmp<L>(M, plane, (size_t)(k0 + c) * ldm + kk, (size_t)(k0 + c) * ldm + kp);
+                swap_cmp<L>(M, plane, wb + (size_t)c * ldm + kk, wb + (size_t)c * ldm + kp);
+            }
+            for (int r = kk + 1 + tid; r < n; r += NT) {
+                if (r < kp) st_cmp<L>(M, plane, (size_t)r * ldm + kp, c_conj<L>(ld_cmp<L>(M, plane, (size_t)kk * ldm + r)));
+                else if (r > kp) st_cmp<L>(M, plane, (size_t)kp * ldm + r, ld_cmp<L>(M, plane, (size_t)kk * ldm + r));
+            }
+            if (tid == 0) {
+                swap_cmp<L>(M, plane, bc + kk, bc + kp);
+                st_cmp<L>(M, plane, (size_t)kp * ldm + kp, ld_cmp<L>(M, plane, (size_t)kk * ldm + kk));
+            }
+            // window vectors: column kk takes the candidate's vector, and a
+            // candidate inside the window takes column kk's
+            const int jkk = kk - k;
+            if (kk < wend) {
+                if (kp_in) {
+                    const int jp = kp - k;
+#pragma unroll
+                    for (int a = 0; a < 2; a++)
+#pragma unroll
+                        for (int b = 1; b < kLdlLA; b++)
+                            if (a == jkk && b == jp && a < b)
+#pragma unroll
+                                for (int q = 0; q < R; q++) {
+                                    const cmp<L> x = V[a][q];
+                                    V[a][q] = V[b][q];
+                                    V[b][q] = x;
+                                }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < R; q++) {
+                        const int r = wbase + tid + NT * q;
+                        if (r >= k && r < n) {
+                            const cmp<L> x = ld_cmp<L>(M, plane, xc + r);
+                            if (jkk == 0) V[0][q] = x;
+                            else V[1][q] = x;
+                        }
+                    }
+                }
+            }
+            // rows kk and kp of every live window vector, through LDS
+            const int okk = (kk - wbase) % NT, skk = (kk - wbase) / NT;
+            const int okp = (kp - wbase) % NT, skp = (kp - wbase) / NT;
+            if (tid == okk)
+                for (int j = 0; j < live; j++) s_ex[0][j] = vget(j, skk);
+            if (tid == okp)
+                for (int j = 0; j < live; j++) s_ex[1][j] = vget(j, skp);
+            __syncthreads();
+            if (tid == okk)
+                for (int j = 0; j < live; j++) vput(j, skk, s_ex[1][j]);
+            if (tid == okp)
+                for (int j = 0; j < live; j++) vput(j, skp, s_ex[0][j]);
+            if (tid == 0 && kstep == 2 && !v1_in) swap_cmp<L>(M, plane, xc + kk, xc + kp);
+            __syncthreads();
+        }
+        const int j1 = k + kstep;   // first window column after the block
+        // the pivot block's entries and W(j, k) (, W(j, k+1)) of the window's later columns
+        if ((k - wbase) % NT == tid) s_el[0] = vget(0, (k - wbase) / NT);
+        if (kstep == 2) {
+            if ((k + 1 - wbase) % NT == tid) {
+                s_el[1] = vget(0, (k + 1 - wbase) / NT);
+                if (v1_in) s_el[2] = vget(1, (k + 1 - wbase) / NT);
+            }
+            if (!v1_in && tid == 0) s_el[2] = ld_cmp<L>(M, plane, xc + k + 1);
+        }
+        for (int j = kstep; j < live; j++) {
+            const int r = k + j;
+            if ((r - wbase) % NT == tid) {
+                s_pj[0][j - kstep] = c_conj<L>(vget(0, (r - wbase) / NT));
+                if (kstep == 2) s_pj[1][j - kstep] = c_conj<L>(vget(1, (r - wbase) / NT));
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            if (kstep == 1) {
+                mp<L> d = s_el[0].re;
+                if (fabs(d.x[0]) < 2048.0 * ptol) tiny++;
+                if (fabs(d.x[0]) < ptol) {
+                    d = mp_from<L>(d.x[0] < 0.0 ? -ptol : ptol);
+                    guard = 1;
+                }
+                s_inv = div(mp_from<L>(1.0), d);
+                cmp<L> dz;
+                dz.re = d;
+                dz.im = mp_zero<L>();
+                st_cmp<L>(M, plane, (size_t)k * ldm + k, dz);
+                ipiv[k] = kp;
+                s_y[0] = ld_cmp<L>(M, plane, bc + k);
+            } else {
+                const mp<L> d11 = s_el[0].re, d22 = s_el[2].re;
+                const cmp<L> d21 = s_el[1];
+                const mp<L> det = sub(mul(d11, d22), c_abs2(d21));
+                s_d11 = d11;
+                s_d22 = d22;
+                s_d21 = d21;
+                s_idet = div(mp_from<L>(1.0), det);
+                const double a = d11.x[0], b = d22.x[0];
+                const double big = fabs(0.5 * (a + b)) + sqrt(0.25 * (a - b) * (a - b) + c_mag1(d21) * c_mag1(d21));
+                if (big > 0.0 && fabs(det.x[0]) / big < 2048.0 * ptol) tiny++;
+                cmp<L> z;
+                z.re = d11;
+                z.im = mp_zero<L>();
+                st_cmp<L>(M, plane, (size_t)k * ldm + k, z);
+                z.re = d22;
+                st_cmp<L>(M, plane, (size_t)(k + 1) * ldm + k + 1, z);
+                st_cmp<L>(M, plane, (size_t)k * ldm + k + 1, d21);
+                ipiv[k] = -(kp + 1);
+                ipiv[k + 1] = kIpiv2nd;
+                s_y[0] = ld_cmp<L>(M, plane, bc + k);
+                s_y[1] = ld_cmp<L>(M, plane, bc + k + 1);
+            }
+            for (int q = 0; q < kstep; q++) ipiv[n + k + q] = (k + q == k0) ? 1 : 0;
+        }
+        __syncthreads();
+        if (kstep == 1) {
+            const mp<L> inv = s_inv;
+            const cmp<L> y = s_y[0];
+#pragma unroll
+            for (int q = 0; q < R; q++) {
+                const int r = wbase + tid + NT * q;
+                if (r >= j1 && r < n) {
+                    const cmp<L> w = V[0][q];
+                    const cmp<L> l = c_scale(w, inv);
+                    st_cmp<L>(M, plane, (size_t)k * ldm + r, l);
+                    st_cmp<L>(M, plane, wb + (size_t)nk * ldm + r, w);
+                    CAcc<L> b;
+                    b.init(ld_cmp<L>(M, plane, bc + r));
+                    b.sub_mul(l, y);
+                    st_cmp<L>(M, plane, bc + r, b.get());
+#pragma unroll
+                    for (int j = 1; j < kLdlLA; j++)
+                        if (j < live) {
+                            CAcc<L> v;
+                            v.init(V[j][q]);
+                            v.sub_mul(l, s_pj[0][j - 1]);
+                            V[j][q] = v.get();
+                        }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < R; q++) {
+                V[0][q] = V[1][q];
+                V[1][q] = V[2][q];
+                V[2][q] = V[3][q];
+            }
+        } else {
+            const mp<L> d11 = s_d11, d22 = s_d22, idet = s_idet;
+            const cmp<L> d21 = s_d21, y0 = s_y[0], y1 = s_y[1];
+#pragma unroll
+            for (int q = 0; q < R; q++) {
+                const int r = wbase + tid + NT * q;
+                if (r >= j1 && r < n) {
+                    const cmp<L> a = V[0][q];
+                    const cmp<L> b2 = v1_in ? V[1][q] : ld_cmp<L>(M, plane, xc + r);
+                    const cmp<L> l0 = c_scale(c_sub(c_scale(a, d22), c_mul(b2, d21)), idet);
+                    const cmp<L> l1 = c_scale(c_sub(c_scale(b2, d11), c_mul(a, c_conj<L>(d21))), idet);
+                    st_cmp<L>(M, plane, (size_t)k * ldm + r, l0);
+                    st_cmp<L>(M, plane, (size_t)(k + 1) * ldm + r, l1);
+                    st_cmp<L>(M, plane, wb + (size_t)nk * ldm + r, a);
+                    st_cmp<L>(M, plane, wb + (size_t)(nk + 1) * ldm + r, b2);
+                    CAcc<L> b;
+                    b.init(ld_cmp<L>(M, plane, bc + r));
+                    b.sub_mul(l0, y0);
+                    b.sub_mul(l1, y1);
+                    st_cmp<L>(M, plane, bc + r, b.get());
+#pragma unroll
+                    for (int j = 2; j < kLdlLA; j++)
+                        if (j < live) {
+                            CAcc<L> v;
+                            v.init(V[j][q]);
+                            v.sub_mul(l0, s_pj[0][j - 2]);
+                            v.sub_mul(l1, s_pj[1][j - 2]);
+                            V[j][q] = v.get();
+                        }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < R; q++) {
+                V[0][q] = V[2][q];
+                V[1][q] = V[3][q];
+            }
+        }
+        k += kstep;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        Q.lk0 = k0;
+        Q.lkb = k - k0;
+        if (guard) Q.flags |= 4;
+        Q.tiny = (k0 == 0 ? 0 : Q.tiny) + tiny;
+    }
+}
+
+// work-group sum of a complex multi-limb value over NT threads (thread 0
 // returns it)
-template <int L>
-__device__ __forceinline__ cmp<L> wg_sum256(cmp<L> v, cmp<L> *red)
+template <int L, int NT>
+__device__ __forceinline__ cmp<L> wg_sum(cmp<L> v, cmp<L> *red)
 {
     for (int off = 32; off > 0; off >>= 1) {
         cmp<L> o;
@@ -1314,17 +1707,20 @@ __device__ __forceinline__ cmp<L> wg_sum256(cmp<L> v, cmp<L> *red)
         }
         v = c_add(v, o);
     }
+    if (NT == 64) return v;
     __syncthreads();
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
-    return c_add(c_add(red[0], red[1]), c_add(red[2], red[3]));
+    cmp<L> t = red[0];
+    for (int q = 1; q < NT / 64; q++) t = c_add(t, red[q]);
+    return t;
 }
 
 // x = P^T L^{-H} D^{-1} y (y = column n after the factorisation), scaled by a
 // power of two to max-norm ~1 and written as the pair's new iterate.  One
 // work-group (256) per pair; column n is overwritten.
-template <int L>
-__global__ void __launch_bounds__(256) k_s2_ldl_backsolve(Stage2Batch B)
+template <int L, int NT>
+__global__ void __launch_bounds__(NT) k_s2_ldl_backsolve(Stage2Batch B)
 {
     const int t = blockIdx.x;
     PairDesc &Q = B.dev_pairs[B.dev_active[t]];
@@ -1338,7 +1734,7 @@ __global__ void __launch_bounds__(256) k_s2_ldl_backsolve(Stage2Batch B)
     __shared__ cmp<L> red[4];
     __shared__ double redd[4];
     // z = D^{-1} y
-    for (int i = threadIdx.x; i < n; i += 256) {
+    for (int i = threadIdx.x; i < n; i += NT) {
         const int p = ipiv[i];
         if (p >= 0) {
             const mp<L> d = ld_cmp<L>(M, plane, (size_t)i * ldm + i).re;
@@ -1363,16 +1759,16 @@ __global__ void __launch_bounds__(256) k_s2_ldl_backsolve(Stage2Batch B)
         CAcc<L> a0, a1;
         a0.init(c_zero<L>());
         a1.init(c_zero<L>());
-        for (int r = i + 1 + threadIdx.x; r < n; r += 256) {
+        for (int r = i + 1 + threadIdx.x; r < n; r += NT) {
             const cmp<L> x = ld_cmp<L>(M, plane, yc + r);
             a0.add_mulc(ld_cmp<L>(M, plane, (size_t)i * ldm + r), x);
             if (two) a1.add_mulc(ld_cmp<L>(M, plane, (size_t)c0 * ldm + r), x);
         }
-        const cmp<L> s0 = wg_sum256<L>(a0.get(), red);
+        const cmp<L> s0 = wg_sum<L, NT>(a0.get(), red);
         cmp<L> s1 = c_zero<L>();
         if (two) {
             __syncthreads();
-            s1 = wg_sum256<L>(a1.get(), red);
+            s1 = wg_sum<L, NT>(a1.get(), red);
         }
         if (threadIdx.x == 0) {
             st_cmp<L>(M, plane, yc + i, c_sub(ld_cmp<L>(M, plane, yc + i), s0));
@@ -1394,14 +1790,14 @@ __global__ void __launch_bounds__(256) k_s2_ldl_backsolve(Stage2Batch B)
         i = c0 - 1;
     }
     double mx = 0.0;
-    for (int r = threadIdx.x; r < n; r += 256) mx = fmax(mx, c_mag1(ld_cmp<L>(M, plane, yc + r)));
+    for (int r = threadIdx.x; r < n; r += NT) mx = fmax(mx, c_mag1(ld_cmp<L>(M, plane, yc + r)));
     for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
     if ((threadIdx.x & 63) == 0) redd[threadIdx.x >> 6] = mx;
     __syncthreads();
-    mx = fmax(fmax(redd[0], redd[1]), fmax(redd[2], redd[3]));
+    for (int q = 0; q < NT / 64; q++) mx = fmax(mx, redd[q]);
     int e = 0;
     if (mx > 0.0 && isfinite(mx)) frexp(mx, &e);
-    for (int r = threadIdx.x; r < n; r += 256) {
+    for (int r = threadIdx.x; r < n; r += NT) {
         cmp<L> w = ld_cmp<L>(M, plane, yc + r);
         w.re = ldexp_mp(w.re, -e);
         w.im = ldexp_mp(w.im, -e);
@@ -2095,7 +2491,8 @@ template <int L>
 int stage2_rq(const Stage2Batch &B, hipStream_t st)
 {
     if (B.count <= 0) return 0;
-    hipLaunchKernelGGL(k_s2_rq<L>, dim3(B.count), dim3(256), 0, st, B.dev_pairs, B.dev_probs, B.dev_active, B.final_pass);
+    hipLaunchKernelGGL(k_s2_rq<L>, dim3(B.count), dim3(256), 0, st, B.dev_pairs, B.dev_probs, B.dev_active, B.final_pass,
+                       B.ldl);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -2131,7 +2528,12 @@ int stage2_solve(const Stage2Batch &B, const int *orders, hipStream_t st)
                 wu += 0.5 * (double)(m - r0) * (m - r0 + 1) * (r0 - k0);   // complex multi-limb multiply-adds of the lower triangle
             }
             id = T.begin(KC_LU_PANEL, wp, st);
-            hipLaunchKernelGGL(k_s2_ldl_panel<L>, dim3(c), dim3(256), 0, st, B);
+            // dd orders up to 128: one wave per pair with the window in
+            // registers (at 1024 the 256-thread register form, one work-group
+            // per CU at 256 VGPRs, measured slower than the memory form)
+            if (L == 2 && n <= 128) hipLaunchKernelGGL((k_s2_ldl_panel_reg<64, 2>), dim3(c), dim3(64), 0, st, B);
+            else if (n <= 128) hipLaunchKernelGGL((k_s2_ldl_panel<L, 64>), dim3(c), dim3(64), 0, st, B);
+            else hipLaunchKernelGGL((k_s2_ldl_panel<L, 256>), dim3(c), dim3(256), 0, st, B);
             T.end(id, st);
             // the largest trailing block any pair can have after this step
             const int mrows = n - std::min(n, (s + 1) * w);
@@ -2149,7 +2551,8 @@ int stage2_solve(const Stage2Batch &B, const int *orders, hipStream_t st)
         double wb = 0.0;
         for (int q = 0; q < cnt; q++) wb += 0.5 * (double)orders[q] * orders[q];
         id = T.begin(KC_BACKSOLVE, wb, st);
-        hipLaunchKernelGGL(k_s2_ldl_backsolve<L>, dim3(cnt), dim3(256), 0, st, B);
+        if (n <= 128) hipLaunchKernelGGL((k_s2_ldl_backsolve<L, 64>), dim3(cnt), dim3(64), 0, st, B);
+        else hipLaunchKernelGGL((k_s2_ldl_backsolve<L, 256>), dim3(cnt), dim3(256), 0, st, B);
         T.end(id, st);
         if (!B.timer) dummy.collect();
         return hipGetLastError() == hipSuccess ? 0 : -1;
