@@ -401,7 +401,8 @@ __global__ void __launch_bounds__(256) k_s2_rq(PairDesc *pairs, RqiProb *probs, 
 }
 
 // =============================================================== build ====
-// M = [H - sigma I | v]; grid (ceil((n+1)/8), count), block 256.
+// M = [H - sigma I | v] (LDL^H: the lower triangle and v); grid
+// (ceil((n+1)/8), count), block 256.
 template <int L>
 __global__ void __launch_bounds__(256) k_s2_build(Stage2Batch B)
 {
@@ -431,7 +432,9 @@ __global__ void __launch_bounds__(256) k_s2_build(Stage2Batch B)
     for (int jj = 0; jj < 8; jj++) {
         const int j = blockIdx.x * 8 + jj;
         if (j > n) break;
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        // LDL^H reads the lower triangle only
+        const int i0 = (B.ldl && j < n) ? j : 0;
+        for (int i = i0 + threadIdx.x; i < n; i += blockDim.x) {
             cmp<L> z;
             if (j < n) {
                 z = ld_h<L>(P, i, j);
