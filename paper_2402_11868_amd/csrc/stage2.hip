@@ -2270,6 +2270,8 @@ template int stage2_prr_rotate<4>(const PrrDesc *, int, int, int, RqiProb *, hip
 // The Ritz vectors separate the members of the cluster, which the binary64
 // vectors mix when the gaps inside the cluster are near binary64 resolution.
 constexpr int RRMAX = 32;
+constexpr int kRrV = 4;   // cluster members per work-group of k_rr_hv
+constexpr int kRrS = 4;   // row slices of k_rr_hv
 
 // Y = H V for every member of the Rayleigh-Ritz clusters; one work-group per
 // member; Y in scratch at cluster offset + member * n (limb-planar, 2L planes
@@ -2277,26 +2279,36 @@ constexpr int RRMAX = 32;
 template <int L>
 __global__ void __launch_bounds__(256) k_rr_hv(const GsCluster *cls, const int *list, const RqiProb *probs, double *scratch)
 {
+    // kRrV members per work-group (each H entry loaded serves all of them),
+    // rows interleaved over kRrS work-groups in slices of 256
     const GsCluster C = cls[blockIdx.y];
-    const int a = blockIdx.x;
-    if (a >= C.size) return;
+    const int a0 = (blockIdx.x / kRrS) * kRrV, slice = blockIdx.x % kRrS;
+    if (a0 >= C.size) return;
     const RqiProb &P = probs[C.prob];
     const int n = P.n;
     const size_t nn = (size_t)n * n;
-    const int ka = list[C.off + a];
+    int ka[kRrV];
+#pragma unroll
+    for (int v = 0; v < kRrV; v++) ka[v] = list[C.off + min(a0 + v, C.size - 1)];
     double *Y = scratch + C.sofs;
     const size_t yplane = (size_t)n * RRMAX;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        CAcc<L> y;
-        y.init(c_zero<L>());
+    for (int i = threadIdx.x + 256 * slice; i < n; i += 256 * kRrS) {
+        CAcc<L> y[kRrV];
+#pragma unroll
+        for (int v = 0; v < kRrV; v++) y[v].init(c_zero<L>());
         for (int j = 0; j < n; j++) {
             const cmp<L> h = ld_h<L>(P, i, j);
-            const cmp<L> v = ld_cmp<L>(P.vec, nn, (size_t)ka * n + j);
-            // y += h v  ==  y -= (-h) v
-            y.sub_mul(cmp<L>{mp_neg<L>(h.re), mp_neg<L>(h.im)}, v);
-            if ((j & 15) == 15) y.renorm();
+            const cmp<L> nh = cmp<L>{mp_neg<L>(h.re), mp_neg<L>(h.im)};
+#pragma unroll
+            for (int v = 0; v < kRrV; v++) {
+                // y += h v  ==  y -= (-h) v
+                y[v].sub_mul(nh, ld_cmp<L>(P.vec, nn, (size_t)ka[v] * n + j));
+                if ((j & 15) == 15) y[v].renorm();
+            }
         }
-        st_cmp<L>(Y, yplane, (size_t)a * n + i, y.get());
+#pragma unroll
+        for (int v = 0; v < kRrV; v++)
+            if (a0 + v < C.size) st_cmp<L>(Y, yplane, (size_t)(a0 + v) * n + i, y[v].get());
     }
 }
 
@@ -2471,7 +2483,8 @@ template <int L>
 int stage2_rr(const GsPlan &G, RqiProb *probs, int sweeps, hipStream_t st)
 {
     if (G.ncl <= 0) return 0;
-    hipLaunchKernelGGL(k_rr_hv<L>, dim3(RRMAX, G.ncl), dim3(256), 0, st, G.dev_cls, G.dev_list, (const RqiProb *)probs, G.scratch);
+    hipLaunchKernelGGL(k_rr_hv<L>, dim3(RRMAX / kRrV * kRrS, G.ncl), dim3(256), 0, st, G.dev_cls, G.dev_list,
+                       (const RqiProb *)probs, G.scratch);
     hipLaunchKernelGGL(k_rr_solve<L>, dim3(G.ncl), dim3(256), 0, st, G.dev_cls, G.dev_list, probs, (const double *)G.scratch,
                        sweeps);
     return hipGetLastError() == hipSuccess ? 0 : -1;
