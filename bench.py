@@ -157,19 +157,27 @@ def cpu_baseline():
 def batch_leg(Z, ctx, torch, tol=1e-30):
     """The batch workload: 256 independent 128x128 matrices (spectra 10^(-k/8)
     down to 1e-16 with four exact 2-fold degeneracies each) in one zk_heev_dd
-    call; eigenpairs/s of pairs within the device residual gate, and the
-    binary64 stage's MFMA rate over the batched trailing updates."""
+    call: eigenpairs/s of pairs within the device residual gate (median of 3
+    plain calls), then one call with every kernel class timed for the phase
+    split, the binary64 stage's MFMA rate over the batched trailing updates
+    and the trailing update's fraction of its VALU peak."""
+    import numpy as np
     import workloads as W
     mats = [torch.from_numpy(W.workload(2, index=i)["A"]).cuda() for i in range(256)]
     Z.heev(ctx, [[m] for m in mats], limbs_out=2)   # warm-up
     torch.cuda.synchronize()
+    ts = []
+    st = {}
+    for _ in range(3):
+        t0 = time.perf_counter()
+        res = Z.heev(ctx, [[m] for m in mats], limbs_out=2, stats=st)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    dt = float(np.median(ts))
     ctx.prof(True)
     ctx.prof_reset()
-    st = {}
-    t0 = time.perf_counter()
-    res = Z.heev(ctx, [[m] for m in mats], limbs_out=2, stats=st)
+    Z.heev(ctx, [[m] for m in mats], limbs_out=2)
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
     p = ctx.prof_read()
     ctx.prof(False)
     ok = sum(1 for r in res for x in r.info if x["resid"] <= tol)
@@ -597,6 +605,8 @@ def main():
     ap.add_argument("--no-batch-leg", action="store_true", help="skip the 256 x 128^2 batch run")
     ap.add_argument("--no-allpairs-leg", action="store_true", help="skip the all-pairs refinement runs")
     ap.add_argument("--no-mp-leg", action="store_true", help="skip the beyond-double-double runs")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="the 1024 workload alone (with the --no-* flags: a clean trace of its kernels)")
     ap.add_argument("--no-svd-leg", action="store_true", help="skip the 512 x 512 SVD runs")
     ap.add_argument("--serving-requests", type=int, default=1000,
                     help="requests of the serving-stream leg (0 = skip the leg; the all-pairs leg serves twice as many)")
@@ -765,12 +775,13 @@ def main():
     if not args.no_batch_leg:
         log("batch of 256 x 128^2")
         out["batch"] = batch_leg(Z, ctx, torch)
-    log("64 x 64 workload")
-    out["c1"] = c1_leg(Z, ctx, torch)
-    log("quad-double companions")
-    out["qd_companions"] = qd_companions_leg(Z, ctx, torch)
-    log("MPS stream")
-    out["mps_stream"] = mps_stream_leg(Z, ctx, torch)
+    if not args.headline_only:
+        log("64 x 64 workload")
+        out["c1"] = c1_leg(Z, ctx, torch)
+        log("quad-double companions")
+        out["qd_companions"] = qd_companions_leg(Z, ctx, torch)
+        log("MPS stream")
+        out["mps_stream"] = mps_stream_leg(Z, ctx, torch)
     if not args.no_mp_leg:
         log("beyond double-double")
         out["mp"] = mp_leg(Z, ctx, torch)
