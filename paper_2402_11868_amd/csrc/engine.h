@@ -72,7 +72,13 @@ struct S2Prob {
 template <int L>
 class Stage2Engine {
   public:
-    Stage2Engine(zk_ctx *c, const ResolvedOpts &o, Stage2Stats *s) : ctx(c), O(o), stats(s) { st = c->stream; }
+    Stage2Engine(zk_ctx *c, const ResolvedOpts &o, Stage2Stats *s) : ctx(c), O(o), stats(s)
+    {
+        st = c->stream;
+        // ZK_S2_SPLIT=0: every chunk of pairs in one group (for measurements)
+        const char *e = std::getenv("ZK_S2_SPLIT");
+        s2_split_ = !(e && e[0] == '0');
+    }
     ~Stage2Engine()
     {
         for (S2Prob *p : live) release(p);
@@ -228,8 +234,10 @@ class Stage2Engine {
     static constexpr double kPrrDeep = 1e-3;
     static constexpr double kPurify = 1e-18;
     static constexpr double kReorthWindow = 0.1;
+    static constexpr int kSplitMin = 32;   // pairs per group below which a chunk is not split
 
   private:
+    bool s2_split_ = false;
     zk_ctx *ctx;
     ResolvedOpts O;
     Stage2Stats *stats;
@@ -570,6 +578,31 @@ class Stage2Engine {
                 lst.push_back(g);
                 ord.push_back(it->first);
             }
+        // Two groups of pairs on two streams (LDL^H, enough pairs): the pairs
+        // at even and at odd positions of each chunk (both lists stay ordered
+        // by non-increasing order).  Their trailing updates alternate, so one
+        // group's panels (bound by latency and memory) run beside the other
+        // group's update (bound by the FP64 VALU).  A pair's arithmetic is the
+        // same in either group and in either slot.
+        const bool split = ldl && s2_split_ && !ctx->arena;
+        if (split) {
+            for (size_t c0 = 0; c0 < lst.size(); c0 += (size_t)S) {
+                const size_t cnt = std::min<size_t>((size_t)S, lst.size() - c0);
+                if (cnt < 2 * (size_t)kSplitMin) continue;
+                std::vector<int> l2, o2;
+                for (int par = 0; par < 2; par++)
+                    for (size_t q = par; q < cnt; q += 2) {
+                        l2.push_back(lst[c0 + q]);
+                        o2.push_back(ord[c0 + q]);
+                    }
+                std::copy(l2.begin(), l2.end(), lst.begin() + c0);
+                std::copy(o2.begin(), o2.end(), ord.begin() + c0);
+            }
+            for (int k = 0; k < 1; k++)
+                if (!ctx->side[k]) HIPCHK_(hipStreamCreateWithFlags(&ctx->side[k], hipStreamNonBlocking));
+            for (int k = 0; k < 3; k++)
+                if (!ctx->ev[k]) HIPCHK_(hipEventCreateWithFlags(&ctx->ev[k], hipEventDisableTiming));
+        }
         HIPCHK_(hipMemcpyAsync(d_active, lst.data(), 4 * lst.size(), hipMemcpyHostToDevice, st));
         Stage2Batch B = batch_base();
         B.ldl = ldl ? 1 : 0;
@@ -582,6 +615,26 @@ class Stage2Engine {
             B.ldm = s2_lu_ldm(n);
             B.lu_stride = s2_lu_slot_doubles(n, L);
             B.piv_stride = 2 * (size_t)n;
+            if (split && cnt >= 2 * kSplitMin) {
+                const int h = (cnt + 1) / 2;
+                Stage2Batch G[2] = {B, B};
+                G[0].count = h;
+                G[1].dev_active = d_active + c0 + h;
+                G[1].n = ord[c0 + h];
+                G[1].count = cnt - h;
+                G[1].lu_base = B.lu_base + (size_t)h * B.lu_stride;
+                G[1].piv_base = B.piv_base + (size_t)h * B.piv_stride;
+                const int *og[2] = {ord.data() + c0, ord.data() + c0 + h};
+                const hipStream_t sg[2] = {st, ctx->side[0]};
+                const hipEvent_t eg[2] = {ctx->ev[1], ctx->ev[2]};
+                // the side stream starts after everything enqueued on the context stream
+                HIPCHK_(hipEventRecord(ctx->ev[0], st));
+                HIPCHK_(hipStreamWaitEvent(sg[1], ctx->ev[0], 0));
+                if (stage2_solve_pair<L>(G, og, sg, eg)) return ctx->fail(ZK_EDEVICE, "solve launch failed");
+                HIPCHK_(hipEventRecord(ctx->ev[0], sg[1]));
+                HIPCHK_(hipStreamWaitEvent(st, ctx->ev[0], 0));
+                continue;
+            }
             if (stage2_solve<L>(B, ord.data() + c0, st)) return ctx->fail(ZK_EDEVICE, "solve launch failed");
         }
         HIPCHK_(hipStreamSynchronize(st));

@@ -276,6 +276,10 @@ template <int L> int stage2_rq(const Stage2Batch &B, hipStream_t st);
 // orders: the pairs' matrix orders (host, count entries, non-increasing);
 // B.n = orders[0] sets the grid extents, the LU slots are B.lu_stride apart
 template <int L> int stage2_solve(const Stage2Batch &B, const int *orders, hipStream_t st);
+// LDL^H solves of two groups of pairs in disjoint slots, group g on stream
+// st[g]; their trailing updates alternate (ev[g]: group g's last update)
+template <int L>
+int stage2_solve_pair(const Stage2Batch *B, const int *const *orders, const hipStream_t *st, const hipEvent_t *ev);
 template <int L> int stage2_output(PairDesc *pairs, RqiProb *probs, const int *dst, int npairs, hipStream_t st);
 
 }  // namespace zk

@@ -2512,6 +2512,85 @@ int stage2_rq(const Stage2Batch &B, hipStream_t st)
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+// The LDL^H launch sequence in parts, so that two groups of pairs on two
+// streams can interleave theirs.  Panels of kLuNB - 1 or kLuNB columns (per
+// pair): after s steps every pair has factorised at least
+// min(order, s (kLuNB - 1)) columns.
+constexpr int kLdlStepW = kLuNB - 1;
+
+static inline int ldl_steps(int n) { return (n + kLdlStepW - 1) / kLdlStepW; }
+
+// pairs (leading entries of the non-increasing order list) that take part in step s
+static inline int ldl_live(const int *orders, int cnt, int s)
+{
+    int c = cnt;
+    while (c > 0 && orders[c - 1] <= s * kLdlStepW) c--;
+    return c;
+}
+
+template <int L>
+static void ldl_build(const Stage2Batch &B, KernelTimer &T, hipStream_t st)
+{
+    const int id = T.begin(KC_BUILD, 0.0, st);
+    hipLaunchKernelGGL(k_s2_build<L>, dim3(cdiv2(B.n + 1, 8), B.count), dim3(256), 0, st, B);
+    T.end(id, st);
+}
+
+template <int L>
+static void ldl_panel(const Stage2Batch &B, const int *orders, int s, int c, KernelTimer &T, hipStream_t st)
+{
+    const int n = B.n;
+    double wp = 0.0;
+    for (int q = 0; q < c; q++) {
+        const int m = orders[q], k0 = std::min(m, s * kLuNB);
+        wp += 0.5 * (double)(m - k0) * kLuNB * kLuNB;
+    }
+    const int id = T.begin(KC_LU_PANEL, wp, st);
+    // dd orders up to 128: one wave per pair with the window in registers
+    // (at 1024 the 256-thread register form, one work-group per CU at 256
+    // VGPRs, measured slower than the memory form)
+    if (L == 2 && n <= 128) hipLaunchKernelGGL((k_s2_ldl_panel_reg<64, 2>), dim3(c), dim3(64), 0, st, B);
+    else if (n <= 128) hipLaunchKernelGGL((k_s2_ldl_panel<L, 64>), dim3(c), dim3(64), 0, st, B);
+    else hipLaunchKernelGGL((k_s2_ldl_panel<L, 256>), dim3(c), dim3(256), 0, st, B);
+    T.end(id, st);
+}
+
+// the trailing update of step s; false when no pair has a trailing block left
+template <int L>
+static bool ldl_update(const Stage2Batch &B, const int *orders, int s, int c, KernelTimer &T, hipStream_t st)
+{
+    const int n = B.n;
+    // the largest trailing block any pair can have after this step
+    const int mrows = n - std::min(n, (s + 1) * kLdlStepW);
+    if (mrows <= 0) return false;
+    double wu = 0.0;
+    for (int q = 0; q < c; q++) {
+        const int m = orders[q], k0 = std::min(m, s * kLuNB), r0 = std::min(m, k0 + kLuNB);
+        wu += 0.5 * (double)(m - r0) * (m - r0 + 1) * (r0 - k0);   // complex multi-limb multiply-adds of the lower triangle
+    }
+    const int id = T.begin(KC_LU_UPDATE, wu, st);
+    if (L == 2) {
+        const unsigned tt = cdiv2(mrows, 64);
+        hipLaunchKernelGGL(k_s2_lu_update_dd<true>, dim3(tt * (tt + 1) / 2, c), dim3(256), 0, st, B, 0, 0);
+    } else {
+        const unsigned tt = cdiv2(mrows, 32);
+        hipLaunchKernelGGL((k_s2_lu_update_gen<L, true>), dim3(tt * (tt + 1) / 2, c), dim3(256), 0, st, B, 0, 0);
+    }
+    T.end(id, st);
+    return true;
+}
+
+template <int L>
+static void ldl_backsolve(const Stage2Batch &B, const int *orders, KernelTimer &T, hipStream_t st)
+{
+    double wb = 0.0;
+    for (int q = 0; q < B.count; q++) wb += 0.5 * (double)orders[q] * orders[q];
+    const int id = T.begin(KC_BACKSOLVE, wb, st);
+    if (B.n <= 128) hipLaunchKernelGGL((k_s2_ldl_backsolve<L, 64>), dim3(B.count), dim3(64), 0, st, B);
+    else hipLaunchKernelGGL((k_s2_ldl_backsolve<L, 256>), dim3(B.count), dim3(256), 0, st, B);
+    T.end(id, st);
+}
+
 template <int L>
 int stage2_solve(const Stage2Batch &B, const int *orders, hipStream_t st)
 {
@@ -2525,54 +2604,22 @@ int stage2_solve(const Stage2Batch &B, const int *orders, hipStream_t st)
     if (cnt <= 0) return 0;
     KernelTimer dummy;
     KernelTimer &T = B.timer ? *B.timer : dummy;
-    int id = T.begin(KC_BUILD, 0.0, st);
-    hipLaunchKernelGGL(k_s2_build<L>, dim3(cdiv2(n + 1, 8), cnt), dim3(256), 0, st, B);
-    T.end(id, st);
     if (B.ldl) {
-        // Panels of kLuNB - 1 or kLuNB columns (per pair): after s steps every
-        // pair has factorised at least min(order, s (kLuNB - 1)) columns.
-        const int w = kLuNB - 1;
-        const int steps = (n + w - 1) / w;
+        ldl_build<L>(B, T, st);
+        const int steps = ldl_steps(n);
         for (int s = 0; s < steps; s++) {
-            int c = cnt;
-            while (c > 0 && orders[c - 1] <= s * w) c--;
+            const int c = ldl_live(orders, cnt, s);
             if (c == 0) break;
-            double wp = 0.0, wu = 0.0;
-            for (int q = 0; q < c; q++) {
-                const int m = orders[q], k0 = std::min(m, s * kLuNB), r0 = std::min(m, k0 + kLuNB);
-                wp += 0.5 * (double)(m - k0) * kLuNB * kLuNB;
-                wu += 0.5 * (double)(m - r0) * (m - r0 + 1) * (r0 - k0);   // complex multi-limb multiply-adds of the lower triangle
-            }
-            id = T.begin(KC_LU_PANEL, wp, st);
-            // dd orders up to 128: one wave per pair with the window in
-            // registers (at 1024 the 256-thread register form, one work-group
-            // per CU at 256 VGPRs, measured slower than the memory form)
-            if (L == 2 && n <= 128) hipLaunchKernelGGL((k_s2_ldl_panel_reg<64, 2>), dim3(c), dim3(64), 0, st, B);
-            else if (n <= 128) hipLaunchKernelGGL((k_s2_ldl_panel<L, 64>), dim3(c), dim3(64), 0, st, B);
-            else hipLaunchKernelGGL((k_s2_ldl_panel<L, 256>), dim3(c), dim3(256), 0, st, B);
-            T.end(id, st);
-            // the largest trailing block any pair can have after this step
-            const int mrows = n - std::min(n, (s + 1) * w);
-            if (mrows <= 0) continue;
-            id = T.begin(KC_LU_UPDATE, wu, st);
-            if (L == 2) {
-                const unsigned tt = cdiv2(mrows, 64);
-                hipLaunchKernelGGL(k_s2_lu_update_dd<true>, dim3(tt * (tt + 1) / 2, c), dim3(256), 0, st, B, 0, 0);
-            } else {
-                const unsigned tt = cdiv2(mrows, 32);
-                hipLaunchKernelGGL((k_s2_lu_update_gen<L, true>), dim3(tt * (tt + 1) / 2, c), dim3(256), 0, st, B, 0, 0);
-            }
-            T.end(id, st);
+            ldl_panel<L>(B, orders, s, c, T, st);
+            ldl_update<L>(B, orders, s, c, T, st);
         }
-        double wb = 0.0;
-        for (int q = 0; q < cnt; q++) wb += 0.5 * (double)orders[q] * orders[q];
-        id = T.begin(KC_BACKSOLVE, wb, st);
-        if (n <= 128) hipLaunchKernelGGL((k_s2_ldl_backsolve<L, 64>), dim3(cnt), dim3(64), 0, st, B);
-        else hipLaunchKernelGGL((k_s2_ldl_backsolve<L, 256>), dim3(cnt), dim3(256), 0, st, B);
-        T.end(id, st);
+        ldl_backsolve<L>(B, orders, T, st);
         if (!B.timer) dummy.collect();
         return hipGetLastError() == hipSuccess ? 0 : -1;
     }
+    int id = T.begin(KC_BUILD, 0.0, st);
+    hipLaunchKernelGGL(k_s2_build<L>, dim3(cdiv2(n + 1, 8), cnt), dim3(256), 0, st, B);
+    T.end(id, st);
     for (int k0 = 0; k0 < n; k0 += kLuNB) {
         int c = cnt;
         while (c > 0 && orders[c - 1] <= k0) c--;
@@ -2614,6 +2661,44 @@ int stage2_solve(const Stage2Batch &B, const int *orders, hipStream_t st)
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+// Two groups of pairs (LDL^H), group g on stream st[g], in disjoint slots:
+// the trailing updates of the two groups alternate (group 0's update of step
+// s, then group 1's, then group 0's of step s + 1, ...; ev[g] marks group g's
+// last update), so that while one group's update has the chip, the other
+// group factorises its next panel beside it, and no two updates overlap.
+template <int L>
+int stage2_solve_pair(const Stage2Batch *B, const int *const *orders, const hipStream_t *st, const hipEvent_t *ev)
+{
+    KernelTimer dummy[2];
+    KernelTimer *T[2];
+    int steps = 0;
+    for (int g = 0; g < 2; g++) {
+        T[g] = B[g].timer ? B[g].timer : &dummy[g];
+        if (B[g].count > 0) {
+            ldl_build<L>(B[g], *T[g], st[g]);
+            steps = std::max(steps, ldl_steps(B[g].n));
+        }
+    }
+    bool upd[2] = {false, false};   // group g has an update enqueued (ev[g] recorded)
+    for (int s = 0; s < steps; s++)
+        for (int g = 0; g < 2; g++) {
+            if (B[g].count <= 0 || s >= ldl_steps(B[g].n)) continue;
+            const int c = ldl_live(orders[g], B[g].count, s);
+            if (c == 0) continue;
+            ldl_panel<L>(B[g], orders[g], s, c, *T[g], st[g]);
+            if (upd[1 - g] && hipStreamWaitEvent(st[g], ev[1 - g], 0) != hipSuccess) return -1;
+            if (ldl_update<L>(B[g], orders[g], s, c, *T[g], st[g])) {
+                if (hipEventRecord(ev[g], st[g]) != hipSuccess) return -1;
+                upd[g] = true;
+            }
+        }
+    for (int g = 0; g < 2; g++)
+        if (B[g].count > 0) ldl_backsolve<L>(B[g], orders[g], *T[g], st[g]);
+    for (int g = 0; g < 2; g++)
+        if (!B[g].timer) dummy[g].collect();
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 template <int L>
 int stage2_output(PairDesc *pairs, RqiProb *probs, const int *dst, int npairs, hipStream_t st)
 {
@@ -2627,6 +2712,8 @@ template int stage2_rq<2>(const Stage2Batch &, hipStream_t);
 template int stage2_rq<4>(const Stage2Batch &, hipStream_t);
 template int stage2_solve<2>(const Stage2Batch &, const int *, hipStream_t);
 template int stage2_solve<4>(const Stage2Batch &, const int *, hipStream_t);
+template int stage2_solve_pair<2>(const Stage2Batch *, const int *const *, const hipStream_t *, const hipEvent_t *);
+template int stage2_solve_pair<4>(const Stage2Batch *, const int *const *, const hipStream_t *, const hipEvent_t *);
 template int stage2_output<2>(PairDesc *, RqiProb *, const int *, int, hipStream_t);
 template int stage2_output<4>(PairDesc *, RqiProb *, const int *, int, hipStream_t);
 
