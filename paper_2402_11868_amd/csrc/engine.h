@@ -234,7 +234,7 @@ class Stage2Engine {
     static constexpr double kPrrDeep = 1e-3;
     static constexpr double kPurify = 1e-18;
     static constexpr double kReorthWindow = 0.1;
-    static constexpr int kSplitMin = 32;   // pairs per group below which a chunk is not split
+    static constexpr int kSplitMin = 8;   // pairs per group below which a chunk is not split
 
   private:
     bool s2_split_ = false;

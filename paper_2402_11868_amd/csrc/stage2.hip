@@ -1022,6 +1022,20 @@ __device__ __forceinline__ void swap_cmp(double *M, size_t plane, size_t a, size
     st_cmp<L>(M, plane, b, x);
 }
 
+// Row r of the panel's L columns c0 .. c0 + U - 1 (U = ldl_ldu<L>; columns
+// past nk - 1 repeat column nk - 1 and are not used): the loads are issued
+// together, so that one memory latency covers U columns of a Schur-complement
+// sum (issued one by one, each column's load latency adds up along the sum).
+template <int L>
+constexpr int ldl_ldu() { return L == 2 ? 8 : 4; }
+
+template <int L>
+__device__ __forceinline__ void ldl_load_l(cmp<L> *lb, const double *M, size_t plane, int ldm, int k0, int c0, int nk, int r)
+{
+#pragma unroll
+    for (int u = 0; u < ldl_ldu<L>(); u++) lb[u] = ld_cmp<L>(M, plane, (size_t)(k0 + min(c0 + u, nk - 1)) * ldm + r);
+}
+
 // one work-group (NT threads: 256, or one wave for small orders) per pair:
 // the pair's next panel, from column lk0 + lkb.
 // Left-looking with a look-ahead window: one pass over the panel's L columns
@@ -1405,11 +1419,15 @@ __global__ void __launch_bounds__(NT) k_s2_ldl_panel_reg(Stage2Batch B)
                     a[j].init(z);
                 }
                 if (r < n)
-                    for (int c = 0; c < nk; c++) {
-                        const cmp<L> l = ld_cmp<L>(M, plane, (size_t)(k0 + c) * ldm + r);
+                    for (int c0 = 0; c0 < nk; c0 += ldl_ldu<L>()) {
+                        cmp<L> lb[ldl_ldu<L>()];
+                        ldl_load_l<L>(lb, M, plane, ldm, k0, c0, nk, r);
 #pragma unroll
-                        for (int j = 0; j < kLdlLA; j++)
-                            if (j < nw) a[j].sub_mul(l, s_wt[j][c]);
+                        for (int u = 0; u < ldl_ldu<L>(); u++)
+                            if (c0 + u < nk)
+#pragma unroll
+                                for (int j = 0; j < kLdlLA; j++)
+                                    if (j < nw) a[j].sub_mul(lb[u], s_wt[j][c0 + u]);
                     }
 #pragma unroll
                 for (int j = 0; j < kLdlLA; j++) V[j][q] = a[j].get();
@@ -1449,7 +1467,13 @@ __global__ void __launch_bounds__(NT) k_s2_ldl_panel_reg(Stage2Batch B)
                     CAcc<L> a;
                     a.init(r >= imax ? ld_cmp<L>(M, plane, (size_t)imax * ldm + r)
                                      : c_conj<L>(ld_cmp<L>(M, plane, (size_t)r * ldm + imax)));
-                    for (int c = 0; c < nk; c++) a.sub_mul(ld_cmp<L>(M, plane, (size_t)(k0 + c) * ldm + r), s_wt[0][c]);
+                    for (int c0 = 0; c0 < nk; c0 += ldl_ldu<L>()) {
+                        cmp<L> lb[ldl_ldu<L>()];
+                        ldl_load_l<L>(lb, M, plane, ldm, k0, c0, nk, r);
+#pragma unroll
+                        for (int u = 0; u < ldl_ldu<L>(); u++)
+                            if (c0 + u < nk) a.sub_mul(lb[u], s_wt[0][c0 + u]);
+                    }
                     st_cmp<L>(M, plane, xc + r, a.get());
                 }
                 __syncthreads();
@@ -2517,6 +2541,7 @@ int stage2_rq(const Stage2Batch &B, hipStream_t st)
 // pair): after s steps every pair has factorised at least
 // min(order, s (kLuNB - 1)) columns.
 constexpr int kLdlStepW = kLuNB - 1;
+constexpr int kRegPanelPairs = 256;
 
 static inline int ldl_steps(int n) { return (n + kLdlStepW - 1) / kLdlStepW; }
 
@@ -2546,11 +2571,17 @@ static void ldl_panel(const Stage2Batch &B, const int *orders, int s, int c, Ker
         wp += 0.5 * (double)(m - k0) * kLuNB * kLuNB;
     }
     const int id = T.begin(KC_LU_PANEL, wp, st);
-    // dd orders up to 128: one wave per pair with the window in registers
-    // (at 1024 the 256-thread register form, one work-group per CU at 256
-    // VGPRs, measured slower than the memory form)
+    // dd orders up to 128: one wave per pair with the window in registers.
+    // Larger dd orders: the 256-thread register form while the launch has at
+    // most kRegPanelPairs pairs (its time is then the latency of one
+    // work-group, which the register window shortens), else the memory form
+    // (the register form's 256 VGPRs at order 1024 allow one work-group per
+    // CU; with hundreds of pairs it was measured slower)
     if (L == 2 && n <= 128) hipLaunchKernelGGL((k_s2_ldl_panel_reg<64, 2>), dim3(c), dim3(64), 0, st, B);
     else if (n <= 128) hipLaunchKernelGGL((k_s2_ldl_panel<L, 64>), dim3(c), dim3(64), 0, st, B);
+    else if (L == 2 && c <= kRegPanelPairs && n <= 256) hipLaunchKernelGGL((k_s2_ldl_panel_reg<256, 1>), dim3(c), dim3(256), 0, st, B);
+    else if (L == 2 && c <= kRegPanelPairs && n <= 512) hipLaunchKernelGGL((k_s2_ldl_panel_reg<256, 2>), dim3(c), dim3(256), 0, st, B);
+    else if (L == 2 && c <= kRegPanelPairs && n <= 1024) hipLaunchKernelGGL((k_s2_ldl_panel_reg<256, 4>), dim3(c), dim3(256), 0, st, B);
     else hipLaunchKernelGGL((k_s2_ldl_panel<L, 256>), dim3(c), dim3(256), 0, st, B);
     T.end(id, st);
 }
