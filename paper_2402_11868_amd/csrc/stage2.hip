@@ -739,6 +739,9 @@ __global__ void __launch_bounds__(256, 2) k_s2_lu_update_dd(Stage2Batch B, int k
     if (ti * 64 >= mrows || tj * 64 >= mcols) return;
     // LDL^H diagonal tile: its 16x16 sub-blocks above the diagonal (b > a) are not needed
     const bool diag = LDL && ti == tj;
+    // 16-row groups of the tile that hold rows of the block (a tile of the
+    // last tile row may hold fewer than 64; the groups past the end are skipped)
+    const int amax = min(4, (n - i0 + 15) / 16);
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
     // planes: 0 re_hi, 1 re_lo, 2 im_hi, 3 im_lo; two buffers: the next chunk
     // is loaded from global memory while the current one is multiplied
@@ -806,6 +809,7 @@ __global__ void __launch_bounds__(256, 2) k_s2_lu_update_dd(Stage2Batch B, int k
                 uih[b] = sU[buf][2][kk][ty + 16 * b]; uil[b] = sU[buf][3][kk][ty + 16 * b];
             }
             for (int a = 0; a < 4; a++) {
+                if (a >= amax) continue;
                 // negated L: the update subtracts
                 const double lrh = -sL[buf][0][kk][tx + 16 * a], lrl = -sL[buf][1][kk][tx + 16 * a];
                 const double lih = sL[buf][2][kk][tx + 16 * a], lil = sL[buf][3][kk][tx + 16 * a];
