@@ -867,6 +867,10 @@ __global__ void __launch_bounds__(256) k_s2_lu_update_gen(Stage2Batch B, int k0,
     const int i0 = r0 + ti * 32, j0 = r0 + tj * 32;
     if (ti * 32 >= mrows || tj * 32 >= mcols) return;
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    // LDL^H diagonal tile: the 16x16 sub-block above the diagonal (b > a) is
+    // not needed; 16-row groups past the last row are skipped
+    const bool diag = LDL && ti == tj;
+    const int amax = min(2, (n - i0 + 15) / 16);
     __shared__ cmp<L> sL[KC][32];
     __shared__ cmp<L> sU[KC][32];
     // outputs (rows tx + 16a, columns ty + 16b): 16 lanes touch 16 consecutive rows
@@ -898,13 +902,18 @@ __global__ void __launch_bounds__(256) k_s2_lu_update_gen(Stage2Batch B, int k0,
         __syncthreads();
         const int kmax = min(KC, nbw - kc);
         for (int kk = 0; kk < kmax; kk++)
-            for (int a = 0; a < 2; a++)
-                for (int b = 0; b < 2; b++) acc[a][b].sub_mul(sL[kk][tx + 16 * a], sU[kk][ty + 16 * b]);
+            for (int a = 0; a < 2; a++) {
+                if (a >= amax) continue;
+                for (int b = 0; b < 2; b++) {
+                    if (diag && b > a) continue;
+                    acc[a][b].sub_mul(sL[kk][tx + 16 * a], sU[kk][ty + 16 * b]);
+                }
+            }
     }
     for (int a = 0; a < 2; a++)
         for (int b = 0; b < 2; b++) {
             const int i = i0 + tx + 16 * a, j = j0 + ty + 16 * b;
-            if (i < n && j < jend) st_cmp<L>(M, plane, (size_t)j * ldm + i, acc[a][b].get());
+            if (i < n && j < jend && !(diag && b > a)) st_cmp<L>(M, plane, (size_t)j * ldm + i, acc[a][b].get());
         }
 }
 
