@@ -449,7 +449,7 @@ class Stage2Engine {
             c.nact = (int)act.size();
             c.size = c.nconv + c.nact;
             c.sofs = sofs;
-            sofs += (long long)c.size * 32 * 2 * L;
+            sofs += (long long)c.size * 32 * 2 * L * gs_slices(set[pi]->rp.n);
             list.insert(list.end(), fro.begin(), fro.end());
             list.insert(list.end(), act.begin(), act.end());
             cls.push_back(c);

@@ -225,8 +225,13 @@ struct GsCluster {
     int nconv;       // leading entries left untouched
     int nact;        // entries orthogonalised, in order
     int size;        // nconv + nact
-    long long sofs;  // scratch offset (doubles), 2L planes of size * 32 values
+    long long sofs;  // scratch offset (doubles): Gram-Schmidt, kGsSlices sets of 2L planes of
+                     // size * 32 values; Rayleigh-Ritz, 2L planes of n * 32 values
 };
+constexpr int kGsSlices = 8;   // row slices of the Gram-Schmidt coefficient sums, at most
+// row slices for a cluster of order n: a function of n alone, so that a
+// matrix's coefficients do not depend on the other matrices of a call
+__host__ __device__ inline int gs_slices(int n) { return n / 128 < 1 ? 1 : (n / 128 > kGsSlices ? kGsSlices : n / 128); }
 struct GsPlan {
     int ncl;
     int max_blocks;   // max over clusters of ceil(nact / 32)

@@ -1886,6 +1886,10 @@ constexpr int RB = 32;
 constexpr int RBP = RB * (RB + 1) / 2;   // packed upper triangle, column by column
 __device__ __forceinline__ int pk(int a, int c) { return c * (c + 1) / 2 + a; }
 
+// Row slices of the coefficient dot products: a cluster of order n splits its
+// n rows into gs_slices(n) slices; each slice writes its partial sums into its
+// own plane set of the cluster's scratch and k_gs_dsum adds them in slice
+// order.
 template <int L>
 __global__ void __launch_bounds__(256) k_gs_dot(const GsCluster *cls, const int *list, const RqiProb *probs, int b,
                                                 double *scratch)
@@ -1893,30 +1897,53 @@ __global__ void __launch_bounds__(256) k_gs_dot(const GsCluster *cls, const int 
     const GsCluster C = cls[blockIdx.z];
     const int j0 = C.nconv + b * RB, bw = min(RB, C.nact - b * RB);
     if (bw <= 0 || j0 == 0) return;
-    if (blockIdx.x * 16 >= j0 || blockIdx.y * 16 >= bw) return;
+    const int tile = blockIdx.x / kGsSlices, slice = blockIdx.x % kGsSlices;
+    if (tile * 16 >= j0 || blockIdx.y * 16 >= bw) return;
     const RqiProb &P = probs[C.prob];
     const int n = P.n;
+    const int kd = gs_slices(n);
+    if (slice >= kd) return;
+    const int rc = ((n + kd - 1) / kd + 15) / 16 * 16;
+    const int rbeg = slice * rc, rend = min(n, rbeg + rc);
     const size_t nn = (size_t)n * n;
     const int *lst = list + C.off;
-    double *Cm = scratch + C.sofs;
     const size_t cplane = (size_t)C.size * RB;
+    double *Cm = scratch + C.sofs + (size_t)slice * 2 * L * cplane;
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    const int i = blockIdx.x * 16 + ty, jb = blockIdx.y * 16 + tx;
+    const int i = tile * 16 + ty, jb = blockIdx.y * 16 + tx;
     __shared__ cmp<L> si[16][16], sj[16][16];   // [row][vector]
-    const int vi = blockIdx.x * 16 + ty, vj = blockIdx.y * 16 + ty;
+    const int vi = tile * 16 + ty, vj = blockIdx.y * 16 + ty;
     const int ci = vi < j0 ? lst[vi] : -1, cj = vj < bw ? lst[j0 + vj] : -1;
     CAcc<L> acc;
     acc.init(c_zero<L>());
-    for (int r0 = 0; r0 < n; r0 += 16) {
+    for (int r0 = rbeg; r0 < rend; r0 += 16) {
         __syncthreads();
         const int r = r0 + tx;
-        si[tx][ty] = (r < n && ci >= 0) ? ld_cmp<L>(P.vec, nn, (size_t)ci * n + r) : c_zero<L>();
-        sj[tx][ty] = (r < n && cj >= 0) ? ld_cmp<L>(P.vec, nn, (size_t)cj * n + r) : c_zero<L>();
+        si[tx][ty] = (r < rend && ci >= 0) ? ld_cmp<L>(P.vec, nn, (size_t)ci * n + r) : c_zero<L>();
+        sj[tx][ty] = (r < rend && cj >= 0) ? ld_cmp<L>(P.vec, nn, (size_t)cj * n + r) : c_zero<L>();
         __syncthreads();
         for (int q = 0; q < 16; q++) acc.add_mulc(si[q][ty], sj[q][tx]);
         acc.renorm();
     }
     if (i < j0 && jb < bw) st_cmp<L>(Cm, cplane, (size_t)jb * C.size + i, acc.get());
+}
+
+// coefficients = sum of the slices' partial sums, in slice order, into slice 0
+template <int L>
+__global__ void __launch_bounds__(256) k_gs_dsum(const GsCluster *cls, const RqiProb *probs, int b, double *scratch)
+{
+    const GsCluster C = cls[blockIdx.z];
+    const int j0 = C.nconv + b * RB, bw = min(RB, C.nact - b * RB);
+    if (bw <= 0 || j0 == 0) return;
+    const int kd = gs_slices(probs[C.prob].n);
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (kd == 1 || e >= j0 * bw) return;
+    const int jb = e / j0, i = e - jb * j0;
+    const size_t cplane = (size_t)C.size * RB, o = (size_t)jb * C.size + i;
+    double *Cm = scratch + C.sofs;
+    cmp<L> x = ld_cmp<L>(Cm, cplane, o);
+    for (int sl = 1; sl < kd; sl++) x = c_add(x, ld_cmp<L>(Cm + (size_t)sl * 2 * L * cplane, cplane, o));
+    st_cmp<L>(Cm, cplane, o, x);
 }
 
 template <int L>
@@ -2158,8 +2185,10 @@ int stage2_gs(const GsPlan &G, RqiProb *probs, PairDesc *pairs, hipStream_t st)
         const int j0max = G.max_nconv + b * RB;
         if (j0max > 0) {
             for (int pass = 0; pass < 2; pass++) {
-                hipLaunchKernelGGL(k_gs_dot<L>, dim3((j0max + 15) / 16, RB / 16, G.ncl), dim3(256), 0, st, G.dev_cls,
-                                   G.dev_list, (const RqiProb *)probs, b, G.scratch);
+                hipLaunchKernelGGL(k_gs_dot<L>, dim3((j0max + 15) / 16 * kGsSlices, RB / 16, G.ncl), dim3(256), 0, st,
+                                   G.dev_cls, G.dev_list, (const RqiProb *)probs, b, G.scratch);
+                hipLaunchKernelGGL(k_gs_dsum<L>, dim3((j0max * RB + 255) / 256, 1, G.ncl), dim3(256), 0, st, G.dev_cls,
+                                   (const RqiProb *)probs, b, G.scratch);
                 hipLaunchKernelGGL(k_gs_update<L>, dim3((G.max_n + 63) / 64, RB / 4, G.ncl), dim3(256), 0, st, G.dev_cls,
                                    G.dev_list, probs, b, (const double *)G.scratch);
             }
