@@ -252,6 +252,31 @@ __device__ __forceinline__ void hv_row_casc(const RqiProb &P, const double *vec,
 
 constexpr int kRqRows = 4;   // rows per thread whose cascaded sums k_s2_rq keeps between its passes
 
+// hv_row_casc for the rows i0 + 256 q (q < kRqRows, rows below n) in one pass
+// over j: the same operations per row, the rows' sums independent of each
+// other (so they overlap in the pipeline) and v_j loaded once for all of them
+__device__ __forceinline__ void hv_rows_casc(const RqiProb &P, const double *vec, size_t nn, int n, int k, int i0,
+                                             Casc3 *re, Casc3 *im)
+{
+    for (int j = 0; j < n; j++) {
+        const cmp<2> v = ld_cmp<2>(vec, nn, (size_t)k * n + j);
+        for (int l = 0; l < P.limbs_in; l++) {
+#pragma unroll
+            for (int q = 0; q < kRqRows; q++) {
+                const int i = i0 + 256 * q;
+                if (i < n) {
+                    const size_t o = (size_t)j * n + i;
+                    const double hr = P.hf[(2 * l) * nn + o], hi = P.hf[(2 * l + 1) * nn + o];
+                    re[q].add(hr, v.re.x[0], v.re.x[1]);
+                    re[q].add(-hi, v.im.x[0], v.im.x[1]);
+                    im[q].add(hr, v.im.x[0], v.im.x[1]);
+                    im[q].add(hi, v.re.x[0], v.re.x[1]);
+                }
+            }
+        }
+    }
+}
+
 // One work-group per active pair: y = H v, sigma = Re(v^H y), r = y - sigma v;
 // convergence, stagnation and iteration-limit decisions.
 template <int L>
@@ -273,11 +298,11 @@ __global__ void __launch_bounds__(256) k_s2_rq(PairDesc *pairs, RqiProb *probs, 
             // recomputing form below, with one product H v instead of two
             Casc3 yr[kRqRows], yi[kRqRows];
             mp<2> sacc = mp_zero<2>();
+            hv_rows_casc(P, vec, nn, n, k, threadIdx.x, yr, yi);
 #pragma unroll
             for (int q = 0; q < kRqRows; q++) {
                 const int i = threadIdx.x + 256 * q;
                 if (i < n) {
-                    hv_row_casc(P, vec, nn, n, k, i, yr[q], yi[q]);
                     const cmp<2> vi = ld_cmp<2>(vec, nn, (size_t)k * n + i);
                     dd a, b;
                     yr[q].get(a.x[0], a.x[1]);
