@@ -91,6 +91,7 @@ __global__ void k_zero_panel(ProbDesc *probs)
 // its rows and writes a partial norm; the last chunk to finish forms the
 // reflector and writes it for every row.
 constexpr int kColRows = 64;
+constexpr int kLdU = 4;   // loads issued together in the per-column kernels' panel loops
 
 __global__ void __launch_bounds__(256) k_trd_col(ProbDesc *probs, int c, int k0, int crows)
 {
@@ -124,10 +125,20 @@ __global__ void __launch_bounds__(256) k_trd_col(ProbDesc *probs, int c, int k0,
         const int r = r0 + lane;
         double2 s = make_double2(0.0, 0.0);
         if (r < rend) {
-            for (int j = wid; j < i; j += 4) {
-                const double2 v = ld2(P.P + 2 * ((size_t)j * n + r));
-                const double2 w = ld2(P.P + 2 * ((size_t)(kNB + j) * n + r));
-                s = cadd(s, cadd(cmul(v, make_double2(sWc[j].x, -sWc[j].y)), cmul(w, make_double2(sVc[j].x, -sVc[j].y))));
+            for (int j0 = wid; j0 < i; j0 += 4 * kLdU) {
+                double2 v[kLdU], w[kLdU];
+#pragma unroll
+                for (int u = 0; u < kLdU; u++) {
+                    const int j = min(j0 + 4 * u, i - 1);
+                    v[u] = ld2(P.P + 2 * ((size_t)j * n + r));
+                    w[u] = ld2(P.P + 2 * ((size_t)(kNB + j) * n + r));
+                }
+#pragma unroll
+                for (int u = 0; u < kLdU; u++) {
+                    const int j = j0 + 4 * u;
+                    if (j < i)
+                        s = cadd(s, cadd(cmul(v[u], make_double2(sWc[j].x, -sWc[j].y)), cmul(w[u], make_double2(sVc[j].x, -sVc[j].y))));
+                }
             }
         }
         sacc[wid][lane] = s;
@@ -154,17 +165,30 @@ __global__ void __launch_bounds__(256) k_trd_col(ProbDesc *probs, int c, int k0,
         {
             // every lane takes part in the wave sums (zero outside the chunk)
             const double2 x = sx[lane];
-            for (int j = wid; j < i; j += 4) {
-                double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
-                if (r < rend) {
-                    a = cmulc(ld2(P.P + 2 * ((size_t)(kNB + j) * n + r)), x);
-                    b = cmulc(ld2(P.P + 2 * ((size_t)j * n + r)), x);
+            const int rr = r < rend ? r : c;   // a valid row for lanes outside the chunk (their terms are zero)
+            for (int j0 = wid; j0 < i; j0 += 4 * kLdU) {
+                double2 wv[kLdU], vv[kLdU];
+#pragma unroll
+                for (int u = 0; u < kLdU; u++) {
+                    const int j = min(j0 + 4 * u, i - 1);
+                    wv[u] = ld2(P.P + 2 * ((size_t)(kNB + j) * n + rr));
+                    vv[u] = ld2(P.P + 2 * ((size_t)j * n + rr));
                 }
-                a = wave_sum2(a);
-                b = wave_sum2(b);
-                if (lane == 0) {
-                    sdot[j] = cadd(sdot[j], a);
-                    sdot[kNB + j] = cadd(sdot[kNB + j], b);
+#pragma unroll
+                for (int u = 0; u < kLdU; u++) {
+                    const int j = j0 + 4 * u;
+                    if (j >= i) break;
+                    double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+                    if (r < rend) {
+                        a = cmulc(wv[u], x);
+                        b = cmulc(vv[u], x);
+                    }
+                    a = wave_sum2(a);
+                    b = wave_sum2(b);
+                    if (lane == 0) {
+                        sdot[j] = cadd(sdot[j], a);
+                        sdot[kNB + j] = cadd(sdot[kNB + j], b);
+                    }
                 }
             }
         }
@@ -254,15 +278,29 @@ __global__ void __launch_bounds__(256) k_trd_hemv(ProbDesc *probs, int c)
     const double2 *A = reinterpret_cast<const double2 *>(P.A);
     const double2 *Yc = reinterpret_cast<const double2 *>(P.Y) + (size_t)c * n + base;
     // load tile: column jj (0..63) of the tile, rows ii
-    for (int q = tid; q < 64 * 64; q += 256) {
-        const int ii = q & 63, jj = q >> 6;
-        const int gi = I * 64 + ii, gj = J * 64 + jj;
-        double2 a = make_double2(0.0, 0.0);
-        if (gi < m && gj < m && gi >= gj) {
-            a = A[(size_t)(base + gj) * n + base + gi];
-            if (gi == gj) a.y = 0.0;
+    // the tile's 16 loads per thread issued together (a clamped address for
+    // entries outside the lower triangle of A22, whose values are discarded)
+#pragma unroll
+    for (int q0 = 0; q0 < 64 * 64; q0 += 256 * 8) {
+        double2 av[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const int q = q0 + 256 * u + tid, ii = q & 63, jj = q >> 6;
+            const int gi = I * 64 + ii, gj = J * 64 + jj;
+            const bool ok = gi < m && gj < m && gi >= gj;
+            av[u] = A[ok ? (size_t)(base + gj) * n + base + gi : (size_t)base * n + base];
         }
-        tile[ii][jj] = a;
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const int q = q0 + 256 * u + tid, ii = q & 63, jj = q >> 6;
+            const int gi = I * 64 + ii, gj = J * 64 + jj;
+            double2 a = make_double2(0.0, 0.0);
+            if (gi < m && gj < m && gi >= gj) {
+                a = av[u];
+                if (gi == gj) a.y = 0.0;
+            }
+            tile[ii][jj] = a;
+        }
     }
     if (tid < 64) {
         const int gi = I * 64 + tid, gj = J * 64 + tid;
@@ -351,17 +389,45 @@ __global__ void __launch_bounds__(256) k_trd_wfin(ProbDesc *probs, int c, int k0
         const int r = r0 + lane;
         double2 s = make_double2(0.0, 0.0);
         if (r < rend)
-            for (int j = wid; j < i; j += 4) {
-                s = cadd(s, cmul(Pv[(size_t)j * n + r], t1[j]));
-                s = cadd(s, cmul(Pv[(size_t)(kNB + j) * n + r], t2[j]));
+            for (int j0 = wid; j0 < i; j0 += 4 * kLdU) {
+                double2 v[kLdU], w[kLdU];
+#pragma unroll
+                for (int u = 0; u < kLdU; u++) {
+                    const int j = min(j0 + 4 * u, i - 1);
+                    v[u] = Pv[(size_t)j * n + r];
+                    w[u] = Pv[(size_t)(kNB + j) * n + r];
+                }
+#pragma unroll
+                for (int u = 0; u < kLdU; u++) {
+                    const int j = j0 + 4 * u;
+                    if (j < i) {
+                        s = cadd(s, cmul(v[u], t1[j]));
+                        s = cadd(s, cmul(w[u], t2[j]));
+                    }
+                }
             }
         sacc[wid][lane] = s;
         __syncthreads();
         if (wid == 0 && r < rend) {
             const int b = (r - base) / 64;
             double2 y = make_double2(0.0, 0.0);
-            for (int J = 0; J <= b; J++) y = cadd(y, ld2(P.part + 2 * ((size_t)J * n + r)));
-            for (int I2 = b; I2 < T; I2++) y = cadd(y, ld2(P.part + 2 * ((size_t)(T + I2) * n + r)));
+            // the partials in the same order, their loads issued kLdU at a time
+            for (int J0 = 0; J0 <= b; J0 += kLdU) {
+                double2 pv[kLdU];
+#pragma unroll
+                for (int u = 0; u < kLdU; u++) pv[u] = ld2(P.part + 2 * ((size_t)min(J0 + u, b) * n + r));
+#pragma unroll
+                for (int u = 0; u < kLdU; u++)
+                    if (J0 + u <= b) y = cadd(y, pv[u]);
+            }
+            for (int I0 = b; I0 < T; I0 += kLdU) {
+                double2 pv[kLdU];
+#pragma unroll
+                for (int u = 0; u < kLdU; u++) pv[u] = ld2(P.part + 2 * ((size_t)(T + min(I0 + u, T - 1)) * n + r));
+#pragma unroll
+                for (int u = 0; u < kLdU; u++)
+                    if (I0 + u < T) y = cadd(y, pv[u]);
+            }
             y = csub(y, cadd(cadd(sacc[0][lane], sacc[1][lane]), cadd(sacc[2][lane], sacc[3][lane])));
             y = cmul(tau, y);
             Pw[(size_t)(kNB + i) * n + r] = y;
