@@ -217,11 +217,22 @@ __global__ void __launch_bounds__(256) k_trd_col(ProbDesc *probs, int c, int k0,
     }
     if (!last) return;
     if (tid == 0) {
-        dd xn2 = mp_zero<2>();
-        for (int q = 0; q < G; q++) xn2 = dd_add(xn2, dd{{snorm[2 * q], snorm[2 * q + 1]}});
         const double2 diag = ld2(P.A + 2 * ((size_t)c * n + c));
-        P.d[c] = diag.x;
         const double2 alpha = ld2(P.A + 2 * ((size_t)c * n + c + 1));
+        // the chunks' norms in chunk order, their loads issued 8 at a time
+        dd xn2 = mp_zero<2>();
+        for (int q0 = 0; q0 < G; q0 += 8) {
+            dd pn[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const int q = min(q0 + u, G - 1);
+                pn[u] = dd{{snorm[2 * q], snorm[2 * q + 1]}};
+            }
+#pragma unroll
+            for (int u = 0; u < 8; u++)
+                if (q0 + u < G) xn2 = dd_add(xn2, pn[u]);
+        }
+        P.d[c] = diag.x;
         double2 tau = make_double2(0.0, 0.0);
         double beta = alpha.x;
         double2 scale = make_double2(0.0, 0.0);
@@ -249,13 +260,19 @@ __global__ void __launch_bounds__(256) k_trd_col(ProbDesc *probs, int c, int k0,
     __syncthreads();
     const double2 sc = s_scale;
     // 2. reflector v (v[c+1] = 1) into Y[:, c], V column i of P, V column NB+i of Q
-    for (int r2 = c + 1 + tid; r2 < n; r2 += blockDim.x) {
-        double2 v;
-        if (r2 == c + 1) v = make_double2(1.0, 0.0);
-        else v = cmul(ld2(P.A + 2 * ((size_t)c * n + r2)), sc);
-        st2(P.Y + 2 * ((size_t)c * n + r2), v);
-        st2(P.P + 2 * ((size_t)i * n + r2), v);
-        st2(P.Q + 2 * ((size_t)(kNB + i) * n + r2), v);
+    for (int r0 = c + 1; r0 < n; r0 += 4 * 256) {
+        double2 av[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) av[u] = ld2(P.A + 2 * ((size_t)c * n + min(r0 + 256 * u + tid, n - 1)));
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int r2 = r0 + 256 * u + tid;
+            if (r2 >= n) continue;
+            const double2 v = (r2 == c + 1) ? make_double2(1.0, 0.0) : cmul(av[u], sc);
+            st2(P.Y + 2 * ((size_t)c * n + r2), v);
+            st2(P.P + 2 * ((size_t)i * n + r2), v);
+            st2(P.Q + 2 * ((size_t)(kNB + i) * n + r2), v);
+        }
     }
 }
 
@@ -375,7 +392,14 @@ __global__ void __launch_bounds__(256) k_trd_wfin(ProbDesc *probs, int c, int k0
     if (tid < 2 * i) {
         const int j = tid < i ? tid : tid - i, o = tid < i ? j : kNB + j;
         double2 a = make_double2(0.0, 0.0);
-        for (int q = 0; q < Gc; q++) a = cadd(a, sd[(size_t)q * 2 * kNB + o]);
+        for (int q0 = 0; q0 < Gc; q0 += 8) {
+            double2 pv[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) pv[u] = sd[(size_t)min(q0 + u, Gc - 1) * 2 * kNB + o];
+#pragma unroll
+            for (int u = 0; u < 8; u++)
+                if (q0 + u < Gc) a = cadd(a, pv[u]);
+        }
         const double2 top = Pv[(size_t)(tid < i ? kNB + j : j) * n + base];   // row c+1, where v = 1
         a = cadd(make_double2(top.x, -top.y), cmul(scale, a));
         if (tid < i) t1[j] = a;
@@ -453,15 +477,34 @@ __global__ void __launch_bounds__(256) k_trd_wfin(ProbDesc *probs, int c, int k0
     if (!last) return;
     if (tid == 0) {
         double2 t = make_double2(0.0, 0.0);
-        for (int q = 0; q < G; q++) t = cadd(t, swv[q]);
+        for (int q0 = 0; q0 < G; q0 += 8) {
+            double2 pv[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) pv[u] = swv[min(q0 + u, G - 1)];
+#pragma unroll
+            for (int u = 0; u < 8; u++)
+                if (q0 + u < G) t = cadd(t, pv[u]);
+        }
         s_alpha = cmul(make_double2(-0.5 * tau.x, -0.5 * tau.y), t);
     }
     __syncthreads();
     const double2 alpha = s_alpha;
-    for (int r2 = base + tid; r2 < n; r2 += blockDim.x) {
-        const double2 w = cadd(Pw[(size_t)(kNB + i) * n + r2], cmul(alpha, Yc[r2]));
-        Pw[(size_t)(kNB + i) * n + r2] = w;
-        reinterpret_cast<double2 *>(P.Q)[(size_t)i * n + r2] = w;
+    for (int r0 = base; r0 < n; r0 += 4 * 256) {
+        double2 wv[4], yv[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int r2 = min(r0 + 256 * u + tid, n - 1);
+            wv[u] = Pw[(size_t)(kNB + i) * n + r2];
+            yv[u] = Yc[r2];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int r2 = r0 + 256 * u + tid;
+            if (r2 >= n) continue;
+            const double2 w = cadd(wv[u], cmul(alpha, yv[u]));
+            Pw[(size_t)(kNB + i) * n + r2] = w;
+            reinterpret_cast<double2 *>(P.Q)[(size_t)i * n + r2] = w;
+        }
     }
 }
 
