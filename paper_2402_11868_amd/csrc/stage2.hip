@@ -1109,8 +1109,8 @@ __global__ void __launch_bounds__(NT) k_s2_ldl_panel(Stage2Batch B)
     const double ptol = P.piv_tol;
     __shared__ cmp<L> s_wt[kLdlLA][kLuNB];
     __shared__ cmp<L> s_pj[2][kLdlLA];   // conj W(j, k) (and W(j, k+1)) of the window's later columns
-    __shared__ double s_v[4];
-    __shared__ int s_i[4];
+    __shared__ double s_v[NT / 64 > 4 ? NT / 64 : 4];
+    __shared__ int s_i[NT / 64 > 4 ? NT / 64 : 4];
     __shared__ int s_kstep, s_kp, s_stop;
     __shared__ mp<L> s_inv;
     __shared__ cmp<L> s_d21;
@@ -1399,8 +1399,8 @@ __global__ void __launch_bounds__(NT) k_s2_ldl_panel_reg(Stage2Batch B)
     __shared__ cmp<L> s_pj[2][kLdlLA];
     __shared__ cmp<L> s_ex[2][kLdlLA];   // rows kk and kp of the live window vectors
     __shared__ cmp<L> s_el[4];           // V0(k), V0(k+1), V1(k+1), candidate(imax)
-    __shared__ double s_v[4];
-    __shared__ int s_i[4];
+    __shared__ double s_v[NT / 64 > 4 ? NT / 64 : 4];
+    __shared__ int s_i[NT / 64 > 4 ? NT / 64 : 4];
     __shared__ int s_kstep, s_kp, s_stop;
     __shared__ mp<L> s_inv;
     __shared__ cmp<L> s_d21;
@@ -2639,16 +2639,16 @@ static void ldl_panel(const Stage2Batch &B, const int *orders, int s, int c, Ker
     }
     const int id = T.begin(KC_LU_PANEL, wp, st);
     // dd orders up to 128: one wave per pair with the window in registers.
-    // Larger dd orders: the 256-thread register form while the launch has at
+    // Larger dd orders: the 512-thread register form while the launch has at
     // most kRegPanelPairs pairs (its time is then the latency of one
-    // work-group, which the register window shortens), else the memory form
-    // (the register form's 256 VGPRs at order 1024 allow one work-group per
-    // CU; with hundreds of pairs it was measured slower)
+    // work-group, which the register window and the rows spread over 512
+    // threads shorten), else the memory form (a register form at order 1024
+    // allows one work-group per CU; with hundreds of pairs it was measured
+    // slower)
     if (L == 2 && n <= 128) hipLaunchKernelGGL((k_s2_ldl_panel_reg<64, 2>), dim3(c), dim3(64), 0, st, B);
     else if (n <= 128) hipLaunchKernelGGL((k_s2_ldl_panel<L, 64>), dim3(c), dim3(64), 0, st, B);
-    else if (L == 2 && c <= kRegPanelPairs && n <= 256) hipLaunchKernelGGL((k_s2_ldl_panel_reg<256, 1>), dim3(c), dim3(256), 0, st, B);
-    else if (L == 2 && c <= kRegPanelPairs && n <= 512) hipLaunchKernelGGL((k_s2_ldl_panel_reg<256, 2>), dim3(c), dim3(256), 0, st, B);
-    else if (L == 2 && c <= kRegPanelPairs && n <= 1024) hipLaunchKernelGGL((k_s2_ldl_panel_reg<256, 4>), dim3(c), dim3(256), 0, st, B);
+    else if (L == 2 && c <= kRegPanelPairs && n <= 512) hipLaunchKernelGGL((k_s2_ldl_panel_reg<512, 1>), dim3(c), dim3(512), 0, st, B);
+    else if (L == 2 && c <= kRegPanelPairs && n <= 1024) hipLaunchKernelGGL((k_s2_ldl_panel_reg<512, 2>), dim3(c), dim3(512), 0, st, B);
     else hipLaunchKernelGGL((k_s2_ldl_panel<L, 256>), dim3(c), dim3(256), 0, st, B);
     T.end(id, st);
 }
