@@ -39,10 +39,15 @@ CPLX_DD_FMA_INSTR = 48
 CPLX_QD_FMA_INSTR = 988
 
 
-# sources that the LU trailing-update kernel is compiled from; the stored HBM
-# traffic of that kernel is reported only while their digest is unchanged
-LU_UPDATE_SOURCES = ["paper_2402_11868_amd/csrc/stage2.hip", "paper_2402_11868_amd/csrc/mp.h",
-                     "paper_2402_11868_amd/csrc/common.h", "paper_2402_11868_amd/csrc/stage.h"]
+# what the trailing-update kernel's HBM traffic depends on: the headers it is
+# compiled with, the engine that forms its launches (pairs per launch), and in
+# stage2.hip the kernel's own section and its host launcher; the stored traffic
+# is reported only while their digest is unchanged
+LU_UPDATE_SOURCES = ["paper_2402_11868_amd/csrc/mp.h", "paper_2402_11868_amd/csrc/common.h",
+                     "paper_2402_11868_amd/csrc/stage.h", "paper_2402_11868_amd/csrc/engine.h"]
+LU_UPDATE_REGIONS = [("paper_2402_11868_amd/csrc/stage2.hip", "// =========================================================== LU update ====",
+                      "// Generic (quad-double) update"),
+                     ("paper_2402_11868_amd/csrc/stage2.hip", "static bool ldl_update(", "\n}\n")]
 TRAFFIC_FILE = "profiles/ldl_update_herm1024_dd_traffic.txt"
 
 
@@ -56,6 +61,12 @@ def kernel_source_digest():
     for f in LU_UPDATE_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
+    for f, begin, end in LU_UPDATE_REGIONS:
+        with open(os.path.join(ROOT, f)) as fh:
+            text = fh.read()
+        a = text.index(begin)
+        b = text.index(end, a + len(begin))
+        h.update(text[a:b].encode())
     return h.hexdigest()
 
 
