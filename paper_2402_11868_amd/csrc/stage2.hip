@@ -12,11 +12,15 @@
 //            v <- w / ||w||,  y = H v,  sigma <- v^H y,  r = y - sigma v
 //   until ||r|| <= tol ||H||_2  (or the iteration limit / stagnation)
 //
-// Kernels (each launch covers every active pair of the batch):
+// Kernels (each launch covers the active pairs of a batch; the LDL^H
+// factorisation may split them into two groups on two streams whose trailing
+// updates alternate, stage2_solve_pair):
 //   build      M = [H - sigma I | v], limb-planar
 //   ldl_panel  one work-group per pair factorises its next panel (at most NB
 //              columns, left-looking, symmetric interchanges), writes W = L D
-//              column-major and forward-substitutes the right-hand side
+//              column-major and forward-substitutes the right-hand side; a
+//              memory-window form and a register-window form (the same steps
+//              and results), chosen by order and pairs per launch
 //   lu_panel   (LU) one work-group per pair factorises an n x NB panel
 //   lu_trsm    (LU) applies the panel's row interchanges to the trailing
 //              columns and computes U12 = L11^{-1} A12
