@@ -119,7 +119,11 @@ typedef struct {
     int shifted_solve;    /* factorisation of the shifted systems (H - sigma I) w = v of the Rayleigh
                              quotient iteration: 0 = default (LDL^H), 1 = LU with partial pivoting,
                              2 = Hermitian LDL^H with Bunch-Kaufman pivoting (half the multiply-adds
-                             of LU in the trailing updates).  Sessions use the default. */
+                             of LU in the trailing updates).  Sessions use the default.  With LDL^H
+                             the pairs of a launch run in two groups on the context stream and a
+                             side stream of default priority (one group inside
+                             zk_heev_dd_noalloc); the results are the same bits either way
+                             (environment variable ZK_S2_SPLIT=0: one group). */
 } zk_opts;
 
 /* Fill *o with the defaults (init_fp32 0, tol 0, max_iter 0, cluster_tol 0, want_vectors 1, reorth 1, refine 0,
